@@ -28,7 +28,8 @@ Readings of the paper taken here (each written out in the design notes):
   max_sweeps sweeps.
 * Interpolation formula: C_k = F_k P_k^{-1} with F_k = X(I^{<=k-1}, :, I^{>k})
   unfolded to (r_{k-1} n_k) x r_k and P_k = X(I^{<=k}, I^{>k}) its row subset;
-  computed as Q Q[J,:]^{-1} from the thin QR F_k = Q R.  C_N = F_N.
+  the final cores are computed as Q Q[J,:]^{-1} from the thin QR F_k = Q R,
+  the stopping test uses the direct LU solve.  C_N = F_N.
 * Initialisation (Algorithm 7): q_1, q_2 are full random multi-indices; a
   snapshot (all sets, max condition number of the half-sweep) is kept after
   every half-sweep and the one with the smallest maximum is returned (earliest
@@ -310,8 +311,12 @@ def fibre(ent, L, R, k):
     return ent(idx).reshape(rl * nk, rr)
 
 
-def interp_cores(ent, L, R):
-    """Cores of the cross interpolant (interpolation formula of Appendix A)."""
+def interp_cores(ent, L, R, method="qr"):
+    """Cores of the cross interpolant (interpolation formula of Appendix A).
+
+    method "qr": C_k = Q Q[J,:]^{-1} from the thin QR F_k = Q R (final cores);
+    method "lu": C_k = F_k P_k^{-1} by an LU solve (the sampled stopping test).
+    """
     N, n = ent.N, ent.n
     cores = []
     for k in range(1, N + 1):
@@ -319,8 +324,11 @@ def interp_cores(ent, L, R):
         rl = L[k - 1].shape[0]
         if k < N:
             Jp = _positions_left(L, k, n)
-            Q, _ = np.linalg.qr(F)
-            C = np.linalg.solve(Q[Jp, :].T, Q.T).T            # Q Q[J,:]^{-1}
+            if method == "qr":
+                Q, _ = np.linalg.qr(F)
+                C = np.linalg.solve(Q[Jp, :].T, Q.T).T        # Q Q[J,:]^{-1}
+            else:
+                C = np.linalg.solve(F[Jp, :].T, F.T).T        # F P^{-1}
             cores.append(ttmod.from_g2(C, rl, n[k - 1], C.shape[1]))
         else:
             cores.append(ttmod.from_g2(F, rl, n[k - 1], 1))
@@ -348,7 +356,7 @@ def greedy_cross(ent, eps, seed=0, max_rank=256, max_sweeps=200, init_card=2, in
     tmax = float(np.max(np.abs(tval)))
 
     def sampled_error():
-        c = interp_cores(ent, L, R)
+        c = interp_cores(ent, L, R, method="lu")
         return float(np.max(np.abs(ttmod.evaluate(c, tidx) - tval)) / tmax), c
 
     log = []
@@ -356,7 +364,12 @@ def greedy_cross(ent, eps, seed=0, max_rank=256, max_sweeps=200, init_card=2, in
     errs = [err]
     sweep = 0
     fi = 0
-    while err > eps and sweep < max_sweeps:
+    def keep_going():
+        if forced is not None:          # replay: as many sweeps as the log holds
+            return fi < len(forced)
+        return err > eps and sweep < max_sweeps
+
+    while keep_going():
         added = 0
         for k in range(1, N):
             f = None
@@ -369,8 +382,9 @@ def greedy_cross(ent, eps, seed=0, max_rank=256, max_sweeps=200, init_card=2, in
         sweep += 1
         err, cores = sampled_error()
         errs.append(err)
-        if added == 0:
+        if added == 0 and forced is None:
             break
+    cores = interp_cores(ent, L, R, method="qr")
     info = {"L": L, "R": R, "log": log, "sweeps": sweep, "errors": errs, "error": err,
             "converged": err <= eps, "evals": ent.count, "init": init_info,
             "ranks": [1] + [L[k].shape[0] for k in range(1, N)] + [1]}
