@@ -1,0 +1,247 @@
+/*
+ * tt_kernel.h -- C ABI of the MI355X (gfx950) implementation of the
+ * parametric Chebyshev / tensor-train kernel low-rank method ("PTTK") of
+ * Khan & Saibaba, "Parametric kernel low-rank approximations using tensor
+ * train decomposition" (arXiv 2406.06344).
+ *
+ * The method approximates the parametric kernel matrix
+ *     K(X, Y; theta)[i, j] = kappa(x_i, y_j; theta)          (Section 1)
+ * with rows indexed by the N_s source points x_i and columns by the N_t
+ * target points y_j, in the form K ~ S H(theta) T^T (the low-rank form of
+ * Section 1).  In this library S is called U (N_s x r_s), T is called V
+ * (N_t x r_t) and H(theta) is called M(theta) (r_s x r_t).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns tt_status: 0 = OK, > 0 = warning (result usable),
+ *    < 0 = error (outputs untouched or partially written; the handle, if any,
+ *    stays valid).  Nothing is thrown across the ABI.  tt_kernel_last_error()
+ *    returns a thread-local message for the last non-OK status.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every pointer it
+ *    passes and keeps it valid for the duration of the call (and, for
+ *    asynchronous calls, until the work on `stream` has completed).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All device work of
+ *    a call is enqueued on it; calls return without synchronising unless the
+ *    comment says otherwise.
+ *  - Floating-point buffers named "dtype" hold float (TTK_FP32) or double
+ *    (TTK_FP64) according to tt_kernel_params.dtype.  Kernel-entry
+ *    evaluation feeding the cross approximation, its pivot selection, the
+ *    QR/LU/SVD of the small cores and the core orthogonalisation always run
+ *    in double precision on the device.
+ *  - Points are passed structure-of-arrays: coordinate j of point p at
+ *    X[j * n + p].
+ *  - Matrices are column-major unless stated; "ld" arguments are leading
+ *    dimensions in elements.
+ */
+#ifndef TT_KERNEL_H
+#define TT_KERNEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tt_kernel* tt_kernel_t;
+
+typedef enum {
+  TTK_OK = 0,
+  TTK_WARN_NOT_CONVERGED = 1,   /* cross stopped by a cap with sampled error > tol */
+  TTK_ERR_ARG = -1,             /* invalid argument (sizes, pointers, ranges)     */
+  TTK_ERR_HIP = -2,             /* a HIP runtime call failed                      */
+  TTK_ERR_OOM = -3,             /* device or host allocation failed               */
+  TTK_ERR_SINGULAR_CROSS = -4,  /* an intersection matrix of the cross is singular */
+  TTK_ERR_UNSUPPORTED = -5      /* combination not implemented                    */
+} tt_status;
+
+/* Kernel functions of Table 1 (r = ||x - y||_2), plus two test kernels.
+ * Parameter vector theta, in this order:                                     */
+typedef enum {
+  TTK_SE = 1,           /* exp(-(r/l)^2)                         theta = (l)     */
+  TTK_EXPONENTIAL = 2,  /* exp(-r/l)                             theta = (l)     */
+  TTK_MATERN32 = 3,     /* (1 + a) e^-a,  a = sqrt(3) r / l      theta = (l)     */
+  TTK_MATERN52 = 4,     /* (1 + a + a^2/3) e^-a, a = sqrt(5) r/l theta = (l)     */
+  TTK_MATERN_NU = 5,    /* Matern with fixed nu = kernel_const   theta = (l)     */
+  TTK_MATERN = 6,       /* 2^(1-nu)/Gamma(nu) z^nu K_nu(z), z = sqrt(2 nu) r / l,
+                           kappa(0) = 1                          theta = (l, nu) */
+  TTK_MULTIQUADRIC = 7, /* sqrt(1 + (r/l)^2)                     theta = (l)     */
+  TTK_TPS = 8,          /* (r/l)^2 log((r/l)^2), 0 at r = 0      theta = (l)     */
+  TTK_LAPLACE3D = 9,    /* 1/r                                   no theta        */
+  TTK_LAPLACE2D = 10,   /* -log r                                no theta        */
+  TTK_BIHARMONIC = 11,  /* r^-2                                  no theta        */
+  TTK_THINPLATE = 12,   /* r^2 log r                             no theta        */
+  TTK_TEST_POLY = 13,   /* (1 + theta x.y)^3 (test only)         theta = (t)     */
+  TTK_TEST_SEP = 14     /* exp(sum x) theta exp(-sum y) (test)   theta = (t)     */
+} tt_kernel_kind;
+
+typedef enum { TTK_FP64 = 0, TTK_FP32 = 1 } tt_dtype;
+
+/* Build parameters (inputs of the offline stage, Algorithm 2). */
+typedef struct {
+  int d;                 /* spatial dimension, 1..3                                  */
+  int d_theta;           /* parameter dimension, 0..2 (must match `kind`)            */
+  int n_spatial;         /* Chebyshev nodes per spatial dimension, 2..32             */
+  int n_param;           /* Chebyshev nodes per parameter dimension, 2..32           */
+  int kind;              /* tt_kernel_kind                                           */
+  double kernel_const;   /* nu for TTK_MATERN_NU, unused otherwise                   */
+  double box_s[6];       /* source box [alpha_1, beta_1, ..., alpha_d, beta_d]       */
+  double box_t[6];       /* target box, same layout                                  */
+  double box_theta[4];   /* parameter box [alpha_1, beta_1, alpha_2, beta_2]         */
+  double tol;            /* tolerance of the cross (sampled relative Chebyshev-norm
+                            error) and of the rounding of its cores                  */
+  int max_rank;          /* cap on every TT rank of the cross (<= 256)               */
+  int max_sweeps;        /* cap on cross sweeps                                      */
+  int init_card;         /* 1 or 2: cardinality of the initial index sets (App. B)   */
+  int init_max_it;       /* iterations of the index initialisation (App. B uses 10)  */
+  int n_test;            /* multi-indices of the sampled stopping test (0 = default
+                            max(1000, 20 D n))                                       */
+  uint64_t seed;         /* key of every random draw of the cross                    */
+  int dtype;             /* tt_dtype of U, V, M and the apply                        */
+  int symmetric_psd;     /* reserved (0)                                              */
+} tt_kernel_params;
+
+typedef struct {
+  int D;                       /* 2 d + d_theta                                      */
+  int r_s, r_t;                /* columns of U and V (ranks r_d and r_{d+d_theta})   */
+  int ranks[9];                /* ranks r_0..r_D of the rounded cores                */
+  int cross_ranks[9];          /* ranks of the cross before rounding                 */
+  int64_t kernel_evals;        /* kernel evaluations made on the device by the build */
+  int sweeps;                  /* cross sweeps made                                  */
+  int n_decisions;             /* update-cross steps logged                          */
+  double sampled_error;        /* final sampled relative Chebyshev-norm error        */
+  double init_max_cond;        /* max condition number of the chosen initial sets    */
+  double min_margin;           /* smallest relative top-2 margin of a pivot decision */
+  double t_cross_ms, t_round_ms, t_factor_ms;   /* build phase timings             */
+  int64_t n_src, n_tgt;
+  int dtype;
+} tt_kernel_info;
+
+/* One decision of the update cross step (Algorithm 5), for parity checks. */
+typedef struct {
+  int sweep, k;              /* sweep (0-based) and super-core k (1..D-1)             */
+  int rank_before;           /* |I^{<=k}| before the step                             */
+  int64_t sample_pos;        /* chosen sample, linear position row * cols + col        */
+  int bit;                   /* random bit: 1 = row search, 0 = column search          */
+  int pivot_row, pivot_col;  /* final pivot position in the super-core unfolding       */
+  int added;                 /* 1 if (row, col) was appended to (I^{<=k}, I^{>k})      */
+  double sample_max, sample_margin, pivot_abs, search_margin, tau;
+} tt_kernel_decision;
+
+/* Offline stage (Algorithm 2 with a rounding step on the small cores):
+ *  1. Chebyshev grid of every dimension (Section 2.4),
+ *  2. TT greedy-cross on f_kappa(x, theta, y) over the grid (Algorithms 5-7,
+ *     interpolation formula of Appendix A), kernel entries evaluated on the
+ *     device in double precision,
+ *  3. TT-Round (Algorithm 1) of the cross cores at tol, orthogonalisation so
+ *     that source cores are left- and target cores right-orthonormal, and the
+ *     change of the spatial cores to the Chebyshev coefficient basis,
+ *  4. Phase 3 (Algorithm 2): U = S and V = T by contracting each point's
+ *     Chebyshev values through the spatial cores.
+ * X: device, dtype, SoA d x n_src, points inside box_s.  Y: device, dtype,
+ * SoA d x n_tgt, inside box_t.  Points outside their box are an error of the
+ * caller (the result is then an extrapolation).  Synchronises `stream`.
+ * On success *out receives a new handle owning U, V, the cores and the
+ * cross record; TTK_WARN_NOT_CONVERGED also returns a usable handle. */
+tt_status tt_kernel_build_offline(const tt_kernel_params* p,
+                                  const void* X, int64_t n_src,
+                                  const void* Y, int64_t n_tgt,
+                                  void* stream, tt_kernel_t* out);
+
+/* Same as tt_kernel_build_offline but skips steps 2-3: the nodal TT cores
+ * G_1..G_D (Section 2.3) are given on the host in double precision,
+ * concatenated, core k stored as G_k[a, i, b] at a + i r_{k-1} + b r_{k-1} n_k
+ * (the little-endian layout of Section 2.2); ranks[0..D] with r_0 = r_D = 1.
+ * They must already be gauge-fixed as the caller wants them.  Used to restore
+ * a stored offline stage and to test Phase 3 on given cores. */
+tt_status tt_kernel_build_from_cores(const tt_kernel_params* p, const int* ranks,
+                                     const double* cores,
+                                     const void* X, int64_t n_src,
+                                     const void* Y, int64_t n_tgt,
+                                     void* stream, tt_kernel_t* out);
+
+/* Phase 3 alone (Algorithm 2, Phase 3) for other points of the same boxes:
+ * side 0 gives rows of U for n points in box_s, side 1 rows of V for n points
+ * in box_t (the offline stage does not depend on the points beyond their
+ * boxes; Section 4.1 notes the case of points that move inside fixed boxes).
+ * P: device, dtype, SoA d x n.  out: device, dtype, n x r row-major
+ * (r = r_s or r_t).  One kernel launch on `stream`. */
+tt_status tt_kernel_factor_rows(tt_kernel_t h, int side, const void* P, int64_t n, void* out,
+                                void* stream);
+
+/* Online stage (Algorithm 3): M(theta_b) = H_1(theta_b1) ... H_dt(theta_bdt)
+ * with H_j = G_{d+j} x_2 q^p_j(theta_bj), for b = 0..B-1.
+ * theta: device, dtype, B x d_theta row-major.  M_out: device, dtype,
+ * B x r_s x r_t, matrix b column-major at M_out + b r_s r_t.  dM_out: NULL or
+ * device, dtype, B x d_theta x r_s x r_t: dM(theta_b)/dtheta_j, obtained by
+ * replacing q^p_j with its derivative (the differentiated Chebyshev series).
+ * theta outside box_theta extrapolates.  For d_theta = 0, M = I. */
+tt_status tt_kernel_online_core(tt_kernel_t h, const void* theta, int B,
+                                void* M_out, void* dM_out, void* stream);
+
+/* Apply: y_b = U M(theta_b) V^T x_b for b = 0..B-1 (the low-rank form of
+ * Section 1, used as a matrix in outer loops).  X: device, dtype, n_tgt x B
+ * column-major with leading dimension ldx >= n_tgt.  Y: device, dtype, n_src x B,
+ * ldy >= n_src.  W_save: NULL or device, dtype, r_t x B (column-major):
+ * receives W = V^T X for a later backward call.  B = 1 runs the plain
+ * two-pass form; B > 1 the batched form (one pass over V and U for all b). */
+tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B,
+                          const void* X, int64_t ldx, void* Y, int64_t ldy,
+                          void* W_save, void* stream);
+
+/* Plain per-theta apply for all b: B independent two-pass applies (reads V and
+ * U once per theta).  The reference point for the batched form. */
+tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B,
+                                const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                void* stream);
+
+/* Backward of L = sum_b <g_b, y_b> for y_b as in tt_kernel_apply:
+ *   dX[:, b]      = V M(theta_b)^T U^T g_b
+ *   dtheta[b, j]  = (U^T g_b)^T dM(theta_b)/dtheta_j (V^T x_b)
+ * G: device, dtype, n_src x B (ldg).  X: as in apply (used only when W_saved
+ * is NULL).  W_saved: NULL or the W_save of the forward call.  dX: NULL or
+ * device n_tgt x B (lddx).  dtheta: NULL or device, dtype, B x d_theta
+ * row-major.  Exact derivatives of the approximation (not of kappa). */
+tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B,
+                                   const void* X, int64_t ldx, const void* W_saved,
+                                   const void* G, int64_t ldg,
+                                   void* dX, int64_t lddx, void* dtheta, void* stream);
+
+/* f_kappa at P grid multi-indices (Section 2.4, entries of the grid tensor),
+ * in double precision on the device.  idx: device int32, P x D row-major,
+ * 0-based node indices in the (x, theta, y) order.  out: device double, P. */
+tt_status tt_kernel_eval_entries(const tt_kernel_params* p, const int32_t* idx, int64_t P,
+                                 double* out, void* stream);
+
+/* Dense kernel block K(X, Y; theta)[i, j] (rows = sources, Section 1) in
+ * precision `dtype` of p.  X: device SoA d x nx, Y: device SoA d x ny, theta:
+ * host, d_theta values.  K: device, column-major nx x ny (ldk >= nx). */
+tt_status tt_kernel_eval_dense(const tt_kernel_params* p, const void* X, int64_t nx,
+                               const void* Y, int64_t ny, const double* theta,
+                               void* K, int64_t ldk, void* stream);
+
+/* Query.  Synchronous, host memory. */
+tt_status tt_kernel_get_info(tt_kernel_t h, tt_kernel_info* info);
+
+/* Copy U (n_src x r_s) and V (n_tgt x r_t), row-major dtype, into device
+ * buffers (either may be NULL). */
+tt_status tt_kernel_get_factors(tt_kernel_t h, void* U_out, void* V_out, void* stream);
+
+/* Rounded, gauge-fixed nodal cores G_1..G_D in double precision, host, in
+ * the layout of tt_kernel_build_from_cores; `capacity` doubles available. */
+tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity);
+
+/* Cross record: index sets I^{<=k} (k = 1..D-1) and I^{>k} as host int32
+ * arrays.  left: capacity sum_k r_k k, rows of I^{<=k} concatenated for
+ * k = 1..D-1, each row k indices.  right: same for I^{>k}, rows of D - k
+ * indices.  decisions: up to max_decisions entries.  Any pointer may be NULL. */
+tt_status tt_kernel_get_cross(tt_kernel_t h, int32_t* left, int32_t* right,
+                              tt_kernel_decision* decisions, int max_decisions);
+
+tt_status tt_kernel_destroy(tt_kernel_t h);
+
+const char* tt_kernel_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_KERNEL_H */

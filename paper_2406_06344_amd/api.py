@@ -1,0 +1,289 @@
+"""Python binding of the PTTK C ABI: argument marshalling only.
+
+Every step runs in libttk.so; torch supplies device memory and the stream.
+Shapes follow torch's row-major convention:
+  points X, Y           (N, d)   -> passed structure-of-arrays (d, N)
+  theta                 (B, d_theta)
+  right-hand sides X    (B, N_t)  (row b = x_b; a column-major N_t x B matrix)
+  outputs Y             (B, N_s)
+  U, V                  (N_s, r_s), (N_t, r_t)
+  M(theta)              (B, r_s, r_t)
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import KINDS, KIND_DTHETA, TTK_FP32, TTK_FP64, Decision, Info, Params, check
+
+
+def _stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float32:
+        return TTK_FP32
+    if dtype == torch.float64:
+        return TTK_FP64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def make_params(kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None, tol=1e-6,
+                dtype=torch.float32, seed=0, max_rank=256, max_sweeps=200, init_card=2,
+                init_max_it=10, n_test=0, kernel_const=0.0):
+    p = Params()
+    p.d = int(d)
+    p.d_theta = KIND_DTHETA[kind]
+    p.n_spatial = int(n_spatial)
+    p.n_param = int(n_spatial if n_param is None else n_param)
+    p.kind = KINDS[kind]
+    p.kernel_const = float(kernel_const)
+    bs = np.asarray(box_s, float).reshape(-1)
+    bt = np.asarray(box_t, float).reshape(-1)
+    bp = np.asarray(box_theta, float).reshape(-1)
+    for i, v in enumerate(bs):
+        p.box_s[i] = v
+    for i, v in enumerate(bt):
+        p.box_t[i] = v
+    for i, v in enumerate(bp):
+        p.box_theta[i] = v
+    p.tol = float(tol)
+    p.max_rank = int(max_rank)
+    p.max_sweeps = int(max_sweeps)
+    p.init_card = int(init_card)
+    p.init_max_it = int(init_max_it)
+    p.n_test = int(n_test)
+    p.seed = int(seed)
+    p.dtype = _dtype_code(dtype)
+    p.symmetric_psd = 0
+    return p
+
+
+def _soa(P, dtype):
+    """(N, d) points -> contiguous (d, N) on the current device."""
+    return P.to(device="cuda", dtype=dtype).t().contiguous()
+
+
+class TTKernel:
+    """Offline stage (U, V, parameter cores) held by the C library."""
+
+    def __init__(self, handle, params, dtype, n_src, n_tgt, status=0):
+        self._h = handle
+        self.params = params
+        self.dtype = dtype
+        self.n_src = n_src
+        self.n_tgt = n_tgt
+        self.status = status
+        inf = self.info()
+        self.r_s, self.r_t, self.D = inf["r_s"], inf["r_t"], inf["D"]
+        self.d_theta = params.d_theta
+
+    # ----------------------------------------------------------- builds
+    @classmethod
+    def build_offline(cls, X, Y, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None,
+                      tol=1e-6, dtype=torch.float32, stream=None, **kw):
+        lib = _lib.load()
+        p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, tol, dtype, **kw)
+        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+        h = ctypes.c_void_p()
+        st = check(lib.tt_kernel_build_offline(ctypes.byref(p), _ptr(Xs), Xs.shape[1], _ptr(Ys), Ys.shape[1],
+                                               _stream_ptr(stream), ctypes.byref(h)))
+        return cls(h, p, dtype, Xs.shape[1], Ys.shape[1], st)
+
+    @classmethod
+    def from_cores(cls, cores, X, Y, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None,
+                   dtype=torch.float32, stream=None, **kw):
+        """cores: list of float64 arrays (r0, n, r1) (nodal basis, gauge as given)."""
+        lib = _lib.load()
+        p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, 1e-6, dtype, **kw)
+        ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+        flat = np.concatenate([np.asarray(c, np.float64).reshape(-1, order="F") for c in cores])
+        r_arr = (ctypes.c_int * len(ranks))(*ranks)
+        c_arr = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+        h = ctypes.c_void_p()
+        check(lib.tt_kernel_build_from_cores(ctypes.byref(p), r_arr, c_arr, _ptr(Xs), Xs.shape[1], _ptr(Ys),
+                                             Ys.shape[1], _stream_ptr(stream), ctypes.byref(h)))
+        return cls(h, p, dtype, Xs.shape[1], Ys.shape[1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().tt_kernel_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ----------------------------------------------------------- queries
+    def info(self):
+        inf = Info()
+        check(_lib.load().tt_kernel_get_info(self._h, ctypes.byref(inf)))
+        D = inf.D
+        return {"D": D, "r_s": inf.r_s, "r_t": inf.r_t, "ranks": list(inf.ranks)[:D + 1],
+                "cross_ranks": list(inf.cross_ranks)[:D + 1], "kernel_evals": inf.kernel_evals,
+                "sweeps": inf.sweeps, "n_decisions": inf.n_decisions, "sampled_error": inf.sampled_error,
+                "init_max_cond": inf.init_max_cond, "min_margin": inf.min_margin,
+                "t_cross_ms": inf.t_cross_ms, "t_round_ms": inf.t_round_ms, "t_factor_ms": inf.t_factor_ms,
+                "n_src": inf.n_src, "n_tgt": inf.n_tgt}
+
+    def factors(self, stream=None):
+        U = torch.empty((self.n_src, self.r_s), dtype=self.dtype, device="cuda")
+        V = torch.empty((self.n_tgt, self.r_t), dtype=self.dtype, device="cuda")
+        check(_lib.load().tt_kernel_get_factors(self._h, _ptr(U), _ptr(V), _stream_ptr(stream)))
+        return U, V
+
+    def cores(self):
+        inf = self.info()
+        r = inf["ranks"]
+        n = [self.params.n_spatial] * self.params.d + [self.params.n_param] * self.params.d_theta + \
+            [self.params.n_spatial] * self.params.d
+        sizes = [r[k] * n[k] * r[k + 1] for k in range(inf["D"])]
+        buf = np.zeros(sum(sizes))
+        check(_lib.load().tt_kernel_get_cores(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              buf.size))
+        out, off = [], 0
+        for k, s in enumerate(sizes):
+            out.append(buf[off:off + s].reshape((r[k], n[k], r[k + 1]), order="F"))
+            off += s
+        return out
+
+    def cross_record(self):
+        inf = self.info()
+        D = inf["D"]
+        r = inf["cross_ranks"]
+        nl = sum(r[k] * k for k in range(1, D))
+        nr = sum(r[k] * (D - k) for k in range(1, D))
+        left = (ctypes.c_int32 * max(nl, 1))()
+        right = (ctypes.c_int32 * max(nr, 1))()
+        nd = inf["n_decisions"]
+        dec = (Decision * max(nd, 1))()
+        check(_lib.load().tt_kernel_get_cross(self._h, left, right, dec, nd))
+        L, R = [None] * (D + 1), [None] * (D + 1)
+        lo = ro = 0
+        for k in range(1, D):
+            L[k] = np.array(left[lo:lo + r[k] * k], dtype=np.int64).reshape(r[k], k)
+            lo += r[k] * k
+            R[k] = np.array(right[ro:ro + r[k] * (D - k)], dtype=np.int64).reshape(r[k], D - k)
+            ro += r[k] * (D - k)
+        names = [f[0] for f in Decision._fields_]
+        decisions = [{n: getattr(dec[i], n) for n in names} for i in range(nd)]
+        for rec in decisions:
+            rec["added"] = bool(rec["added"])
+        return L, R, decisions
+
+    def factor_rows(self, P, side=0, out=None, stream=None):
+        """Rows of U (side 0) or V (side 1) for points P (n, d) of the same box."""
+        Ps = _soa(P, self.dtype)
+        n = Ps.shape[1]
+        r = self.r_s if side == 0 else self.r_t
+        if out is None:
+            out = torch.empty((n, r), dtype=self.dtype, device="cuda")
+        check(_lib.load().tt_kernel_factor_rows(self._h, side, _ptr(Ps), n, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def factor_rows_soa(self, Ps, side, out, stream=None):
+        """As factor_rows for points already in (d, n) device layout; no allocation."""
+        check(_lib.load().tt_kernel_factor_rows(self._h, side, _ptr(Ps), Ps.shape[1], _ptr(out),
+                                                _stream_ptr(stream)))
+        return out
+
+    # ------------------------------------------------------------ online
+    def online_core(self, theta, deriv=False, stream=None):
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        B = theta.shape[0]
+        M = torch.empty((B, self.r_t, self.r_s), dtype=self.dtype, device="cuda")
+        dM = torch.empty((B, max(self.d_theta, 1), self.r_t, self.r_s), dtype=self.dtype,
+                         device="cuda") if deriv else None
+        check(_lib.load().tt_kernel_online_core(self._h, _ptr(theta), B, _ptr(M), _ptr(dM), _stream_ptr(stream)))
+        Mt = M.transpose(1, 2)
+        return (Mt, dM.transpose(2, 3)) if deriv else Mt
+
+    def apply(self, theta, X, save_w=False, stream=None):
+        """y_b = U M(theta_b) V^T x_b for every row x_b of X (B, N_t)."""
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        X = X.to(device="cuda", dtype=self.dtype).contiguous()
+        B = X.shape[0]
+        Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
+        W = torch.empty((B, self.r_t), dtype=self.dtype, device="cuda") if save_w else None
+        check(_lib.load().tt_kernel_apply(self._h, _ptr(theta), B, _ptr(X), self.n_tgt, _ptr(Y), self.n_src,
+                                          _ptr(W), _stream_ptr(stream)))
+        return (Y, W) if save_w else Y
+
+    def apply_plain(self, theta, X, stream=None):
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        X = X.to(device="cuda", dtype=self.dtype).contiguous()
+        B = X.shape[0]
+        Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
+        check(_lib.load().tt_kernel_apply_plain(self._h, _ptr(theta), B, _ptr(X), self.n_tgt, _ptr(Y),
+                                                self.n_src, _stream_ptr(stream)))
+        return Y
+
+    def apply_backward(self, theta, G, X=None, W=None, want_dx=True, want_dtheta=True, stream=None):
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        G = G.to(device="cuda", dtype=self.dtype).contiguous()
+        B = G.shape[0]
+        dX = torch.empty((B, self.n_tgt), dtype=self.dtype, device="cuda") if want_dx else None
+        dth = torch.empty((B, max(self.d_theta, 1)), dtype=self.dtype,
+                          device="cuda") if (want_dtheta and self.d_theta > 0) else None
+        Xc = X.to(device="cuda", dtype=self.dtype).contiguous() if X is not None else None
+        check(_lib.load().tt_kernel_apply_backward(self._h, _ptr(theta), B, _ptr(Xc), self.n_tgt, _ptr(W),
+                                                   _ptr(G), self.n_src, _ptr(dX), self.n_tgt, _ptr(dth),
+                                                   _stream_ptr(stream)))
+        return dX, dth
+
+
+class _ApplyFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, X, kern):
+        Y, W = kern.apply(theta, X, save_w=True)
+        ctx.kern = kern
+        ctx.save_for_backward(theta, W)
+        return Y
+
+    @staticmethod
+    def backward(ctx, gY):
+        theta, W = ctx.saved_tensors
+        kern = ctx.kern
+        dX, dth = kern.apply_backward(theta, gY, W=W, want_dx=ctx.needs_input_grad[1],
+                                      want_dtheta=ctx.needs_input_grad[0])
+        if dth is not None:
+            dth = dth.reshape(theta.shape)
+        return dth, dX, None
+
+
+def kernel_apply(kern: TTKernel, theta, X):
+    """Differentiable y_b = U M(theta_b) V^T x_b (gradients in theta and X)."""
+    return _ApplyFn.apply(theta, X, kern)
+
+
+def eval_entries(idx, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None, kernel_const=0.0,
+                 stream=None):
+    """f_kappa at grid multi-indices idx (P, D) int32, on the device, float64."""
+    lib = _lib.load()
+    p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, kernel_const=kernel_const)
+    idx = idx.to(device="cuda", dtype=torch.int32).contiguous()
+    out = torch.empty(idx.shape[0], dtype=torch.float64, device="cuda")
+    check(lib.tt_kernel_eval_entries(ctypes.byref(p), _ptr(idx), idx.shape[0], _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def eval_dense(X, Y, theta, kind, d, dtype=torch.float64, kernel_const=0.0, stream=None):
+    """Dense K(X, Y; theta) block on the device, rows = sources."""
+    lib = _lib.load()
+    p = make_params(kind, d, [[0, 1]] * d, [[0, 1]] * d, [[0, 1]] * KIND_DTHETA[kind], dtype=dtype,
+                    kernel_const=kernel_const)
+    Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+    nx, ny = Xs.shape[1], Ys.shape[1]
+    K = torch.empty((ny, nx), dtype=dtype, device="cuda")       # column-major nx x ny
+    th = (ctypes.c_double * 2)(*([float(v) for v in np.ravel(theta)] + [0.0, 0.0])[:2])
+    check(lib.tt_kernel_eval_dense(ctypes.byref(p), _ptr(Xs), nx, _ptr(Ys), ny, th, _ptr(K), nx,
+                                   _stream_ptr(stream)))
+    return K.t()

@@ -1,0 +1,130 @@
+// Kernel evaluation on the Chebyshev grid: the entries of the grid tensor
+// m_{i_1..i_D} = f_kappa(eta) with eta_j the node i_j of dimension j, in the
+// variable order (x, theta, y) (Section 1, "Our approach"; Section 2.4,
+// "Multivariate approximation").  The cross algorithm addresses entries
+// through its index sets, so multi-indices are assembled here on the device
+// from (left set row, middle node indices, right set row) and never shipped
+// from the host.  All evaluation is double precision.
+#include "ttk_internal.h"
+#include "ttk_kappa.h"
+
+namespace ttk {
+
+namespace {
+
+__device__ inline double eval_coords(const KSpec& ks, const double* c) {
+  return kappa_eval(ks.kind, ks.d, ks.kconst, c, c + ks.d, c + ks.d + ks.dt);
+}
+
+// Multi-index of super-core / fibre position (row, col) -> coordinates.
+__device__ inline void addr_coords(const KSpec& ks, const Addr& a, int row, int col, double* c) {
+  const int s = row % a.rl;
+  const int i0 = row / a.rl;
+  int i1 = 0, t = col;
+  if (a.nmid == 2) { i1 = col % a.nm1; t = col / a.nm1; }
+  int j = 0;
+  for (int q = 0; q < a.lk; ++q, ++j) c[j] = ks.nodes[j * MAXN + a.left[s * a.lk + q]];
+  c[j] = ks.nodes[j * MAXN + i0]; ++j;
+  if (a.nmid == 2) { c[j] = ks.nodes[j * MAXN + i1]; ++j; }
+  for (int q = 0; q < a.lr; ++q, ++j) c[j] = ks.nodes[j * MAXN + a.right[t * a.lr + q]];
+}
+
+__global__ void k_eval_product(KSpec ks, Addr a, const int32_t* rows, int nr,
+                               const int32_t* cols, int nc, double* out) {
+  const int64_t total = (int64_t)nr * nc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % nr);
+    const int jj = (int)(e / nr);
+    const int row = rows ? rows[i] : i;
+    const int col = cols ? cols[jj] : jj;
+    double c[MAXD];
+    addr_coords(ks, a, row, col, c);
+    out[e] = eval_coords(ks, c);
+  }
+}
+
+__global__ void k_eval_list(KSpec ks, Addr a, const int32_t* rows, const int32_t* cols, int np,
+                            double* out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
+    double c[MAXD];
+    addr_coords(ks, a, rows[i], cols[i], c);
+    out[i] = eval_coords(ks, c);
+  }
+}
+
+template <class I>
+__global__ void k_eval_multi(KSpec ks, const I* idx, int64_t P, double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double c[MAXD];
+    for (int j = 0; j < ks.D; ++j) c[j] = ks.nodes[j * MAXN + (int)idx[i * ks.D + j]];
+    out[i] = eval_coords(ks, c);
+  }
+}
+
+// Dense block: one thread per (i, j), i fastest so stores to column-major K coalesce.
+template <class T>
+__global__ void k_eval_dense(KSpec ks, const T* X, int64_t nx, const T* Y, int64_t ny,
+                             double th0, double th1, T* K, int64_t ldk) {
+  const int64_t total = nx * ny;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % nx, j = e / nx;
+    double c[MAXD];
+    for (int q = 0; q < ks.d; ++q) c[q] = (double)X[q * nx + i];
+    if (ks.dt > 0) c[ks.d] = th0;
+    if (ks.dt > 1) c[ks.d + 1] = th1;
+    for (int q = 0; q < ks.d; ++q) c[ks.d + ks.dt + q] = (double)Y[q * ny + j];
+    K[i + j * ldk] = (T)eval_coords(ks, c);
+  }
+}
+
+inline int blocks_for(int64_t n, int bs = 256, int cap = 16384) {
+  int64_t b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  return (int)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr, const int32_t* cols,
+                  int nc, double* out, hipStream_t st) {
+  if (nr <= 0 || nc <= 0) return;
+  hipLaunchKernelGGL(k_eval_product, dim3(blocks_for((int64_t)nr * nc)), dim3(256), 0, st, ks, a, rows,
+                     nr, cols, nc, out);
+}
+
+void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols, int np,
+               double* out, hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_eval_list, dim3(blocks_for(np)), dim3(256), 0, st, ks, a, rows, cols, np, out);
+}
+
+void eval_multi16(const KSpec& ks, const int16_t* idx, int64_t P, double* out, hipStream_t st) {
+  if (P <= 0) return;
+  hipLaunchKernelGGL(k_eval_multi<int16_t>, dim3(blocks_for(P)), dim3(256), 0, st, ks, idx, P, out);
+}
+
+void eval_multi32(const KSpec& ks, const int32_t* idx, int64_t P, double* out, hipStream_t st) {
+  if (P <= 0) return;
+  hipLaunchKernelGGL(k_eval_multi<int32_t>, dim3(blocks_for(P)), dim3(256), 0, st, ks, idx, P, out);
+}
+
+void eval_dense_f32(const KSpec& ks, const float* X, int64_t nx, const float* Y, int64_t ny,
+                    const double* theta, float* K, int64_t ldk, hipStream_t st) {
+  if (nx <= 0 || ny <= 0) return;
+  const double t0 = ks.dt > 0 ? theta[0] : 0.0, t1 = ks.dt > 1 ? theta[1] : 0.0;
+  hipLaunchKernelGGL(k_eval_dense<float>, dim3(blocks_for(nx * ny)), dim3(256), 0, st, ks, X, nx, Y, ny,
+                     t0, t1, K, ldk);
+}
+
+void eval_dense_f64(const KSpec& ks, const double* X, int64_t nx, const double* Y, int64_t ny,
+                    const double* theta, double* K, int64_t ldk, hipStream_t st) {
+  if (nx <= 0 || ny <= 0) return;
+  const double t0 = ks.dt > 0 ? theta[0] : 0.0, t1 = ks.dt > 1 ? theta[1] : 0.0;
+  hipLaunchKernelGGL(k_eval_dense<double>, dim3(blocks_for(nx * ny)), dim3(256), 0, st, ks, X, nx, Y,
+                     ny, t0, t1, K, ldk);
+}
+
+}  // namespace ttk

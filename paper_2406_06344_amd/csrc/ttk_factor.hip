@@ -1,0 +1,158 @@
+// Phase 3 of the offline stage (Algorithm 2): the factor matrices
+//     S <- U_1 G_1^{2},   S <- (U_i face-split S) G_i^{2},  i = 2..d
+// and the mirrored chain for T, evaluated point by point without forming
+// U_i: row p of (U_i face-split S) times G_i^{2} is
+//     out[p, b] = sum_{a, k} S[p, a] q_k(x_{p,i}) G_i[a, k, b].
+// Here the cores are in the Chebyshev coefficient basis (a DCT along mode 2
+// of the nodal cores, Section 2.4's regrouping of the basis sum), so q_k is
+// T_k(t(x)), generated per point by the three-term recurrence in double
+// precision and rounded once.
+//
+// Each stage is a GEMM whose left operand A[p, a + k r_in] = S[p, a] T_k(t_p)
+// is produced on the fly: a workgroup owns TP points, keeps their running
+// rows S in LDS, and forms the next rows 64 columns at a time with a 4 x 4
+// register tile per thread.  Target cores are passed transposed so the
+// target chain (which runs from G_D down to G_{d+dt+1}) uses the same code.
+#include "ttk_internal.h"
+
+namespace ttk {
+
+namespace {
+
+constexpr int FC_THREADS = 256;
+
+struct StageArgs {
+  const void* G2[3];
+  int r_in[3], r_out[3], n[3], coord[3];
+  double lo[3], hi[3];
+  int nst;
+  int rmax;   // max over stages of r_out (and r_in)
+};
+
+template <class T, int TP>
+__global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P, int64_t npts, int d, T* out,
+                                                       int ldo) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sTk = reinterpret_cast<T*>(smem_raw);              // TP x MAXN
+  T* s0 = sTk + TP * MAXN;                              // TP x rmax
+  T* s1 = s0 + (size_t)TP * sa.rmax;                    // TP x rmax
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * TP;
+  // micro-tile: 16 x 16 thread grid -> TP/16 points x 4 columns per thread
+  constexpr int PPT = TP / 16;
+  const int tp = tid / 16, tb = tid % 16;
+  T* sin = s0;
+  T* sout = s1;
+  if (tid < TP) sin[tid * sa.rmax] = (T)1;   // r_0 = 1
+  for (int st = 0; st < sa.nst; ++st) {
+    const int rin = sa.r_in[st], rout = sa.r_out[st], n = sa.n[st];
+    const T* G = static_cast<const T*>(sa.G2[st]);
+    // Chebyshev values of this stage's coordinate
+    if (tid < TP) {
+      const int64_t p = p0 + tid;
+      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * npts + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
+      const double t = (2.0 * x - (sa.lo[st] + sa.hi[st])) / (sa.lo[st] - sa.hi[st]);
+      double tkm = 1.0, tk = t;
+      sTk[tid * MAXN + 0] = (T)1;
+      if (n > 1) sTk[tid * MAXN + 1] = (T)t;
+      for (int k = 2; k < n; ++k) {
+        const double tn = 2.0 * t * tk - tkm;
+        tkm = tk;
+        tk = tn;
+        sTk[tid * MAXN + k] = (T)tn;
+      }
+    }
+    __syncthreads();
+    const int K = rin * n;
+    for (int b0 = 0; b0 < rout; b0 += 64) {
+      T acc[PPT][4];
+#pragma unroll
+      for (int i = 0; i < PPT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+      const int bc = b0 + tb * 4;
+      for (int kk = 0; kk < K; ++kk) {
+        const int a = kk % rin, k = kk / rin;
+        T bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = (bc + j < rout) ? G[(int64_t)kk * rout + bc + j] : (T)0;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+          const int pl = tp * PPT + i;
+          const T av = sin[pl * sa.rmax + a] * sTk[pl * MAXN + k];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += av * bv[j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const int pl = tp * PPT + i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (bc + j < rout) sout[pl * sa.rmax + bc + j] = acc[i][j];
+      }
+    }
+    __syncthreads();
+    T* tmp = sin;
+    sin = sout;
+    sout = tmp;
+  }
+  const int rfin = sa.r_out[sa.nst - 1];
+  for (int e = tid; e < TP * rfin; e += FC_THREADS) {
+    const int pl = e / rfin, b = e % rfin;
+    const int64_t p = p0 + pl;
+    if (p < npts) out[p * ldo + b] = sin[pl * sa.rmax + b];
+  }
+}
+
+template <class T, int TP>
+tt_status launch_tile(const StageArgs& sa, const void* P, int64_t npts, int d, void* out, int ldo, size_t sh,
+                      hipStream_t st) {
+  if (sh > 64 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor<T, TP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  hipLaunchKernelGGL((k_factor<T, TP>), dim3((unsigned)((npts + TP - 1) / TP)), dim3(FC_THREADS), sh, st, sa,
+                     static_cast<const T*>(P), npts, d, static_cast<T*>(out), ldo);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+template <class T>
+tt_status launch_factor(const StageArgs& sa, const void* P, int64_t npts, int d, void* out, int ldo,
+                        hipStream_t st) {
+  int dev = 0, lds = 64 * 1024;
+  TTK_HIP(hipGetDevice(&dev));
+  TTK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t per_tp = (size_t)(MAXN + 2 * sa.rmax) * sizeof(T);
+  // the largest point tile whose LDS footprint fits one workgroup
+  if (per_tp * 64 <= (size_t)lds) return launch_tile<T, 64>(sa, P, npts, d, out, ldo, per_tp * 64, st);
+  if (per_tp * 32 <= (size_t)lds) return launch_tile<T, 32>(sa, P, npts, d, out, ldo, per_tp * 32, st);
+  if (per_tp * 16 <= (size_t)lds) return launch_tile<T, 16>(sa, P, npts, d, out, ldo, per_tp * 16, st);
+  return fail(TTK_ERR_UNSUPPORTED, "Phase 3 tile for rank %d does not fit %d bytes of LDS", sa.rmax, lds);
+}
+
+}  // namespace
+
+tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, const void* P_soa, int64_t npts,
+                          void* out, int ldo, hipStream_t st) {
+  if (npts <= 0) return TTK_OK;
+  StageArgs sa{};
+  sa.nst = nstages;
+  sa.rmax = 1;
+  for (int i = 0; i < nstages; ++i) {
+    sa.G2[i] = stages[i].G2;
+    sa.r_in[i] = stages[i].r_in;
+    sa.r_out[i] = stages[i].r_out;
+    sa.n[i] = stages[i].n;
+    sa.coord[i] = stages[i].coord;
+    sa.lo[i] = stages[i].lo;
+    sa.hi[i] = stages[i].hi;
+    sa.rmax = std::max(sa.rmax, std::max(stages[i].r_in, stages[i].r_out));
+  }
+  int d = 0;
+  for (int i = 0; i < nstages; ++i) d = std::max(d, stages[i].coord + 1);
+  if (dtype == TTK_FP32) return launch_factor<float>(sa, P_soa, npts, d, out, ldo, st);
+  return launch_factor<double>(sa, P_soa, npts, d, out, ldo, st);
+}
+
+}  // namespace ttk

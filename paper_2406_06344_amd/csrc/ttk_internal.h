@@ -1,0 +1,177 @@
+// Internal declarations shared by the host-side translation units of the
+// PTTK library.  Device code of one unit is launched only through the host
+// wrappers declared here, so no relocatable device code is needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tt_kernel.h"
+
+namespace ttk {
+
+constexpr int MAXD = 8;    // 2 d + d_theta with d <= 3, d_theta <= 2
+constexpr int MAXN = 32;   // Chebyshev nodes per dimension
+constexpr int MAXR = 256;  // TT rank cap
+
+// Kernel-function description passed by value to device code.
+struct KSpec {
+  int kind;
+  int d, dt, D;
+  double kconst;
+  const double* nodes;  // device, D x MAXN: node eta_i of dimension j at j*MAXN + i
+};
+
+// Thread-local error message behind tt_kernel_last_error().
+void set_error(const char* fmt, ...);
+tt_status fail(tt_status s, const char* fmt, ...);
+
+#define TTK_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::ttk::fail(TTK_ERR_HIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_),  \
+                         __FILE__, __LINE__);                                          \
+  } while (0)
+
+#define TTK_TRY(expr)            \
+  do {                           \
+    tt_status s_ = (expr);       \
+    if (s_ < 0) return s_;       \
+  } while (0)
+
+// Owning device buffer.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
+  tt_status alloc(size_t nbytes);          // grows only; contents undefined
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host staging buffer (allocated, never registered).
+struct HBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  ~HBuf() { if (p) (void)hipHostFree(p); }
+  tt_status alloc(size_t nbytes);
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------- problem
+struct Grid {
+  int d = 0, dt = 0, D = 0;
+  int n[MAXD] = {0};
+  double lo[MAXD] = {0}, hi[MAXD] = {0};   // box of dimension j in (x, theta, y) order
+  double nodes[MAXD * MAXN] = {0};          // host copy of the node table
+};
+tt_status make_grid(const tt_kernel_params* p, Grid* g);
+
+// ---------------------------------------------------------- kernel entries
+// Entries of the super-core unfolding / fibre addressed through index sets
+// (see ttk_eval.hip): multi-index = (left[s], mid..., right[t]).
+struct Addr {
+  const int16_t* left;   // rl x lk row-major (lk = number of leading dims)
+  const int16_t* right;  // rr x lr row-major (lr = number of trailing dims)
+  int rl, lk, rr, lr;
+  int nmid;              // 1 (fibre) or 2 (super-core)
+  int nm0, nm1;          // node counts of the middle dims
+};
+// out[i + j*nr] = A(rows[i], cols[j]); rows/cols NULL = all rows/cols.
+void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr,
+                  const int32_t* cols, int nc, double* out, hipStream_t st);
+// out[i] = A(rows[i], cols[i]); a NULL list means "the single value *one"
+void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols,
+               int np, double* out, hipStream_t st);
+// out[i] = f_kappa at multi-index idx[i*D .. i*D+D-1] (int16 or int32)
+void eval_multi16(const KSpec& ks, const int16_t* idx, int64_t P, double* out, hipStream_t st);
+void eval_multi32(const KSpec& ks, const int32_t* idx, int64_t P, double* out, hipStream_t st);
+// dense block K[i + j*ldk] = kappa(x_i, y_j; theta), T = float or double
+void eval_dense_f32(const KSpec& ks, const float* X, int64_t nx, const float* Y, int64_t ny,
+                    const double* theta, float* K, int64_t ldk, hipStream_t st);
+void eval_dense_f64(const KSpec& ks, const double* X, int64_t nx, const double* Y, int64_t ny,
+                    const double* theta, double* K, int64_t ldk, hipStream_t st);
+
+// --------------------------------------------------- small dense FP64 algebra
+// All column-major, one workgroup per call unless stated (ttk_linalg.hip).
+void lu_factor(double* A, int n, int lda, int32_t* piv, int32_t* info, hipStream_t st);
+// Solve A X = B (trans = 0) or A^T X = B (trans = 1) for nrhs columns, in place.
+void lu_solve(const double* LU, int n, int lda, const int32_t* piv, int trans, double* B,
+              int ldb, int nrhs, hipStream_t st);
+// Thin Householder QR of A (m x n, m >= n): A <- Q (m x n), R (n x n).
+void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st);
+// One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
+// sigma (n); columns sorted by decreasing sigma.
+void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);
+// C = alpha op(A) op(B) + beta C, small FP64 GEMM (many blocks).
+void gemm64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
+            const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
+// Frobenius norm of a vector into *out (device).
+void nrm2(const double* x, int64_t n, double* out, hipStream_t st);
+
+// ----------------------------------------------------------- the cross
+struct CrossOut {
+  std::vector<int> ranks;                     // r_0..r_D
+  std::vector<std::vector<double>> cores;     // host FP64, little-endian r0 x n x r1
+  std::vector<std::vector<int32_t>> left;     // I^{<=k}, k = 0..D
+  std::vector<std::vector<int32_t>> right;    // I^{>k},  k = 0..D
+  std::vector<tt_kernel_decision> log;
+  int sweeps = 0;
+  double error = 0.0, init_max_cond = 0.0, min_margin = 1.0;
+  int64_t evals = 0;
+  bool converged = false;
+};
+tt_status run_cross(const tt_kernel_params* p, const Grid& g, const KSpec& ks,
+                    hipStream_t st, CrossOut* out);
+
+// -------------------------------------------------- rounding and gauge
+// TT-Round + gauge + signs of host FP64 cores, computed on the device.
+tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>& ranks,
+                      const Grid& g, double eps, hipStream_t st);
+
+// ----------------------------------------------------------- Phase 3
+struct ChainStage {
+  const void* G2;     // device, dtype, row-major (r_in * n) x r_out, row index a + k r_in
+  int r_in, r_out, n;
+  int coord;          // which coordinate of the point feeds this stage
+  double lo, hi;      // box of that coordinate
+};
+tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, const void* P_soa,
+                          int64_t npts, void* out, int ldo, hipStream_t st);
+
+// ----------------------------------------------------------- online / apply
+struct ParamCore {
+  const double* Ghat;  // device FP64, coefficient-basis core, r0 x n x r1 little-endian
+  int r0, n, r1;
+  double lo, hi;
+};
+void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M,
+                 void* dM, double* work, hipStream_t st);
+size_t online_work_doubles(const ParamCore* pc, int dt, int B);
+
+void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
+                  int B, void* W, hipStream_t st);   // W (r x B) = F^T X
+void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B,
+                  void* Y, int64_t ldy, hipStream_t st);  // Y (N x B) = F Z
+void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
+                    int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
+void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,
+                      int B, int dt, void* dtheta, hipStream_t st);  // dtheta[b,j] = a_b^T dM_bj w_b
+void fill_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace ttk

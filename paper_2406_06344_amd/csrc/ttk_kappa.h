@@ -1,0 +1,77 @@
+// Device evaluation of the kernel functions of Table 1 (r = ||x - y||_2)
+// and of the two test kernels, in double precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tt_kernel.h"
+
+namespace ttk {
+
+// z^nu K_nu(z) for z > 0, from the integral K_nu(z) = int_0^inf exp(-z cosh t)
+// cosh(nu t) dt (Abramowitz & Stegun 9.6.24) by the trapezoidal rule, which
+// converges exponentially for this analytic, doubly-exponentially decaying
+// integrand (Trefethen & Weideman, SIAM Review 2014).  The step shrinks like
+// 1/sqrt(z) because the integrand's width does; terms are summed as
+// exp(nu (ln z + t) - z cosh t) (1 + exp(-2 nu t)) / 2 so that z^nu never
+// overflows.  All terms are positive: no cancellation.
+__device__ inline double zpow_besselk(double nu, double z) {
+  const double h = fmin(0.1, 0.5 / sqrt(z));
+  const double lz = log(z);
+  double s = 0.5 * exp(nu * lz - z);
+  const double tstar = asinh(nu / z);   // the integrand peaks at sinh t = nu / z
+  for (int j = 1; j < 20000; ++j) {
+    const double t = j * h;
+    const double term = exp(nu * (lz + t) - z * cosh(t)) * 0.5 * (1.0 + exp(-2.0 * nu * t));
+    s += term;
+    if (t > tstar && term < 1e-18 * s) break;
+  }
+  return h * s;
+}
+
+// Matern with smoothness nu and length scale ell: 2^(1-nu)/Gamma(nu) z^nu K_nu(z),
+// z = sqrt(2 nu) r / ell; the r -> 0 limit is 1.
+__device__ inline double matern_general(double r, double ell, double nu) {
+  if (r <= 0.0) return 1.0;
+  const double z = sqrt(2.0 * nu) * r / ell;
+  return exp2(1.0 - nu) / tgamma(nu) * zpow_besselk(nu, z);
+}
+
+// kappa(x, y; theta) for the kind in tt_kernel_kind.
+__device__ inline double kappa_eval(int kind, int d, double kconst, const double* x,
+                                    const double* th, const double* y) {
+  if (kind == TTK_TEST_POLY) {
+    double dot = 0.0;
+    for (int j = 0; j < d; ++j) dot += x[j] * y[j];
+    const double u = 1.0 + th[0] * dot;
+    return u * u * u;
+  }
+  if (kind == TTK_TEST_SEP) {
+    double sx = 0.0, sy = 0.0;
+    for (int j = 0; j < d; ++j) { sx += x[j]; sy += y[j]; }
+    return exp(sx) * th[0] * exp(-sy);
+  }
+  double r2 = 0.0;
+  for (int j = 0; j < d; ++j) { const double t = x[j] - y[j]; r2 += t * t; }
+  const double r = sqrt(r2);
+  switch (kind) {
+    case TTK_SE: { const double u = r / th[0]; return exp(-u * u); }
+    case TTK_EXPONENTIAL: return exp(-r / th[0]);
+    case TTK_MATERN32: { const double a = 1.7320508075688772 * r / th[0]; return (1.0 + a) * exp(-a); }
+    case TTK_MATERN52: {
+      const double a = 2.23606797749979 * r / th[0];
+      return (1.0 + a + a * a / 3.0) * exp(-a);
+    }
+    case TTK_MATERN_NU: return matern_general(r, th[0], kconst);
+    case TTK_MATERN: return matern_general(r, th[0], th[1]);
+    case TTK_MULTIQUADRIC: { const double u = r / th[0]; return sqrt(1.0 + u * u); }
+    case TTK_TPS: { const double u = r2 / (th[0] * th[0]); return u > 0.0 ? u * log(u) : 0.0; }
+    case TTK_LAPLACE3D: return 1.0 / r;
+    case TTK_LAPLACE2D: return -log(r);
+    case TTK_BIHARMONIC: return 1.0 / r2;
+    case TTK_THINPLATE: return r2 * log(r);
+    default: return __builtin_nan("");
+  }
+}
+
+}  // namespace ttk

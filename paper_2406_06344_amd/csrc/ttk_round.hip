@@ -1,0 +1,205 @@
+// TT-Round (Algorithm 1) of the cross cores, then the gauge used by Phase 3:
+// after the rounding sweep the cores G_1..G_{D-1} are left-orthonormal; the
+// target cores G_D..G_{d+dt+1} are then right-orthonormalised (thin QR of
+// (G^{1})^T, R pushed into the left neighbour), so the last parameter core
+// carries the norm.  Signs: the largest-|.| entry of each column of a
+// left-orthonormal G^{2} (row of a right-orthonormal G^{1}) is made positive,
+// lowest index on ties, and the sign is pushed into the neighbour.
+// Every factorisation runs on the device in double precision; the host only
+// reads back singular values to choose the truncation rank.
+//
+// Readings: ||X||_F is taken as ||G_1||_F after the orthogonalisation sweep;
+// the truncation keeps the smallest r' >= 1 whose discarded tail
+// sqrt(sum_{i > r'} sigma_i^2) is <= delta = eps / sqrt(D - 1) ||X||_F; the
+// mode-3 update of the orthogonalisation is G_{i-1}^{2} <- G_{i-1}^{2} R^T.
+#include <cmath>
+
+#include "ttk_internal.h"
+
+namespace ttk {
+
+namespace {
+
+__global__ void k_transpose64(const double* A, int m, int n, int lda, double* B, int ldb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
+}
+
+// W[a, b] = sigma[a] * V[b, a] for a < rp, b < r  (W = (Sigma V^T)[:rp, :], ld rp)
+__global__ void k_sigma_vt(const double* sigma, const double* V, int r, int rp, double* W) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rp * r) return;
+  const int a = e % rp, b = e / rp;
+  W[a + b * rp] = sigma[a] * V[b + a * r];
+}
+
+// Sign of the largest-|.| entry of each column of A (m x c), lowest row on ties.
+__global__ void k_col_signs(const double* A, int m, int c, int lda, double* sg) {
+  const int col = blockIdx.x;
+  __shared__ double sv[256];
+  __shared__ int si[256];
+  double best = -1.0;
+  int bi = 0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double v = fabs(A[i + (int64_t)col * lda]);
+    if (v > best) { best = v; bi = i; }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double a = sv[threadIdx.x], b = sv[threadIdx.x + s];
+      if (b > a || (b == a && si[threadIdx.x + s] < si[threadIdx.x])) {
+        sv[threadIdx.x] = b;
+        si[threadIdx.x] = si[threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = A[si[0] + (int64_t)col * lda];
+    sg[col] = v < 0.0 ? -1.0 : 1.0;
+  }
+}
+
+// A[:, j] *= sg[j] (mode 0) or A[i, :] *= sg[i] (mode 1), A m x c.
+__global__ void k_scale(double* A, int m, int c, int lda, const double* sg, int mode) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * c) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  A[i + (int64_t)j * lda] *= (mode == 0) ? sg[j] : sg[i];
+}
+
+inline int nb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+struct Cores {
+  std::vector<DBuf> g;        // device copies, core k as G^{2}/G^{1}-compatible memory
+  std::vector<int> r;         // r_0..r_D
+  std::vector<int> n;
+};
+
+// thin QR of (G_i^{1})^T, G_i <- Q^T, G_{i-1}^{2} <- G_{i-1}^{2} R^T
+tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipStream_t st) {
+  const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
+  const int m = n * r1;
+  TTK_TRY(A.alloc((size_t)m * r0 * sizeof(double)));
+  TTK_TRY(R.alloc((size_t)r0 * r0 * sizeof(double)));
+  TTK_TRY(tau.alloc((size_t)(r0 + 64) * sizeof(double)));
+  double* G = c.g[i].as<double>();
+  hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, G, r0, m, r0, A.as<double>(),
+                     m);
+  qr_thin(A.as<double>(), m, r0, m, R.as<double>(), r0, tau.as<double>(), st);
+  hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, A.as<double>(), m, r0, m, G,
+                     r0);
+  const int q0 = c.r[i - 1], qn = c.n[i - 1];
+  TTK_TRY(T.alloc((size_t)q0 * qn * r0 * sizeof(double)));
+  gemm64(0, 1, q0 * qn, r0, r0, 1.0, c.g[i - 1].as<double>(), q0 * qn, R.as<double>(), r0, 0.0, T.as<double>(),
+         q0 * qn, st);
+  TTK_HIP(hipMemcpyAsync(c.g[i - 1].p, T.p, (size_t)q0 * qn * r0 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  TTK_HIP(hipStreamSynchronize(st));   // A, R, T are resized by the next call
+  return TTK_OK;
+}
+
+}  // namespace
+
+tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>& ranks, const Grid& grid,
+                      double eps, hipStream_t st) {
+  const int D = (int)cores.size();
+  Cores c;
+  c.r = ranks;
+  c.n.assign(grid.n, grid.n + D);
+  c.g.resize(D);
+  for (int k = 0; k < D; ++k) {
+    const size_t cnt = (size_t)c.r[k] * c.n[k] * c.r[k + 1];
+    TTK_TRY(c.g[k].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
+    TTK_HIP(hipMemcpyAsync(c.g[k].p, cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
+  }
+  DBuf A, R, T, tau, V, sig, W, nrm, sg;
+  // right-to-left orthogonalisation
+  for (int i = D - 1; i >= 1; --i) TTK_TRY(orth_right(c, i, A, R, T, tau, st));
+  TTK_TRY(nrm.alloc(sizeof(double)));
+  nrm2(c.g[0].as<double>(), (int64_t)c.r[0] * c.n[0] * c.r[1], nrm.as<double>(), st);
+  double norm = 0.0;
+  TTK_HIP(hipMemcpyAsync(&norm, nrm.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  TTK_HIP(hipStreamSynchronize(st));
+  const double delta = eps / std::sqrt((double)std::max(D - 1, 1)) * norm;
+  // left-to-right truncated SVD
+  std::vector<double> hs;
+  for (int i = 0; i < D - 1; ++i) {
+    const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
+    const int m = r0 * n;
+    TTK_TRY(A.alloc((size_t)m * r1 * sizeof(double)));
+    TTK_TRY(R.alloc((size_t)r1 * r1 * sizeof(double)));
+    TTK_TRY(tau.alloc((size_t)(r1 + 64) * sizeof(double)));
+    TTK_TRY(V.alloc((size_t)r1 * r1 * sizeof(double)));
+    TTK_TRY(sig.alloc(((size_t)r1 * r1 + 3 * (size_t)r1 + 64) * sizeof(double)));
+    TTK_HIP(hipMemcpyAsync(A.p, c.g[i].p, (size_t)m * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    qr_thin(A.as<double>(), m, r1, m, R.as<double>(), r1, tau.as<double>(), st);
+    jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
+    hs.resize(r1);
+    TTK_HIP(hipMemcpyAsync(hs.data(), sig.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TTK_HIP(hipStreamSynchronize(st));
+    int rp = r1;
+    {
+      std::vector<double> tail(r1 + 1, 0.0);
+      for (int j = r1 - 1; j >= 0; --j) tail[j] = tail[j + 1] + hs[j] * hs[j];
+      for (int q = 1; q <= r1; ++q)
+        if (std::sqrt(tail[q]) <= delta) { rp = q; break; }
+    }
+    // G_i^{2} <- Q U_R[:, :rp]
+    gemm64(0, 0, m, rp, r1, 1.0, A.as<double>(), m, R.as<double>(), r1, 0.0, c.g[i].as<double>(), m, st);
+    // G_{i+1}^{1} <- (Sigma V^T)[:rp, :] G_{i+1}^{1}
+    const int n2 = c.n[i + 1], r2 = c.r[i + 2];
+    TTK_TRY(W.alloc((size_t)rp * r1 * sizeof(double)));
+    hipLaunchKernelGGL(k_sigma_vt, dim3(nb((int64_t)rp * r1)), dim3(256), 0, st, sig.as<double>(), V.as<double>(),
+                       r1, rp, W.as<double>());
+    TTK_TRY(T.alloc((size_t)rp * n2 * r2 * sizeof(double)));
+    gemm64(0, 0, rp, n2 * r2, r1, 1.0, W.as<double>(), rp, c.g[i + 1].as<double>(), r1, 0.0, T.as<double>(), rp,
+           st);
+    TTK_HIP(hipMemcpyAsync(c.g[i + 1].p, T.p, (size_t)rp * n2 * r2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    c.r[i + 1] = rp;
+  }
+  // gauge: right-orthonormal target cores
+  const int first_target = grid.d + grid.dt;
+  for (int i = D - 1; i >= first_target && i >= 1; --i) TTK_TRY(orth_right(c, i, A, R, T, tau, st));
+  // signs
+  TTK_TRY(sg.alloc((size_t)MAXR * sizeof(double)));
+  for (int i = 0; i + 1 < first_target; ++i) {
+    const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
+    hipLaunchKernelGGL(k_col_signs, dim3(r1), dim3(256), 0, st, c.g[i].as<double>(), r0 * n, r1, r0 * n,
+                       sg.as<double>());
+    hipLaunchKernelGGL(k_scale, dim3(nb((int64_t)r0 * n * r1)), dim3(256), 0, st, c.g[i].as<double>(), r0 * n, r1,
+                       r0 * n, sg.as<double>(), 0);
+    const int n2 = c.n[i + 1], r2 = c.r[i + 2];
+    hipLaunchKernelGGL(k_scale, dim3(nb((int64_t)r1 * n2 * r2)), dim3(256), 0, st, c.g[i + 1].as<double>(), r1,
+                       n2 * r2, r1, sg.as<double>(), 1);
+  }
+  for (int i = D - 1; i >= first_target && i >= 1; --i) {
+    const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
+    // rows of G^{1} (r0 x n r1) = columns of its transpose
+    TTK_TRY(A.alloc((size_t)r0 * n * r1 * sizeof(double)));
+    hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * n * r1)), dim3(256), 0, st, c.g[i].as<double>(), r0,
+                       n * r1, r0, A.as<double>(), n * r1);
+    hipLaunchKernelGGL(k_col_signs, dim3(r0), dim3(256), 0, st, A.as<double>(), n * r1, r0, n * r1,
+                       sg.as<double>());
+    hipLaunchKernelGGL(k_scale, dim3(nb((int64_t)r0 * n * r1)), dim3(256), 0, st, c.g[i].as<double>(), r0, n * r1,
+                       r0, sg.as<double>(), 1);
+    const int q0 = c.r[i - 1], qn = c.n[i - 1];
+    hipLaunchKernelGGL(k_scale, dim3(nb((int64_t)q0 * qn * r0)), dim3(256), 0, st, c.g[i - 1].as<double>(),
+                       q0 * qn, r0, q0 * qn, sg.as<double>(), 0);
+  }
+  TTK_HIP(hipGetLastError());
+  for (int k = 0; k < D; ++k) {
+    const size_t cnt = (size_t)c.r[k] * c.n[k] * c.r[k + 1];
+    cores[k].resize(cnt);
+    TTK_HIP(hipMemcpyAsync(cores[k].data(), c.g[k].p, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  TTK_HIP(hipStreamSynchronize(st));
+  ranks = c.r;
+  return TTK_OK;
+}
+
+}  // namespace ttk
