@@ -27,9 +27,10 @@ Readings of the paper taken here (each written out in the design notes):
   (seed, TAG_TEST); also stops when a whole sweep adds no pivot or after
   max_sweeps sweeps.
 * Interpolation formula: C_k = F_k P_k^{-1} with F_k = X(I^{<=k-1}, :, I^{>k})
-  unfolded to (r_{k-1} n_k) x r_k and P_k = X(I^{<=k}, I^{>k}) its row subset;
-  the final cores are computed as Q Q[J,:]^{-1} from the thin QR F_k = Q R,
-  the stopping test uses the direct LU solve.  C_N = F_N.
+  unfolded to (r_{k-1} n_k) x r_k and P_k = X(I^{<=k}, I^{>k}) its row subset,
+  applied by a direct LU solve.  The cores returned are those whose sampled
+  error the stopping test measured last.  C_N = F_N.  (The QR form
+  Q Q[J,:]^{-1} of F_k = Q R, equal in exact arithmetic, stays available.)
 * Initialisation (Algorithm 7): q_1, q_2 are full random multi-indices; a
   snapshot (all sets, max condition number of the half-sweep) is kept after
   every half-sweep and the one with the smallest maximum is returned (earliest
@@ -384,7 +385,7 @@ def greedy_cross(ent, eps, seed=0, max_rank=256, max_sweeps=200, init_card=2, in
         errs.append(err)
         if added == 0 and forced is None:
             break
-    cores = interp_cores(ent, L, R, method="qr")
+    cores = interp_cores(ent, L, R, method="lu")
     info = {"L": L, "R": R, "log": log, "sweeps": sweep, "errors": errs, "error": err,
             "converged": err <= eps, "evals": ent.count, "init": init_info,
             "ranks": [1] + [L[k].shape[0] for k in range(1, N)] + [1]}

@@ -15,8 +15,13 @@
 // largest |entry| evaluated so far in the step) go to the lowest position;
 // a pivot is added only if |R| exceeds that band, is new, and the rank is
 // below the cap.  Stopping: max |X - X^| / max |X| over n_test fixed
-// multi-indices (stream (seed, 3)), with cores from C_k = F_k P_k^{-1} (LU);
-// final cores from the QR form C_k = Q Q[J,:]^{-1}.
+// multi-indices (stream (seed, 3)), with cores C_k = F_k P_k^{-1} (LU solve);
+// the cores returned are those of the last stopping test.
+//
+// The LU factorisation of each intersection matrix P_k = X(I^{<=k}, I^{>k})
+// is cached per k: P_k changes only when step k appends a pivot, and the
+// stopping test solves with P_k^T through the same factors.  Right-hand
+// sides are laid out with their index fastest so a solve reads coalesced.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -120,6 +125,7 @@ __global__ void k_select(const double* R, int n, const int32_t* srow, const int3
     if (stage == 0) {
       res->s_pos = p; res->s_max = mx; res->s_margin = margin; res->s_tau = tau;
       res->l = srow[p]; res->t = scol[p];
+      res->q_scale = res->s_scale;      // the search stage widens this scale
     } else {
       res->q_pos = p; res->q_max = mx; res->q_margin = margin; res->q_tau = tau;
       res->pivot_abs = fabs(R[p]);
@@ -129,6 +135,7 @@ __global__ void k_select(const double* R, int n, const int32_t* srow, const int3
 
 __global__ void k_finalize(StepRes* res, int bit, const int32_t* I, const int32_t* J, int rk,
                            int max_rank, const int32_t* info) {
+  // (info: LU status of the cached factorisation of A(I, J))
   if (threadIdx.x != 0) return;
   const int row = bit ? res->l : res->q_pos;
   const int col = bit ? res->q_pos : res->t;
@@ -219,12 +226,13 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
   B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
 }
 
-// TT value at test multi-indices: cores given as CT_k (r_k x r_{k-1} n_k,
-// column-major), entry C_k[s, i, t] = CT_k[t + (s + i r_{k-1}) r_k].
+// TT value at test multi-indices: cores given column-major C_k
+// ((r_{k-1} n_k) x r_k), entry C_k[s, i, t] = C_k[(s + i r_{k-1}) + t r_{k-1} n_k].
 // One wave per point, the running vector in LDS.
 struct TTView {
-  const double* CT[MAXD];
+  const double* C[MAXD];
   int r[MAXD + 1];
+  int m[MAXD];
   int D;
 };
 __global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx, int P, double* out) {
@@ -239,10 +247,10 @@ __global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx
   for (int k = 0; k < tv.D; ++k) {
     const int r0 = tv.r[k], r1 = tv.r[k + 1];
     const int i = idx[(int64_t)p * tv.D + k];
-    const double* blk = tv.CT[k] + (int64_t)i * r0 * r1;   // r1 x r0 block
+    const double* blk = tv.C[k] + (int64_t)i * r0;     // rows s + i r0
     for (int t = lane; t < r1; t += 64) {
       double s = 0.0;
-      for (int q = 0; q < r0; ++q) s += blk[t + (int64_t)q * r1] * v[q];
+      for (int q = 0; q < r0; ++q) s += blk[q + (int64_t)t * tv.m[k]] * v[q];
       vn[t] = s;
     }
     __builtin_amdgcn_wave_barrier();
@@ -262,6 +270,14 @@ __global__ void k_err_max(const double* a, const double* b, int n, double* out) 
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_set_scale(StepRes* res, const double* base) {
+  if (threadIdx.x == 0) { res->s_scale = *base; res->q_scale = 0.0; }
+}
+
+__global__ void k_zero1(double* p) {
+  if (threadIdx.x == 0) *p = 0.0;
 }
 
 inline int nblk(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
@@ -291,7 +307,8 @@ class Cross {
   tt_status upload_sets(int k_left, int k_right, int16_t* dl, int16_t* dr);
   tt_status init_sets();
   tt_status update_step(int k, int sweep, tt_kernel_decision* rec);
-  tt_status build_cores(bool qr, std::vector<double*>* CT);
+  tt_status build_cores(std::vector<double*>* C);
+  tt_status factor_from_rows(int k, const double* F, int ldf, const int32_t* rows);
   tt_status sampled_error(double* err);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
@@ -307,9 +324,45 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_idx_, d_vals_, d_lu_, d_piv_, d_info_, d_res_, d_scratch_, d_R_;
+  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_;
   DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_fib_, d_tmp_, d_P_, d_err_;
+  // cached LU of P_k per k: factors, pivots, info and max |entry| of P_k
+  DBuf d_lu_[MAXD], d_lupiv_[MAXD], d_luaux_;
+  bool lu_valid_[MAXD] = {false};
+  double* luamax(int k) { return d_luaux_.as<double>() + k; }
+  int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
   HBuf h_stage_, h_res_;
+  // upload arena: host pinned + device mirror, bump-allocated between stream
+  // synchronisations, flushed with one copy before the kernels that read it
+  HBuf ar_h_;
+  DBuf ar_d_;
+  size_t ar_off_ = 0, ar_flushed_ = 0, ar_cap_ = 0;
+  const int16_t* cur_left_ = nullptr;
+  const int16_t* cur_right_ = nullptr;
+  tt_status arena_init(size_t bytes) {
+    ar_cap_ = bytes;
+    TTK_TRY(ar_h_.alloc(bytes));
+    TTK_TRY(ar_d_.alloc(bytes));
+    return TTK_OK;
+  }
+  void arena_reset() { ar_off_ = ar_flushed_ = 0; }   // only after a stream synchronisation
+  template <class T>
+  tt_status arena_push(const T* src, size_t n, const T** dev) {
+    const size_t at = (ar_off_ + 255) & ~(size_t)255;
+    const size_t bytes = n * sizeof(T);
+    if (at + bytes > ar_cap_) return fail(TTK_ERR_OOM, "cross upload arena too small (%zu bytes)", ar_cap_);
+    if (bytes) std::memcpy(ar_h_.as<char>() + at, src, bytes);
+    *dev = reinterpret_cast<const T*>(ar_d_.as<char>() + at);
+    ar_off_ = at + bytes;
+    return TTK_OK;
+  }
+  tt_status arena_flush() {
+    if (ar_off_ > ar_flushed_)
+      TTK_HIP(hipMemcpyAsync(ar_d_.as<char>() + ar_flushed_, ar_h_.as<char>() + ar_flushed_, ar_off_ - ar_flushed_,
+                             hipMemcpyHostToDevice, st_));
+    ar_flushed_ = ar_off_;
+    return TTK_OK;
+  }
   int n_test_ = 0;
   double test_max_ = 0.0;
   double init_max_cond_ = 0.0;
@@ -317,8 +370,8 @@ class Cross {
 
 Addr Cross::fibre_addr(int k) const {
   Addr a{};
-  a.left = d_left_.as<int16_t>();
-  a.right = d_right_.as<int16_t>();
+  a.left = cur_left_;
+  a.right = cur_right_;
   a.rl = rank(k - 1);
   a.lk = k - 1;
   a.rr = rank(k);
@@ -331,8 +384,8 @@ Addr Cross::fibre_addr(int k) const {
 
 Addr Cross::super_addr(int k) const {
   Addr a{};
-  a.left = d_left_.as<int16_t>();
-  a.right = d_right_.as<int16_t>();
+  a.left = cur_left_;
+  a.right = cur_right_;
   a.rl = rank(k - 1);
   a.lk = k - 1;
   a.rr = rank(k + 1);
@@ -343,18 +396,17 @@ Addr Cross::super_addr(int k) const {
   return a;
 }
 
-// Upload I^{<=k_left} and I^{>k_right} as int16 row-major arrays.
-tt_status Cross::upload_sets(int k_left, int k_right, int16_t* dl, int16_t* dr) {
+// Stage I^{<=k_left} and I^{>k_right} (int16, row-major) in the upload arena;
+// cur_left_ / cur_right_ point at their device copies after the next flush.
+tt_status Cross::upload_sets(int k_left, int k_right, int16_t*, int16_t*) {
   const size_t nl = (k_left == 0) ? 0 : L_[k_left].size();
   const size_t nr = (k_right == N_) ? 0 : R_[k_right].size();
-  TTK_TRY(h_stage_.alloc((nl + nr + 2) * sizeof(int16_t)));
-  int16_t* h = h_stage_.as<int16_t>();
-  for (size_t i = 0; i < nl; ++i) h[i] = (int16_t)L_[k_left][i];
-  for (size_t i = 0; i < nr; ++i) h[nl + i] = (int16_t)R_[k_right][i];
-  if (nl) TTK_HIP(hipMemcpyAsync(dl, h, nl * sizeof(int16_t), hipMemcpyHostToDevice, st_));
-  if (nr) TTK_HIP(hipMemcpyAsync(dr, h + nl, nr * sizeof(int16_t), hipMemcpyHostToDevice, st_));
-  // the staging buffer is reused by the next call: wait for the copies
-  return sync();
+  std::vector<int16_t> tmp(nl + nr + 1);
+  for (size_t i = 0; i < nl; ++i) tmp[i] = (int16_t)L_[k_left][i];
+  for (size_t i = 0; i < nr; ++i) tmp[nl + i] = (int16_t)R_[k_right][i];
+  TTK_TRY(arena_push(tmp.data(), nl + 1, &cur_left_));
+  TTK_TRY(arena_push(tmp.data() + nl, nr + 1, &cur_right_));
+  return TTK_OK;
 }
 
 tt_status Cross::init_sets() {
@@ -391,10 +443,12 @@ tt_status Cross::init_sets() {
   double* dval = reinterpret_cast<double*>(d_res_.as<char>() + 8);
   auto probe = [&](int k, int mode, int kl, int kr, int* j1, int* j2, double* cv) -> tt_status {
     // two-row sets I^{<=kl} (kl = k-1) and I^{>kr} (kr = k): fibre of dimension k-1
-    TTK_TRY(upload_sets(kl, kr, d_left_.as<int16_t>(), d_right_.as<int16_t>()));
+    arena_reset();
+    TTK_TRY(upload_sets(kl, kr, nullptr, nullptr));
+    TTK_TRY(arena_flush());
     Addr a{};
-    a.left = d_left_.as<int16_t>();
-    a.right = d_right_.as<int16_t>();
+    a.left = cur_left_;
+    a.right = cur_right_;
     a.rl = (kl == 0) ? 1 : 2;
     a.lk = kl;
     a.rr = (kr == N) ? 1 : 2;
@@ -490,86 +544,89 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const int ns = std::max(rows, cols);
   std::vector<int64_t> lin = g.floyd((int64_t)rows * cols, ns);
   const int bit = g.bit();
-  // upload the neighbouring sets and the integer lists
-  TTK_TRY(d_left_.alloc(std::max<size_t>(2, L_[k - 1].size()) * sizeof(int16_t)));
-  TTK_TRY(d_right_.alloc(std::max<size_t>(2, (k + 1 < N ? R_[k + 1].size() : 0)) * sizeof(int16_t)));
-  TTK_TRY(upload_sets(k - 1, k + 1, d_left_.as<int16_t>(), d_right_.as<int16_t>()));
+  // upload the neighbouring sets and the integer lists in one copy
+  arena_reset();
+  TTK_TRY(upload_sets(k - 1, k + 1, nullptr, nullptr));
   const size_t nint = (size_t)2 * rk + 2 * (size_t)ns;
-  TTK_TRY(d_idx_.alloc(nint * sizeof(int32_t)));
-  TTK_TRY(h_stage_.alloc(nint * sizeof(int32_t)));
-  int32_t* hi = h_stage_.as<int32_t>();
-  std::copy(I.begin(), I.end(), hi);
-  std::copy(J.begin(), J.end(), hi + rk);
+  std::vector<int32_t> hi(nint);
+  std::copy(I.begin(), I.end(), hi.begin());
+  std::copy(J.begin(), J.end(), hi.begin() + rk);
   for (int i = 0; i < ns; ++i) {
     hi[2 * rk + i] = (int32_t)(lin[i] / cols);
     hi[2 * rk + ns + i] = (int32_t)(lin[i] % cols);
   }
-  TTK_HIP(hipMemcpyAsync(d_idx_.p, hi, nint * sizeof(int32_t), hipMemcpyHostToDevice, st_));
-  const int32_t* dI = d_idx_.as<int32_t>();
+  const int32_t* dI = nullptr;
+  TTK_TRY(arena_push(hi.data(), nint, &dI));
+  TTK_TRY(arena_flush());
   const int32_t* dJ = dI + rk;
   const int32_t* dsr = dJ + rk;
   const int32_t* dsc = dsr + ns;
   // value buffers
   const size_t nsearch = std::max((size_t)rk + (size_t)rk * cols + cols, (size_t)rows * rk + rk + rows);
-  const size_t nvals = (size_t)rk * rk + 2 * (size_t)ns * rk + ns + nsearch;
+  const size_t nvals = 2 * (size_t)ns * rk + ns + nsearch;
   TTK_TRY(d_vals_.alloc(nvals * sizeof(double)));
   TTK_TRY(d_R_.alloc((size_t)std::max(ns, std::max(rows, cols)) * sizeof(double)));
-  TTK_TRY(d_piv_.alloc(MAXR * sizeof(int32_t)));
-  TTK_TRY(d_info_.alloc(sizeof(int32_t)));
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   TTK_TRY(h_res_.alloc(sizeof(StepRes)));
-  double* AIJ = d_vals_.as<double>();
-  double* AsJ = AIJ + (size_t)rk * rk;
-  double* AIs = AsJ + (size_t)ns * rk;
+  double* AsJ = d_vals_.as<double>();
+  double* AIs = AsJ + (size_t)ns * rk;          // (q, sample) at sample + q ns
   double* As = AIs + (size_t)rk * ns;
   double* S0 = As + ns;
   StepRes* dres = d_res_.as<StepRes>();
   const int32_t* d_l = &dres->l;
   const int32_t* d_t = &dres->t;
   const Addr a = super_addr(k);
-  eval_product(ks_, a, dI, rk, dJ, rk, AIJ, st_);
-  eval_product(ks_, a, dsr, ns, dJ, rk, AsJ, st_);
-  eval_product(ks_, a, dI, rk, dsc, ns, AIs, st_);
-  eval_list(ks_, a, dsr, dsc, ns, As, st_);
-  evals_ += (int64_t)rk * rk + 2 * (int64_t)ns * rk + ns;
-  hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st_, AIJ, rk * rk, AsJ, ns * rk, AIs, rk * ns, As, ns,
-                     (const double*)nullptr, &dres->s_scale);
-  lu_factor(AIJ, rk, rk, d_piv_.as<int32_t>(), d_info_.as<int32_t>(), st_);
-  lu_solve(AIJ, rk, rk, d_piv_.as<int32_t>(), 0, AIs, rk, ns, st_);
+  // LU of A(I, J) = P_k, reused until step k appends a pivot
+  if (!lu_valid_[k]) {
+    TTK_TRY(d_lu_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
+    TTK_TRY(d_lupiv_[k].alloc((size_t)MAXR * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st_, luamax(k));
+    eval_product(ks_, a, dI, rk, dJ, rk, d_lu_[k].as<double>(), st_, luamax(k));
+    evals_ += (int64_t)rk * rk;
+    lu_factor(d_lu_[k].as<double>(), rk, rk, d_lupiv_[k].as<int32_t>(), luinfo(k), st_);
+    lu_valid_[k] = true;
+  }
+  const double* LU = d_lu_[k].as<double>();
+  const int32_t* piv = d_lupiv_[k].as<int32_t>();
+  hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(64), 0, st_, dres, (const double*)luamax(k));
+  {
+    const EvalSeg sg[3] = {{dsr, dJ, ns, rk, 0, AsJ}, {dI, dsc, rk, ns, 1, AIs}, {dsr, dsc, ns, 1, 2, As}};
+    eval_segs(ks_, a, sg, 3, st_, &dres->s_scale);
+  }
+  evals_ += 2 * (int64_t)ns * rk + ns;
+  lu_solve_rm(LU, rk, rk, piv, 0, AIs, ns, ns, st_);
   hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 256)), dim3(256), 0, st_, AsJ, (int64_t)1, (int64_t)ns, AIs,
-                     (int64_t)1, (int64_t)rk, As, ns, rk, d_R_.as<double>());
+                     (int64_t)ns, (int64_t)1, As, ns, rk, d_R_.as<double>());
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), ns, dsr, dsc, 0, dres);
   if (bit == 1) {   // search the row of the sample's pivot
     double* AlJ = S0;
-    double* AIall = AlJ + rk;
+    double* AIall = AlJ + rk;                   // (q, c) at c + q cols
     double* Alall = AIall + (size_t)rk * cols;
-    eval_product(ks_, a, d_l, 1, dJ, rk, AlJ, st_);
-    eval_product(ks_, a, dI, rk, nullptr, cols, AIall, st_);
-    eval_product(ks_, a, d_l, 1, nullptr, cols, Alall, st_);
+    {
+      const EvalSeg sg[3] = {{d_l, dJ, 1, rk, 0, AlJ}, {dI, nullptr, rk, cols, 1, AIall}, {d_l, nullptr, 1, cols, 0, Alall}};
+      eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
+    }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st_, AlJ, rk, AIall, rk * cols, Alall, cols,
-                       (const double*)nullptr, 0, &dres->s_scale, &dres->q_scale);
-    lu_solve(AIJ, rk, rk, d_piv_.as<int32_t>(), 0, AIall, rk, cols, st_);
+    lu_solve_rm(LU, rk, rk, piv, 0, AIall, cols, cols, st_);
     hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 256)), dim3(256), 0, st_, AlJ, (int64_t)0, (int64_t)1, AIall,
-                       (int64_t)1, (int64_t)rk, Alall, cols, rk, d_R_.as<double>());
+                       (int64_t)cols, (int64_t)1, Alall, cols, rk, d_R_.as<double>());
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), cols, dsr, dsc, 1, dres);
   } else {          // search the column
     double* AallJ = S0;
     double* AIt = AallJ + (size_t)rows * rk;
     double* Aallt = AIt + rk;
-    eval_product(ks_, a, nullptr, rows, dJ, rk, AallJ, st_);
-    eval_product(ks_, a, dI, rk, d_t, 1, AIt, st_);
-    eval_product(ks_, a, nullptr, rows, d_t, 1, Aallt, st_);
+    {
+      const EvalSeg sg[3] = {{nullptr, dJ, rows, rk, 0, AallJ}, {dI, d_t, rk, 1, 0, AIt}, {nullptr, d_t, rows, 1, 0, Aallt}};
+      eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
+    }
     evals_ += (int64_t)rows * rk + rk + rows;
-    hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st_, AallJ, rows * rk, AIt, rk, Aallt, rows,
-                       (const double*)nullptr, 0, &dres->s_scale, &dres->q_scale);
-    lu_solve(AIJ, rk, rk, d_piv_.as<int32_t>(), 0, AIt, rk, 1, st_);
+    lu_solve_rm(LU, rk, rk, piv, 0, AIt, 1, 1, st_);
     hipLaunchKernelGGL(k_resid, dim3(nblk(rows, 256)), dim3(256), 0, st_, AallJ, (int64_t)1, (int64_t)rows,
                        AIt, (int64_t)1, (int64_t)0, Aallt, rows, rk, d_R_.as<double>());
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), rows, dsr, dsc, 1, dres);
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st_, dres, bit, dI, dJ, rk,
-                     std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR), d_info_.as<int32_t>());
+                     std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR), (const int32_t*)luinfo(k));
   TTK_HIP(hipGetLastError());
   TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, sizeof(StepRes), hipMemcpyDeviceToHost, st_));
   TTK_TRY(sync());
@@ -593,6 +650,7 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   if (r.s_max > 0) min_margin_ = std::min(min_margin_, r.s_margin);
   if (r.q_max > 0) min_margin_ = std::min(min_margin_, r.q_margin);
   if (r.added) {
+    lu_valid_[k] = false;   // P_k grows by a row and a column
     const int l = r.pivot_row, t = r.pivot_col;
     const int s = l % rl, ik = l / rl;
     if (k > 1) L_[k].insert(L_[k].end(), L_[k - 1].begin() + (size_t)s * (k - 1),
@@ -607,70 +665,69 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   return TTK_OK;
 }
 
-// Cores of the cross interpolant, stored transposed: CT_k = C_k^T (r_k x r_{k-1} n_k).
-// qr = false: C_k = F_k P_k^{-1} (LU).  qr = true: C_k = Q Q[J,:]^{-1} with F_k = Q R.
-tt_status Cross::build_cores(bool qr, std::vector<double*>* CT) {
+// Factor P_k = F[rows, :] (rows of a fibre at the positions of I^{<=k}) into the cache.
+tt_status Cross::factor_from_rows(int k, const double* F, int ldf, const int32_t* rows) {
+  const int r1 = rank(k);
+  TTK_TRY(d_lu_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
+  TTK_TRY(d_lupiv_[k].alloc((size_t)MAXR * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_gather_rows, dim3(nblk(r1 * r1, 256)), dim3(256), 0, st_, F, ldf, rows, r1, r1,
+                     d_lu_[k].as<double>());
+  hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st_, d_lu_[k].as<double>(), r1 * r1, (const double*)nullptr,
+                     0, (const double*)nullptr, 0, (const double*)nullptr, 0, (const double*)nullptr, luamax(k));
+  lu_factor(d_lu_[k].as<double>(), r1, r1, d_lupiv_[k].as<int32_t>(), luinfo(k), st_);
+  lu_valid_[k] = true;
+  return TTK_OK;
+}
+
+// Cores of the cross interpolant, column-major C_k ((r_{k-1} n_k) x r_k):
+// C_k = F_k P_k^{-1} (a solve with P_k^T through the cached LU), C_D = F_D.
+tt_status Cross::build_cores(std::vector<double*>* C) {
   const int N = N_;
-  CT->assign(N, nullptr);
+  C->assign(N, nullptr);
+  arena_reset();
   for (int k = 1; k <= N; ++k) {
     const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
     const int m = r0 * n;
-    TTK_TRY(d_left_.alloc(std::max<size_t>(2, L_[k - 1].size()) * sizeof(int16_t)));
-    TTK_TRY(d_right_.alloc(std::max<size_t>(2, (k < N ? R_[k].size() : 0)) * sizeof(int16_t)));
-    TTK_TRY(upload_sets(k - 1, k, d_left_.as<int16_t>(), d_right_.as<int16_t>()));
-    TTK_TRY(d_fib_.alloc((size_t)m * r1 * sizeof(double)));
+    TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
+    TTK_TRY(arena_flush());
     TTK_TRY(d_core_[k - 1].alloc((size_t)m * r1 * sizeof(double)));
-    double* F = d_fib_.as<double>();
-    double* C = d_core_[k - 1].as<double>();
+    double* F = d_core_[k - 1].as<double>();
     eval_product(ks_, fibre_addr(k), nullptr, m, nullptr, r1, F, st_);
     evals_ += (int64_t)m * r1;
-    if (k == N) {
-      hipLaunchKernelGGL(k_transpose, dim3(nblk((int64_t)m * r1, 256)), dim3(256), 0, st_, F, m, r1, m, C, r1);
-      (*CT)[k - 1] = C;
-      continue;
+    (*C)[k - 1] = F;
+    if (k == N) continue;
+    if (!lu_valid_[k]) {
+      // row positions of I^{<=k} among the rows (s + i r0) of F_k
+      std::unordered_map<uint64_t, int> lpos;
+      for (int s = 0; s < r0; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
+      std::vector<int32_t> hj(r1);
+      for (int q = 0; q < r1; ++q) {
+        const int32_t* e = &L_[k][(size_t)q * k];
+        hj[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * r0;
+      }
+      const int32_t* dj = nullptr;
+      TTK_TRY(arena_push(hj.data(), (size_t)r1, &dj));
+      TTK_TRY(arena_flush());
+      TTK_TRY(factor_from_rows(k, F, m, dj));
     }
-    // row positions of I^{<=k} among the rows (s + i r0) of F_k
-    std::unordered_map<uint64_t, int> lpos;
-    for (int s = 0; s < r0; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
-    std::vector<int32_t> Jp(r1);
-    for (int q = 0; q < r1; ++q) {
-      const int32_t* e = &L_[k][(size_t)q * k];
-      Jp[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * r0;
-    }
-    TTK_TRY(d_idx_.alloc((size_t)r1 * sizeof(int32_t)));
-    TTK_TRY(h_stage_.alloc((size_t)r1 * sizeof(int32_t)));
-    std::copy(Jp.begin(), Jp.end(), h_stage_.as<int32_t>());
-    TTK_HIP(hipMemcpyAsync(d_idx_.p, h_stage_.p, (size_t)r1 * sizeof(int32_t), hipMemcpyHostToDevice, st_));
-    TTK_TRY(d_P_.alloc(((size_t)r1 * r1 + (size_t)r1 * r1 + 64) * sizeof(double)));
-    double* Pm = d_P_.as<double>();
-    double* Rq = Pm + (size_t)r1 * r1;
-    if (qr) {
-      TTK_TRY(d_tmp_.alloc((size_t)(r1 + 64) * sizeof(double)));
-      qr_thin(F, m, r1, m, Rq, r1, d_tmp_.as<double>(), st_);
-    }
-    hipLaunchKernelGGL(k_gather_rows, dim3(nblk(r1 * r1, 256)), dim3(256), 0, st_, F, m, d_idx_.as<int32_t>(),
-                       r1, r1, Pm);
-    TTK_TRY(d_piv_.alloc(MAXR * sizeof(int32_t)));
-    TTK_TRY(d_info_.alloc(sizeof(int32_t)));
-    lu_factor(Pm, r1, r1, d_piv_.as<int32_t>(), d_info_.as<int32_t>(), st_);
-    hipLaunchKernelGGL(k_transpose, dim3(nblk((int64_t)m * r1, 256)), dim3(256), 0, st_, F, m, r1, m, C, r1);
-    lu_solve(Pm, r1, r1, d_piv_.as<int32_t>(), 1, C, r1, m, st_);
-    int32_t info = 0;
-    TTK_HIP(hipMemcpyAsync(&info, d_info_.p, sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-    TTK_TRY(sync());
-    if (info != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
-    (*CT)[k - 1] = C;
+    // (k', c) of the right-hand sides F^T sits at c + k' m: F's own layout
+    lu_solve_rm(d_lu_[k].as<double>(), r1, r1, d_lupiv_[k].as<int32_t>(), 1, F, m, m, st_);
   }
   TTK_HIP(hipGetLastError());
+  std::vector<int32_t> info(MAXD, 0);
+  TTK_HIP(hipMemcpyAsync(info.data(), luinfo(0), MAXD * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  TTK_TRY(sync());
+  for (int k = 1; k < N; ++k)
+    if (info[k] != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
   return TTK_OK;
 }
 
 tt_status Cross::sampled_error(double* err) {
-  std::vector<double*> CT;
-  TTK_TRY(build_cores(false, &CT));
+  std::vector<double*> C;
+  TTK_TRY(build_cores(&C));
   TTView tv{};
   tv.D = N_;
-  for (int k = 0; k < N_; ++k) tv.CT[k] = CT[k];
+  for (int k = 0; k < N_; ++k) { tv.C[k] = C[k]; tv.m[k] = rank(k) * g_.n[k]; }
   for (int k = 0; k <= N_; ++k) tv.r[k] = rank(k);
   hipLaunchKernelGGL(k_tt_points, dim3(nblk(n_test_, 4)), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(),
                      n_test_, d_test_hat_.as<double>());
@@ -685,6 +742,9 @@ tt_status Cross::sampled_error(double* err) {
 
 tt_status Cross::run(CrossOut* out) {
   const int N = N_;
+  TTK_TRY(arena_init((size_t)4 << 20));
+  TTK_TRY(d_luaux_.alloc(MAXD * (sizeof(double) + sizeof(int32_t))));
+  fill_zero(d_luaux_.p, MAXD * (sizeof(double) + sizeof(int32_t)), st_);
   TTK_TRY(init_sets());
   // fixed test multi-indices of the stopping rule
   int nmax = 0;
@@ -724,23 +784,19 @@ tt_status Cross::run(CrossOut* out) {
     TTK_TRY(sampled_error(&err));
     if (added == 0) break;
   }
-  std::vector<double*> CT;
-  TTK_TRY(build_cores(true, &CT));
+  // the cores of the last stopping test are the result (d_core_ holds them)
   out->ranks.assign(N + 1, 1);
   for (int k = 0; k <= N; ++k) out->ranks[k] = rank(k);
   out->cores.assign(N, {});
   for (int k = 1; k <= N; ++k) {
     const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
     const size_t cnt = (size_t)r0 * n * r1;
-    std::vector<double> ct(cnt);
-    TTK_HIP(hipMemcpyAsync(ct.data(), CT[k - 1], cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
-    TTK_TRY(sync());
-    // G_k[a + i r0 + b r0 n] = C_k[(a + i r0), b] = CT[b + (a + i r0) r1]
-    std::vector<double>& G = out->cores[k - 1];
-    G.resize(cnt);
-    for (int row = 0; row < r0 * n; ++row)
-      for (int b = 0; b < r1; ++b) G[row + (size_t)b * r0 * n] = ct[b + (size_t)row * r1];
+    // column-major C_k ((r0 n) x r1) is the little-endian core layout itself
+    out->cores[k - 1].resize(cnt);
+    TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), d_core_[k - 1].p, cnt * sizeof(double),
+                           hipMemcpyDeviceToHost, st_));
   }
+  TTK_TRY(sync());
   out->left.assign(N + 1, {});
   out->right.assign(N + 1, {});
   for (int k = 1; k < N; ++k) { out->left[k] = L_[k]; out->right[k] = R_[k]; }

@@ -29,28 +29,78 @@ __device__ inline void addr_coords(const KSpec& ks, const Addr& a, int row, int 
   for (int q = 0; q < a.lr; ++q, ++j) c[j] = ks.nodes[j * MAXN + a.right[t * a.lr + q]];
 }
 
+// Running max of |value| folded into *amax (non-negative doubles order like
+// their bit patterns, so an integer atomic max is exact).
+__device__ inline void fold_amax(double v, double* amax) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(amax), (unsigned long long)__double_as_longlong(v));
+}
+
+// out[i + j*nr] (or out[j + i*nc] when trans_out) = A(rows[i], cols[j])
 __global__ void k_eval_product(KSpec ks, Addr a, const int32_t* rows, int nr,
-                               const int32_t* cols, int nc, double* out) {
+                               const int32_t* cols, int nc, int trans_out, double* out, double* amax) {
   const int64_t total = (int64_t)nr * nc;
+  double m = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e % nr);
-    const int jj = (int)(e / nr);
+    int i, jj;
+    if (trans_out) { jj = (int)(e % nc); i = (int)(e / nc); }
+    else { i = (int)(e % nr); jj = (int)(e / nr); }
     const int row = rows ? rows[i] : i;
     const int col = cols ? cols[jj] : jj;
     double c[MAXD];
     addr_coords(ks, a, row, col, c);
-    out[e] = eval_coords(ks, c);
+    const double v = eval_coords(ks, c);
+    out[e] = v;
+    m = fmax(m, fabs(v));
   }
+  if (amax) fold_amax(m, amax);
 }
 
 __global__ void k_eval_list(KSpec ks, Addr a, const int32_t* rows, const int32_t* cols, int np,
-                            double* out) {
+                            double* out, double* amax) {
+  double m = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     double c[MAXD];
     addr_coords(ks, a, rows[i], cols[i], c);
-    out[i] = eval_coords(ks, c);
+    const double v = eval_coords(ks, c);
+    out[i] = v;
+    m = fmax(m, fabs(v));
   }
+  if (amax) fold_amax(m, amax);
+}
+
+// Up to three blocks of entries in one launch (see EvalSeg).
+__global__ void k_eval_segs(KSpec ks, Addr a, EvalSeg s0, EvalSeg s1, EvalSeg s2, int nseg, double* amax) {
+  const int64_t n0 = (int64_t)s0.nr * s0.nc;
+  const int64_t n1 = nseg > 1 ? (int64_t)s1.nr * s1.nc : 0;
+  const int64_t n2 = nseg > 2 ? (int64_t)s2.nr * s2.nc : 0;
+  const int64_t total = n0 + n1 + n2;
+  double m = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const bool in0 = g < n0, in1 = !in0 && g < n0 + n1;
+    const EvalSeg sg = in0 ? s0 : (in1 ? s1 : s2);
+    const int64_t e = in0 ? g : (in1 ? g - n0 : g - n0 - n1);
+    int row, col;
+    if (sg.mode == 2) {                   // list of (row, col) pairs, nc == 1
+      row = sg.rows[e];
+      col = sg.cols[e];
+    } else {
+      int i, jj;
+      if (sg.mode == 1) { jj = (int)(e % sg.nc); i = (int)(e / sg.nc); }
+      else { i = (int)(e % sg.nr); jj = (int)(e / sg.nr); }
+      row = sg.rows ? sg.rows[i] : i;
+      col = sg.cols ? sg.cols[jj] : jj;
+    }
+    double c[MAXD];
+    addr_coords(ks, a, row, col, c);
+    const double v = eval_coords(ks, c);
+    sg.out[e] = v;
+    m = fmax(m, fabs(v));
+  }
+  if (amax) fold_amax(m, amax);
 }
 
 template <class I>
@@ -89,16 +139,25 @@ inline int blocks_for(int64_t n, int bs = 256, int cap = 16384) {
 }  // namespace
 
 void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr, const int32_t* cols,
-                  int nc, double* out, hipStream_t st) {
+                  int nc, double* out, hipStream_t st, double* amax, bool trans_out) {
   if (nr <= 0 || nc <= 0) return;
   hipLaunchKernelGGL(k_eval_product, dim3(blocks_for((int64_t)nr * nc)), dim3(256), 0, st, ks, a, rows,
-                     nr, cols, nc, out);
+                     nr, cols, nc, trans_out ? 1 : 0, out, amax);
 }
 
 void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols, int np,
-               double* out, hipStream_t st) {
+               double* out, hipStream_t st, double* amax) {
   if (np <= 0) return;
-  hipLaunchKernelGGL(k_eval_list, dim3(blocks_for(np)), dim3(256), 0, st, ks, a, rows, cols, np, out);
+  hipLaunchKernelGGL(k_eval_list, dim3(blocks_for(np)), dim3(256), 0, st, ks, a, rows, cols, np, out, amax);
+}
+
+void eval_segs(const KSpec& ks, const Addr& a, const EvalSeg* segs, int nseg, hipStream_t st, double* amax) {
+  int64_t total = 0;
+  for (int i = 0; i < nseg; ++i) total += (int64_t)segs[i].nr * segs[i].nc;
+  if (total <= 0) return;
+  const EvalSeg z{};
+  hipLaunchKernelGGL(k_eval_segs, dim3(blocks_for(total)), dim3(256), 0, st, ks, a, segs[0], nseg > 1 ? segs[1] : z,
+                     nseg > 2 ? segs[2] : z, nseg, amax);
 }
 
 void eval_multi16(const KSpec& ks, const int16_t* idx, int64_t P, double* out, hipStream_t st) {

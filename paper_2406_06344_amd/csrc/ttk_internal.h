@@ -92,12 +92,24 @@ struct Addr {
   int nmid;              // 1 (fibre) or 2 (super-core)
   int nm0, nm1;          // node counts of the middle dims
 };
-// out[i + j*nr] = A(rows[i], cols[j]); rows/cols NULL = all rows/cols.
+// out[i + j*nr] = A(rows[i], cols[j]) (out[j + i*nc] when trans_out); rows/cols
+// NULL = all rows/cols.  amax (device, may be NULL): max |value| folded in.
 void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr,
-                  const int32_t* cols, int nc, double* out, hipStream_t st);
-// out[i] = A(rows[i], cols[i]); a NULL list means "the single value *one"
+                  const int32_t* cols, int nc, double* out, hipStream_t st,
+                  double* amax = nullptr, bool trans_out = false);
+// One block of entries for eval_segs: mode 0 = product (i fastest), 1 = product
+// with the column index fastest, 2 = list of (rows[i], cols[i]) with nc = 1.
+struct EvalSeg {
+  const int32_t* rows;
+  const int32_t* cols;
+  int nr, nc, mode;
+  double* out;
+};
+void eval_segs(const KSpec& ks, const Addr& a, const EvalSeg* segs, int nseg, hipStream_t st,
+               double* amax);
+// out[i] = A(rows[i], cols[i])
 void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols,
-               int np, double* out, hipStream_t st);
+               int np, double* out, hipStream_t st, double* amax = nullptr);
 // out[i] = f_kappa at multi-index idx[i*D .. i*D+D-1] (int16 or int32)
 void eval_multi16(const KSpec& ks, const int16_t* idx, int64_t P, double* out, hipStream_t st);
 void eval_multi32(const KSpec& ks, const int32_t* idx, int64_t P, double* out, hipStream_t st);
@@ -113,8 +125,16 @@ void lu_factor(double* A, int n, int lda, int32_t* piv, int32_t* info, hipStream
 // Solve A X = B (trans = 0) or A^T X = B (trans = 1) for nrhs columns, in place.
 void lu_solve(const double* LU, int n, int lda, const int32_t* piv, int trans, double* B,
               int ldb, int nrhs, hipStream_t st);
+// Same with the right-hand-side index fastest: entry (k, c) of B at c + k * ldb,
+// so one wave reads consecutive addresses.
+void lu_solve_rm(const double* LU, int n, int lda, const int32_t* piv, int trans, double* B,
+                 int64_t ldb, int nrhs, hipStream_t st);
 // Thin Householder QR of A (m x n, m >= n): A <- Q (m x n), R (n x n).
 void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st);
+// Blocked Householder QR (same result layout as qr_thin); work holds
+// qr_blocked_work(m, n) doubles.
+tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st);
+size_t qr_blocked_work(int m, int n);
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);

@@ -32,34 +32,39 @@ __device__ inline double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------- LU
 __global__ void __launch_bounds__(BS) k_lu(double* A, int n, int lda, int32_t* piv, int32_t* info) {
-  __shared__ double sv[BS];
-  __shared__ int si[BS];
-  const int tid = threadIdx.x;
+  __shared__ double wv[NW];
+  __shared__ int wi[NW];
+  __shared__ int s_piv;
+  __shared__ double s_pv;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) *info = 0;
   for (int j = 0; j < n; ++j) {
+    // partial pivoting: largest |A[i, j]|, i >= j, lowest row on ties
     double best = -1.0;
-    int bi = j;
+    int bi = n;
     for (int i = j + tid; i < n; i += BS) {
       const double v = fabs(A[i + (size_t)j * lda]);
       if (v > best) { best = v; bi = i; }
     }
-    sv[tid] = best;
-    si[tid] = bi;
-    __syncthreads();
-    for (int s = BS / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        const double a = sv[tid], b = sv[tid + s];
-        if (b > a || (b == a && si[tid + s] < si[tid])) { sv[tid] = b; si[tid] = si[tid + s]; }
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
     }
-    const int p = si[0];
-    const double pv = sv[0];
+    if (lane == 0) { wv[w] = best; wi[w] = bi; }
     __syncthreads();
     if (tid == 0) {
+      double b = wv[0];
+      int p = wi[0];
+      for (int q = 1; q < NW; ++q)
+        if (wv[q] > b || (wv[q] == b && wi[q] < p)) { b = wv[q]; p = wi[q]; }
+      s_piv = p;
+      s_pv = b;
       piv[j] = p;
-      if (pv == 0.0 && *info == 0) *info = j + 1;
+      if (b == 0.0 && *info == 0) *info = j + 1;
     }
+    __syncthreads();
+    const int p = s_piv;
     if (p != j)
       for (int c = tid; c < n; c += BS) {
         const double t = A[j + (size_t)c * lda];
@@ -71,6 +76,7 @@ __global__ void __launch_bounds__(BS) k_lu(double* A, int n, int lda, int32_t* p
     if (dg != 0.0)
       for (int i = j + 1 + tid; i < n; i += BS) A[i + (size_t)j * lda] /= dg;
     __syncthreads();
+    // trailing update, element-parallel with consecutive threads on consecutive rows
     const int m = n - j - 1;
     for (int e = tid; e < m * m; e += BS) {
       const int i = j + 1 + e % m, c = j + 1 + e / m;
@@ -78,6 +84,64 @@ __global__ void __launch_bounds__(BS) k_lu(double* A, int n, int lda, int32_t* p
     }
     __syncthreads();
   }
+}
+
+// The same factorisation with the matrix held in LDS (n x n doubles).
+template <int TB>
+__global__ void __launch_bounds__(TB) k_lu_lds(double* Ag, int n, int lda, int32_t* piv, int32_t* info) {
+  constexpr int BS = TB, NW = TB / 64;
+  extern __shared__ double A[];
+  __shared__ double wv[NW];
+  __shared__ int wi[NW];
+  __shared__ int s_piv;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < n * n; e += BS) A[e] = Ag[e % n + (size_t)(e / n) * lda];
+  if (tid == 0) *info = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = j + tid; i < n; i += BS) {
+      const double v = fabs(A[i + j * n]);
+      if (v > best) { best = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+    }
+    if (lane == 0) { wv[w] = best; wi[w] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = wv[0];
+      int p = wi[0];
+      for (int q = 1; q < NW; ++q)
+        if (wv[q] > b || (wv[q] == b && wi[q] < p)) { b = wv[q]; p = wi[q]; }
+      s_piv = p;
+      piv[j] = p;
+      if (b == 0.0 && *info == 0) *info = j + 1;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != j)
+      for (int c = tid; c < n; c += BS) {
+        const double t = A[j + c * n];
+        A[j + c * n] = A[p + c * n];
+        A[p + c * n] = t;
+      }
+    __syncthreads();
+    const double dg = A[j + j * n];
+    if (dg != 0.0)
+      for (int i = j + 1 + tid; i < n; i += BS) A[i + j * n] /= dg;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int e = tid; e < m * m; e += BS) {
+      const int i = j + 1 + e % m, c = j + 1 + e / m;
+      A[i + c * n] -= A[i + j * n] * A[j + c * n];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += BS) Ag[e % n + (size_t)(e / n) * lda] = A[e];
 }
 
 // One thread per right-hand side: row swaps, then the two triangular solves.
@@ -117,6 +181,197 @@ __global__ void k_lu_solve(const double* LU, int n, int lda, const int32_t* piv,
       if (p != i) { const double t = b[i]; b[i] = b[p]; b[p] = t; }
     }
   }
+}
+
+// Right-hand side c in one thread, b(k) at B[c + k ldb] (coalesced across a
+// wave); the factor is staged in LDS when it fits.
+__global__ void k_lu_solve_rm(const double* LUg, int n, int lda, const int32_t* piv, int trans, double* B,
+                              int64_t ldb, int nrhs, int in_lds) {
+  extern __shared__ double sLU[];
+  const double* LU = LUg;
+  int ld = lda;
+  if (in_lds) {
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) sLU[e] = LUg[e % n + (size_t)(e / n) * lda];
+    __syncthreads();
+    LU = sLU;
+    ld = n;
+  }
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nrhs) return;
+  double* b = B + c;
+#define BV(k) b[(int64_t)(k) * ldb]
+  if (!trans) {
+    for (int i = 0; i < n; ++i) {
+      const int p = piv[i];
+      if (p != i) { const double t = BV(i); BV(i) = BV(p); BV(p) = t; }
+    }
+    for (int i = 0; i < n; ++i) {
+      double s = BV(i);
+      for (int k = 0; k < i; ++k) s -= LU[i + k * ld] * BV(k);
+      BV(i) = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = BV(i);
+      for (int k = i + 1; k < n; ++k) s -= LU[i + k * ld] * BV(k);
+      BV(i) = s / LU[i + i * ld];
+    }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      double s = BV(i);
+      for (int k = 0; k < i; ++k) s -= LU[k + i * ld] * BV(k);
+      BV(i) = s / LU[i + i * ld];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = BV(i);
+      for (int k = i + 1; k < n; ++k) s -= LU[k + i * ld] * BV(k);
+      BV(i) = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      const int p = piv[i];
+      if (p != i) { const double t = BV(i); BV(i) = BV(p); BV(p) = t; }
+    }
+  }
+#undef BV
+}
+
+// Blocked solve with the LU factors for many right-hand sides.  A workgroup
+// owns RB right-hand sides, kept in LDS as rows of the permuted system; the
+// triangular solves go 16 rows at a time: a short serial solve of the 16 x 16
+// diagonal block per right-hand side, then a parallel update of the rest.
+// trans = 0 solves A x = b (P A = L U); trans = 1 solves A^T x = b.
+// Entry (k, c) of B is at c + k ldb.
+template <int RB>
+__global__ void __launch_bounds__(256) k_lu_trsm(const double* LU, int n, int lda, const int32_t* piv, int trans,
+                                                 double* B, int64_t ldb, int nrhs) {
+  constexpr int NB = 16;
+  extern __shared__ double smem[];
+  double* X = smem;                                            // n x RB
+  double* Pn = X + (size_t)n * RB;                              // NB x n coefficient panel
+  int* perm = reinterpret_cast<int*>(Pn + (size_t)NB * n);      // n
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * RB;
+  const int nc = min(RB, nrhs - c0);
+  if (tid == 0) {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+    for (int i = 0; i < n; ++i) {
+      const int p = piv[i];
+      if (p != i) { const int t = perm[i]; perm[i] = perm[p]; perm[p] = t; }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n * RB; e += 256) {
+    const int i = e / RB, c = e % RB;
+    const int src = trans ? i : perm[i];
+    X[i * RB + c] = (c < nc) ? B[(c0 + c) + (int64_t)src * ldb] : 0.0;
+  }
+  // coefficient of X[k] in row i: lower solve L[i,k] (trans 0) or U[k,i] (trans 1),
+  // upper solve U[i,k] (trans 0) or L[k,i] (trans 1); staged as Pn[(k - i0) n + i]
+  auto stage = [&](int i0, int i1, int ilo, int ihi) {
+    const int nb = i1 - i0, cnt = ihi - ilo;
+    if (!trans) {
+      for (int e = tid; e < nb * cnt; e += 256) {
+        const int i = ilo + e % cnt, kl = e / cnt;
+        Pn[kl * n + i] = LU[i + (size_t)(i0 + kl) * lda];
+      }
+    } else {
+      for (int e = tid; e < nb * cnt; e += 256) {
+        const int kl = e % nb, i = ilo + e / nb;
+        Pn[kl * n + i] = LU[(i0 + kl) + (size_t)i * lda];
+      }
+    }
+  };
+  __syncthreads();
+  // lower solve: L (unit) for trans 0, U^T for trans 1
+  for (int i0 = 0; i0 < n; i0 += NB) {
+    const int i1 = min(i0 + NB, n);
+    stage(i0, i1, i0, n);
+    __syncthreads();
+    if (tid < RB) {
+      const int c = tid;
+      for (int i = i0; i < i1; ++i) {
+        double s = X[i * RB + c];
+        for (int k = i0; k < i; ++k) s -= Pn[(k - i0) * n + i] * X[k * RB + c];
+        X[i * RB + c] = trans ? s / Pn[(i - i0) * n + i] : s;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < (n - i1) * RB; e += 256) {
+      const int i = i1 + e / RB, c = e % RB;
+      double s = X[i * RB + c];
+      for (int k = i0; k < i1; ++k) s -= Pn[(k - i0) * n + i] * X[k * RB + c];
+      X[i * RB + c] = s;
+    }
+    __syncthreads();
+  }
+  // upper solve: U for trans 0, L^T (unit) for trans 1
+  for (int i1 = n; i1 > 0; i1 -= NB) {
+    const int i0 = max(i1 - NB, 0);
+    stage(i0, i1, 0, i1);
+    __syncthreads();
+    if (tid < RB) {
+      const int c = tid;
+      for (int i = i1 - 1; i >= i0; --i) {
+        double s = X[i * RB + c];
+        for (int k = i + 1; k < i1; ++k) s -= Pn[(k - i0) * n + i] * X[k * RB + c];
+        X[i * RB + c] = trans ? s : s / Pn[(i - i0) * n + i];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < i0 * RB; e += 256) {
+      const int i = e / RB, c = e % RB;
+      double s = X[i * RB + c];
+      for (int k = i0; k < i1; ++k) s -= Pn[(k - i0) * n + i] * X[k * RB + c];
+      X[i * RB + c] = s;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * RB; e += 256) {
+    const int i = e / RB, c = e % RB;
+    if (c < nc) {
+      const int dst = trans ? perm[i] : i;
+      B[(c0 + c) + (int64_t)dst * ldb] = X[i * RB + c];
+    }
+  }
+}
+
+// One right-hand side per single-wave workgroup: each substitution step is a
+// dot product spread over the 64 lanes and reduced by shuffles.
+__global__ void __launch_bounds__(64) k_lu_solve_wave(const double* LU, int n, int lda, const int32_t* piv,
+                                                      int trans, double* B, int64_t ldb) {
+  extern __shared__ double xw[];
+  const int lane = threadIdx.x;
+  double* b = B + blockIdx.x;               // entry k at b[k * ldb]
+  for (int k = lane; k < n; k += 64) xw[k] = b[(int64_t)k * ldb];
+  __syncthreads();
+  if (!trans && lane == 0)
+    for (int i = 0; i < n; ++i) {
+      const int p = piv[i];
+      if (p != i) { const double t = xw[i]; xw[i] = xw[p]; xw[p] = t; }
+    }
+  __syncthreads();
+  // lower: L (unit) or U^T
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int k = lane; k < i; k += 64) s += (trans ? LU[k + (size_t)i * lda] : LU[i + (size_t)k * lda]) * xw[k];
+    s = wave_sum(s);
+    if (lane == 0) xw[i] = trans ? (xw[i] - s) / LU[i + (size_t)i * lda] : xw[i] - s;
+    __syncthreads();
+  }
+  // upper: U or L^T (unit)
+  for (int i = n - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int k = i + 1 + lane; k < n; k += 64) s += (trans ? LU[k + (size_t)i * lda] : LU[i + (size_t)k * lda]) * xw[k];
+    s = wave_sum(s);
+    if (lane == 0) xw[i] = trans ? xw[i] - s : (xw[i] - s) / LU[i + (size_t)i * lda];
+    __syncthreads();
+  }
+  if (trans && lane == 0)
+    for (int i = n - 1; i >= 0; --i) {
+      const int p = piv[i];
+      if (p != i) { const double t = xw[i]; xw[i] = xw[p]; xw[p] = t; }
+    }
+  __syncthreads();
+  for (int k = lane; k < n; k += 64) b[(int64_t)k * ldb] = xw[k];
 }
 
 // ------------------------------------------------------------------- QR
@@ -194,6 +449,130 @@ __global__ void __launch_bounds__(BS) k_qr(double* A, int m, int n, int lda, dou
     if (tid == 0) aj[j] = 1.0 - tj;
     __syncthreads();
   }
+}
+
+// --------------------------------------------------- blocked Householder QR
+// Panel factorisation (unblocked, one workgroup) of an m x jb panel: reflectors
+// with v(j) = 1 below the diagonal, R's diagonal on it, tau out.
+__global__ void __launch_bounds__(BS) k_qr_panel(double* A, int m, int jb, int lda, double* tau) {
+  __shared__ double red[NW];
+  __shared__ double s_tau, s_alpha;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int j = 0; j < jb && j < m; ++j) {
+    double* aj = A + (size_t)j * lda;
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += BS) part += aj[i] * aj[i];
+    const double tail = block_sum(part, red);
+    if (tid == 0) {
+      const double x0 = aj[j];
+      const double nrm = sqrt(x0 * x0 + tail);
+      if (tail == 0.0) {
+        s_tau = 0.0;
+        s_alpha = x0;
+      } else {
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        s_tau = (alpha - x0) / alpha;
+        s_alpha = alpha;
+        aj[j] = x0 - alpha;
+      }
+    }
+    __syncthreads();
+    const double tj = s_tau;
+    if (tj != 0.0) {
+      const double v0 = aj[j];
+      for (int i = j + 1 + tid; i < m; i += BS) aj[i] /= v0;
+    }
+    __syncthreads();
+    if (tid == 0) { aj[j] = s_alpha; tau[j] = tj; }
+    __syncthreads();
+    if (tj != 0.0)
+      for (int c = j + 1 + w; c < jb; c += NW) {
+        double* ac = A + (size_t)c * lda;
+        double dot = (lane == 0) ? ac[j] : 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) dot += aj[i] * ac[i];
+        dot = wave_sum(dot) * tj;
+        if (lane == 0) ac[j] -= dot;
+        for (int i = j + 1 + lane; i < m; i += 64) ac[i] -= dot * aj[i];
+      }
+    __syncthreads();
+  }
+}
+
+// V (m x jb, explicit): unit diagonal, reflectors below, zeros above.
+__global__ void k_build_v(const double* A, int m, int jb, int lda, double* V) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * jb) return;
+  const int i = (int)(e % m), q = (int)(e / m);
+  V[e] = (i == q) ? 1.0 : (i > q ? A[i + (size_t)q * lda] : 0.0);
+}
+
+// T (jb x jb upper) with H_0 ... H_{jb-1} = I - V T V^T (forward, columnwise).
+__global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, const double* tau, double* T) {
+  __shared__ double G[16][16];
+  __shared__ double Ts[16][16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // G = V^T V (upper part)
+  for (int pq = w; pq < jb * jb; pq += NW) {
+    const int p = pq / jb, q = pq % jb;
+    if (p > q) continue;
+    double sdot = 0.0;
+    for (int i = lane; i < m; i += 64) sdot += V[i + (size_t)p * m] * V[i + (size_t)q * m];
+    sdot = wave_sum(sdot);
+    if (lane == 0) G[p][q] = sdot;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < jb; ++i) {
+      for (int r = 0; r < jb; ++r) Ts[r][i] = 0.0;
+      Ts[i][i] = tau[i];
+      for (int r = 0; r < i; ++r) {
+        double acc = 0.0;
+        for (int q = r; q < i; ++q) acc += Ts[r][q] * G[q][i];
+        Ts[r][i] = -tau[i] * acc;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < jb * jb; e += BS) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
+}
+
+// Columns of Q for one panel from its reflectors (backward accumulation), in place.
+__global__ void __launch_bounds__(BS) k_qr_panel_q(double* A, int m, int jb, int lda, const double* tau) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int j = jb - 1; j >= 0; --j) {
+    double* aj = A + (size_t)j * lda;
+    const double tj = tau[j];
+    if (j < jb - 1) {
+      if (tid == 0) aj[j] = 1.0;
+      __syncthreads();
+      for (int c = j + 1 + w; c < jb; c += NW) {
+        double* ac = A + (size_t)c * lda;
+        double dot = 0.0;
+        for (int i = j + lane; i < m; i += 64) dot += aj[i] * ac[i];
+        dot = wave_sum(dot) * tj;
+        for (int i = j + lane; i < m; i += 64) ac[i] -= dot * aj[i];
+      }
+      __syncthreads();
+    }
+    for (int i = j + 1 + tid; i < m; i += BS) aj[i] *= -tj;
+    for (int i = tid; i < j; i += BS) aj[i] = 0.0;
+    __syncthreads();
+    if (tid == 0) aj[j] = 1.0 - tj;
+    __syncthreads();
+  }
+}
+
+__global__ void k_extract_r(const double* A, int n, int lda, double* R, int ldr) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e % n, c = e / n;
+  R[i + (size_t)c * ldr] = (i <= c) ? A[i + (size_t)c * lda] : 0.0;
+}
+
+__global__ void k_zero_rows(double* A, int rows, int cols, int lda) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  A[e % rows + (size_t)(e / rows) * lda] = 0.0;
 }
 
 // ------------------------------------------------------------ Jacobi SVD
@@ -329,6 +708,30 @@ __global__ void k_nrm2(const double* x, int64_t n, double* out) {
 }  // namespace
 
 void lu_factor(double* A, int n, int lda, int32_t* piv, int32_t* info, hipStream_t st) {
+  // the matrix in LDS when it fits the workgroup's limit, else in global memory
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      lds_limit = v;
+    else
+      lds_limit = 64 * 1024;
+    (void)hipGetLastError();
+  }
+  const size_t sh = (size_t)n * n * sizeof(double);
+  const size_t stat = 2 * NW * sizeof(double) + 64;   // static LDS of the kernel
+  if (sh + stat <= (size_t)lds_limit) {
+    bool ok = true;
+    if (sh > 48 * 1024)
+      ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lu_lds<256>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) == hipSuccess;
+    if (ok) {
+      hipLaunchKernelGGL(k_lu_lds<256>, dim3(1), dim3(256), sh, st, A, n, lda, piv, info);
+      if (hipGetLastError() == hipSuccess) return;
+    }
+    (void)hipGetLastError();
+  }
   hipLaunchKernelGGL(k_lu, dim3(1), dim3(BS), 0, st, A, n, lda, piv, info);
 }
 
@@ -339,8 +742,88 @@ void lu_solve(const double* LU, int n, int lda, const int32_t* piv, int trans, d
                      nrhs);
 }
 
+void lu_solve_rm(const double* LU, int n, int lda, const int32_t* piv, int trans, double* B, int64_t ldb,
+                 int nrhs, hipStream_t st) {
+  if (nrhs <= 0 || n <= 0) return;
+  if (nrhs <= 8) {   // a handful of right-hand sides: one wave each
+    hipLaunchKernelGGL(k_lu_solve_wave, dim3(nrhs), dim3(64), (size_t)n * sizeof(double), st, LU, n, lda, piv,
+                       trans, B, ldb);
+    return;
+  }
+  // 16 right-hand sides per workgroup (8 for the largest ranks, to stay
+  // within 64 KB of LDS): enough workgroups to spread over the CUs
+  if (n <= 248) {
+    const size_t sh = (size_t)n * 16 * sizeof(double) + (size_t)16 * n * sizeof(double) + (size_t)n * sizeof(int);
+    hipLaunchKernelGGL(k_lu_trsm<16>, dim3((nrhs + 15) / 16), dim3(256), sh, st, LU, n, lda, piv, trans, B, ldb,
+                       nrhs);
+  } else {
+    const size_t sh = (size_t)n * 8 * sizeof(double) + (size_t)16 * n * sizeof(double) + (size_t)n * sizeof(int);
+    hipLaunchKernelGGL(k_lu_trsm<8>, dim3((nrhs + 7) / 8), dim3(256), sh, st, LU, n, lda, piv, trans, B, ldb, nrhs);
+  }
+}
+
 void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
   hipLaunchKernelGGL(k_qr, dim3(1), dim3(BS), 0, st, A, m, n, lda, R, ldr, work);
+}
+
+// Blocked Householder QR, compact WY with panels of 16: the panel factors in
+// one workgroup, the trailing update and the formation of Q are GEMMs.
+// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) + 16 n (W) doubles.
+tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
+  constexpr int NB = 16;
+  if (m < n) return fail(TTK_ERR_ARG, "qr_blocked needs m >= n");
+  double* tau = work;
+  double* V = tau + n;
+  double* Tall = V + (size_t)NB * m;
+  double* W = Tall + (size_t)NB * NB * ((n + NB - 1) / NB);
+  const int npan = (n + NB - 1) / NB;
+  for (int p = 0; p < npan; ++p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0);
+    const int mm = m - j0;
+    double* Ap = A + j0 + (size_t)j0 * lda;
+    hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+    double* T = Tall + (size_t)p * NB * NB;
+    hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb, lda,
+                       V);
+    hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, V, mm, jb, tau + j0, T);
+    const int nc = n - j0 - jb;
+    if (nc > 0) {
+      double* A2 = A + j0 + (size_t)(j0 + jb) * lda;
+      // A2 <- (I - V T^T V^T) A2
+      gemm64(1, 0, jb, nc, mm, 1.0, V, mm, A2, lda, 0.0, W, jb, st);           // W = V^T A2
+      gemm64(1, 0, jb, nc, jb, 1.0, T, jb, W, jb, 0.0, W + (size_t)jb * nc, jb, st);  // T^T W
+      gemm64(0, 0, mm, nc, jb, -1.0, V, mm, W + (size_t)jb * nc, jb, 1.0, A2, lda, st);
+    }
+  }
+  hipLaunchKernelGGL(k_extract_r, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, lda, R, ldr);
+  // Q = H_0 ... H_{n-1} [I; 0], panels from last to first
+  for (int p = npan - 1; p >= 0; --p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0);
+    const int mm = m - j0;
+    double* Ap = A + j0 + (size_t)j0 * lda;
+    const double* T = Tall + (size_t)p * NB * NB;
+    const int nc = n - j0 - jb;
+    if (nc > 0) {
+      hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
+                         lda, V);
+      double* Q2 = A + j0 + (size_t)(j0 + jb) * lda;
+      // Q2 <- (I - V T V^T) Q2
+      gemm64(1, 0, jb, nc, mm, 1.0, V, mm, Q2, lda, 0.0, W, jb, st);
+      gemm64(0, 0, jb, nc, jb, 1.0, T, jb, W, jb, 0.0, W + (size_t)jb * nc, jb, st);
+      gemm64(0, 0, mm, nc, jb, -1.0, V, mm, W + (size_t)jb * nc, jb, 1.0, Q2, lda, st);
+    }
+    hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+    if (j0 > 0)
+      hipLaunchKernelGGL(k_zero_rows, dim3((j0 * jb + 255) / 256), dim3(256), 0, st, A + (size_t)j0 * lda, j0, jb,
+                         lda);
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+size_t qr_blocked_work(int m, int n) {
+  constexpr int NB = 16;
+  return (size_t)n + (size_t)NB * m + (size_t)NB * NB * ((n + NB - 1) / NB) + 2 * (size_t)NB * n + 64;
 }
 
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {

@@ -87,11 +87,11 @@ tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipS
   const int m = n * r1;
   TTK_TRY(A.alloc((size_t)m * r0 * sizeof(double)));
   TTK_TRY(R.alloc((size_t)r0 * r0 * sizeof(double)));
-  TTK_TRY(tau.alloc((size_t)(r0 + 64) * sizeof(double)));
+  TTK_TRY(tau.alloc(qr_blocked_work(m, r0) * sizeof(double)));
   double* G = c.g[i].as<double>();
   hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, G, r0, m, r0, A.as<double>(),
                      m);
-  qr_thin(A.as<double>(), m, r0, m, R.as<double>(), r0, tau.as<double>(), st);
+  TTK_TRY(qr_blocked(A.as<double>(), m, r0, m, R.as<double>(), r0, tau.as<double>(), st));
   hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, A.as<double>(), m, r0, m, G,
                      r0);
   const int q0 = c.r[i - 1], qn = c.n[i - 1];
@@ -133,11 +133,11 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     const int m = r0 * n;
     TTK_TRY(A.alloc((size_t)m * r1 * sizeof(double)));
     TTK_TRY(R.alloc((size_t)r1 * r1 * sizeof(double)));
-    TTK_TRY(tau.alloc((size_t)(r1 + 64) * sizeof(double)));
+    TTK_TRY(tau.alloc(qr_blocked_work(m, r1) * sizeof(double)));
     TTK_TRY(V.alloc((size_t)r1 * r1 * sizeof(double)));
     TTK_TRY(sig.alloc(((size_t)r1 * r1 + 3 * (size_t)r1 + 64) * sizeof(double)));
     TTK_HIP(hipMemcpyAsync(A.p, c.g[i].p, (size_t)m * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    qr_thin(A.as<double>(), m, r1, m, R.as<double>(), r1, tau.as<double>(), st);
+    TTK_TRY(qr_blocked(A.as<double>(), m, r1, m, R.as<double>(), r1, tau.as<double>(), st));
     jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
     hs.resize(r1);
     TTK_HIP(hipMemcpyAsync(hs.data(), sig.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
