@@ -105,6 +105,120 @@ __global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P,
   }
 }
 
+// ---------------------------------------------------------------- MFMA path
+// The same contraction on the matrix cores (float32 in, float32 accumulate):
+// v_mfma_f32_16x16x4f32, whose 64 lanes hold A[i][k] at lane i + 16 k,
+// B[k][j] at lane j + 16 k and D[4 (l / 16) + v][l % 16] in register v.
+// A workgroup of 4 waves owns 64 points (16 per wave) and walks the
+// contraction index kk = a + k r_in in slabs of 64 rows of G^{2}, staged in
+// LDS; the A operand s[p, a] T_k(t_p) is formed per lane from LDS.
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int MF_P = 64;     // points per workgroup
+constexpr int MF_KS = 64;    // rows of G^{2} per LDS slab
+constexpr int MF_GLD = 68;   // slab row stride (bank spread across the 4 rows a K-step reads)
+constexpr int MF_TLD = 33;   // row stride of the Chebyshev table
+
+__global__ void __launch_bounds__(256) k_factor_mfma(StageArgs sa, const float* P, int64_t npts, float* out, int ldo,
+                                                     int sld) {
+  extern __shared__ float smf[];
+  float* sTk = smf;                                  // MF_P x MF_TLD
+  float* s0 = sTk + MF_P * MF_TLD;                    // MF_P x sld
+  float* s1 = s0 + MF_P * sld;                        // MF_P x sld
+  float* Gs = s1 + MF_P * sld;                        // MF_KS x MF_GLD
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t p0 = (int64_t)blockIdx.x * MF_P;
+  const int pl = 16 * w + (lane & 15);                // this lane's point for the A operand
+  const int kq = lane >> 4;                           // this lane's row within a K-step
+  float* sin = s0;
+  float* sout = s1;
+  if (tid < MF_P) sin[tid * sld] = 1.0f;
+  for (int st = 0; st < sa.nst; ++st) {
+    const int rin = sa.r_in[st], rout = sa.r_out[st], n = sa.n[st];
+    const float* G = static_cast<const float*>(sa.G2[st]);
+    if (tid < MF_P) {
+      const int64_t p = p0 + tid;
+      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * npts + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
+      const double t = (2.0 * x - (sa.lo[st] + sa.hi[st])) / (sa.lo[st] - sa.hi[st]);
+      double tkm = 1.0, tk = t;
+      sTk[tid * MF_TLD + 0] = 1.0f;
+      if (n > 1) sTk[tid * MF_TLD + 1] = (float)t;
+      for (int k = 2; k < n; ++k) {
+        const double tn = 2.0 * t * tk - tkm;
+        tkm = tk;
+        tk = tn;
+        sTk[tid * MF_TLD + k] = (float)tn;
+      }
+    }
+    __syncthreads();
+    const int K = rin * n;
+    for (int b0 = 0; b0 < rout; b0 += 64) {
+      f4 acc[4];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) acc[jb] = f4{0.f, 0.f, 0.f, 0.f};
+      const int cb = min(64, rout - b0);
+      for (int kk0 = 0; kk0 < K; kk0 += MF_KS) {
+        const int ck = min(MF_KS, K - kk0);
+        __syncthreads();                               // the previous slab is consumed
+        for (int e = tid; e < MF_KS * 64; e += 256) {
+          const int r = e >> 6, c = e & 63;
+          Gs[r * MF_GLD + c] = (r < ck && c < cb) ? G[(int64_t)(kk0 + r) * rout + b0 + c] : 0.0f;
+        }
+        __syncthreads();
+        // this lane's contraction index kk = kk0 + 4 s + kq as (a, k)
+        int kk = kk0 + kq;
+        int a = kk % rin, k = kk / rin;
+        const int nsteps = (ck + 3) >> 2;
+        for (int s4 = 0; s4 < nsteps; ++s4) {
+          const float av = (kk < K) ? sin[pl * sld + a] * sTk[pl * MF_TLD + k] : 0.0f;
+          const float* gr = Gs + (4 * s4 + kq) * MF_GLD + (lane & 15);
+#pragma unroll
+          for (int jb = 0; jb < 4; ++jb) acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gr[16 * jb], acc[jb], 0, 0, 0);
+          kk += 4;
+          a += 4;
+          while (a >= rin) { a -= rin; ++k; }
+        }
+      }
+      // D[4 (l / 16) + v][l % 16]: point 16 w + 4 (l / 16) + v, column b0 + 16 jb + l % 16
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) {
+        const int col = b0 + 16 * jb + (lane & 15);
+        if (col < rout)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) sout[(16 * w + 4 * kq + v) * sld + col] = acc[jb][v];
+      }
+    }
+    __syncthreads();
+    float* tmp = sin;
+    sin = sout;
+    sout = tmp;
+  }
+  const int rfin = sa.r_out[sa.nst - 1];
+  for (int e = tid; e < MF_P * rfin; e += 256) {
+    const int q = e / rfin, b = e % rfin;
+    const int64_t p = p0 + q;
+    if (p < npts) out[p * ldo + b] = sin[q * sld + b];
+  }
+}
+
+tt_status launch_factor_mfma(const StageArgs& sa, const void* P, int64_t npts, void* out, int ldo, hipStream_t st,
+                             bool* launched) {
+  *launched = false;
+  int dev = 0, lds = 64 * 1024;
+  TTK_HIP(hipGetDevice(&dev));
+  TTK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const int sld = sa.rmax + 1;
+  const size_t sh = sizeof(float) * ((size_t)MF_P * MF_TLD + 2 * (size_t)MF_P * sld + (size_t)MF_KS * MF_GLD);
+  if (sh > (size_t)lds) return TTK_OK;
+  if (sh > 64 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_mfma),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  hipLaunchKernelGGL(k_factor_mfma, dim3((unsigned)((npts + MF_P - 1) / MF_P)), dim3(256), sh, st, sa,
+                     static_cast<const float*>(P), npts, static_cast<float*>(out), ldo, sld);
+  TTK_HIP(hipGetLastError());
+  *launched = true;
+  return TTK_OK;
+}
+
 template <class T, int TP>
 tt_status launch_tile(const StageArgs& sa, const void* P, int64_t npts, int d, void* out, int ldo, size_t sh,
                       hipStream_t st) {
@@ -151,7 +265,13 @@ tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, cons
   }
   int d = 0;
   for (int i = 0; i < nstages; ++i) d = std::max(d, stages[i].coord + 1);
-  if (dtype == TTK_FP32) return launch_factor<float>(sa, P_soa, npts, d, out, ldo, st);
+  if (dtype == TTK_FP32) {
+    // matrix cores when the LDS tiles fit the workgroup, register-tiled VALU otherwise
+    bool launched = false;
+    TTK_TRY(launch_factor_mfma(sa, P_soa, npts, out, ldo, st, &launched));
+    if (launched) return TTK_OK;
+    return launch_factor<float>(sa, P_soa, npts, d, out, ldo, st);
+  }
   return launch_factor<double>(sa, P_soa, npts, d, out, ldo, st);
 }
 
