@@ -97,7 +97,8 @@ typedef struct {
                             max(1000, 20 D n))                                       */
   uint64_t seed;         /* key of every random draw of the cross                    */
   int dtype;             /* tt_dtype of U, V, M and the apply                        */
-  int symmetric_psd;     /* reserved (0)                                              */
+  int symmetric_psd;     /* 1 = PTTK-Global-1 (Algorithm 4), X = Y and box_t = box_s,
+                            and the build also computes the thin QR [U V] = Q R      */
 } tt_kernel_params;
 
 typedef struct {
@@ -205,6 +206,32 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B,
                                    const void* X, int64_t ldx, const void* W_saved,
                                    const void* G, int64_t ldg,
                                    void* dX, int64_t lddx, void* dtheta, void* stream);
+
+/* PTTK-Global-1, online part (Algorithm 4, Section 3.5), for a handle built
+ * with symmetric_psd = 1 (the build computed [U V] = Q R, Q: N x k with
+ * orthonormal columns, R: k x k upper triangular, k = r_s + r_t, by blocked
+ * Householder QR in double precision).  For each theta_b:
+ *   Hhat_b = [[0, M_b / 2], [M_b^T / 2, 0]]  (M_b = M(theta_b), Algorithm 3),
+ *   R Hhat_b R^T = U_b Lambda_b U_b^T,  W_b = U_b max(Lambda_b, 0) U_b^T,
+ * so that Q W_b Q^T is the nearest (in the Frobenius norm) positive
+ * semidefinite matrix to the symmetric part of U M_b V^T restricted to the
+ * range of Q.  Computed in double precision (one-sided Jacobi SVD of the
+ * symmetric k x k matrix: |.| of a symmetric matrix is V Sigma V^T).
+ * theta: device, dtype, B x d_theta row-major.  W_out: device, dtype,
+ * B x k x k, matrix b column-major at W_out + b k k. */
+tt_status tt_kernel_global_online(tt_kernel_t h, const void* theta, int B, void* W_out, void* stream);
+
+/* Global-1 apply y_b = Q W_b Q^T x_b (N x N, symmetric PSD).  Exactly one of
+ * theta (device, B x d_theta: W is formed as in tt_kernel_global_online) and
+ * W (device, dtype, B x k x k from tt_kernel_global_online) is non-NULL.
+ * X, Y: device, dtype, N x B column-major, ldx, ldy >= N. */
+tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W, int B,
+                                 const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
+
+/* Global-1 factors: *k = r_s + r_t (k may be NULL); Q_out: NULL or device,
+ * dtype, N x k row-major; R_out: NULL or host FP64 k x k column-major
+ * (synchronises `stream` when given). */
+tt_status tt_kernel_global_factors(tt_kernel_t h, int* k, void* Q_out, double* R_out, void* stream);
 
 /* f_kappa at P grid multi-indices (Section 2.4, entries of the grid tensor),
  * in double precision on the device.  idx: device int32, P x D row-major,

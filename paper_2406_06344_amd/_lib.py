@@ -63,6 +63,7 @@ class Decision(ctypes.Structure):
 EXPORTS = [
     "tt_kernel_build_offline", "tt_kernel_build_from_cores", "tt_kernel_factor_rows", "tt_kernel_online_core",
     "tt_kernel_apply", "tt_kernel_apply_plain", "tt_kernel_apply_backward",
+    "tt_kernel_global_online", "tt_kernel_global_apply", "tt_kernel_global_factors",
     "tt_kernel_eval_entries", "tt_kernel_eval_dense", "tt_kernel_get_info",
     "tt_kernel_get_factors", "tt_kernel_get_cores", "tt_kernel_get_cross",
     "tt_kernel_destroy", "tt_kernel_last_error",
@@ -89,6 +90,9 @@ def load():
     lib.tt_kernel_apply.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp, vp]
     lib.tt_kernel_apply_plain.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp]
     lib.tt_kernel_apply_backward.argtypes = [vp, vp, c_int, vp, i64, vp, vp, i64, vp, i64, vp, vp]
+    lib.tt_kernel_global_online.argtypes = [vp, vp, c_int, vp, vp]
+    lib.tt_kernel_global_apply.argtypes = [vp, vp, vp, c_int, vp, i64, vp, i64, vp]
+    lib.tt_kernel_global_factors.argtypes = [vp, P(c_int), vp, P(ctypes.c_double), vp]
     lib.tt_kernel_eval_entries.argtypes = [P(Params), vp, i64, vp, vp]
     lib.tt_kernel_eval_dense.argtypes = [P(Params), vp, i64, vp, i64, P(ctypes.c_double), vp, i64, vp]
     lib.tt_kernel_get_info.argtypes = [vp, P(Info)]

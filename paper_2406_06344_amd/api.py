@@ -37,7 +37,7 @@ def _dtype_code(dtype):
 
 def make_params(kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None, tol=1e-6,
                 dtype=torch.float32, seed=0, max_rank=256, max_sweeps=200, init_card=2,
-                init_max_it=10, n_test=0, kernel_const=0.0):
+                init_max_it=10, n_test=0, kernel_const=0.0, symmetric_psd=False):
     p = Params()
     p.d = int(d)
     p.d_theta = KIND_DTHETA[kind]
@@ -62,7 +62,7 @@ def make_params(kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None,
     p.n_test = int(n_test)
     p.seed = int(seed)
     p.dtype = _dtype_code(dtype)
-    p.symmetric_psd = 0
+    p.symmetric_psd = 1 if symmetric_psd else 0
     return p
 
 
@@ -89,9 +89,11 @@ class TTKernel:
     @classmethod
     def build_offline(cls, X, Y, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None,
                       tol=1e-6, dtype=torch.float32, stream=None, **kw):
+        """Y = None (or Y is X) with symmetric_psd=True builds PTTK-Global-1."""
         lib = _lib.load()
         p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, tol, dtype, **kw)
-        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+        Xs = _soa(X, dtype)
+        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype)
         h = ctypes.c_void_p()
         st = check(lib.tt_kernel_build_offline(ctypes.byref(p), _ptr(Xs), Xs.shape[1], _ptr(Ys), Ys.shape[1],
                                                _stream_ptr(stream), ctypes.byref(h)))
@@ -107,7 +109,8 @@ class TTKernel:
         flat = np.concatenate([np.asarray(c, np.float64).reshape(-1, order="F") for c in cores])
         r_arr = (ctypes.c_int * len(ranks))(*ranks)
         c_arr = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+        Xs = _soa(X, dtype)
+        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype)
         h = ctypes.c_void_p()
         check(lib.tt_kernel_build_from_cores(ctypes.byref(p), r_arr, c_arr, _ptr(Xs), Xs.shape[1], _ptr(Ys),
                                              Ys.shape[1], _stream_ptr(stream), ctypes.byref(h)))
@@ -238,6 +241,48 @@ class TTKernel:
                                                    _ptr(G), self.n_src, _ptr(dX), self.n_tgt, _ptr(dth),
                                                    _stream_ptr(stream)))
         return dX, dth
+
+    # ------------------------------------------------ Global-1 (Algorithm 4)
+    def global_factors(self, stream=None):
+        """(Q (N, k), R (k, k) float64 numpy) of the thin QR [U V] = Q R."""
+        lib = _lib.load()
+        k = ctypes.c_int()
+        check(lib.tt_kernel_global_factors(self._h, ctypes.byref(k), None, None, _stream_ptr(stream)))
+        k = k.value
+        Q = torch.empty((self.n_src, k), dtype=self.dtype, device="cuda")
+        R = np.zeros((k, k), order="F")
+        check(lib.tt_kernel_global_factors(self._h, None, _ptr(Q), R.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           _stream_ptr(stream)))
+        return Q, R
+
+    def global_online(self, theta, stream=None):
+        """W(theta_b) (B, k, k): PSD part of R Hhat R^T."""
+        lib = _lib.load()
+        k = ctypes.c_int()
+        check(lib.tt_kernel_global_factors(self._h, ctypes.byref(k), None, None, _stream_ptr(stream)))
+        k = k.value
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        B = theta.shape[0]
+        W = torch.empty((B, k, k), dtype=self.dtype, device="cuda")
+        check(lib.tt_kernel_global_online(self._h, _ptr(theta), B, _ptr(W), _stream_ptr(stream)))
+        return W.transpose(1, 2)   # stored column-major
+
+    def global_apply(self, X, theta=None, W=None, stream=None):
+        """y_b = Q W_b Q^T x_b for rows x_b of X (B, N); theta (B, d_theta) or W (B, k, k)."""
+        if (theta is None) == (W is None):
+            raise ValueError("give exactly one of theta and W")
+        X = X.to(device="cuda", dtype=self.dtype).contiguous()
+        B = X.shape[0]
+        Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
+        th = None
+        Wc = None
+        if theta is not None:
+            th = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        else:
+            Wc = W.transpose(1, 2).contiguous()   # column-major per matrix
+        check(_lib.load().tt_kernel_global_apply(self._h, _ptr(th), _ptr(Wc), B, _ptr(X), self.n_src, _ptr(Y),
+                                                 self.n_src, _stream_ptr(stream)))
+        return Y
 
 
 class _ApplyFn(torch.autograd.Function):

@@ -172,6 +172,9 @@ struct tt_kernel {
   int rs = 0, rt = 0, ldu = 0, ldv = 0;
   DBuf U, V, nodes, dct, stage[6], pcore[2], gtmp;
   DBuf work, Mbuf, dMbuf, Wbuf, Zbuf, Abuf;
+  // Global-1 (Algorithm 4): Q (N x kg row-major, dtype), R (kg x kg FP64)
+  int kg = 0;
+  DBuf Q, Rg, Gwork, M64, Wg;
   ParamCore pc[2];
   ChainStage src[3], tgt[3];
   KSpec ks{};
@@ -274,6 +277,38 @@ static tt_status begin_build(const tt_kernel_params* p, const void* X, int64_t n
   return TTK_OK;
 }
 
+// Algorithm 4 takes one point set in one box: Y must be X (or NULL).
+static tt_status check_symmetric(const tt_kernel_params* p, const void* X, int64_t n_src, const void** Y,
+                                 int64_t* n_tgt) {
+  if (!p || !p->symmetric_psd) return TTK_OK;
+  if (*Y == nullptr) {
+    *Y = X;
+    *n_tgt = n_src;
+  }
+  if (*Y != X || *n_tgt != n_src)
+    return fail(TTK_ERR_ARG, "symmetric_psd needs Y == X (or Y = NULL) and n_tgt == n_src");
+  for (int j = 0; j < 2 * p->d; ++j)
+    if (p->box_s[j] != p->box_t[j]) return fail(TTK_ERR_ARG, "symmetric_psd needs box_t == box_s");
+  return TTK_OK;
+}
+
+// Offline part of Algorithm 4: thin QR [U V] = Q R.
+static tt_status finish_global(tt_kernel* h, hipStream_t st) {
+  if (!h->P.symmetric_psd) return TTK_OK;
+  h->kg = h->rs + h->rt;
+  TTK_TRY(h->Q.alloc((size_t)std::max<int64_t>(h->ns, 1) * h->kg * h->es));
+  TTK_TRY(h->Rg.alloc((size_t)h->kg * h->kg * sizeof(double)));
+  auto t0 = std::chrono::steady_clock::now();
+  const tt_status s =
+      global_qr(h->dtype, h->U.p, h->ldu, h->rs, h->V.p, h->ldv, h->rt, h->ns, h->Q.p, h->Rg.as<double>(), st);
+  if (s < 0) {
+    h->kg = 0;
+    return s;
+  }
+  h->info.t_factor_ms += ms_since(t0);
+  return TTK_OK;
+}
+
 static void fill_info(tt_kernel* h) {
   tt_kernel_info& I = h->info;
   I.D = h->g.D;
@@ -301,6 +336,7 @@ const char* tt_kernel_last_error(void) { return g_err.c_str(); }
 tt_status tt_kernel_build_offline(const tt_kernel_params* p, const void* X, int64_t n_src, const void* Y,
                                   int64_t n_tgt, void* stream, tt_kernel_t* out) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  TTK_TRY(check_symmetric(p, X, n_src, &Y, &n_tgt));
   std::unique_ptr<tt_kernel> h;
   TTK_TRY(begin_build(p, X, n_src, Y, n_tgt, out, &h, st));
   if (h->P.tol <= 0) return fail(TTK_ERR_ARG, "tol must be positive");
@@ -317,6 +353,7 @@ tt_status tt_kernel_build_offline(const tt_kernel_params* p, const void* X, int6
   TTK_TRY(round_gauge(h->cores, h->ranks, h->g, h->P.tol, st));
   h->info.t_round_ms = ms_since(t0);
   TTK_TRY(finish_build(h.get(), X, Y, st));
+  TTK_TRY(finish_global(h.get(), st));
   fill_info(h.get());
   const tt_status s = h->cross.converged ? TTK_OK : TTK_WARN_NOT_CONVERGED;
   if (s != TTK_OK) set_error("cross stopped with sampled error %.3e > tol %.3e", h->cross.error, h->P.tol);
@@ -327,6 +364,7 @@ tt_status tt_kernel_build_offline(const tt_kernel_params* p, const void* X, int6
 tt_status tt_kernel_build_from_cores(const tt_kernel_params* p, const int* ranks, const double* cores, const void* X,
                                      int64_t n_src, const void* Y, int64_t n_tgt, void* stream, tt_kernel_t* out) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  TTK_TRY(check_symmetric(p, X, n_src, &Y, &n_tgt));
   std::unique_ptr<tt_kernel> h;
   TTK_TRY(begin_build(p, X, n_src, Y, n_tgt, out, &h, st));
   if (!ranks || !cores) return fail(TTK_ERR_ARG, "ranks or cores is NULL");
@@ -343,6 +381,7 @@ tt_status tt_kernel_build_from_cores(const tt_kernel_params* p, const int* ranks
   }
   h->cross_ranks = h->ranks;
   TTK_TRY(finish_build(h.get(), X, Y, st));
+  TTK_TRY(finish_global(h.get(), st));
   fill_info(h.get());
   *out = h.release();
   return TTK_OK;
@@ -460,6 +499,64 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
     // no parameters: nothing to write
   }
   TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tt_kernel_global_online(tt_kernel_t h, const void* theta, int B, void* W_out, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
+  if (B < 0 || (B > 0 && !W_out)) return fail(TTK_ERR_ARG, "bad B or W_out");
+  if (B == 0) return TTK_OK;
+  if (h->g.dt > 0 && !theta) return fail(TTK_ERR_ARG, "theta is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t msz = (size_t)h->rs * h->rt * B;
+  TTK_TRY(h->M64.alloc(msz * sizeof(double)));
+  if (h->g.dt == 0) {
+    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, h->M64.p, h->rs, B, false);
+  } else {
+    TTK_TRY(h->work.alloc(online_work_doubles(h->pc, h->g.dt, B) * sizeof(double)));
+    online_core_mixed(h->dtype, TTK_FP64, h->pc, h->g.dt, theta, B, h->M64.p, nullptr, h->work.as<double>(), st);
+  }
+  TTK_TRY(h->Gwork.alloc(global_online_work(h->rs, h->rt, B) * sizeof(double)));
+  global_online(h->Rg.as<double>(), h->rs, h->rt, h->M64.as<double>(), B, h->dtype, W_out, h->Gwork.as<double>(), st);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W, int B, const void* X, int64_t ldx,
+                                 void* Y, int64_t ldy, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
+  if (B <= 0) return B == 0 ? TTK_OK : fail(TTK_ERR_ARG, "B < 0");
+  if (!X || !Y) return fail(TTK_ERR_ARG, "X or Y is NULL");
+  if (ldx < h->ns || ldy < h->ns) return fail(TTK_ERR_ARG, "leading dimension too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int k = h->kg;
+  if (!W) {
+    TTK_TRY(h->Wg.alloc((size_t)k * k * B * h->es));
+    TTK_TRY(tt_kernel_global_online(h, theta, B, h->Wg.p, stream));
+    W = h->Wg.p;
+  }
+  TTK_TRY(h->Wbuf.alloc((size_t)k * B * h->es));
+  TTK_TRY(h->Zbuf.alloc((size_t)k * B * h->es));
+  apply_reduce(h->dtype, h->Q.p, k, h->ns, k, X, ldx, B, h->Wbuf.p, st);          // Q^T x
+  batched_matvec(h->dtype, W, k, k, 0, h->Wbuf.p, B, h->Zbuf.p, st);             // W (Q^T x)
+  apply_expand(h->dtype, h->Q.p, k, h->ns, k, h->Zbuf.p, B, Y, ldy, st);          // Q (...)
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tt_kernel_global_factors(tt_kernel_t h, int* k, void* Q_out, double* R_out, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (k) *k = h->kg;
+  if (Q_out && h->ns > 0)
+    TTK_HIP(hipMemcpyAsync(Q_out, h->Q.p, (size_t)h->ns * h->kg * h->es, hipMemcpyDeviceToDevice, st));
+  if (R_out) {
+    TTK_HIP(hipMemcpyAsync(R_out, h->Rg.p, (size_t)h->kg * h->kg * sizeof(double), hipMemcpyDeviceToHost, st));
+    TTK_HIP(hipStreamSynchronize(st));
+  }
   return TTK_OK;
 }
 

@@ -1,0 +1,159 @@
+// PTTK-Global-1 (Algorithm 4, Section 3.5) for the symmetric case X = Y.
+//
+// Offline: thin QR of A = [U V] (N x k, k = r_s + r_t) by blocked Householder
+// QR in double precision.  For one point set the source and target factors
+// span nearly the same subspace (for d = 2, n = 8 and ranks n^d they span
+// exactly the same 64-dimensional space), so [U V] is numerically rank
+// deficient; Householder reflections keep Q orthonormal regardless, which a
+// Gram-matrix (Cholesky QR) route cannot.  The panel factorisation runs in
+// one workgroup; the trailing updates and the formation of Q are GEMMs.
+//
+// Online: with Hhat = [[0, M/2], [M^T/2, 0]] (the symmetric-part identity of
+// Section 3.5), W = U Lambda_+ U^T for R Hhat R^T = U Lambda U^T.  The
+// non-negative spectral part is formed as (Mh + |Mh|) / 2 with |Mh| = V Sigma
+// V^T from a one-sided Jacobi SVD Mh = U' Sigma V^T (for symmetric Mh the
+// right singular vectors are eigenvectors and Sigma = |Lambda|).
+#include <cmath>
+
+#include "ttk_internal.h"
+
+namespace ttk {
+
+namespace {
+
+// A (N x k column-major, FP64) = [U V].
+template <class T>
+__global__ void k_concat_cm(const T* U, int ldu, int rs, const T* V, int ldv, int rt, int64_t N, double* A) {
+  const int k = rs + rt;
+  const int64_t total = N * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e % N;
+    const int c = (int)(e / N);
+    A[e] = c < rs ? (double)U[p * ldu + c] : (double)V[p * ldv + (c - rs)];
+  }
+}
+
+// out (N x k row-major, dtype) = Q (N x k column-major, FP64).
+template <class T>
+__global__ void k_q_rowmajor(const double* Q, int64_t N, int k, T* out) {
+  const int64_t total = N * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / k;
+    const int c = (int)(e % k);
+    out[e] = (T)Q[p + (int64_t)c * N];
+  }
+}
+
+// Mh_b <- Mh_b + Mh_b^T (in place, k x k, one block per b) and copies to Jb
+// (the Jacobi input, overwritten by the SVD).
+__global__ void k_sym_copy(double* Mh, double* J, int k, size_t stride) {
+  double* M = Mh + blockIdx.x * stride;
+  double* Jb = J + blockIdx.x * stride;
+  const int64_t total = (int64_t)k * k;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    if (i < j) {
+      const double s = M[i + (size_t)j * k] + M[j + (size_t)i * k];
+      M[i + (size_t)j * k] = s;
+      M[j + (size_t)i * k] = s;
+    } else if (i == j) {
+      M[e] *= 2.0;
+    }
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) Jb[e] = M[e];
+}
+
+// VS_b = V_b diag(sigma_b); the sigma buffer of matrix b starts at sig + b sS.
+__global__ void k_scale_cols(const double* V, const double* sig, size_t sS, int k, size_t stride, double* VS) {
+  const double* Vb = V + blockIdx.x * stride;
+  const double* sb = sig + blockIdx.x * sS;
+  double* out = VS + blockIdx.x * stride;
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) out[e] = Vb[e] * sb[e / k];
+}
+
+// W_b = (Mh_b + VS_b V_b^T) / 2 in the output precision.
+template <class T>
+__global__ void k_psd_part(const double* Mh, const double* VS, const double* V, int k, size_t stride, T* W) {
+  const double* M = Mh + blockIdx.x * stride;
+  const double* A = VS + blockIdx.x * stride;
+  const double* B = V + blockIdx.x * stride;
+  T* out = W + blockIdx.x * (size_t)k * k;
+  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s += A[i + (size_t)q * k] * B[j + (size_t)q * k];
+    out[e] = (T)(0.5 * (M[e] + s));
+  }
+}
+
+inline unsigned nblocks(int64_t n, int64_t cap = 8192) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap));
+}
+
+}  // namespace
+
+tt_status global_qr(int dtype, const void* U, int ldu, int rs, const void* V, int ldv, int rt, int64_t N, void* Q,
+                    double* R, hipStream_t st) {
+  const int k = rs + rt;
+  if (k <= 0) return fail(TTK_ERR_ARG, "Global-1 needs r_s + r_t > 0");
+  if (N < k)
+    return fail(TTK_ERR_UNSUPPORTED, "Global-1 QR needs at least r_s + r_t = %d points (got %lld)", k, (long long)N);
+  if (N > INT32_MAX) return fail(TTK_ERR_UNSUPPORTED, "Global-1 QR supports at most 2^31 - 1 points");
+  DBuf A, work;
+  TTK_TRY(A.alloc((size_t)N * k * sizeof(double)));
+  TTK_TRY(work.alloc(qr_blocked_work((int)N, k) * sizeof(double)));
+  if (dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_concat_cm<float>, dim3(nblocks(N * k)), dim3(256), 0, st, static_cast<const float*>(U), ldu,
+                       rs, static_cast<const float*>(V), ldv, rt, N, A.as<double>());
+  else
+    hipLaunchKernelGGL(k_concat_cm<double>, dim3(nblocks(N * k)), dim3(256), 0, st, static_cast<const double*>(U),
+                       ldu, rs, static_cast<const double*>(V), ldv, rt, N, A.as<double>());
+  TTK_HIP(hipGetLastError());
+  TTK_TRY(qr_blocked(A.as<double>(), (int)N, k, (int)N, R, k, work.as<double>(), st));
+  if (dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_q_rowmajor<float>, dim3(nblocks(N * k)), dim3(256), 0, st, A.as<double>(), N, k,
+                       static_cast<float*>(Q));
+  else
+    hipLaunchKernelGGL(k_q_rowmajor<double>, dim3(nblocks(N * k)), dim3(256), 0, st, A.as<double>(), N, k,
+                       static_cast<double*>(Q));
+  TTK_HIP(hipGetLastError());
+  TTK_HIP(hipStreamSynchronize(st));   // the local buffers are freed on return
+  return TTK_OK;
+}
+
+size_t global_online_work(int rs, int rt, int B) {
+  const size_t k = (size_t)rs + rt;
+  // per theta: P (k x rt), Mh, J (Jacobi input), V, VS (k x k each), sigma + SVD workspace
+  return (size_t)B * (k * rt + 4 * k * k + jacobi_sigma_doubles((int)k)) + 16;
+}
+
+void global_online(const double* R, int rs, int rt, const double* M, int B, int out_dtype, void* W, double* work,
+                   hipStream_t st) {
+  if (B <= 0) return;
+  const int k = rs + rt;
+  const size_t kk = (size_t)k * k;
+  double* P = work;
+  double* Mh = P + (size_t)B * k * rt;
+  double* J = Mh + (size_t)B * kk;
+  double* V = J + (size_t)B * kk;
+  double* VS = V + (size_t)B * kk;
+  double* sig = VS + (size_t)B * kk;
+  const size_t sS = jacobi_sigma_doubles(k);
+  const double* R1 = R;                    // R[:, :rs]
+  const double* R2 = R + (size_t)rs * k;   // R[:, rs:]
+  for (int b = 0; b < B; ++b) {
+    // P = R1 M_b / 2 (k x rt); Mh_b = P R2^T, symmetrised below: R Hhat R^T = P R2^T + R2 P^T
+    gemm64(0, 0, k, rt, rs, 0.5, R1, k, M + (size_t)b * rs * rt, rs, 0.0, P + (size_t)b * k * rt, k, st);
+    gemm64(0, 1, k, k, rt, 1.0, P + (size_t)b * k * rt, k, R2, k, 0.0, Mh + (size_t)b * kk, k, st);
+  }
+  hipLaunchKernelGGL(k_sym_copy, dim3(B), dim3(256), 0, st, Mh, J, k, kk);
+  jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);
+  hipLaunchKernelGGL(k_scale_cols, dim3(B), dim3(256), 0, st, V, sig, sS, k, kk, VS);
+  if (out_dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_psd_part<float>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<float*>(W));
+  else
+    hipLaunchKernelGGL(k_psd_part<double>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<double*>(W));
+}
+
+}  // namespace ttk

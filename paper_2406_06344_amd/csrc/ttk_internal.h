@@ -138,6 +138,11 @@ size_t qr_blocked_work(int m, int n);
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);
+// count independent SVDs, one workgroup each; matrix b at A + b sA, V + b sV,
+// sigma (and its workspace) at sigma + b sS, sS >= jacobi_sigma_doubles(n).
+void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,
+                        size_t sS, int count, hipStream_t st);
+size_t jacobi_sigma_doubles(int n);
 // C = alpha op(A) op(B) + beta C, small FP64 GEMM (many blocks).
 void gemm64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
             const double* B, int ldb, double beta, double* C, int ldc, hipStream_t st);
@@ -182,6 +187,9 @@ struct ParamCore {
 };
 void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M,
                  void* dM, double* work, hipStream_t st);
+// Same with theta and the outputs in separate precisions (TTK_FP32 / TTK_FP64).
+void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
+                       void* M, void* dM, double* work, hipStream_t st);
 size_t online_work_doubles(const ParamCore* pc, int dt, int B);
 
 void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
@@ -193,5 +201,19 @@ void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, con
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,
                       int B, int dt, void* dtheta, hipStream_t st);  // dtheta[b,j] = a_b^T dM_bj w_b
 void fill_zero(void* p, size_t bytes, hipStream_t st);
+// ----------------------------------------------- Global-1 (Algorithm 4)
+// Thin QR of A = [U V] (N x k, k = rs + rt; U, V row-major in dtype) by
+// blocked Householder QR in double precision.  Q: device, dtype, N x k
+// row-major.  R: device, FP64, k x k column-major upper triangular.
+// Synchronises st.
+tt_status global_qr(int dtype, const void* U, int ldu, int rs, const void* V, int ldv, int rt, int64_t N,
+                    void* Q, double* R, hipStream_t st);
+// W_b = (Mh_b + |Mh_b|) / 2, the non-negative spectral part of
+// Mh_b = R Hhat_b R^T, Hhat_b = [[0, M_b / 2], [M_b^T / 2, 0]], for M_b (FP64,
+// rs x rt column-major at M + b rs rt).  W: device, out_dtype, B x k x k.
+// work: global_online_work(rs, rt, B) doubles.
+void global_online(const double* R, int rs, int rt, const double* M, int B, int out_dtype, void* W,
+                   double* work, hipStream_t st);
+size_t global_online_work(int rs, int rt, int B);
 
 }  // namespace ttk

@@ -580,8 +580,14 @@ __global__ void k_zero_rows(double* A, int rows, int cols, int lda) {
 // Pairs follow a round-robin tournament so each round's rotations are
 // disjoint; one wave per pair.
 __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double* V, int ldv,
-                                               double* sigma, double* work, int32_t* order) {
+                                               double* sigma, size_t sA, size_t sV, size_t sS) {
   __shared__ int rotated;
+  // one matrix per workgroup: A, V, sigma (+ its workspace) offset by the batch index
+  A += blockIdx.x * sA;
+  V += blockIdx.x * sV;
+  sigma += blockIdx.x * sS;
+  double* work = sigma + n;
+  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int e = tid; e < n * n; e += BS) V[e % n + (size_t)(e / n) * ldv] = (e % n == e / n) ? 1.0 : 0.0;
   const int np = (n + 1) & ~1;    // players, one dummy when n is odd
@@ -828,10 +834,17 @@ size_t qr_blocked_work(int m, int n) {
 
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {
   // work: n*n + n doubles followed by n int32 (caller-sized through sigma's buffer)
-  double* work = sigma + n;
-  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(BS), 0, st, A, n, lda, V, ldv, sigma, work, order);
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(BS), 0, st, A, n, lda, V, ldv, sigma, (size_t)0, (size_t)0,
+                     (size_t)0);
 }
+
+void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,
+                        size_t sS, int count, hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(BS), 0, st, A, n, lda, V, ldv, sigma, sA, sV, sS);
+}
+
+size_t jacobi_sigma_doubles(int n) { return (size_t)n * n + 3 * (size_t)n + 2; }
 
 void gemm64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
             int ldb, double beta, double* C, int ldc, hipStream_t st) {

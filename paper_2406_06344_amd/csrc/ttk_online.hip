@@ -58,8 +58,8 @@ __device__ void block_gemm(const double* A, const double* B, double* C, int m, i
   __syncthreads();
 }
 
-template <class T>
-__global__ void k_online(OnlineArgs oa, const T* theta, int B, T* M, T* dM, double* work, size_t wstride) {
+template <class TT, class T>
+__global__ void k_online(OnlineArgs oa, const TT* theta, int B, T* M, T* dM, double* work, size_t wstride) {
   __shared__ double tk[MAXN];
   double* w = work + (size_t)blockIdx.x * wstride;
   const int rs = oa.r0[0];
@@ -110,8 +110,8 @@ size_t online_stride(const ParamCore* pc, int dt) {
 
 }  // namespace
 
-void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M, void* dM,
-                 double* work, hipStream_t st) {
+void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
+                       void* M, void* dM, double* work, hipStream_t st) {
   if (B <= 0) return;
   OnlineArgs oa{};
   oa.dt = dt;
@@ -126,12 +126,27 @@ void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int 
   }
   wstride = online_stride(pc, dt);
   const int nblk = std::min(B, 256);
-  if (dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_online<float>, dim3(nblk), dim3(256), 0, st, oa, static_cast<const float*>(theta), B,
-                       static_cast<float*>(M), static_cast<float*>(dM), work, wstride);
+  const bool tf = theta_dtype == TTK_FP32, of = out_dtype == TTK_FP32;
+  if (tf && of)
+    hipLaunchKernelGGL((k_online<float, float>), dim3(nblk), dim3(256), 0, st, oa, static_cast<const float*>(theta),
+                       B, static_cast<float*>(M), static_cast<float*>(dM), work, wstride);
+  else if (tf)
+    hipLaunchKernelGGL((k_online<float, double>), dim3(nblk), dim3(256), 0, st, oa,
+                       static_cast<const float*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
+                       wstride);
+  else if (of)
+    hipLaunchKernelGGL((k_online<double, float>), dim3(nblk), dim3(256), 0, st, oa,
+                       static_cast<const double*>(theta), B, static_cast<float*>(M), static_cast<float*>(dM), work,
+                       wstride);
   else
-    hipLaunchKernelGGL(k_online<double>, dim3(nblk), dim3(256), 0, st, oa, static_cast<const double*>(theta), B,
-                       static_cast<double*>(M), static_cast<double*>(dM), work, wstride);
+    hipLaunchKernelGGL((k_online<double, double>), dim3(nblk), dim3(256), 0, st, oa,
+                       static_cast<const double*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
+                       wstride);
+}
+
+void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M, void* dM,
+                 double* work, hipStream_t st) {
+  online_core_mixed(dtype, dtype, pc, dt, theta, B, M, dM, work, st);
 }
 
 size_t online_work_doubles(const ParamCore* pc, int dt, int B) {
