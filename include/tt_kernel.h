@@ -233,6 +233,96 @@ tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W
  * (synchronises `stream` when given). */
 tt_status tt_kernel_global_factors(tt_kernel_t h, int* k, void* Q_out, double* R_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Interaction lists: many source/target box pairs at once (Section 1 names
+ * the low-rank blocks of FMM / H-matrix forms as the use case).
+ *
+ * Pairs whose grid tensors coincide share one TT: every kernel of Table 1
+ * depends on x and y only through r = ||x - y||_2, so a common translation,
+ * reflection of an axis or permutation of the axes of both boxes leaves the
+ * tensor unchanged up to reversing / permuting node indices.  A pair is
+ * mapped to its canonical frame (axes sorted by (source side, target side,
+ * |centre offset|), offsets made non-negative, source box at [0, side]);
+ * pairs with equal canonical boxes form one class and one cross / rounding
+ * is run per class.  The two test kernels get one class per pair.  Phase 3
+ * then runs for the points of every pair, through its class cores with its
+ * own axis order and orientation, in ONE persistent launch over a work list
+ * of (pair, 64-point tile) items.
+ */
+typedef struct tt_kernel_batch* tt_kernel_batch_t;
+
+typedef struct {
+  double box_s[6];          /* source box [alpha_1, beta_1, ..., alpha_d, beta_d]    */
+  double box_t[6];          /* target box, same layout                               */
+  int64_t src_off, n_src;   /* sources of the pair: points src_off .. src_off+n_src-1 of X */
+  int64_t tgt_off, n_tgt;   /* targets: points tgt_off .. tgt_off+n_tgt-1 of Y       */
+} tt_kernel_pair;
+
+typedef struct {
+  int num_pairs, num_classes;
+  int64_t kernel_evals;     /* device kernel evaluations of all class builds          */
+  int64_t factor_rows;      /* sum over pairs of n_src + n_tgt                        */
+  double t_cross_ms, t_round_ms, t_factor_ms;
+  int factor_grid;          /* workgroups of the persistent Phase 3 launch (0 = one
+                               per tile, or one launch per pair in double precision) */
+  int reduce_rows;          /* rows per work item of the tall reductions (last apply) */
+  int graph;                /* 1 if applies replay a captured HIP graph               */
+} tt_kernel_batch_info;
+
+/* Build a batch: p gives the kernel, the grid sizes, the tolerance and dtype
+ * (its box_s / box_t are ignored).  pairs: host array of num_pairs >= 1.
+ * X: device, dtype, SoA d x n_x (all source points), Y: device, dtype,
+ * SoA d x n_y; each pair's points must lie in its boxes.  Synchronises
+ * `stream`.  The Phase 3 launch shape (workgroups of the persistent launch)
+ * is chosen by timing candidates on the device unless set by
+ * tt_kernel_batch_configure before a refactor. */
+tt_status tt_kernel_batch_build(const tt_kernel_params* p, const tt_kernel_pair* pairs, int num_pairs,
+                                const void* X, int64_t n_x, const void* Y, int64_t n_y,
+                                void* stream, tt_kernel_batch_t* out);
+
+/* Overrides of the autotuned choices (0 = choose by timing): use_graph (1 =
+ * capture the apply once per argument set and replay it, 0 = launch
+ * directly), factor_grid (workgroups of the persistent Phase 3 launch, -1 =
+ * one per tile), reduce_rows (rows per item of the tall reductions). */
+tt_status tt_kernel_batch_configure(tt_kernel_batch_t b, int use_graph, int factor_grid, int reduce_rows);
+
+/* Phase 3 again for new points with the same pair layout (same offsets and
+ * counts, same boxes): one persistent launch on `stream`. */
+tt_status tt_kernel_batch_factor(tt_kernel_batch_t b, const void* X, const void* Y, void* stream);
+
+/* info: host.  class_of_pair: NULL or host int[num_pairs].  class_ranks:
+ * NULL or host int[num_classes * 9] (ranks r_0..r_D of each class). */
+tt_status tt_kernel_batch_get_info(tt_kernel_batch_t b, tt_kernel_batch_info* info, int* class_of_pair,
+                                   int* class_ranks);
+
+/* Borrowed handle of class c (owned by the batch: do not destroy).  It has
+ * no points (n_src = n_tgt = 0); its cores, online core and cross record are
+ * those of the class, in the canonical frame. */
+tt_status tt_kernel_batch_get_class(tt_kernel_batch_t b, int c, tt_kernel_t* h);
+
+/* Rows of U (n_src x r_s) and V (n_tgt x r_t) of one pair, row-major dtype,
+ * into device buffers (either may be NULL). */
+tt_status tt_kernel_batch_get_factors(tt_kernel_batch_t b, int pair, void* U_out, void* V_out, void* stream);
+
+/* Apply over the list, for b = 0..B-1:
+ *   Y[:, b] = sum_p E_p U_p M_c(p)(theta_b) V_p^T F_p^T X[:, b]
+ * (E_p, F_p scatter / gather the pair's source / target rows; rows covered by
+ * no pair are set to 0), and when G is not NULL the backward pass of
+ * L = sum_b <g_b, y_b>:
+ *   dX[:, b] = sum_p F_p V_p M_c^T U_p^T E_p^T G[:, b]   (dX may be NULL)
+ *   dtheta[b, j] = sum_p (U_p^T g_pb)^T dM_c/dtheta_j (V_p^T x_pb)   (may be NULL)
+ * theta: device, dtype, B x d_theta.  X: n_y x B (ldx), Y: n_x x B (ldy),
+ * G: n_x x B (ldg), dX: n_y x B (lddx), dtheta: B x d_theta; all device,
+ * dtype, column-major.  Every tall contraction is one launch over a work list
+ * of (pair, row chunk, theta tile) items; the whole sequence is captured as a
+ * HIP graph on the first call with a given argument set and replayed on
+ * later calls with the same arguments.  Calls on one batch must not overlap. */
+tt_status tt_kernel_batch_apply(tt_kernel_batch_t b, const void* theta, int B, const void* X, int64_t ldx,
+                                void* Y, int64_t ldy, const void* G, int64_t ldg, void* dX, int64_t lddx,
+                                void* dtheta, void* stream);
+
+tt_status tt_kernel_batch_destroy(tt_kernel_batch_t b);
+
 /* f_kappa at P grid multi-indices (Section 2.4, entries of the grid tensor),
  * in double precision on the device.  idx: device int32, P x D row-major,
  * 0-based node indices in the (x, theta, y) order.  out: device double, P. */

@@ -92,8 +92,11 @@ def offline(kind, d, box_theta, n_spatial, n_param, pairs, X, Y, eps, seed=0, co
         P, out = builds[c]
         Xp = to_canonical(X[p["src_off"]:p["src_off"] + p["n_src"]], fr)
         Yp = to_canonical(Y[p["tgt_off"]:p["tgt_off"] + p["n_tgt"]], fr)
-        S.append(pttk.phase3_source(pttk.factor_values(Xp, P.box_s, n_spatial), out["cores"][:d]))
-        T.append(pttk.phase3_target(pttk.factor_values(Yp, P.box_t, n_spatial), out["cores"][d + P.dt:]))
+        rs, rt = out["ranks"][d], out["ranks"][d + P.dt]
+        S.append(pttk.phase3_source(pttk.factor_values(Xp, P.box_s, n_spatial), out["cores"][:d])
+                 if len(Xp) else np.zeros((0, rs)))
+        T.append(pttk.phase3_target(pttk.factor_values(Yp, P.box_t, n_spatial), out["cores"][d + P.dt:])
+                 if len(Yp) else np.zeros((0, rt)))
     return {"class": cls, "frames": frames, "builds": builds, "S": S, "T": T}
 
 

@@ -60,10 +60,29 @@ class Decision(ctypes.Structure):
     ]
 
 
+class Pair(ctypes.Structure):
+    _fields_ = [
+        ("box_s", ctypes.c_double * 6), ("box_t", ctypes.c_double * 6),
+        ("src_off", ctypes.c_int64), ("n_src", ctypes.c_int64),
+        ("tgt_off", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("num_pairs", ctypes.c_int), ("num_classes", ctypes.c_int), ("kernel_evals", ctypes.c_int64),
+        ("factor_rows", ctypes.c_int64), ("t_cross_ms", ctypes.c_double), ("t_round_ms", ctypes.c_double),
+        ("t_factor_ms", ctypes.c_double), ("factor_grid", ctypes.c_int), ("reduce_rows", ctypes.c_int),
+        ("graph", ctypes.c_int),
+    ]
+
+
 EXPORTS = [
     "tt_kernel_build_offline", "tt_kernel_build_from_cores", "tt_kernel_factor_rows", "tt_kernel_online_core",
     "tt_kernel_apply", "tt_kernel_apply_plain", "tt_kernel_apply_backward",
     "tt_kernel_global_online", "tt_kernel_global_apply", "tt_kernel_global_factors",
+    "tt_kernel_batch_build", "tt_kernel_batch_configure", "tt_kernel_batch_factor", "tt_kernel_batch_get_info",
+    "tt_kernel_batch_get_class", "tt_kernel_batch_get_factors", "tt_kernel_batch_apply", "tt_kernel_batch_destroy",
     "tt_kernel_eval_entries", "tt_kernel_eval_dense", "tt_kernel_get_info",
     "tt_kernel_get_factors", "tt_kernel_get_cores", "tt_kernel_get_cross",
     "tt_kernel_destroy", "tt_kernel_last_error",
@@ -93,6 +112,14 @@ def load():
     lib.tt_kernel_global_online.argtypes = [vp, vp, c_int, vp, vp]
     lib.tt_kernel_global_apply.argtypes = [vp, vp, vp, c_int, vp, i64, vp, i64, vp]
     lib.tt_kernel_global_factors.argtypes = [vp, P(c_int), vp, P(ctypes.c_double), vp]
+    lib.tt_kernel_batch_build.argtypes = [P(Params), P(Pair), c_int, vp, i64, vp, i64, vp, P(vp)]
+    lib.tt_kernel_batch_configure.argtypes = [vp, c_int, c_int, c_int]
+    lib.tt_kernel_batch_factor.argtypes = [vp, vp, vp, vp]
+    lib.tt_kernel_batch_get_info.argtypes = [vp, P(BatchInfo), P(c_int), P(c_int)]
+    lib.tt_kernel_batch_get_class.argtypes = [vp, c_int, P(vp)]
+    lib.tt_kernel_batch_get_factors.argtypes = [vp, c_int, vp, vp, vp]
+    lib.tt_kernel_batch_apply.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]
+    lib.tt_kernel_batch_destroy.argtypes = [vp]
     lib.tt_kernel_eval_entries.argtypes = [P(Params), vp, i64, vp, vp]
     lib.tt_kernel_eval_dense.argtypes = [P(Params), vp, i64, vp, i64, P(ctypes.c_double), vp, i64, vp]
     lib.tt_kernel_get_info.argtypes = [vp, P(Info)]

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import KINDS, KIND_DTHETA, TTK_FP32, TTK_FP64, Decision, Info, Params, check
+from ._lib import KINDS, KIND_DTHETA, TTK_FP32, TTK_FP64, BatchInfo, Decision, Info, Pair, Params, check
 
 
 def _stream_ptr(stream=None):
@@ -118,6 +118,8 @@ class TTKernel:
 
     def __del__(self):
         h = getattr(self, "_h", None)
+        if getattr(self, "_borrowed", False):
+            return
         if h is not None and h.value:
             try:
                 _lib.load().tt_kernel_destroy(h)
@@ -332,3 +334,117 @@ def eval_dense(X, Y, theta, kind, d, dtype=torch.float64, kernel_const=0.0, stre
     check(lib.tt_kernel_eval_dense(ctypes.byref(p), _ptr(Xs), nx, _ptr(Ys), ny, th, _ptr(K), nx,
                                    _stream_ptr(stream)))
     return K.t()
+
+
+class TTBatch:
+    """An interaction list of source/target box pairs (one TT per geometry
+    class, Phase 3 for every pair in one persistent launch, batched apply and
+    backward as one captured graph).  pairs: list of dicts with box_s, box_t
+    ((d, 2) boxes), src_off, n_src, tgt_off, n_tgt (rows of X / Y)."""
+
+    def __init__(self, handle, params, dtype, pairs, n_x, n_y, status):
+        self._h = handle
+        self.params = params
+        self.dtype = dtype
+        self.pairs = pairs
+        self.n_x, self.n_y = n_x, n_y
+        self.status = status
+        self.d_theta = params.d_theta
+
+    @classmethod
+    def build(cls, pairs, X, Y, kind, d, box_theta=(), n_spatial=16, n_param=None, tol=1e-6,
+              dtype=torch.float32, stream=None, **kw):
+        lib = _lib.load()
+        p = make_params(kind, d, [[0, 1]] * d, [[2, 3]] * d, box_theta, n_spatial, n_param, tol, dtype, **kw)
+        arr = (Pair * len(pairs))()
+        for i, q in enumerate(pairs):
+            bs = np.asarray(q["box_s"], float).reshape(-1)
+            bt = np.asarray(q["box_t"], float).reshape(-1)
+            for j in range(bs.size):
+                arr[i].box_s[j] = bs[j]
+                arr[i].box_t[j] = bt[j]
+            arr[i].src_off, arr[i].n_src = int(q["src_off"]), int(q["n_src"])
+            arr[i].tgt_off, arr[i].n_tgt = int(q["tgt_off"]), int(q["n_tgt"])
+        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+        h = ctypes.c_void_p()
+        st = check(lib.tt_kernel_batch_build(ctypes.byref(p), arr, len(pairs), _ptr(Xs), Xs.shape[1], _ptr(Ys),
+                                             Ys.shape[1], _stream_ptr(stream), ctypes.byref(h)))
+        return cls(h, p, dtype, pairs, Xs.shape[1], Ys.shape[1], st)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().tt_kernel_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def configure(self, use_graph=True, factor_grid=0, reduce_rows=0):
+        check(_lib.load().tt_kernel_batch_configure(self._h, int(bool(use_graph)), int(factor_grid),
+                                                    int(reduce_rows)))
+
+    def refactor(self, X, Y, stream=None):
+        """Phase 3 again for points (same layout); returns the SoA copies used."""
+        Xs, Ys = _soa(X, self.dtype), _soa(Y, self.dtype)
+        check(_lib.load().tt_kernel_batch_factor(self._h, _ptr(Xs), _ptr(Ys), _stream_ptr(stream)))
+        return Xs, Ys
+
+    def refactor_soa(self, Xs, Ys, stream=None):
+        check(_lib.load().tt_kernel_batch_factor(self._h, _ptr(Xs), _ptr(Ys), _stream_ptr(stream)))
+
+    def info(self):
+        lib = _lib.load()
+        inf = BatchInfo()
+        check(lib.tt_kernel_batch_get_info(self._h, ctypes.byref(inf), None, None))
+        cop = (ctypes.c_int * max(inf.num_pairs, 1))()
+        cr = (ctypes.c_int * (9 * max(inf.num_classes, 1)))()
+        check(lib.tt_kernel_batch_get_info(self._h, None, cop, cr))
+        D = 2 * self.params.d + self.params.d_theta
+        return {"num_pairs": inf.num_pairs, "num_classes": inf.num_classes, "kernel_evals": inf.kernel_evals,
+                "factor_rows": inf.factor_rows, "t_cross_ms": inf.t_cross_ms, "t_round_ms": inf.t_round_ms,
+                "t_factor_ms": inf.t_factor_ms, "factor_grid": inf.factor_grid, "reduce_rows": inf.reduce_rows,
+                "graph": bool(inf.graph), "class_of_pair": list(cop)[:inf.num_pairs],
+                "class_ranks": [list(cr[9 * c:9 * c + D + 1]) for c in range(inf.num_classes)]}
+
+    def class_kernel(self, c):
+        """The TTKernel of class c (borrowed from the batch, canonical frame, no points)."""
+        h = ctypes.c_void_p()
+        check(_lib.load().tt_kernel_batch_get_class(self._h, int(c), ctypes.byref(h)))
+        k = TTKernel.__new__(TTKernel)
+        k._borrowed = True
+        k._owner = self
+        TTKernel.__init__(k, h, self.params, self.dtype, 0, 0)
+        return k
+
+    def factors(self, pair, stream=None):
+        inf = self.info()
+        c = inf["class_of_pair"][pair]
+        r = inf["class_ranks"][c]
+        d = self.params.d
+        rs, rt = r[d], r[d + self.d_theta]
+        q = self.pairs[pair]
+        U = torch.empty((int(q["n_src"]), rs), dtype=self.dtype, device="cuda")
+        V = torch.empty((int(q["n_tgt"]), rt), dtype=self.dtype, device="cuda")
+        check(_lib.load().tt_kernel_batch_get_factors(self._h, int(pair), _ptr(U), _ptr(V), _stream_ptr(stream)))
+        return U, V
+
+    def apply(self, theta, X, G=None, want_dx=True, want_dtheta=True, out=None, stream=None):
+        """Y (B, n_x) = sum over pairs; with G (B, n_x) also dX (B, n_y) and dtheta (B, d_theta).
+        out: optional (Y, dX, dtheta) tensors to write into (keeps the captured graph valid)."""
+        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        X = X.to(device="cuda", dtype=self.dtype).contiguous()
+        B = X.shape[0]
+        if out is not None:
+            Y, dX, dth = out
+        else:
+            Y = torch.empty((B, self.n_x), dtype=self.dtype, device="cuda")
+            dX = torch.empty((B, self.n_y), dtype=self.dtype, device="cuda") if (G is not None and want_dx) \
+                else None
+            dth = torch.empty((B, max(self.d_theta, 1)), dtype=self.dtype, device="cuda") \
+                if (G is not None and want_dtheta and self.d_theta > 0) else None
+        Gc = G.to(device="cuda", dtype=self.dtype).contiguous() if G is not None else None
+        check(_lib.load().tt_kernel_batch_apply(self._h, _ptr(theta), B, _ptr(X), self.n_y, _ptr(Y), self.n_x,
+                                                _ptr(Gc), self.n_x, _ptr(dX), self.n_y, _ptr(dth),
+                                                _stream_ptr(stream)))
+        return (Y, dX, dth) if G is not None else Y

@@ -1,8 +1,11 @@
 // C ABI of the PTTK library (tt_kernel.h): handle lifecycle, argument checks,
 // and the orchestration of the offline stage (Algorithm 2), the online stage
 // (Algorithm 3) and the apply / backward calls on the caller's stream.
+#include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -655,6 +658,555 @@ tt_status tt_kernel_get_cross(tt_kernel_t h, int32_t* left, int32_t* right, tt_k
 
 tt_status tt_kernel_destroy(tt_kernel_t h) {
   delete h;
+  return TTK_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================
+// Interaction lists (tt_kernel_batch_*)
+// ===================================================================
+
+namespace {
+
+// Canonical frame of a box pair: canonical axis j is the pair's axis perm[j],
+// reflected when sign[j] < 0; canonical source box [0, hs], target box centred
+// at hs/2 + |delta|.  identity: the pair's own boxes (test kernels).
+struct Frame {
+  int perm[3] = {0, 1, 2};
+  int sign[3] = {1, 1, 1};
+  double cbs[6] = {0}, cbt[6] = {0};
+  std::vector<double> key;
+};
+
+bool isotropic_kind(int kind) { return kind != TTK_TEST_POLY && kind != TTK_TEST_SEP; }
+
+double round12(double v) {
+  char buf[64];
+  snprintf(buf, sizeof(buf), "%.11e", v);
+  return std::strtod(buf, nullptr);
+}
+
+Frame pair_frame(int kind, int d, const tt_kernel_pair& pr) {
+  Frame f;
+  if (!isotropic_kind(kind)) {
+    for (int j = 0; j < 2 * d; ++j) {
+      f.cbs[j] = pr.box_s[j];
+      f.cbt[j] = pr.box_t[j];
+      f.key.push_back(pr.box_s[j]);
+      f.key.push_back(pr.box_t[j]);
+    }
+    f.key.push_back(-1.0);
+    return f;
+  }
+  double hs[3], ht[3], dl[3];
+  for (int i = 0; i < d; ++i) {
+    hs[i] = pr.box_s[2 * i + 1] - pr.box_s[2 * i];
+    ht[i] = pr.box_t[2 * i + 1] - pr.box_t[2 * i];
+    dl[i] = 0.5 * (pr.box_t[2 * i] + pr.box_t[2 * i + 1]) - 0.5 * (pr.box_s[2 * i] + pr.box_s[2 * i + 1]);
+  }
+  auto tup = [&](int i) { return std::array<double, 3>{round12(hs[i]), round12(ht[i]), round12(std::fabs(dl[i]))}; };
+  std::vector<int> ax(d);
+  for (int i = 0; i < d; ++i) ax[i] = i;
+  std::stable_sort(ax.begin(), ax.end(), [&](int a, int b) { return tup(a) < tup(b); });
+  for (int j = 0; j < d; ++j) {
+    const int i = ax[j];
+    f.perm[j] = i;
+    f.sign[j] = dl[i] >= 0.0 ? 1 : -1;
+    f.cbs[2 * j] = 0.0;
+    f.cbs[2 * j + 1] = hs[i];
+    const double m = 0.5 * hs[i] + std::fabs(dl[i]);
+    f.cbt[2 * j] = m - 0.5 * ht[i];
+    f.cbt[2 * j + 1] = m + 0.5 * ht[i];
+    const auto t = tup(i);
+    f.key.insert(f.key.end(), t.begin(), t.end());
+  }
+  return f;
+}
+
+}  // namespace
+
+struct tt_kernel_batch {
+  tt_kernel_params P{};
+  int dtype = TTK_FP32, d = 0, dt = 0, D = 0;
+  size_t es = 4;
+  std::vector<tt_kernel_pair> pairs;
+  std::vector<int> cls;
+  std::vector<std::unique_ptr<tt_kernel>> classes;
+  std::vector<ChainStage> stages;          // per pair: d source stages, then d target stages
+  std::vector<int64_t> uoff, voff;         // element offsets of the pair blocks of U and V
+  int64_t nx = 0, ny = 0;
+  DBuf U, V;
+  FactorBatchPlan plan;
+  const void* lastX = nullptr;
+  const void* lastY = nullptr;
+  int factor_grid = 0;                     // chosen persistent grid (0 = one per tile)
+  bool converged = true;
+  int cfg_graph = 1, cfg_factor_grid = 0, cfg_reduce_rows = 0;
+  tt_kernel_batch_info info{};
+  // apply state, prepared per B
+  int prepB = -1, reduce_rows = 0;
+  std::vector<BatchSide> hs, ht;
+  DBuf dsides_s, dsides_t, dmoff, ddmoff;
+  DBuf it_rt, it_rs, it_es, it_et;         // reduce over targets / sources, expand over sources / targets
+  int64_t n_rt = 0, n_rs = 0, n_es = 0, n_et = 0;
+  DBuf Mall, dMall, work, Wt, Zs, As, Zt, part;
+  std::vector<int64_t> Moff, dMoff;        // per class
+  // captured graph
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+  ~tt_kernel_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+tt_status batch_phase3(tt_kernel_batch* b, const void* X, const void* Y, int grid, hipStream_t st) {
+  const int d = b->d;
+  if (X != b->lastX || Y != b->lastY) {
+    b->plan.njobs = -1;   // the job list holds the point pointers
+    b->lastX = X;
+    b->lastY = Y;
+  }
+  const int np = (int)b->pairs.size();
+  std::vector<FactorJob> jobs;
+  jobs.reserve(2 * np);
+  for (int p = 0; p < np; ++p) {
+    const tt_kernel_pair& pr = b->pairs[p];
+    const tt_kernel* c = b->classes[b->cls[p]].get();
+    if (pr.n_src > 0)
+      jobs.push_back(FactorJob{&b->stages[(size_t)p * 2 * d], d, static_cast<const char*>(X) + pr.src_off * b->es,
+                               b->nx, pr.n_src, b->U.as<char>() + b->uoff[p] * b->es, c->rs});
+    if (pr.n_tgt > 0)
+      jobs.push_back(FactorJob{&b->stages[(size_t)p * 2 * d + d], d, static_cast<const char*>(Y) + pr.tgt_off * b->es,
+                               b->ny, pr.n_tgt, b->V.as<char>() + b->voff[p] * b->es, c->rt});
+  }
+  return factor_contract_batch(b->dtype, jobs.data(), (int)jobs.size(), grid, st, &b->plan);
+}
+
+// Phase 3 with the launch shape chosen by timing when not fixed by the caller.
+tt_status batch_phase3_tuned(tt_kernel_batch* b, const void* X, const void* Y, hipStream_t st) {
+  if (b->cfg_factor_grid != 0) {
+    b->factor_grid = b->cfg_factor_grid < 0 ? 0 : b->cfg_factor_grid;
+    return batch_phase3(b, X, Y, b->factor_grid, st);
+  }
+  TTK_TRY(batch_phase3(b, X, Y, 0, st));
+  if (!b->plan.persistent) {
+    b->factor_grid = 0;
+    return TTK_OK;
+  }
+  int dev = 0, cus = 256;
+  TTK_HIP(hipGetDevice(&dev));
+  TTK_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int cand[5] = {0, cus, 2 * cus, 4 * cus, 8 * cus};
+  hipEvent_t e0, e1;
+  TTK_HIP(hipEventCreate(&e0));
+  TTK_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_g = 0;
+  for (int g : cand) {
+    TTK_TRY(batch_phase3(b, X, Y, g, st));   // warm
+    TTK_HIP(hipEventRecord(e0, st));
+    TTK_TRY(batch_phase3(b, X, Y, g, st));
+    TTK_HIP(hipEventRecord(e1, st));
+    TTK_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TTK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; best_g = g; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->factor_grid = best_g;
+  return batch_phase3(b, X, Y, best_g, st);
+}
+
+void make_items(const std::vector<BatchSide>& sides, int64_t rows, bool rank_tiles, int B,
+                std::vector<BatchItem>* out) {
+  out->clear();
+  for (int s = 0; s < (int)sides.size(); ++s) {
+    const BatchSide& sd = sides[s];
+    const int nrt = rank_tiles ? (sd.r + 63) / 64 : 1;
+    for (int64_t r0 = 0; r0 < sd.n; r0 += rows)
+      for (int rt = 0; rt < nrt; ++rt)
+        for (int b0 = 0; b0 < B; b0 += 64)
+          out->push_back(BatchItem{r0, s, (int)std::min<int64_t>(rows, sd.n - r0), rt * 64, b0});
+  }
+}
+
+tt_status upload_items(const std::vector<BatchItem>& v, DBuf* buf, int64_t* n, hipStream_t st) {
+  *n = (int64_t)v.size();
+  TTK_TRY(buf->alloc(std::max<size_t>(1, v.size()) * sizeof(BatchItem)));
+  if (!v.empty()) TTK_HIP(hipMemcpyAsync(buf->p, v.data(), v.size() * sizeof(BatchItem), hipMemcpyHostToDevice, st));
+  return TTK_OK;
+}
+
+tt_status set_reduce_rows(tt_kernel_batch* b, int rows, int B, hipStream_t st) {
+  std::vector<BatchItem> v;
+  make_items(b->ht, rows, true, B, &v);
+  TTK_TRY(upload_items(v, &b->it_rt, &b->n_rt, st));
+  make_items(b->hs, rows, true, B, &v);
+  TTK_TRY(upload_items(v, &b->it_rs, &b->n_rs, st));
+  TTK_HIP(hipStreamSynchronize(st));   // host staging goes out of scope
+  b->reduce_rows = rows;
+  return TTK_OK;
+}
+
+// Buffers, side tables and work lists for B thetas; the reduction chunk is
+// chosen by timing the target-side reduction on X when not fixed.
+tt_status batch_prepare(tt_kernel_batch* b, int B, const void* X, int64_t ldx, hipStream_t st) {
+  if (b->prepB == B) return TTK_OK;
+  const int np = (int)b->pairs.size(), nc = (int)b->classes.size();
+  const size_t es = b->es;
+  b->hs.assign(np, BatchSide{});
+  b->ht.assign(np, BatchSide{});
+  std::vector<int64_t> moff(np), dmoff(np);
+  b->Moff.assign(nc, 0);
+  b->dMoff.assign(nc, 0);
+  int64_t m = 0, dm = 0;
+  size_t wmax = 16;
+  for (int c = 0; c < nc; ++c) {
+    const tt_kernel* k = b->classes[c].get();
+    b->Moff[c] = m;
+    b->dMoff[c] = dm;
+    m += (int64_t)B * k->rs * k->rt;
+    dm += (int64_t)B * std::max(b->dt, 1) * k->rs * k->rt;
+    if (b->dt > 0) wmax = std::max(wmax, online_work_doubles(k->pc, b->dt, B));
+  }
+  int64_t ws = 0, wt = 0;
+  for (int p = 0; p < np; ++p) {
+    const tt_kernel_pair& pr = b->pairs[p];
+    const tt_kernel* k = b->classes[b->cls[p]].get();
+    b->hs[p] = BatchSide{b->uoff[p], pr.n_src, pr.src_off, ws, k->rs, 0};
+    b->ht[p] = BatchSide{b->voff[p], pr.n_tgt, pr.tgt_off, wt, k->rt, 0};
+    ws += (int64_t)k->rs * B;
+    wt += (int64_t)k->rt * B;
+    moff[p] = b->Moff[b->cls[p]];
+    dmoff[p] = b->dMoff[b->cls[p]];
+  }
+  TTK_TRY(b->dsides_s.alloc(sizeof(BatchSide) * np));
+  TTK_TRY(b->dsides_t.alloc(sizeof(BatchSide) * np));
+  TTK_TRY(b->dmoff.alloc(sizeof(int64_t) * np));
+  TTK_TRY(b->ddmoff.alloc(sizeof(int64_t) * np));
+  TTK_HIP(hipMemcpyAsync(b->dsides_s.p, b->hs.data(), sizeof(BatchSide) * np, hipMemcpyHostToDevice, st));
+  TTK_HIP(hipMemcpyAsync(b->dsides_t.p, b->ht.data(), sizeof(BatchSide) * np, hipMemcpyHostToDevice, st));
+  TTK_HIP(hipMemcpyAsync(b->dmoff.p, moff.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice, st));
+  TTK_HIP(hipMemcpyAsync(b->ddmoff.p, dmoff.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice, st));
+  TTK_TRY(b->Mall.alloc(std::max<int64_t>(m, 1) * es));
+  TTK_TRY(b->dMall.alloc(std::max<int64_t>(dm, 1) * es));
+  TTK_TRY(b->work.alloc(wmax * sizeof(double)));
+  TTK_TRY(b->Wt.alloc(std::max<int64_t>(wt, 1) * es));
+  TTK_TRY(b->Zt.alloc(std::max<int64_t>(wt, 1) * es));
+  TTK_TRY(b->Zs.alloc(std::max<int64_t>(ws, 1) * es));
+  TTK_TRY(b->As.alloc(std::max<int64_t>(ws, 1) * es));
+  TTK_TRY(b->part.alloc(std::max<size_t>(1, (size_t)B * std::max(b->dt, 1) * np) * sizeof(double)));
+  std::vector<BatchItem> v;
+  make_items(b->hs, 64, false, B, &v);
+  TTK_TRY(upload_items(v, &b->it_es, &b->n_es, st));
+  make_items(b->ht, 64, false, B, &v);
+  TTK_TRY(upload_items(v, &b->it_et, &b->n_et, st));
+  TTK_HIP(hipStreamSynchronize(st));
+  if (b->cfg_reduce_rows > 0) {
+    TTK_TRY(set_reduce_rows(b, b->cfg_reduce_rows, B, st));
+  } else {
+    // time the target-side reduction for each candidate chunk
+    const int cand[4] = {256, 1024, 4096, 16384};
+    hipEvent_t e0, e1;
+    TTK_HIP(hipEventCreate(&e0));
+    TTK_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_r = 1024;
+    for (int rows : cand) {
+      TTK_TRY(set_reduce_rows(b, rows, B, st));
+      fill_zero(b->Wt.p, (size_t)std::max<int64_t>(wt, 1) * es, st);
+      batch_reduce(b->dtype, b->V.p, b->dsides_t.as<BatchSide>(), b->it_rt.as<BatchItem>(), b->n_rt, X, ldx, B,
+                   b->Wt.p, st);
+      TTK_HIP(hipEventRecord(e0, st));
+      fill_zero(b->Wt.p, (size_t)std::max<int64_t>(wt, 1) * es, st);
+      batch_reduce(b->dtype, b->V.p, b->dsides_t.as<BatchSide>(), b->it_rt.as<BatchItem>(), b->n_rt, X, ldx, B,
+                   b->Wt.p, st);
+      TTK_HIP(hipEventRecord(e1, st));
+      TTK_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TTK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; best_r = rows; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    TTK_TRY(set_reduce_rows(b, best_r, B, st));
+  }
+  TTK_HIP(hipGetLastError());
+  b->prepB = B;
+  b->info.reduce_rows = b->reduce_rows;
+  return TTK_OK;
+}
+
+// The whole apply (+ backward) on stream st: launches only, no allocation or
+// synchronisation, so it can be captured.
+tt_status batch_enqueue(tt_kernel_batch* b, const void* theta, int B, const void* X, int64_t ldx, void* Y,
+                        int64_t ldy, const void* G, int64_t ldg, void* dX, int64_t lddx, void* dtheta,
+                        hipStream_t st) {
+  const int np = (int)b->pairs.size();
+  const int dt = b->dt;
+  const size_t es = b->es;
+  const bool want_dth = G && dtheta && dt > 0;
+  for (int c = 0; c < (int)b->classes.size(); ++c) {
+    tt_kernel* k = b->classes[c].get();
+    char* Mc = b->Mall.as<char>() + b->Moff[c] * es;
+    char* dMc = b->dMall.as<char>() + b->dMoff[c] * es;
+    if (dt == 0)
+      hipLaunchKernelGGL(k_identity_batch, dim3(64), dim3(256), 0, st, Mc, k->rs, B, b->dtype == TTK_FP32);
+    else
+      online_core(b->dtype, k->pc, dt, theta, B, Mc, want_dth ? dMc : nullptr, b->work.as<double>(), st);
+  }
+  int64_t wt = 0, ws = 0;
+  for (int p = 0; p < np; ++p) {
+    wt += (int64_t)b->ht[p].r * B;
+    ws += (int64_t)b->hs[p].r * B;
+  }
+  const BatchSide* ss = b->dsides_s.as<BatchSide>();
+  const BatchSide* ts = b->dsides_t.as<BatchSide>();
+  // forward: W_p = V_p^T x_p, Z_p = M W_p, Y = sum_p U_p Z_p
+  fill_zero(b->Wt.p, (size_t)std::max<int64_t>(wt, 1) * es, st);
+  batch_reduce(b->dtype, b->V.p, ts, b->it_rt.as<BatchItem>(), b->n_rt, X, ldx, B, b->Wt.p, st);
+  batch_small(b->dtype, b->Mall.p, b->dmoff.as<int64_t>(), ts, ss, 0, b->Wt.p, b->Zs.p, B, np, st);
+  fill_cols(b->dtype, Y, b->nx, B, ldy, st);
+  batch_expand(b->dtype, b->U.p, ss, b->it_es.as<BatchItem>(), b->n_es, b->Zs.p, B, Y, ldy, st);
+  if (G) {
+    // backward: A_p = U_p^T g_p; dX = sum_p V_p M^T A_p; dtheta = sum_p A_p^T dM W_p
+    fill_zero(b->As.p, (size_t)std::max<int64_t>(ws, 1) * es, st);
+    batch_reduce(b->dtype, b->U.p, ss, b->it_rs.as<BatchItem>(), b->n_rs, G, ldg, B, b->As.p, st);
+    if (dX) {
+      batch_small(b->dtype, b->Mall.p, b->dmoff.as<int64_t>(), ss, ts, 1, b->As.p, b->Zt.p, B, np, st);
+      fill_cols(b->dtype, dX, b->ny, B, lddx, st);
+      batch_expand(b->dtype, b->V.p, ts, b->it_et.as<BatchItem>(), b->n_et, b->Zt.p, B, dX, lddx, st);
+    }
+    if (want_dth)
+      batch_dtheta(b->dtype, b->As.p, ss, b->dMall.p, b->ddmoff.as<int64_t>(), b->Wt.p, ts, B, dt, np,
+                   b->part.as<double>(), dtheta, st);
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tt_status tt_kernel_batch_build(const tt_kernel_params* p, const tt_kernel_pair* pairs, int num_pairs, const void* X,
+                                int64_t n_x, const void* Y, int64_t n_y, void* stream, tt_kernel_batch_t* out) {
+  if (!out) return fail(TTK_ERR_ARG, "out handle pointer is NULL");
+  if (!p || !pairs || num_pairs <= 0) return fail(TTK_ERR_ARG, "params, pairs or num_pairs invalid");
+  if (p->symmetric_psd) return fail(TTK_ERR_UNSUPPORTED, "batches of Global-1 pairs are not supported");
+  if (n_x < 0 || n_y < 0 || (n_x > 0 && !X) || (n_y > 0 && !Y)) return fail(TTK_ERR_ARG, "bad point arrays");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int d = p->d;
+  for (int i = 0; i < num_pairs; ++i) {
+    const tt_kernel_pair& pr = pairs[i];
+    if (pr.n_src < 0 || pr.n_tgt < 0 || pr.src_off < 0 || pr.tgt_off < 0 || pr.src_off + pr.n_src > n_x ||
+        pr.tgt_off + pr.n_tgt > n_y)
+      return fail(TTK_ERR_ARG, "pair %d: point range outside the arrays", i);
+    for (int j = 0; j < d && j < 3; ++j)
+      if (!(pr.box_s[2 * j] < pr.box_s[2 * j + 1]) || !(pr.box_t[2 * j] < pr.box_t[2 * j + 1]))
+        return fail(TTK_ERR_ARG, "pair %d: empty box along axis %d", i, j);
+  }
+  std::unique_ptr<tt_kernel_batch> b(new (std::nothrow) tt_kernel_batch());
+  if (!b) return fail(TTK_ERR_OOM, "batch allocation failed");
+  b->P = *p;
+  b->dtype = p->dtype;
+  b->es = p->dtype == TTK_FP32 ? 4 : 8;
+  b->d = d;
+  b->dt = p->d_theta;
+  b->D = 2 * d + p->d_theta;
+  b->nx = n_x;
+  b->ny = n_y;
+  b->pairs.assign(pairs, pairs + num_pairs);
+  // classes
+  std::vector<Frame> frames(num_pairs);
+  std::vector<std::vector<double>> keys;
+  std::vector<int> rep;   // representative pair of each class
+  b->cls.resize(num_pairs);
+  for (int i = 0; i < num_pairs; ++i) {
+    frames[i] = pair_frame(p->kind, d, pairs[i]);
+    int c = -1;
+    for (int q = 0; q < (int)keys.size(); ++q)
+      if (keys[q] == frames[i].key) { c = q; break; }
+    if (c < 0) {
+      c = (int)keys.size();
+      keys.push_back(frames[i].key);
+      rep.push_back(i);
+    }
+    b->cls[i] = c;
+  }
+  // one cross + rounding per class, in the class's canonical boxes, no points
+  for (int c = 0; c < (int)keys.size(); ++c) {
+    tt_kernel_params cp = *p;
+    const Frame& f = frames[rep[c]];
+    for (int j = 0; j < 2 * d; ++j) {
+      cp.box_s[j] = f.cbs[j];
+      cp.box_t[j] = f.cbt[j];
+    }
+    tt_kernel_t h = nullptr;
+    const tt_status s = tt_kernel_build_offline(&cp, nullptr, 0, nullptr, 0, stream, &h);
+    if (s < 0) return s;
+    if (s == TTK_WARN_NOT_CONVERGED) b->converged = false;
+    b->classes.emplace_back(h);
+    b->info.kernel_evals += h->info.kernel_evals;
+    b->info.t_cross_ms += h->info.t_cross_ms;
+    b->info.t_round_ms += h->info.t_round_ms;
+  }
+  // per-pair stages: the class cores read through the pair's own axes and orientation
+  b->stages.resize((size_t)num_pairs * 2 * d);
+  b->uoff.resize(num_pairs);
+  b->voff.resize(num_pairs);
+  int64_t uo = 0, vo = 0;
+  for (int i = 0; i < num_pairs; ++i) {
+    const tt_kernel* k = b->classes[b->cls[i]].get();
+    const Frame& f = frames[i];
+    const tt_kernel_pair& pr = pairs[i];
+    for (int side = 0; side < 2; ++side)
+      for (int si = 0; si < d; ++si) {
+        ChainStage cs = side == 0 ? k->src[si] : k->tgt[si];
+        const int canon = cs.coord;
+        const int ax = f.perm[canon];
+        const double* box = side == 0 ? pr.box_s : pr.box_t;
+        double lo = box[2 * ax], hi = box[2 * ax + 1];
+        if (f.sign[canon] < 0) std::swap(lo, hi);
+        cs.coord = ax;
+        cs.lo = lo;
+        cs.hi = hi;
+        b->stages[(size_t)i * 2 * d + side * d + si] = cs;
+      }
+    b->uoff[i] = uo;
+    b->voff[i] = vo;
+    uo += pr.n_src * k->rs;
+    vo += pr.n_tgt * k->rt;
+    b->info.factor_rows += pr.n_src + pr.n_tgt;
+  }
+  TTK_TRY(b->U.alloc((size_t)std::max<int64_t>(uo, 1) * b->es));
+  TTK_TRY(b->V.alloc((size_t)std::max<int64_t>(vo, 1) * b->es));
+  auto t0 = std::chrono::steady_clock::now();
+  TTK_TRY(batch_phase3_tuned(b.get(), X, Y, st));
+  TTK_HIP(hipStreamSynchronize(st));
+  b->info.t_factor_ms = ms_since(t0);
+  b->info.num_pairs = num_pairs;
+  b->info.num_classes = (int)b->classes.size();
+  b->info.factor_grid = b->factor_grid;
+  const tt_status s = b->converged ? TTK_OK : TTK_WARN_NOT_CONVERGED;
+  if (s != TTK_OK) set_error("the cross of at least one class stopped above tol");
+  *out = b.release();
+  return s;
+}
+
+tt_status tt_kernel_batch_configure(tt_kernel_batch_t b, int use_graph, int factor_grid, int reduce_rows) {
+  if (!b) return fail(TTK_ERR_ARG, "NULL batch");
+  if (reduce_rows < 0) return fail(TTK_ERR_ARG, "reduce_rows must be >= 0");
+  b->cfg_graph = use_graph ? 1 : 0;
+  b->cfg_factor_grid = factor_grid;
+  b->cfg_reduce_rows = reduce_rows;
+  b->prepB = -1;   // work lists are rebuilt on the next apply
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  b->key.clear();
+  return TTK_OK;
+}
+
+tt_status tt_kernel_batch_factor(tt_kernel_batch_t b, const void* X, const void* Y, void* stream) {
+  if (!b) return fail(TTK_ERR_ARG, "NULL batch");
+  if ((b->nx > 0 && !X) || (b->ny > 0 && !Y)) return fail(TTK_ERR_ARG, "NULL point array");
+  if (b->cfg_factor_grid != 0) b->factor_grid = b->cfg_factor_grid < 0 ? 0 : b->cfg_factor_grid;
+  b->info.factor_grid = b->factor_grid;
+  return batch_phase3(b, X, Y, b->factor_grid, static_cast<hipStream_t>(stream));
+}
+
+tt_status tt_kernel_batch_get_info(tt_kernel_batch_t b, tt_kernel_batch_info* info, int* class_of_pair,
+                                   int* class_ranks) {
+  if (!b) return fail(TTK_ERR_ARG, "NULL batch");
+  b->info.graph = b->cfg_graph;
+  if (info) *info = b->info;
+  if (class_of_pair)
+    for (size_t i = 0; i < b->cls.size(); ++i) class_of_pair[i] = b->cls[i];
+  if (class_ranks)
+    for (size_t c = 0; c < b->classes.size(); ++c)
+      for (int k = 0; k < 9; ++k)
+        class_ranks[c * 9 + k] = k <= b->D ? b->classes[c]->ranks[k] : 0;
+  return TTK_OK;
+}
+
+tt_status tt_kernel_batch_get_class(tt_kernel_batch_t b, int c, tt_kernel_t* h) {
+  if (!b || !h) return fail(TTK_ERR_ARG, "NULL argument");
+  if (c < 0 || c >= (int)b->classes.size()) return fail(TTK_ERR_ARG, "class %d out of range", c);
+  *h = b->classes[c].get();
+  return TTK_OK;
+}
+
+tt_status tt_kernel_batch_get_factors(tt_kernel_batch_t b, int pair, void* U_out, void* V_out, void* stream) {
+  if (!b) return fail(TTK_ERR_ARG, "NULL batch");
+  if (pair < 0 || pair >= (int)b->pairs.size()) return fail(TTK_ERR_ARG, "pair %d out of range", pair);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const tt_kernel* k = b->classes[b->cls[pair]].get();
+  const tt_kernel_pair& pr = b->pairs[pair];
+  if (U_out && pr.n_src > 0)
+    TTK_HIP(hipMemcpyAsync(U_out, b->U.as<char>() + b->uoff[pair] * b->es, (size_t)pr.n_src * k->rs * b->es,
+                           hipMemcpyDeviceToDevice, st));
+  if (V_out && pr.n_tgt > 0)
+    TTK_HIP(hipMemcpyAsync(V_out, b->V.as<char>() + b->voff[pair] * b->es, (size_t)pr.n_tgt * k->rt * b->es,
+                           hipMemcpyDeviceToDevice, st));
+  return TTK_OK;
+}
+
+tt_status tt_kernel_batch_apply(tt_kernel_batch_t b, const void* theta, int B, const void* X, int64_t ldx, void* Y,
+                                int64_t ldy, const void* G, int64_t ldg, void* dX, int64_t lddx, void* dtheta,
+                                void* stream) {
+  if (!b) return fail(TTK_ERR_ARG, "NULL batch");
+  if (B <= 0) return B == 0 ? TTK_OK : fail(TTK_ERR_ARG, "B < 0");
+  if (!X || !Y) return fail(TTK_ERR_ARG, "X or Y is NULL");
+  if (b->dt > 0 && !theta) return fail(TTK_ERR_ARG, "theta is NULL");
+  if (ldx < b->ny || ldy < b->nx) return fail(TTK_ERR_ARG, "leading dimension too small");
+  if (G && ldg < b->nx) return fail(TTK_ERR_ARG, "ldg too small");
+  if (G && dX && lddx < b->ny) return fail(TTK_ERR_ARG, "lddx too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TTK_TRY(batch_prepare(b, B, X, ldx, st));
+  if (!b->cfg_graph)
+    return batch_enqueue(b, theta, B, X, ldx, Y, ldy, G, ldg, dX, lddx, dtheta, st);
+  const std::vector<const void*> key = {theta, X, Y, G, dX, dtheta, reinterpret_cast<const void*>((intptr_t)B),
+                                        reinterpret_cast<const void*>((intptr_t)ldx),
+                                        reinterpret_cast<const void*>((intptr_t)ldy),
+                                        reinterpret_cast<const void*>((intptr_t)ldg),
+                                        reinterpret_cast<const void*>((intptr_t)lddx)};
+  if (!b->exec || b->key != key) {
+    if (b->exec) {
+      TTK_HIP(hipGraphExecDestroy(b->exec));
+      b->exec = nullptr;
+    }
+    if (!b->cap) TTK_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    TTK_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+    const tt_status s = batch_enqueue(b, theta, B, X, ldx, Y, ldy, G, ldg, dX, lddx, dtheta, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (s < 0) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return fail(TTK_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      b->exec = nullptr;
+      return fail(TTK_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    }
+    b->key = key;
+  }
+  TTK_HIP(hipGraphLaunch(b->exec, st));
+  return TTK_OK;
+}
+
+tt_status tt_kernel_batch_destroy(tt_kernel_batch_t b) {
+  delete b;
   return TTK_OK;
 }
 

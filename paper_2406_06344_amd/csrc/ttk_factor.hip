@@ -30,7 +30,7 @@ struct StageArgs {
 };
 
 template <class T, int TP>
-__global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P, int64_t npts, int d, T* out,
+__global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P, int64_t ldp, int64_t npts, T* out,
                                                        int ldo) {
   extern __shared__ unsigned char smem_raw[];
   T* sTk = reinterpret_cast<T*>(smem_raw);              // TP x MAXN
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P,
     // Chebyshev values of this stage's coordinate
     if (tid < TP) {
       const int64_t p = p0 + tid;
-      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * npts + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
+      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * ldp + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
       const double t = (2.0 * x - (sa.lo[st] + sa.hi[st])) / (sa.lo[st] - sa.hi[st]);
       double tkm = 1.0, tk = t;
       sTk[tid * MAXN + 0] = (T)1;
@@ -118,15 +118,15 @@ constexpr int MF_KS = 64;    // rows of G^{2} per LDS slab
 constexpr int MF_GLD = 68;   // slab row stride (bank spread across the 4 rows a K-step reads)
 constexpr int MF_TLD = 33;   // row stride of the Chebyshev table
 
-__global__ void __launch_bounds__(256) k_factor_mfma(StageArgs sa, const float* P, int64_t npts, float* out, int ldo,
-                                                     int sld) {
-  extern __shared__ float smf[];
+// One tile of MF_P points of one chain.  P: coordinate j of point q at
+// P[j * ldp + q]; points p0 .. p0 + MF_P - 1 of npts; rows written to out.
+__device__ void mfma_tile(const StageArgs& sa, const float* P, int64_t ldp, int64_t npts, int64_t p0, float* out,
+                          int ldo, int sld, float* smf) {
   float* sTk = smf;                                  // MF_P x MF_TLD
   float* s0 = sTk + MF_P * MF_TLD;                    // MF_P x sld
   float* s1 = s0 + MF_P * sld;                        // MF_P x sld
   float* Gs = s1 + MF_P * sld;                        // MF_KS x MF_GLD
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t p0 = (int64_t)blockIdx.x * MF_P;
   const int pl = 16 * w + (lane & 15);                // this lane's point for the A operand
   const int kq = lane >> 4;                           // this lane's row within a K-step
   float* sin = s0;
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_factor_mfma(StageArgs sa, const float* 
     const float* G = static_cast<const float*>(sa.G2[st]);
     if (tid < MF_P) {
       const int64_t p = p0 + tid;
-      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * npts + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
+      const double x = (p < npts) ? (double)P[(int64_t)sa.coord[st] * ldp + p] : 0.5 * (sa.lo[st] + sa.hi[st]);
       const double t = (2.0 * x - (sa.lo[st] + sa.hi[st])) / (sa.lo[st] - sa.hi[st]);
       double tkm = 1.0, tk = t;
       sTk[tid * MF_TLD + 0] = 1.0f;
@@ -198,58 +198,114 @@ __global__ void __launch_bounds__(256) k_factor_mfma(StageArgs sa, const float* 
     const int64_t p = p0 + q;
     if (p < npts) out[p * ldo + b] = sin[q * sld + b];
   }
+  __syncthreads();                                     // LDS is reused by the next tile
 }
 
-tt_status launch_factor_mfma(const StageArgs& sa, const void* P, int64_t npts, void* out, int ldo, hipStream_t st,
-                             bool* launched) {
+__global__ void __launch_bounds__(256) k_factor_mfma(StageArgs sa, const float* P, int64_t npts, float* out, int ldo,
+                                                     int sld) {
+  extern __shared__ float smf[];
+  mfma_tile(sa, P, npts, npts, (int64_t)blockIdx.x * MF_P, out, ldo, sld, smf);
+}
+
+// Phase 3 of many chains (one per box pair and side) in one persistent launch:
+// tile t of the concatenated work list belongs to job j with
+// prefix[j] <= t < prefix[j + 1]; workgroups stride over the tiles.
+struct FacJob {
+  StageArgs sa;
+  const float* P;
+  int64_t ldp, npts;
+  float* out;
+  int ldo;
+};
+
+__global__ void __launch_bounds__(256) k_factor_mfma_batch(const FacJob* jobs, const int64_t* prefix, int njobs,
+                                                           int sld) {
+  extern __shared__ float smf[];
+  __shared__ FacJob job;
+  __shared__ int cur;
+  const int64_t total = prefix[njobs];
+  if (threadIdx.x == 0) cur = -1;
+  __syncthreads();
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    // job of tile t: the last j with prefix[j] <= t
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    if (lo != cur) {
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        job = jobs[lo];
+        cur = lo;
+      }
+      __syncthreads();
+    }
+    mfma_tile(job.sa, job.P, job.ldp, job.npts, (t - prefix[lo]) * MF_P, job.out, job.ldo, sld, smf);
+  }
+}
+
+size_t mfma_lds_bytes(int rmax) {
+  const int sld = rmax + 1;
+  return sizeof(float) * ((size_t)MF_P * MF_TLD + 2 * (size_t)MF_P * sld + (size_t)MF_KS * MF_GLD);
+}
+
+int lds_limit() {
+  static int lim = -1;
+  if (lim < 0) {
+    int dev = 0, v = 64 * 1024;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 64 * 1024;
+    (void)hipGetLastError();
+    lim = v;
+  }
+  return lim;
+}
+
+tt_status launch_factor_mfma(const StageArgs& sa, const void* P, int64_t ldp, int64_t npts, void* out, int ldo,
+                             hipStream_t st, bool* launched) {
   *launched = false;
-  int dev = 0, lds = 64 * 1024;
-  TTK_HIP(hipGetDevice(&dev));
-  TTK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const int sld = sa.rmax + 1;
-  const size_t sh = sizeof(float) * ((size_t)MF_P * MF_TLD + 2 * (size_t)MF_P * sld + (size_t)MF_KS * MF_GLD);
-  if (sh > (size_t)lds) return TTK_OK;
+  const size_t sh = mfma_lds_bytes(sa.rmax);
+  if (sh > (size_t)lds_limit()) return TTK_OK;
   if (sh > 64 * 1024)
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_mfma),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
-  hipLaunchKernelGGL(k_factor_mfma, dim3((unsigned)((npts + MF_P - 1) / MF_P)), dim3(256), sh, st, sa,
-                     static_cast<const float*>(P), npts, static_cast<float*>(out), ldo, sld);
-  TTK_HIP(hipGetLastError());
-  *launched = true;
+  if (ldp == npts) {
+    hipLaunchKernelGGL(k_factor_mfma, dim3((unsigned)((npts + MF_P - 1) / MF_P)), dim3(256), sh, st, sa,
+                       static_cast<const float*>(P), npts, static_cast<float*>(out), ldo, sa.rmax + 1);
+    TTK_HIP(hipGetLastError());
+    *launched = true;
+  }
   return TTK_OK;
 }
 
 template <class T, int TP>
-tt_status launch_tile(const StageArgs& sa, const void* P, int64_t npts, int d, void* out, int ldo, size_t sh,
+tt_status launch_tile(const StageArgs& sa, const void* P, int64_t ldp, int64_t npts, void* out, int ldo, size_t sh,
                       hipStream_t st) {
   if (sh > 64 * 1024)
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor<T, TP>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   hipLaunchKernelGGL((k_factor<T, TP>), dim3((unsigned)((npts + TP - 1) / TP)), dim3(FC_THREADS), sh, st, sa,
-                     static_cast<const T*>(P), npts, d, static_cast<T*>(out), ldo);
+                     static_cast<const T*>(P), ldp, npts, static_cast<T*>(out), ldo);
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
 
 template <class T>
-tt_status launch_factor(const StageArgs& sa, const void* P, int64_t npts, int d, void* out, int ldo,
+tt_status launch_factor(const StageArgs& sa, const void* P, int64_t ldp, int64_t npts, void* out, int ldo,
                         hipStream_t st) {
-  int dev = 0, lds = 64 * 1024;
-  TTK_HIP(hipGetDevice(&dev));
-  TTK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const int lds = lds_limit();
   const size_t per_tp = (size_t)(MAXN + 2 * sa.rmax) * sizeof(T);
   // the largest point tile whose LDS footprint fits one workgroup
-  if (per_tp * 64 <= (size_t)lds) return launch_tile<T, 64>(sa, P, npts, d, out, ldo, per_tp * 64, st);
-  if (per_tp * 32 <= (size_t)lds) return launch_tile<T, 32>(sa, P, npts, d, out, ldo, per_tp * 32, st);
-  if (per_tp * 16 <= (size_t)lds) return launch_tile<T, 16>(sa, P, npts, d, out, ldo, per_tp * 16, st);
+  if (per_tp * 64 <= (size_t)lds) return launch_tile<T, 64>(sa, P, ldp, npts, out, ldo, per_tp * 64, st);
+  if (per_tp * 32 <= (size_t)lds) return launch_tile<T, 32>(sa, P, ldp, npts, out, ldo, per_tp * 32, st);
+  if (per_tp * 16 <= (size_t)lds) return launch_tile<T, 16>(sa, P, ldp, npts, out, ldo, per_tp * 16, st);
   return fail(TTK_ERR_UNSUPPORTED, "Phase 3 tile for rank %d does not fit %d bytes of LDS", sa.rmax, lds);
 }
 
-}  // namespace
-
-tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, const void* P_soa, int64_t npts,
-                          void* out, int ldo, hipStream_t st) {
-  if (npts <= 0) return TTK_OK;
+StageArgs make_stage_args(const ChainStage* stages, int nstages) {
   StageArgs sa{};
   sa.nst = nstages;
   sa.rmax = 1;
@@ -263,16 +319,77 @@ tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, cons
     sa.hi[i] = stages[i].hi;
     sa.rmax = std::max(sa.rmax, std::max(stages[i].r_in, stages[i].r_out));
   }
-  int d = 0;
-  for (int i = 0; i < nstages; ++i) d = std::max(d, stages[i].coord + 1);
+  return sa;
+}
+
+tt_status contract_one(int dtype, const StageArgs& sa, const void* P, int64_t ldp, int64_t npts, void* out, int ldo,
+                       hipStream_t st) {
+  if (npts <= 0) return TTK_OK;
   if (dtype == TTK_FP32) {
     // matrix cores when the LDS tiles fit the workgroup, register-tiled VALU otherwise
     bool launched = false;
-    TTK_TRY(launch_factor_mfma(sa, P_soa, npts, out, ldo, st, &launched));
+    TTK_TRY(launch_factor_mfma(sa, P, ldp, npts, out, ldo, st, &launched));
     if (launched) return TTK_OK;
-    return launch_factor<float>(sa, P_soa, npts, d, out, ldo, st);
+    return launch_factor<float>(sa, P, ldp, npts, out, ldo, st);
   }
-  return launch_factor<double>(sa, P_soa, npts, d, out, ldo, st);
+  return launch_factor<double>(sa, P, ldp, npts, out, ldo, st);
+}
+
+}  // namespace
+
+tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, const void* P_soa, int64_t npts,
+                          void* out, int ldo, hipStream_t st) {
+  return contract_one(dtype, make_stage_args(stages, nstages), P_soa, npts, npts, out, ldo, st);
+}
+
+tt_status factor_contract_batch(int dtype, const FactorJob* jobs, int njobs, int grid, hipStream_t st,
+                                FactorBatchPlan* plan) {
+  if (njobs <= 0) return TTK_OK;
+  int rmax = 1;
+  for (int j = 0; j < njobs; ++j) {
+    const StageArgs sa = make_stage_args(jobs[j].stages, jobs[j].nstages);
+    rmax = std::max(rmax, sa.rmax);
+  }
+  const size_t sh = mfma_lds_bytes(rmax);
+  if (dtype != TTK_FP32 || sh > (size_t)lds_limit()) {
+    // one launch per job (double precision, or ranks beyond the MFMA tile)
+    for (int j = 0; j < njobs; ++j)
+      TTK_TRY(contract_one(dtype, make_stage_args(jobs[j].stages, jobs[j].nstages), jobs[j].P, jobs[j].ldp,
+                           jobs[j].npts, jobs[j].out, jobs[j].ldo, st));
+    plan->persistent = false;
+    return TTK_OK;
+  }
+  // the work list: job descriptors and the prefix sum of their tile counts
+  if (plan->njobs != njobs) {
+    std::vector<FacJob> hj(njobs);
+    std::vector<int64_t> pre(njobs + 1, 0);
+    for (int j = 0; j < njobs; ++j) {
+      hj[j].sa = make_stage_args(jobs[j].stages, jobs[j].nstages);
+      hj[j].P = static_cast<const float*>(jobs[j].P);
+      hj[j].ldp = jobs[j].ldp;
+      hj[j].npts = jobs[j].npts;
+      hj[j].out = static_cast<float*>(jobs[j].out);
+      hj[j].ldo = jobs[j].ldo;
+      pre[j + 1] = pre[j] + (jobs[j].npts + MF_P - 1) / MF_P;
+    }
+    TTK_TRY(plan->desc.alloc(sizeof(FacJob) * njobs));
+    TTK_TRY(plan->prefix.alloc(sizeof(int64_t) * (njobs + 1)));
+    TTK_HIP(hipMemcpyAsync(plan->desc.p, hj.data(), sizeof(FacJob) * njobs, hipMemcpyHostToDevice, st));
+    TTK_HIP(hipMemcpyAsync(plan->prefix.p, pre.data(), sizeof(int64_t) * (njobs + 1), hipMemcpyHostToDevice, st));
+    TTK_HIP(hipStreamSynchronize(st));   // host staging vectors go out of scope
+    plan->njobs = njobs;
+    plan->tiles = pre[njobs];
+  }
+  if (plan->tiles == 0) return TTK_OK;
+  if (sh > 64 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_factor_mfma_batch),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
+  const int64_t g = grid > 0 ? std::min<int64_t>(grid, plan->tiles) : plan->tiles;
+  hipLaunchKernelGGL(k_factor_mfma_batch, dim3((unsigned)g), dim3(256), sh, st, plan->desc.as<const FacJob>(),
+                     plan->prefix.as<const int64_t>(), njobs, rmax + 1);
+  TTK_HIP(hipGetLastError());
+  plan->persistent = true;
+  return TTK_OK;
 }
 
 }  // namespace ttk

@@ -178,6 +178,27 @@ struct ChainStage {
 };
 tt_status factor_contract(int dtype, const ChainStage* stages, int nstages, const void* P_soa,
                           int64_t npts, void* out, int ldo, hipStream_t st);
+// Phase 3 of many chains.  Job j: points with coordinate c of point q at
+// P[c * ldp + q], q < npts, rows written to out (row-major, ldo).
+struct FactorJob {
+  const ChainStage* stages;
+  int nstages;
+  const void* P;
+  int64_t ldp, npts;
+  void* out;
+  int ldo;
+};
+// Device copy of a job list (kept between calls with the same jobs).
+struct FactorBatchPlan {
+  DBuf desc, prefix;
+  int njobs = -1;
+  int64_t tiles = 0;
+  bool persistent = false;
+};
+// FP32: one persistent launch of `grid` workgroups (0 = one per 64-point tile)
+// striding over the tiles of all jobs; otherwise one launch per job.
+tt_status factor_contract_batch(int dtype, const FactorJob* jobs, int njobs, int grid, hipStream_t st,
+                                FactorBatchPlan* plan);
 
 // ----------------------------------------------------------- online / apply
 struct ParamCore {
@@ -201,6 +222,30 @@ void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, con
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,
                       int B, int dt, void* dtheta, hipStream_t st);  // dtheta[b,j] = a_b^T dM_bj w_b
 void fill_zero(void* p, size_t bytes, hipStream_t st);
+// ------------------------------------------ interaction-list batch apply
+// One side (sources or targets) of one pair: its factor block F_p (n x r
+// row-major at element offset foff), its first row in the N x B vectors and
+// its r x B block of W / Z / A (column-major, element offset woff).
+struct BatchSide {
+  int64_t foff, n, roff, woff;
+  int r, pad;
+};
+// Work item of the tall launches: rows row0 .. row0 + nrows - 1 of side
+// `side`, rank columns r0 .. r0 + 63 (reduce only), thetas b0 .. b0 + 63.
+struct BatchItem {
+  int64_t row0;
+  int side, nrows, r0, b0;
+};
+void batch_reduce(int dtype, const void* F, const BatchSide* sides, const BatchItem* items, int64_t nitems,
+                  const void* X, int64_t ldx, int B, void* W, hipStream_t st);      // W_p += F_p^T X_p
+void batch_expand(int dtype, const void* F, const BatchSide* sides, const BatchItem* items, int64_t nitems,
+                  const void* Z, int B, void* Y, int64_t ldy, hipStream_t st);      // Y_p += F_p Z_p
+void batch_small(int dtype, const void* M, const int64_t* moff, const BatchSide* in_s, const BatchSide* out_s,
+                 int trans, const void* Win, void* Zout, int B, int npairs, hipStream_t st);
+void batch_dtheta(int dtype, const void* A, const BatchSide* s_side, const void* dM, const int64_t* dmoff,
+                  const void* W, const BatchSide* t_side, int B, int dt, int npairs, double* part, void* dtheta,
+                  hipStream_t st);
+void fill_cols(int dtype, void* Y, int64_t rows, int B, int64_t ldy, hipStream_t st);
 // ----------------------------------------------- Global-1 (Algorithm 4)
 // Thin QR of A = [U V] (N x k, k = rs + rt; U, V row-major in dtype) by
 // blocked Householder QR in double precision.  Q: device, dtype, N x k

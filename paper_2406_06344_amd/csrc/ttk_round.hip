@@ -81,24 +81,33 @@ struct Cores {
   std::vector<int> n;
 };
 
-// thin QR of (G_i^{1})^T, G_i <- Q^T, G_{i-1}^{2} <- G_{i-1}^{2} R^T
+// thin QR of (G_i^{1})^T, G_i <- Q^T, G_{i-1}^{2} <- G_{i-1}^{2} R^T.  When
+// (G_i^{1})^T (n r1 x r0) is wide, the rank drops to n r1: the matrix is
+// padded with zero rows to r0 x r0, whose Householder QR leaves the padding
+// untouched (every reflector vanishes there), so the leading n r1 x n r1
+// block of Q and the leading n r1 rows of R are the thin factors.
 tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipStream_t st) {
   const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
   const int m = n * r1;
-  TTK_TRY(A.alloc((size_t)m * r0 * sizeof(double)));
+  const int ma = std::max(m, r0);   // rows of the (padded) QR input
+  const int rp = std::min(m, r0);   // new rank r_i
+  TTK_TRY(A.alloc((size_t)ma * r0 * sizeof(double)));
   TTK_TRY(R.alloc((size_t)r0 * r0 * sizeof(double)));
-  TTK_TRY(tau.alloc(qr_blocked_work(m, r0) * sizeof(double)));
+  TTK_TRY(tau.alloc(qr_blocked_work(ma, r0) * sizeof(double)));
   double* G = c.g[i].as<double>();
+  if (ma > m) fill_zero(A.p, (size_t)ma * r0 * sizeof(double), st);
   hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, G, r0, m, r0, A.as<double>(),
-                     m);
-  TTK_TRY(qr_blocked(A.as<double>(), m, r0, m, R.as<double>(), r0, tau.as<double>(), st));
-  hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, A.as<double>(), m, r0, m, G,
-                     r0);
+                     ma);
+  TTK_TRY(qr_blocked(A.as<double>(), ma, r0, ma, R.as<double>(), r0, tau.as<double>(), st));
+  // G_i^{1} (rp x m) = Q[:m, :rp]^T
+  hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)rp * m)), dim3(256), 0, st, A.as<double>(), m, rp, ma, G, rp);
   const int q0 = c.r[i - 1], qn = c.n[i - 1];
-  TTK_TRY(T.alloc((size_t)q0 * qn * r0 * sizeof(double)));
-  gemm64(0, 1, q0 * qn, r0, r0, 1.0, c.g[i - 1].as<double>(), q0 * qn, R.as<double>(), r0, 0.0, T.as<double>(),
+  TTK_TRY(T.alloc((size_t)q0 * qn * rp * sizeof(double)));
+  // G_{i-1}^{2} (q0 qn x r0) R[:rp, :]^T
+  gemm64(0, 1, q0 * qn, rp, r0, 1.0, c.g[i - 1].as<double>(), q0 * qn, R.as<double>(), r0, 0.0, T.as<double>(),
          q0 * qn, st);
-  TTK_HIP(hipMemcpyAsync(c.g[i - 1].p, T.p, (size_t)q0 * qn * r0 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  TTK_HIP(hipMemcpyAsync(c.g[i - 1].p, T.p, (size_t)q0 * qn * rp * sizeof(double), hipMemcpyDeviceToDevice, st));
+  c.r[i] = rp;
   TTK_HIP(hipStreamSynchronize(st));   // A, R, T are resized by the next call
   return TTK_OK;
 }
@@ -131,13 +140,17 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
   for (int i = 0; i < D - 1; ++i) {
     const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
     const int m = r0 * n;
-    TTK_TRY(A.alloc((size_t)m * r1 * sizeof(double)));
+    // a wide G_i^{2} (after truncation of r_i) is padded with zero rows, as in orth_right
+    const int ma = std::max(m, r1);
+    TTK_TRY(A.alloc((size_t)ma * r1 * sizeof(double)));
     TTK_TRY(R.alloc((size_t)r1 * r1 * sizeof(double)));
-    TTK_TRY(tau.alloc(qr_blocked_work(m, r1) * sizeof(double)));
+    TTK_TRY(tau.alloc(qr_blocked_work(ma, r1) * sizeof(double)));
     TTK_TRY(V.alloc((size_t)r1 * r1 * sizeof(double)));
     TTK_TRY(sig.alloc(((size_t)r1 * r1 + 3 * (size_t)r1 + 64) * sizeof(double)));
-    TTK_HIP(hipMemcpyAsync(A.p, c.g[i].p, (size_t)m * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    TTK_TRY(qr_blocked(A.as<double>(), m, r1, m, R.as<double>(), r1, tau.as<double>(), st));
+    if (ma > m) fill_zero(A.p, (size_t)ma * r1 * sizeof(double), st);
+    TTK_HIP(hipMemcpy2DAsync(A.p, (size_t)ma * sizeof(double), c.g[i].p, (size_t)m * sizeof(double),
+                             (size_t)m * sizeof(double), (size_t)r1, hipMemcpyDeviceToDevice, st));
+    TTK_TRY(qr_blocked(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
     jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
     hs.resize(r1);
     TTK_HIP(hipMemcpyAsync(hs.data(), sig.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -149,8 +162,9 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
       for (int q = 1; q <= r1; ++q)
         if (std::sqrt(tail[q]) <= delta) { rp = q; break; }
     }
-    // G_i^{2} <- Q U_R[:, :rp]
-    gemm64(0, 0, m, rp, r1, 1.0, A.as<double>(), m, R.as<double>(), r1, 0.0, c.g[i].as<double>(), m, st);
+    rp = std::min(rp, m);   // a wide unfolding has at most m singular values
+    // G_i^{2} <- Q[:m, :] U_R[:, :rp]
+    gemm64(0, 0, m, rp, r1, 1.0, A.as<double>(), ma, R.as<double>(), r1, 0.0, c.g[i].as<double>(), m, st);
     // G_{i+1}^{1} <- (Sigma V^T)[:rp, :] G_{i+1}^{1}
     const int n2 = c.n[i + 1], r2 = c.r[i + 2];
     TTK_TRY(W.alloc((size_t)rp * r1 * sizeof(double)));

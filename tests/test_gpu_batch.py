@@ -1,0 +1,203 @@
+"""GPU parity of the interaction-list batch (tt_kernel_batch_*) against the
+FP64 oracle in oracle/pairs.py on the same seeded pairs and points.
+
+Checked: the class assignment and class ranks, every pair's factor rows,
+the batched apply, dX and dtheta (float64: <= 1e-10, float32: <= 2e-5
+relative Frobenius), graph replays against direct launches, the autotuned
+launch shapes against fixed ones, ragged and empty pairs."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import dense as odense
+from oracle import pairs as opairs
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return odense.rel_fro(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
+
+
+def make_pairs(d, geo, h, counts, seed):
+    """Pairs of cells c -> c + o of side h with (n_src, n_tgt) points each."""
+    rng = np.random.default_rng(seed)
+    ps, xs, ys = [], [], []
+    so = to = 0
+    for (c, o), (ns, nt) in zip(geo, counts):
+        c = np.asarray(c)
+        t = c + np.asarray(o)
+        p = {"box_s": [[c[i] * h, (c[i] + 1) * h] for i in range(d)],
+             "box_t": [[t[i] * h, (t[i] + 1) * h] for i in range(d)],
+             "src_off": so, "n_src": ns, "tgt_off": to, "n_tgt": nt}
+        bs, bt = np.array(p["box_s"]), np.array(p["box_t"])
+        x = rng.uniform(bs[:, 0], bs[:, 1], (ns, d)).astype(np.float32).astype(np.float64)
+        y = rng.uniform(bt[:, 0], bt[:, 1], (nt, d)).astype(np.float32).astype(np.float64)
+        xs.append(np.clip(x, bs[:, 0], bs[:, 1]))
+        ys.append(np.clip(y, bt[:, 0], bt[:, 1]))
+        so += ns
+        to += nt
+        ps.append(p)
+    return ps, np.vstack(xs), np.vstack(ys)
+
+
+CASES = {
+    # d, kind, box_theta, n, tol, geometry, counts, h
+    "d2": (2, "matern32", [[0.5, 2.0]], 8, 1e-7,
+           [([0, 0], [2, 0]), ([3, 1], [-2, 0]), ([1, 1], [0, 2]), ([0, 3], [2, -1]), ([2, 2], [-1, -2]),
+            ([1, 3], [0, -3]), ([2, 0], [-2, 0])],
+           [(130, 70), (65, 1), (1, 200), (257, 63), (40, 0), (33, 47), (0, 9)], 0.25),
+    "d3": (3, "matern32", [[0.5, 2.0]], 6, 1e-6,
+           [([0, 0, 0], [2, 1, 0]), ([3, 3, 1], [0, -1, -2]), ([1, 2, 3], [-2, 0, 0])],
+           [(90, 70), (64, 130), (17, 5)], 0.25),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(name):
+    d, kind, bth, n, tol, geo, counts, h = CASES[name]
+    ps, X, Y = make_pairs(d, geo, h, counts, seed=11)
+    ob = opairs.offline(kind, d, bth, n, n, ps, X, Y, tol)
+    rng = np.random.default_rng(12)
+    B = 5
+    th = rng.uniform(np.array(bth)[:, 0], np.array(bth)[:, 1], (B, len(bth))).astype(np.float32).astype(np.float64)
+    xv = rng.standard_normal((Y.shape[0], B)).astype(np.float32).astype(np.float64)
+    gv = rng.standard_normal((X.shape[0], B)).astype(np.float32).astype(np.float64)
+    Hs, dHs = opairs.online(ob, th)
+    yv = opairs.apply(ob, ps, Hs, xv, X.shape[0])
+    dX, dth = opairs.backward(ob, ps, Hs, dHs, xv, gv, Y.shape[0])
+    return ps, X, Y, ob, th, xv, gv, yv, dX, dth
+
+
+def gpu_case(name, dtype):
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    d, kind, bth, n, tol, geo, counts, h = CASES[name]
+    ps, X, Y, ob, *_ = oracle_case(name)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    bt = pkg.TTBatch.build(ps, torch.tensor(X), torch.tensor(Y), kind, d, bth, n_spatial=n, n_param=n, tol=tol,
+                           dtype=tdt)
+    return bt, tdt
+
+
+@pytest.mark.parametrize("name,dtype", [("d2", "f64"), ("d2", "f32"), ("d3", "f32")])
+def test_batch_matches_oracle(name, dtype):
+    torch = _torch()
+    say(f"[batch] {name} {dtype}")
+    ps, X, Y, ob, th, xv, gv, yv, dXo, dtho = oracle_case(name)
+    bt, tdt = gpu_case(name, dtype)
+    inf = bt.info()
+    say(f"  classes {inf['num_classes']} grid {inf['factor_grid']} ranks {inf['class_ranks']}")
+    assert inf["class_of_pair"] == ob["class"]
+    assert inf["num_classes"] == len(ob["builds"])
+    for c, (P, out) in enumerate(ob["builds"]):
+        assert inf["class_ranks"][c] == out["ranks"]
+    tolr = 1e-10 if dtype == "f64" else 2e-5
+    # factor rows of every pair: the rounding's singular vectors for near-equal
+    # singular values are fixed only up to O(u / gap), so U_p and V_p alone get a
+    # looser bar; the gauge-invariant products below get the full one
+    for i, p in enumerate(ps):
+        U, V = bt.factors(i)
+        if p["n_src"]:
+            e = rel(U.double().cpu().numpy(), ob["S"][i])
+            assert e <= max(tolr, 1e-7), (i, e)
+        if p["n_tgt"]:
+            e = rel(V.double().cpu().numpy(), ob["T"][i])
+            assert e <= max(tolr, 1e-7), (i, e)
+    # apply + backward (graph path: first call captures, later calls replay)
+    tht = torch.tensor(th, dtype=tdt, device="cuda")
+    xt = torch.tensor(xv.T.copy(), dtype=tdt, device="cuda")
+    gt = torch.tensor(gv.T.copy(), dtype=tdt, device="cuda")
+    Yg, dXg, dthg = bt.apply(tht, xt, G=gt)
+    ey, ex, et = rel(Yg.double().cpu().numpy().T, yv), rel(dXg.double().cpu().numpy().T, dXo), \
+        rel(dthg.double().cpu().numpy(), dtho)
+    say(f"  rel err y {ey:.2e} dX {ex:.2e} dtheta {et:.2e}")
+    assert ey <= tolr and ex <= tolr and et <= tolr
+
+
+def test_batch_graph_replays_match_direct_launches():
+    torch = _torch()
+    ps, X, Y, ob, th, xv, gv, yv, dXo, dtho = oracle_case("d2")
+    bt, tdt = gpu_case("d2", "f32")
+    tht = torch.tensor(th, dtype=tdt, device="cuda")
+    xt = torch.tensor(xv.T.copy(), dtype=tdt, device="cuda")
+    gt = torch.tensor(gv.T.copy(), dtype=tdt, device="cuda")
+    B = xt.shape[0]
+    out = (torch.empty((B, bt.n_x), dtype=tdt, device="cuda"), torch.empty((B, bt.n_y), dtype=tdt, device="cuda"),
+           torch.empty((B, 1), dtype=tdt, device="cuda"))
+    bt.configure(use_graph=False)
+    ref = [t.clone() for t in bt.apply(tht, xt, G=gt)]
+    bt.configure(use_graph=True)
+    for rep in range(4):
+        for t in out:
+            t.fill_(7.0)                       # stale values must be overwritten by every replay
+        torch.cuda.synchronize()
+        got = bt.apply(tht, xt, G=gt, out=out)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            # the reductions use atomics, so replays may differ in the last bits
+            assert rel(a.double().cpu().numpy(), b.double().cpu().numpy()) <= 1e-6, rep
+        _ = (xt * 2.0).sum().item()            # eager work between replays
+    assert bt.info()["graph"]
+
+
+def test_batch_autotuned_shapes_match_fixed_shapes():
+    torch = _torch()
+    ps, X, Y, ob, th, xv, gv, yv, dXo, dtho = oracle_case("d2")
+    bt, tdt = gpu_case("d2", "f32")
+    U0 = [bt.factors(i)[0].clone() for i in range(len(ps))]
+    for grid in (-1, 1, 7, 512):
+        bt.configure(use_graph=False, factor_grid=grid, reduce_rows=64 if grid == 7 else 0)
+        bt.refactor(torch.tensor(X), torch.tensor(Y))
+        for i in range(len(ps)):
+            assert torch.equal(bt.factors(i)[0], U0[i]), (grid, i)   # same arithmetic per point
+        tht = torch.tensor(th, dtype=tdt, device="cuda")
+        xt = torch.tensor(xv.T.copy(), dtype=tdt, device="cuda")
+        Yg = bt.apply(tht, xt)
+        assert rel(Yg.double().cpu().numpy().T, yv) <= 2e-5
+
+
+def test_batch_test_kernel_has_one_class_per_pair():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    d = 2
+    geo = [([0, 0], [2, 0]), ([3, 1], [-2, 0])]
+    ps, X, Y = make_pairs(d, geo, 0.25, [(20, 30), (25, 15)], seed=3)
+    bt = pkg.TTBatch.build(ps, torch.tensor(X), torch.tensor(Y), "poly", d, [[0.5, 1.5]], n_spatial=6,
+                           n_param=6, tol=1e-10, dtype=torch.float64)
+    assert bt.info()["num_classes"] == 2
+    ob = opairs.offline("poly", d, [[0.5, 1.5]], 6, 6, ps, X, Y, 1e-10)
+    th = np.array([[0.9]])
+    xv = np.random.default_rng(4).standard_normal((Y.shape[0], 1))
+    Hs, _ = opairs.online(ob, th)
+    yv = opairs.apply(ob, ps, Hs, xv, X.shape[0])
+    Yg = bt.apply(torch.tensor(th, device="cuda"), torch.tensor(xv.T.copy(), device="cuda"))
+    assert rel(Yg.cpu().numpy().T, yv) <= 1e-10
+
+
+def test_batch_argument_errors():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    from paper_2406_06344_amd._lib import TTKError
+    ps, X, Y = make_pairs(2, [([0, 0], [2, 0])], 0.25, [(10, 10)], seed=1)
+    bad = [dict(ps[0], n_src=11)]              # past the end of X
+    with pytest.raises(TTKError, match="ERR_ARG"):
+        pkg.TTBatch.build(bad, torch.tensor(X), torch.tensor(Y), "matern32", 2, [[0.5, 2.0]], n_spatial=6,
+                          tol=1e-6, dtype=torch.float64)
+    with pytest.raises(TTKError, match="ERR_ARG"):
+        pkg.TTBatch.build([], torch.tensor(X), torch.tensor(Y), "matern32", 2, [[0.5, 2.0]], n_spatial=6,
+                          tol=1e-6, dtype=torch.float64)
