@@ -32,6 +32,10 @@ import synth  # noqa: E402
 
 METRIC = "offline U/V rows/s + batched apply+grad GB/s vs plain apply, at ≤1e-5 rel err"
 HBM_PEAK_GBPS = 8000.0
+# HBM bytes of the roofline kernel from rocprofv3 counter runs (FETCH_SIZE and
+# WRITE_SIZE, separate runs) scaled by the same counters on a plain copy of
+# known size; None until taken for the current kernel.
+TRAFFIC = 29000379   # bytes per launch, k_factor_mfma on matern32_d3 (see profiles/)
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -81,6 +85,191 @@ def cpu_baseline(w, X, Y, thetas, n_pts):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def time_wall(fn, reps, torch):
+    """Average wall time (ms) of fn() over reps calls, device synchronised on both sides."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / reps
+
+
+def base_result(w, args, value, unit, ms_per_step, B, extra_cfg=None):
+    cfg = {"workload": w.name, "kernel": w.kind, "d": w.d, "d_theta": w.d_theta, "N_s": w.n_src, "N_t": w.n_tgt,
+           "n_spatial": w.n_spatial, "n_param": w.n_param, "tol": w.tol, "n_theta": B,
+           "parallelism": "single GPU"}
+    cfg.update(extra_cfg or {})
+    return {"metric": METRIC, "value": round(value, 1), "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if w.fp64 else "f32", "data": "synthetic",
+            "config": cfg}
+
+
+def bench_global(args, torch, pkg):
+    """Symmetric PSD variant (Algorithm 4, Global-1): X = Y, N points in the unit cube."""
+    w = synth.WORKLOADS["matern_global"]
+    X, _ = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)
+    B = th.shape[0]
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    xb = torch.tensor(synth.rhs(w.n_src, B, seed=2).T.copy(), dtype=torch.float32, device="cuda")
+    kw = dict(kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta, n_spatial=w.n_spatial,
+              n_param=w.n_param, tol=w.tol, dtype=torch.float32, seed=0, symmetric_psd=True)
+
+    def step():
+        kern = pkg.TTKernel.build_offline(Xd, None, **kw)
+        y = kern.global_apply(xb, theta=thd)
+        return kern, y
+
+    for i in range(args.warmup):
+        kern, _ = step()
+        print(f"warmup {i} done: ranks {kern.info()['ranks']}", file=sys.stderr, flush=True)
+    ms = time_wall(step, args.steps, torch)
+    kern, _ = step()
+    inf = kern.info()
+    Q, R = kern.global_factors()
+    k = Q.shape[1]
+    ms_online = time_events(lambda: kern.global_online(thd), 5, torch)
+    W = kern.global_online(thd)
+    ms_apply = time_events(lambda: kern.global_apply(xb, W=W), 10, torch)
+    bytes_apply = 2 * 4 * w.n_src * k + 2 * 4 * B * w.n_src
+    # accuracy against dense float64 K(X, X) on a 4000-point subsample
+    rng = np.random.default_rng(11)
+    si = np.sort(rng.choice(w.n_src, 4000, replace=False))
+    Qs = Q[si].double()
+    errs = []
+    for b in range(B):
+        K = pkg.eval_dense(torch.tensor(X[si]), torch.tensor(X[si]), th[b], w.kind, w.d, dtype=torch.float64)
+        Kh = Qs @ W[b].double() @ Qs.t()
+        errs.append((torch.linalg.norm(K - Kh) / torch.linalg.norm(K)).item())
+    rows = 2 * w.n_src
+    res = base_result(w, args, rows / (ms / 1000.0), "rows/s", ms, B, {"variant": "Global-1", "X=Y": True})
+    res.update({"ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
+                "k": k, "kernel_evals": inf["kernel_evals"], "t_cross_ms": round(inf["t_cross_ms"], 2),
+                "t_round_ms": round(inf["t_round_ms"], 2), "t_factor_and_qr_ms": round(inf["t_factor_ms"], 2),
+                "online_ms_per_theta": round(ms_online / B, 4), "global_apply_ms": round(ms_apply, 4),
+                "global_apply_GBps": round(bytes_apply / (ms_apply * 1e-3) / 1e9, 1),
+                "max_rel_err_vs_dense_fp64": float(f"{max(errs):.3e}"), "status": kern.status,
+                "accuracy_note": "Q W Q^T against dense float64 K(X, X) on a 4000-point subsample, worst theta"})
+    res["roofline"] = {"kernel": "Global-1 apply (Q^T x, W, Q z)", "bound": "hbm",
+                       "achieved": res["global_apply_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": round(res["global_apply_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None}
+    return res
+
+
+def bench_batched(args, torch, pkg):
+    """Batched + differentiated apply at 1M + 1M points and B = 4096 theta samples."""
+    w = synth.WORKLOADS["matern_batched"]
+    X, Y = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)
+    B = th.shape[0]
+    Xd = torch.tensor(X, dtype=torch.float32, device="cuda")
+    Yd = torch.tensor(Y, dtype=torch.float32, device="cuda")
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    xb = torch.randn((B, w.n_tgt), generator=gen, device="cuda", dtype=torch.float32)
+    gb = torch.randn((B, w.n_src), generator=gen, device="cuda", dtype=torch.float32)
+    kw = dict(kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta, n_spatial=w.n_spatial,
+              n_param=w.n_param, tol=w.tol, dtype=torch.float32, seed=0)
+
+    def step():
+        kern = pkg.TTKernel.build_offline(Xd, Yd, **kw)
+        Yo, Wv = kern.apply(thd, xb, save_w=True)
+        kern.apply_backward(thd, gb, W=Wv)
+        return kern
+
+    for i in range(args.warmup):
+        kern = step()
+        print(f"warmup {i} done: ranks {kern.info()['ranks']}", file=sys.stderr, flush=True)
+    ms = time_wall(step, args.steps, torch)
+    kern = step()
+    inf = kern.info()
+    rs, rt = kern.r_s, kern.r_t
+    ms_ag = time_events(lambda: kern.apply_backward(thd, gb, W=kern.apply(thd, xb, save_w=True)[1]), 3, torch)
+    bytes_ag = 2 * 4 * (w.n_src * rs + w.n_tgt * rt) + 2 * 4 * B * (w.n_src + w.n_tgt)
+    flops_ag = 4 * B * (w.n_src * rs + w.n_tgt * rt)   # four tall products, 2 N r B each
+    nplain = 64
+    ms_plain = time_events(lambda: kern.apply_plain(thd[:nplain], xb[:nplain]), 2, torch)
+    gbps = bytes_ag / (ms_ag * 1e-3) / 1e9
+    res = base_result(w, args, (w.n_src + w.n_tgt) / (ms / 1000.0), "rows/s", ms, B)
+    res.update({"ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
+                "t_cross_ms": round(inf["t_cross_ms"], 2), "t_round_ms": round(inf["t_round_ms"], 2),
+                "t_factor_ms": round(inf["t_factor_ms"], 3), "apply_grad_ms": round(ms_ag, 3),
+                "apply_grad_GBps": round(gbps, 1), "apply_grad_TFLOPs": round(flops_ag / (ms_ag * 1e-3) / 1e12, 2),
+                "batched_vs_plain_theta_per_s": round((B / ms_ag) / (nplain / ms_plain), 3),
+                "plain_note": f"plain per-theta apply timed on {nplain} of the {B} thetas"})
+    res["roofline"] = {"kernel": "batched apply + backward (four tall contractions)", "bound": "hbm",
+                       "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None}
+    return res
+
+
+def bench_pairs(args, torch, pkg):
+    """Uneven batch: 512 box pairs of an FMM-like interaction list, 256 thetas."""
+    base = synth.WORKLOADS["matern_batched"]
+    pairs = synth.uneven_pairs()
+    rng = np.random.default_rng(0)
+    xs, ys = [], []
+    so = to = 0
+    for p in pairs:
+        bs, bt = np.asarray(p["box_s"]), np.asarray(p["box_t"])
+        xs.append(np.clip(rng.uniform(bs[:, 0], bs[:, 1], (p["n_src"], 3)).astype(np.float32), bs[:, 0], bs[:, 1]))
+        ys.append(np.clip(rng.uniform(bt[:, 0], bt[:, 1], (p["n_tgt"], 3)).astype(np.float32), bt[:, 0], bt[:, 1]))
+        p["src_off"], p["tgt_off"] = so, to
+        so += p["n_src"]
+        to += p["n_tgt"]
+    Xd = torch.tensor(np.vstack(xs), device="cuda")
+    Yd = torch.tensor(np.vstack(ys), device="cuda")
+    B = 256
+    th = synth.thetas(base, count=B, seed=1)
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2)
+    xb = torch.randn((B, to), generator=gen, device="cuda")
+    gb = torch.randn((B, so), generator=gen, device="cuda")
+    out = (torch.empty((B, so), device="cuda"), torch.empty((B, to), device="cuda"),
+           torch.empty((B, 2), device="cuda"))
+    kw = dict(kind="matern", d=3, box_theta=base.box_theta, n_spatial=14, n_param=14, tol=1e-6,
+              dtype=torch.float32, seed=0)
+
+    def step():
+        bt = pkg.TTBatch.build(pairs, Xd, Yd, **kw)
+        bt.apply(thd, xb, G=gb, out=out)
+        return bt
+
+    for i in range(args.warmup):
+        bt = step()
+        print(f"warmup {i} done: {bt.info()['num_classes']} classes", file=sys.stderr, flush=True)
+    ms = time_wall(step, args.steps, torch)
+    bt = step()
+    inf = bt.info()
+    Xs, Ys = Xd.t().contiguous(), Yd.t().contiguous()
+    ms_p3 = time_events(lambda: bt.refactor_soa(Xs, Ys), 5, torch)
+    ms_ag = time_events(lambda: bt.apply(thd, xb, G=gb, out=out), 5, torch)
+    rs_rows = sum(p["n_src"] * inf["class_ranks"][c][3] for p, c in zip(pairs, inf["class_of_pair"]))
+    rt_rows = sum(p["n_tgt"] * inf["class_ranks"][c][5] for p, c in zip(pairs, inf["class_of_pair"]))
+    bytes_ag = 2 * 4 * (rs_rows + rt_rows) + 2 * 4 * B * (so + to)
+    gbps = bytes_ag / (ms_ag * 1e-3) / 1e9
+    res = {"metric": METRIC, "value": round((so + to) / (ms / 1000.0), 1), "unit": "rows/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "uneven_pairs", "kernel": "matern", "d": 3, "d_theta": 2, "pairs": len(pairs),
+                      "N_s": so, "N_t": to, "n_spatial": 14, "n_param": 14, "tol": 1e-6, "n_theta": B,
+                      "parallelism": "single GPU"},
+           "classes": inf["num_classes"], "kernel_evals": inf["kernel_evals"],
+           "t_cross_ms": round(inf["t_cross_ms"], 1), "t_round_ms": round(inf["t_round_ms"], 1),
+           "phase3_all_pairs_ms": round(ms_p3, 3), "phase3_rows_per_s": round((so + to) / (ms_p3 * 1e-3), 1),
+           "factor_grid": inf["factor_grid"], "reduce_rows": inf["reduce_rows"], "graph": inf["graph"],
+           "apply_grad_ms": round(ms_ag, 3), "apply_grad_GBps": round(gbps, 1)}
+    res["roofline"] = {"kernel": "batched apply + backward over all pairs", "bound": "hbm", "achieved": round(gbps, 1),
+                       "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                       "traffic": None}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +279,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-only", action="store_true", help="time the steps only (profiling runs)")
     ap.add_argument("--cpu-points", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -103,6 +294,19 @@ def main():
     import paper_2406_06344_amd as pkg
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = 1 << 28                                   # 2^28 floats = 1 GiB read + 1 GiB written
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 3}), flush=True)
+        return
+    other = {"matern_global": bench_global, "matern_batched": bench_batched, "uneven_pairs": bench_pairs}
+    if args.workload in other:
+        print(json.dumps(other[args.workload](args, torch, pkg)), flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     X, Y = synth.points(w, seed=0)
     th = synth.thetas(w, seed=1)
@@ -207,12 +411,18 @@ def main():
         "accuracy_note": "relative Frobenius error of U M V^T against dense float64 K on a 4000 x 4000 "
                          "subsample, worst of the theta samples",
     })
-    # dominant N-dependent kernel: Phase 3 on the target side (more flops per point)
+    # the dominant N-dependent kernel: Phase 3 (k_factor_mfma), one launch per side;
+    # achieved = algorithmic flops of both launches / their summed durations
+    tf_both = (fl_u + fl_v) / ((ms_u + ms_v) * 1e-3) / 1e12
     result["roofline"] = {
-        "kernel": "k_factor (Phase 3, target chain)", "bound": "mfma",
-        "achieved": round(tf_v, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(tf_v / FP32_PEAK_TFLOPS, 4), "traffic": None,
-        "algorithmic": f"{fl_v / w.n_tgt:.0f} flop per point x {w.n_tgt} points per launch",
+        "kernel": "k_factor_mfma (Phase 3, source and target launches)", "bound": "mfma",
+        "achieved": round(tf_both, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(tf_both / FP32_PEAK_TFLOPS, 4), "traffic": TRAFFIC,
+        "avg_launch_ms": round((ms_u + ms_v) / 2, 4),
+        "traffic_note": "HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a plain "
+                        "1 GiB copy), average of the two launches; algorithmic 28.1 MB",
+        "algorithmic": f"{fl_u / w.n_src:.0f} (source) and {fl_v / w.n_tgt:.0f} (target) flop per point, "
+                       f"{w.n_src} and {w.n_tgt} points per launch",
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, X, Y, th, args.cpu_points)
