@@ -4,8 +4,10 @@
 //     expand:  Y = F Z     (N x B)
 // and small per-theta products done by batched_matvec / batched_bilinear.
 // Plain (B = 1): a GEMV pair, bound by reading F once.  Batched: register-
-// tiled GEMMs that read F once for all B columns.  Partial sums of the
-// reduce over point chunks are combined with atomics (order not fixed).
+// tiled GEMMs that read F once for all B columns.  Products are formed in
+// the working precision and summed in double over point tiles (a float32
+// running sum over 10^5 points loses digits); partial sums of the reduce over
+// point chunks are combined with atomics (order not fixed).
 #include "ttk_internal.h"
 
 namespace ttk {
@@ -18,25 +20,33 @@ __global__ void k_fill(T* p, size_t n) {
     p[i] = (T)0;
 }
 
+// Widest factor the apply kernels take: U, V (r <= MAXR) and the Global-1 Q
+// (k = r_s + r_t <= 2 MAXR).
+constexpr int MAXF = 2 * MAXR;
+
 // w[c] += sum_p F[p, c] x[p]; one row per wave at a time, lanes over columns.
 template <class T>
 __global__ void __launch_bounds__(256) k_reduce_plain(const T* F, int ldf, int64_t N, int r, const T* x, T* w) {
-  __shared__ T red[4][MAXR];
+  __shared__ T red[4][MAXF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+  // products in T, sums in double: a long reduction over points must not
+  // accumulate the rounding of a float32 running sum
+  double acc[MAXF / 64];
+#pragma unroll
+  for (int q = 0; q < MAXF / 64; ++q) acc[q] = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * 4 + wv; p < N; p += (int64_t)gridDim.x * 4) {
     const T xv = x[p];
     const T* row = F + p * ldf;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < MAXF / 64; ++q) {
       const int c = lane + 64 * q;
-      if (c < r) acc[q] += row[c] * xv;
+      if (c < r) acc[q] += (double)(row[c] * xv);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < MAXF / 64; ++q) {
     const int c = lane + 64 * q;
-    if (c < r) red[wv][c] = acc[q];
+    if (c < r) red[wv][c] = (T)acc[q];
   }
   __syncthreads();
   for (int c = threadIdx.x; c < r; c += 256) atomicAdd(&w[c], red[0][c] + red[1][c] + red[2][c] + red[3][c]);
@@ -45,7 +55,7 @@ __global__ void __launch_bounds__(256) k_reduce_plain(const T* F, int ldf, int64
 // y[p] = sum_c F[p, c] z[c]; 16 lanes per row, reduced by shuffles.
 template <class T>
 __global__ void __launch_bounds__(256) k_expand_plain(const T* F, int ldf, int64_t N, int r, const T* z, T* y) {
-  __shared__ T zs[MAXR];
+  __shared__ T zs[MAXF];
   for (int c = threadIdx.x; c < r; c += 256) zs[c] = z[c];
   __syncthreads();
   const int sub = threadIdx.x & 15;
@@ -70,11 +80,12 @@ __global__ void __launch_bounds__(256) k_reduce_tiled(const T* F, int ldf, int64
   const int64_t pbeg = (int64_t)blockIdx.z * chunk;
   const int64_t pend = (pbeg + chunk < N) ? pbeg + chunk : N;
   const int tr = tid / 16, tb = tid % 16;
-  T acc[4][4];
+  // each 16-row tile is summed in T, the tiles in double
+  double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
     for (int e = tid; e < 16 * 64; e += 256) {
       const int kk = e / 64, c = e % 64;
@@ -87,6 +98,11 @@ __global__ void __launch_bounds__(256) k_reduce_tiled(const T* F, int ldf, int64
       Xs[kk][j] = (p < pend && b0 + j < B) ? X[p + (int64_t)(b0 + j) * ldx] : (T)0;
     }
     __syncthreads();
+    T t[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[i][j] = (T)0;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       T a[4], b[4];
@@ -97,8 +113,12 @@ __global__ void __launch_bounds__(256) k_reduce_tiled(const T* F, int ldf, int64
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < 4; ++j) t[i][j] += a[i] * b[j];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += (double)t[i][j];
     __syncthreads();
   }
 #pragma unroll
@@ -106,7 +126,7 @@ __global__ void __launch_bounds__(256) k_reduce_tiled(const T* F, int ldf, int64
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int rr = r0 + tr * 4 + i, bb = b0 + tb * 4 + j;
-      if (rr < r && bb < B) atomicAdd(&W[rr + (int64_t)bb * r], acc[i][j]);
+      if (rr < r && bb < B) atomicAdd(&W[rr + (int64_t)bb * r], (T)acc[i][j]);
     }
 }
 
@@ -121,11 +141,11 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
   const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int b0 = blockIdx.y * 64;
   const int tp = tid % 16, tb = tid / 16;
-  T acc[4][4];
+  double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   for (int k0 = 0; k0 < r; k0 += 16) {
     for (int e = tid; e < 64 * 16; e += 256) {
       const int pl = e / 16, kk = e % 16;
@@ -137,6 +157,11 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
       Zs[kk][j] = (k0 + kk < r && b0 + j < B) ? Z[(k0 + kk) + (int64_t)(b0 + j) * r] : (T)0;
     }
     __syncthreads();
+    T t[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[i][j] = (T)0;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       T a[4], b[4];
@@ -147,8 +172,12 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < 4; ++j) t[i][j] += a[i] * b[j];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += (double)t[i][j];
     __syncthreads();
   }
 #pragma unroll
@@ -158,7 +187,7 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t p = p0 + tp + 16 * i;
-      if (p < N) Y[p + (int64_t)bb * ldy] = acc[i][j];
+      if (p < N) Y[p + (int64_t)bb * ldy] = (T)acc[i][j];
     }
   }
 }
@@ -167,7 +196,7 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
 template <class T>
 __global__ void __launch_bounds__(256) k_bmatvec(const T* M, int rows, int cols, int trans, const T* x, int B,
                                                  T* y) {
-  __shared__ T xs[MAXR];
+  __shared__ T xs[MAXF];
   const int nin = trans ? rows : cols, nout = trans ? cols : rows;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const T* Mb = M + (size_t)b * rows * cols;
@@ -175,12 +204,12 @@ __global__ void __launch_bounds__(256) k_bmatvec(const T* M, int rows, int cols,
     for (int i = threadIdx.x; i < nin; i += 256) xs[i] = x[(size_t)b * nin + i];
     __syncthreads();
     for (int o = threadIdx.x; o < nout; o += 256) {
-      T s = (T)0;
+      double s = 0.0;
       if (!trans)
-        for (int c = 0; c < cols; ++c) s += Mb[o + (size_t)c * rows] * xs[c];
+        for (int c = 0; c < cols; ++c) s += (double)Mb[o + (size_t)c * rows] * (double)xs[c];
       else
-        for (int i = 0; i < rows; ++i) s += Mb[i + (size_t)o * rows] * xs[i];
-      y[(size_t)b * nout + o] = s;
+        for (int i = 0; i < rows; ++i) s += (double)Mb[i + (size_t)o * rows] * (double)xs[i];
+      y[(size_t)b * nout + o] = (T)s;
     }
   }
 }

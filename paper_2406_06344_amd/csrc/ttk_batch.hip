@@ -30,11 +30,11 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const T* F, const BatchSid
   const T* Fp = F + sd.foff;
   const int tid = threadIdx.x;
   const int tr = tid / 16, tb = tid % 16;
-  T acc[4][4];
+  double acc[4][4];   // tiles of BK rows summed in T, the tiles in double
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (T)0;
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   const int64_t pend = it.row0 + it.nrows;
   for (int64_t p0 = it.row0; p0 < pend; p0 += BK) {
     for (int e = tid; e < BK * BT; e += 256) {
@@ -48,6 +48,11 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const T* F, const BatchSid
       Xs[kk][j] = (p < pend && it.b0 + j < B) ? X[sd.roff + p + (int64_t)(it.b0 + j) * ldx] : (T)0;
     }
     __syncthreads();
+    T t[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[i][j] = (T)0;
 #pragma unroll
     for (int kk = 0; kk < BK; ++kk) {
       T a[4], b[4];
@@ -58,8 +63,12 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const T* F, const BatchSid
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int j = 0; j < 4; ++j) t[i][j] += a[i] * b[j];
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += (double)t[i][j];
     __syncthreads();
   }
   T* Wp = W + sd.woff;
@@ -68,7 +77,7 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const T* F, const BatchSid
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int rr = it.r0 + tr * 4 + i, bb = it.b0 + tb * 4 + j;
-      if (rr < r && bb < B) atomicAdd(&Wp[rr + (int64_t)bb * r], acc[i][j]);
+      if (rr < r && bb < B) atomicAdd(&Wp[rr + (int64_t)bb * r], (T)acc[i][j]);
     }
 }
 

@@ -1,0 +1,44 @@
+"""Writes tests/golden/<workload>_oracle.npz: the oracle's offline stage (TT
+greedy-cross, rounding, gauge) for a workload of synth.WORKLOADS, so the
+full-size GPU parity tests need not rerun the slow CPU cross.  The cross does
+not depend on the points; the stored cores, ranks and index sets are the
+oracle's alone (this script calls only oracle/ and synth/).
+
+usage: python tests/golden/make_oracle_offline.py matern32_d3
+"""
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import driver, kernels  # noqa: E402
+
+
+def main(name):
+    w = synth.WORKLOADS[name]
+    P = kernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param, w.const or None)
+    x0 = np.asarray(w.box_s, float)[:, :1].T
+    y0 = np.asarray(w.box_t, float)[:, :1].T
+    out = driver.offline(P, x0, y0, w.tol, seed=0)
+    info = out["info"]
+    arrays = {"ranks": np.array(out["ranks"]), "cross_ranks": np.array(info["ranks"]),
+              "sweeps": np.array(info["sweeps"]), "error": np.array(info["error"])}
+    for k, g in enumerate(out["cores"]):
+        arrays[f"core{k}"] = g
+    for k in range(1, P.D):
+        arrays[f"left{k}"] = np.asarray(info["L"][k], dtype=np.int32)
+        arrays[f"right{k}"] = np.asarray(info["R"][k], dtype=np.int32)
+    margins = [min(r.get("sample_margin", np.inf), r.get("search_margin", np.inf)) for r in info["log"]]
+    arrays["min_margin"] = np.array(min(margins) if margins else np.inf)
+    path = os.path.join(HERE, f"{name}_oracle.npz")
+    np.savez_compressed(path, **arrays)
+    print(path, out["ranks"], info["ranks"], info["sweeps"])
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "matern32_d3")

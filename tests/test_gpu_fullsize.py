@@ -1,0 +1,273 @@
+"""Full-size GPU checks, in the launch configurations bench.py times.
+
+- matern32_d3 (the benchmark workload, 100k + 100k points, float32): the
+  oracle's cross for the same problem is stored in tests/golden (written by
+  tests/golden/make_oracle_offline.py from oracle/ alone).  The GPU build must
+  reproduce its ranks and index sets; sampled rows of U and V, and the apply
+  and backward on inputs supported on sampled points, are compared with the
+  oracle computing those entries one by one.
+- se_d2_fp64 (2000 + 2000 points, float64): everything against a live oracle
+  run, including U M V^T on the full 2000 x 2000 block.
+- The Global-1 (200k points), batched (1M + 1M points, 4096 thetas) and
+  uneven-pair (512 pairs, 15M points, 256 thetas) workloads: properties that
+  hold at any size (orthonormal Q, Q R = [U V], PSD W, the adjoint identity of
+  the backward, batched = plain apply), since the oracle's cross for them takes
+  far longer than a test.  Their oracle parity is checked at reduced sizes in
+  test_gpu_global.py and test_gpu_batch.py.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import synth
+from oracle import dense as odense
+from oracle import driver as odriver
+from oracle import kernels as okernels
+from oracle import pttk as opttk
+from oracle import tt as ott
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return odense.rel_fro(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
+
+
+def adjoint_gap(dX, x, g, y, chunk=256):
+    """max over b of |<dX_b, x_b> - <g_b, y_b>| / (|g_b| |y_b|), in float64, by chunks of thetas."""
+    worst = 0.0
+    for b0 in range(0, x.shape[0], chunk):
+        sl = slice(b0, b0 + chunk)
+        lhs = (dX[sl].double() * x[sl].double()).sum(dim=1)
+        rhs = (g[sl].double() * y[sl].double()).sum(dim=1)
+        scale = g[sl].double().norm(dim=1) * y[sl].double().norm(dim=1)
+        worst = max(worst, ((lhs - rhs).abs() / scale).max().item())
+    return worst
+
+
+def test_benchmark_workload_full_size_matches_oracle():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    w = synth.WORKLOADS["matern32_d3"]
+    say(f"[full] {w.name}: build on {w.n_src} + {w.n_tgt} points")
+    g = np.load(os.path.join(GOLDEN, "matern32_d3_oracle.npz"))
+    X, Y = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)
+    B = th.shape[0]
+    kern = pkg.TTKernel.build_offline(torch.tensor(X, dtype=torch.float32), torch.tensor(Y, dtype=torch.float32),
+                                      kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta,
+                                      n_spatial=w.n_spatial, n_param=w.n_param, tol=w.tol, dtype=torch.float32,
+                                      seed=0)
+    inf = kern.info()
+    say(f"  ranks {inf['ranks']} cross {inf['cross_ranks']} sweeps {inf['sweeps']} min margin {inf['min_margin']:.2e}")
+    assert inf["ranks"] == list(g["ranks"])
+    assert inf["cross_ranks"] == list(g["cross_ranks"])
+    assert inf["sweeps"] == int(g["sweeps"])
+    L, R, _ = kern.cross_record()
+    D = inf["D"]
+    for k in range(1, D):
+        assert np.array_equal(L[k], g[f"left{k}"]), k
+        assert np.array_equal(R[k], g[f"right{k}"]), k
+    # rounded cores: the two TTs agree at sampled multi-indices
+    Gg = kern.cores()
+    Go = [g[f"core{k}"] for k in range(D)]
+    rng = np.random.default_rng(21)
+    P = okernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param)
+    idx = np.stack([rng.integers(0, nj, 20000) for nj in P.n], axis=1)
+    vo = ott.evaluate(Go, idx)
+    assert np.abs(ott.evaluate(Gg, idx) - vo).max() <= 1e-10 * np.abs(vo).max()
+    # sampled rows of U and V against the oracle's Phase 3 at those points
+    si = np.sort(rng.choice(w.n_src, 2000, replace=False))
+    ti = np.sort(rng.choice(w.n_tgt, 2000, replace=False))
+    d, dt = w.d, w.d_theta
+    S = opttk.phase3_source(opttk.factor_values(X[si], P.box_s, w.n_spatial), Go[:d])
+    T = opttk.phase3_target(opttk.factor_values(Y[ti], P.box_t, w.n_spatial), Go[d + dt:])
+    U, V = kern.factors()
+    eu, ev = rel(U[si].double().cpu().numpy(), S), rel(V[ti].double().cpu().numpy(), T)
+    say(f"  sampled rows: U {eu:.2e} V {ev:.2e}")
+    assert eu <= 2e-5 and ev <= 2e-5
+    # apply + backward in the benchmark's configuration, inputs supported on the samples
+    xs = synth.rhs(2000, B, seed=2)
+    gs = synth.rhs(2000, B, seed=3)
+    xb = torch.zeros((B, w.n_tgt), dtype=torch.float32, device="cuda")
+    gb = torch.zeros((B, w.n_src), dtype=torch.float32, device="cuda")
+    xb[:, torch.tensor(ti)] = torch.tensor(xs.T, dtype=torch.float32, device="cuda")
+    gb[:, torch.tensor(si)] = torch.tensor(gs.T, dtype=torch.float32, device="cuda")
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    Yo, Wv = kern.apply(thd, xb, save_w=True)
+    dX, dth = kern.apply_backward(thd, gb, W=Wv)
+    Hs = [opttk.online_H(Go[d:d + dt], t, P.box_theta, w.n_param) for t in th]
+    dHs = [opttk.online_dH(Go[d:d + dt], t, P.box_theta, w.n_param) for t in th]
+    y_o = np.stack([S @ (Hs[b] @ (T.T @ xs[:, b])) for b in range(B)])
+    dx_o = np.stack([T @ (Hs[b].T @ (S.T @ gs[:, b])) for b in range(B)])
+    dth_o = np.array([[(S.T @ gs[:, b]) @ dHs[b][j] @ (T.T @ xs[:, b]) for j in range(dt)] for b in range(B)])
+    ey = rel(Yo[:, torch.tensor(si)].double().cpu().numpy(), y_o)
+    ex = rel(dX[:, torch.tensor(ti)].double().cpu().numpy(), dx_o)
+    et = rel(dth.double().cpu().numpy(), dth_o)
+    say(f"  apply {ey:.2e} dX {ex:.2e} dtheta {et:.2e}")
+    assert ey <= 2e-5 and ex <= 2e-5 and et <= 2e-5
+
+
+def test_fp64_workload_full_size_matches_oracle():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    w = synth.WORKLOADS["se_d2_fp64"]
+    say(f"[full] {w.name}")
+    X, Y = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)
+    P = okernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param)
+    out = odriver.offline(P, X, Y, w.tol, seed=0)
+    kern = pkg.TTKernel.build_offline(torch.tensor(X), torch.tensor(Y), kind=w.kind, d=w.d, box_s=w.box_s,
+                                      box_t=w.box_t, box_theta=w.box_theta, n_spatial=w.n_spatial,
+                                      n_param=w.n_param, tol=w.tol, dtype=torch.float64, seed=0)
+    inf = kern.info()
+    assert inf["ranks"] == out["ranks"]
+    U, V = kern.factors()
+    M = kern.online_core(torch.tensor(th, device="cuda"))
+    d = w.d
+    worst_o = worst_g = 0.0
+    for b in range(th.shape[0]):
+        H = opttk.online_H(out["param"], th[b], P.box_theta, w.n_param)
+        Ko = out["S"] @ H @ out["T"].T
+        Kg = (U @ M[b] @ V.t()).cpu().numpy()
+        e = rel(Kg, Ko)
+        assert e <= 1e-10, (b, e)
+        K = odense.dense_K(w.kind, X, Y, th[b])
+        worst_o = max(worst_o, rel(Ko, K))
+        worst_g = max(worst_g, rel(Kg, K))
+    say(f"  |U M V^T - K| / |K| (2000 x 2000, worst theta): gpu {worst_g:.3e} oracle {worst_o:.3e}")
+    assert abs(worst_g - worst_o) <= 1e-9
+
+
+def test_global_workload_full_size_properties():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    w = synth.WORKLOADS["matern_global"]
+    say(f"[full] {w.name}: Global-1 on {w.n_src} points")
+    X, _ = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)[:4]
+    kern = pkg.TTKernel.build_offline(torch.tensor(X, dtype=torch.float32), None, kind=w.kind, d=w.d,
+                                      box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta, n_spatial=w.n_spatial,
+                                      n_param=w.n_param, tol=w.tol, dtype=torch.float32, seed=0,
+                                      symmetric_psd=True)
+    Q, R = kern.global_factors()
+    k = Q.shape[1]
+    Qd = Q.double()
+    orth = (Qd.t() @ Qd - torch.eye(k, dtype=torch.float64, device="cuda")).abs().max().item()
+    U, V = kern.factors()
+    A = torch.cat([U, V], dim=1).double()
+    resid = (torch.linalg.norm(Qd @ torch.tensor(R, device="cuda") - A) / torch.linalg.norm(A)).item()
+    say(f"  k = {k}, |Q^T Q - I| = {orth:.2e}, |QR - [U V]| / |[U V]| = {resid:.2e}")
+    assert orth <= 1e-5 and resid <= 1e-6
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    W = kern.global_online(thd).double()
+    for b in range(W.shape[0]):
+        lam = torch.linalg.eigvalsh(0.5 * (W[b] + W[b].t()))
+        assert lam.min().item() >= -1e-6 * lam.abs().max().item()
+    x = torch.randn((4, w.n_src), device="cuda", generator=torch.Generator(device="cuda").manual_seed(5))
+    y = kern.global_apply(x, W=kern.global_online(thd)).double()
+    for b in range(4):
+        yb = Qd @ (W[b] @ (Qd.t() @ x[b].double()))
+        assert (torch.linalg.norm(y[b] - yb) / torch.linalg.norm(yb)).item() <= 1e-5
+        # x^T (Q W Q^T) x >= 0
+        assert (x[b].double() @ y[b]).item() >= -1e-6 * torch.linalg.norm(x[b].double()).item() ** 2 * \
+            torch.linalg.eigvalsh(W[b]).abs().max().item()
+
+
+def test_batched_workload_full_size_properties():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    w = synth.WORKLOADS["matern_batched"]
+    say(f"[full] {w.name}: {w.n_src} + {w.n_tgt} points, {w.n_theta} thetas")
+    X, Y = synth.points(w, seed=0)
+    th = synth.thetas(w, seed=1)
+    B = th.shape[0]
+    kern = pkg.TTKernel.build_offline(torch.tensor(X, dtype=torch.float32), torch.tensor(Y, dtype=torch.float32),
+                                      kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta,
+                                      n_spatial=w.n_spatial, n_param=w.n_param, tol=w.tol, dtype=torch.float32,
+                                      seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(2)
+    xb = torch.randn((B, w.n_tgt), generator=gen, device="cuda")
+    gb = torch.randn((B, w.n_src), generator=gen, device="cuda")
+    thd = torch.tensor(th, dtype=torch.float32, device="cuda")
+    Yo, Wv = kern.apply(thd, xb, save_w=True)
+    dX, dth = kern.apply_backward(thd, gb, W=Wv)
+    # adjoint identity per theta: <dX_b, x_b> = <g_b, y_b>
+    adj = adjoint_gap(dX, xb, gb, Yo)
+    say(f"  adjoint identity: max |<dX,x> - <g,y>| / (|g||y|) = {adj:.2e}")
+    assert adj <= 1e-5
+    # the batched apply equals the plain per-theta apply (other kernels) on a few thetas
+    sel = [0, 1, 2047, 4095]
+    Yp = kern.apply_plain(thd[sel], xb[sel])
+    e = (torch.linalg.norm(Yp.double() - Yo[sel].double()) / torch.linalg.norm(Yo[sel].double())).item()
+    say(f"  batched vs plain apply: {e:.2e}")
+    assert e <= 1e-5
+    assert torch.isfinite(dth).all()
+
+
+def test_uneven_pairs_full_size_properties():
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    base = synth.WORKLOADS["matern_batched"]
+    pairs = synth.uneven_pairs()
+    rng = np.random.default_rng(0)
+    xs, ys = [], []
+    so = to = 0
+    for p in pairs:
+        bs, bt = np.asarray(p["box_s"]), np.asarray(p["box_t"])
+        xs.append(np.clip(rng.uniform(bs[:, 0], bs[:, 1], (p["n_src"], 3)).astype(np.float32), bs[:, 0], bs[:, 1]))
+        ys.append(np.clip(rng.uniform(bt[:, 0], bt[:, 1], (p["n_tgt"], 3)).astype(np.float32), bt[:, 0], bt[:, 1]))
+        p["src_off"], p["tgt_off"] = so, to
+        so += p["n_src"]
+        to += p["n_tgt"]
+    say(f"[full] uneven pairs: {len(pairs)} pairs, {so} + {to} points")
+    bt = pkg.TTBatch.build(pairs, torch.tensor(np.vstack(xs)), torch.tensor(np.vstack(ys)), "matern", 3,
+                           base.box_theta, n_spatial=14, n_param=14, tol=1e-6, dtype=torch.float32, seed=0)
+    inf = bt.info()
+    say(f"  {inf['num_classes']} classes, factor grid {inf['factor_grid']}")
+    B = 256
+    th = torch.tensor(synth.thetas(base, count=B, seed=1), dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(2)
+    xb = torch.randn((B, to), generator=gen, device="cuda")
+    gb = torch.randn((B, so), generator=gen, device="cuda")
+    out = (torch.empty((B, so), device="cuda"), torch.empty((B, to), device="cuda"), torch.empty((B, 2), device="cuda"))
+    Yo, dX, dth = bt.apply(th, xb, G=gb, out=out)
+    adj = adjoint_gap(dX, xb, gb, Yo)
+    say(f"  adjoint identity {adj:.2e}")
+    assert adj <= 1e-5
+    # replays of the captured graph reproduce the first call
+    ref = [t.clone() for t in out]
+    for _ in range(2):
+        bt.apply(th, xb, G=gb, out=out)
+        for a, b in zip(out, ref):
+            assert (torch.linalg.norm(a.double() - b.double()) / torch.linalg.norm(b.double())).item() <= 1e-6
+    # one pair against its own class kernel applied to its rows
+    p0 = 7
+    c = inf["class_of_pair"][p0]
+    U, V = bt.factors(p0)
+    ck = bt.class_kernel(c)
+    M = ck.online_core(th[:3])
+    q = pairs[p0]
+    xr = torch.zeros((3, to), device="cuda")
+    xr[:, q["tgt_off"]:q["tgt_off"] + q["n_tgt"]] = xb[:3, q["tgt_off"]:q["tgt_off"] + q["n_tgt"]]
+    Yr = bt.apply(th[:3], xr)
+    for b in range(3):
+        yb = U.double() @ (M[b].double() @ (V.double().t() @ xr[b, q["tgt_off"]:q["tgt_off"] + q["n_tgt"]].double()))
+        got = Yr[b, q["src_off"]:q["src_off"] + q["n_src"]].double()
+        assert (torch.linalg.norm(got - yb) / torch.linalg.norm(yb)).item() <= 1e-5
