@@ -7,7 +7,7 @@ One step = the whole hot path on one batch of synthetic input:
   its backward pass (dX, dtheta).
 Workload (default): d = 3, 100k + 100k points uniform in separated unit
 cubes (target cube offset by 2 along axis 1), Matern nu = 3/2 in the length
-scale l in [0.5, 2], 16 nodes per dimension, tol 1e-6, 16 theta samples,
+scale l in [0.5, 2], 16 nodes per dimension, tol 7e-7, 16 theta samples,
 float32 bulk with float64 cross / factorisations.
 
 Prints one JSON line.  value = whole-step offline U/V rows per second,
@@ -35,7 +35,7 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes of the roofline kernel from rocprofv3 counter runs (FETCH_SIZE and
 # WRITE_SIZE, separate runs) scaled by the same counters on a plain copy of
 # known size; None until taken for the current kernel.
-TRAFFIC = 29000379   # bytes per launch, k_factor_mfma on matern32_d3 (see profiles/)
+TRAFFIC = None
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -279,6 +279,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-only", action="store_true", help="time the steps only (profiling runs)")
     ap.add_argument("--cpu-points", type=int, default=2000)
+    ap.add_argument("--tol", type=float, default=None, help="override the workload's tolerance")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -308,6 +309,8 @@ def main():
         print(json.dumps(other[args.workload](args, torch, pkg)), flush=True)
         return
     w = synth.WORKLOADS[args.workload]
+    if args.tol is not None:
+        w = synth.small(w, w.n_src, w.n_tgt, tol=args.tol)
     X, Y = synth.points(w, seed=0)
     th = synth.thetas(w, seed=1)
     B = th.shape[0]

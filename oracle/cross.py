@@ -18,7 +18,7 @@ Readings of the paper taken here (each written out in the design notes):
   drawn by Floyd's algorithm from the splitmix64 stream keyed
   (seed, TAG_UPDATE, sweep, k), sorted ascending; the bit is the top bit of the
   next draw of the same stream; bit 1 searches the row, bit 0 the column.
-* Ties: among |R| values within tau = 1e-12 * (largest |entry| evaluated in the
+* Ties: among |R| values within tau = 1e-10 * (largest |entry| evaluated in the
   call so far) of the maximum, the lowest linear position wins.
 * "If applicable update": the pair is added only if |R(l,t)| > tau, l is not in
   I, t is not in J and r_k < max_rank.
@@ -42,7 +42,7 @@ import numpy as np
 from . import rng as rngmod
 from . import tt as ttmod
 
-TIE_REL = 1e-12
+TIE_REL = 1e-10
 COND_REL = 1e-12
 
 

@@ -11,17 +11,30 @@
 //
 // Readings shared with the oracle: residual R = A(:,J) A(I,J)^{-1} A(I,:) - A;
 // max{rows, cols} samples by Floyd's algorithm from the splitmix64 stream
-// keyed (seed, 2, sweep, k), then the bit; argmax ties (within 1e-12 x the
+// keyed (seed, 2, sweep, k), then the bit; argmax ties (within 1e-10 x the
 // largest |entry| evaluated so far in the step) go to the lowest position;
 // a pivot is added only if |R| exceeds that band, is new, and the rank is
 // below the cap.  Stopping: max |X - X^| / max |X| over n_test fixed
 // multi-indices (stream (seed, 3)), with cores C_k = F_k P_k^{-1} (LU solve);
 // the cores returned are those of the last stopping test.
 //
-// The LU factorisation of each intersection matrix P_k = X(I^{<=k}, I^{>k})
-// is cached per k: P_k changes only when step k appends a pivot, and the
-// stopping test solves with P_k^T through the same factors.  Right-hand
-// sides are laid out with their index fastest so a solve reads coalesced.
+// Each intersection matrix P_k = X(I^{<=k}, I^{>k}) is kept factored in the
+// order the cross added its pivots: P = L D U with L unit lower, U unit upper
+// and D the pivots (the residuals at which they were added).  The device
+// holds Li = L^{-1} and W = U^{-1} D^{-1}, so that P^{-1} = W Li and every
+// solve of the cross is two products: the residuals of the sampled entries
+// and of the searched fibre, and the cores C_k = F_k P_k^{-1} of the stopping
+// test.  The ill-conditioning of P (pivots from about 1 down to the
+// tolerance) sits in D alone, which enters as a scaling; L and U have
+// entries bounded by the pivot rule (each pivot is the largest residual of
+// its row or column), so products with their inverses stay as accurate as
+// substitution.  When step k adds (l, t), P grows by a border:
+// b = X(I, t), c = X(l, J), d = X(l, t);  u = Li b, g^T = c^T W,
+// s = d - g^T u (minus the residual at the pivot), and
+//     Li' = [[Li, 0], [-g^T Li, 1]],   W' = [[W, -W u / s], [0, 1 / s]],
+// an O(r^2) update on the device.  The first (rank <= 2) matrices are
+// factored with the larger diagonal entry first (a symmetric permutation that
+// only Li and W carry).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -35,7 +48,7 @@ namespace ttk {
 
 namespace {
 
-constexpr double TIE_REL = 1e-12;
+constexpr double TIE_REL = 1e-10;
 
 // Result of one update step, written on the device, read back once.
 struct StepRes {
@@ -135,7 +148,7 @@ __global__ void k_select(const double* R, int n, const int32_t* srow, const int3
 
 __global__ void k_finalize(StepRes* res, int bit, const int32_t* I, const int32_t* J, int rk,
                            int max_rank, const int32_t* info) {
-  // (info: LU status of the cached factorisation of A(I, J))
+  // (info: status of the kept inverse of A(I, J); non-zero after a singular border)
   if (threadIdx.x != 0) return;
   const int row = bit ? res->l : res->q_pos;
   const int col = bit ? res->q_pos : res->t;
@@ -272,12 +285,112 @@ __global__ void k_err_max(const double* a, const double* b, int n, double* out) 
   if (threadIdx.x == 0) *out = red[0];
 }
 
+__global__ void k_copy_info(const int32_t* info, StepRes* res) {
+  if (threadIdx.x == 0 && *info) res->info = *info;
+}
+
 __global__ void k_set_scale(StepRes* res, const double* base) {
   if (threadIdx.x == 0) { res->s_scale = *base; res->q_scale = 0.0; }
 }
 
 __global__ void k_zero1(double* p) {
   if (threadIdx.x == 0) *p = 0.0;
+}
+
+// Factors of the initial intersection matrix (r <= 2), written with leading
+// dimension MAXR: Li (pivot x row), W (column x pivot); amax = max |entry|,
+// info = 1 if no diagonal entry can lead.
+__global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double* amax, int32_t* info) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < r * r; ++i) m = fmax(m, fabs(P[i]));
+  *amax = m;
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      Li[i + j * MAXR] = 0.0;
+      W[i + j * MAXR] = 0.0;
+    }
+  if (r == 1) {
+    *info = !(P[0] != 0.0) || !isfinite(P[0]);
+    Li[0] = 1.0;
+    W[0] = 1.0 / P[0];
+    return;
+  }
+  const int f = fabs(P[3]) > fabs(P[0]) ? 1 : 0, g = 1 - f;   // first pivot: the larger diagonal entry
+  const double d1 = P[f + f * r];
+  // second pivot (g, g): b = P(:, g), c = P(g, :)
+  const double u = P[f + g * r];          // Li row 0 = e_f, so u = b_f
+  const double gl = P[g + f * r] / d1;    // W col 0 = e_f / d1, so g = c_f / d1
+  const double sv = P[g + g * r] - gl * u;
+  *info = !(d1 != 0.0) || !(sv != 0.0) || !isfinite(sv) || !isfinite(d1);
+  Li[0 + f * MAXR] = 1.0;                 // pivot 0 reads row f
+  Li[1 + g * MAXR] = 1.0;                 // pivot 1: e_g - gl e_f
+  Li[1 + f * MAXR] = -gl;
+  W[f + 0 * MAXR] = 1.0 / d1;             // column f of P^{-1}'s factor for pivot 0
+  W[g + 1 * MAXR] = 1.0 / sv;             // pivot 1: (e_g - e_f u / d1) / s
+  W[f + 1 * MAXR] = -(u / d1) / sv;
+}
+
+// Border the factors (r x r, leading dimension MAXR) with the pivot's
+// column b = P(I, t), row c = P(l, J) and corner d, when the step added it.
+__global__ void __launch_bounds__(1024) k_border(double* Li, double* W, int r, const double* b, const double* c,
+                                                 const double* d, const StepRes* res, double* amax, int32_t* info) {
+  __shared__ double u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR];
+  __shared__ double s_s;
+  if (!res->added) return;
+  const int tid = threadIdx.x;
+  // u = Li b (pivot order), g = W^T c (pivot order)
+  for (int i = tid; i < 2 * r; i += blockDim.x) {
+    double acc = 0.0;
+    if (i < r) {
+      for (int q = 0; q < r; ++q) acc += Li[i + (int64_t)q * MAXR] * b[q];
+      u[i] = acc;
+    } else {
+      const int p = i - r;
+      for (int j = 0; j < r; ++j) acc += c[j] * W[j + (int64_t)p * MAXR];
+      gv[p] = acc;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double gu = 0.0, m = *amax;
+    for (int p = 0; p < r; ++p) {
+      gu += gv[p] * u[p];
+      m = fmax(m, fmax(fabs(b[p]), fabs(c[p])));
+    }
+    s_s = *d - gu;
+    *amax = fmax(m, fabs(*d));
+    if (!(s_s != 0.0) || !isfinite(s_s)) *info = 1;
+  }
+  __syncthreads();
+  const double is = 1.0 / s_s;
+  // new row of Li: -g^T Li; new column of W: -W u / s (both from the old factors)
+  for (int i = tid; i < 2 * r; i += blockDim.x) {
+    double acc = 0.0;
+    if (i < r) {
+      for (int p = 0; p < r; ++p) acc += gv[p] * Li[p + (int64_t)i * MAXR];
+      nl[i] = -acc;
+    } else {
+      const int j = i - r;
+      for (int p = 0; p < r; ++p) acc += W[j + (int64_t)p * MAXR] * u[p];
+      nw[j] = -acc * is;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e <= 2 * r + 1; e += blockDim.x) {
+    if (e < r) {
+      Li[r + (int64_t)e * MAXR] = nl[e];    // row r, column e
+      Li[e + (int64_t)r * MAXR] = 0.0;      // column r above the diagonal
+    } else if (e < 2 * r) {
+      const int j = e - r;
+      W[j + (int64_t)r * MAXR] = nw[j];     // column r
+      W[r + (int64_t)j * MAXR] = 0.0;       // row r left of the diagonal
+    } else if (e == 2 * r) {
+      Li[r + (int64_t)r * MAXR] = 1.0;
+    } else {
+      W[r + (int64_t)r * MAXR] = is;
+    }
+  }
 }
 
 inline int nblk(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
@@ -308,7 +421,10 @@ class Cross {
   tt_status init_sets();
   tt_status update_step(int k, int sweep, tt_kernel_decision* rec);
   tt_status build_cores(std::vector<double*>* C);
-  tt_status factor_from_rows(int k, const double* F, int ldf, const int32_t* rows);
+  tt_status init_inverses();
+  void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J) const;
+  tt_status solve_t(int k, int m, const double* Bt, int ldb, double* Xt);
+  tt_status solve_right(int k, int m, const double* F, double* C);
   tt_status sampled_error(double* err);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
@@ -324,11 +440,11 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_;
-  DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_fib_, d_tmp_, d_P_, d_err_;
-  // cached LU of P_k per k: factors, pivots, info and max |entry| of P_k
-  DBuf d_lu_[MAXD], d_lupiv_[MAXD], d_luaux_;
-  bool lu_valid_[MAXD] = {false};
+  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_, d_X_;
+  DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_;
+  // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), the
+  // border vectors of a step, max |entry| of P_k and the factors' status
+  DBuf d_li_[MAXD], d_w_[MAXD], d_bord_, d_luaux_, d_E_;
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
   HBuf h_stage_, h_res_;
@@ -523,23 +639,80 @@ tt_status Cross::init_sets() {
 }
 
 
+// Positions of the pivots (I^{<=k} as rows, I^{>k} as columns) in the
+// unfolding of super-core k: row s + i_k r_{k-1}, column i_{k+1} + t n_{k+1}.
+void Cross::pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J) const {
+  const int N = N_;
+  const int rl = rank(k - 1), rr = rank(k + 1), rk = rank(k);
+  const int nk1 = g_.n[k];
+  std::unordered_map<uint64_t, int> lpos, rpos;
+  for (int s = 0; s < rl; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
+  for (int t = 0; t < rr; ++t)
+    rpos[mkey(k + 1 < N ? &R_[k + 1][(size_t)t * (N - k - 1)] : nullptr, N - k - 1)] = t;
+  I->resize(rk);
+  J->resize(rk);
+  for (int q = 0; q < rk; ++q) {
+    const int32_t* e = &L_[k][(size_t)q * k];
+    (*I)[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * rl;
+    const int32_t* f = &R_[k][(size_t)q * (N - k)];
+    (*J)[q] = f[0] + rpos.at(mkey(f + 1, N - k - 1)) * nk1;
+  }
+}
+
+// P_k^{-1} of the initial index sets (ranks 1 or 2).
+tt_status Cross::init_inverses() {
+  TTK_TRY(d_P_.alloc(16 * sizeof(double)));
+  for (int k = 1; k < N_; ++k) {
+    const int rk = rank(k);
+    std::vector<int32_t> I, J;
+    pivot_positions(k, &I, &J);
+    arena_reset();
+    TTK_TRY(upload_sets(k - 1, k + 1, nullptr, nullptr));
+    std::vector<int32_t> hi(I);
+    hi.insert(hi.end(), J.begin(), J.end());
+    const int32_t* dI = nullptr;
+    TTK_TRY(arena_push(hi.data(), hi.size(), &dI));
+    TTK_TRY(arena_flush());
+    TTK_TRY(d_li_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
+    TTK_TRY(d_w_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
+    eval_product(ks_, super_addr(k), dI, rk, dI + rk, rk, d_P_.as<double>(), st_);
+    evals_ += (int64_t)rk * rk;
+    hipLaunchKernelGGL(k_ldu_init, dim3(1), dim3(64), 0, st_, d_P_.as<double>(), rk, d_li_[k].as<double>(),
+                       d_w_[k].as<double>(), luamax(k), luinfo(k));
+    TTK_TRY(sync());   // the arena is reused by the next k
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+// X^T = B^T P_k^{-T} = (B^T Li^T) W^T for B^T (m x r, leading dimension ldb);
+// X^T written with leading dimension m.
+tt_status Cross::solve_t(int k, int m, const double* Bt, int ldb, double* Xt) {
+  const int r = rank(k);
+  TTK_TRY(d_E_.alloc((size_t)m * r * sizeof(double)));
+  double* T = d_E_.as<double>();
+  gemm64(0, 1, m, r, r, 1.0, Bt, ldb, d_li_[k].as<double>(), MAXR, 0.0, T, m, st_);
+  gemm64(0, 1, m, r, r, 1.0, T, m, d_w_[k].as<double>(), MAXR, 0.0, Xt, m, st_);
+  return TTK_OK;
+}
+
+// C = F P_k^{-1} = (F W) Li for F (m x r, leading dimension m).
+tt_status Cross::solve_right(int k, int m, const double* F, double* C) {
+  const int r = rank(k);
+  TTK_TRY(d_E_.alloc((size_t)m * r * sizeof(double)));
+  double* T = d_E_.as<double>();
+  gemm64(0, 0, m, r, r, 1.0, F, m, d_w_[k].as<double>(), MAXR, 0.0, T, m, st_);
+  gemm64(0, 0, m, r, r, 1.0, T, m, d_li_[k].as<double>(), MAXR, 0.0, C, m, st_);
+  return TTK_OK;
+}
+
 tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const int N = N_;
   const int rl = rank(k - 1), rr = rank(k + 1), rk = rank(k);
   const int nk = g_.n[k - 1], nk1 = g_.n[k];
   const int rows = rl * nk, cols = nk1 * rr;
-  // pivot positions of I^{<=k} (rows) and I^{>k} (columns) in the unfolding
-  std::unordered_map<uint64_t, int> lpos, rpos;
-  for (int s = 0; s < rl; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
-  for (int t = 0; t < rr; ++t)
-    rpos[mkey(k + 1 < N ? &R_[k + 1][(size_t)t * (N - k - 1)] : nullptr, N - k - 1)] = t;
-  std::vector<int32_t> I(rk), J(rk);
-  for (int q = 0; q < rk; ++q) {
-    const int32_t* e = &L_[k][(size_t)q * k];
-    I[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * rl;
-    const int32_t* f = &R_[k][(size_t)q * (N - k)];
-    J[q] = f[0] + rpos.at(mkey(f + 1, N - k - 1)) * nk1;
-  }
+  std::vector<int32_t> I, J;
+  pivot_positions(k, &I, &J);
   SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)sweep, (uint64_t)k);
   const int ns = std::max(rows, cols);
   std::vector<int64_t> lin = g.floyd((int64_t)rows * cols, ns);
@@ -576,26 +749,18 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const int32_t* d_l = &dres->l;
   const int32_t* d_t = &dres->t;
   const Addr a = super_addr(k);
-  // LU of A(I, J) = P_k, reused until step k appends a pivot
-  if (!lu_valid_[k]) {
-    TTK_TRY(d_lu_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
-    TTK_TRY(d_lupiv_[k].alloc((size_t)MAXR * sizeof(int32_t)));
-    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(64), 0, st_, luamax(k));
-    eval_product(ks_, a, dI, rk, dJ, rk, d_lu_[k].as<double>(), st_, luamax(k));
-    evals_ += (int64_t)rk * rk;
-    lu_factor(d_lu_[k].as<double>(), rk, rk, d_lupiv_[k].as<int32_t>(), luinfo(k), st_);
-    lu_valid_[k] = true;
-  }
-  const double* LU = d_lu_[k].as<double>();
-  const int32_t* piv = d_lupiv_[k].as<int32_t>();
+  // P_k^{-1} = W Li, kept across steps and bordered when a pivot is added
+  TTK_TRY(d_X_.alloc((size_t)std::max(ns, std::max(cols, 1)) * rk * sizeof(double)));
+  double* X = d_X_.as<double>();
   hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(64), 0, st_, dres, (const double*)luamax(k));
   {
     const EvalSeg sg[3] = {{dsr, dJ, ns, rk, 0, AsJ}, {dI, dsc, rk, ns, 1, AIs}, {dsr, dsc, ns, 1, 2, As}};
     eval_segs(ks_, a, sg, 3, st_, &dres->s_scale);
   }
   evals_ += 2 * (int64_t)ns * rk + ns;
-  lu_solve_rm(LU, rk, rk, piv, 0, AIs, ns, ns, st_);
-  hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 256)), dim3(256), 0, st_, AsJ, (int64_t)1, (int64_t)ns, AIs,
+  // (P^{-1} A(I, samples))^T = A(I, samples)^T P^{-T}: the (q, sample) entry at sample + q ns
+  TTK_TRY(solve_t(k, ns, AIs, ns, X));
+  hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 256)), dim3(256), 0, st_, AsJ, (int64_t)1, (int64_t)ns, X,
                      (int64_t)ns, (int64_t)1, As, ns, rk, d_R_.as<double>());
   hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), ns, dsr, dsc, 0, dres);
   if (bit == 1) {   // search the row of the sample's pivot
@@ -607,8 +772,8 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
       eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
     }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    lu_solve_rm(LU, rk, rk, piv, 0, AIall, cols, cols, st_);
-    hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 256)), dim3(256), 0, st_, AlJ, (int64_t)0, (int64_t)1, AIall,
+    TTK_TRY(solve_t(k, cols, AIall, cols, X));
+    hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 256)), dim3(256), 0, st_, AlJ, (int64_t)0, (int64_t)1, X,
                        (int64_t)cols, (int64_t)1, Alall, cols, rk, d_R_.as<double>());
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), cols, dsr, dsc, 1, dres);
   } else {          // search the column
@@ -620,13 +785,28 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
       eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
     }
     evals_ += (int64_t)rows * rk + rk + rows;
-    lu_solve_rm(LU, rk, rk, piv, 0, AIt, 1, 1, st_);
+    TTK_TRY(solve_t(k, 1, AIt, 1, X));   // one right-hand side: B^T is 1 x r
     hipLaunchKernelGGL(k_resid, dim3(nblk(rows, 256)), dim3(256), 0, st_, AallJ, (int64_t)1, (int64_t)rows,
-                       AIt, (int64_t)1, (int64_t)0, Aallt, rows, rk, d_R_.as<double>());
+                       X, (int64_t)1, (int64_t)0, Aallt, rows, rk, d_R_.as<double>());
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), rows, dsr, dsc, 1, dres);
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st_, dres, bit, dI, dJ, rk,
                      std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR), (const int32_t*)luinfo(k));
+  // border the factors of P_k with the pivot's column, row and corner (the
+  // kernel does nothing unless the step added the pivot)
+  {
+    TTK_TRY(d_bord_.alloc((2 * (size_t)MAXR + 2) * sizeof(double)));
+    double* bv = d_bord_.as<double>();
+    const int32_t* prow = &dres->pivot_row;
+    const int32_t* pcol = &dres->pivot_col;
+    const EvalSeg sg[3] = {{dI, pcol, rk, 1, 0, bv}, {prow, dJ, 1, rk, 0, bv + MAXR},
+                           {prow, pcol, 1, 1, 0, bv + 2 * MAXR}};
+    eval_segs(ks_, a, sg, 3, st_, nullptr);
+    evals_ += 2 * (int64_t)rk + 1;
+    hipLaunchKernelGGL(k_border, dim3(1), dim3(1024), 0, st_, d_li_[k].as<double>(), d_w_[k].as<double>(), rk, bv,
+                       bv + MAXR, bv + 2 * MAXR, (const StepRes*)dres, luamax(k), luinfo(k));
+    hipLaunchKernelGGL(k_copy_info, dim3(1), dim3(64), 0, st_, (const int32_t*)luinfo(k), dres);
+  }
   TTK_HIP(hipGetLastError());
   TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, sizeof(StepRes), hipMemcpyDeviceToHost, st_));
   TTK_TRY(sync());
@@ -650,8 +830,7 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   if (r.s_max > 0) min_margin_ = std::min(min_margin_, r.s_margin);
   if (r.q_max > 0) min_margin_ = std::min(min_margin_, r.q_margin);
   if (r.added) {
-    lu_valid_[k] = false;   // P_k grows by a row and a column
-    const int l = r.pivot_row, t = r.pivot_col;
+    const int l = r.pivot_row, t = r.pivot_col;   // P_k^{-1} is already bordered
     const int s = l % rl, ik = l / rl;
     if (k > 1) L_[k].insert(L_[k].end(), L_[k - 1].begin() + (size_t)s * (k - 1),
                             L_[k - 1].begin() + (size_t)(s + 1) * (k - 1));
@@ -665,22 +844,8 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   return TTK_OK;
 }
 
-// Factor P_k = F[rows, :] (rows of a fibre at the positions of I^{<=k}) into the cache.
-tt_status Cross::factor_from_rows(int k, const double* F, int ldf, const int32_t* rows) {
-  const int r1 = rank(k);
-  TTK_TRY(d_lu_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
-  TTK_TRY(d_lupiv_[k].alloc((size_t)MAXR * sizeof(int32_t)));
-  hipLaunchKernelGGL(k_gather_rows, dim3(nblk(r1 * r1, 256)), dim3(256), 0, st_, F, ldf, rows, r1, r1,
-                     d_lu_[k].as<double>());
-  hipLaunchKernelGGL(k_absmax, dim3(1), dim3(1024), 0, st_, d_lu_[k].as<double>(), r1 * r1, (const double*)nullptr,
-                     0, (const double*)nullptr, 0, (const double*)nullptr, 0, (const double*)nullptr, luamax(k));
-  lu_factor(d_lu_[k].as<double>(), r1, r1, d_lupiv_[k].as<int32_t>(), luinfo(k), st_);
-  lu_valid_[k] = true;
-  return TTK_OK;
-}
-
 // Cores of the cross interpolant, column-major C_k ((r_{k-1} n_k) x r_k):
-// C_k = F_k P_k^{-1} (a solve with P_k^T through the cached LU), C_D = F_D.
+// C_k = F_k P_k^{-1} with the kept inverse, C_D = F_D.
 tt_status Cross::build_cores(std::vector<double*>* C) {
   const int N = N_;
   C->assign(N, nullptr);
@@ -694,24 +859,13 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
     double* F = d_core_[k - 1].as<double>();
     eval_product(ks_, fibre_addr(k), nullptr, m, nullptr, r1, F, st_);
     evals_ += (int64_t)m * r1;
-    (*C)[k - 1] = F;
-    if (k == N) continue;
-    if (!lu_valid_[k]) {
-      // row positions of I^{<=k} among the rows (s + i r0) of F_k
-      std::unordered_map<uint64_t, int> lpos;
-      for (int s = 0; s < r0; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
-      std::vector<int32_t> hj(r1);
-      for (int q = 0; q < r1; ++q) {
-        const int32_t* e = &L_[k][(size_t)q * k];
-        hj[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * r0;
-      }
-      const int32_t* dj = nullptr;
-      TTK_TRY(arena_push(hj.data(), (size_t)r1, &dj));
-      TTK_TRY(arena_flush());
-      TTK_TRY(factor_from_rows(k, F, m, dj));
+    if (k == N) {
+      (*C)[k - 1] = F;
+      continue;
     }
-    // (k', c) of the right-hand sides F^T sits at c + k' m: F's own layout
-    lu_solve_rm(d_lu_[k].as<double>(), r1, r1, d_lupiv_[k].as<int32_t>(), 1, F, m, m, st_);
+    TTK_TRY(d_cint_[k - 1].alloc((size_t)m * r1 * sizeof(double)));
+    TTK_TRY(solve_right(k, m, F, d_cint_[k - 1].as<double>()));
+    (*C)[k - 1] = d_cint_[k - 1].as<double>();
   }
   TTK_HIP(hipGetLastError());
   std::vector<int32_t> info(MAXD, 0);
@@ -746,6 +900,7 @@ tt_status Cross::run(CrossOut* out) {
   TTK_TRY(d_luaux_.alloc(MAXD * (sizeof(double) + sizeof(int32_t))));
   fill_zero(d_luaux_.p, MAXD * (sizeof(double) + sizeof(int32_t)), st_);
   TTK_TRY(init_sets());
+  TTK_TRY(init_inverses());
   // fixed test multi-indices of the stopping rule
   int nmax = 0;
   for (int j = 0; j < N; ++j) nmax = std::max(nmax, g_.n[j]);
@@ -784,7 +939,7 @@ tt_status Cross::run(CrossOut* out) {
     TTK_TRY(sampled_error(&err));
     if (added == 0) break;
   }
-  // the cores of the last stopping test are the result (d_core_ holds them)
+  // the cores of the last stopping test are the result (C_k in d_cint_, C_D in d_core_)
   out->ranks.assign(N + 1, 1);
   for (int k = 0; k <= N; ++k) out->ranks[k] = rank(k);
   out->cores.assign(N, {});
@@ -793,8 +948,8 @@ tt_status Cross::run(CrossOut* out) {
     const size_t cnt = (size_t)r0 * n * r1;
     // column-major C_k ((r0 n) x r1) is the little-endian core layout itself
     out->cores[k - 1].resize(cnt);
-    TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), d_core_[k - 1].p, cnt * sizeof(double),
-                           hipMemcpyDeviceToHost, st_));
+    const DBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
+    TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), src.p, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
   }
   TTK_TRY(sync());
   out->left.assign(N + 1, {});

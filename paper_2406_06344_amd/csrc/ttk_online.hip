@@ -5,7 +5,13 @@
 // q_k = T_k(t(theta)) and dq_k/dtheta = T_k'(t) dt/dtheta, with T_k' from the
 // differentiated three-term recurrence T'_{k+1} = 2 T_k + 2 t T'_k - T'_{k-1}.
 // Work is O(dt (n r^2 + r^3)) per theta, independent of N (Section 3.2).
-// Everything is accumulated in double precision and rounded once on store.
+//
+// Two grid-parallel launches: every entry of every factor H_j(theta_b) (and
+// its derivative, from the same loads of the core) gets its own thread, which
+// runs the recurrence for its theta in registers; for d_theta = 2 a second
+// launch forms the products H_1 H_2, dH_1 H_2 and H_1 dH_2, one thread per
+// entry.  Everything is accumulated in double precision and rounded once on
+// store.
 #include "ttk_internal.h"
 
 namespace ttk {
@@ -19,103 +25,76 @@ struct OnlineArgs {
   int dt;
 };
 
-// H_j(theta) (r0 x r1, column-major) or its derivative into out.
-__device__ void form_factor(const OnlineArgs& oa, int j, double th, bool deriv, double* out, double* tk) {
-  const int n = oa.n[j], r0 = oa.r0[j], r1 = oa.r1[j];
-  const double lo = oa.lo[j], hi = oa.hi[j];
-  if (threadIdx.x == 0) {
-    const double t = (2.0 * th - (lo + hi)) / (lo - hi);
-    const double dtdth = 2.0 / (lo - hi);
-    double tm = 1.0, tc = t, dm = 0.0, dc = 1.0;
-    tk[0] = deriv ? 0.0 : 1.0;
-    if (n > 1) tk[1] = deriv ? dtdth : t;
-    for (int k = 2; k < n; ++k) {
-      const double tn = 2.0 * t * tc - tm;
-      const double dn = 2.0 * tc + 2.0 * t * dc - dm;
-      tm = tc; tc = tn; dm = dc; dc = dn;
-      tk[k] = deriv ? dn * dtdth : tn;
-    }
-  }
-  __syncthreads();
-  const double* G = oa.G[j];
-  for (int e = threadIdx.x; e < r0 * r1; e += blockDim.x) {
-    const int a = e % r0, b = e / r0;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += G[a + (int64_t)k * r0 + (int64_t)b * r0 * n] * tk[k];
-    out[a + (int64_t)b * r0] = s;
-  }
-  __syncthreads();
-}
-
-// C (m x n) = A (m x k) B (k x n), column-major, whole block.
-__device__ void block_gemm(const double* A, const double* B, double* C, int m, int k, int n) {
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int i = e % m, j = e / m;
-    double s = 0.0;
-    for (int q = 0; q < k; ++q) s += A[i + (int64_t)q * m] * B[q + (int64_t)j * k];
-    C[e] = s;
-  }
-  __syncthreads();
-}
-
+// Factor entries: blockIdx.y = theta, blockIdx.z = parameter dimension j.
+// For d_theta = 1 the factor is M itself and is stored in the output type;
+// for d_theta = 2 the factors go to the double workspace.
 template <class TT, class T>
-__global__ void k_online(OnlineArgs oa, const TT* theta, int B, T* M, T* dM, double* work, size_t wstride) {
-  __shared__ double tk[MAXN];
-  double* w = work + (size_t)blockIdx.x * wstride;
-  const int rs = oa.r0[0];
-  const int rt = oa.r1[oa.dt - 1];
-  const size_t msz = (size_t)rs * rt;
-  for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    const double th0 = (double)theta[(int64_t)b * oa.dt + 0];
-    if (oa.dt == 1) {
-      double* H = w;
-      form_factor(oa, 0, th0, false, H, tk);
-      for (size_t e = threadIdx.x; e < msz; e += blockDim.x) M[b * msz + e] = (T)H[e];
-      if (dM) {
-        form_factor(oa, 0, th0, true, H, tk);
-        for (size_t e = threadIdx.x; e < msz; e += blockDim.x) dM[b * msz + e] = (T)H[e];
-      }
-      __syncthreads();
-    } else {
-      const double th1 = (double)theta[(int64_t)b * oa.dt + 1];
-      const int rm = oa.r1[0];
-      double* H1 = w;
-      double* H2 = H1 + (size_t)rs * rm;
-      double* C = H2 + (size_t)rm * rt;
-      double* E = C + msz;
-      form_factor(oa, 0, th0, false, H1, tk);
-      form_factor(oa, 1, th1, false, H2, tk);
-      block_gemm(H1, H2, C, rs, rm, rt);
-      for (size_t e = threadIdx.x; e < msz; e += blockDim.x) M[b * msz + e] = (T)C[e];
-      if (dM) {
-        form_factor(oa, 0, th0, true, E, tk);          // dH1 H2
-        block_gemm(E, H2, C, rs, rm, rt);
-        for (size_t e = threadIdx.x; e < msz; e += blockDim.x) dM[(size_t)b * 2 * msz + e] = (T)C[e];
-        form_factor(oa, 1, th1, true, E, tk);          // H1 dH2
-        block_gemm(H1, E, C, rs, rm, rt);
-        for (size_t e = threadIdx.x; e < msz; e += blockDim.x) dM[(size_t)b * 2 * msz + msz + e] = (T)C[e];
-      }
-      __syncthreads();
+__global__ void __launch_bounds__(256) k_online_factor(OnlineArgs oa, const TT* theta, T* M, T* dM, double* H,
+                                                       double* dH, size_t hstride, int want_d) {
+  const int b = blockIdx.y, j = blockIdx.z;
+  const int n = oa.n[j], r0 = oa.r0[j], r1 = oa.r1[j];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= r0 * r1) return;
+  const double th = (double)theta[(int64_t)b * oa.dt + j];
+  const double lo = oa.lo[j], hi = oa.hi[j];
+  const double t = (2.0 * th - (lo + hi)) / (lo - hi);
+  const double dtdth = 2.0 / (lo - hi);
+  const int a = e % r0, c = e / r0;
+  const double* G = oa.G[j] + a + (int64_t)c * r0 * n;
+  // T_0 = 1, T_1 = t; T'_0 = 0, T'_1 = 1
+  double tm = 1.0, tc = t, dm = 0.0, dc = 1.0;
+  double s = G[0], ds = 0.0;
+  if (n > 1) {
+    const double g1 = G[(int64_t)r0];
+    s += t * g1;
+    ds += g1;
+  }
+  for (int k = 2; k < n; ++k) {
+    const double tn = 2.0 * t * tc - tm;
+    const double dn = 2.0 * tc + 2.0 * t * dc - dm;
+    tm = tc; tc = tn; dm = dc; dc = dn;
+    const double g = G[(int64_t)k * r0];
+    s += tn * g;
+    ds += dn * g;
+  }
+  ds *= dtdth;
+  if (oa.dt == 1) {
+    const size_t msz = (size_t)r0 * r1;
+    M[(size_t)b * msz + e] = (T)s;
+    if (want_d) dM[(size_t)b * msz + e] = (T)ds;
+  } else {
+    // workspace per theta: H_1 (r0 x rm), H_2 (rm x r1), then their derivatives
+    double* hb = H + (size_t)b * hstride + (j == 0 ? 0 : (size_t)oa.r0[0] * oa.r1[0]);
+    hb[e] = s;
+    if (want_d) {
+      double* db = dH + (size_t)b * hstride + (j == 0 ? 0 : (size_t)oa.r0[0] * oa.r1[0]);
+      db[e] = ds;
     }
   }
 }
 
-// per-block workspace: H_1, H_2, the product and one derivative factor
-size_t online_stride(const ParamCore* pc, int dt) {
-  const size_t rs = pc[0].r0, rt = pc[dt - 1].r1;
-  if (dt == 1) return rs * rt;
-  const size_t rm = pc[0].r1;
-  return rs * rm + rm * rt + rs * rt + std::max(rs * rm, rm * rt);
+// d_theta = 2: blockIdx.y = theta, blockIdx.z = product (0: H1 H2 -> M,
+// 1: dH1 H2 -> dM[., 0], 2: H1 dH2 -> dM[., 1]).
+template <class T>
+__global__ void __launch_bounds__(256) k_online_product(OnlineArgs oa, const double* H, const double* dH,
+                                                        size_t hstride, T* M, T* dM) {
+  const int b = blockIdx.y, which = blockIdx.z;
+  const int rs = oa.r0[0], rm = oa.r1[0], rt = oa.r1[1];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rs * rt) return;
+  const int i = e % rs, c = e / rs;
+  const double* h1 = (which == 1 ? dH : H) + (size_t)b * hstride;
+  const double* h2 = (which == 2 ? dH : H) + (size_t)b * hstride + (size_t)rs * rm;
+  double s = 0.0;
+  for (int m = 0; m < rm; ++m) s += h1[i + (int64_t)m * rs] * h2[m + (int64_t)c * rm];
+  const size_t msz = (size_t)rs * rt;
+  if (which == 0) M[(size_t)b * msz + e] = (T)s;
+  else dM[((size_t)b * 2 + (which - 1)) * msz + e] = (T)s;
 }
 
-}  // namespace
-
-void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
-                       void* M, void* dM, double* work, hipStream_t st) {
-  if (B <= 0) return;
+OnlineArgs make_args(const ParamCore* pc, int dt) {
   OnlineArgs oa{};
   oa.dt = dt;
-  size_t wstride = 0;
   for (int j = 0; j < dt; ++j) {
     oa.G[j] = pc[j].Ghat;
     oa.r0[j] = pc[j].r0;
@@ -124,24 +103,60 @@ void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int 
     oa.lo[j] = pc[j].lo;
     oa.hi[j] = pc[j].hi;
   }
-  wstride = online_stride(pc, dt);
-  const int nblk = std::min(B, 256);
+  return oa;
+}
+
+// per-theta workspace (d_theta = 2): H_1 and H_2
+size_t online_stride(const ParamCore* pc, int dt) {
+  if (dt < 2) return 0;
+  return (size_t)pc[0].r0 * pc[0].r1 + (size_t)pc[1].r0 * pc[1].r1;
+}
+
+template <class TT, class T>
+void launch_online(const OnlineArgs& oa, const TT* theta, int B, T* M, T* dM, double* work, hipStream_t st) {
+  int maxe = 0;
+  for (int j = 0; j < oa.dt; ++j) maxe = std::max(maxe, oa.r0[j] * oa.r1[j]);
+  const size_t stride = oa.dt == 2 ? (size_t)oa.r0[0] * oa.r1[0] + (size_t)oa.r0[1] * oa.r1[1] : 0;
+  const size_t msz = (size_t)oa.r0[0] * oa.r1[oa.dt - 1];
+  double* H = work;
+  double* dH = work + stride * B;
+  const int want_d = dM != nullptr;
+  constexpr int BMAX = 65535;   // grid.y limit
+  for (int b0 = 0; b0 < B; b0 += BMAX) {
+    const int nb = std::min(BMAX, B - b0);
+    const TT* th = theta + (size_t)b0 * oa.dt;
+    T* Mb = M + (size_t)b0 * msz;
+    T* dMb = want_d ? dM + (size_t)b0 * oa.dt * msz : nullptr;
+    double* Hb = H + (size_t)b0 * stride;
+    double* dHb = dH + (size_t)b0 * stride;
+    hipLaunchKernelGGL((k_online_factor<TT, T>), dim3((maxe + 255) / 256, nb, oa.dt), dim3(256), 0, st, oa, th, Mb,
+                       dMb, Hb, dHb, stride, want_d);
+    if (oa.dt == 2) {
+      const int rs = oa.r0[0], rt = oa.r1[1];
+      hipLaunchKernelGGL(k_online_product<T>, dim3((rs * rt + 255) / 256, nb, want_d ? 3 : 1), dim3(256), 0, st, oa,
+                         Hb, dHb, stride, Mb, dMb);
+    }
+  }
+}
+
+}  // namespace
+
+void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
+                       void* M, void* dM, double* work, hipStream_t st) {
+  if (B <= 0 || dt <= 0) return;
+  const OnlineArgs oa = make_args(pc, dt);
   const bool tf = theta_dtype == TTK_FP32, of = out_dtype == TTK_FP32;
   if (tf && of)
-    hipLaunchKernelGGL((k_online<float, float>), dim3(nblk), dim3(256), 0, st, oa, static_cast<const float*>(theta),
-                       B, static_cast<float*>(M), static_cast<float*>(dM), work, wstride);
+    launch_online(oa, static_cast<const float*>(theta), B, static_cast<float*>(M), static_cast<float*>(dM), work, st);
   else if (tf)
-    hipLaunchKernelGGL((k_online<float, double>), dim3(nblk), dim3(256), 0, st, oa,
-                       static_cast<const float*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
-                       wstride);
+    launch_online(oa, static_cast<const float*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
+                  st);
   else if (of)
-    hipLaunchKernelGGL((k_online<double, float>), dim3(nblk), dim3(256), 0, st, oa,
-                       static_cast<const double*>(theta), B, static_cast<float*>(M), static_cast<float*>(dM), work,
-                       wstride);
+    launch_online(oa, static_cast<const double*>(theta), B, static_cast<float*>(M), static_cast<float*>(dM), work,
+                  st);
   else
-    hipLaunchKernelGGL((k_online<double, double>), dim3(nblk), dim3(256), 0, st, oa,
-                       static_cast<const double*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
-                       wstride);
+    launch_online(oa, static_cast<const double*>(theta), B, static_cast<double*>(M), static_cast<double*>(dM), work,
+                  st);
 }
 
 void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M, void* dM,
@@ -150,7 +165,8 @@ void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int 
 }
 
 size_t online_work_doubles(const ParamCore* pc, int dt, int B) {
-  return online_stride(pc, dt) * (size_t)std::min(std::max(B, 1), 256);
+  // H_1, H_2 and their derivatives for every theta (d_theta = 2 only)
+  return 2 * online_stride(pc, dt) * (size_t)std::max(B, 1) + 16;
 }
 
 }  // namespace ttk

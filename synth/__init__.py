@@ -43,9 +43,11 @@ WORKLOADS = {
     # Gaussian kernel, d = 2, float64 throughout.
     "se_d2_fp64": Workload("se_d2_fp64", "se", 2, [[0, 1], [0, 1]], [[2, 3], [0, 1]], [[0.5, 2.0]],
                            12, 12, 2000, 2000, 1e-8, 5, True),
-    # Matern nu = 3/2 in the length scale, d = 3, separated unit cubes.
+    # Matern nu = 3/2 in the length scale, d = 3, separated unit cubes.  The
+    # tolerance is set so that U M V^T is within 1e-5 (relative Frobenius) of
+    # dense K; the error measured against dense K is about 9 x tol.
     "matern32_d3": Workload("matern32_d3", "matern32", 3, UNIT3, [[2, 3], [0, 1], [0, 1]], [[0.5, 2.0]],
-                            16, 16, 100_000, 100_000, 1e-6, 16, False),
+                            16, 16, 100_000, 100_000, 7e-7, 16, False),
     # Symmetric PSD variant, X = Y in the unit cube, Matern (l, nu).
     "matern_global": Workload("matern_global", "matern", 3, UNIT3, UNIT3, [[0.5, 2.0], [0.5, 2.5]],
                               16, 12, 200_000, 200_000, 1e-5, 16, False, symmetric=True),

@@ -107,25 +107,31 @@ def test_batch_matches_oracle(name, dtype):
     for c, (P, out) in enumerate(ob["builds"]):
         assert inf["class_ranks"][c] == out["ranks"]
     tolr = 1e-10 if dtype == "f64" else 2e-5
-    # factor rows of every pair: the rounding's singular vectors for near-equal
-    # singular values are fixed only up to O(u / gap), so U_p and V_p alone get a
-    # looser bar; the gauge-invariant products below get the full one
-    for i, p in enumerate(ps):
-        U, V = bt.factors(i)
-        if p["n_src"]:
-            e = rel(U.double().cpu().numpy(), ob["S"][i])
-            assert e <= max(tolr, 1e-7), (i, e)
-        if p["n_tgt"]:
-            e = rel(V.double().cpu().numpy(), ob["T"][i])
-            assert e <= max(tolr, 1e-7), (i, e)
-    # apply + backward (graph path: first call captures, later calls replay)
+    # apply + backward (graph path: first call captures, later calls replay):
+    # products that do not depend on the gauge of the rounded cores
     tht = torch.tensor(th, dtype=tdt, device="cuda")
     xt = torch.tensor(xv.T.copy(), dtype=tdt, device="cuda")
     gt = torch.tensor(gv.T.copy(), dtype=tdt, device="cuda")
     Yg, dXg, dthg = bt.apply(tht, xt, G=gt)
     ey, ex, et = rel(Yg.double().cpu().numpy().T, yv), rel(dXg.double().cpu().numpy().T, dXo), \
         rel(dthg.double().cpu().numpy(), dtho)
-    say(f"  rel err y {ey:.2e} dX {ex:.2e} dtheta {et:.2e}")
+    # factor rows of every pair, up to the orthogonal gauge of the rounded
+    # cores (U -> U O with the parameter cores taking O^T), reported only.
+    # Singular vectors of nearly equal singular values, the sign rule at a near
+    # tie and the kept subspace at a truncation boundary (sigma_r close to
+    # delta) are fixed only up to O(u / gap): two correct roundings can differ
+    # there by O(1) in directions that the products weigh by about delta, so
+    # parity is asserted on the gauge-invariant products above
+    ef = 0.0
+    for i, p in enumerate(ps):
+        U, V = bt.factors(i)
+        for G_, O_, n_ in ((U, ob["S"][i], p["n_src"]), (V, ob["T"][i], p["n_tgt"])):
+            if n_ < 2:
+                continue
+            g = G_.double().cpu().numpy()
+            w, _, zt = np.linalg.svd(O_.T @ g)
+            ef = max(ef, rel(g, O_ @ (w @ zt)))
+    say(f"  rel err y {ey:.2e} dX {ex:.2e} dtheta {et:.2e}; factor rows up to gauge {ef:.2e}")
     assert ey <= tolr and ex <= tolr and et <= tolr
 
 
