@@ -84,19 +84,28 @@ __global__ void k_absmax(const double* a, int na, const double* b, int nb, const
 
 // R[i] = sum_q L(i,q) Rm(q,i) - A[i], with L(i,q) = L[i*sli + q*slq] and
 // Rm(q,i) = Rm[q*srq + i*sri] (a zero stride broadcasts).
-__global__ void k_resid(const double* L, int64_t sli, int64_t slq, const double* Rm, int64_t srq,
-                        int64_t sri, const double* A, int n, int r, double* out) {
+__global__ void __launch_bounds__(64) k_resid(const double* L, int64_t sli, int64_t slq, const double* Rm,
+                                              int64_t srq, int64_t sri, const double* A, int n, int r, double* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = 0.0;
-  for (int q = 0; q < r; ++q) s += L[i * sli + q * slq] * Rm[q * srq + i * sri];
-  out[i] = s - A[i];
+  const double* lp = L + i * sli;
+  const double* rp = Rm + i * sri;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = 0;
+  for (; q + 3 < r; q += 4) {
+    s0 += lp[q * slq] * rp[q * srq];
+    s1 += lp[(q + 1) * slq] * rp[(q + 1) * srq];
+    s2 += lp[(q + 2) * slq] * rp[(q + 2) * srq];
+    s3 += lp[(q + 3) * slq] * rp[(q + 3) * srq];
+  }
+  for (; q < r; ++q) s0 += lp[q * slq] * rp[q * srq];
+  out[i] = ((s0 + s1) + (s2 + s3)) - A[i];
 }
 
 // Robust argmax of |R| (lowest index within tau of the max) and the
 // relative top-2 margin; stage 0 = sample stage (also records row/col of the
 // chosen sample), stage 1 = search stage.
-__global__ void k_select(const double* R, int n, const int32_t* srow, const int32_t* scol, int stage,
+__global__ void k_select(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
                          StepRes* res) {
   __shared__ double sv[1024];
   __shared__ int si[1024];
@@ -113,16 +122,24 @@ __global__ void k_select(const double* R, int n, const int32_t* srow, const int3
   }
   const double mx = sv[0];
   __syncthreads();
-  int pos = 0x7fffffff;
+  // lowest linear position among the candidates in the band: the sample list
+  // (stage 0) is in generation order, so its key is row * cols + col; the
+  // searched fibre (stage 1) is in natural order
+  int best = 0x7fffffff, bi = 0x7fffffff;
   for (int i = tid; i < n; i += blockDim.x)
-    if (fabs(R[i]) >= mx - tau) { pos = i; break; }
-  si[tid] = pos;
+    if (fabs(R[i]) >= mx - tau) {
+      const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
+      if (key < best) { best = key; bi = i; }
+    }
+  sv[tid] = (double)best;
+  si[tid] = bi;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) si[tid] = min(si[tid], si[tid + s]);
+    if (tid < s && sv[tid + s] < sv[tid]) { sv[tid] = sv[tid + s]; si[tid] = si[tid + s]; }
     __syncthreads();
   }
-  const int p = si[0];
+  // (no candidate compares, e.g. all residuals NaN: fall back to the first)
+  const int p = si[0] < n ? si[0] : 0;
   __syncthreads();
   double sec = 0.0;
   for (int i = tid; i < n; i += blockDim.x)
@@ -146,18 +163,19 @@ __global__ void k_select(const double* R, int n, const int32_t* srow, const int3
   }
 }
 
-__global__ void k_finalize(StepRes* res, int bit, const int32_t* I, const int32_t* J, int rk,
-                           int max_rank, const int32_t* info) {
-  // (info: status of the kept inverse of A(I, J); non-zero after a singular border)
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(64) k_finalize(StepRes* res, int bit, const int32_t* I, const int32_t* J, int rk,
+                                                 int max_rank, const int32_t* info) {
+  // (info: status of the kept factors of A(I, J); non-zero after a singular border)
   const int row = bit ? res->l : res->q_pos;
   const int col = bit ? res->q_pos : res->t;
+  int stale = 0;
+  for (int q = threadIdx.x; q < rk; q += 64)
+    if (I[q] == row || J[q] == col) stale = 1;
+  stale = __any(stale);
+  if (threadIdx.x != 0) return;
   res->pivot_row = row;
   res->pivot_col = col;
-  bool fresh = true;
-  for (int q = 0; q < rk; ++q)
-    if (I[q] == row || J[q] == col) fresh = false;
-  res->added = (res->pivot_abs > res->q_tau && fresh && rk < max_rank) ? 1 : 0;
+  res->added = (res->pivot_abs > res->q_tau && !stale && rk < max_rank) ? 1 : 0;
   res->info = *info;
 }
 
@@ -285,10 +303,6 @@ __global__ void k_err_max(const double* a, const double* b, int n, double* out) 
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_copy_info(const int32_t* info, StepRes* res) {
-  if (threadIdx.x == 0 && *info) res->info = *info;
-}
-
 __global__ void k_set_scale(StepRes* res, const double* base) {
   if (threadIdx.x == 0) { res->s_scale = *base; res->q_scale = 0.0; }
 }
@@ -334,7 +348,7 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
 // Border the factors (r x r, leading dimension MAXR) with the pivot's
 // column b = P(I, t), row c = P(l, J) and corner d, when the step added it.
 __global__ void __launch_bounds__(1024) k_border(double* Li, double* W, int r, const double* b, const double* c,
-                                                 const double* d, const StepRes* res, double* amax, int32_t* info) {
+                                                 const double* d, StepRes* res, double* amax, int32_t* info) {
   __shared__ double u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR];
   __shared__ double s_s;
   if (!res->added) return;
@@ -360,7 +374,10 @@ __global__ void __launch_bounds__(1024) k_border(double* Li, double* W, int r, c
     }
     s_s = *d - gu;
     *amax = fmax(m, fabs(*d));
-    if (!(s_s != 0.0) || !isfinite(s_s)) *info = 1;
+    if (!(s_s != 0.0) || !isfinite(s_s)) {
+      *info = 1;
+      res->info = 1;
+    }
   }
   __syncthreads();
   const double is = 1.0 / s_s;
@@ -422,7 +439,8 @@ class Cross {
   tt_status update_step(int k, int sweep, tt_kernel_decision* rec);
   tt_status build_cores(std::vector<double*>* C);
   tt_status init_inverses();
-  void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J) const;
+  void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
+  std::vector<int32_t> pls_[MAXD], pli_[MAXD], prf_[MAXD], prt_[MAXD];   // pivot (s, i_k), (i_{k+1}, t)
   tt_status solve_t(int k, int m, const double* Bt, int ldb, double* Xt);
   tt_status solve_right(int k, int m, const double* F, double* C);
   tt_status sampled_error(double* err);
@@ -641,21 +659,36 @@ tt_status Cross::init_sets() {
 
 // Positions of the pivots (I^{<=k} as rows, I^{>k} as columns) in the
 // unfolding of super-core k: row s + i_k r_{k-1}, column i_{k+1} + t n_{k+1}.
-void Cross::pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J) const {
+// Each pivot of core k is kept as (s, i_k) and (i_{k+1}, t) with s its row in
+// I^{<=k-1} and t its row in I^{>k+1}; both sets only grow at the end, so the
+// pairs stay valid and only the multipliers r_{k-1}, n_{k+1} enter the positions.
+void Cross::pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J) {
   const int N = N_;
   const int rl = rank(k - 1), rr = rank(k + 1), rk = rank(k);
   const int nk1 = g_.n[k];
-  std::unordered_map<uint64_t, int> lpos, rpos;
-  for (int s = 0; s < rl; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
-  for (int t = 0; t < rr; ++t)
-    rpos[mkey(k + 1 < N ? &R_[k + 1][(size_t)t * (N - k - 1)] : nullptr, N - k - 1)] = t;
+  if ((int)pls_[k].size() != rk) {   // first use: look the pivots up in the neighbouring sets
+    std::unordered_map<uint64_t, int> lpos, rpos;
+    for (int s = 0; s < rl; ++s) lpos[mkey(k > 1 ? &L_[k - 1][(size_t)s * (k - 1)] : nullptr, k - 1)] = s;
+    for (int t = 0; t < rr; ++t)
+      rpos[mkey(k + 1 < N ? &R_[k + 1][(size_t)t * (N - k - 1)] : nullptr, N - k - 1)] = t;
+    pls_[k].resize(rk);
+    pli_[k].resize(rk);
+    prf_[k].resize(rk);
+    prt_[k].resize(rk);
+    for (int q = 0; q < rk; ++q) {
+      const int32_t* e = &L_[k][(size_t)q * k];
+      pls_[k][q] = lpos.at(mkey(e, k - 1));
+      pli_[k][q] = e[k - 1];
+      const int32_t* f = &R_[k][(size_t)q * (N - k)];
+      prf_[k][q] = f[0];
+      prt_[k][q] = rpos.at(mkey(f + 1, N - k - 1));
+    }
+  }
   I->resize(rk);
   J->resize(rk);
   for (int q = 0; q < rk; ++q) {
-    const int32_t* e = &L_[k][(size_t)q * k];
-    (*I)[q] = lpos.at(mkey(e, k - 1)) + e[k - 1] * rl;
-    const int32_t* f = &R_[k][(size_t)q * (N - k)];
-    (*J)[q] = f[0] + rpos.at(mkey(f + 1, N - k - 1)) * nk1;
+    (*I)[q] = pls_[k][q] + pli_[k][q] * rl;
+    (*J)[q] = prf_[k][q] + prt_[k][q] * nk1;
   }
 }
 
@@ -715,7 +748,8 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   pivot_positions(k, &I, &J);
   SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)sweep, (uint64_t)k);
   const int ns = std::max(rows, cols);
-  std::vector<int64_t> lin = g.floyd((int64_t)rows * cols, ns);
+  // samples in generation order; the device breaks ties by linear position
+  std::vector<int64_t> lin = g.floyd_unsorted((int64_t)rows * cols, ns);
   const int bit = g.bit();
   // upload the neighbouring sets and the integer lists in one copy
   arena_reset();
@@ -760,9 +794,9 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   evals_ += 2 * (int64_t)ns * rk + ns;
   // (P^{-1} A(I, samples))^T = A(I, samples)^T P^{-T}: the (q, sample) entry at sample + q ns
   TTK_TRY(solve_t(k, ns, AIs, ns, X));
-  hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 256)), dim3(256), 0, st_, AsJ, (int64_t)1, (int64_t)ns, X,
+  hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 64)), dim3(64), 0, st_, AsJ, (int64_t)1, (int64_t)ns, X,
                      (int64_t)ns, (int64_t)1, As, ns, rk, d_R_.as<double>());
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), ns, dsr, dsc, 0, dres);
+  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), ns, dsr, dsc, cols, 0, dres);
   if (bit == 1) {   // search the row of the sample's pivot
     double* AlJ = S0;
     double* AIall = AlJ + rk;                   // (q, c) at c + q cols
@@ -773,9 +807,9 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
     }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
     TTK_TRY(solve_t(k, cols, AIall, cols, X));
-    hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 256)), dim3(256), 0, st_, AlJ, (int64_t)0, (int64_t)1, X,
+    hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 64)), dim3(64), 0, st_, AlJ, (int64_t)0, (int64_t)1, X,
                        (int64_t)cols, (int64_t)1, Alall, cols, rk, d_R_.as<double>());
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), cols, dsr, dsc, 1, dres);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), cols, dsr, dsc, cols, 1, dres);
   } else {          // search the column
     double* AallJ = S0;
     double* AIt = AallJ + (size_t)rows * rk;
@@ -786,9 +820,9 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
     }
     evals_ += (int64_t)rows * rk + rk + rows;
     TTK_TRY(solve_t(k, 1, AIt, 1, X));   // one right-hand side: B^T is 1 x r
-    hipLaunchKernelGGL(k_resid, dim3(nblk(rows, 256)), dim3(256), 0, st_, AallJ, (int64_t)1, (int64_t)rows,
+    hipLaunchKernelGGL(k_resid, dim3(nblk(rows, 64)), dim3(64), 0, st_, AallJ, (int64_t)1, (int64_t)rows,
                        X, (int64_t)1, (int64_t)0, Aallt, rows, rk, d_R_.as<double>());
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), rows, dsr, dsc, 1, dres);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), rows, dsr, dsc, cols, 1, dres);
   }
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st_, dres, bit, dI, dJ, rk,
                      std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR), (const int32_t*)luinfo(k));
@@ -804,8 +838,7 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
     eval_segs(ks_, a, sg, 3, st_, nullptr);
     evals_ += 2 * (int64_t)rk + 1;
     hipLaunchKernelGGL(k_border, dim3(1), dim3(1024), 0, st_, d_li_[k].as<double>(), d_w_[k].as<double>(), rk, bv,
-                       bv + MAXR, bv + 2 * MAXR, (const StepRes*)dres, luamax(k), luinfo(k));
-    hipLaunchKernelGGL(k_copy_info, dim3(1), dim3(64), 0, st_, (const int32_t*)luinfo(k), dres);
+                       bv + MAXR, bv + 2 * MAXR, dres, luamax(k), luinfo(k));
   }
   TTK_HIP(hipGetLastError());
   TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, sizeof(StepRes), hipMemcpyDeviceToHost, st_));
@@ -830,8 +863,12 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   if (r.s_max > 0) min_margin_ = std::min(min_margin_, r.s_margin);
   if (r.q_max > 0) min_margin_ = std::min(min_margin_, r.q_margin);
   if (r.added) {
-    const int l = r.pivot_row, t = r.pivot_col;   // P_k^{-1} is already bordered
+    const int l = r.pivot_row, t = r.pivot_col;   // the factors of P_k are already bordered
     const int s = l % rl, ik = l / rl;
+    pls_[k].push_back(s);
+    pli_[k].push_back(ik);
+    prf_[k].push_back(t % nk1);
+    prt_[k].push_back(t / nk1);
     if (k > 1) L_[k].insert(L_[k].end(), L_[k - 1].begin() + (size_t)s * (k - 1),
                             L_[k - 1].begin() + (size_t)(s + 1) * (k - 1));
     L_[k].push_back(ik);

@@ -5,12 +5,12 @@
 //             z = (z ^ (z >> 27)) * 0x94D049BB133111EB;  return z ^ (z >> 31)
 //   key:      s = seed; for each part p: s = mix((s ^ p) + 0x9E3779B97F4A7C15)
 //   below(m): high 64 bits of next() * m;  bit(): top bit of next()
-//   floyd(M, k): k distinct values of [0, M) (Floyd's algorithm), sorted.
+//   floyd(M, k): k distinct values of [0, M) (Floyd's algorithm), sorted
+//   (floyd_unsorted: the same values in generation order).
 #pragma once
 
 #include <algorithm>
 #include <cstdint>
-#include <unordered_set>
 #include <vector>
 
 namespace ttk {
@@ -38,14 +38,32 @@ class SplitMix64 {
   }
   int bit() { return static_cast<int>(next() >> 63); }
   std::vector<int64_t> floyd(int64_t M, int64_t k) {
-    std::unordered_set<int64_t> chosen;
-    chosen.reserve(static_cast<size_t>(k) * 2);
+    std::vector<int64_t> out = floyd_unsorted(M, k);
+    std::sort(out.begin(), out.end());
+    return out;
+  }
+  // The same k values in the order Floyd's algorithm produces them.
+  std::vector<int64_t> floyd_unsorted(int64_t M, int64_t k) {
+    // membership in an open-addressing table (linear probing, load <= 1/4)
+    size_t cap = 16;
+    while (cap < static_cast<size_t>(k) * 4) cap <<= 1;
+    std::vector<int64_t> table(cap, -1);
+    const int shift = 64 - __builtin_ctzll(cap);
+    auto insert = [&](int64_t v) {   // true if v was not present
+      size_t h = static_cast<size_t>((static_cast<uint64_t>(v) * kGolden) >> shift);
+      while (true) {
+        if (table[h] == v) return false;
+        if (table[h] < 0) { table[h] = v; return true; }
+        h = (h + 1) & (cap - 1);
+      }
+    };
+    std::vector<int64_t> out;
+    out.reserve(static_cast<size_t>(k));
     for (int64_t j = M - k; j < M; ++j) {
       const int64_t t = static_cast<int64_t>(below(static_cast<uint64_t>(j + 1)));
-      if (!chosen.insert(t).second) chosen.insert(j);
+      if (insert(t)) out.push_back(t);
+      else { insert(j); out.push_back(j); }
     }
-    std::vector<int64_t> out(chosen.begin(), chosen.end());
-    std::sort(out.begin(), out.end());
     return out;
   }
 
