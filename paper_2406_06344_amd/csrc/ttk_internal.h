@@ -138,6 +138,9 @@ size_t qr_blocked_work(int m, int n);
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);
+// Same without the right vectors (A <- U Sigma normalised to U, sigma); false
+// (nothing launched) when A does not fit the workgroup's LDS.
+bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st);
 // count independent SVDs, one workgroup each; matrix b at A + b sA, V + b sV,
 // sigma (and its workspace) at sigma + b sS, sS >= jacobi_sigma_doubles(n).
 void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,

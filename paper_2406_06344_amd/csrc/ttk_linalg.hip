@@ -575,68 +575,11 @@ __global__ void k_zero_rows(double* A, int rows, int cols, int lda) {
   A[e % rows + (size_t)(e / rows) * lda] = 0.0;
 }
 
-// ------------------------------------------------------------ Jacobi SVD
-// One-sided (Hestenes) Jacobi on the columns of A (n x n): A V = U Sigma.
-// Pairs follow a round-robin tournament so each round's rotations are
-// disjoint; one wave per pair.
-__global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double* V, int ldv,
-                                               double* sigma, size_t sA, size_t sV, size_t sS) {
-  __shared__ int rotated;
-  // one matrix per workgroup: A, V, sigma (+ its workspace) offset by the batch index
-  A += blockIdx.x * sA;
-  V += blockIdx.x * sV;
-  sigma += blockIdx.x * sS;
-  double* work = sigma + n;
-  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
+// Singular values (column norms), normalised left vectors, columns sorted
+// by decreasing sigma (stable in the column index); whole workgroup.
+__device__ void jacobi_finish(double* A, int n, int lda, double* V, int ldv, double* sigma, double* work,
+                              int32_t* order) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < n * n; e += BS) V[e % n + (size_t)(e / n) * ldv] = (e % n == e / n) ? 1.0 : 0.0;
-  const int np = (n + 1) & ~1;    // players, one dummy when n is odd
-  __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int pr = w; pr < np / 2; pr += NW) {
-        // circle method: player 0 fixed, others rotate
-        int p = (pr == 0) ? 0 : 1 + (pr - 1 + rnd) % (np - 1);
-        int q = 1 + (np - 2 - pr + rnd) % (np - 1);
-        if (p > q) { const int t = p; p = q; q = t; }
-        if (q >= n || p == q) continue;
-        double* ap = A + (size_t)p * lda;
-        double* aq = A + (size_t)q * lda;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < n; i += 64) {
-          al += ap[i] * ap[i];
-          be += aq[i] * aq[i];
-          ga += ap[i] * aq[i];
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < n; i += 64) {
-          const double x = ap[i], y = aq[i];
-          ap[i] = c * x - s * y;
-          aq[i] = s * x + c * y;
-        }
-        double* vp = V + (size_t)p * ldv;
-        double* vq = V + (size_t)q * ldv;
-        for (int i = lane; i < n; i += 64) {
-          const double x = vp[i], y = vq[i];
-          vp[i] = c * x - s * y;
-          vq[i] = s * x + c * y;
-        }
-        if (lane == 0) rotated = 1;
-      }
-      __syncthreads();
-    }
-    if (!rotated) break;
-    __syncthreads();
-  }
-  // singular values, normalised left vectors
   for (int c = w; c < n; c += NW) {
     double* ac = A + (size_t)c * lda;
     double s = 0.0;
@@ -663,12 +606,189 @@ __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double
   __syncthreads();
   for (int e = tid; e < n * n; e += BS) A[e % n + (size_t)(e / n) * lda] = tmp[e];
   __syncthreads();
-  for (int e = tid; e < n * n; e += BS) tmp[e] = V[e % n + (size_t)order[e / n] * ldv];
-  __syncthreads();
-  for (int e = tid; e < n * n; e += BS) V[e % n + (size_t)(e / n) * ldv] = tmp[e];
+  if (V) {
+    for (int e = tid; e < n * n; e += BS) tmp[e] = V[e % n + (size_t)order[e / n] * ldv];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += BS) V[e % n + (size_t)(e / n) * ldv] = tmp[e];
+  }
   for (int c = tid; c < n; c += BS) tmp[n * n + c] = sigma[order[c]];
   __syncthreads();
   for (int c = tid; c < n; c += BS) sigma[c] = tmp[n * n + c];
+}
+
+// ------------------------------------------------------------ Jacobi SVD
+// One-sided (Hestenes) Jacobi on the columns of A (n x n): A V = U Sigma.
+// Pairs follow a round-robin tournament so each round's rotations are
+// disjoint; one wave per pair.
+__global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double* V, int ldv,
+                                               double* sigma, size_t sA, size_t sV, size_t sS) {
+  __shared__ int rotated;
+  // one matrix per workgroup: A, V, sigma (+ its workspace) offset by the batch index
+  A += blockIdx.x * sA;
+  V += blockIdx.x * sV;
+  sigma += blockIdx.x * sS;
+  double* work = sigma + n;
+  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < n * n; e += BS) V[e % n + (size_t)(e / n) * ldv] = (e % n == e / n) ? 1.0 : 0.0;
+  const int np = (n + 1) & ~1;    // players, one dummy when n is odd
+  // ||A||_F^2 (invariant under the rotations): pairs whose inner product is
+  // below eps^2 of it are converged whatever their own norms, so columns at
+  // rounding-noise level stop rotating among themselves
+  __shared__ double red_nf[NW];
+  double nf = 0.0;
+  for (int e = tid; e < n * n; e += BS) {
+    const double a = A[e % n + (size_t)(e / n) * lda];
+    nf += a * a;
+  }
+  const double gfloor = 1e-30 * block_sum(nf, red_nf);
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < np - 1; ++rnd) {
+      for (int pr = w; pr < np / 2; pr += NW) {
+        // circle method: player 0 fixed, others rotate
+        int p = (pr == 0) ? 0 : 1 + (pr - 1 + rnd) % (np - 1);
+        int q = 1 + (np - 2 - pr + rnd) % (np - 1);
+        if (p > q) { const int t = p; p = q; q = t; }
+        if (q >= n || p == q) continue;
+        double* ap = A + (size_t)p * lda;
+        double* aq = A + (size_t)q * lda;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < n; i += 64) {
+          al += ap[i] * ap[i];
+          be += aq[i] * aq[i];
+          ga += ap[i] * aq[i];
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (fabs(ga) <= 1e-15 * sqrt(al * be) || fabs(ga) <= gfloor || ga == 0.0) continue;
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = lane; i < n; i += 64) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = c * x - s * y;
+          aq[i] = s * x + c * y;
+        }
+        double* vp = V + (size_t)p * ldv;
+        double* vq = V + (size_t)q * ldv;
+        for (int i = lane; i < n; i += 64) {
+          const double x = vp[i], y = vq[i];
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  jacobi_finish(A, n, lda, V, ldv, sigma, work, order);
+}
+
+// The same iteration with A in LDS: each round first rotates the column
+// pairs of A in LDS (one wave per pair) and records the rotations, then all
+// threads apply them to V in global memory in one parallel pass, so a round
+// costs one global round trip instead of one per pair.  The rotations, their
+// order and their arithmetic are those of k_jacobi.
+__global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, double* V, int ldv, double* sigma,
+                                                   int want_v) {
+  extern __shared__ double smj[];
+  __shared__ int rotated;
+  double* A = smj;                                  // n x n, leading dimension n
+  const int np = (n + 1) & ~1;
+  double* rc = A + (size_t)n * n;                   // np/2 cosines
+  double* rs = rc + np / 2;                         // np/2 sines
+  int* rp = reinterpret_cast<int*>(rs + np / 2);    // np/2 column pairs (p, q), p = -1: none
+  int* rq = rp + np / 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ double red_nf[NW];
+  double nf = 0.0;
+  for (int e = tid; e < n * n; e += BS) {
+    const double a = Ag[e % n + (size_t)(e / n) * lda];
+    A[e] = a;
+    nf += a * a;
+    if (want_v) V[e % n + (size_t)(e / n) * ldv] = (e % n == e / n) ? 1.0 : 0.0;
+  }
+  const double gfloor = 1e-30 * block_sum(nf, red_nf);   // as in k_jacobi
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    // a column pair per group of 16 lanes (64 groups): a whole round of
+    // disjoint pairs runs at once, with 16-lane reductions
+    const int grp = tid >> 4, gl = tid & 15;
+    for (int rnd = 0; rnd < np - 1; ++rnd) {
+      for (int pr = grp; pr < np / 2; pr += BS / 16) {
+        int p = (pr == 0) ? 0 : 1 + (pr - 1 + rnd) % (np - 1);
+        int q = 1 + (np - 2 - pr + rnd) % (np - 1);
+        if (p > q) { const int t = p; p = q; q = t; }
+        int keep = 0;
+        double c = 1.0, sn = 0.0;
+        if (q < n && p != q) {
+          double* ap = A + (size_t)p * n;
+          double* aq = A + (size_t)q * n;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = gl; i < n; i += 16) {
+            al += ap[i] * ap[i];
+            be += aq[i] * aq[i];
+            ga += ap[i] * aq[i];
+          }
+          for (int o = 8; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o, 16);
+            be += __shfl_xor(be, o, 16);
+            ga += __shfl_xor(ga, o, 16);
+          }
+          if (!(fabs(ga) <= 1e-15 * sqrt(al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = c * t;
+            for (int i = gl; i < n; i += 16) {
+              const double x = ap[i], y = aq[i];
+              ap[i] = c * x - sn * y;
+              aq[i] = sn * x + c * y;
+            }
+            keep = 1;
+            if (gl == 0) rotated = 1;
+          }
+        }
+        if (gl == 0) {
+          rp[pr] = keep ? p : -1;
+          rq[pr] = q;
+          rc[pr] = c;
+          rs[pr] = sn;
+        }
+      }
+      __syncthreads();
+      // V <- V G for this round's rotations (disjoint column pairs)
+      const int npairs = want_v ? np / 2 : 0;
+      for (int e = tid; e < npairs * n; e += BS) {
+        const int pr = e / n, i = e % n;
+        const int p = rp[pr];
+        if (p < 0) continue;
+        const int q = rq[pr];
+        const double c = rc[pr], sn = rs[pr];
+        double* vp = V + (size_t)p * ldv + i;
+        double* vq = V + (size_t)q * ldv + i;
+        const double x = *vp, y = *vq;
+        *vp = c * x - sn * y;
+        *vq = sn * x + c * y;
+      }
+      if (want_v) __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += BS) Ag[e % n + (size_t)(e / n) * lda] = A[e];
+  __syncthreads();
+  double* work = sigma + n;
+  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
+  jacobi_finish(Ag, n, lda, want_v ? V : nullptr, ldv, sigma, work, order);
 }
 
 // ----------------------------------------------------------------- GEMM
@@ -832,10 +952,47 @@ size_t qr_blocked_work(int m, int n) {
   return (size_t)n + (size_t)NB * m + (size_t)NB * NB * ((n + NB - 1) / NB) + 2 * (size_t)NB * n + 64;
 }
 
+namespace {
+
+// Launch the LDS form of the Jacobi SVD if the matrix fits; false if it does not.
+bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 64 * 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      lds_limit = v;
+    else
+      lds_limit = 64 * 1024;
+    (void)hipGetLastError();
+  }
+  const int np = (n + 1) & ~1;
+  const size_t sh = (size_t)n * n * sizeof(double) + (size_t)(np / 2) * (2 * sizeof(double) + 2 * sizeof(int));
+  if (n >= 2 && sh + 64 <= (size_t)lds_limit) {
+    bool ok = true;
+    if (sh > 48 * 1024)
+      ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sh) == hipSuccess;
+    if (ok) {
+      hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(BS), sh, st, A, n, lda, V, ldv, sigma, V ? 1 : 0);
+      if (hipGetLastError() == hipSuccess) return true;
+    }
+    (void)hipGetLastError();
+  }
+  return false;
+}
+
+}  // namespace
+
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {
   // work: n*n + n doubles followed by n int32 (caller-sized through sigma's buffer)
+  if (jacobi_lds_launch(A, n, lda, V, ldv, sigma, st)) return;
   hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(BS), 0, st, A, n, lda, V, ldv, sigma, (size_t)0, (size_t)0,
                      (size_t)0);
+}
+
+bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
+  return jacobi_lds_launch(A, n, lda, nullptr, 0, sigma, st);
 }
 
 void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,

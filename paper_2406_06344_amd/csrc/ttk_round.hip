@@ -151,7 +151,11 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     TTK_HIP(hipMemcpy2DAsync(A.p, (size_t)ma * sizeof(double), c.g[i].p, (size_t)m * sizeof(double),
                              (size_t)m * sizeof(double), (size_t)r1, hipMemcpyDeviceToDevice, st));
     TTK_TRY(qr_blocked(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
-    jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
+    // SVD of R.  Sigma V^T, pushed into the next core, is U^T R: with a copy of R
+    // kept, only the left vectors are needed (V stays unaccumulated)
+    TTK_HIP(hipMemcpyAsync(V.p, R.p, (size_t)r1 * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const bool left_only = jacobi_svd_left(R.as<double>(), r1, r1, sig.as<double>(), st);
+    if (!left_only) jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
     hs.resize(r1);
     TTK_HIP(hipMemcpyAsync(hs.data(), sig.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
     TTK_HIP(hipStreamSynchronize(st));
@@ -168,8 +172,11 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     // G_{i+1}^{1} <- (Sigma V^T)[:rp, :] G_{i+1}^{1}
     const int n2 = c.n[i + 1], r2 = c.r[i + 2];
     TTK_TRY(W.alloc((size_t)rp * r1 * sizeof(double)));
-    hipLaunchKernelGGL(k_sigma_vt, dim3(nb((int64_t)rp * r1)), dim3(256), 0, st, sig.as<double>(), V.as<double>(),
-                       r1, rp, W.as<double>());
+    if (left_only)   // (Sigma V^T)[:rp, :] = U[:, :rp]^T R, R's copy in V
+      gemm64(1, 0, rp, r1, r1, 1.0, R.as<double>(), r1, V.as<double>(), r1, 0.0, W.as<double>(), rp, st);
+    else
+      hipLaunchKernelGGL(k_sigma_vt, dim3(nb((int64_t)rp * r1)), dim3(256), 0, st, sig.as<double>(),
+                         V.as<double>(), r1, rp, W.as<double>());
     TTK_TRY(T.alloc((size_t)rp * n2 * r2 * sizeof(double)));
     gemm64(0, 0, rp, n2 * r2, r1, 1.0, W.as<double>(), rp, c.g[i + 1].as<double>(), r1, 0.0, T.as<double>(), rp,
            st);
