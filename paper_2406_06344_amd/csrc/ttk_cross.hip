@@ -41,6 +41,7 @@
 #include <cstring>
 #include <unordered_map>
 
+#include "ttk_eval_dev.h"
 #include "ttk_internal.h"
 #include "ttk_rng.h"
 
@@ -57,6 +58,7 @@ struct StepRes {
   double s_max, s_margin, s_scale, s_tau;
   double q_max, q_margin, q_scale, q_tau;
   double pivot_abs, pad;
+  int32_t ctr, pad2;   // blocks done in the current residual launch (reset by the last)
 };
 
 __device__ inline double wsum(double v) {
@@ -80,103 +82,6 @@ __global__ void k_absmax(const double* a, int na, const double* b, int nb, const
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = base ? fmax(*base, red[0]) : red[0];
-}
-
-// R[i] = sum_q L(i,q) Rm(q,i) - A[i], with L(i,q) = L[i*sli + q*slq] and
-// Rm(q,i) = Rm[q*srq + i*sri] (a zero stride broadcasts).
-__global__ void __launch_bounds__(64) k_resid(const double* L, int64_t sli, int64_t slq, const double* Rm,
-                                              int64_t srq, int64_t sri, const double* A, int n, int r, double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double* lp = L + i * sli;
-  const double* rp = Rm + i * sri;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int q = 0;
-  for (; q + 3 < r; q += 4) {
-    s0 += lp[q * slq] * rp[q * srq];
-    s1 += lp[(q + 1) * slq] * rp[(q + 1) * srq];
-    s2 += lp[(q + 2) * slq] * rp[(q + 2) * srq];
-    s3 += lp[(q + 3) * slq] * rp[(q + 3) * srq];
-  }
-  for (; q < r; ++q) s0 += lp[q * slq] * rp[q * srq];
-  out[i] = ((s0 + s1) + (s2 + s3)) - A[i];
-}
-
-// Robust argmax of |R| (lowest index within tau of the max) and the
-// relative top-2 margin; stage 0 = sample stage (also records row/col of the
-// chosen sample), stage 1 = search stage.
-__global__ void k_select(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
-                         StepRes* res) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const int tid = threadIdx.x;
-  const double scale = stage == 0 ? res->s_scale : res->q_scale;
-  const double tau = TIE_REL * scale;
-  double m = -1.0;
-  for (int i = tid; i < n; i += blockDim.x) m = fmax(m, fabs(R[i]));
-  sv[tid] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
-    __syncthreads();
-  }
-  const double mx = sv[0];
-  __syncthreads();
-  // lowest linear position among the candidates in the band: the sample list
-  // (stage 0) is in generation order, so its key is row * cols + col; the
-  // searched fibre (stage 1) is in natural order
-  int best = 0x7fffffff, bi = 0x7fffffff;
-  for (int i = tid; i < n; i += blockDim.x)
-    if (fabs(R[i]) >= mx - tau) {
-      const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
-      if (key < best) { best = key; bi = i; }
-    }
-  sv[tid] = (double)best;
-  si[tid] = bi;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s && sv[tid + s] < sv[tid]) { sv[tid] = sv[tid + s]; si[tid] = si[tid + s]; }
-    __syncthreads();
-  }
-  // (no candidate compares, e.g. all residuals NaN: fall back to the first)
-  const int p = si[0] < n ? si[0] : 0;
-  __syncthreads();
-  double sec = 0.0;
-  for (int i = tid; i < n; i += blockDim.x)
-    if (i != p) sec = fmax(sec, fabs(R[i]));
-  sv[tid] = sec;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double margin = mx > 0.0 ? (mx - sv[0]) / mx : 0.0;
-    if (stage == 0) {
-      res->s_pos = p; res->s_max = mx; res->s_margin = margin; res->s_tau = tau;
-      res->l = srow[p]; res->t = scol[p];
-      res->q_scale = res->s_scale;      // the search stage widens this scale
-    } else {
-      res->q_pos = p; res->q_max = mx; res->q_margin = margin; res->q_tau = tau;
-      res->pivot_abs = fabs(R[p]);
-    }
-  }
-}
-
-__global__ void __launch_bounds__(64) k_finalize(StepRes* res, int bit, const int32_t* I, const int32_t* J, int rk,
-                                                 int max_rank, const int32_t* info) {
-  // (info: status of the kept factors of A(I, J); non-zero after a singular border)
-  const int row = bit ? res->l : res->q_pos;
-  const int col = bit ? res->q_pos : res->t;
-  int stale = 0;
-  for (int q = threadIdx.x; q < rk; q += 64)
-    if (I[q] == row || J[q] == col) stale = 1;
-  stale = __any(stale);
-  if (threadIdx.x != 0) return;
-  res->pivot_row = row;
-  res->pivot_col = col;
-  res->added = (res->pivot_abs > res->q_tau && !stale && rk < max_rank) ? 1 : 0;
-  res->info = *info;
 }
 
 // 2-norm condition numbers of the 2x2 probes of the index initialisation.
@@ -259,7 +164,12 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
 
 // TT value at test multi-indices: cores given column-major C_k
 // ((r_{k-1} n_k) x r_k), entry C_k[s, i, t] = C_k[(s + i r_{k-1}) + t r_{k-1} n_k].
-// One wave per point, the running vector in LDS.
+// One block of 256 threads per point.  Per core the block forms
+// v C_k[:, i_k, :] with 16 lanes along r_{k-1} (contiguous in memory, so a
+// wave's load covers 4 cache lines) and 16 lane groups along r_k; the 16
+// partial sums of a column are reduced by shuffles.  The running vector sits
+// in LDS between cores and in registers (v[l + 16 c] in lane l's slot c)
+// during a core.
 struct TTView {
   const double* C[MAXD];
   int r[MAXD + 1];
@@ -267,27 +177,38 @@ struct TTView {
   int D;
 };
 __global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx, int P, double* out) {
-  __shared__ double buf[4][2][MAXR];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int p = blockIdx.x * 4 + w;
+  __shared__ double v[MAXR];
+  const int p = blockIdx.x;
   if (p >= P) return;
-  double* v = buf[w][0];
-  double* vn = buf[w][1];
-  if (lane == 0) v[0] = 1.0;
-  __builtin_amdgcn_wave_barrier();
+  const int lq = threadIdx.x & 15, lt = threadIdx.x >> 4;
+  if (threadIdx.x == 0) v[0] = 1.0;
+  __syncthreads();
   for (int k = 0; k < tv.D; ++k) {
     const int r0 = tv.r[k], r1 = tv.r[k + 1];
+    const int64_t m = tv.m[k];
     const int i = idx[(int64_t)p * tv.D + k];
     const double* blk = tv.C[k] + (int64_t)i * r0;     // rows s + i r0
-    for (int t = lane; t < r1; t += 64) {
+    double vr[MAXR / 16];
+#pragma unroll
+    for (int c = 0; c < MAXR / 16; ++c) vr[c] = (lq + 16 * c < r0) ? v[lq + 16 * c] : 0.0;
+    __syncthreads();   // every thread holds its slice of v before v is overwritten
+    for (int t0 = 0; t0 < r1; t0 += 16) {
+      const int t = t0 + lt;
       double s = 0.0;
-      for (int q = 0; q < r0; ++q) s += blk[q + (int64_t)t * tv.m[k]] * v[q];
-      vn[t] = s;
+      if (t < r1) {
+        const double* col = blk + t * m;
+#pragma unroll
+        for (int c = 0; c < MAXR / 16; ++c) {
+          if (16 * c >= r0) break;
+          if (lq + 16 * c < r0) s += col[lq + 16 * c] * vr[c];
+        }
+      }
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      if (lq == 0 && t < r1) v[t] = s;
     }
-    __builtin_amdgcn_wave_barrier();
-    double* tmp = v; v = vn; vn = tmp;
+    __syncthreads();
   }
-  if (lane == 0) out[p] = v[0];
+  if (threadIdx.x == 0) out[p] = v[0];
 }
 
 __global__ void k_err_max(const double* a, const double* b, int n, double* out) {
@@ -303,17 +224,26 @@ __global__ void k_err_max(const double* a, const double* b, int n, double* out) 
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_set_scale(StepRes* res, const double* base) {
-  if (threadIdx.x == 0) { res->s_scale = *base; res->q_scale = 0.0; }
-}
-
 __global__ void k_zero1(double* p) {
   if (threadIdx.x == 0) *p = 0.0;
 }
 
+// Li^T and W^T, kept beside Li and W (second half of each factor buffer) so
+// that every product of the cross reads its factor along rows.
+constexpr int64_t FT = (int64_t)MAXR * MAXR;
+
+// Copies of the leading r x r blocks of Li and W into their transposes.
+__device__ inline void store_transposes(double* Li, double* W, int r) {
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      Li[FT + j + i * MAXR] = Li[i + j * MAXR];
+      W[FT + j + i * MAXR] = W[i + j * MAXR];
+    }
+}
+
 // Factors of the initial intersection matrix (r <= 2), written with leading
-// dimension MAXR: Li (pivot x row), W (column x pivot); amax = max |entry|,
-// info = 1 if no diagonal entry can lead.
+// dimension MAXR: Li (pivot x row), W (column x pivot), and their
+// transposes; amax = max |entry|, info = 1 if no diagonal entry can lead.
 __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double* amax, int32_t* info) {
   if (threadIdx.x != 0) return;
   double m = 0.0;
@@ -328,6 +258,7 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
     *info = !(P[0] != 0.0) || !isfinite(P[0]);
     Li[0] = 1.0;
     W[0] = 1.0 / P[0];
+    store_transposes(Li, W, 1);
     return;
   }
   const int f = fabs(P[3]) > fabs(P[0]) ? 1 : 0, g = 1 - f;   // first pivot: the larger diagonal entry
@@ -343,69 +274,311 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
   W[f + 0 * MAXR] = 1.0 / d1;             // column f of P^{-1}'s factor for pivot 0
   W[g + 1 * MAXR] = 1.0 / sv;             // pivot 1: (e_g - e_f u / d1) / s
   W[f + 1 * MAXR] = -(u / d1) / sv;
+  store_transposes(Li, W, 2);
 }
 
-// Border the factors (r x r, leading dimension MAXR) with the pivot's
-// column b = P(I, t), row c = P(l, J) and corner d, when the step added it.
-__global__ void __launch_bounds__(1024) k_border(double* Li, double* W, int r, const double* b, const double* c,
-                                                 const double* d, StepRes* res, double* amax, int32_t* info) {
-  __shared__ double u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR];
-  __shared__ double s_s;
-  if (!res->added) return;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
+// MAXR): one thread per row, so a wave's loads are contiguous.
+template <int BS>
+__device__ inline void row_dots(const double* M, const double* v, int r, double* out) {
+  for (int t = threadIdx.x; t < r; t += BS) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 3 < r; q += 4) {
+      s0 += M[t + (int64_t)q * MAXR] * v[q];
+      s1 += M[t + (int64_t)(q + 1) * MAXR] * v[q + 1];
+      s2 += M[t + (int64_t)(q + 2) * MAXR] * v[q + 2];
+      s3 += M[t + (int64_t)(q + 3) * MAXR] * v[q + 3];
+    }
+    for (; q < r; ++q) s0 += M[t + (int64_t)q * MAXR] * v[q];
+    out[t] = (s0 + s1) + (s2 + s3);
+  }
+}
+
+// Robust argmax of |R| over the whole block (lowest key within tau of the
+// max) and the relative top-2 margin; stage 0 = sample stage (also records
+// row/col of the chosen sample), stage 1 = search stage.  The sample list is
+// in generation order, so its key is the linear position row * cols + col;
+// the searched fibre is in natural order.
+template <int BS>
+__device__ void select_block(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
+                             double scale, StepRes* res) {
+  __shared__ double sv[BS];
+  __shared__ int sk[BS], si[BS];
   const int tid = threadIdx.x;
-  // u = Li b (pivot order), g = W^T c (pivot order)
-  for (int i = tid; i < 2 * r; i += blockDim.x) {
-    double acc = 0.0;
-    if (i < r) {
-      for (int q = 0; q < r; ++q) acc += Li[i + (int64_t)q * MAXR] * b[q];
-      u[i] = acc;
-    } else {
-      const int p = i - r;
-      for (int j = 0; j < r; ++j) acc += c[j] * W[j + (int64_t)p * MAXR];
-      gv[p] = acc;
-    }
-  }
+  const double tau = TIE_REL * scale;
+  double m = -1.0;
+  for (int i = tid; i < n; i += BS) m = fmax(m, fabs(R[i]));
+  sv[tid] = m;
   __syncthreads();
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
+    __syncthreads();
+  }
+  const double mx = sv[0];
+  __syncthreads();
+  int best = 0x7fffffff, bi = 0x7fffffff;
+  for (int i = tid; i < n; i += BS)
+    if (fabs(R[i]) >= mx - tau) {
+      const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
+      if (key < best) { best = key; bi = i; }
+    }
+  sk[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (tid < s && sk[tid + s] < sk[tid]) { sk[tid] = sk[tid + s]; si[tid] = si[tid + s]; }
+    __syncthreads();
+  }
+  // (no candidate compares, e.g. all residuals NaN: fall back to the first)
+  const int p = si[0] < n ? si[0] : 0;
+  double sec = 0.0;
+  for (int i = tid; i < n; i += BS)
+    if (i != p) sec = fmax(sec, fabs(R[i]));
+  __syncthreads();
+  sv[tid] = sec;
+  __syncthreads();
+  for (int s = BS / 2; s > 0; s >>= 1) {
+    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
+    __syncthreads();
+  }
   if (tid == 0) {
-    double gu = 0.0, m = *amax;
-    for (int p = 0; p < r; ++p) {
-      gu += gv[p] * u[p];
-      m = fmax(m, fmax(fabs(b[p]), fabs(c[p])));
-    }
-    s_s = *d - gu;
-    *amax = fmax(m, fabs(*d));
-    if (!(s_s != 0.0) || !isfinite(s_s)) {
-      *info = 1;
-      res->info = 1;
-    }
-  }
-  __syncthreads();
-  const double is = 1.0 / s_s;
-  // new row of Li: -g^T Li; new column of W: -W u / s (both from the old factors)
-  for (int i = tid; i < 2 * r; i += blockDim.x) {
-    double acc = 0.0;
-    if (i < r) {
-      for (int p = 0; p < r; ++p) acc += gv[p] * Li[p + (int64_t)i * MAXR];
-      nl[i] = -acc;
+    const double margin = mx > 0.0 ? (mx - sv[0]) / mx : 0.0;
+    if (stage == 0) {
+      res->s_pos = p; res->s_max = mx; res->s_margin = margin; res->s_tau = tau;
+      res->l = srow[p]; res->t = scol[p];
+      res->s_scale = scale;
+      res->q_scale = scale;             // the search stage widens this scale
     } else {
-      const int j = i - r;
-      for (int p = 0; p < r; ++p) acc += W[j + (int64_t)p * MAXR] * u[p];
-      nw[j] = -acc * is;
+      res->q_pos = p; res->q_max = mx; res->q_margin = margin; res->q_tau = tau;
+      res->pivot_abs = fabs(R[p]);
     }
   }
+}
+
+// True in every thread of the block that finishes last among the blocks of
+// the launch (its residuals, and everyone else's, are then visible).
+__device__ inline bool last_block(StepRes* res) {
+  __shared__ int s_last;
+  __threadfence();
   __syncthreads();
-  for (int e = tid; e <= 2 * r + 1; e += blockDim.x) {
+  if (threadIdx.x == 0) {
+    s_last = atomicAdd(&res->ctr, 1) == (int)gridDim.x - 1;
+    if (s_last) res->ctr = 0;
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last;
+}
+
+// Sample stage: residuals R_i = A(s_i, J) P^{-1} A(I, s_i) - A(s_i) of the
+// sampled entries, written as the row-wise dot product of G = A(s, J) W and
+// T = (Li A(I, s))^T, both 16-sample tiles formed with FP64 MFMA
+// (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16], D row
+// l / 16 + 4 v, column l % 16 in lane l, slot v), then the selection in the
+// last block.  AsJ and AIs hold A(s_i, J_q) and A(I_q, s_i) at i + q ns.  The
+// block's A operands are staged once in LDS in lane order (dynamic, 2 x 64 x
+// ceil(r / 4) doubles); the B operands (rows of W^T and Li) stream from L2,
+// eight MFMA steps of loads in flight per batch.
+constexpr int SW = 4;   // waves per block; one block per 16 samples
+constexpr int SB = 8;   // MFMA steps per batch of B loads
+__global__ void __launch_bounds__(SW * 64) k_sample_resid(const double* AsJ, const double* AIs, const double* As,
+                                                          int ns, int r, const double* Li, const double* W,
+                                                          double* R, const int32_t* srow, const int32_t* scol,
+                                                          int cols, const double* luamax, StepRes* res) {
+  extern __shared__ double sa[];
+  __shared__ double red[SW][16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = blockIdx.x * 16;
+  const int nst = (r + 3) / 4;
+  for (int e = tid; e < 64 * nst; e += SW * 64) {
+    const int ii = e & 15, q = e >> 4;
+    const int i = i0 + ii;
+    const bool ok = i < ns && q < r;
+    const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
+    sa[slot] = ok ? AsJ[i + (int64_t)q * ns] : 0.0;
+    sa[64 * nst + slot] = ok ? AIs[i + (int64_t)q * ns] : 0.0;
+  }
+  __syncthreads();
+  const double* Wt = W + FT;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ntile = (r + 15) / 16;
+  for (int jt = wv; jt < ntile; jt += SW) {
+    const int p = jt * 16 + li;
+    const bool pok = p < r;
+    dbl4 g = {0.0, 0.0, 0.0, 0.0}, t = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < nst; s0 += SB) {
+      double bg[SB], bt[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int q = 4 * (s0 + u) + lk;
+        const bool ok = pok && q < r;
+        bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
+        bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        if (s0 + u < nst) {
+          g = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], bg[u], g, 0, 0, 0);
+          t = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[64 * nst + (s0 + u) * 64 + lane], bt[u], t, 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[v] += g[v] * t[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    for (int o = 8; o > 0; o >>= 1) part[v] += __shfl_xor(part[v], o, 16);
+  if (li == 0)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wv][lk + 4 * v] = part[v];
+  __syncthreads();
+  if (tid < 16 && i0 + tid < ns) {
+    double s = 0.0;
+    for (int w = 0; w < SW; ++w) s += red[w][tid];
+    R[i0 + tid] = s - As[i0 + tid];
+  }
+  if (!last_block(res)) return;
+  select_block<SW * 64>(R, ns, srow, scol, cols, 0, fmax(res->s_scale, *luamax), res);
+}
+
+// dynamic LDS of k_sample_resid for rank r
+inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
+
+// Search stage: x = (u W) Li for the row of the chosen sample (bit 1, u =
+// A(l, J)) or x = W (Li u) for its column (bit 0, u = A(I, t)), both P^{-1}
+// applied to one vector (every block forms x itself); then R_i = sum_q
+// Lm[i + q n] x_q - Ad[i] over the fibre, and the selection in the last block.
+constexpr int QB = 256;
+__global__ void __launch_bounds__(QB) k_search_resid(int bit, const double* u, const double* Lm, const double* Ad,
+                                                     int n, int r, const double* Li, const double* W, double* R,
+                                                     int cols, StepRes* res) {
+  __shared__ double su[MAXR], sy[MAXR], sx[MAXR];
+  for (int q = threadIdx.x; q < r; q += QB) su[q] = u[q];
+  __syncthreads();
+  if (bit) {
+    row_dots<QB>(W + FT, su, r, sy);    // W^T u
+    __syncthreads();
+    row_dots<QB>(Li + FT, sy, r, sx);   // Li^T (W^T u)
+  } else {
+    row_dots<QB>(Li, su, r, sy);
+    __syncthreads();
+    row_dots<QB>(W, sy, r, sx);
+  }
+  __syncthreads();
+  for (int i = blockIdx.x * QB + threadIdx.x; i < n; i += gridDim.x * QB) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = 0;
+    for (; q + 3 < r; q += 4) {
+      s0 += Lm[i + (int64_t)q * n] * sx[q];
+      s1 += Lm[i + (int64_t)(q + 1) * n] * sx[q + 1];
+      s2 += Lm[i + (int64_t)(q + 2) * n] * sx[q + 2];
+      s3 += Lm[i + (int64_t)(q + 3) * n] * sx[q + 3];
+    }
+    for (; q < r; ++q) s0 += Lm[i + (int64_t)q * n] * sx[q];
+    R[i] = ((s0 + s1) + (s2 + s3)) - Ad[i];
+  }
+  if (!last_block(res)) return;
+  select_block<QB>(R, n, nullptr, nullptr, cols, 1, res->q_scale, res);
+}
+
+// End of a step, one block: the pivot (l, t) from the two stages; it is added
+// if its residual exceeds the tie band, it is not yet in I or J and the rank
+// is below the cap.  Then, if added, the border of P_k: b = A(I, t), c =
+// A(l, J) and d = A(l, t) are evaluated here and the factors bordered,
+// u = Li b, g = W^T c, s = d - g^T u,
+//   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
+// (leading dimension MAXR).  Clears the sample-stage scale for the next step.
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* res, int bit, const int32_t* I,
+                                                     const int32_t* J, int r, int max_rank, double* Li, double* W,
+                                                     double* amax, int32_t* info) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR];
+  __shared__ double s_d, s_s;
+  __shared__ int s_added, s_row, s_col;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_row = bit ? res->l : res->q_pos;
+    s_col = bit ? res->q_pos : res->t;
+  }
+  stage_nodes<D>(ks.nodes, sn);
+  const int row = s_row, col = s_col;
+  int stale = 0;
+  for (int q = tid; q < r; q += 256)
+    if (I[q] == row || J[q] == col) stale = 1;
+  stale = __syncthreads_or(stale);
+  if (tid == 0) {
+    const int added = (res->pivot_abs > res->q_tau && !stale && r < max_rank) ? 1 : 0;
+    res->pivot_row = row;
+    res->pivot_col = col;
+    res->added = added;
+    res->info = *info;   // status of the kept factors (non-zero after a singular border)
+    res->s_scale = 0.0;
+    s_added = added;
+  }
+  __syncthreads();
+  if (!s_added) return;
+  for (int e = tid; e <= 2 * r; e += 256) {
+    if (e < r) bv[e] = addr_eval<d, dt, G>(ks, a, sn, I[e], col);
+    else if (e < 2 * r) cv[e - r] = addr_eval<d, dt, G>(ks, a, sn, row, J[e - r]);
+    else s_d = addr_eval<d, dt, G>(ks, a, sn, row, col);
+  }
+  __syncthreads();
+  double* Lit = Li + FT;
+  double* Wt = W + FT;
+  row_dots<256>(Li, bv, r, u);    // Li b
+  row_dots<256>(Wt, cv, r, gv);   // W^T c
+  __syncthreads();
+  {
+    double gu = 0.0, m = 0.0;
+    for (int p = tid; p < r; p += 256) {
+      gu += gv[p] * u[p];
+      m = fmax(m, fmax(fabs(bv[p]), fabs(cv[p])));
+    }
+    gu = wsum(gu);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((tid & 63) == 0) { nl[tid >> 6] = gu; nw[tid >> 6] = m; }
+    __syncthreads();
+    if (tid == 0) {
+      gu = (nl[0] + nl[1]) + (nl[2] + nl[3]);
+      m = fmax(fmax(nw[0], nw[1]), fmax(nw[2], nw[3]));
+      s_s = s_d - gu;
+      *amax = fmax(fmax(*amax, m), fabs(s_d));
+      if (!(s_s != 0.0) || !isfinite(s_s)) {
+        *info = 1;
+        res->info = 1;
+      }
+    }
+    __syncthreads();
+  }
+  const double is = 1.0 / s_s;
+  row_dots<256>(Lit, gv, r, nl);   // Li^T g, i.e. g^T Li (from the old factors)
+  row_dots<256>(W, u, r, nw);      // W u
+  __syncthreads();
+  for (int e = tid; e <= 2 * r + 1; e += 256) {
     if (e < r) {
-      Li[r + (int64_t)e * MAXR] = nl[e];    // row r, column e
-      Li[e + (int64_t)r * MAXR] = 0.0;      // column r above the diagonal
+      Li[r + (int64_t)e * MAXR] = -nl[e];    // row r, column e
+      Lit[e + (int64_t)r * MAXR] = -nl[e];
+      Li[e + (int64_t)r * MAXR] = 0.0;       // column r above the diagonal
+      Lit[r + (int64_t)e * MAXR] = 0.0;
     } else if (e < 2 * r) {
       const int j = e - r;
-      W[j + (int64_t)r * MAXR] = nw[j];     // column r
-      W[r + (int64_t)j * MAXR] = 0.0;       // row r left of the diagonal
+      W[j + (int64_t)r * MAXR] = -nw[j] * is;    // column r
+      Wt[r + (int64_t)j * MAXR] = -nw[j] * is;
+      W[r + (int64_t)j * MAXR] = 0.0;            // row r left of the diagonal
+      Wt[j + (int64_t)r * MAXR] = 0.0;
     } else if (e == 2 * r) {
       Li[r + (int64_t)r * MAXR] = 1.0;
+      Lit[r + (int64_t)r * MAXR] = 1.0;
     } else {
       W[r + (int64_t)r * MAXR] = is;
+      Wt[r + (int64_t)r * MAXR] = is;
     }
   }
 }
@@ -438,10 +611,10 @@ class Cross {
   tt_status init_sets();
   tt_status update_step(int k, int sweep, tt_kernel_decision* rec);
   tt_status build_cores(std::vector<double*>* C);
+  tt_status refine_cores();
   tt_status init_inverses();
   void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
   std::vector<int32_t> pls_[MAXD], pli_[MAXD], prf_[MAXD], prt_[MAXD];   // pivot (s, i_k), (i_{k+1}, t)
-  tt_status solve_t(int k, int m, const double* Bt, int ldb, double* Xt);
   tt_status solve_right(int k, int m, const double* F, double* C);
   tt_status sampled_error(double* err);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
@@ -458,11 +631,11 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_, d_X_;
-  DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_;
-  // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), the
-  // border vectors of a step, max |entry| of P_k and the factors' status
-  DBuf d_li_[MAXD], d_w_[MAXD], d_bord_, d_luaux_, d_E_;
+  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_;
+  DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
+  // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
+  // |entry| of P_k and the factors' status
+  DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
   HBuf h_stage_, h_res_;
@@ -706,8 +879,8 @@ tt_status Cross::init_inverses() {
     const int32_t* dI = nullptr;
     TTK_TRY(arena_push(hi.data(), hi.size(), &dI));
     TTK_TRY(arena_flush());
-    TTK_TRY(d_li_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
-    TTK_TRY(d_w_[k].alloc((size_t)MAXR * MAXR * sizeof(double)));
+    TTK_TRY(d_li_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));   // Li, then Li^T
+    TTK_TRY(d_w_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));    // W, then W^T
     eval_product(ks_, super_addr(k), dI, rk, dI + rk, rk, d_P_.as<double>(), st_);
     evals_ += (int64_t)rk * rk;
     hipLaunchKernelGGL(k_ldu_init, dim3(1), dim3(64), 0, st_, d_P_.as<double>(), rk, d_li_[k].as<double>(),
@@ -715,17 +888,6 @@ tt_status Cross::init_inverses() {
     TTK_TRY(sync());   // the arena is reused by the next k
   }
   TTK_HIP(hipGetLastError());
-  return TTK_OK;
-}
-
-// X^T = B^T P_k^{-T} = (B^T Li^T) W^T for B^T (m x r, leading dimension ldb);
-// X^T written with leading dimension m.
-tt_status Cross::solve_t(int k, int m, const double* Bt, int ldb, double* Xt) {
-  const int r = rank(k);
-  TTK_TRY(d_E_.alloc((size_t)m * r * sizeof(double)));
-  double* T = d_E_.as<double>();
-  gemm64(0, 1, m, r, r, 1.0, Bt, ldb, d_li_[k].as<double>(), MAXR, 0.0, T, m, st_);
-  gemm64(0, 1, m, r, r, 1.0, T, m, d_w_[k].as<double>(), MAXR, 0.0, Xt, m, st_);
   return TTK_OK;
 }
 
@@ -784,19 +946,16 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const int32_t* d_t = &dres->t;
   const Addr a = super_addr(k);
   // P_k^{-1} = W Li, kept across steps and bordered when a pivot is added
-  TTK_TRY(d_X_.alloc((size_t)std::max(ns, std::max(cols, 1)) * rk * sizeof(double)));
-  double* X = d_X_.as<double>();
-  hipLaunchKernelGGL(k_set_scale, dim3(1), dim3(64), 0, st_, dres, (const double*)luamax(k));
-  {
+  const double* Li = d_li_[k].as<double>();
+  const double* W = d_w_[k].as<double>();
+  double* R = d_R_.as<double>();
+  {   // the sample-stage maximum folds into s_scale (cleared by the previous step)
     const EvalSeg sg[3] = {{dsr, dJ, ns, rk, 0, AsJ}, {dI, dsc, rk, ns, 1, AIs}, {dsr, dsc, ns, 1, 2, As}};
     eval_segs(ks_, a, sg, 3, st_, &dres->s_scale);
   }
   evals_ += 2 * (int64_t)ns * rk + ns;
-  // (P^{-1} A(I, samples))^T = A(I, samples)^T P^{-T}: the (q, sample) entry at sample + q ns
-  TTK_TRY(solve_t(k, ns, AIs, ns, X));
-  hipLaunchKernelGGL(k_resid, dim3(nblk(ns, 64)), dim3(64), 0, st_, AsJ, (int64_t)1, (int64_t)ns, X,
-                     (int64_t)ns, (int64_t)1, As, ns, rk, d_R_.as<double>());
-  hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), ns, dsr, dsc, cols, 0, dres);
+  hipLaunchKernelGGL(k_sample_resid, dim3(nblk(ns, 16)), dim3(SW * 64), sample_lds(rk), st_, AsJ, AIs, As, ns, rk,
+                     Li, W, R, dsr, dsc, cols, (const double*)luamax(k), dres);
   if (bit == 1) {   // search the row of the sample's pivot
     double* AlJ = S0;
     double* AIall = AlJ + rk;                   // (q, c) at c + q cols
@@ -806,10 +965,8 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
       eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
     }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    TTK_TRY(solve_t(k, cols, AIall, cols, X));
-    hipLaunchKernelGGL(k_resid, dim3(nblk(cols, 64)), dim3(64), 0, st_, AlJ, (int64_t)0, (int64_t)1, X,
-                       (int64_t)cols, (int64_t)1, Alall, cols, rk, d_R_.as<double>());
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), cols, dsr, dsc, cols, 1, dres);
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QB)), dim3(QB), 0, st_, 1, (const double*)AlJ,
+                       (const double*)AIall, (const double*)Alall, cols, rk, Li, W, R, cols, dres);
   } else {          // search the column
     double* AallJ = S0;
     double* AIt = AallJ + (size_t)rows * rk;
@@ -819,27 +976,17 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
       eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
     }
     evals_ += (int64_t)rows * rk + rk + rows;
-    TTK_TRY(solve_t(k, 1, AIt, 1, X));   // one right-hand side: B^T is 1 x r
-    hipLaunchKernelGGL(k_resid, dim3(nblk(rows, 64)), dim3(64), 0, st_, AallJ, (int64_t)1, (int64_t)rows,
-                       X, (int64_t)1, (int64_t)0, Aallt, rows, rk, d_R_.as<double>());
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, st_, d_R_.as<double>(), rows, dsr, dsc, cols, 1, dres);
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QB)), dim3(QB), 0, st_, 0, (const double*)AIt,
+                       (const double*)AallJ, (const double*)Aallt, rows, rk, Li, W, R, cols, dres);
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st_, dres, bit, dI, dJ, rk,
-                     std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR), (const int32_t*)luinfo(k));
-  // border the factors of P_k with the pivot's column, row and corner (the
-  // kernel does nothing unless the step added the pivot)
-  {
-    TTK_TRY(d_bord_.alloc((2 * (size_t)MAXR + 2) * sizeof(double)));
-    double* bv = d_bord_.as<double>();
-    const int32_t* prow = &dres->pivot_row;
-    const int32_t* pcol = &dres->pivot_col;
-    const EvalSeg sg[3] = {{dI, pcol, rk, 1, 0, bv}, {prow, dJ, 1, rk, 0, bv + MAXR},
-                           {prow, pcol, 1, 1, 0, bv + 2 * MAXR}};
-    eval_segs(ks_, a, sg, 3, st_, nullptr);
-    evals_ += 2 * (int64_t)rk + 1;
-    hipLaunchKernelGGL(k_border, dim3(1), dim3(1024), 0, st_, d_li_[k].as<double>(), d_w_[k].as<double>(), rk, bv,
-                       bv + MAXR, bv + 2 * MAXR, dres, luamax(k), luinfo(k));
-  }
+  // decide, and border the factors of P_k with the pivot's column, row and
+  // corner when the step added it
+  const int maxr = std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR);
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
+                       dim3(256), 0, st_, ks_, a, dres, bit, dI, dJ, rk, maxr, d_li_[k].as<double>(),
+                       d_w_[k].as<double>(), luamax(k), luinfo(k));
+  });
   TTK_HIP(hipGetLastError());
   TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, sizeof(StepRes), hipMemcpyDeviceToHost, st_));
   TTK_TRY(sync());
@@ -863,6 +1010,7 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   if (r.s_max > 0) min_margin_ = std::min(min_margin_, r.s_margin);
   if (r.q_max > 0) min_margin_ = std::min(min_margin_, r.q_margin);
   if (r.added) {
+    evals_ += 2 * (int64_t)rk + 1;                 // the border entries
     const int l = r.pivot_row, t = r.pivot_col;   // the factors of P_k are already bordered
     const int s = l % rl, ik = l / rl;
     pls_[k].push_back(s);
@@ -913,6 +1061,41 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   return TTK_OK;
 }
 
+// One step of residual refinement of the returned cores C_k = F_k P_k^{-1}
+// (k < D): with P_k = F_k(I, :) (the rows at the pivot positions),
+// C_k <- C_k + (F_k - C_k P_k) W Li.  The factors are exact up to the growth
+// of elimination in pivot order, which can amplify rounding where P_k is
+// very ill-conditioned; the correction brings C_k to the accuracy of a
+// pivoted solve at the cost of three products per core.
+tt_status Cross::refine_cores() {
+  const int N = N_;
+  for (int k = 1; k < N; ++k) {
+    const int r0 = rank(k - 1), r = rank(k), n = g_.n[k - 1];
+    const int m = r0 * n;
+    std::vector<int32_t> I, J;
+    pivot_positions(k, &I, &J);
+    arena_reset();
+    const int32_t* dI = nullptr;
+    TTK_TRY(arena_push(I.data(), I.size(), &dI));
+    TTK_TRY(arena_flush());
+    const double* F = d_core_[k - 1].as<double>();
+    double* C = d_cint_[k - 1].as<double>();
+    TTK_TRY(d_P_.alloc((size_t)r * r * sizeof(double)));
+    TTK_TRY(d_ref_.alloc((size_t)2 * m * r * sizeof(double)));
+    double* P = d_P_.as<double>();
+    double* E = d_ref_.as<double>();
+    double* T = E + (size_t)m * r;
+    hipLaunchKernelGGL(k_gather_rows, dim3(nblk((int64_t)r * r, 256)), dim3(256), 0, st_, F, m, dI, r, r, P);
+    TTK_HIP(hipMemcpyAsync(E, F, (size_t)m * r * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    gemm64(0, 0, m, r, r, -1.0, C, m, P, r, 1.0, E, m, st_);
+    gemm64(0, 0, m, r, r, 1.0, E, m, d_w_[k].as<double>(), MAXR, 0.0, T, m, st_);
+    gemm64(0, 0, m, r, r, 1.0, T, m, d_li_[k].as<double>(), MAXR, 1.0, C, m, st_);
+    TTK_TRY(sync());   // the arena is reused by the next k
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
 tt_status Cross::sampled_error(double* err) {
   std::vector<double*> C;
   TTK_TRY(build_cores(&C));
@@ -920,7 +1103,7 @@ tt_status Cross::sampled_error(double* err) {
   tv.D = N_;
   for (int k = 0; k < N_; ++k) { tv.C[k] = C[k]; tv.m[k] = rank(k) * g_.n[k]; }
   for (int k = 0; k <= N_; ++k) tv.r[k] = rank(k);
-  hipLaunchKernelGGL(k_tt_points, dim3(nblk(n_test_, 4)), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(),
+  hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(),
                      n_test_, d_test_hat_.as<double>());
   hipLaunchKernelGGL(k_err_max, dim3(1), dim3(1024), 0, st_, d_test_val_.as<double>(),
                      d_test_hat_.as<double>(), n_test_, d_err_.as<double>());
@@ -960,6 +1143,13 @@ tt_status Cross::run(CrossOut* out) {
     TTK_HIP(hipMemcpyAsync(&test_max_, d_err_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
     TTK_TRY(sync());
   }
+  // the sample stage stages up to 2 x 64 x MAXR / 4 doubles of LDS per block
+  if (sample_lds(MAXR) > 48 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample_resid),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR)));
+  // step state: the block counter and the sample-stage scale start at zero
+  TTK_TRY(d_res_.alloc(sizeof(StepRes)));
+  fill_zero(d_res_.p, sizeof(StepRes), st_);
   double err = 0.0;
   TTK_TRY(sampled_error(&err));
   int sweep = 0;
@@ -976,7 +1166,9 @@ tt_status Cross::run(CrossOut* out) {
     TTK_TRY(sampled_error(&err));
     if (added == 0) break;
   }
-  // the cores of the last stopping test are the result (C_k in d_cint_, C_D in d_core_)
+  // the cores of the last stopping test, refined, are the result (C_k in
+  // d_cint_, C_D in d_core_)
+  TTK_TRY(refine_cores());
   out->ranks.assign(N + 1, 1);
   for (int k = 0; k <= N; ++k) out->ranks[k] = rank(k);
   out->cores.assign(N, {});

@@ -5,41 +5,36 @@
 // through its index sets, so multi-indices are assembled here on the device
 // from (left set row, middle node indices, right set row) and never shipped
 // from the host.  All evaluation is double precision.
-#include "ttk_internal.h"
-#include "ttk_kappa.h"
+#include "ttk_eval_dev.h"
 
 namespace ttk {
 
 namespace {
 
-__device__ inline double eval_coords(const KSpec& ks, const double* c) {
-  return kappa_eval(ks.kind, ks.d, ks.kconst, c, c + ks.d, c + ks.d + ks.dt);
-}
+constexpr int EB = 256;   // threads per evaluation block
 
-// Multi-index of super-core / fibre position (row, col) -> coordinates.
-__device__ inline void addr_coords(const KSpec& ks, const Addr& a, int row, int col, double* c) {
-  const int s = row % a.rl;
-  const int i0 = row / a.rl;
-  int i1 = 0, t = col;
-  if (a.nmid == 2) { i1 = col % a.nm1; t = col / a.nm1; }
-  int j = 0;
-  for (int q = 0; q < a.lk; ++q, ++j) c[j] = ks.nodes[j * MAXN + a.left[s * a.lk + q]];
-  c[j] = ks.nodes[j * MAXN + i0]; ++j;
-  if (a.nmid == 2) { c[j] = ks.nodes[j * MAXN + i1]; ++j; }
-  for (int q = 0; q < a.lr; ++q, ++j) c[j] = ks.nodes[j * MAXN + a.right[t * a.lr + q]];
-}
-
-// Running max of |value| folded into *amax (non-negative doubles order like
-// their bit patterns, so an integer atomic max is exact).
+// Block-wide max of |value| folded into *amax with one atomic per block
+// (non-negative doubles order like their bit patterns, so an integer atomic
+// max is exact).
 __device__ inline void fold_amax(double v, double* amax) {
+  __shared__ double red[EB / 64];
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  if ((threadIdx.x & 63) == 0)
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
     atomicMax(reinterpret_cast<unsigned long long*>(amax), (unsigned long long)__double_as_longlong(v));
+  }
 }
 
 // out[i + j*nr] (or out[j + i*nc] when trans_out) = A(rows[i], cols[j])
-__global__ void k_eval_product(KSpec ks, Addr a, const int32_t* rows, int nr,
-                               const int32_t* cols, int nc, int trans_out, double* out, double* amax) {
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(EB) k_eval_product(KSpec ks, Addr a, const int32_t* rows, int nr,
+                                                     const int32_t* cols, int nc, int trans_out, double* out,
+                                                     double* amax) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  stage_nodes<D>(ks.nodes, sn);
   const int64_t total = (int64_t)nr * nc;
   double m = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -49,22 +44,26 @@ __global__ void k_eval_product(KSpec ks, Addr a, const int32_t* rows, int nr,
     else { i = (int)(e % nr); jj = (int)(e / nr); }
     const int row = rows ? rows[i] : i;
     const int col = cols ? cols[jj] : jj;
-    double c[MAXD];
-    addr_coords(ks, a, row, col, c);
-    const double v = eval_coords(ks, c);
+    double c[D];
+    addr_coords<D>(a, sn, row, col, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
     out[e] = v;
     m = fmax(m, fabs(v));
   }
   if (amax) fold_amax(m, amax);
 }
 
-__global__ void k_eval_list(KSpec ks, Addr a, const int32_t* rows, const int32_t* cols, int np,
-                            double* out, double* amax) {
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(EB) k_eval_list(KSpec ks, Addr a, const int32_t* rows, const int32_t* cols,
+                                                  int np, double* out, double* amax) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  stage_nodes<D>(ks.nodes, sn);
   double m = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
-    double c[MAXD];
-    addr_coords(ks, a, rows[i], cols[i], c);
-    const double v = eval_coords(ks, c);
+    double c[D];
+    addr_coords<D>(a, sn, rows[i], cols[i], c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
     out[i] = v;
     m = fmax(m, fabs(v));
   }
@@ -72,7 +71,12 @@ __global__ void k_eval_list(KSpec ks, Addr a, const int32_t* rows, const int32_t
 }
 
 // Up to three blocks of entries in one launch (see EvalSeg).
-__global__ void k_eval_segs(KSpec ks, Addr a, EvalSeg s0, EvalSeg s1, EvalSeg s2, int nseg, double* amax) {
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(EB) k_eval_segs(KSpec ks, Addr a, EvalSeg s0, EvalSeg s1, EvalSeg s2, int nseg,
+                                                  double* amax) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  stage_nodes<D>(ks.nodes, sn);
   const int64_t n0 = (int64_t)s0.nr * s0.nc;
   const int64_t n1 = nseg > 1 ? (int64_t)s1.nr * s1.nc : 0;
   const int64_t n2 = nseg > 2 ? (int64_t)s2.nr * s2.nc : 0;
@@ -94,43 +98,49 @@ __global__ void k_eval_segs(KSpec ks, Addr a, EvalSeg s0, EvalSeg s1, EvalSeg s2
       row = sg.rows ? sg.rows[i] : i;
       col = sg.cols ? sg.cols[jj] : jj;
     }
-    double c[MAXD];
-    addr_coords(ks, a, row, col, c);
-    const double v = eval_coords(ks, c);
+    double c[D];
+    addr_coords<D>(a, sn, row, col, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
     sg.out[e] = v;
     m = fmax(m, fabs(v));
   }
   if (amax) fold_amax(m, amax);
 }
 
-template <class I>
-__global__ void k_eval_multi(KSpec ks, const I* idx, int64_t P, double* out) {
+template <class I, int d, int dt, bool G>
+__global__ void __launch_bounds__(EB) k_eval_multi(KSpec ks, const I* idx, int64_t P, double* out) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  stage_nodes<D>(ks.nodes, sn);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P;
        i += (int64_t)gridDim.x * blockDim.x) {
-    double c[MAXD];
-    for (int j = 0; j < ks.D; ++j) c[j] = ks.nodes[j * MAXN + (int)idx[i * ks.D + j]];
-    out[i] = eval_coords(ks, c);
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = sn[j * MAXN + (int)idx[i * D + j]];
+    out[i] = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
   }
 }
 
 // Dense block: one thread per (i, j), i fastest so stores to column-major K coalesce.
-template <class T>
-__global__ void k_eval_dense(KSpec ks, const T* X, int64_t nx, const T* Y, int64_t ny,
-                             double th0, double th1, T* K, int64_t ldk) {
+template <class T, int d, int dt, bool G>
+__global__ void __launch_bounds__(EB) k_eval_dense(KSpec ks, const T* X, int64_t nx, const T* Y, int64_t ny,
+                                                   double th0, double th1, T* K, int64_t ldk) {
   const int64_t total = nx * ny;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e % nx, j = e / nx;
-    double c[MAXD];
-    for (int q = 0; q < ks.d; ++q) c[q] = (double)X[q * nx + i];
-    if (ks.dt > 0) c[ks.d] = th0;
-    if (ks.dt > 1) c[ks.d + 1] = th1;
-    for (int q = 0; q < ks.d; ++q) c[ks.d + ks.dt + q] = (double)Y[q * ny + j];
-    K[i + j * ldk] = (T)eval_coords(ks, c);
+    double c[2 * d + dt];
+#pragma unroll
+    for (int q = 0; q < d; ++q) c[q] = (double)X[q * nx + i];
+    if (dt > 0) c[d] = th0;
+    if (dt > 1) c[d + (dt > 1 ? 1 : 0)] = th1;
+#pragma unroll
+    for (int q = 0; q < d; ++q) c[d + dt + q] = (double)Y[q * ny + j];
+    K[i + j * ldk] = (T)kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
   }
 }
 
-inline int blocks_for(int64_t n, int bs = 256, int cap = 16384) {
+inline int blocks_for(int64_t n, int bs = EB, int cap = 16384) {
   int64_t b = (n + bs - 1) / bs;
   if (b < 1) b = 1;
   return (int)(b > cap ? cap : b);
@@ -141,14 +151,20 @@ inline int blocks_for(int64_t n, int bs = 256, int cap = 16384) {
 void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr, const int32_t* cols,
                   int nc, double* out, hipStream_t st, double* amax, bool trans_out) {
   if (nr <= 0 || nc <= 0) return;
-  hipLaunchKernelGGL(k_eval_product, dim3(blocks_for((int64_t)nr * nc)), dim3(256), 0, st, ks, a, rows,
-                     nr, cols, nc, trans_out ? 1 : 0, out, amax);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_product<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(blocks_for((int64_t)nr * nc)), dim3(EB), 0, st, ks, a, rows, nr, cols, nc,
+                       trans_out ? 1 : 0, out, amax);
+  });
 }
 
 void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols, int np,
                double* out, hipStream_t st, double* amax) {
   if (np <= 0) return;
-  hipLaunchKernelGGL(k_eval_list, dim3(blocks_for(np)), dim3(256), 0, st, ks, a, rows, cols, np, out, amax);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_list<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(blocks_for(np)), dim3(EB),
+                       0, st, ks, a, rows, cols, np, out, amax);
+  });
 }
 
 void eval_segs(const KSpec& ks, const Addr& a, const EvalSeg* segs, int nseg, hipStream_t st, double* amax) {
@@ -156,34 +172,46 @@ void eval_segs(const KSpec& ks, const Addr& a, const EvalSeg* segs, int nseg, hi
   for (int i = 0; i < nseg; ++i) total += (int64_t)segs[i].nr * segs[i].nc;
   if (total <= 0) return;
   const EvalSeg z{};
-  hipLaunchKernelGGL(k_eval_segs, dim3(blocks_for(total)), dim3(256), 0, st, ks, a, segs[0], nseg > 1 ? segs[1] : z,
-                     nseg > 2 ? segs[2] : z, nseg, amax);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_segs<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(blocks_for(total)), dim3(EB),
+                       0, st, ks, a, segs[0], nseg > 1 ? segs[1] : z, nseg > 2 ? segs[2] : z, nseg, amax);
+  });
 }
 
 void eval_multi16(const KSpec& ks, const int16_t* idx, int64_t P, double* out, hipStream_t st) {
   if (P <= 0) return;
-  hipLaunchKernelGGL(k_eval_multi<int16_t>, dim3(blocks_for(P)), dim3(256), 0, st, ks, idx, P, out);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_multi<int16_t, decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(blocks_for(P)),
+                       dim3(EB), 0, st, ks, idx, P, out);
+  });
 }
 
 void eval_multi32(const KSpec& ks, const int32_t* idx, int64_t P, double* out, hipStream_t st) {
   if (P <= 0) return;
-  hipLaunchKernelGGL(k_eval_multi<int32_t>, dim3(blocks_for(P)), dim3(256), 0, st, ks, idx, P, out);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_multi<int32_t, decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(blocks_for(P)),
+                       dim3(EB), 0, st, ks, idx, P, out);
+  });
 }
 
 void eval_dense_f32(const KSpec& ks, const float* X, int64_t nx, const float* Y, int64_t ny,
                     const double* theta, float* K, int64_t ldk, hipStream_t st) {
   if (nx <= 0 || ny <= 0) return;
   const double t0 = ks.dt > 0 ? theta[0] : 0.0, t1 = ks.dt > 1 ? theta[1] : 0.0;
-  hipLaunchKernelGGL(k_eval_dense<float>, dim3(blocks_for(nx * ny)), dim3(256), 0, st, ks, X, nx, Y, ny,
-                     t0, t1, K, ldk);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_dense<float, decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(blocks_for(nx * ny)), dim3(EB), 0, st, ks, X, nx, Y, ny, t0, t1, K, ldk);
+  });
 }
 
 void eval_dense_f64(const KSpec& ks, const double* X, int64_t nx, const double* Y, int64_t ny,
                     const double* theta, double* K, int64_t ldk, hipStream_t st) {
   if (nx <= 0 || ny <= 0) return;
   const double t0 = ks.dt > 0 ? theta[0] : 0.0, t1 = ks.dt > 1 ? theta[1] : 0.0;
-  hipLaunchKernelGGL(k_eval_dense<double>, dim3(blocks_for(nx * ny)), dim3(256), 0, st, ks, X, nx, Y,
-                     ny, t0, t1, K, ldk);
+  with_dims(ks, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_dense<double, decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(blocks_for(nx * ny)), dim3(EB), 0, st, ks, X, nx, Y, ny, t0, t1, K, ldk);
+  });
 }
 
 }  // namespace ttk

@@ -37,35 +37,44 @@ __device__ inline double matern_general(double r, double ell, double nu) {
   return exp2(1.0 - nu) / tgamma(nu) * zpow_besselk(nu, z);
 }
 
-// kappa(x, y; theta) for the kind in tt_kernel_kind.
-__device__ inline double kappa_eval(int kind, int d, double kconst, const double* x,
-                                    const double* th, const double* y) {
+// kappa(x, y; theta) for the kind in tt_kernel_kind, at the coordinates
+// c = (x_1..x_d, theta_1..theta_dt, y_1..y_d).  d and dt are compile-time so
+// that c stays in registers (every index below is a constant).  The general
+// Matern kinds (Bessel integral) are compiled in only when G is set, so the
+// closed-form kinds keep a small register footprint.
+template <int d, int dt, bool G>
+__device__ inline double kappa_eval(int kind, double kconst, const double (&c)[2 * d + dt]) {
+  const double th0 = c[dt > 0 ? d : 0];       // meaningless when dt == 0
+  const double th1 = c[dt > 1 ? d + 1 : 0];   // meaningless when dt < 2
   if (kind == TTK_TEST_POLY) {
     double dot = 0.0;
-    for (int j = 0; j < d; ++j) dot += x[j] * y[j];
-    const double u = 1.0 + th[0] * dot;
+#pragma unroll
+    for (int j = 0; j < d; ++j) dot += c[j] * c[d + dt + j];
+    const double u = 1.0 + th0 * dot;
     return u * u * u;
   }
   if (kind == TTK_TEST_SEP) {
     double sx = 0.0, sy = 0.0;
-    for (int j = 0; j < d; ++j) { sx += x[j]; sy += y[j]; }
-    return exp(sx) * th[0] * exp(-sy);
+#pragma unroll
+    for (int j = 0; j < d; ++j) { sx += c[j]; sy += c[d + dt + j]; }
+    return exp(sx) * th0 * exp(-sy);
   }
   double r2 = 0.0;
-  for (int j = 0; j < d; ++j) { const double t = x[j] - y[j]; r2 += t * t; }
+#pragma unroll
+  for (int j = 0; j < d; ++j) { const double t = c[j] - c[d + dt + j]; r2 += t * t; }
   const double r = sqrt(r2);
   switch (kind) {
-    case TTK_SE: { const double u = r / th[0]; return exp(-u * u); }
-    case TTK_EXPONENTIAL: return exp(-r / th[0]);
-    case TTK_MATERN32: { const double a = 1.7320508075688772 * r / th[0]; return (1.0 + a) * exp(-a); }
+    case TTK_SE: { const double u = r / th0; return exp(-u * u); }
+    case TTK_EXPONENTIAL: return exp(-r / th0);
+    case TTK_MATERN32: { const double a = 1.7320508075688772 * r / th0; return (1.0 + a) * exp(-a); }
     case TTK_MATERN52: {
-      const double a = 2.23606797749979 * r / th[0];
+      const double a = 2.23606797749979 * r / th0;
       return (1.0 + a + a * a / 3.0) * exp(-a);
     }
-    case TTK_MATERN_NU: return matern_general(r, th[0], kconst);
-    case TTK_MATERN: return matern_general(r, th[0], th[1]);
-    case TTK_MULTIQUADRIC: { const double u = r / th[0]; return sqrt(1.0 + u * u); }
-    case TTK_TPS: { const double u = r2 / (th[0] * th[0]); return u > 0.0 ? u * log(u) : 0.0; }
+    case TTK_MATERN_NU: return G ? matern_general(r, th0, kconst) : __builtin_nan("");
+    case TTK_MATERN: return G ? matern_general(r, th0, th1) : __builtin_nan("");
+    case TTK_MULTIQUADRIC: { const double u = r / th0; return sqrt(1.0 + u * u); }
+    case TTK_TPS: { const double u = r2 / (th0 * th0); return u > 0.0 ? u * log(u) : 0.0; }
     case TTK_LAPLACE3D: return 1.0 / r;
     case TTK_LAPLACE2D: return -log(r);
     case TTK_BIHARMONIC: return 1.0 / r2;

@@ -1,8 +1,9 @@
 """Writes tests/golden/<workload>_oracle.npz: the oracle's offline stage (TT
 greedy-cross, rounding, gauge) for a workload of synth.WORKLOADS, so the
-full-size GPU parity tests need not rerun the slow CPU cross.  The cross does
-not depend on the points; the stored cores, ranks and index sets are the
-oracle's alone (this script calls only oracle/ and synth/).
+full-size GPU parity tests need not rerun the free-running CPU cross.  The
+cross does not depend on the points; the stored cores, ranks, index sets,
+decision log and per-sweep errors are the oracle's alone (this script calls
+only oracle/ and synth/).
 
 usage: python tests/golden/make_oracle_offline.py matern32_d3
 """
@@ -35,6 +36,12 @@ def main(name):
         arrays[f"right{k}"] = np.asarray(info["R"][k], dtype=np.int32)
     margins = [min(r.get("sample_margin", np.inf), r.get("search_margin", np.inf)) for r in info["log"]]
     arrays["min_margin"] = np.array(min(margins) if margins else np.inf)
+    # the decision log: pivot (row, col) of each step, whether it was added,
+    # and the step's smaller top-2 margin (a tie within rounding when tiny)
+    arrays["log_pivot"] = np.array([[r["pivot_row"], r["pivot_col"], int(r["added"])] for r in info["log"]],
+                                   dtype=np.int64).reshape(-1, 3)
+    arrays["log_margin"] = np.array(margins, dtype=np.float64)
+    arrays["errors"] = np.array(info["errors"], dtype=np.float64)
     path = os.path.join(HERE, f"{name}_oracle.npz")
     np.savez_compressed(path, **arrays)
     print(path, out["ranks"], info["ranks"], info["sweeps"])

@@ -1,11 +1,13 @@
 """Full-size GPU checks, in the launch configurations bench.py times.
 
 - matern32_d3 (the benchmark workload, 100k + 100k points, float32): the
-  oracle's cross for the same problem is stored in tests/golden (written by
-  tests/golden/make_oracle_offline.py from oracle/ alone).  The GPU build must
-  reproduce its ranks and index sets; sampled rows of U and V, and the apply
-  and backward on inputs supported on sampled points, are compared with the
-  oracle computing those entries one by one.
+  oracle replays the GPU's cross decisions (each must lie in the oracle's own
+  tie band) and reaches the same index sets, ranks and stopping error; the
+  free-running oracle's decision log, stored in tests/golden (written by
+  tests/golden/make_oracle_offline.py from oracle/ alone), must agree up to
+  the first step that is a tie within rounding.  Sampled rows of U and V, and
+  the apply and backward on inputs supported on sampled points, are compared
+  with the oracle computing those entries one by one from the replay's cores.
 - se_d2_fp64 (2000 + 2000 points, float64): everything against a live oracle
   run, including U M V^T on the full 2000 x 2000 block.
 - The Global-1 (200k points), batched (1M + 1M points, 4096 thetas) and
@@ -64,6 +66,7 @@ def adjoint_gap(dX, x, g, y, chunk=256):
 def test_benchmark_workload_full_size_matches_oracle():
     torch = _torch()
     import paper_2406_06344_amd as pkg
+    from oracle import cross as ocross
     w = synth.WORKLOADS["matern32_d3"]
     say(f"[full] {w.name}: build on {w.n_src} + {w.n_tgt} points")
     g = np.load(os.path.join(GOLDEN, "matern32_d3_oracle.npz"))
@@ -76,26 +79,51 @@ def test_benchmark_workload_full_size_matches_oracle():
                                       seed=0)
     inf = kern.info()
     say(f"  ranks {inf['ranks']} cross {inf['cross_ranks']} sweeps {inf['sweeps']} min margin {inf['min_margin']:.2e}")
-    assert inf["ranks"] == list(g["ranks"])
-    assert inf["cross_ranks"] == list(g["cross_ranks"])
-    assert inf["sweeps"] == int(g["sweeps"])
-    L, R, _ = kern.cross_record()
+    L, R, log = kern.cross_record()
     D = inf["D"]
-    for k in range(1, D):
-        assert np.array_equal(L[k], g[f"left{k}"]), k
-        assert np.array_equal(R[k], g[f"right{k}"]), k
-    # rounded cores: the two TTs agree at sampled multi-indices
-    Gg = kern.cores()
-    Go = [g[f"core{k}"] for k in range(D)]
-    rng = np.random.default_rng(21)
+    d, dt = w.d, w.d_theta
     P = okernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param)
+    # 1. the oracle replays the GPU's decisions: each one lies in the oracle's
+    #    own tie band, and the replay reaches the same index sets, ranks,
+    #    sweep count and stopping error
+    forced = [{"sample_pos": r["sample_pos"], "pivot_row": r["pivot_row"], "pivot_col": r["pivot_col"],
+               "added": r["added"]} for r in log]
+    cross_cores, rep = ocross.greedy_cross(ocross.Entries(P.entries, P.n), w.tol, seed=0, forced=forced)
+    bad = [i for i, r in enumerate(rep["log"])
+           if not (r["replay_sample_ok"] and r["replay_search_ok"] and r["replay_add_ok"])]
+    assert not bad, bad[:5]
+    assert inf["cross_ranks"] == rep["ranks"] and inf["sweeps"] == rep["sweeps"]
+    for k in range(1, D):
+        assert np.array_equal(L[k], rep["L"][k]), k
+        assert np.array_equal(R[k], rep["R"][k]), k
+    say(f"  stopping error: gpu {inf['sampled_error']:.6e} oracle replay {rep['error']:.6e}")
+    assert abs(inf["sampled_error"] - rep["error"]) <= 1e-4 * rep["error"]
+    # 2. against the free-running oracle (stored): identical decisions up to
+    #    the first step whose top-2 margin is a tie within rounding; with no
+    #    such divergence, the same ranks and sweep count
+    lp, lm = g["log_pivot"], g["log_margin"]
+    n_same = 0
+    for a, r in zip(lp, log):
+        if (int(a[0]), int(a[1]), int(a[2])) != (r["pivot_row"], r["pivot_col"], int(r["added"])):
+            assert lm[n_same] < 1e-9, (n_same, lm[n_same])
+            break
+        n_same += 1
+    say(f"  decisions {len(log)}, identical to the free-running oracle for the first {n_same} "
+        f"(free-running: {len(lp)} decisions, cross ranks {list(g['cross_ranks'])})")
+    if n_same == len(lp) == len(log):
+        assert inf["cross_ranks"] == list(g["cross_ranks"]) and inf["sweeps"] == int(g["sweeps"])
+    # rounded cores from the replay's cross: same ranks, and the two TTs agree
+    # at sampled multi-indices
+    Go = opttk.round_and_gauge(cross_cores, w.tol, d, dt)
+    assert inf["ranks"] == [1] + [c.shape[2] for c in Go]
+    Gg = kern.cores()
+    rng = np.random.default_rng(21)
     idx = np.stack([rng.integers(0, nj, 20000) for nj in P.n], axis=1)
     vo = ott.evaluate(Go, idx)
     assert np.abs(ott.evaluate(Gg, idx) - vo).max() <= 1e-10 * np.abs(vo).max()
     # sampled rows of U and V against the oracle's Phase 3 at those points
     si = np.sort(rng.choice(w.n_src, 2000, replace=False))
     ti = np.sort(rng.choice(w.n_tgt, 2000, replace=False))
-    d, dt = w.d, w.d_theta
     S = opttk.phase3_source(opttk.factor_values(X[si], P.box_s, w.n_spatial), Go[:d])
     T = opttk.phase3_target(opttk.factor_values(Y[ti], P.box_t, w.n_spatial), Go[d + dt:])
     U, V = kern.factors()
