@@ -59,6 +59,10 @@ struct StepRes {
   double q_max, q_margin, q_scale, q_tau;
   double pivot_abs, pad;
   int32_t ctr, pad2;   // blocks done in the current residual launch (reset by the last)
+  // running max |entry| of the step's evaluations, spread over AMAX_SLOTS
+  // slots (block b folds into slot b mod AMAX_SLOTS) to avoid one contended
+  // address; cleared at the end of every step
+  double s_slot[AMAX_SLOTS], q_slot[AMAX_SLOTS];
 };
 
 __device__ inline double wsum(double v) {
@@ -162,6 +166,22 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
   B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
 }
 
+// True in every thread of the block that finishes last among the blocks of
+// the launch (the results of every block are then visible to it); *ctr counts
+// finished blocks and is reset by the last one.
+__device__ inline bool last_block(int32_t* ctr) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_last = atomicAdd(ctr, 1) == (int)gridDim.x - 1;
+    if (s_last) *ctr = 0;
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last;
+}
+
 // TT value at test multi-indices: cores given column-major C_k
 // ((r_{k-1} n_k) x r_k), entry C_k[s, i, t] = C_k[(s + i r_{k-1}) + t r_{k-1} n_k].
 // One block of 256 threads per point.  Per core the block forms
@@ -170,13 +190,15 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
 // partial sums of a column are reduced by shuffles.  The running vector sits
 // in LDS between cores and in registers (v[l + 16 c] in lane l's slot c)
 // during a core.
+constexpr int TEST_SLOTS = 64;
 struct TTView {
   const double* C[MAXD];
   int r[MAXD + 1];
   int m[MAXD];
   int D;
 };
-__global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx, int P, double* out) {
+__global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx, int P, const double* vals,
+                                                   double* err) {
   __shared__ double v[MAXR];
   const int p = blockIdx.x;
   if (p >= P) return;
@@ -208,20 +230,12 @@ __global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[p] = v[0];
-}
-
-__global__ void k_err_max(const double* a, const double* b, int n, double* out) {
-  __shared__ double red[1024];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(a[i] - b[i]));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = red[0];
+  // |vals[p] - v| folded into err[p mod TEST_SLOTS] (cleared beforehand;
+  // non-negative doubles order like their bit patterns, so an integer atomic
+  // max is exact); the host takes the max of the slots
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(err + p % TEST_SLOTS),
+              (unsigned long long)__double_as_longlong(fabs(vals[p] - v[0])));
 }
 
 __global__ void k_zero1(double* p) {
@@ -280,72 +294,95 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
-// MAXR): one thread per row, so a wave's loads are contiguous.
+// MAXR, so a wave's loads are contiguous).  With r rounded up to 64 as ru,
+// min(4, BS / ru) threads share a row, each over a contiguous range of q with
+// eight loads in flight; the partial sums meet in scratch (BS doubles).  Every
+// thread of the block calls it; out is visible to all on return.
 template <int BS>
-__device__ inline void row_dots(const double* M, const double* v, int r, double* out) {
-  for (int t = threadIdx.x; t < r; t += BS) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = 0;
-    for (; q + 3 < r; q += 4) {
-      s0 += M[t + (int64_t)q * MAXR] * v[q];
-      s1 += M[t + (int64_t)(q + 1) * MAXR] * v[q + 1];
-      s2 += M[t + (int64_t)(q + 2) * MAXR] * v[q + 2];
-      s3 += M[t + (int64_t)(q + 3) * MAXR] * v[q + 3];
+__device__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch) {
+  const int ru = (r + 63) & ~63;
+  const int S = min(4, BS / ru);
+  const int tid = threadIdx.x, t = tid % ru, h = tid / ru;
+  double acc = 0.0;
+  if (h < S && t < r) {
+    const int chunk = (r + S - 1) / S;
+    const int q0 = h * chunk, q1 = min(r, q0 + chunk);
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int q = q0;
+    for (; q + 7 < q1; q += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += M[t + (int64_t)(q + u) * MAXR] * v[q + u];
     }
-    for (; q < r; ++q) s0 += M[t + (int64_t)q * MAXR] * v[q];
-    out[t] = (s0 + s1) + (s2 + s3);
+    for (; q < q1; ++q) a[0] += M[t + (int64_t)q * MAXR] * v[q];
+    acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
+  scratch[tid] = acc;
+  __syncthreads();
+  if (tid < r) {
+    double sum = scratch[tid];
+    for (int k = 1; k < S; ++k) sum += scratch[tid + k * ru];
+    out[tid] = sum;
+  }
+  __syncthreads();
 }
 
 // Robust argmax of |R| over the whole block (lowest key within tau of the
 // max) and the relative top-2 margin; stage 0 = sample stage (also records
 // row/col of the chosen sample), stage 1 = search stage.  The sample list is
 // in generation order, so its key is the linear position row * cols + col;
-// the searched fibre is in natural order.
+// the searched fibre is in natural order.  Wave shuffles, then one LDS stage.
 template <int BS>
 __device__ void select_block(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
                              double scale, StepRes* res) {
-  __shared__ double sv[BS];
-  __shared__ int sk[BS], si[BS];
-  const int tid = threadIdx.x;
+  constexpr int NWV = BS / 64;
+  __shared__ double sv[NWV];
+  __shared__ int sk[NWV], si[NWV];
+  __shared__ double s_mx;
+  __shared__ int s_p;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double tau = TIE_REL * scale;
   double m = -1.0;
   for (int i = tid; i < n; i += BS) m = fmax(m, fabs(R[i]));
-  sv[tid] = m;
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if (lane == 0) sv[w] = m;
   __syncthreads();
-  for (int s = BS / 2; s > 0; s >>= 1) {
-    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
-    __syncthreads();
+  if (tid == 0) {
+    double x = sv[0];
+    for (int k = 1; k < NWV; ++k) x = fmax(x, sv[k]);
+    s_mx = x;
   }
-  const double mx = sv[0];
   __syncthreads();
+  const double mx = s_mx;
   int best = 0x7fffffff, bi = 0x7fffffff;
   for (int i = tid; i < n; i += BS)
     if (fabs(R[i]) >= mx - tau) {
       const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
       if (key < best) { best = key; bi = i; }
     }
-  sk[tid] = best;
-  si[tid] = bi;
-  __syncthreads();
-  for (int s = BS / 2; s > 0; s >>= 1) {
-    if (tid < s && sk[tid + s] < sk[tid]) { sk[tid] = sk[tid + s]; si[tid] = si[tid + s]; }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    const int ob = __shfl_xor(best, o, 64), oi = __shfl_xor(bi, o, 64);
+    if (ob < best) { best = ob; bi = oi; }
   }
-  // (no candidate compares, e.g. all residuals NaN: fall back to the first)
-  const int p = si[0] < n ? si[0] : 0;
+  if (lane == 0) { sk[w] = best; si[w] = bi; }
+  __syncthreads();
+  if (tid == 0) {
+    int b = sk[0], ii = si[0];
+    for (int k = 1; k < NWV; ++k)
+      if (sk[k] < b) { b = sk[k]; ii = si[k]; }
+    s_p = ii < n ? ii : 0;   // (no candidate compares, e.g. all residuals NaN: the first)
+  }
+  __syncthreads();
+  const int p = s_p;
   double sec = 0.0;
   for (int i = tid; i < n; i += BS)
     if (i != p) sec = fmax(sec, fabs(R[i]));
+  for (int o = 32; o > 0; o >>= 1) sec = fmax(sec, __shfl_xor(sec, o, 64));
+  if (lane == 0) sv[w] = sec;
   __syncthreads();
-  sv[tid] = sec;
-  __syncthreads();
-  for (int s = BS / 2; s > 0; s >>= 1) {
-    if (tid < s) sv[tid] = fmax(sv[tid], sv[tid + s]);
-    __syncthreads();
-  }
   if (tid == 0) {
-    const double margin = mx > 0.0 ? (mx - sv[0]) / mx : 0.0;
+    for (int k = 1; k < NWV; ++k) sec = fmax(sec, sv[k]);
+    sec = fmax(sec, sv[0]);
+    const double margin = mx > 0.0 ? (mx - sec) / mx : 0.0;
     if (stage == 0) {
       res->s_pos = p; res->s_max = mx; res->s_margin = margin; res->s_tau = tau;
       res->l = srow[p]; res->t = scol[p];
@@ -353,32 +390,25 @@ __device__ void select_block(const double* R, int n, const int32_t* srow, const 
       res->q_scale = scale;             // the search stage widens this scale
     } else {
       res->q_pos = p; res->q_max = mx; res->q_margin = margin; res->q_tau = tau;
+      res->q_scale = scale;
       res->pivot_abs = fabs(R[p]);
     }
   }
 }
 
-// True in every thread of the block that finishes last among the blocks of
-// the launch (its residuals, and everyone else's, are then visible).
-__device__ inline bool last_block(StepRes* res) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s_last = atomicAdd(&res->ctr, 1) == (int)gridDim.x - 1;
-    if (s_last) res->ctr = 0;
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last;
+// max of the AMAX_SLOTS slots of a fold
+__device__ inline double slots_max(const double* sl) {
+  double m = 0.0;
+  for (int i = 0; i < AMAX_SLOTS; ++i) m = fmax(m, sl[i]);
+  return m;
 }
 
 // Sample stage: residuals R_i = A(s_i, J) P^{-1} A(I, s_i) - A(s_i) of the
 // sampled entries, written as the row-wise dot product of G = A(s, J) W and
 // T = (Li A(I, s))^T, both 16-sample tiles formed with FP64 MFMA
 // (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16], D row
-// l / 16 + 4 v, column l % 16 in lane l, slot v), then the selection in the
-// last block.  AsJ and AIs hold A(s_i, J_q) and A(I_q, s_i) at i + q ns.  The
+// l / 16 + 4 v, column l % 16 in lane l, slot v).  AsJ and AIs hold
+// A(s_i, J_q) and A(I_q, s_i) at i + q ns.  The
 // block's A operands are staged once in LDS in lane order (dynamic, 2 x 64 x
 // ceil(r / 4) doubles); the B operands (rows of W^T and Li) stream from L2,
 // eight MFMA steps of loads in flight per batch.
@@ -386,8 +416,7 @@ constexpr int SW = 4;   // waves per block; one block per 16 samples
 constexpr int SB = 8;   // MFMA steps per batch of B loads
 __global__ void __launch_bounds__(SW * 64) k_sample_resid(const double* AsJ, const double* AIs, const double* As,
                                                           int ns, int r, const double* Li, const double* W,
-                                                          double* R, const int32_t* srow, const int32_t* scol,
-                                                          int cols, const double* luamax, StepRes* res) {
+                                                          double* R) {
   extern __shared__ double sa[];
   __shared__ double red[SW][16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -442,8 +471,13 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(const double* AsJ, con
     for (int w = 0; w < SW; ++w) s += red[w][tid];
     R[i0 + tid] = s - As[i0 + tid];
   }
-  if (!last_block(res)) return;
-  select_block<SW * 64>(R, ns, srow, scol, cols, 0, fmax(res->s_scale, *luamax), res);
+}
+
+// Sample-stage selection over the residuals of k_sample_resid (one block).
+__global__ void __launch_bounds__(1024) k_sample_select(const double* R, int ns, const int32_t* srow,
+                                                        const int32_t* scol, int cols, const double* luamax,
+                                                        StepRes* res) {
+  select_block<1024>(R, ns, srow, scol, cols, 0, fmax(slots_max(res->s_slot), *luamax), res);
 }
 
 // dynamic LDS of k_sample_resid for rank r
@@ -452,38 +486,45 @@ inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof
 // Search stage: x = (u W) Li for the row of the chosen sample (bit 1, u =
 // A(l, J)) or x = W (Li u) for its column (bit 0, u = A(I, t)), both P^{-1}
 // applied to one vector (every block forms x itself); then R_i = sum_q
-// Lm[i + q n] x_q - Ad[i] over the fibre, and the selection in the last block.
+// Lm[i + q n] x_q - Ad[i] over the fibre, 64 entries per block with four
+// threads on each, and the selection in the last block.
 constexpr int QB = 256;
+constexpr int QR = 64;   // fibre entries per block
 __global__ void __launch_bounds__(QB) k_search_resid(int bit, const double* u, const double* Lm, const double* Ad,
                                                      int n, int r, const double* Li, const double* W, double* R,
                                                      int cols, StepRes* res) {
-  __shared__ double su[MAXR], sy[MAXR], sx[MAXR];
-  for (int q = threadIdx.x; q < r; q += QB) su[q] = u[q];
+  __shared__ double su[MAXR], sy[MAXR], sx[MAXR], scr[QB];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < r; q += QB) su[q] = u[q];
   __syncthreads();
   if (bit) {
-    row_dots<QB>(W + FT, su, r, sy);    // W^T u
-    __syncthreads();
-    row_dots<QB>(Li + FT, sy, r, sx);   // Li^T (W^T u)
+    row_dots<QB>(W + FT, su, r, sy, scr);    // W^T u
+    row_dots<QB>(Li + FT, sy, r, sx, scr);   // Li^T (W^T u)
   } else {
-    row_dots<QB>(Li, su, r, sy);
-    __syncthreads();
-    row_dots<QB>(W, sy, r, sx);
+    row_dots<QB>(Li, su, r, sy, scr);        // Li u
+    row_dots<QB>(W, sy, r, sx, scr);         // W (Li u)
   }
-  __syncthreads();
-  for (int i = blockIdx.x * QB + threadIdx.x; i < n; i += gridDim.x * QB) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = 0;
-    for (; q + 3 < r; q += 4) {
-      s0 += Lm[i + (int64_t)q * n] * sx[q];
-      s1 += Lm[i + (int64_t)(q + 1) * n] * sx[q + 1];
-      s2 += Lm[i + (int64_t)(q + 2) * n] * sx[q + 2];
-      s3 += Lm[i + (int64_t)(q + 3) * n] * sx[q + 3];
+  {
+    const int i = blockIdx.x * QR + (tid & (QR - 1)), h = tid / QR;
+    const int chunk = (r + QB / QR - 1) / (QB / QR);
+    const int q0 = h * chunk, q1 = min(r, q0 + chunk);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (i < n) {
+      int q = q0;
+      for (; q + 3 < q1; q += 4) {
+        a0 += Lm[i + (int64_t)q * n] * sx[q];
+        a1 += Lm[i + (int64_t)(q + 1) * n] * sx[q + 1];
+        a2 += Lm[i + (int64_t)(q + 2) * n] * sx[q + 2];
+        a3 += Lm[i + (int64_t)(q + 3) * n] * sx[q + 3];
+      }
+      for (; q < q1; ++q) a0 += Lm[i + (int64_t)q * n] * sx[q];
     }
-    for (; q < r; ++q) s0 += Lm[i + (int64_t)q * n] * sx[q];
-    R[i] = ((s0 + s1) + (s2 + s3)) - Ad[i];
+    scr[tid] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (tid < QR && i < n) R[i] = ((scr[tid] + scr[tid + QR]) + (scr[tid + 2 * QR] + scr[tid + 3 * QR])) - Ad[i];
   }
-  if (!last_block(res)) return;
-  select_block<QB>(R, n, nullptr, nullptr, cols, 1, res->q_scale, res);
+  if (!last_block(&res->ctr)) return;
+  select_block<QB>(R, n, nullptr, nullptr, cols, 1, fmax(res->q_scale, slots_max(res->q_slot)), res);
 }
 
 // End of a step, one block: the pivot (l, t) from the two stages; it is added
@@ -492,14 +533,14 @@ __global__ void __launch_bounds__(QB) k_search_resid(int bit, const double* u, c
 // A(l, J) and d = A(l, t) are evaluated here and the factors bordered,
 // u = Li b, g = W^T c, s = d - g^T u,
 //   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
-// (leading dimension MAXR).  Clears the sample-stage scale for the next step.
+// (leading dimension MAXR).  Clears the fold slots for the next step.
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* res, int bit, const int32_t* I,
                                                      const int32_t* J, int r, int max_rank, double* Li, double* W,
                                                      double* amax, int32_t* info) {
   constexpr int D = 2 * d + dt;
   __shared__ double sn[D * MAXN];
-  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR];
+  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[256];
   __shared__ double s_d, s_s;
   __shared__ int s_added, s_row, s_col;
   const int tid = threadIdx.x;
@@ -519,8 +560,11 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
     res->pivot_col = col;
     res->added = added;
     res->info = *info;   // status of the kept factors (non-zero after a singular border)
-    res->s_scale = 0.0;
     s_added = added;
+  }
+  if (tid < AMAX_SLOTS) {   // the next step folds its maxima into cleared slots
+    res->s_slot[tid] = 0.0;
+    res->q_slot[tid] = 0.0;
   }
   __syncthreads();
   if (!s_added) return;
@@ -532,8 +576,8 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
   __syncthreads();
   double* Lit = Li + FT;
   double* Wt = W + FT;
-  row_dots<256>(Li, bv, r, u);    // Li b
-  row_dots<256>(Wt, cv, r, gv);   // W^T c
+  row_dots<256>(Li, bv, r, u, scr);    // Li b
+  row_dots<256>(Wt, cv, r, gv, scr);   // W^T c
   __syncthreads();
   {
     double gu = 0.0, m = 0.0;
@@ -558,8 +602,8 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
     __syncthreads();
   }
   const double is = 1.0 / s_s;
-  row_dots<256>(Lit, gv, r, nl);   // Li^T g, i.e. g^T Li (from the old factors)
-  row_dots<256>(W, u, r, nw);      // W u
+  row_dots<256>(Lit, gv, r, nl, scr);   // Li^T g, i.e. g^T Li (from the old factors)
+  row_dots<256>(W, u, r, nw, scr);      // W u
   __syncthreads();
   for (int e = tid; e <= 2 * r + 1; e += 256) {
     if (e < r) {
@@ -582,6 +626,114 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
     }
   }
 }
+
+// Every fibre F_k = X(I^{<=k-1}, i_k, I^{>k}) ((r_{k-1} n_k) x r_k,
+// column-major) of the stopping test in one launch; block ranges per core
+// (blk[j] .. blk[j + 1]) so that the core is uniform over a block.
+struct CoreEval {
+  Addr a[MAXD];
+  double* out[MAXD];
+  int nr[MAXD];
+  int64_t size[MAXD];
+  int blk[MAXD + 1];
+  int n;
+};
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_eval_cores(KSpec ks, CoreEval ce, double* clear) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  if (blockIdx.x == 0 && threadIdx.x < TEST_SLOTS) clear[threadIdx.x] = 0.0;   // the stopping test's error slots
+  stage_nodes<D>(ks.nodes, sn);
+  int j = 0;
+  while (j + 1 < ce.n && (int)blockIdx.x >= ce.blk[j + 1]) ++j;
+  const int64_t e = (int64_t)(blockIdx.x - ce.blk[j]) * 256 + threadIdx.x;
+  if (e >= ce.size[j]) return;
+  const int nr = ce.nr[j];
+  ce.out[j][e] = addr_eval<d, dt, G>(ks, ce.a[j], sn, (int)(e % nr), (int)(e / nr));
+}
+
+// One 16 x 16 output tile of A B with FP64 MFMA: A (16 rows x 4 nst) in LDS in
+// lane order (step s, lane l at s * 64 + l), B(q, p) = Bt[p + q MAXR] for this
+// lane's column p; SB steps of B loads in flight per batch.
+__device__ inline dbl4 mfma_tile_lds(const double* sa, int nst, const double* Bt, int p, int r, int lane) {
+  const int lk = lane >> 4;
+  const bool pok = p < r;
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < nst; s0 += SB) {
+    double b[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int q = 4 * (s0 + u) + lk;
+      b[u] = (pok && q < r) ? Bt[p + (int64_t)q * MAXR] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u)
+      if (s0 + u < nst) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], b[u], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Cores of the interpolation formula C_k = F_k P_k^{-1} = (F_k W) Li for
+// every k < D in one launch: one block per 16 rows of one core (tile ranges
+// tile[j] .. tile[j + 1]); F rows and then T = F W are held in LDS in lane
+// order (dynamic, 2 x 64 x ceil(r / 4) doubles), W and Li read through their
+// transposes.
+struct CoreSolve {
+  const double* F[MAXD];
+  double* C[MAXD];
+  const double* Li[MAXD];
+  const double* W[MAXD];
+  int m[MAXD], r[MAXD];
+  int tile[MAXD + 1];
+  int n;
+};
+constexpr int CW = 4;   // waves per block
+__global__ void __launch_bounds__(CW * 64) k_solve_cores(CoreSolve cs) {
+  extern __shared__ double lds[];
+  int j = 0;
+  while (j + 1 < cs.n && (int)blockIdx.x >= cs.tile[j + 1]) ++j;
+  const int m = cs.m[j], r = cs.r[j];
+  const int row0 = ((int)blockIdx.x - cs.tile[j]) * 16;
+  const int nst = (r + 3) / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double* sa = lds;
+  double* sb = lds + 64 * nst;
+  const double* F = cs.F[j];
+  for (int e = tid; e < 64 * nst; e += CW * 64) {
+    const int ii = e & 15, q = e >> 4;
+    const int i = row0 + ii;
+    sa[(q >> 2) * 64 + (q & 3) * 16 + ii] = (i < m && q < r) ? F[i + (int64_t)q * m] : 0.0;
+    sb[e] = 0.0;
+  }
+  __syncthreads();
+  const int ntile = (r + 15) / 16;
+  // T = F W, B(q, p) = W(q, p) = W^T[p + q MAXR]; T(i, p) goes to the lane-order
+  // slot of the next product, whose k-index is p
+  for (int jt = wv; jt < ntile; jt += CW) {
+    const int p = jt * 16 + li;
+    const dbl4 t = mfma_tile_lds(sa, nst, cs.W[j] + FT, p, r, lane);
+    if (p < r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sb[(p >> 2) * 64 + (p & 3) * 16 + lk + 4 * v] = t[v];
+  }
+  __syncthreads();
+  // C = T Li, B(q, p) = Li(q, p) = Li^T[p + q MAXR]
+  double* C = cs.C[j];
+  for (int jt = wv; jt < ntile; jt += CW) {
+    const int p = jt * 16 + li;
+    const dbl4 c = mfma_tile_lds(sb, nst, cs.Li[j] + FT, p, r, lane);
+    if (p < r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = row0 + lk + 4 * v;
+        if (row < m) C[row + (int64_t)p * m] = c[v];
+      }
+  }
+}
+
+// dynamic LDS of k_solve_cores for rank r
+inline size_t solve_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
 
 inline int nblk(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
@@ -632,7 +784,7 @@ class Cross {
 
   // device buffers
   DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_;
-  DBuf d_test_idx_, d_test_val_, d_test_hat_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
+  DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
   DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
@@ -949,23 +1101,25 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const double* Li = d_li_[k].as<double>();
   const double* W = d_w_[k].as<double>();
   double* R = d_R_.as<double>();
-  {   // the sample-stage maximum folds into s_scale (cleared by the previous step)
+  {   // the sample-stage maximum folds into the s slots (cleared by the previous step)
     const EvalSeg sg[3] = {{dsr, dJ, ns, rk, 0, AsJ}, {dI, dsc, rk, ns, 1, AIs}, {dsr, dsc, ns, 1, 2, As}};
-    eval_segs(ks_, a, sg, 3, st_, &dres->s_scale);
+    eval_segs(ks_, a, sg, 3, st_, dres->s_slot);
   }
   evals_ += 2 * (int64_t)ns * rk + ns;
   hipLaunchKernelGGL(k_sample_resid, dim3(nblk(ns, 16)), dim3(SW * 64), sample_lds(rk), st_, AsJ, AIs, As, ns, rk,
-                     Li, W, R, dsr, dsc, cols, (const double*)luamax(k), dres);
+                     Li, W, R);
+  hipLaunchKernelGGL(k_sample_select, dim3(1), dim3(1024), 0, st_, (const double*)R, ns, dsr, dsc, cols,
+                     (const double*)luamax(k), dres);
   if (bit == 1) {   // search the row of the sample's pivot
     double* AlJ = S0;
     double* AIall = AlJ + rk;                   // (q, c) at c + q cols
     double* Alall = AIall + (size_t)rk * cols;
     {
       const EvalSeg sg[3] = {{d_l, dJ, 1, rk, 0, AlJ}, {dI, nullptr, rk, cols, 1, AIall}, {d_l, nullptr, 1, cols, 0, Alall}};
-      eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
+      eval_segs(ks_, a, sg, 3, st_, dres->q_slot);
     }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QB)), dim3(QB), 0, st_, 1, (const double*)AlJ,
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QR)), dim3(QB), 0, st_, 1, (const double*)AlJ,
                        (const double*)AIall, (const double*)Alall, cols, rk, Li, W, R, cols, dres);
   } else {          // search the column
     double* AallJ = S0;
@@ -973,10 +1127,10 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
     double* Aallt = AIt + rk;
     {
       const EvalSeg sg[3] = {{nullptr, dJ, rows, rk, 0, AallJ}, {dI, d_t, rk, 1, 0, AIt}, {nullptr, d_t, rows, 1, 0, Aallt}};
-      eval_segs(ks_, a, sg, 3, st_, &dres->q_scale);
+      eval_segs(ks_, a, sg, 3, st_, dres->q_slot);
     }
     evals_ += (int64_t)rows * rk + rk + rows;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QB)), dim3(QB), 0, st_, 0, (const double*)AIt,
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QR)), dim3(QB), 0, st_, 0, (const double*)AIt,
                        (const double*)AallJ, (const double*)Aallt, rows, rk, Li, W, R, cols, dres);
   }
   // decide, and border the factors of P_k with the pivot's column, row and
@@ -1030,34 +1184,56 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
 }
 
 // Cores of the cross interpolant, column-major C_k ((r_{k-1} n_k) x r_k):
-// C_k = F_k P_k^{-1} with the kept inverse, C_D = F_D.
+// C_k = F_k P_k^{-1} with the kept factors, C_D = F_D.  One upload of the
+// index sets, one launch for every fibre, one for every product.
 tt_status Cross::build_cores(std::vector<double*>* C) {
   const int N = N_;
   C->assign(N, nullptr);
   arena_reset();
+  CoreEval ce{};
+  ce.n = N;
+  int nb = 0;
   for (int k = 1; k <= N; ++k) {
     const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
     const int m = r0 * n;
     TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
-    TTK_TRY(arena_flush());
     TTK_TRY(d_core_[k - 1].alloc((size_t)m * r1 * sizeof(double)));
-    double* F = d_core_[k - 1].as<double>();
-    eval_product(ks_, fibre_addr(k), nullptr, m, nullptr, r1, F, st_);
+    ce.a[k - 1] = fibre_addr(k);
+    ce.out[k - 1] = d_core_[k - 1].as<double>();
+    ce.nr[k - 1] = m;
+    ce.size[k - 1] = (int64_t)m * r1;
+    ce.blk[k - 1] = nb;
+    nb += nblk(ce.size[k - 1], 256);
     evals_ += (int64_t)m * r1;
-    if (k == N) {
-      (*C)[k - 1] = F;
-      continue;
-    }
-    TTK_TRY(d_cint_[k - 1].alloc((size_t)m * r1 * sizeof(double)));
-    TTK_TRY(solve_right(k, m, F, d_cint_[k - 1].as<double>()));
+  }
+  ce.blk[N] = nb;
+  TTK_TRY(arena_flush());
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_cores<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(nb),
+                       dim3(256), 0, st_, ks_, ce, d_err_.as<double>());
+  });
+  CoreSolve cs{};
+  cs.n = N - 1;
+  int nt = 0, rmax = 1;
+  for (int k = 1; k < N; ++k) {
+    const int m = rank(k - 1) * g_.n[k - 1], r = rank(k);
+    TTK_TRY(d_cint_[k - 1].alloc((size_t)m * r * sizeof(double)));
+    cs.F[k - 1] = d_core_[k - 1].as<double>();
+    cs.C[k - 1] = d_cint_[k - 1].as<double>();
+    cs.Li[k - 1] = d_li_[k].as<double>();
+    cs.W[k - 1] = d_w_[k].as<double>();
+    cs.m[k - 1] = m;
+    cs.r[k - 1] = r;
+    cs.tile[k - 1] = nt;
+    nt += nblk(m, 16);
+    rmax = std::max(rmax, r);
     (*C)[k - 1] = d_cint_[k - 1].as<double>();
   }
+  cs.tile[N - 1] = nt;
+  (*C)[N - 1] = d_core_[N - 1].as<double>();
+  if (nt > 0)
+    hipLaunchKernelGGL(k_solve_cores, dim3(nt), dim3(CW * 64), solve_lds(rmax), st_, cs);
   TTK_HIP(hipGetLastError());
-  std::vector<int32_t> info(MAXD, 0);
-  TTK_HIP(hipMemcpyAsync(info.data(), luinfo(0), MAXD * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-  TTK_TRY(sync());
-  for (int k = 1; k < N; ++k)
-    if (info[k] != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
   return TTK_OK;
 }
 
@@ -1103,13 +1279,18 @@ tt_status Cross::sampled_error(double* err) {
   tv.D = N_;
   for (int k = 0; k < N_; ++k) { tv.C[k] = C[k]; tv.m[k] = rank(k) * g_.n[k]; }
   for (int k = 0; k <= N_; ++k) tv.r[k] = rank(k);
-  hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(),
-                     n_test_, d_test_hat_.as<double>());
-  hipLaunchKernelGGL(k_err_max, dim3(1), dim3(1024), 0, st_, d_test_val_.as<double>(),
-                     d_test_hat_.as<double>(), n_test_, d_err_.as<double>());
-  double e = 0.0;
-  TTK_HIP(hipMemcpyAsync(&e, d_err_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
+  hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(), n_test_,
+                     (const double*)d_test_val_.as<double>(), d_err_.as<double>());
+  TTK_HIP(hipGetLastError());
+  // the error and the status of every P_k's factors in one copy each
+  double slots[TEST_SLOTS];
+  std::vector<int32_t> info(MAXD, 0);
+  TTK_HIP(hipMemcpyAsync(info.data(), luinfo(0), MAXD * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  TTK_HIP(hipMemcpyAsync(slots, d_err_.p, sizeof(slots), hipMemcpyDeviceToHost, st_));
   TTK_TRY(sync());
+  for (int k = 1; k < N_; ++k)
+    if (info[k] != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
+  const double e = *std::max_element(slots, slots + TEST_SLOTS);
   *err = test_max_ > 0 ? e / test_max_ : e;
   return TTK_OK;
 }
@@ -1132,8 +1313,7 @@ tt_status Cross::run(CrossOut* out) {
       for (int j = 0; j < N; ++j) idx[(size_t)p * N + j] = (int16_t)g.below((uint64_t)g_.n[j]);
     TTK_TRY(d_test_idx_.alloc(idx.size() * sizeof(int16_t)));
     TTK_TRY(d_test_val_.alloc((size_t)n_test_ * sizeof(double)));
-    TTK_TRY(d_test_hat_.alloc((size_t)n_test_ * sizeof(double)));
-    TTK_TRY(d_err_.alloc(2 * sizeof(double)));
+    TTK_TRY(d_err_.alloc(TEST_SLOTS * sizeof(double)));
     TTK_HIP(hipMemcpyAsync(d_test_idx_.p, idx.data(), idx.size() * sizeof(int16_t), hipMemcpyHostToDevice, st_));
     eval_multi16(ks_, d_test_idx_.as<int16_t>(), n_test_, d_test_val_.as<double>(), st_);
     evals_ += n_test_;
@@ -1147,6 +1327,9 @@ tt_status Cross::run(CrossOut* out) {
   if (sample_lds(MAXR) > 48 * 1024)
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample_resid),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR)));
+  if (solve_lds(MAXR) > 48 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_cores),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
   // step state: the block counter and the sample-stage scale start at zero
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   fill_zero(d_res_.p, sizeof(StepRes), st_);

@@ -13,9 +13,9 @@ namespace {
 
 constexpr int EB = 256;   // threads per evaluation block
 
-// Block-wide max of |value| folded into *amax with one atomic per block
-// (non-negative doubles order like their bit patterns, so an integer atomic
-// max is exact).
+// Block-wide max of |value| folded into amax[b mod AMAX_SLOTS] for block b
+// with one atomic per block (non-negative doubles order like their bit
+// patterns, so an integer atomic max is exact).
 __device__ inline void fold_amax(double v, double* amax) {
   __shared__ double red[EB / 64];
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -23,7 +23,8 @@ __device__ inline void fold_amax(double v, double* amax) {
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
-    atomicMax(reinterpret_cast<unsigned long long*>(amax), (unsigned long long)__double_as_longlong(v));
+    atomicMax(reinterpret_cast<unsigned long long*>(amax + (blockIdx.x % AMAX_SLOTS)),
+              (unsigned long long)__double_as_longlong(v));
   }
 }
 

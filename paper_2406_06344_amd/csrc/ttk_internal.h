@@ -93,7 +93,8 @@ struct Addr {
   int nm0, nm1;          // node counts of the middle dims
 };
 // out[i + j*nr] = A(rows[i], cols[j]) (out[j + i*nc] when trans_out); rows/cols
-// NULL = all rows/cols.  amax (device, may be NULL): max |value| folded in.
+// NULL = all rows/cols.  amax (device, may be NULL): max |value| folded into
+// AMAX_SLOTS slots as for eval_segs.
 void eval_product(const KSpec& ks, const Addr& a, const int32_t* rows, int nr,
                   const int32_t* cols, int nc, double* out, hipStream_t st,
                   double* amax = nullptr, bool trans_out = false);
@@ -105,9 +106,12 @@ struct EvalSeg {
   int nr, nc, mode;
   double* out;
 };
+// amax (device, may be NULL): AMAX_SLOTS doubles; block b folds its max
+// |value| into slot b mod AMAX_SLOTS (one contended address would serialise).
+constexpr int AMAX_SLOTS = 32;
 void eval_segs(const KSpec& ks, const Addr& a, const EvalSeg* segs, int nseg, hipStream_t st,
                double* amax);
-// out[i] = A(rows[i], cols[i])
+// out[i] = A(rows[i], cols[i]); amax as for eval_product
 void eval_list(const KSpec& ks, const Addr& a, const int32_t* rows, const int32_t* cols,
                int np, double* out, hipStream_t st, double* amax = nullptr);
 // out[i] = f_kappa at multi-index idx[i*D .. i*D+D-1] (int16 or int32)
