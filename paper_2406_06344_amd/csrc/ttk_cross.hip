@@ -37,6 +37,7 @@
 // only Li and W carry).
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -527,47 +528,19 @@ __global__ void __launch_bounds__(QB) k_search_resid(int bit, const double* u, c
   select_block<QB>(R, n, nullptr, nullptr, cols, 1, fmax(res->q_scale, slots_max(res->q_slot)), res);
 }
 
-// End of a step, one block: the pivot (l, t) from the two stages; it is added
-// if its residual exceeds the tie band, it is not yet in I or J and the rank
-// is below the cap.  Then, if added, the border of P_k: b = A(I, t), c =
-// A(l, J) and d = A(l, t) are evaluated here and the factors bordered,
+// The border of P_k's factors for the pivot (row, col) added by step k:
+// b = A(I, t), c = A(l, J) and d = A(l, t) are evaluated here, then
 // u = Li b, g = W^T c, s = d - g^T u,
 //   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
-// (leading dimension MAXR).  Clears the fold slots for the next step.
+// (leading dimension MAXR, transposes alongside).  Every thread of the block
+// calls it.
 template <int d, int dt, bool G>
-__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* res, int bit, const int32_t* I,
-                                                     const int32_t* J, int r, int max_rank, double* Li, double* W,
-                                                     double* amax, int32_t* info) {
-  constexpr int D = 2 * d + dt;
-  __shared__ double sn[D * MAXN];
+__device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn, StepRes* res, const int32_t* I,
+                               const int32_t* J, int r, int row, int col, double* Li, double* W, double* amax,
+                               int32_t* info) {
   __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[256];
   __shared__ double s_d, s_s;
-  __shared__ int s_added, s_row, s_col;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    s_row = bit ? res->l : res->q_pos;
-    s_col = bit ? res->q_pos : res->t;
-  }
-  stage_nodes<D>(ks.nodes, sn);
-  const int row = s_row, col = s_col;
-  int stale = 0;
-  for (int q = tid; q < r; q += 256)
-    if (I[q] == row || J[q] == col) stale = 1;
-  stale = __syncthreads_or(stale);
-  if (tid == 0) {
-    const int added = (res->pivot_abs > res->q_tau && !stale && r < max_rank) ? 1 : 0;
-    res->pivot_row = row;
-    res->pivot_col = col;
-    res->added = added;
-    res->info = *info;   // status of the kept factors (non-zero after a singular border)
-    s_added = added;
-  }
-  if (tid < AMAX_SLOTS) {   // the next step folds its maxima into cleared slots
-    res->s_slot[tid] = 0.0;
-    res->q_slot[tid] = 0.0;
-  }
-  __syncthreads();
-  if (!s_added) return;
   for (int e = tid; e <= 2 * r; e += 256) {
     if (e < r) bv[e] = addr_eval<d, dt, G>(ks, a, sn, I[e], col);
     else if (e < 2 * r) cv[e - r] = addr_eval<d, dt, G>(ks, a, sn, row, J[e - r]);
@@ -624,6 +597,57 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
       W[r + (int64_t)r * MAXR] = is;
       Wt[r + (int64_t)r * MAXR] = is;
     }
+  }
+}
+
+// End of a step, one block: the pivot (l, t) from the two stages; it is added
+// if its residual exceeds the tie band, it is not yet in I or J and the rank
+// is below the cap.  Then, if added, the border of P_k (border_factors).
+// Clears the fold slots for the next step and publishes the result to the
+// host mailbox.
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* res, int bit, const int32_t* I,
+                                                     const int32_t* J, int r, int max_rank, double* Li, double* W,
+                                                     double* amax, int32_t* info, StepRes* mail, uint32_t* mail_seq,
+                                                     uint32_t seq) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  __shared__ int s_added, s_row, s_col;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_row = bit ? res->l : res->q_pos;
+    s_col = bit ? res->q_pos : res->t;
+  }
+  stage_nodes<D>(ks.nodes, sn);
+  const int row = s_row, col = s_col;
+  int stale = 0;
+  for (int q = tid; q < r; q += 256)
+    if (I[q] == row || J[q] == col) stale = 1;
+  stale = __syncthreads_or(stale);
+  if (tid == 0) {
+    const int added = (res->pivot_abs > res->q_tau && !stale && r < max_rank) ? 1 : 0;
+    res->pivot_row = row;
+    res->pivot_col = col;
+    res->added = added;
+    res->info = *info;   // status of the kept factors (non-zero after a singular border)
+    s_added = added;
+  }
+  if (tid < AMAX_SLOTS) {   // the next step folds its maxima into cleared slots
+    res->s_slot[tid] = 0.0;
+    res->q_slot[tid] = 0.0;
+  }
+  __syncthreads();
+  if (s_added) border_factors<d, dt, G>(ks, a, sn, res, I, J, r, row, col, Li, W, amax, info);
+  // publish the step's result to the host mailbox: the fields up to the
+  // fold slots, then (after a system-scope fence) the sequence number the
+  // host waits for
+  __syncthreads();
+  if (tid == 0) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(res);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(mail);
+    for (int i = 0; i < (int)(offsetof(StepRes, s_slot) / 8); ++i) dst[i] = src[i];
+    __threadfence_system();
+    __hip_atomic_store(mail_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -744,6 +768,38 @@ inline uint64_t mkey(const int32_t* e, int len) {
   return k;
 }
 
+// Host mailbox of the update steps: mapped, coherent pinned memory that the
+// finishing kernel writes (the step's result, then its sequence number) and
+// the host polls, so a step costs no copy and no stream synchronisation.
+struct HostMail {
+  StepRes* res = nullptr;        // host address
+  uint32_t* seq = nullptr;
+  StepRes* dres = nullptr;       // device addresses of the same memory
+  uint32_t* dseq = nullptr;
+  void* p = nullptr;
+  HostMail() = default;
+  HostMail(const HostMail&) = delete;
+  HostMail& operator=(const HostMail&) = delete;
+  ~HostMail() { if (p) (void)hipHostFree(p); }
+  tt_status alloc() {
+    if (p) return TTK_OK;
+    const size_t bytes = sizeof(StepRes) + 64;
+    if (hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(TTK_ERR_OOM, "pinned host allocation of %zu bytes failed", bytes);
+    }
+    std::memset(p, 0, bytes);
+    void* dp = nullptr;
+    TTK_HIP(hipHostGetDevicePointer(&dp, p, 0));
+    res = static_cast<StepRes*>(p);
+    seq = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + sizeof(StepRes));
+    dres = static_cast<StepRes*>(dp);
+    dseq = reinterpret_cast<uint32_t*>(static_cast<char*>(dp) + sizeof(StepRes));
+    return TTK_OK;
+  }
+};
+
 class Cross {
  public:
   Cross(const tt_kernel_params* p, const Grid& g, const KSpec& ks, hipStream_t st)
@@ -771,7 +827,12 @@ class Cross {
   tt_status sampled_error(double* err);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
-  tt_status ensure(DBuf& b, size_t bytes) { return b.alloc(bytes); }
+  // Working buffers that follow the growing ranks: grown by at least half
+  // their size at a time, so that the (synchronising) reallocations are few.
+  tt_status ensure(DBuf& b, size_t bytes) {
+    if (bytes <= b.bytes && b.p) return TTK_OK;
+    return b.alloc(std::max(bytes, b.bytes + b.bytes / 2));
+  }
   tt_status sync() { TTK_HIP(hipStreamSynchronize(st_)); return TTK_OK; }
 
   tt_kernel_params P_;
@@ -791,6 +852,9 @@ class Cross {
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
   HBuf h_stage_, h_res_;
+  HostMail mail_;
+  uint32_t mail_seq_ = 0;
+  tt_status wait_mail(uint32_t seq);
   // upload arena: host pinned + device mirror, bump-allocated between stream
   // synchronisations, flushed with one copy before the kernels that read it
   HBuf ar_h_;
@@ -1046,11 +1110,29 @@ tt_status Cross::init_inverses() {
 // C = F P_k^{-1} = (F W) Li for F (m x r, leading dimension m).
 tt_status Cross::solve_right(int k, int m, const double* F, double* C) {
   const int r = rank(k);
-  TTK_TRY(d_E_.alloc((size_t)m * r * sizeof(double)));
+  TTK_TRY(ensure(d_E_, (size_t)m * r * sizeof(double)));
   double* T = d_E_.as<double>();
   gemm64(0, 0, m, r, r, 1.0, F, m, d_w_[k].as<double>(), MAXR, 0.0, T, m, st_);
   gemm64(0, 0, m, r, r, 1.0, T, m, d_li_[k].as<double>(), MAXR, 0.0, C, m, st_);
   return TTK_OK;
+}
+
+// Polls the mailbox until the finishing kernel has published sequence
+// number seq.  Every 1024 polls the stream is queried: an error is returned
+// as such, and a stream that has drained without publishing is an error too
+// (so a failed launch cannot leave the host polling forever).
+tt_status Cross::wait_mail(uint32_t seq) {
+  for (uint64_t spin = 1;; ++spin) {
+    if (__atomic_load_n(mail_.seq, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
+    if ((spin & 1023) == 0) {
+      const hipError_t e = hipStreamQuery(st_);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(mail_.seq, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
+        return fail(TTK_ERR_HIP, "cross: the step kernel finished without publishing its result");
+      }
+      if (e != hipErrorNotReady) return fail(TTK_ERR_HIP, "cross: %s", hipGetErrorString(e));
+    }
+  }
 }
 
 tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
@@ -1085,10 +1167,8 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   // value buffers
   const size_t nsearch = std::max((size_t)rk + (size_t)rk * cols + cols, (size_t)rows * rk + rk + rows);
   const size_t nvals = 2 * (size_t)ns * rk + ns + nsearch;
-  TTK_TRY(d_vals_.alloc(nvals * sizeof(double)));
-  TTK_TRY(d_R_.alloc((size_t)std::max(ns, std::max(rows, cols)) * sizeof(double)));
-  TTK_TRY(d_res_.alloc(sizeof(StepRes)));
-  TTK_TRY(h_res_.alloc(sizeof(StepRes)));
+  TTK_TRY(ensure(d_vals_, nvals * sizeof(double)));
+  TTK_TRY(ensure(d_R_, (size_t)std::max(ns, std::max(rows, cols)) * sizeof(double)));
   double* AsJ = d_vals_.as<double>();
   double* AIs = AsJ + (size_t)ns * rk;          // (q, sample) at sample + q ns
   double* As = AIs + (size_t)rk * ns;
@@ -1139,12 +1219,12 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
     hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
                        dim3(256), 0, st_, ks_, a, dres, bit, dI, dJ, rk, maxr, d_li_[k].as<double>(),
-                       d_w_[k].as<double>(), luamax(k), luinfo(k));
+                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres, mail_.dseq, mail_seq_ + 1);
   });
   TTK_HIP(hipGetLastError());
-  TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, sizeof(StepRes), hipMemcpyDeviceToHost, st_));
-  TTK_TRY(sync());
-  const StepRes r = *h_res_.as<StepRes>();
+  TTK_TRY(wait_mail(++mail_seq_));
+  StepRes r;
+  std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
   if (r.info != 0)
     return fail(TTK_ERR_SINGULAR_CROSS, "cross: intersection matrix of super-core %d singular (sweep %d)", k,
                 sweep);
@@ -1197,7 +1277,7 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
     const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
     const int m = r0 * n;
     TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
-    TTK_TRY(d_core_[k - 1].alloc((size_t)m * r1 * sizeof(double)));
+    TTK_TRY(ensure(d_core_[k - 1], (size_t)m * r1 * sizeof(double)));
     ce.a[k - 1] = fibre_addr(k);
     ce.out[k - 1] = d_core_[k - 1].as<double>();
     ce.nr[k - 1] = m;
@@ -1217,7 +1297,7 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   int nt = 0, rmax = 1;
   for (int k = 1; k < N; ++k) {
     const int m = rank(k - 1) * g_.n[k - 1], r = rank(k);
-    TTK_TRY(d_cint_[k - 1].alloc((size_t)m * r * sizeof(double)));
+    TTK_TRY(ensure(d_cint_[k - 1], (size_t)m * r * sizeof(double)));
     cs.F[k - 1] = d_core_[k - 1].as<double>();
     cs.C[k - 1] = d_cint_[k - 1].as<double>();
     cs.Li[k - 1] = d_li_[k].as<double>();
@@ -1330,6 +1410,7 @@ tt_status Cross::run(CrossOut* out) {
   if (solve_lds(MAXR) > 48 * 1024)
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_cores),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
+  TTK_TRY(mail_.alloc());
   // step state: the block counter and the sample-stage scale start at zero
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   fill_zero(d_res_.p, sizeof(StepRes), st_);
