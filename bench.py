@@ -32,10 +32,13 @@ import synth  # noqa: E402
 
 METRIC = "offline U/V rows/s + batched apply+grad GB/s vs plain apply, at ≤1e-5 rel err"
 HBM_PEAK_GBPS = 8000.0
-# HBM bytes of the roofline kernel from rocprofv3 counter runs (FETCH_SIZE and
-# WRITE_SIZE, separate runs) scaled by the same counters on a plain copy of
-# known size; None until taken for the current kernel.
-TRAFFIC = None
+# HBM bytes per launch of the roofline kernel (k_factor_mfma on matern32_d3,
+# rounded ranks 1,6,23,71 | 72,30,7,1) from rocprofv3 counter runs
+# (FETCH_SIZE and WRITE_SIZE, separate runs): (2 x 1066.75 + 27734.375) KiB
+# and (2 x 1214.4375 + 28125.0) KiB for the two launches, averaged, with the
+# scales 2.000 and 1.000 read off the same counters on a plain 1 GiB copy.
+# None whenever the kernel has changed since the counters were taken.
+TRAFFIC = 30935936
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -417,13 +420,19 @@ def main():
     # the dominant N-dependent kernel: Phase 3 (k_factor_mfma), one launch per side;
     # achieved = algorithmic flops of both launches / their summed durations
     tf_both = (fl_u + fl_v) / ((ms_u + ms_v) * 1e-3) / 1e12
+    # algorithmic HBM bytes per launch (average): d float32 coordinates in and
+    # r float32 entries out per point (the cores stay in L2)
+    rk = inf["ranks"]
+    r_u, r_v = rk[w.d], rk[w.d + w.d_theta]
+    alg_bytes = (w.n_src * 4 * (w.d + r_u) + w.n_tgt * 4 * (w.d + r_v)) / 2
     result["roofline"] = {
         "kernel": "k_factor_mfma (Phase 3, source and target launches)", "bound": "mfma",
         "achieved": round(tf_both, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": round(tf_both / FP32_PEAK_TFLOPS, 4), "traffic": TRAFFIC,
         "avg_launch_ms": round((ms_u + ms_v) / 2, 4),
         "traffic_note": "HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a plain "
-                        "1 GiB copy), average of the two launches; algorithmic 28.1 MB",
+                        "1 GiB copy), average of the two launches; algorithmic "
+                        f"{alg_bytes / 1e6:.2f} MB (points in, rows out, float32)",
         "algorithmic": f"{fl_u / w.n_src:.0f} (source) and {fl_v / w.n_tgt:.0f} (target) flop per point, "
                        f"{w.n_src} and {w.n_tgt} points per launch",
     }

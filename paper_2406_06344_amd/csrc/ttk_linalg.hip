@@ -521,18 +521,23 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
     if (lane == 0) G[p][q] = sdot;
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < jb; ++i) {
-      for (int r = 0; r < jb; ++r) Ts[r][i] = 0.0;
-      Ts[i][i] = tau[i];
-      for (int r = 0; r < i; ++r) {
+  // column i of T from columns < i: T[r][i] = -tau_i sum_{r <= q < i} T[r][q] G[q][i]
+  // for r < i, tau_i on the diagonal; rows in parallel
+  for (int i = 0; i < jb; ++i) {
+    if (tid < jb) {
+      const int r = tid;
+      double v = 0.0;
+      if (r < i) {
         double acc = 0.0;
         for (int q = r; q < i; ++q) acc += Ts[r][q] * G[q][i];
-        Ts[r][i] = -tau[i] * acc;
+        v = -tau[i] * acc;
+      } else if (r == i) {
+        v = tau[i];
       }
+      Ts[r][i] = v;
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = tid; e < jb * jb; e += BS) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
 }
 
