@@ -19,6 +19,23 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sum over each row of 16 lanes, in every lane of the row: a butterfly of
+// DPP row rotations (by 8, 4, 2, 1) on the two 32-bit halves, no LDS traffic.
+template <int N>
+__device__ inline double row_ror(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x120 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double row16_sum(double v) {
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  return v;
+}
+
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -541,6 +558,335 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
   for (int e = tid; e < jb * jb; e += BS) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
 }
 
+// Register-resident panel factorisation for panels of at most PB * RPT rows
+// (RPT <= 8) and 16 columns: thread t holds rows t + k PB (k < RPT) of every
+// column.
+// Per column j: the norm below the diagonal is one block reduction and the
+// sixteen products v_j^T a_c one more (both through LDS, no lane shuffles);
+// for c > j they update the trailing panel columns, for c < j they are
+// v_c^T v_j, from which column j of T (H_0 ... H_{jb-1} = I - V T V^T) follows
+// by the forward recurrence T(r, j) = -tau_j sum_{r <= q < j} T(r, q) v_q^T v_j.
+// Writes the reflectors below the diagonal of the panel (unit diagonal
+// implicit), R on and above it, tau, V explicit (mm x jb) and T (jb x jb).
+constexpr int PB = 256;
+template <int RPT>
+__global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V,
+                                                     double* T) {
+  constexpr int NB = 16, S = PB / NB;   // S strips per column in the first reduction stage
+  // block sums through LDS: every thread's partials in P (conflict-free
+  // columns), then S partial sums per column in Q, then the final sums
+  __shared__ double P[NB][PB], Q[NB][S];
+  __shared__ double sd[NB], Ts[NB][NB];
+  __shared__ double s_x0;
+  const int tid = threadIdx.x;
+  const int rc = tid / S, rj = tid % S;   // (column, strip) of the first reduction stage
+  double a[RPT][NB];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * PB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[k][c] = (i < mm && c < jb) ? A[i + (size_t)c * lda] : 0.0;
+  }
+#pragma clang loop unroll(full)
+  for (int j = 0; j < NB; ++j) {
+    if (j >= jb) continue;   // uniform; the loop is fully unrolled (constant j)
+    // norm of column j below the diagonal; x0 = A(j, j) sits in thread j
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k)
+      if (tid + k * PB > j) part += a[k][j] * a[k][j];
+    P[0][tid] = part;
+    if (tid == j) s_x0 = a[0][j];
+    __syncthreads();
+    if (tid < S) {
+      double sum = 0.0;
+#pragma unroll
+      for (int u = 0; u < PB / S; ++u) sum += P[0][u * S + tid];
+      Q[0][tid] = sum;
+    }
+    __syncthreads();
+    double tail = 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) tail += Q[0][q];
+    const double x0 = s_x0;
+    double tj = 0.0, alpha = x0, scale = 0.0;
+    if (tail != 0.0) {
+      const double nrm = sqrt(x0 * x0 + tail);
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      tj = (alpha - x0) / alpha;
+      scale = 1.0 / (x0 - alpha);
+    }
+    // v_j: 1 at row j, the scaled column below it
+    double v[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * PB;
+      if (i > j && tj != 0.0) a[k][j] *= scale;
+      v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
+    }
+    // products with every other column: a_c for c > j, v_c for c < j
+    __syncthreads();   // every thread has read Q[0][] and s_x0
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      double sum = 0.0;
+      if (c != j && c < jb) {
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int i = tid + k * PB;
+          const double x = (c > j) ? a[k][c] : ((i > c) ? a[k][c] : (i == c ? 1.0 : 0.0));
+          sum += v[k] * x;
+        }
+      }
+      P[c][tid] = sum;
+    }
+    __syncthreads();
+    {
+      double sum = 0.0;
+#pragma unroll
+      for (int u = 0; u < PB / S; ++u) sum += P[rc][u * S + rj];
+      Q[rc][rj] = sum;
+    }
+    __syncthreads();
+    if (tid < NB) {
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < S; ++q) sum += Q[tid][q];
+      sd[tid] = sum;
+    }
+    __syncthreads();
+    // apply H_j to the later columns; column j of T from the earlier ones
+#pragma unroll
+    for (int c = j + 1; c < NB; ++c) {
+      if (c < jb) {
+        const double f = tj * sd[c];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) a[k][c] -= f * v[k];
+      }
+    }
+    if (tid < NB) {
+      double t = 0.0;
+      if (tid < j) {
+        double acc = 0.0;
+        for (int q = tid; q < j; ++q) acc += Ts[tid][q] * sd[q];
+        t = -tj * acc;
+      } else if (tid == j) {
+        t = tj;
+      }
+      Ts[tid][j] = t;
+    }
+    if (tid == j) a[0][j] = alpha;   // R's diagonal entry
+    if (tid == 0) tau[j] = tj;
+    __syncthreads();   // sd and Ts column j are complete before the next column
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * PB;
+    if (i < mm)
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < jb) {
+          A[i + (size_t)c * lda] = a[k][c];
+          V[i + (size_t)c * mm] = (i > c) ? a[k][c] : (i == c ? 1.0 : 0.0);
+        }
+  }
+  for (int e = tid; e < jb * jb; e += PB) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
+}
+
+// Launches the register panel for mm <= 8 PB rows; false if the panel is taller.
+bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, double* T, hipStream_t st) {
+  if (mm <= PB)
+    hipLaunchKernelGGL(k_qr_panel_reg<1>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+  else if (mm <= 2 * PB)
+    hipLaunchKernelGGL(k_qr_panel_reg<2>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+  else if (mm <= 4 * PB)
+    hipLaunchKernelGGL(k_qr_panel_reg<4>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+  else if (mm <= 8 * PB)
+    hipLaunchKernelGGL(k_qr_panel_reg<8>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+  else
+    return false;
+  return true;
+}
+
+typedef double qdbl4 __attribute__((ext_vector_type(4)));
+
+// C <- (I - V op(T) V^T) C for one panel of the blocked QR: V (mm x jb,
+// explicit, ld mm), T (jb x jb, ld jb), op(T) = T^T (trans = 1: applying Q^T
+// to the trailing matrix) or T (trans = 0: forming Q).  One block per 16
+// columns of C, so the three products need no grid-wide ordering:
+// W = V^T C (FP64 MFMA v_mfma_f64_16x16x4, the long dimension split over the
+// sixteen waves, eight steps of loads in flight), W2 = op(T) W in LDS, and
+// C -= V W2 by 16-row tiles (A at [l % 16][l / 16], B at [l / 16][l % 16],
+// D row l / 16 + 4 v, column l % 16 in lane l, slot v).
+constexpr int QAW = 16;   // waves of k_qr_apply
+__global__ void __launch_bounds__(QAW * 64) k_qr_apply(const double* V, int mm, int jb, const double* T, int trans,
+                                                        double* C, int nc, int lda) {
+  constexpr int SBQ = 8;
+  __shared__ double Wp[QAW][16][17], W2[16][17];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int c = blockIdx.x * 16 + li;
+  const bool cok = c < nc, pok = li < jb;
+  const int nst = (mm + 3) / 4;
+  qdbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = wv * SBQ; s0 < nst; s0 += QAW * SBQ) {
+    double a[SBQ], b[SBQ];
+#pragma unroll
+    for (int u = 0; u < SBQ; ++u) {
+      const int i = 4 * (s0 + u) + lk;
+      const bool ok = i < mm;
+      a[u] = (ok && pok) ? V[i + (size_t)li * mm] : 0.0;
+      b[u] = (ok && cok) ? C[i + (size_t)c * lda] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SBQ; ++u)
+      if (s0 + u < nst) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Wp[wv][lk + 4 * v][li] = acc[v];
+  __syncthreads();
+  if (tid < 256) {
+    const int p = tid >> 4, cc = tid & 15;
+    double sum = 0.0;
+    for (int w = 0; w < QAW; ++w) sum += Wp[w][p][cc];
+    Wp[0][p][cc] = sum;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int p = tid >> 4, cc = tid & 15;
+    double sum = 0.0;
+    if (p < jb)
+      for (int q = 0; q < jb; ++q) sum += (trans ? T[q + p * jb] : T[p + q * jb]) * Wp[0][q][cc];
+    W2[p][cc] = sum;
+  }
+  __syncthreads();
+  // C -= V W2, two row tiles per wave at a time (their loads in flight together)
+  const int ntile = (mm + 15) / 16;
+  for (int rt = wv; rt < ntile; rt += 2 * QAW) {
+    double av[2][4], cv[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = rt + h * QAW;
+      const int r = t * 16 + li;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int q = 4 * st + lk;
+        av[h][st] = (t < ntile && r < mm && q < jb) ? V[r + (size_t)q * mm] : 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = t * 16 + lk + 4 * v;
+        cv[h][v] = (t < ntile && row < mm && cok) ? C[row + (size_t)c * lda] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = rt + h * QAW;
+      qdbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][st], W2[4 * st + lk][li], d, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = t * 16 + lk + 4 * v;
+        if (t < ntile && row < mm && cok) C[row + (size_t)c * lda] = cv[h][v] - d[v];
+      }
+    }
+  }
+}
+
+// Columns of Q for one panel from its reflectors (backward accumulation, as
+// k_qr_panel_q), register-resident like k_qr_panel_reg: for j = jb-1 .. 0 the
+// products v_j^T q_c with the already formed columns c > j are one block
+// reduction through LDS, then q_c -= tau_j (v_j^T q_c) v_j and column j
+// becomes H_j e_j.
+template <int RPT>
+__global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau) {
+  constexpr int NB = 16, S = PB / NB;
+  __shared__ double P[NB][PB], Q[NB][S];
+  __shared__ double sd[NB];
+  const int tid = threadIdx.x;
+  const int rc = tid / S, rj = tid % S;
+  double a[RPT][NB];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * PB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[k][c] = (i < mm && c < jb) ? A[i + (size_t)c * lda] : 0.0;
+  }
+#pragma clang loop unroll(full)
+  for (int j = NB - 1; j >= 0; --j) {
+    if (j >= jb) continue;   // uniform; the loop is fully unrolled (constant j)
+    const double tj = tau[j];
+    double v[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * PB;
+      v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
+    }
+    if (j < jb - 1) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double sum = 0.0;
+        if (c > j && c < jb)
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) sum += v[k] * a[k][c];
+        P[c][tid] = sum;
+      }
+      __syncthreads();
+      {
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < PB / S; ++u) sum += P[rc][u * S + rj];
+        Q[rc][rj] = sum;
+      }
+      __syncthreads();
+      if (tid < NB) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) sum += Q[tid][q];
+        sd[tid] = sum;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = j + 1; c < NB; ++c) {
+        if (c < jb) {
+          const double f = tj * sd[c];
+#pragma unroll
+          for (int k = 0; k < RPT; ++k) a[k][c] -= f * v[k];
+        }
+      }
+      __syncthreads();   // sd is read by every thread before the next column writes P
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * PB;
+      a[k][j] = (i > j) ? -tj * v[k] : (i == j ? 1.0 - tj : 0.0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * PB;
+    if (i < mm)
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < jb) A[i + (size_t)c * lda] = a[k][c];
+  }
+}
+
+// Launches the register form of the panel's Q for mm <= 8 PB rows; false otherwise.
+bool qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau, hipStream_t st) {
+  if (mm <= PB)
+    hipLaunchKernelGGL(k_qr_panel_q_reg<1>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+  else if (mm <= 2 * PB)
+    hipLaunchKernelGGL(k_qr_panel_q_reg<2>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+  else if (mm <= 4 * PB)
+    hipLaunchKernelGGL(k_qr_panel_q_reg<4>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+  else if (mm <= 8 * PB)
+    hipLaunchKernelGGL(k_qr_panel_q_reg<8>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+  else
+    return false;
+  return true;
+}
+
 // Columns of Q for one panel from its reflectors (backward accumulation), in place.
 __global__ void __launch_bounds__(BS) k_qr_panel_q(double* A, int m, int jb, int lda, const double* tau) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -743,11 +1089,9 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
             be += aq[i] * aq[i];
             ga += ap[i] * aq[i];
           }
-          for (int o = 8; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o, 16);
-            be += __shfl_xor(be, o, 16);
-            ga += __shfl_xor(ga, o, 16);
-          }
+          al = row16_sum(al);
+          be = row16_sum(be);
+          ga = row16_sum(ga);
           if (!(fabs(ga) <= 1e-15 * sqrt(al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -898,32 +1242,34 @@ void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work,
 }
 
 // Blocked Householder QR, compact WY with panels of 16: the panel factors in
-// one workgroup, the trailing update and the formation of Q are GEMMs.
-// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) + 16 n (W) doubles.
+// one workgroup (registers when it has at most 2048 rows), the trailing update
+// and the formation of Q are one k_qr_apply launch per panel.
+// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) doubles (qr_blocked_work
+// keeps a spare 32 n).
 tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
   constexpr int NB = 16;
   if (m < n) return fail(TTK_ERR_ARG, "qr_blocked needs m >= n");
   double* tau = work;
   double* V = tau + n;
   double* Tall = V + (size_t)NB * m;
-  double* W = Tall + (size_t)NB * NB * ((n + NB - 1) / NB);
   const int npan = (n + NB - 1) / NB;
   for (int p = 0; p < npan; ++p) {
     const int j0 = p * NB, jb = std::min(NB, n - j0);
     const int mm = m - j0;
     double* Ap = A + j0 + (size_t)j0 * lda;
-    hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
     double* T = Tall + (size_t)p * NB * NB;
-    hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb, lda,
-                       V);
-    hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, V, mm, jb, tau + j0, T);
+    if (!qr_panel_reg(Ap, mm, jb, lda, tau + j0, V, T, st)) {
+      hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+      hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
+                         lda, V);
+      hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, V, mm, jb, tau + j0, T);
+    }
     const int nc = n - j0 - jb;
     if (nc > 0) {
       double* A2 = A + j0 + (size_t)(j0 + jb) * lda;
       // A2 <- (I - V T^T V^T) A2
-      gemm64(1, 0, jb, nc, mm, 1.0, V, mm, A2, lda, 0.0, W, jb, st);           // W = V^T A2
-      gemm64(1, 0, jb, nc, jb, 1.0, T, jb, W, jb, 0.0, W + (size_t)jb * nc, jb, st);  // T^T W
-      gemm64(0, 0, mm, nc, jb, -1.0, V, mm, W + (size_t)jb * nc, jb, 1.0, A2, lda, st);
+      hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
+                         (const double*)T, 1, A2, nc, lda);
     }
   }
   hipLaunchKernelGGL(k_extract_r, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, lda, R, ldr);
@@ -939,11 +1285,11 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
                          lda, V);
       double* Q2 = A + j0 + (size_t)(j0 + jb) * lda;
       // Q2 <- (I - V T V^T) Q2
-      gemm64(1, 0, jb, nc, mm, 1.0, V, mm, Q2, lda, 0.0, W, jb, st);
-      gemm64(0, 0, jb, nc, jb, 1.0, T, jb, W, jb, 0.0, W + (size_t)jb * nc, jb, st);
-      gemm64(0, 0, mm, nc, jb, -1.0, V, mm, W + (size_t)jb * nc, jb, 1.0, Q2, lda, st);
+      hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
+                         (const double*)T, 0, Q2, nc, lda);
     }
-    hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+    if (!qr_panel_q_reg(Ap, mm, jb, lda, tau + j0, st))
+      hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
     if (j0 > 0)
       hipLaunchKernelGGL(k_zero_rows, dim3((j0 * jb + 255) / 256), dim3(256), 0, st, A + (size_t)j0 * lda, j0, jb,
                          lda);
