@@ -45,6 +45,7 @@
 #include "ttk_eval_dev.h"
 #include "ttk_internal.h"
 #include "ttk_rng.h"
+#include "ttk_wave.h"
 
 namespace ttk {
 
@@ -66,10 +67,7 @@ struct StepRes {
   double s_slot[AMAX_SLOTS], q_slot[AMAX_SLOTS];
 };
 
-__device__ inline double wsum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
+__device__ inline double wsum(double v) { return wave64_sum(v); }
 
 // Largest |value| over up to four buffers, combined with *base (if non-NULL).
 __global__ void k_absmax(const double* a, int na, const double* b, int nb, const double* c, int nc,
@@ -226,7 +224,7 @@ __global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx
           if (lq + 16 * c < r0) s += col[lq + 16 * c] * vr[c];
         }
       }
-      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      s = row16_sum(s);
       if (lq == 0 && t < r1) v[t] = s;
     }
     __syncthreads();
@@ -332,9 +330,10 @@ __device__ void row_dots(const double* M, const double* v, int r, double* out, d
 // row/col of the chosen sample), stage 1 = search stage.  The sample list is
 // in generation order, so its key is the linear position row * cols + col;
 // the searched fibre is in natural order.  Wave shuffles, then one LDS stage.
+// Returns the chosen position in every thread.
 template <int BS>
-__device__ void select_block(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
-                             double scale, StepRes* res) {
+__device__ int select_block(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
+                            double scale, StepRes* res) {
   constexpr int NWV = BS / 64;
   __shared__ double sv[NWV];
   __shared__ int sk[NWV], si[NWV];
@@ -344,7 +343,7 @@ __device__ void select_block(const double* R, int n, const int32_t* srow, const 
   const double tau = TIE_REL * scale;
   double m = -1.0;
   for (int i = tid; i < n; i += BS) m = fmax(m, fabs(R[i]));
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  m = wave64_max(m);
   if (lane == 0) sv[w] = m;
   __syncthreads();
   if (tid == 0) {
@@ -360,9 +359,10 @@ __device__ void select_block(const double* R, int n, const int32_t* srow, const 
       const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
       if (key < best) { best = key; bi = i; }
     }
-  for (int o = 32; o > 0; o >>= 1) {
-    const int ob = __shfl_xor(best, o, 64), oi = __shfl_xor(bi, o, 64);
-    if (ob < best) { best = ob; bi = oi; }
+  {   // keys are distinct, so the lowest key names one entry
+    const int kmin = wave64_min_i(best);
+    bi = wave64_min_i(best == kmin ? bi : 0x7fffffff);
+    best = kmin;
   }
   if (lane == 0) { sk[w] = best; si[w] = bi; }
   __syncthreads();
@@ -377,7 +377,7 @@ __device__ void select_block(const double* R, int n, const int32_t* srow, const 
   double sec = 0.0;
   for (int i = tid; i < n; i += BS)
     if (i != p) sec = fmax(sec, fabs(R[i]));
-  for (int o = 32; o > 0; o >>= 1) sec = fmax(sec, __shfl_xor(sec, o, 64));
+  sec = wave64_max(sec);
   if (lane == 0) sv[w] = sec;
   __syncthreads();
   if (tid == 0) {
@@ -395,6 +395,7 @@ __device__ void select_block(const double* R, int n, const int32_t* srow, const 
       res->pivot_abs = fabs(R[p]);
     }
   }
+  return p;
 }
 
 // max of the AMAX_SLOTS slots of a fold
@@ -406,33 +407,64 @@ __device__ inline double slots_max(const double* sl) {
 
 // Sample stage: residuals R_i = A(s_i, J) P^{-1} A(I, s_i) - A(s_i) of the
 // sampled entries, written as the row-wise dot product of G = A(s, J) W and
-// T = (Li A(I, s))^T, both 16-sample tiles formed with FP64 MFMA
+// T = (Li A(I, s))^T, both formed with FP64 MFMA on 16-row tiles that hold
+// SPB samples
 // (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16], D row
-// l / 16 + 4 v, column l % 16 in lane l, slot v).  AsJ and AIs hold
-// A(s_i, J_q) and A(I_q, s_i) at i + q ns.  The
-// block's A operands are staged once in LDS in lane order (dynamic, 2 x 64 x
-// ceil(r / 4) doubles); the B operands (rows of W^T and Li) stream from L2,
-// eight MFMA steps of loads in flight per batch.
-constexpr int SW = 4;   // waves per block; one block per 16 samples
+// l / 16 + 4 v, column l % 16 in lane l, slot v).  The block evaluates its
+// samples' entries A(s_i, J_q), A(I_q, s_i) and A(s_i) itself, straight into
+// LDS in MFMA lane order (dynamic, 2 x 64 x ceil(r / 4) doubles), and folds
+// their max |.| into the sample-stage slots; the B operands (rows of W^T and
+// Li) stream from L2, eight MFMA steps of loads in flight per batch.
+constexpr int SW = 4;    // waves per block
+constexpr int SPB = 8;  // samples per block (MFMA rows SPB..15 are zero): twice the blocks of a
+                        // full 16-row tile, so the entry evaluations spread over more CUs
 constexpr int SB = 8;   // MFMA steps per batch of B loads
-__global__ void __launch_bounds__(SW * 64) k_sample_resid(const double* AsJ, const double* AIs, const double* As,
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, Addr ad, const int32_t* srow,
+                                                          const int32_t* scol, const int32_t* I, const int32_t* J,
                                                           int ns, int r, const double* Li, const double* W,
-                                                          double* R) {
+                                                          double* R, double* slots) {
+  constexpr int D = 2 * d + dt;
   extern __shared__ double sa[];
-  __shared__ double red[SW][16];
+  __shared__ double red[SW][16], sn[D * MAXN], sAs[16], redm[SW];
+  __shared__ int sr[16], sc[16];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int i0 = blockIdx.x * 16;
+  const int i0 = blockIdx.x * SPB;
   const int nst = (r + 3) / 4;
+  if (tid < 16) {
+    const bool ok = tid < SPB && i0 + tid < ns;
+    sr[tid] = ok ? srow[i0 + tid] : 0;
+    sc[tid] = ok ? scol[i0 + tid] : 0;
+  }
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  double m = 0.0;
   for (int e = tid; e < 64 * nst; e += SW * 64) {
     const int ii = e & 15, q = e >> 4;
-    const int i = i0 + ii;
-    const bool ok = i < ns && q < r;
     const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
-    sa[slot] = ok ? AsJ[i + (int64_t)q * ns] : 0.0;
-    sa[64 * nst + slot] = ok ? AIs[i + (int64_t)q * ns] : 0.0;
+    double vg = 0.0, vt = 0.0;
+    if (ii < SPB && i0 + ii < ns && q < r) {
+      vg = addr_eval<d, dt, G>(ks, ad, sn, sr[ii], J[q]);
+      vt = addr_eval<d, dt, G>(ks, ad, sn, I[q], sc[ii]);
+      m = fmax(m, fmax(fabs(vg), fabs(vt)));
+    }
+    sa[slot] = vg;
+    sa[64 * nst + slot] = vt;
   }
+  if (tid < SPB && i0 + tid < ns) {
+    const double v = addr_eval<d, dt, G>(ks, ad, sn, sr[tid], sc[tid]);
+    sAs[tid] = v;
+    m = fmax(m, fabs(v));
+  }
+  m = wave64_max(m);
+  if (lane == 0) redm[wv] = m;
   __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < SW; ++w) m = fmax(m, redm[w]);
+    m = fmax(m, redm[0]);
+    atomicMax(reinterpret_cast<unsigned long long*>(slots + blockIdx.x % AMAX_SLOTS),
+              (unsigned long long)__double_as_longlong(m));
+  }
   const double* Wt = W + FT;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int ntile = (r + 15) / 16;
@@ -462,49 +494,73 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(const double* AsJ, con
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v)
-    for (int o = 8; o > 0; o >>= 1) part[v] += __shfl_xor(part[v], o, 16);
+    part[v] = row16_sum(part[v]);
   if (li == 0)
 #pragma unroll
     for (int v = 0; v < 4; ++v) red[wv][lk + 4 * v] = part[v];
   __syncthreads();
-  if (tid < 16 && i0 + tid < ns) {
+  if (tid < SPB && i0 + tid < ns) {
     double s = 0.0;
     for (int w = 0; w < SW; ++w) s += red[w][tid];
-    R[i0 + tid] = s - As[i0 + tid];
+    R[i0 + tid] = s - sAs[tid];
   }
-}
-
-// Sample-stage selection over the residuals of k_sample_resid (one block).
-__global__ void __launch_bounds__(1024) k_sample_select(const double* R, int ns, const int32_t* srow,
-                                                        const int32_t* scol, int cols, const double* luamax,
-                                                        StepRes* res) {
-  select_block<1024>(R, ns, srow, scol, cols, 0, fmax(slots_max(res->s_slot), *luamax), res);
 }
 
 // dynamic LDS of k_sample_resid for rank r
 inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
 
-// Search stage: x = (u W) Li for the row of the chosen sample (bit 1, u =
-// A(l, J)) or x = W (Li u) for its column (bit 0, u = A(I, t)), both P^{-1}
-// applied to one vector (every block forms x itself); then R_i = sum_q
-// Lm[i + q n] x_q - Ad[i] over the fibre, 64 entries per block with four
-// threads on each, and the selection in the last block.
+// Sample-stage selection over the residuals of k_sample_resid (one block),
+// then the search stage's solve: u = A(l, J) for a row search (bit 1) or
+// u = A(I, t) for a column search (bit 0) is evaluated here and
+// x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search_resid
+// (P^{-1} applied to one vector, through the rows of the factors or of their
+// transposes).  |u| folds into the search-stage scale.
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, Addr a, const double* R, int ns,
+                                                        const int32_t* srow, const int32_t* scol, int cols,
+                                                        const double* luamax, StepRes* res, int bit,
+                                                        const int32_t* I, const int32_t* J, int r, const double* Li,
+                                                        const double* W, double* x) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN], su[MAXR], sy[MAXR], scr[1024], red[16];
+  const int p = select_block<1024>(R, ns, srow, scol, cols, 0, fmax(slots_max(res->s_slot), *luamax), res);
+  const int l = srow[p], t = scol[p];
+  stage_nodes<D>(ks.nodes, sn);
+  double m = 0.0;
+  for (int q = threadIdx.x; q < r; q += 1024) {
+    const double v = bit ? addr_eval<d, dt, G>(ks, a, sn, l, J[q]) : addr_eval<d, dt, G>(ks, a, sn, I[q], t);
+    su[q] = v;
+    m = fmax(m, fabs(v));
+  }
+  m = wave64_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
+    m = fmax(m, red[0]);
+    res->q_slot[0] = fmax(res->q_slot[0], m);
+  }
+  if (bit) {
+    row_dots<1024>(W + FT, su, r, sy, scr);    // W^T u
+    row_dots<1024>(Li + FT, sy, r, su, scr);   // Li^T (W^T u), into su (u is consumed)
+  } else {
+    row_dots<1024>(Li, su, r, sy, scr);        // Li u
+    row_dots<1024>(W, sy, r, su, scr);         // W (Li u)
+  }
+  for (int q = threadIdx.x; q < r; q += 1024) x[q] = su[q];
+}
+
+// Search stage: R_i = sum_q Lm[i + q n] x_q - Ad[i] over the searched fibre
+// with x from k_sample_select, 64 entries per block with four threads on
+// each, then the selection in the block that finishes last.
 constexpr int QB = 256;
 constexpr int QR = 64;   // fibre entries per block
-__global__ void __launch_bounds__(QB) k_search_resid(int bit, const double* u, const double* Lm, const double* Ad,
-                                                     int n, int r, const double* Li, const double* W, double* R,
-                                                     int cols, StepRes* res) {
-  __shared__ double su[MAXR], sy[MAXR], sx[MAXR], scr[QB];
+__global__ void __launch_bounds__(QB) k_search_resid(const double* x, const double* Lm, const double* Ad, int n,
+                                                     int r, double* R, int cols, StepRes* res) {
+  __shared__ double sx[MAXR], scr[QB];
   const int tid = threadIdx.x;
-  for (int q = tid; q < r; q += QB) su[q] = u[q];
+  for (int q = tid; q < r; q += QB) sx[q] = x[q];
   __syncthreads();
-  if (bit) {
-    row_dots<QB>(W + FT, su, r, sy, scr);    // W^T u
-    row_dots<QB>(Li + FT, sy, r, sx, scr);   // Li^T (W^T u)
-  } else {
-    row_dots<QB>(Li, su, r, sy, scr);        // Li u
-    row_dots<QB>(W, sy, r, sx, scr);         // W (Li u)
-  }
   {
     const int i = blockIdx.x * QR + (tid & (QR - 1)), h = tid / QR;
     const int chunk = (r + QB / QR - 1) / (QB / QR);
@@ -559,7 +615,7 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
       m = fmax(m, fmax(fabs(bv[p]), fabs(cv[p])));
     }
     gu = wsum(gu);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    m = wave64_max(m);
     if ((tid & 63) == 0) { nl[tid >> 6] = gu; nw[tid >> 6] = m; }
     __syncthreads();
     if (tid == 0) {
@@ -844,7 +900,7 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_idx_, d_vals_, d_res_, d_scratch_, d_R_;
+  DBuf d_left_, d_right_, d_vals_, d_res_, d_R_, d_x_;
   DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
@@ -1166,13 +1222,10 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const int32_t* dsc = dsr + ns;
   // value buffers
   const size_t nsearch = std::max((size_t)rk + (size_t)rk * cols + cols, (size_t)rows * rk + rk + rows);
-  const size_t nvals = 2 * (size_t)ns * rk + ns + nsearch;
+  const size_t nvals = nsearch;
   TTK_TRY(ensure(d_vals_, nvals * sizeof(double)));
   TTK_TRY(ensure(d_R_, (size_t)std::max(ns, std::max(rows, cols)) * sizeof(double)));
-  double* AsJ = d_vals_.as<double>();
-  double* AIs = AsJ + (size_t)ns * rk;          // (q, sample) at sample + q ns
-  double* As = AIs + (size_t)rk * ns;
-  double* S0 = As + ns;
+  double* S0 = d_vals_.as<double>();            // the searched fibre's entries
   StepRes* dres = d_res_.as<StepRes>();
   const int32_t* d_l = &dres->l;
   const int32_t* d_t = &dres->t;
@@ -1181,37 +1234,43 @@ tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
   const double* Li = d_li_[k].as<double>();
   const double* W = d_w_[k].as<double>();
   double* R = d_R_.as<double>();
-  {   // the sample-stage maximum folds into the s slots (cleared by the previous step)
-    const EvalSeg sg[3] = {{dsr, dJ, ns, rk, 0, AsJ}, {dI, dsc, rk, ns, 1, AIs}, {dsr, dsc, ns, 1, 2, As}};
-    eval_segs(ks_, a, sg, 3, st_, dres->s_slot);
-  }
+  // the sample stage evaluates its entries itself; their maximum folds into
+  // the s slots (cleared by the previous step)
   evals_ += 2 * (int64_t)ns * rk + ns;
-  hipLaunchKernelGGL(k_sample_resid, dim3(nblk(ns, 16)), dim3(SW * 64), sample_lds(rk), st_, AsJ, AIs, As, ns, rk,
-                     Li, W, R);
-  hipLaunchKernelGGL(k_sample_select, dim3(1), dim3(1024), 0, st_, (const double*)R, ns, dsr, dsc, cols,
-                     (const double*)luamax(k), dres);
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_sample_resid<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(nblk(ns, SPB)), dim3(SW * 64), sample_lds(rk), st_, ks_, a, dsr, dsc, dI, dJ, ns, rk, Li,
+                       W, R, dres->s_slot);
+  });
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_sample_select<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(1), dim3(1024), 0, st_, ks_, a, (const double*)R, ns, dsr, dsc, cols,
+                       (const double*)luamax(k), dres, bit, dI, dJ, rk, Li, W, d_x_.as<double>());
+  });
   if (bit == 1) {   // search the row of the sample's pivot
     double* AlJ = S0;
     double* AIall = AlJ + rk;                   // (q, c) at c + q cols
     double* Alall = AIall + (size_t)rk * cols;
+    (void)AlJ;   // A(l, J) is evaluated by k_sample_select
     {
-      const EvalSeg sg[3] = {{d_l, dJ, 1, rk, 0, AlJ}, {dI, nullptr, rk, cols, 1, AIall}, {d_l, nullptr, 1, cols, 0, Alall}};
-      eval_segs(ks_, a, sg, 3, st_, dres->q_slot);
+      const EvalSeg sg[2] = {{dI, nullptr, rk, cols, 1, AIall}, {d_l, nullptr, 1, cols, 0, Alall}};
+      eval_segs(ks_, a, sg, 2, st_, dres->q_slot);
     }
     evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QR)), dim3(QB), 0, st_, 1, (const double*)AlJ,
-                       (const double*)AIall, (const double*)Alall, cols, rk, Li, W, R, cols, dres);
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QR)), dim3(QB), 0, st_, (const double*)d_x_.as<double>(),
+                       (const double*)AIall, (const double*)Alall, cols, rk, R, cols, dres);
   } else {          // search the column
     double* AallJ = S0;
     double* AIt = AallJ + (size_t)rows * rk;
     double* Aallt = AIt + rk;
+    (void)AIt;   // A(I, t) is evaluated by k_sample_select
     {
-      const EvalSeg sg[3] = {{nullptr, dJ, rows, rk, 0, AallJ}, {dI, d_t, rk, 1, 0, AIt}, {nullptr, d_t, rows, 1, 0, Aallt}};
-      eval_segs(ks_, a, sg, 3, st_, dres->q_slot);
+      const EvalSeg sg[2] = {{nullptr, dJ, rows, rk, 0, AallJ}, {nullptr, d_t, rows, 1, 0, Aallt}};
+      eval_segs(ks_, a, sg, 2, st_, dres->q_slot);
     }
     evals_ += (int64_t)rows * rk + rk + rows;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QR)), dim3(QB), 0, st_, 0, (const double*)AIt,
-                       (const double*)AallJ, (const double*)Aallt, rows, rk, Li, W, R, cols, dres);
+    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QR)), dim3(QB), 0, st_, (const double*)d_x_.as<double>(),
+                       (const double*)AallJ, (const double*)Aallt, rows, rk, R, cols, dres);
   }
   // decide, and border the factors of P_k with the pivot's column, row and
   // corner when the step added it
@@ -1404,13 +1463,21 @@ tt_status Cross::run(CrossOut* out) {
     TTK_TRY(sync());
   }
   // the sample stage stages up to 2 x 64 x MAXR / 4 doubles of LDS per block
-  if (sample_lds(MAXR) > 48 * 1024)
-    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sample_resid),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR)));
+  if (sample_lds(MAXR) > 48 * 1024) {
+    hipError_t e = hipSuccess;
+    with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+      e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(
+              &k_sample_resid<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR));
+    });
+    TTK_HIP(e);
+  }
   if (solve_lds(MAXR) > 48 * 1024)
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_cores),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
   TTK_TRY(mail_.alloc());
+  TTK_TRY(d_x_.alloc(MAXR * sizeof(double)));   // the search stage's P^{-1} u
   // step state: the block counter and the sample-stage scale start at zero
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   fill_zero(d_res_.p, sizeof(StepRes), st_);

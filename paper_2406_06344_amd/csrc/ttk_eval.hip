@@ -6,6 +6,7 @@
 // from (left set row, middle node indices, right set row) and never shipped
 // from the host.  All evaluation is double precision.
 #include "ttk_eval_dev.h"
+#include "ttk_wave.h"
 
 namespace ttk {
 
@@ -18,7 +19,7 @@ constexpr int EB = 256;   // threads per evaluation block
 // patterns, so an integer atomic max is exact).
 __device__ inline void fold_amax(double v, double* amax) {
   __shared__ double red[EB / 64];
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  v = wave64_max(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -111,12 +111,65 @@ __global__ void __launch_bounds__(FC_THREADS) k_factor(StageArgs sa, const T* P,
 // B[k][j] at lane j + 16 k and D[4 (l / 16) + v][l % 16] in register v.
 // A workgroup of 4 waves owns 64 points (16 per wave) and walks the
 // contraction index kk = a + k r_in in slabs of 64 rows of G^{2}, staged in
-// LDS; the A operand s[p, a] T_k(t_p) is formed per lane from LDS.
+// LDS; the A operand s[p, a] T_k(t_p) is formed per lane from LDS.  Output
+// columns go in passes of at most 128, each as wide as its stage needs
+// (r_out rounded up to 16), so no MFMA work is spent on padding beyond that.
 typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int MF_P = 64;     // points per workgroup
 constexpr int MF_KS = 64;    // rows of G^{2} per LDS slab
-constexpr int MF_GLD = 68;   // slab row stride (bank spread across the 4 rows a K-step reads)
+constexpr int MF_NC = 128;   // output columns per pass (8 tiles of 16)
+// Slab row stride for running-row stride sld (> every rank): the widest pass
+// rounded up to 32, plus 16, so it is 16 mod 32 banks and the two rows a
+// half-wave reads in one K-step fall on disjoint banks.
+__host__ __device__ inline int mfma_gld(int sld) {
+  const int wc = min(MF_NC, 16 * ((sld - 1 + 15) / 16));
+  return (wc + 31) / 32 * 32 + 16;
+}
 constexpr int MF_TLD = 33;   // row stride of the Chebyshev table
+
+// The MFMA steps over one staged slab of G^{2} for NJ 16-column tiles.  The
+// A operand of step s is s_in[p, a] T_k(t_p) at this lane's contraction index
+// kk = kk0 + 4 s + kq = a + k r_in, zero past K (from clamped, always valid
+// LDS indices, so no branch); the next step's A and B operands are read from
+// LDS while the current step's MFMAs issue.
+template <int NJ>
+__device__ inline void slab_steps(const float* Gs, int gld, const float* srow, const float* trow, int lane, int kq,
+                                  int kk0, int ck, int K, int rin, int n, f4 (&acc)[MF_NC / 16]) {
+  const int nsteps = (ck + 3) >> 2;
+  int kk = kk0 + kq;
+  int a = kk % rin, k = kk / rin;
+  const int da = 4 % rin, dk = 4 / rin;   // kk += 4 as (a, k) += (da, dk), then at most one wrap
+  const float* g0 = Gs + kq * gld + (lane & 15);
+  // operands of step s into (av, bv): A from the lane's point row and the
+  // Chebyshev table (clamped indices, zero past K), B from the staged slab
+  auto load = [&](int s, float& av, float (&bv)[NJ]) {
+    const float x = srow[min(a, rin - 1)] * trow[min(k, n - 1)];
+    av = kk < K ? x : 0.0f;
+    const float* g = g0 + 4 * s * gld;
+#pragma unroll
+    for (int jb = 0; jb < NJ; ++jb) bv[jb] = g[16 * jb];
+    kk += 4;
+    a += da;
+    k += dk;
+    if (a >= rin) { a -= rin; ++k; }
+  };
+  auto issue = [&](float av, const float (&bv)[NJ]) {
+#pragma unroll
+    for (int jb = 0; jb < NJ; ++jb) acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[jb], acc[jb], 0, 0, 0);
+  };
+  // two operand sets in ping-pong: the loads of one step overlap the MFMAs of
+  // the other, with no register copies
+  float a0, a1, b0v[NJ], b1v[NJ];
+  load(0, a0, b0v);
+  int s = 0;
+  for (; s + 1 < nsteps; s += 2) {
+    load(s + 1, a1, b1v);
+    issue(a0, b0v);
+    if (s + 2 < nsteps) load(s + 2, a0, b0v);
+    issue(a1, b1v);
+  }
+  if (s < nsteps) issue(a0, b0v);
+}
 
 // One tile of MF_P points of one chain.  P: coordinate j of point q at
 // P[j * ldp + q]; points p0 .. p0 + MF_P - 1 of npts; rows written to out.
@@ -125,7 +178,8 @@ __device__ void mfma_tile(const StageArgs& sa, const float* P, int64_t ldp, int6
   float* sTk = smf;                                  // MF_P x MF_TLD
   float* s0 = sTk + MF_P * MF_TLD;                    // MF_P x sld
   float* s1 = s0 + MF_P * sld;                        // MF_P x sld
-  float* Gs = s1 + MF_P * sld;                        // MF_KS x MF_GLD
+  float* Gs = s1 + MF_P * sld;                        // MF_KS x gld
+  const int gld = mfma_gld(sld);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int pl = 16 * w + (lane & 15);                // this lane's point for the A operand
   const int kq = lane >> 4;                           // this lane's row within a K-step
@@ -151,38 +205,52 @@ __device__ void mfma_tile(const StageArgs& sa, const float* P, int64_t ldp, int6
     }
     __syncthreads();
     const int K = rin * n;
-    for (int b0 = 0; b0 < rout; b0 += 64) {
-      f4 acc[4];
+    for (int b0 = 0; b0 < rout; b0 += MF_NC) {
+      const int cb = min(MF_NC, rout - b0);
+      const int nj = (cb + 15) >> 4;                 // 16-column tiles in this pass
+      const int wc = nj * 16;                        // staged slab width
+      f4 acc[MF_NC / 16];
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) acc[jb] = f4{0.f, 0.f, 0.f, 0.f};
-      const int cb = min(64, rout - b0);
+      for (int jb = 0; jb < MF_NC / 16; ++jb) acc[jb] = f4{0.f, 0.f, 0.f, 0.f};
+      // slab staging: thread t owns column t % 128 of rows t / 128 + 2 u; the
+      // next slab is loaded into registers while the current one is used
+      const int sc = tid & (MF_NC - 1), sr = tid >> 7;
+      float pre[MF_KS / 2];
+      auto load_slab = [&](int k0) {
+        const int ckn = min(MF_KS, K - k0);
+        const float* g = G + (size_t)(k0 + sr) * rout + b0 + sc;   // row k0 + sr of this pass
+        const int stride = 2 * rout;
+#pragma unroll
+        for (int u = 0; u < MF_KS / 2; ++u)
+          pre[u] = (sc < cb && sr + 2 * u < ckn) ? g[u * stride] : 0.0f;
+      };
+      load_slab(0);
       for (int kk0 = 0; kk0 < K; kk0 += MF_KS) {
         const int ck = min(MF_KS, K - kk0);
         __syncthreads();                               // the previous slab is consumed
-        for (int e = tid; e < MF_KS * 64; e += 256) {
-          const int r = e >> 6, c = e & 63;
-          Gs[r * MF_GLD + c] = (r < ck && c < cb) ? G[(int64_t)(kk0 + r) * rout + b0 + c] : 0.0f;
-        }
-        __syncthreads();
-        // this lane's contraction index kk = kk0 + 4 s + kq as (a, k)
-        int kk = kk0 + kq;
-        int a = kk % rin, k = kk / rin;
-        const int nsteps = (ck + 3) >> 2;
-        for (int s4 = 0; s4 < nsteps; ++s4) {
-          const float av = (kk < K) ? sin[pl * sld + a] * sTk[pl * MF_TLD + k] : 0.0f;
-          const float* gr = Gs + (4 * s4 + kq) * MF_GLD + (lane & 15);
+        if (sc < wc)
 #pragma unroll
-          for (int jb = 0; jb < 4; ++jb) acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, gr[16 * jb], acc[jb], 0, 0, 0);
-          kk += 4;
-          a += 4;
-          while (a >= rin) { a -= rin; ++k; }
+          for (int u = 0; u < MF_KS / 2; ++u) Gs[(sr + 2 * u) * gld + sc] = pre[u];
+        __syncthreads();
+        if (kk0 + MF_KS < K) load_slab(kk0 + MF_KS);
+        const float* srow = sin + pl * sld;
+        const float* trow = sTk + pl * MF_TLD;
+        switch (nj) {
+          case 1: slab_steps<1>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 2: slab_steps<2>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 3: slab_steps<3>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 4: slab_steps<4>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 5: slab_steps<5>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 6: slab_steps<6>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          case 7: slab_steps<7>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
+          default: slab_steps<8>(Gs, gld, srow, trow, lane, kq, kk0, ck, K, rin, n, acc); break;
         }
       }
       // D[4 (l / 16) + v][l % 16]: point 16 w + 4 (l / 16) + v, column b0 + 16 jb + l % 16
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
+      for (int jb = 0; jb < MF_NC / 16; ++jb) {
         const int col = b0 + 16 * jb + (lane & 15);
-        if (col < rout)
+        if (jb < nj && col < rout)
 #pragma unroll
           for (int v = 0; v < 4; ++v) sout[(16 * w + 4 * kq + v) * sld + col] = acc[jb][v];
       }
@@ -246,9 +314,13 @@ __global__ void __launch_bounds__(256) k_factor_mfma_batch(const FacJob* jobs, c
   }
 }
 
+// LDS row stride of the running rows: odd, so the 16 points a K-step reads
+// fall on 16 distinct banks
+inline int mfma_sld(int rmax) { return (rmax + 1) | 1; }
+
 size_t mfma_lds_bytes(int rmax) {
-  const int sld = rmax + 1;
-  return sizeof(float) * ((size_t)MF_P * MF_TLD + 2 * (size_t)MF_P * sld + (size_t)MF_KS * MF_GLD);
+  const int sld = mfma_sld(rmax);
+  return sizeof(float) * ((size_t)MF_P * MF_TLD + 2 * (size_t)MF_P * sld + (size_t)MF_KS * mfma_gld(sld));
 }
 
 int lds_limit() {
@@ -274,7 +346,7 @@ tt_status launch_factor_mfma(const StageArgs& sa, const void* P, int64_t ldp, in
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   if (ldp == npts) {
     hipLaunchKernelGGL(k_factor_mfma, dim3((unsigned)((npts + MF_P - 1) / MF_P)), dim3(256), sh, st, sa,
-                       static_cast<const float*>(P), npts, static_cast<float*>(out), ldo, sa.rmax + 1);
+                       static_cast<const float*>(P), npts, static_cast<float*>(out), ldo, mfma_sld(sa.rmax));
     TTK_HIP(hipGetLastError());
     *launched = true;
   }
@@ -386,7 +458,7 @@ tt_status factor_contract_batch(int dtype, const FactorJob* jobs, int njobs, int
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh));
   const int64_t g = grid > 0 ? std::min<int64_t>(grid, plan->tiles) : plan->tiles;
   hipLaunchKernelGGL(k_factor_mfma_batch, dim3((unsigned)g), dim3(256), sh, st, plan->desc.as<const FacJob>(),
-                     plan->prefix.as<const int64_t>(), njobs, rmax + 1);
+                     plan->prefix.as<const int64_t>(), njobs, mfma_sld(rmax));
   TTK_HIP(hipGetLastError());
   plan->persistent = true;
   return TTK_OK;

@@ -6,6 +6,7 @@
 // factorisations run in one workgroup: they are sequential in the column
 // index and their sizes (<= 8192 x 256) keep them in L2.
 #include "ttk_internal.h"
+#include "ttk_wave.h"
 
 namespace ttk {
 
@@ -16,23 +17,6 @@ constexpr int NW = BS / 64;   // waves per workgroup
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over each row of 16 lanes, in every lane of the row: a butterfly of
-// DPP row rotations (by 8, 4, 2, 1) on the two 32-bit halves, no LDS traffic.
-template <int N>
-__device__ inline double row_ror(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x120 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x120 + N, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ inline double row16_sum(double v) {
-  v += row_ror<8>(v);
-  v += row_ror<4>(v);
-  v += row_ror<2>(v);
-  v += row_ror<1>(v);
   return v;
 }
 
