@@ -31,6 +31,14 @@ Readings of the paper taken here (each written out in the design notes):
   applied by a direct LU solve.  The cores returned are those whose sampled
   error the stopping test measured last.  C_N = F_N.  (The QR form
   Q Q[J,:]^{-1} of F_k = Q R, equal in exact arithmetic, stays available.)
+* Replay of decisions taken by another computation of the same residuals
+  (the GPU path): a forced choice is accepted if its |R| here lies within the
+  tie band of this computation's maximum, widened by twice the disagreement
+  the two computations show on the same residuals (|sample max| there vs
+  here, and |R| at the forced pivot there vs here), which must itself stay
+  below 10 tau.  Algorithm 5 takes an argmax of computed residuals, so an
+  entry whose residual is within rounding of the band edge is an equally
+  valid choice; the add test |R| > tau is judged the same way.
 * Initialisation (Algorithm 7): q_1, q_2 are full random multi-indices; a
   snapshot (all sets, max condition number of the half-sweep) is kept after
   every half-sweep and the one with the smallest maximum is returned (earliest
@@ -85,6 +93,14 @@ def _argmin_band(vals, rel):
         return int(np.argmax(vals == m)) if np.any(vals == m) else 0
     cand = np.nonzero(vals <= m * (1.0 + rel))[0]
     return int(cand[0])
+
+
+def _forced_eps(forced, eps, here):
+    """Largest disagreement seen so far in the step between the forced
+    computation's residuals and this one's (|R| at the forced pivot)."""
+    if "pivot_abs" in forced:
+        eps = max(eps, abs(float(forced["pivot_abs"]) - here))
+    return eps
 
 
 def _argmax_band(absvals, tau):
@@ -244,10 +260,13 @@ def update_cross(ent, L, R, k, sweep, seed, max_rank, forced=None):
     p, m0, margin0 = _argmax_band(np.abs(Rs), tau)
     rec = {"sweep": sweep, "k": k, "rank_before": rk,
            "sample_pos": int(lin[p]), "sample_max": m0, "sample_margin": margin0}
+    eps = 0.0   # disagreement between the forced computation's residuals and these
     if forced is not None:
         fpos = int(forced["sample_pos"])
         where = np.nonzero(lin == fpos)[0]
-        ok = where.size == 1 and abs(Rs[where[0]]) >= m0 - max(tau, 1e-9 * m0)
+        if "sample_max" in forced:
+            eps = abs(float(forced["sample_max"]) - m0)
+        ok = where.size == 1 and abs(Rs[where[0]]) >= m0 - max(tau, 1e-9 * m0) - 2 * eps and eps <= 10 * tau
         rec["replay_sample_ok"] = bool(ok)
         if where.size == 1:
             p = int(where[0])
@@ -265,7 +284,8 @@ def update_cross(ent, L, R, k, sweep, seed, max_rank, forced=None):
         q, m1, margin1 = _argmax_band(np.abs(Rrow), tau)
         if forced is not None:
             fq = int(forced["pivot_col"])
-            rec["replay_search_ok"] = bool(abs(Rrow[fq]) >= m1 - max(tau, 1e-9 * m1))
+            eps = _forced_eps(forced, eps, abs(Rrow[fq]))
+            rec["replay_search_ok"] = bool(abs(Rrow[fq]) >= m1 - max(tau, 1e-9 * m1) - 2 * eps and eps <= 10 * tau)
             q = fq
         t = q
         val = abs(Rrow[t])
@@ -280,13 +300,16 @@ def update_cross(ent, L, R, k, sweep, seed, max_rank, forced=None):
         q, m1, margin1 = _argmax_band(np.abs(Rcol), tau)
         if forced is not None:
             fq = int(forced["pivot_row"])
-            rec["replay_search_ok"] = bool(abs(Rcol[fq]) >= m1 - max(tau, 1e-9 * m1))
+            eps = _forced_eps(forced, eps, abs(Rcol[fq]))
+            rec["replay_search_ok"] = bool(abs(Rcol[fq]) >= m1 - max(tau, 1e-9 * m1) - 2 * eps and eps <= 10 * tau)
             q = fq
         l = q
         val = abs(Rcol[l])
-    add = (val > tau) and (l not in set(I.tolist())) and (t not in set(J.tolist())) and rk < max_rank
+    fresh = (l not in set(I.tolist())) and (t not in set(J.tolist())) and rk < max_rank
+    add = (val > tau) and fresh
     if forced is not None:
-        rec["replay_add_ok"] = bool(add == bool(forced["added"]))
+        # |R| > tau within rounding of the band edge may go either way
+        rec["replay_add_ok"] = bool(add == bool(forced["added"]) or (fresh and abs(val - tau) <= 2 * eps))
         add = bool(forced["added"])
     rec.update({"pivot_row": l, "pivot_col": t, "pivot_abs": float(val),
                 "search_margin": margin1, "tau": float(tau), "added": bool(add)})

@@ -60,11 +60,28 @@ struct StepRes {
   double s_max, s_margin, s_scale, s_tau;
   double q_max, q_margin, q_scale, q_tau;
   double pivot_abs, pad;
-  int32_t ctr, pad2;   // blocks done in the current residual launch (reset by the last)
+  int32_t pad2, pad3;
   // running max |entry| of the step's evaluations, spread over AMAX_SLOTS
   // slots (block b folds into slot b mod AMAX_SLOTS) to avoid one contended
   // address; cleared at the end of every step
   double s_slot[AMAX_SLOTS], q_slot[AMAX_SLOTS];
+};
+
+// The inputs of one update step in one of its two variants: variant v holds
+// what the step uses when the previous step of the sweep added (v = 1) or did
+// not add (v = 0) a pivot, which changes the left rank r_{k-1}, hence the
+// super-core rows, the sample draw, the row positions of P_k's pivots and the
+// left index set (whose extra row the previous step's finishing kernel
+// writes).  The step's kernels read desc[*sel], with *sel written by that
+// finishing kernel, so the host can enqueue a step before the previous one
+// has decided.
+struct StepDesc {
+  Addr a;                 // super-core k: left set (with a spare row), right set
+  const int32_t* I;       // row positions of P_k's pivots (r_k)
+  const int32_t* J;       // column positions (r_k)
+  const int32_t* srow;    // samples, generation order (ns)
+  const int32_t* scol;
+  int rows, cols, ns, bit;
 };
 
 __device__ inline double wsum(double v) { return wave64_sum(v); }
@@ -163,22 +180,6 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
   if (e >= (int64_t)m * n) return;
   const int i = (int)(e % m), j = (int)(e / m);
   B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
-}
-
-// True in every thread of the block that finishes last among the blocks of
-// the launch (the results of every block are then visible to it); *ctr counts
-// finished blocks and is reset by the last one.
-__device__ inline bool last_block(int32_t* ctr) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s_last = atomicAdd(ctr, 1) == (int)gridDim.x - 1;
-    if (s_last) *ctr = 0;
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last;
 }
 
 // TT value at test multi-indices: cores given column-major C_k
@@ -294,25 +295,29 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
 // MAXR, so a wave's loads are contiguous).  With r rounded up to 64 as ru,
-// min(4, BS / ru) threads share a row, each over a contiguous range of q with
-// eight loads in flight; the partial sums meet in scratch (BS doubles).  Every
-// thread of the block calls it; out is visible to all on return.
+// min(8, BS / ru) threads share a row, each over a contiguous range of q in
+// batches of 32 loads issued together (one batch covers r <= 128 for
+// BS = 256 and r <= 256 for BS = 1024); the partial sums meet in scratch (BS
+// doubles).  Every thread of the block calls it; out is visible to all on
+// return.
 template <int BS>
 __device__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch) {
+  constexpr int RB = 32;
   const int ru = (r + 63) & ~63;
-  const int S = min(4, BS / ru);
+  const int S = min(8, BS / ru);
   const int tid = threadIdx.x, t = tid % ru, h = tid / ru;
   double acc = 0.0;
   if (h < S && t < r) {
     const int chunk = (r + S - 1) / S;
     const int q0 = h * chunk, q1 = min(r, q0 + chunk);
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int q = q0;
-    for (; q + 7 < q1; q += 8) {
+    for (int q = q0; q < q1; q += RB) {
+      double mv[RB];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += M[t + (int64_t)(q + u) * MAXR] * v[q + u];
+      for (int u = 0; u < RB; ++u) mv[u] = q + u < q1 ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) a[u & 7] += q + u < q1 ? mv[u] * v[q + u] : 0.0;
     }
-    for (; q < q1; ++q) a[0] += M[t + (int64_t)q * MAXR] * v[q];
     acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   scratch[tid] = acc;
@@ -412,47 +417,102 @@ __device__ inline double slots_max(const double* sl) {
 // (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16], D row
 // l / 16 + 4 v, column l % 16 in lane l, slot v).  The block evaluates its
 // samples' entries A(s_i, J_q), A(I_q, s_i) and A(s_i) itself, straight into
-// LDS in MFMA lane order (dynamic, 2 x 64 x ceil(r / 4) doubles), and folds
-// their max |.| into the sample-stage slots; the B operands (rows of W^T and
-// Li) stream from L2, eight MFMA steps of loads in flight per batch.
-constexpr int SW = 4;    // waves per block
-constexpr int SPB = 8;  // samples per block (MFMA rows SPB..15 are zero): twice the blocks of a
-                        // full 16-row tile, so the entry evaluations spread over more CUs
-constexpr int SB = 8;   // MFMA steps per batch of B loads
+// LDS in MFMA lane order, and folds their max |.| into the sample-stage
+// slots.  The coordinates are staged in LDS first: per q the row half of
+// I_q and the column half of J_q in one D-vector (the halves occupy
+// disjoint positions), per sample the coordinates of the sample itself, so
+// every entry combines two LDS vectors.  Each wave owns one 16-column tile
+// of G and T at a time; the B operands of its first tile (rows of W^T and
+// Li) are loaded into registers before the entries are evaluated, which
+// hides their latency behind the evaluation.
+constexpr int SW = 8;    // waves per block
+constexpr int SPB = 8;   // samples per block (MFMA rows SPB..15 are zero): twice the blocks of a
+                         // full 16-row tile, so the entry evaluations spread over more CUs
+constexpr int SB = 32;   // MFMA steps of B operands held in registers (r <= 128: one batch)
 template <int d, int dt, bool G>
-__global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, Addr ad, const int32_t* srow,
-                                                          const int32_t* scol, const int32_t* I, const int32_t* J,
-                                                          int ns, int r, const double* Li, const double* W,
-                                                          double* R, double* slots) {
+__global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDesc* desc, const int32_t* sel, int r,
+                                                          const double* Li, const double* W, double* R,
+                                                          double* slots) {
   constexpr int D = 2 * d + dt;
-  extern __shared__ double sa[];
-  __shared__ double red[SW][16], sn[D * MAXN], sAs[16], redm[SW];
-  __shared__ int sr[16], sc[16];
+  const StepDesc& sd = desc[*sel];
+  const Addr ad = sd.a;
+  const int32_t* srow = sd.srow;
+  const int32_t* scol = sd.scol;
+  const int32_t* I = sd.I;
+  const int32_t* J = sd.J;
+  const int ns = sd.ns;
+  extern __shared__ double sa[];   // A operands (2 x 64 x nst), then IJ (r x D)
+  __shared__ double red[SW][16], sn[D * MAXN], sAs[16], redm[SW], S[SPB * D];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
+  const int li = lane & 15, lg = lane >> 4;
   const int i0 = blockIdx.x * SPB;
+  const int nv = min(SPB, ns - i0);   // samples of this block (none past the variant's extent)
   const int nst = (r + 3) / 4;
-  if (tid < 16) {
-    const bool ok = tid < SPB && i0 + tid < ns;
-    sr[tid] = ok ? srow[i0 + tid] : 0;
-    sc[tid] = ok ? scol[i0 + tid] : 0;
+  const int ntile = (r + 15) / 16;
+  double* IJ = sa + 2 * 64 * nst;
+  const double* Wt = W + FT;
+  double bg[SB], bt[SB];
+  {
+    const int p = wv * 16 + li;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int q = 4 * u + lg;
+      const bool ok = p < r && q < r;
+      bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
+      bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
+    }
   }
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
-  double m = 0.0;
-  for (int e = tid; e < 64 * nst; e += SW * 64) {
-    const int ii = e & 15, q = e >> 4;
-    const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
-    double vg = 0.0, vt = 0.0;
-    if (ii < SPB && i0 + ii < ns && q < r) {
-      vg = addr_eval<d, dt, G>(ks, ad, sn, sr[ii], J[q]);
-      vt = addr_eval<d, dt, G>(ks, ad, sn, I[q], sc[ii]);
-      m = fmax(m, fmax(fabs(vg), fabs(vt)));
+  for (int q = tid; q < r; q += SW * 64) {
+    double c[D];
+    addr_row_part<D>(ad, sn, I[q], c);
+    addr_col_part<D>(ad, sn, J[q], c);
+#pragma unroll
+    for (int j = 0; j < D; ++j) IJ[q * D + j] = c[j];
+  }
+  if (tid < SPB) {
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = 0.0;
+    if (tid < nv) {
+      addr_row_part<D>(ad, sn, srow[i0 + tid], c);
+      addr_col_part<D>(ad, sn, scol[i0 + tid], c);
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) S[tid * D + j] = c[j];
+  }
+  for (int e = tid; e < 64 * nst; e += SW * 64) {   // operand rows without a sample or a q
+    const int ii = e & 15, q = e >> 4;
+    if (ii >= nv || q >= r) {
+      const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
+      sa[slot] = 0.0;
+      sa[64 * nst + slot] = 0.0;
+    }
+  }
+  __syncthreads();
+  double m = 0.0;
+  for (int e = tid; e < SPB * r; e += SW * 64) {
+    const int ii = e & (SPB - 1), q = e / SPB;
+    if (ii >= nv) continue;
+    double cg[D], ct[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const double sj = S[ii * D + j], qj = IJ[q * D + j];
+      cg[j] = j <= ad.lk ? sj : qj;   // A(s_i, J_q)
+      ct[j] = j <= ad.lk ? qj : sj;   // A(I_q, s_i)
+    }
+    const double vg = kappa_eval<d, dt, G>(ks.kind, ks.kconst, cg);
+    const double vt = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ct);
+    const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
     sa[slot] = vg;
     sa[64 * nst + slot] = vt;
+    m = fmax(m, fmax(fabs(vg), fabs(vt)));
   }
-  if (tid < SPB && i0 + tid < ns) {
-    const double v = addr_eval<d, dt, G>(ks, ad, sn, sr[tid], sc[tid]);
+  if (tid < nv) {
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = S[tid * D + j];
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
     sAs[tid] = v;
     m = fmax(m, fabs(v));
   }
@@ -465,21 +525,20 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, Addr ad, con
     atomicMax(reinterpret_cast<unsigned long long*>(slots + blockIdx.x % AMAX_SLOTS),
               (unsigned long long)__double_as_longlong(m));
   }
-  const double* Wt = W + FT;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  const int ntile = (r + 15) / 16;
   for (int jt = wv; jt < ntile; jt += SW) {
     const int p = jt * 16 + li;
     const bool pok = p < r;
     dbl4 g = {0.0, 0.0, 0.0, 0.0}, t = {0.0, 0.0, 0.0, 0.0};
     for (int s0 = 0; s0 < nst; s0 += SB) {
-      double bg[SB], bt[SB];
+      if (jt != wv || s0 != 0) {   // (the first batch of the first tile is already loaded)
 #pragma unroll
-      for (int u = 0; u < SB; ++u) {
-        const int q = 4 * (s0 + u) + lk;
-        const bool ok = pok && q < r;
-        bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
-        bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
+        for (int u = 0; u < SB; ++u) {
+          const int q = 4 * (s0 + u) + lg;
+          const bool ok = pok && q < r;
+          bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
+          bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
+        }
       }
 #pragma unroll
       for (int u = 0; u < SB; ++u) {
@@ -497,31 +556,38 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, Addr ad, con
     part[v] = row16_sum(part[v]);
   if (li == 0)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[wv][lk + 4 * v] = part[v];
+    for (int v = 0; v < 4; ++v) red[wv][lg + 4 * v] = part[v];
   __syncthreads();
-  if (tid < SPB && i0 + tid < ns) {
+  if (tid < nv) {
     double s = 0.0;
     for (int w = 0; w < SW; ++w) s += red[w][tid];
     R[i0 + tid] = s - sAs[tid];
   }
 }
 
-// dynamic LDS of k_sample_resid for rank r
-inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
+// dynamic LDS of k_sample_resid for rank r and D coordinates per entry
+inline size_t sample_lds(int r, int D) {
+  return ((size_t)2 * 64 * ((r + 3) / 4) + (size_t)r * D) * sizeof(double);
+}
 
 // Sample-stage selection over the residuals of k_sample_resid (one block),
 // then the search stage's solve: u = A(l, J) for a row search (bit 1) or
 // u = A(I, t) for a column search (bit 0) is evaluated here and
-// x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search_resid
+// x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search
 // (P^{-1} applied to one vector, through the rows of the factors or of their
 // transposes).  |u| folds into the search-stage scale.
 template <int d, int dt, bool G>
-__global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, Addr a, const double* R, int ns,
-                                                        const int32_t* srow, const int32_t* scol, int cols,
-                                                        const double* luamax, StepRes* res, int bit,
-                                                        const int32_t* I, const int32_t* J, int r, const double* Li,
-                                                        const double* W, double* x) {
+__global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc* desc, const int32_t* sel,
+                                                        const double* R, const double* luamax, StepRes* res, int r,
+                                                        const double* Li, const double* W, double* x) {
   constexpr int D = 2 * d + dt;
+  const StepDesc& sdv = desc[*sel];
+  const Addr a = sdv.a;
+  const int32_t* srow = sdv.srow;
+  const int32_t* scol = sdv.scol;
+  const int32_t* I = sdv.I;
+  const int32_t* J = sdv.J;
+  const int ns = sdv.ns, cols = sdv.cols, bit = sdv.bit;
   __shared__ double sn[D * MAXN], su[MAXR], sy[MAXR], scr[1024], red[16];
   const int p = select_block<1024>(R, ns, srow, scol, cols, 0, fmax(slots_max(res->s_slot), *luamax), res);
   const int l = srow[p], t = scol[p];
@@ -550,38 +616,67 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, Addr a, const 
   for (int q = threadIdx.x; q < r; q += 1024) x[q] = su[q];
 }
 
-// Search stage: R_i = sum_q Lm[i + q n] x_q - Ad[i] over the searched fibre
-// with x from k_sample_select, 64 entries per block with four threads on
-// each, then the selection in the block that finishes last.
-constexpr int QB = 256;
-constexpr int QR = 64;   // fibre entries per block
-__global__ void __launch_bounds__(QB) k_search_resid(const double* x, const double* Lm, const double* Ad, int n,
-                                                     int r, double* R, int cols, StepRes* res) {
-  __shared__ double sx[MAXR], scr[QB];
+// Search stage: the residual over the searched fibre,
+//   R_i = sum_q A(I_q, i) x_q - A(l, i)   (row search, bit 1, i < cols), or
+//   R_i = sum_q A(i, J_q) x_q - A(i, t)   (column search, bit 0, i < rows),
+// with (l, t) the chosen sample and x = P^{-1} u from k_sample_select.  The
+// entries are evaluated where they are used and never stored: sixteen
+// fibre entries per block, one 16-lane row per entry with the q terms
+// strided over its lanes and summed by DPP.  The fixed side's coordinates
+// (rows I_q and l, or columns J_q and t) are staged in LDS once per block.
+// The entries' max |.| folds into the search-stage slots.
+constexpr int QE = 16;   // fibre entries per block
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, const int32_t* sel,
+                                                const StepRes* res, const double* x, int r, double* R,
+                                                double* slots) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN], sx[MAXR + 1], fc[(MAXR + 1) * D], redm[4];
+  const StepDesc& sd = desc[*sel];
+  const Addr a = sd.a;
+  const int bit = sd.bit;
+  const int n = bit ? sd.cols : sd.rows;
   const int tid = threadIdx.x;
-  for (int q = tid; q < r; q += QB) sx[q] = x[q];
-  __syncthreads();
-  {
-    const int i = blockIdx.x * QR + (tid & (QR - 1)), h = tid / QR;
-    const int chunk = (r + QB / QR - 1) / (QB / QR);
-    const int q0 = h * chunk, q1 = min(r, q0 + chunk);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (i < n) {
-      int q = q0;
-      for (; q + 3 < q1; q += 4) {
-        a0 += Lm[i + (int64_t)q * n] * sx[q];
-        a1 += Lm[i + (int64_t)(q + 1) * n] * sx[q + 1];
-        a2 += Lm[i + (int64_t)(q + 2) * n] * sx[q + 2];
-        a3 += Lm[i + (int64_t)(q + 3) * n] * sx[q + 3];
-      }
-      for (; q < q1; ++q) a0 += Lm[i + (int64_t)q * n] * sx[q];
-    }
-    scr[tid] = (a0 + a1) + (a2 + a3);
-    __syncthreads();
-    if (tid < QR && i < n) R[i] = ((scr[tid] + scr[tid + QR]) + (scr[tid + 2 * QR] + scr[tid + 3 * QR])) - Ad[i];
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  const int l = res->l, t = res->t;
+  for (int q = tid; q <= r; q += 256) {
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = 0.0;
+    if (bit) addr_row_part<D>(a, sn, q < r ? sd.I[q] : l, c);
+    else addr_col_part<D>(a, sn, q < r ? sd.J[q] : t, c);
+#pragma unroll
+    for (int j = 0; j < D; ++j) fc[q * D + j] = c[j];
+    sx[q] = q < r ? x[q] : -1.0;   // the fibre's own entry enters with weight -1
   }
-  if (!last_block(&res->ctr)) return;
-  select_block<QB>(R, n, nullptr, nullptr, cols, 1, fmax(res->q_scale, slots_max(res->q_slot)), res);
+  __syncthreads();
+  const int i = blockIdx.x * QE + (tid >> 4), lj = tid & 15;
+  double acc = 0.0, m = 0.0;
+  if (i < n) {
+    double vc[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) vc[j] = 0.0;
+    if (bit) addr_col_part<D>(a, sn, i, vc);
+    else addr_row_part<D>(a, sn, i, vc);
+    for (int q = lj; q <= r; q += 16) {
+      double c[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[q * D + j] : vc[j];
+      const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+      acc += v * sx[q];
+      m = fmax(m, fabs(v));
+    }
+  }
+  acc = row16_sum(acc);
+  if (lj == 0 && i < n) R[i] = acc;
+  m = wave64_max(m);
+  if ((tid & 63) == 0) redm[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) {
+    m = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+    atomicMax(reinterpret_cast<unsigned long long*>(slots + blockIdx.x % AMAX_SLOTS),
+              (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // The border of P_k's factors for the pivot (row, col) added by step k:
@@ -656,23 +751,34 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
   }
 }
 
-// End of a step, one block: the pivot (l, t) from the two stages; it is added
+// End of a step, one block: the search stage's selection, then the pivot
+// (l, t) from the two stages; it is added
 // if its residual exceeds the tie band, it is not yet in I or J and the rank
 // is below the cap.  Then, if added, the border of P_k (border_factors).
 // Clears the fold slots for the next step and publishes the result to the
 // host mailbox.
 template <int d, int dt, bool G>
-__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* res, int bit, const int32_t* I,
-                                                     const int32_t* J, int r, int max_rank, double* Li, double* W,
+__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, const StepDesc* desc, const int32_t* sel,
+                                                     const double* R, StepRes* res, int r, int max_rank,
+                                                     double* Li, double* W,
                                                      double* amax, int32_t* info, StepRes* mail, uint32_t* mail_seq,
-                                                     uint32_t seq) {
+                                                     uint32_t seq, int32_t* sel_next, int16_t* next_left,
+                                                     int next_row) {
   constexpr int D = 2 * d + dt;
+  const StepDesc& sd = desc[*sel];
+  const Addr a = sd.a;
+  const int bit = sd.bit;
+  const int32_t* I = sd.I;
+  const int32_t* J = sd.J;
   __shared__ double sn[D * MAXN];
   __shared__ int s_added, s_row, s_col;
   const int tid = threadIdx.x;
+  // the search stage's selection over R (written by k_search)
+  const int qp = select_block<256>(R, bit ? sd.cols : sd.rows, nullptr, nullptr, sd.cols, 1,
+                                   fmax(res->q_scale, slots_max(res->q_slot)), res);
   if (tid == 0) {
-    s_row = bit ? res->l : res->q_pos;
-    s_col = bit ? res->q_pos : res->t;
+    s_row = bit ? res->l : qp;
+    s_col = bit ? qp : res->t;
   }
   stage_nodes<D>(ks.nodes, sn);
   const int row = s_row, col = s_col;
@@ -694,6 +800,15 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, Addr a, StepRes* 
   }
   __syncthreads();
   if (s_added) border_factors<d, dt, G>(ks, a, sn, res, I, J, r, row, col, Li, W, amax, info);
+  // the next step of the sweep runs on variant s_added; if the pivot was
+  // added, I^{<=k} gains the row (left row s of the pivot, node i_k), which
+  // the next step's left set receives after its r_k current rows
+  if (tid == 0 && sel_next) *sel_next = s_added;
+  if (s_added && next_left) {
+    const int s = row % a.rl, ik = row / a.rl;
+    for (int j = tid; j <= a.lk; j += 256)
+      next_left[(size_t)next_row * (a.lk + 1) + j] = j < a.lk ? a.left[(size_t)s * a.lk + j] : (int16_t)ik;
+  }
   // publish the step's result to the host mailbox: the fields up to the
   // fold slots, then (after a system-scope fence) the sequence number the
   // host waits for
@@ -873,7 +988,26 @@ class Cross {
 
   tt_status upload_sets(int k_left, int k_right, int16_t* dl, int16_t* dr);
   tt_status init_sets();
-  tt_status update_step(int k, int sweep, tt_kernel_decision* rec);
+  // One update step of a sweep (Alg 5) as the host prepares it.  While the
+  // previous step of the sweep is still on the device, both of its possible
+  // outcomes are prepared (variant v = 1: it adds a pivot) and the kernels
+  // read the variant that the previous finishing kernel selects.
+  struct HostStep {
+    int k = 0, sweep = 0, rk = 0, nvar = 1, var = 0, cols = 0;
+    int rows[2] = {0, 0}, ns[2] = {0, 0}, bit[2] = {0, 0};
+    std::vector<int64_t> lin[2];        // samples (linear positions), generation order
+    const StepDesc* desc = nullptr;     // device, two entries
+    const int32_t* sel = nullptr;       // device: the entry the kernels read
+    int16_t* left = nullptr;            // device I^{<=k-1}, spare row after rank(k-1) rows
+    uint32_t seq = 0;                   // mailbox sequence number of its finishing kernel
+  };
+  HostStep hs_[2];
+  DBuf d_sel_;   // int32: variant selectors of odd and even steps, then a constant 0
+  int max_rank() const { return std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR); }
+  tt_status prepare_step(HostStep& h, int k, int sweep, bool speculate);
+  tt_status enqueue_front(const HostStep& h);
+  tt_status enqueue_finish(HostStep& h, const HostStep* next);
+  tt_status collect(const HostStep& h, tt_kernel_decision* rec);
   tt_status build_cores(std::vector<double*>* C);
   tt_status refine_cores();
   tt_status init_inverses();
@@ -900,7 +1034,7 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_vals_, d_res_, d_R_, d_x_;
+  DBuf d_left_, d_right_, d_res_, d_R_, d_x_;
   DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
@@ -911,25 +1045,32 @@ class Cross {
   HostMail mail_;
   uint32_t mail_seq_ = 0;
   tt_status wait_mail(uint32_t seq);
-  // upload arena: host pinned + device mirror, bump-allocated between stream
-  // synchronisations, flushed with one copy before the kernels that read it
+  // upload arena: host pinned + device mirror, bump-allocated, flushed with
+  // one copy before the kernels that read it.  Update steps alternate
+  // between its two halves (step k uses half k & 1), so a step can be
+  // uploaded while the previous one runs; the whole arena is reset only
+  // after a stream synchronisation.
   HBuf ar_h_;
   DBuf ar_d_;
-  size_t ar_off_ = 0, ar_flushed_ = 0, ar_cap_ = 0;
+  size_t ar_off_ = 0, ar_flushed_ = 0, ar_cap_ = 0, ar_end_ = 0;
   const int16_t* cur_left_ = nullptr;
   const int16_t* cur_right_ = nullptr;
   tt_status arena_init(size_t bytes) {
-    ar_cap_ = bytes;
+    ar_cap_ = ar_end_ = bytes;
     TTK_TRY(ar_h_.alloc(bytes));
     TTK_TRY(ar_d_.alloc(bytes));
     return TTK_OK;
   }
-  void arena_reset() { ar_off_ = ar_flushed_ = 0; }   // only after a stream synchronisation
+  void arena_reset(int half = -1) {
+    const size_t mid = (ar_cap_ / 2) & ~(size_t)255;
+    ar_off_ = ar_flushed_ = half == 1 ? mid : 0;
+    ar_end_ = half == 0 ? mid : ar_cap_;
+  }
   template <class T>
   tt_status arena_push(const T* src, size_t n, const T** dev) {
     const size_t at = (ar_off_ + 255) & ~(size_t)255;
     const size_t bytes = n * sizeof(T);
-    if (at + bytes > ar_cap_) return fail(TTK_ERR_OOM, "cross upload arena too small (%zu bytes)", ar_cap_);
+    if (at + bytes > ar_end_) return fail(TTK_ERR_OOM, "cross upload arena too small (%zu bytes)", ar_cap_);
     if (bytes) std::memcpy(ar_h_.as<char>() + at, src, bytes);
     *dev = reinterpret_cast<const T*>(ar_d_.as<char>() + at);
     ar_off_ = at + bytes;
@@ -1191,106 +1332,151 @@ tt_status Cross::wait_mail(uint32_t seq) {
   }
 }
 
-tt_status Cross::update_step(int k, int sweep, tt_kernel_decision* rec) {
+// Uploads step k of the sweep: the left set I^{<=k-1} (with a spare row for
+// the one the previous step may add, which its finishing kernel writes), the
+// right set I^{>k+1}, and per variant the pivot positions, the samples (drawn
+// from the step's own keyed stream, so both variants draw as the oracle does
+// for its r_{k-1}) and the descriptor.
+tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
   const int N = N_;
-  const int rl = rank(k - 1), rr = rank(k + 1), rk = rank(k);
+  const int rl0 = rank(k - 1), rr = rank(k + 1), rk = rank(k);
   const int nk = g_.n[k - 1], nk1 = g_.n[k];
-  const int rows = rl * nk, cols = nk1 * rr;
-  std::vector<int32_t> I, J;
-  pivot_positions(k, &I, &J);
-  SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)sweep, (uint64_t)k);
-  const int ns = std::max(rows, cols);
-  // samples in generation order; the device breaks ties by linear position
-  std::vector<int64_t> lin = g.floyd_unsorted((int64_t)rows * cols, ns);
-  const int bit = g.bit();
-  // upload the neighbouring sets and the integer lists in one copy
-  arena_reset();
-  TTK_TRY(upload_sets(k - 1, k + 1, nullptr, nullptr));
-  const size_t nint = (size_t)2 * rk + 2 * (size_t)ns;
-  std::vector<int32_t> hi(nint);
-  std::copy(I.begin(), I.end(), hi.begin());
-  std::copy(J.begin(), J.end(), hi.begin() + rk);
-  for (int i = 0; i < ns; ++i) {
-    hi[2 * rk + i] = (int32_t)(lin[i] / cols);
-    hi[2 * rk + ns + i] = (int32_t)(lin[i] % cols);
+  if ((int)pls_[k].size() != rk) {
+    std::vector<int32_t> I, J;
+    pivot_positions(k, &I, &J);
   }
-  const int32_t* dI = nullptr;
-  TTK_TRY(arena_push(hi.data(), nint, &dI));
+  h.k = k;
+  h.sweep = sweep;
+  h.rk = rk;
+  h.var = 0;
+  h.nvar = (speculate && rl0 < max_rank()) ? 2 : 1;
+  h.cols = nk1 * rr;
+  arena_reset(k & 1);
+  {
+    const size_t lk = (size_t)k - 1, nl = (k == 1) ? 0 : L_[k - 1].size();
+    const size_t nr = (k + 1 == N) ? 0 : R_[k + 1].size();
+    std::vector<int16_t> tmp(nl + lk + 1 + nr + 1, 0);
+    for (size_t i = 0; i < nl; ++i) tmp[i] = (int16_t)L_[k - 1][i];
+    for (size_t i = 0; i < nr; ++i) tmp[nl + lk + 1 + i] = (int16_t)R_[k + 1][i];
+    const int16_t* dl = nullptr;
+    TTK_TRY(arena_push(tmp.data(), nl + lk + 1, &dl));
+    TTK_TRY(arena_push(tmp.data() + nl + lk + 1, nr + 1, &cur_right_));
+    h.left = const_cast<int16_t*>(dl);
+  }
+  StepDesc hd[2];
+  if ((int64_t)(rl0 + h.nvar - 1) * nk > (int64_t)MAXR * MAXN || h.cols > MAXR * MAXN)
+    return fail(TTK_ERR_ARG, "cross: super-core %d unfolding exceeds %d rows or columns", k, MAXR * MAXN);
+  for (int v = 0; v < h.nvar; ++v) {
+    const int rl = rl0 + v, rows = rl * nk;
+    SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)sweep, (uint64_t)k);
+    const int ns = std::max(rows, h.cols);
+    h.lin[v] = g.floyd_unsorted((int64_t)rows * h.cols, ns);
+    h.bit[v] = g.bit();
+    h.rows[v] = rows;
+    h.ns[v] = ns;
+    std::vector<int32_t> hi((size_t)2 * rk + 2 * (size_t)ns);
+    for (int q = 0; q < rk; ++q) {
+      hi[q] = pls_[k][q] + pli_[k][q] * rl;
+      hi[rk + q] = prf_[k][q] + prt_[k][q] * nk1;
+    }
+    for (int i = 0; i < ns; ++i) {
+      hi[2 * rk + i] = (int32_t)(h.lin[v][i] / h.cols);
+      hi[2 * rk + ns + i] = (int32_t)(h.lin[v][i] % h.cols);
+    }
+    const int32_t* dI = nullptr;
+    TTK_TRY(arena_push(hi.data(), hi.size(), &dI));
+    StepDesc& sd = hd[v];
+    sd.a.left = h.left;
+    sd.a.right = cur_right_;
+    sd.a.rl = rl;
+    sd.a.lk = k - 1;
+    sd.a.rr = rr;
+    sd.a.lr = N - k - 1;
+    sd.a.nmid = 2;
+    sd.a.nm0 = nk;
+    sd.a.nm1 = nk1;
+    sd.I = dI;
+    sd.J = dI + rk;
+    sd.srow = dI + 2 * rk;
+    sd.scol = dI + 2 * rk + ns;
+    sd.rows = rows;
+    sd.cols = h.cols;
+    sd.ns = ns;
+    sd.bit = h.bit[v];
+  }
+  if (h.nvar == 1) hd[1] = hd[0];   // a selector of 1 cannot occur, but stays in bounds
+  TTK_TRY(arena_push(hd, 2, &h.desc));
   TTK_TRY(arena_flush());
-  const int32_t* dJ = dI + rk;
-  const int32_t* dsr = dJ + rk;
-  const int32_t* dsc = dsr + ns;
-  // value buffers
-  const size_t nsearch = std::max((size_t)rk + (size_t)rk * cols + cols, (size_t)rows * rk + rk + rows);
-  const size_t nvals = nsearch;
-  TTK_TRY(ensure(d_vals_, nvals * sizeof(double)));
-  TTK_TRY(ensure(d_R_, (size_t)std::max(ns, std::max(rows, cols)) * sizeof(double)));
-  double* S0 = d_vals_.as<double>();            // the searched fibre's entries
+  h.sel = d_sel_.as<int32_t>() + (speculate ? (k & 1) : 2);
+  return TTK_OK;
+}
+
+// The step's sample and search stages (four launches), sized for the larger
+// variant; blocks past the selected variant's extent do no work.
+tt_status Cross::enqueue_front(const HostStep& h) {
+  const int k = h.k, rk = h.rk;
+  int nsm = 0, nqm = 0;
+  for (int v = 0; v < h.nvar; ++v) {
+    nsm = std::max(nsm, h.ns[v]);
+    nqm = std::max(nqm, h.bit[v] ? h.cols : h.rows[v]);
+  }
   StepRes* dres = d_res_.as<StepRes>();
-  const int32_t* d_l = &dres->l;
-  const int32_t* d_t = &dres->t;
-  const Addr a = super_addr(k);
-  // P_k^{-1} = W Li, kept across steps and bordered when a pivot is added
   const double* Li = d_li_[k].as<double>();
   const double* W = d_w_[k].as<double>();
   double* R = d_R_.as<double>();
-  // the sample stage evaluates its entries itself; their maximum folds into
-  // the s slots (cleared by the previous step)
-  evals_ += 2 * (int64_t)ns * rk + ns;
+  double* x = d_x_.as<double>();
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_sample_resid<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-                       dim3(nblk(ns, SPB)), dim3(SW * 64), sample_lds(rk), st_, ks_, a, dsr, dsc, dI, dJ, ns, rk, Li,
-                       W, R, dres->s_slot);
-  });
-  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_sample_select<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-                       dim3(1), dim3(1024), 0, st_, ks_, a, (const double*)R, ns, dsr, dsc, cols,
-                       (const double*)luamax(k), dres, bit, dI, dJ, rk, Li, W, d_x_.as<double>());
-  });
-  if (bit == 1) {   // search the row of the sample's pivot
-    double* AlJ = S0;
-    double* AIall = AlJ + rk;                   // (q, c) at c + q cols
-    double* Alall = AIall + (size_t)rk * cols;
-    (void)AlJ;   // A(l, J) is evaluated by k_sample_select
-    {
-      const EvalSeg sg[2] = {{dI, nullptr, rk, cols, 1, AIall}, {d_l, nullptr, 1, cols, 0, Alall}};
-      eval_segs(ks_, a, sg, 2, st_, dres->q_slot);
-    }
-    evals_ += (int64_t)rk + (int64_t)rk * cols + cols;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(cols, QR)), dim3(QB), 0, st_, (const double*)d_x_.as<double>(),
-                       (const double*)AIall, (const double*)Alall, cols, rk, R, cols, dres);
-  } else {          // search the column
-    double* AallJ = S0;
-    double* AIt = AallJ + (size_t)rows * rk;
-    double* Aallt = AIt + rk;
-    (void)AIt;   // A(I, t) is evaluated by k_sample_select
-    {
-      const EvalSeg sg[2] = {{nullptr, dJ, rows, rk, 0, AallJ}, {nullptr, d_t, rows, 1, 0, Aallt}};
-      eval_segs(ks_, a, sg, 2, st_, dres->q_slot);
-    }
-    evals_ += (int64_t)rows * rk + rk + rows;
-    hipLaunchKernelGGL(k_search_resid, dim3(nblk(rows, QR)), dim3(QB), 0, st_, (const double*)d_x_.as<double>(),
-                       (const double*)AallJ, (const double*)Aallt, rows, rk, R, cols, dres);
-  }
-  // decide, and border the factors of P_k with the pivot's column, row and
-  // corner when the step added it
-  const int maxr = std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR);
-  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
-                       dim3(256), 0, st_, ks_, a, dres, bit, dI, dJ, rk, maxr, d_li_[k].as<double>(),
-                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres, mail_.dseq, mail_seq_ + 1);
+    constexpr int D_ = decltype(dd)::value, T_ = decltype(tt)::value;
+    constexpr bool G_ = decltype(gg)::value;
+    hipLaunchKernelGGL((k_sample_resid<D_, T_, G_>), dim3(nblk(nsm, SPB)), dim3(SW * 64), sample_lds(rk, 2 * D_ + T_), st_, ks_,
+                       h.desc, h.sel, rk, Li, W, R, dres->s_slot);
+    hipLaunchKernelGGL((k_sample_select<D_, T_, G_>), dim3(1), dim3(1024), 0, st_, ks_, h.desc, h.sel,
+                       (const double*)R, (const double*)luamax(k), dres, rk, Li, W, x);
+    hipLaunchKernelGGL((k_search<D_, T_, G_>), dim3(nblk(nqm, QE)), dim3(256), 0, st_, ks_, h.desc, h.sel,
+                       (const StepRes*)dres, (const double*)x, rk, R, dres->q_slot);
   });
   TTK_HIP(hipGetLastError());
-  TTK_TRY(wait_mail(++mail_seq_));
+  return TTK_OK;
+}
+
+// The step's decision, the border of P_k's factors, the next step's
+// variant selector and spare left row, and the mailbox.
+tt_status Cross::enqueue_finish(HostStep& h, const HostStep* next) {
+  const int k = h.k;
+  h.seq = ++mail_seq_;
+  int32_t* sel_next = next ? const_cast<int32_t*>(next->sel) : nullptr;
+  int16_t* next_left = (next && next->nvar == 2) ? next->left : nullptr;
+  StepRes* dres = d_res_.as<StepRes>();
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
+                       dim3(256), 0, st_, ks_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres, h.rk,
+                       max_rank(), d_li_[k].as<double>(),
+                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres, mail_.dseq, h.seq, sel_next,
+                       next_left, h.rk);
+  });
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+// Waits for the step's result and applies it to the host index sets.
+tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
+  const int N = N_, k = h.k, v = h.var, rk = h.rk;
+  const int rl = rank(k - 1), nk = g_.n[k - 1], nk1 = g_.n[k];
+  if (v >= h.nvar || rl * nk != h.rows[v] || rank(k) != rk)
+    return fail(TTK_ERR_HIP, "cross: step %d ran on a variant its predecessor did not select", k);
+  TTK_TRY(wait_mail(h.seq));
   StepRes r;
   std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
   if (r.info != 0)
     return fail(TTK_ERR_SINGULAR_CROSS, "cross: intersection matrix of super-core %d singular (sweep %d)", k,
-                sweep);
-  rec->sweep = sweep;
+                h.sweep);
+  const int rows = h.rows[v], cols = h.cols, ns = h.ns[v], bit = h.bit[v];
+  evals_ += 2 * (int64_t)ns * rk + ns;
+  evals_ += bit ? (int64_t)rk + (int64_t)rk * cols + cols : (int64_t)rows * rk + rk + rows;
+  rec->sweep = h.sweep;
   rec->k = k;
   rec->rank_before = rk;
-  rec->sample_pos = lin[r.s_pos];
+  rec->sample_pos = h.lin[v][r.s_pos];
   rec->bit = bit;
   rec->pivot_row = r.pivot_row;
   rec->pivot_col = r.pivot_col;
@@ -1462,14 +1648,14 @@ tt_status Cross::run(CrossOut* out) {
     TTK_HIP(hipMemcpyAsync(&test_max_, d_err_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
     TTK_TRY(sync());
   }
-  // the sample stage stages up to 2 x 64 x MAXR / 4 doubles of LDS per block
-  if (sample_lds(MAXR) > 48 * 1024) {
+  // the sample stage stages up to 2 x 64 x MAXR / 4 + MAXR x MAXD doubles of LDS per block
+  if (sample_lds(MAXR, MAXD) > 48 * 1024) {
     hipError_t e = hipSuccess;
     with_dims(ks_, [&](auto dd, auto tt, auto gg) {
       e = hipFuncSetAttribute(
           reinterpret_cast<const void*>(
               &k_sample_resid<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR));
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR, MAXD));
     });
     TTK_HIP(e);
   }
@@ -1478,6 +1664,11 @@ tt_status Cross::run(CrossOut* out) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
   TTK_TRY(mail_.alloc());
   TTK_TRY(d_x_.alloc(MAXR * sizeof(double)));   // the search stage's P^{-1} u
+  // the residuals of either stage: at most max(rows, cols) <= MAXR x MAXN
+  // entries, allocated once so that no queued step ever sees it move
+  TTK_TRY(d_R_.alloc((size_t)MAXR * MAXN * sizeof(double)));
+  TTK_TRY(d_sel_.alloc(4 * sizeof(int32_t)));
+  fill_zero(d_sel_.p, 4 * sizeof(int32_t), st_);
   // step state: the block counter and the sample-stage scale start at zero
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   fill_zero(d_res_.p, sizeof(StepRes), st_);
@@ -1486,12 +1677,24 @@ tt_status Cross::run(CrossOut* out) {
   int sweep = 0;
   const int max_sweeps = P_.max_sweeps > 0 ? P_.max_sweeps : 200;
   while (err > P_.tol && sweep < max_sweeps) {
+    // step k + 1 is uploaded and queued behind step k's finishing kernel
+    // before the host waits for step k's result
     int added = 0;
+    HostStep* cur = &hs_[0];
+    HostStep* nxt = &hs_[1];
+    TTK_TRY(prepare_step(*cur, 1, sweep, false));
+    TTK_TRY(enqueue_front(*cur));
     for (int k = 1; k < N; ++k) {
+      const bool more = k + 1 < N;
+      if (more) TTK_TRY(prepare_step(*nxt, k + 1, sweep, true));
+      TTK_TRY(enqueue_finish(*cur, more ? nxt : nullptr));
+      if (more) TTK_TRY(enqueue_front(*nxt));
       tt_kernel_decision rec{};
-      TTK_TRY(update_step(k, sweep, &rec));
+      TTK_TRY(collect(*cur, &rec));
       out->log.push_back(rec);
       added += rec.added;
+      if (more) nxt->var = rec.added;
+      std::swap(cur, nxt);
     }
     ++sweep;
     TTK_TRY(sampled_error(&err));
@@ -1529,7 +1732,11 @@ tt_status Cross::run(CrossOut* out) {
 tt_status run_cross(const tt_kernel_params* p, const Grid& g, const KSpec& ks, hipStream_t st, CrossOut* out) {
   if (g.D < 2) return fail(TTK_ERR_ARG, "cross needs at least two dimensions");
   Cross c(p, g, ks, st);
-  return c.run(out);
+  const tt_status s = c.run(out);
+  // a failed run may leave update steps queued on the stream; they finish
+  // before the buffers they use are released
+  if (s != TTK_OK && s != TTK_WARN_NOT_CONVERGED) (void)hipStreamSynchronize(st);
+  return s;
 }
 
 }  // namespace ttk

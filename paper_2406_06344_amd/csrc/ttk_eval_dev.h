@@ -41,6 +41,33 @@ __device__ inline void addr_coords(const Addr& a, const double* sn, int row, int
   }
 }
 
+// The two halves of addr_coords: positions 0..lk come from the row (left set,
+// then i_k), positions lk+1..D-1 from the column (i_{k+1} of a super-core,
+// then the right set).  Each fills only its own positions of c.
+template <int D>
+__device__ inline void addr_row_part(const Addr& a, const double* sn, int row, double (&c)[D]) {
+  const int s = row % a.rl;
+  const int i0 = row / a.rl;
+  const int16_t* L = a.left + (int64_t)s * a.lk;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (j < a.lk) c[j] = sn[j * MAXN + L[j]];
+    else if (j == a.lk) c[j] = sn[j * MAXN + i0];
+  }
+}
+template <int D>
+__device__ inline void addr_col_part(const Addr& a, const double* sn, int col, double (&c)[D]) {
+  int i1 = 0, t = col;
+  if (a.nmid == 2) { i1 = col % a.nm1; t = col / a.nm1; }
+  const int roff = t * a.lr - a.lk - a.nmid;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (j <= a.lk) continue;
+    if (a.nmid == 2 && j == a.lk + 1) c[j] = sn[j * MAXN + i1];
+    else c[j] = sn[j * MAXN + a.right[roff + j]];
+  }
+}
+
 // Entry (row, col) of the super-core / fibre addressed by a.
 template <int d, int dt, bool G>
 __device__ inline double addr_eval(const KSpec& ks, const Addr& a, const double* sn, int row, int col) {

@@ -87,7 +87,7 @@ def test_benchmark_workload_full_size_matches_oracle():
     #    own tie band, and the replay reaches the same index sets, ranks,
     #    sweep count and stopping error
     forced = [{"sample_pos": r["sample_pos"], "pivot_row": r["pivot_row"], "pivot_col": r["pivot_col"],
-               "added": r["added"]} for r in log]
+               "added": r["added"], "sample_max": r["sample_max"], "pivot_abs": r["pivot_abs"]} for r in log]
     cross_cores, rep = ocross.greedy_cross(ocross.Entries(P.entries, P.n), w.tol, seed=0, forced=forced)
     bad = [i for i, r in enumerate(rep["log"])
            if not (r["replay_sample_ok"] and r["replay_search_ok"] and r["replay_add_ok"])]

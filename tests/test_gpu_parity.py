@@ -243,7 +243,7 @@ def _replay_and_compare(P, tol, gpu_L, gpu_R, gpu_log, seed):
     tie band, and where the oracle's own margin is clear the choices agree."""
     ent = ocross.Entries(P.entries, P.n)
     forced = [{"sample_pos": r["sample_pos"], "pivot_row": r["pivot_row"], "pivot_col": r["pivot_col"],
-               "added": r["added"]} for r in gpu_log]
+               "added": r["added"], "sample_max": r["sample_max"], "pivot_abs": r["pivot_abs"]} for r in gpu_log]
     cores, info = ocross.greedy_cross(ent, tol, seed=seed, forced=forced)
     bad = [r for r in info["log"] if not (r["replay_sample_ok"] and r["replay_search_ok"] and r["replay_add_ok"])]
     assert not bad, bad[:3]

@@ -163,3 +163,20 @@ def test_prop1_tt_error_amplification_bound():
         Kt = np.einsum("abc,pa,b,qc->pq", Mh, q[0], q[1], q[2])
         worst = max(worst, np.abs(Kf - Kt).max())
     assert worst <= lam ** 3 * np.abs(M - Mh).max() * (1 + 1e-12)
+
+
+def test_replay_band_widening_is_capped():
+    """The replay band widens by the disagreement the forced computation shows
+    on the same residuals, but a disagreement above 10 tau fails the check."""
+    P = kernels.Problem("matern32", 1, [[0, 1]], [[2, 3]], [[0.5, 2.0]], 8)
+    ent = cross.Entries(P.entries, P.n)
+    L, R, _ = cross.greedy_init(ent, 4)
+    cp = lambda S: [None if x is None else x.copy() for x in S]
+    good = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256)
+    tau = good["tau"]
+    near = dict(good, sample_max=good["sample_max"] + 5 * tau, pivot_abs=good["pivot_abs"] + 5 * tau)
+    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=near)
+    assert rec["replay_sample_ok"] and rec["replay_search_ok"] and rec["replay_add_ok"]
+    far = dict(good, sample_max=good["sample_max"] + 11 * tau)
+    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=far)
+    assert not rec["replay_sample_ok"] and not rec["replay_search_ok"]
