@@ -40,6 +40,7 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "ttk_eval_dev.h"
@@ -334,20 +335,28 @@ __device__ void row_dots(const double* M, const double* v, int r, double* out, d
 // max) and the relative top-2 margin; stage 0 = sample stage (also records
 // row/col of the chosen sample), stage 1 = search stage.  The sample list is
 // in generation order, so its key is the linear position row * cols + col;
-// the searched fibre is in natural order.  Wave shuffles, then one LDS stage.
-// Returns the chosen position in every thread.
-template <int BS>
+// the searched fibre is in natural order.  |R| is read once, C values per
+// thread held in registers (n <= BS C), then wave shuffles and one LDS stage
+// per pass.  Returns the chosen position in every thread, its key and its
+// |R|.
+template <int BS, int C>
 __device__ int select_block(const double* R, int n, const int32_t* srow, const int32_t* scol, int cols, int stage,
-                            double scale, StepRes* res) {
+                            double scale, StepRes* res, int* key_out, double* val_out) {
   constexpr int NWV = BS / 64;
   __shared__ double sv[NWV];
   __shared__ int sk[NWV], si[NWV];
-  __shared__ double s_mx;
-  __shared__ int s_p;
+  __shared__ double s_mx, s_pa;
+  __shared__ int s_p, s_key;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const double tau = TIE_REL * scale;
+  double av[C];
   double m = -1.0;
-  for (int i = tid; i < n; i += BS) m = fmax(m, fabs(R[i]));
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i = tid + c * BS;
+    av[c] = i < n ? fabs(R[i]) : -1.0;
+    m = fmax(m, av[c]);
+  }
   m = wave64_max(m);
   if (lane == 0) sv[w] = m;
   __syncthreads();
@@ -359,11 +368,14 @@ __device__ int select_block(const double* R, int n, const int32_t* srow, const i
   __syncthreads();
   const double mx = s_mx;
   int best = 0x7fffffff, bi = 0x7fffffff;
-  for (int i = tid; i < n; i += BS)
-    if (fabs(R[i]) >= mx - tau) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i = tid + c * BS;
+    if (i < n && av[c] >= mx - tau) {
       const int key = stage == 0 ? srow[i] * cols + scol[i] : i;
       if (key < best) { best = key; bi = i; }
     }
+  }
   {   // keys are distinct, so the lowest key names one entry
     const int kmin = wave64_min_i(best);
     bi = wave64_min_i(best == kmin ? bi : 0x7fffffff);
@@ -375,13 +387,19 @@ __device__ int select_block(const double* R, int n, const int32_t* srow, const i
     int b = sk[0], ii = si[0];
     for (int k = 1; k < NWV; ++k)
       if (sk[k] < b) { b = sk[k]; ii = si[k]; }
-    s_p = ii < n ? ii : 0;   // (no candidate compares, e.g. all residuals NaN: the first)
+    const bool found = ii < n;   // (no candidate compares, e.g. all residuals NaN: the first)
+    s_p = found ? ii : 0;
+    s_key = found ? b : (stage == 0 ? srow[0] * cols + scol[0] : 0);
   }
   __syncthreads();
   const int p = s_p;
   double sec = 0.0;
-  for (int i = tid; i < n; i += BS)
-    if (i != p) sec = fmax(sec, fabs(R[i]));
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int i = tid + c * BS;
+    if (i < n && i != p) sec = fmax(sec, av[c]);
+    if (i == p) s_pa = av[c];
+  }
   sec = wave64_max(sec);
   if (lane == 0) sv[w] = sec;
   __syncthreads();
@@ -391,16 +409,63 @@ __device__ int select_block(const double* R, int n, const int32_t* srow, const i
     const double margin = mx > 0.0 ? (mx - sec) / mx : 0.0;
     if (stage == 0) {
       res->s_pos = p; res->s_max = mx; res->s_margin = margin; res->s_tau = tau;
-      res->l = srow[p]; res->t = scol[p];
+      res->l = s_key / cols; res->t = s_key % cols;
       res->s_scale = scale;
       res->q_scale = scale;             // the search stage widens this scale
     } else {
       res->q_pos = p; res->q_max = mx; res->q_margin = margin; res->q_tau = tau;
       res->q_scale = scale;
-      res->pivot_abs = fabs(R[p]);
+      res->pivot_abs = s_pa;
     }
   }
+  *key_out = s_key;
+  *val_out = s_pa;
   return p;
+}
+
+// Fused pair of row_dots: out1 = M1 v1 and out2 = M2 v2 in one pass, batches
+// of RB loads of each matrix (scratch: 2 BS doubles).
+template <int BS, int RB>
+__device__ void row_dots2(const double* M1, const double* v1, double* out1, const double* M2, const double* v2,
+                          double* out2, int r, double* scratch) {
+  const int ru = (r + 63) & ~63;
+  const int S = min(8, BS / ru);
+  const int tid = threadIdx.x, t = tid % ru, h = tid / ru;
+  double acc1 = 0.0, acc2 = 0.0;
+  if (h < S && t < r) {
+    const int chunk = (r + S - 1) / S;
+    const int q0 = h * chunk, q1 = min(r, q0 + chunk);
+    double a1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double a2[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = q0; q < q1; q += RB) {
+      double m1[RB], m2[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        m1[u] = q + u < q1 ? M1[t + (int64_t)(q + u) * MAXR] : 0.0;
+        m2[u] = q + u < q1 ? M2[t + (int64_t)(q + u) * MAXR] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        a1[u & 7] += q + u < q1 ? m1[u] * v1[q + u] : 0.0;
+        a2[u & 7] += q + u < q1 ? m2[u] * v2[q + u] : 0.0;
+      }
+    }
+    acc1 = ((a1[0] + a1[1]) + (a1[2] + a1[3])) + ((a1[4] + a1[5]) + (a1[6] + a1[7]));
+    acc2 = ((a2[0] + a2[1]) + (a2[2] + a2[3])) + ((a2[4] + a2[5]) + (a2[6] + a2[7]));
+  }
+  scratch[tid] = acc1;
+  scratch[BS + tid] = acc2;
+  __syncthreads();
+  if (tid < r) {
+    double s1 = scratch[tid], s2 = scratch[BS + tid];
+    for (int k = 1; k < S; ++k) {
+      s1 += scratch[tid + k * ru];
+      s2 += scratch[BS + tid + k * ru];
+    }
+    out1[tid] = s1;
+    out2[tid] = s2;
+  }
+  __syncthreads();
 }
 
 // max of the AMAX_SLOTS slots of a fold
@@ -575,7 +640,9 @@ inline size_t sample_lds(int r, int D) {
 // u = A(I, t) for a column search (bit 0) is evaluated here and
 // x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search
 // (P^{-1} applied to one vector, through the rows of the factors or of their
-// transposes).  |u| folds into the search-stage scale.
+// transposes).  |u| folds into the search-stage scale.  The loads that do
+// not depend on the selection (node table, the node indices of J_q or I_q)
+// are issued before it.
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc* desc, const int32_t* sel,
                                                         const double* R, const double* luamax, StepRes* res, int r,
@@ -585,23 +652,44 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
   const Addr a = sdv.a;
   const int32_t* srow = sdv.srow;
   const int32_t* scol = sdv.scol;
-  const int32_t* I = sdv.I;
-  const int32_t* J = sdv.J;
   const int ns = sdv.ns, cols = sdv.cols, bit = sdv.bit;
   __shared__ double sn[D * MAXN], su[MAXR], sy[MAXR], scr[1024], red[16];
-  const int p = select_block<1024>(R, ns, srow, scol, cols, 0, fmax(slots_max(res->s_slot), *luamax), res);
-  const int l = srow[p], t = scol[p];
-  stage_nodes<D>(ks.nodes, sn);
+  const int tid = threadIdx.x;
+  const double ndv = tid < D * MAXN ? ks.nodes[tid] : 0.0;
+  int nq[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) nq[j] = 0;
+  if (tid < r) {
+    if (bit) addr_col_nodes<D>(a, sdv.J[tid], nq);
+    else addr_row_nodes<D>(a, sdv.I[tid], nq);
+  }
+  int key;
+  double val;
+  select_block<1024, (MAXR * MAXN + 1023) / 1024>(R, ns, srow, scol, cols, 0,
+                                                  fmax(slots_max(res->s_slot), *luamax), res, &key, &val);
+  const int l = key / cols, t = key - l * cols;
+  if (tid < D * MAXN) sn[tid] = ndv;
+  int nf[D];   // the sample's own half: the row of l (bit 1) or the column of t (bit 0)
+#pragma unroll
+  for (int j = 0; j < D; ++j) nf[j] = 0;
+  if (tid < r) {
+    if (bit) addr_row_nodes<D>(a, l, nf);
+    else addr_col_nodes<D>(a, t, nf);
+  }
+  __syncthreads();
   double m = 0.0;
-  for (int q = threadIdx.x; q < r; q += 1024) {
-    const double v = bit ? addr_eval<d, dt, G>(ks, a, sn, l, J[q]) : addr_eval<d, dt, G>(ks, a, sn, I[q], t);
-    su[q] = v;
-    m = fmax(m, fabs(v));
+  if (tid < r) {
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = sn[j * MAXN + (((j <= a.lk) == (bit != 0)) ? nf[j] : nq[j])];
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    su[tid] = v;
+    m = fabs(v);
   }
   m = wave64_max(m);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  if ((tid & 63) == 0) red[tid >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     for (int w = 1; w < 16; ++w) m = fmax(m, red[w]);
     m = fmax(m, red[0]);
     res->q_slot[0] = fmax(res->q_slot[0], m);
@@ -613,7 +701,7 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
     row_dots<1024>(Li, su, r, sy, scr);        // Li u
     row_dots<1024>(W, sy, r, su, scr);         // W (Li u)
   }
-  for (int q = threadIdx.x; q < r; q += 1024) x[q] = su[q];
+  for (int q = tid; q < r; q += 1024) x[q] = su[q];
 }
 
 // Search stage: the residual over the searched fibre,
@@ -683,16 +771,19 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
 // b = A(I, t), c = A(l, J) and d = A(l, t) are evaluated here, then
 // u = Li b, g = W^T c, s = d - g^T u,
 //   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
-// (leading dimension MAXR, transposes alongside).  Every thread of the block
-// calls it.
+// (leading dimension MAXR, transposes alongside).  I and J are in LDS,
+// amax0 is the value of *amax read at the start of the kernel.  Every thread
+// of the block calls it.
+constexpr int FB = 1024;   // threads of the finishing kernel
 template <int d, int dt, bool G>
 __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn, StepRes* res, const int32_t* I,
                                const int32_t* J, int r, int row, int col, double* Li, double* W, double* amax,
-                               int32_t* info) {
-  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[256];
+                               double amax0, int32_t* info) {
+  constexpr int NW = FB / 64;
+  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[2 * FB];
   __shared__ double s_d, s_s;
   const int tid = threadIdx.x;
-  for (int e = tid; e <= 2 * r; e += 256) {
+  for (int e = tid; e <= 2 * r; e += FB) {
     if (e < r) bv[e] = addr_eval<d, dt, G>(ks, a, sn, I[e], col);
     else if (e < 2 * r) cv[e - r] = addr_eval<d, dt, G>(ks, a, sn, row, J[e - r]);
     else s_d = addr_eval<d, dt, G>(ks, a, sn, row, col);
@@ -700,12 +791,10 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
   __syncthreads();
   double* Lit = Li + FT;
   double* Wt = W + FT;
-  row_dots<256>(Li, bv, r, u, scr);    // Li b
-  row_dots<256>(Wt, cv, r, gv, scr);   // W^T c
-  __syncthreads();
+  row_dots2<FB, 16>(Li, bv, u, Wt, cv, gv, r, scr);   // Li b, W^T c
   {
     double gu = 0.0, m = 0.0;
-    for (int p = tid; p < r; p += 256) {
+    for (int p = tid; p < r; p += FB) {
       gu += gv[p] * u[p];
       m = fmax(m, fmax(fabs(bv[p]), fabs(cv[p])));
     }
@@ -714,10 +803,14 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
     if ((tid & 63) == 0) { nl[tid >> 6] = gu; nw[tid >> 6] = m; }
     __syncthreads();
     if (tid == 0) {
-      gu = (nl[0] + nl[1]) + (nl[2] + nl[3]);
-      m = fmax(fmax(nw[0], nw[1]), fmax(nw[2], nw[3]));
+      gu = 0.0;
+      m = 0.0;
+      for (int w = 0; w < NW; ++w) {
+        gu += nl[w];
+        m = fmax(m, nw[w]);
+      }
       s_s = s_d - gu;
-      *amax = fmax(fmax(*amax, m), fabs(s_d));
+      *amax = fmax(fmax(amax0, m), fabs(s_d));
       if (!(s_s != 0.0) || !isfinite(s_s)) {
         *info = 1;
         res->info = 1;
@@ -726,10 +819,8 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
     __syncthreads();
   }
   const double is = 1.0 / s_s;
-  row_dots<256>(Lit, gv, r, nl, scr);   // Li^T g, i.e. g^T Li (from the old factors)
-  row_dots<256>(W, u, r, nw, scr);      // W u
-  __syncthreads();
-  for (int e = tid; e <= 2 * r + 1; e += 256) {
+  row_dots2<FB, 16>(Lit, gv, nl, W, u, nw, r, scr);   // Li^T g (i.e. g^T Li, old factors), W u
+  for (int e = tid; e <= 2 * r + 1; e += FB) {
     if (e < r) {
       Li[r + (int64_t)e * MAXR] = -nl[e];    // row r, column e
       Lit[e + (int64_t)r * MAXR] = -nl[e];
@@ -757,8 +848,9 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
 // is below the cap.  Then, if added, the border of P_k (border_factors).
 // Clears the fold slots for the next step and publishes the result to the
 // host mailbox.
+static_assert(MAXR <= FB, "k_finish_step holds one pivot per thread");
 template <int d, int dt, bool G>
-__global__ void __launch_bounds__(256) k_finish_step(KSpec ks, const StepDesc* desc, const int32_t* sel,
+__global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* desc, const int32_t* sel,
                                                      const double* R, StepRes* res, int r, int max_rank,
                                                      double* Li, double* W,
                                                      double* amax, int32_t* info, StepRes* mail, uint32_t* mail_seq,
@@ -768,30 +860,46 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, const StepDesc* d
   const StepDesc& sd = desc[*sel];
   const Addr a = sd.a;
   const int bit = sd.bit;
-  const int32_t* I = sd.I;
-  const int32_t* J = sd.J;
   __shared__ double sn[D * MAXN];
-  __shared__ int s_added, s_row, s_col;
+  __shared__ int32_t sI[MAXR], sJ[MAXR];
+  __shared__ int s_added;
   const int tid = threadIdx.x;
-  // the search stage's selection over R (written by k_search)
-  const int qp = select_block<256>(R, bit ? sd.cols : sd.rows, nullptr, nullptr, sd.cols, 1,
-                                   fmax(res->q_scale, slots_max(res->q_slot)), res);
-  if (tid == 0) {
-    s_row = bit ? res->l : qp;
-    s_col = bit ? qp : res->t;
+  // loads that do not depend on the selection, issued before it
+  const double ndv = tid < D * MAXN ? ks.nodes[tid] : 0.0;
+  int32_t iq = -1, jq = -1;
+  if (tid < r) {
+    iq = sd.I[tid];
+    jq = sd.J[tid];
   }
-  stage_nodes<D>(ks.nodes, sn);
-  const int row = s_row, col = s_col;
-  int stale = 0;
-  for (int q = tid; q < r; q += 256)
-    if (I[q] == row || J[q] == col) stale = 1;
-  stale = __syncthreads_or(stale);
+  const int l0 = res->l, t0 = res->t;
+  const double amax0 = *amax;
+  const int32_t info0 = *info;
+  const double scale = fmax(res->q_scale, slots_max(res->q_slot));
+  // the search stage's selection over R (written by k_search)
+  int key;
+  double pabs;
+  const int qp = select_block<FB, (MAXR * MAXN + FB - 1) / FB>(R, bit ? sd.cols : sd.rows, nullptr, nullptr,
+                                                               sd.cols, 1, scale, res, &key, &pabs);
+  const int row = bit ? l0 : qp, col = bit ? qp : t0;
+  // the pivot's left row, for the next step's left set: loaded now, stored
+  // at the end if the pivot is added
+  int16_t lv = 0;
+  if (next_left && tid <= a.lk) {
+    const int s = row % a.rl;
+    lv = tid < a.lk ? a.left[(size_t)s * a.lk + tid] : (int16_t)(row / a.rl);
+  }
+  if (tid < D * MAXN) sn[tid] = ndv;
+  if (tid < r) {
+    sI[tid] = iq;
+    sJ[tid] = jq;
+  }
+  const int stale = __syncthreads_or(tid < r && (iq == row || jq == col));
   if (tid == 0) {
-    const int added = (res->pivot_abs > res->q_tau && !stale && r < max_rank) ? 1 : 0;
+    const int added = (pabs > TIE_REL * scale && !stale && r < max_rank) ? 1 : 0;
     res->pivot_row = row;
     res->pivot_col = col;
     res->added = added;
-    res->info = *info;   // status of the kept factors (non-zero after a singular border)
+    res->info = info0;   // status of the kept factors (non-zero after a singular border)
     s_added = added;
   }
   if (tid < AMAX_SLOTS) {   // the next step folds its maxima into cleared slots
@@ -799,16 +907,12 @@ __global__ void __launch_bounds__(256) k_finish_step(KSpec ks, const StepDesc* d
     res->q_slot[tid] = 0.0;
   }
   __syncthreads();
-  if (s_added) border_factors<d, dt, G>(ks, a, sn, res, I, J, r, row, col, Li, W, amax, info);
+  if (s_added) border_factors<d, dt, G>(ks, a, sn, res, sI, sJ, r, row, col, Li, W, amax, amax0, info);
   // the next step of the sweep runs on variant s_added; if the pivot was
   // added, I^{<=k} gains the row (left row s of the pivot, node i_k), which
   // the next step's left set receives after its r_k current rows
   if (tid == 0 && sel_next) *sel_next = s_added;
-  if (s_added && next_left) {
-    const int s = row % a.rl, ik = row / a.rl;
-    for (int j = tid; j <= a.lk; j += 256)
-      next_left[(size_t)next_row * (a.lk + 1) + j] = j < a.lk ? a.left[(size_t)s * a.lk + j] : (int16_t)ik;
-  }
+  if (s_added && next_left && tid <= a.lk) next_left[(size_t)next_row * (a.lk + 1) + tid] = lv;
   // publish the step's result to the host mailbox: the fields up to the
   // fold slots, then (after a system-scope fence) the sequence number the
   // host waits for
@@ -942,8 +1046,11 @@ inline uint64_t mkey(const int32_t* e, int len) {
 // Host mailbox of the update steps: mapped, coherent pinned memory that the
 // finishing kernel writes (the step's result, then its sequence number) and
 // the host polls, so a step costs no copy and no stream synchronisation.
+// Mapped, coherent pinned host memory the finishing kernels publish to: one
+// result slot and one sequence word per super-core k, so a whole sweep can
+// be queued and its results read in order.
 struct HostMail {
-  StepRes* res = nullptr;        // host address
+  StepRes* res = nullptr;        // host addresses, MAXD slots each
   uint32_t* seq = nullptr;
   StepRes* dres = nullptr;       // device addresses of the same memory
   uint32_t* dseq = nullptr;
@@ -954,7 +1061,7 @@ struct HostMail {
   ~HostMail() { if (p) (void)hipHostFree(p); }
   tt_status alloc() {
     if (p) return TTK_OK;
-    const size_t bytes = sizeof(StepRes) + 64;
+    const size_t bytes = MAXD * sizeof(StepRes) + MAXD * sizeof(uint32_t) + 64;
     if (hipHostMalloc(&p, bytes, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
       p = nullptr;
       (void)hipGetLastError();
@@ -964,9 +1071,9 @@ struct HostMail {
     void* dp = nullptr;
     TTK_HIP(hipHostGetDevicePointer(&dp, p, 0));
     res = static_cast<StepRes*>(p);
-    seq = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + sizeof(StepRes));
+    seq = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + MAXD * sizeof(StepRes));
     dres = static_cast<StepRes*>(dp);
-    dseq = reinterpret_cast<uint32_t*>(static_cast<char*>(dp) + sizeof(StepRes));
+    dseq = reinterpret_cast<uint32_t*>(static_cast<char*>(dp) + MAXD * sizeof(StepRes));
     return TTK_OK;
   }
 };
@@ -988,10 +1095,12 @@ class Cross {
 
   tt_status upload_sets(int k_left, int k_right, int16_t* dl, int16_t* dr);
   tt_status init_sets();
-  // One update step of a sweep (Alg 5) as the host prepares it.  While the
-  // previous step of the sweep is still on the device, both of its possible
-  // outcomes are prepared (variant v = 1: it adds a pivot) and the kernels
-  // read the variant that the previous finishing kernel selects.
+  // One update step of a sweep (Alg 5) as the host prepares it.  Step k of a
+  // sweep depends on the earlier steps only through whether step k - 1 added
+  // a pivot, so every step is prepared at the start of the sweep in both of
+  // its variants (v = 1: step k - 1 added) and the kernels read the variant
+  // that step k - 1's finishing kernel selects; the whole sweep is queued in
+  // one go and the host reads the results afterwards.
   struct HostStep {
     int k = 0, sweep = 0, rk = 0, nvar = 1, var = 0, cols = 0;
     int rows[2] = {0, 0}, ns[2] = {0, 0}, bit[2] = {0, 0};
@@ -1001,20 +1110,23 @@ class Cross {
     int16_t* left = nullptr;            // device I^{<=k-1}, spare row after rank(k-1) rows
     uint32_t seq = 0;                   // mailbox sequence number of its finishing kernel
   };
-  HostStep hs_[2];
-  DBuf d_sel_;   // int32: variant selectors of odd and even steps, then a constant 0
+  HostStep hs_[MAXD];
+  DBuf d_sel_;   // int32 [MAXD + 1]: variant selector of step k at k (k >= 2); 0 stays 0
   int max_rank() const { return std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR); }
   tt_status prepare_step(HostStep& h, int k, int sweep, bool speculate);
   tt_status enqueue_front(const HostStep& h);
   tt_status enqueue_finish(HostStep& h, const HostStep* next);
   tt_status collect(const HostStep& h, tt_kernel_decision* rec);
+  tt_status stage_steps(int sweep, int k0, int k1);
+  tt_status run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added);
+  int first_half() const { return N_ / 2; }   // steps 1..first_half() are staged first
   tt_status build_cores(std::vector<double*>* C);
   tt_status refine_cores();
   tt_status init_inverses();
   void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
   std::vector<int32_t> pls_[MAXD], pli_[MAXD], prf_[MAXD], prt_[MAXD];   // pivot (s, i_k), (i_{k+1}, t)
   tt_status solve_right(int k, int m, const double* F, double* C);
-  tt_status sampled_error(double* err);
+  tt_status sampled_error(double* err, const std::function<tt_status()>& overlap = nullptr);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
   // Working buffers that follow the growing ranks: grown by at least half
@@ -1044,43 +1156,43 @@ class Cross {
   HBuf h_stage_, h_res_;
   HostMail mail_;
   uint32_t mail_seq_ = 0;
-  tt_status wait_mail(uint32_t seq);
-  // upload arena: host pinned + device mirror, bump-allocated, flushed with
-  // one copy before the kernels that read it.  Update steps alternate
-  // between its two halves (step k uses half k & 1), so a step can be
-  // uploaded while the previous one runs; the whole arena is reset only
-  // after a stream synchronisation.
-  HBuf ar_h_;
-  DBuf ar_d_;
-  size_t ar_off_ = 0, ar_flushed_ = 0, ar_cap_ = 0, ar_end_ = 0;
+  tt_status wait_mail(int slot, uint32_t seq);
+  // upload arenas: host pinned + device mirror, bump-allocated between
+  // stream synchronisations, flushed with one copy before the kernels that
+  // read them.  Arena 0 holds the update steps of a sweep, arena 1 everything
+  // else, so the next sweep can be staged while the stopping test still
+  // reads its own uploads.
+  HBuf ar_h_[2];
+  DBuf ar_d_[2];
+  size_t ar_off_[2] = {0, 0}, ar_flushed_[2] = {0, 0}, ar_cap_ = 0;
+  int ar_ = 1;   // the arena in use
   const int16_t* cur_left_ = nullptr;
   const int16_t* cur_right_ = nullptr;
   tt_status arena_init(size_t bytes) {
-    ar_cap_ = ar_end_ = bytes;
-    TTK_TRY(ar_h_.alloc(bytes));
-    TTK_TRY(ar_d_.alloc(bytes));
+    ar_cap_ = bytes;
+    for (int i = 0; i < 2; ++i) {
+      TTK_TRY(ar_h_[i].alloc(bytes));
+      TTK_TRY(ar_d_[i].alloc(bytes));
+    }
     return TTK_OK;
   }
-  void arena_reset(int half = -1) {
-    const size_t mid = (ar_cap_ / 2) & ~(size_t)255;
-    ar_off_ = ar_flushed_ = half == 1 ? mid : 0;
-    ar_end_ = half == 0 ? mid : ar_cap_;
-  }
+  void arena_reset() { ar_off_[ar_] = ar_flushed_[ar_] = 0; }   // once its readers have drained
   template <class T>
   tt_status arena_push(const T* src, size_t n, const T** dev) {
-    const size_t at = (ar_off_ + 255) & ~(size_t)255;
+    const size_t at = (ar_off_[ar_] + 255) & ~(size_t)255;
     const size_t bytes = n * sizeof(T);
-    if (at + bytes > ar_end_) return fail(TTK_ERR_OOM, "cross upload arena too small (%zu bytes)", ar_cap_);
-    if (bytes) std::memcpy(ar_h_.as<char>() + at, src, bytes);
-    *dev = reinterpret_cast<const T*>(ar_d_.as<char>() + at);
-    ar_off_ = at + bytes;
+    if (at + bytes > ar_cap_) return fail(TTK_ERR_OOM, "cross upload arena too small (%zu bytes)", ar_cap_);
+    if (bytes) std::memcpy(ar_h_[ar_].as<char>() + at, src, bytes);
+    *dev = reinterpret_cast<const T*>(ar_d_[ar_].as<char>() + at);
+    ar_off_[ar_] = at + bytes;
     return TTK_OK;
   }
   tt_status arena_flush() {
-    if (ar_off_ > ar_flushed_)
-      TTK_HIP(hipMemcpyAsync(ar_d_.as<char>() + ar_flushed_, ar_h_.as<char>() + ar_flushed_, ar_off_ - ar_flushed_,
+    const size_t off = ar_off_[ar_], done = ar_flushed_[ar_];
+    if (off > done)
+      TTK_HIP(hipMemcpyAsync(ar_d_[ar_].as<char>() + done, ar_h_[ar_].as<char>() + done, off - done,
                              hipMemcpyHostToDevice, st_));
-    ar_flushed_ = ar_off_;
+    ar_flushed_[ar_] = off;
     return TTK_OK;
   }
   int n_test_ = 0;
@@ -1314,17 +1426,18 @@ tt_status Cross::solve_right(int k, int m, const double* F, double* C) {
   return TTK_OK;
 }
 
-// Polls the mailbox until the finishing kernel has published sequence
-// number seq.  Every 1024 polls the stream is queried: an error is returned
-// as such, and a stream that has drained without publishing is an error too
-// (so a failed launch cannot leave the host polling forever).
-tt_status Cross::wait_mail(uint32_t seq) {
+// Polls mailbox slot `slot` until its finishing kernel has published
+// sequence number seq.  Every 1024 polls the stream is queried: an error is
+// returned as such, and a stream that has drained without publishing is an
+// error too (so a failed launch cannot leave the host polling forever).
+tt_status Cross::wait_mail(int slot, uint32_t seq) {
+  const uint32_t* w = mail_.seq + slot;
   for (uint64_t spin = 1;; ++spin) {
-    if (__atomic_load_n(mail_.seq, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
     if ((spin & 1023) == 0) {
       const hipError_t e = hipStreamQuery(st_);
       if (e == hipSuccess) {
-        if (__atomic_load_n(mail_.seq, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
+        if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == seq) return TTK_OK;
         return fail(TTK_ERR_HIP, "cross: the step kernel finished without publishing its result");
       }
       if (e != hipErrorNotReady) return fail(TTK_ERR_HIP, "cross: %s", hipGetErrorString(e));
@@ -1332,11 +1445,11 @@ tt_status Cross::wait_mail(uint32_t seq) {
   }
 }
 
-// Uploads step k of the sweep: the left set I^{<=k-1} (with a spare row for
-// the one the previous step may add, which its finishing kernel writes), the
-// right set I^{>k+1}, and per variant the pivot positions, the samples (drawn
-// from the step's own keyed stream, so both variants draw as the oracle does
-// for its r_{k-1}) and the descriptor.
+// Stages step k of the sweep in the upload arena: the left set I^{<=k-1}
+// (with a spare row for the one step k - 1 may add, which its finishing
+// kernel writes), the right set I^{>k+1}, and per variant the pivot
+// positions, the samples (drawn from the step's own keyed stream, so both
+// variants draw as the oracle does for its r_{k-1}) and the descriptor.
 tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
   const int N = N_;
   const int rl0 = rank(k - 1), rr = rank(k + 1), rk = rank(k);
@@ -1351,7 +1464,6 @@ tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
   h.var = 0;
   h.nvar = (speculate && rl0 < max_rank()) ? 2 : 1;
   h.cols = nk1 * rr;
-  arena_reset(k & 1);
   {
     const size_t lk = (size_t)k - 1, nl = (k == 1) ? 0 : L_[k - 1].size();
     const size_t nr = (k + 1 == N) ? 0 : R_[k + 1].size();
@@ -1406,8 +1518,7 @@ tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
   }
   if (h.nvar == 1) hd[1] = hd[0];   // a selector of 1 cannot occur, but stays in bounds
   TTK_TRY(arena_push(hd, 2, &h.desc));
-  TTK_TRY(arena_flush());
-  h.sel = d_sel_.as<int32_t>() + (speculate ? (k & 1) : 2);
+  h.sel = d_sel_.as<int32_t>() + (speculate ? k : 0);
   return TTK_OK;
 }
 
@@ -1449,9 +1560,9 @@ tt_status Cross::enqueue_finish(HostStep& h, const HostStep* next) {
   StepRes* dres = d_res_.as<StepRes>();
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
     hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
-                       dim3(256), 0, st_, ks_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres, h.rk,
+                       dim3(FB), 0, st_, ks_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres, h.rk,
                        max_rank(), d_li_[k].as<double>(),
-                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres, mail_.dseq, h.seq, sel_next,
+                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres + k, mail_.dseq + k, h.seq, sel_next,
                        next_left, h.rk);
   });
   TTK_HIP(hipGetLastError());
@@ -1464,9 +1575,9 @@ tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
   const int rl = rank(k - 1), nk = g_.n[k - 1], nk1 = g_.n[k];
   if (v >= h.nvar || rl * nk != h.rows[v] || rank(k) != rk)
     return fail(TTK_ERR_HIP, "cross: step %d ran on a variant its predecessor did not select", k);
-  TTK_TRY(wait_mail(h.seq));
+  TTK_TRY(wait_mail(k, h.seq));
   StepRes r;
-  std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
+  std::memcpy(&r, mail_.res + k, offsetof(StepRes, s_slot));
   if (r.info != 0)
     return fail(TTK_ERR_SINGULAR_CROSS, "cross: intersection matrix of super-core %d singular (sweep %d)", k,
                 h.sweep);
@@ -1504,6 +1615,46 @@ tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
     if (k + 1 < N)
       R_[k].insert(R_[k].end(), R_[k + 1].begin() + (size_t)tt * (N - k - 1),
                    R_[k + 1].begin() + (size_t)(tt + 1) * (N - k - 1));
+  }
+  return TTK_OK;
+}
+
+// Stages steps k0..k1-1 of a sweep in arena 0 (reset at k0 = 1) and
+// uploads them in one copy.
+tt_status Cross::stage_steps(int sweep, int k0, int k1) {
+  struct Use {   // arena 0 while staging, arena 1 again on every return
+    int& a;
+    explicit Use(int& x) : a(x) { a = 0; }
+    ~Use() { a = 1; }
+  } use(ar_);
+  if (k0 == 1) arena_reset();   // the previous sweep has been collected
+  for (int k = k0; k < k1; ++k) TTK_TRY(prepare_step(hs_[k], k, sweep, k > 1));
+  return arena_flush();
+}
+
+// One sweep (Alg 6, k = 1..N-1).  The first steps are staged already (during
+// the previous stopping test) when `staged`; the rest are staged while the
+// first ones run.  All steps are queued without waiting, then the results
+// are read in order and applied to the host sets.
+tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added) {
+  const int N = N_, h = first_half();
+  if (!staged) TTK_TRY(stage_steps(sweep, 1, h + 1));
+  for (int k = 1; k <= h; ++k) {
+    TTK_TRY(enqueue_front(hs_[k]));
+    if (k < h) TTK_TRY(enqueue_finish(hs_[k], &hs_[k + 1]));
+  }
+  TTK_TRY(stage_steps(sweep, h + 1, N));
+  for (int k = h; k < N; ++k) {
+    if (k > h) TTK_TRY(enqueue_front(hs_[k]));
+    TTK_TRY(enqueue_finish(hs_[k], k + 1 < N ? &hs_[k + 1] : nullptr));
+  }
+  *added = 0;
+  for (int k = 1; k < N; ++k) {
+    tt_kernel_decision rec{};
+    TTK_TRY(collect(hs_[k], &rec));
+    log->push_back(rec);
+    *added += rec.added;
+    if (k + 1 < N) hs_[k + 1].var = rec.added;
   }
   return TTK_OK;
 }
@@ -1597,7 +1748,9 @@ tt_status Cross::refine_cores() {
   return TTK_OK;
 }
 
-tt_status Cross::sampled_error(double* err) {
+// The stopping test; `overlap`, if given, runs on the host while the test's
+// kernels run.
+tt_status Cross::sampled_error(double* err, const std::function<tt_status()>& overlap) {
   std::vector<double*> C;
   TTK_TRY(build_cores(&C));
   TTView tv{};
@@ -1607,6 +1760,7 @@ tt_status Cross::sampled_error(double* err) {
   hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(), n_test_,
                      (const double*)d_test_val_.as<double>(), d_err_.as<double>());
   TTK_HIP(hipGetLastError());
+  if (overlap) TTK_TRY(overlap());
   // the error and the status of every P_k's factors in one copy each
   double slots[TEST_SLOTS];
   std::vector<int32_t> info(MAXD, 0);
@@ -1667,37 +1821,26 @@ tt_status Cross::run(CrossOut* out) {
   // the residuals of either stage: at most max(rows, cols) <= MAXR x MAXN
   // entries, allocated once so that no queued step ever sees it move
   TTK_TRY(d_R_.alloc((size_t)MAXR * MAXN * sizeof(double)));
-  TTK_TRY(d_sel_.alloc(4 * sizeof(int32_t)));
-  fill_zero(d_sel_.p, 4 * sizeof(int32_t), st_);
-  // step state: the block counter and the sample-stage scale start at zero
+  TTK_TRY(d_sel_.alloc((MAXD + 1) * sizeof(int32_t)));
+  fill_zero(d_sel_.p, (MAXD + 1) * sizeof(int32_t), st_);
+  // step state: the fold slots and the sample-stage scale start at zero
   TTK_TRY(d_res_.alloc(sizeof(StepRes)));
   fill_zero(d_res_.p, sizeof(StepRes), st_);
   double err = 0.0;
   TTK_TRY(sampled_error(&err));
   int sweep = 0;
   const int max_sweeps = P_.max_sweeps > 0 ? P_.max_sweeps : 200;
+  bool staged = false;
   while (err > P_.tol && sweep < max_sweeps) {
-    // step k + 1 is uploaded and queued behind step k's finishing kernel
-    // before the host waits for step k's result
     int added = 0;
-    HostStep* cur = &hs_[0];
-    HostStep* nxt = &hs_[1];
-    TTK_TRY(prepare_step(*cur, 1, sweep, false));
-    TTK_TRY(enqueue_front(*cur));
-    for (int k = 1; k < N; ++k) {
-      const bool more = k + 1 < N;
-      if (more) TTK_TRY(prepare_step(*nxt, k + 1, sweep, true));
-      TTK_TRY(enqueue_finish(*cur, more ? nxt : nullptr));
-      if (more) TTK_TRY(enqueue_front(*nxt));
-      tt_kernel_decision rec{};
-      TTK_TRY(collect(*cur, &rec));
-      out->log.push_back(rec);
-      added += rec.added;
-      if (more) nxt->var = rec.added;
-      std::swap(cur, nxt);
-    }
+    TTK_TRY(run_sweep(sweep, staged, &out->log, &added));
     ++sweep;
-    TTK_TRY(sampled_error(&err));
+    // the next sweep's first steps are staged while the stopping test runs
+    // (discarded if the test stops the cross)
+    staged = added > 0 && sweep < max_sweeps;
+    TTK_TRY(sampled_error(&err, [&]() -> tt_status {
+      return staged ? stage_steps(sweep, 1, first_half() + 1) : TTK_OK;
+    }));
     if (added == 0) break;
   }
   // the cores of the last stopping test, refined, are the result (C_k in

@@ -68,6 +68,33 @@ __device__ inline void addr_col_part(const Addr& a, const double* sn, int col, d
   }
 }
 
+// Node indices of the same halves (positions 0..lk from the row, lk+1..D-1
+// from the column): the global loads of addr_row_part / addr_col_part
+// without the node table, so they can be issued before the table is staged.
+template <int D>
+__device__ inline void addr_row_nodes(const Addr& a, int row, int (&nd)[D]) {
+  const int s = row % a.rl;
+  const int i0 = row / a.rl;
+  const int16_t* L = a.left + (int64_t)s * a.lk;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (j < a.lk) nd[j] = L[j];
+    else if (j == a.lk) nd[j] = i0;
+  }
+}
+template <int D>
+__device__ inline void addr_col_nodes(const Addr& a, int col, int (&nd)[D]) {
+  int i1 = 0, t = col;
+  if (a.nmid == 2) { i1 = col % a.nm1; t = col / a.nm1; }
+  const int roff = t * a.lr - a.lk - a.nmid;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (j <= a.lk) continue;
+    if (a.nmid == 2 && j == a.lk + 1) nd[j] = i1;
+    else nd[j] = a.right[roff + j];
+  }
+}
+
 // Entry (row, col) of the super-core / fibre addressed by a.
 template <int d, int dt, bool G>
 __device__ inline double addr_eval(const KSpec& ks, const Addr& a, const double* sn, int row, int col) {
