@@ -1026,10 +1026,19 @@ __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double
 }
 
 // The same iteration with A in LDS: each round first rotates the column
-// pairs of A in LDS (one wave per pair) and records the rotations, then all
-// threads apply them to V in global memory in one parallel pass, so a round
-// costs one global round trip instead of one per pair.  The rotations, their
-// order and their arithmetic are those of k_jacobi.
+// pairs of A in LDS and records the rotations, then all threads apply them to
+// V in global memory in one parallel pass, so a round costs one global round
+// trip instead of one per pair.  The rotations and their order are those of
+// k_jacobi.  A pair is handled by G lanes (8 or 16), each holding E entries
+// of both columns in registers (n <= G E): all of a lane's loads are issued
+// at once (indices past n are clamped to n - 1, which rewrites that entry
+// with the same value), so a round waits for LDS once before and once after
+// the G-lane reductions.
+template <int G>
+__device__ inline double group_sum(double v) {
+  return G == 8 ? row8_sum(v) : row16_sum(v);
+}
+template <int G, int E>
 __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, double* V, int ldv, double* sigma,
                                                    int want_v) {
   extern __shared__ double smj[];
@@ -1054,37 +1063,56 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
-    // a column pair per group of 16 lanes (64 groups): a whole round of
-    // disjoint pairs runs at once, with 16-lane reductions
-    const int grp = tid >> 4, gl = tid & 15;
+    // a column pair per group of G lanes: a whole round of disjoint pairs
+    // runs at once, with G-lane reductions
+    const int grp = tid / G, gl = tid % G;
     for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int pr = grp; pr < np / 2; pr += BS / 16) {
-        int p = (pr == 0) ? 0 : 1 + (pr - 1 + rnd) % (np - 1);
-        int q = 1 + (np - 2 - pr + rnd) % (np - 1);
+      for (int pr = grp; pr < np / 2; pr += BS / G) {
+        // the round-robin positions (both operands of the reduction are
+        // below 2 (np - 1), so one conditional subtraction is the modulo)
+        int p = 0;
+        if (pr != 0) {
+          const int x = pr - 1 + rnd;
+          p = 1 + (x >= np - 1 ? x - (np - 1) : x);
+        }
+        const int y = np - 2 - pr + rnd;
+        int q = 1 + (y >= np - 1 ? y - (np - 1) : y);
         if (p > q) { const int t = p; p = q; q = t; }
         int keep = 0;
         double c = 1.0, sn = 0.0;
         if (q < n && p != q) {
           double* ap = A + (size_t)p * n;
           double* aq = A + (size_t)q * n;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = gl; i < n; i += 16) {
-            al += ap[i] * ap[i];
-            be += aq[i] * aq[i];
-            ga += ap[i] * aq[i];
+          double xv[E], yv[E];
+#pragma unroll
+          for (int u = 0; u < E; ++u) {
+            const int i = min(gl + G * u, n - 1);
+            xv[u] = ap[i];
+            yv[u] = aq[i];
           }
-          al = row16_sum(al);
-          be = row16_sum(be);
-          ga = row16_sum(ga);
-          if (!(fabs(ga) <= 1e-15 * sqrt(al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int u = 0; u < E; ++u) {
+            const bool in = gl + G * u < n;
+            al += in ? xv[u] * xv[u] : 0.0;
+            be += in ? yv[u] * yv[u] : 0.0;
+            ga += in ? xv[u] * yv[u] : 0.0;
+          }
+          al = group_sum<G>(al);
+          be = group_sum<G>(be);
+          ga = group_sum<G>(ga);
+          // converged pair: |ga| <= 1e-15 sqrt(al be), compared squared (al,
+          // be are squared column norms, far from the overflow range)
+          if (!(ga * ga <= 1e-30 * (al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
             const double zeta = (be - al) / (2.0 * ga);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
+            c = rsqrt(1.0 + t * t);
             sn = c * t;
-            for (int i = gl; i < n; i += 16) {
-              const double x = ap[i], y = aq[i];
-              ap[i] = c * x - sn * y;
-              aq[i] = sn * x + c * y;
+#pragma unroll
+            for (int u = 0; u < E; ++u) {
+              const int i = min(gl + G * u, n - 1);
+              ap[i] = c * xv[u] - sn * yv[u];
+              aq[i] = sn * xv[u] + c * yv[u];
             }
             keep = 1;
             if (gl == 0) rotated = 1;
@@ -1290,6 +1318,24 @@ size_t qr_blocked_work(int m, int n) {
 namespace {
 
 // Launch the LDS form of the Jacobi SVD if the matrix fits; false if it does not.
+template <int G, int E>
+bool jacobi_lds_launch_e(double* A, int n, int lda, double* V, int ldv, double* sigma, size_t sh, int lds_limit,
+                         hipStream_t st) {
+  static size_t attr = 48 * 1024;   // dynamic LDS the instantiation is allowed so far
+  if (sh > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds<G, E>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    attr = sh;
+  }
+  hipLaunchKernelGGL((k_jacobi_lds<G, E>), dim3(1), dim3(BS), sh, st, A, n, lda, V, ldv, sigma, V ? 1 : 0);
+  if (hipGetLastError() == hipSuccess) return true;
+  (void)hipGetLastError();
+  return false;
+}
+
 bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {
   static int lds_limit = -1;
   if (lds_limit < 0) {
@@ -1303,17 +1349,12 @@ bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* si
   }
   const int np = (n + 1) & ~1;
   const size_t sh = (size_t)n * n * sizeof(double) + (size_t)(np / 2) * (2 * sizeof(double) + 2 * sizeof(int));
-  if (n >= 2 && sh + 64 <= (size_t)lds_limit) {
-    bool ok = true;
-    if (sh > 48 * 1024)
-      ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)sh) == hipSuccess;
-    if (ok) {
-      hipLaunchKernelGGL(k_jacobi_lds, dim3(1), dim3(BS), sh, st, A, n, lda, V, ldv, sigma, V ? 1 : 0);
-      if (hipGetLastError() == hipSuccess) return true;
-    }
-    (void)hipGetLastError();
-  }
+  if (n < 2 || sh + 64 > (size_t)lds_limit) return false;
+  // 16 lanes per pair (64 pairs per round at once), up to 9 entries per lane
+  if (n <= 32) return jacobi_lds_launch_e<16, 2>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+  if (n <= 64) return jacobi_lds_launch_e<16, 4>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+  if (n <= 96) return jacobi_lds_launch_e<16, 6>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+  if (n <= 144) return jacobi_lds_launch_e<16, 9>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
   return false;
 }
 

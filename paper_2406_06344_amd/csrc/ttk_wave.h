@@ -22,6 +22,15 @@ __device__ inline int row_ror_i(int x) {
   return __builtin_amdgcn_update_dpp(0, x, 0x120 + N, 0xF, 0xF, false);
 }
 
+// any DPP lane permutation of a double (CTRL: the DPP control word)
+template <int CTRL>
+__device__ inline double dpp_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double readlane_d(double x, int lane) {
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
@@ -35,6 +44,15 @@ __device__ inline double row16_sum(double v) {
   v += row_ror<4>(v);
   v += row_ror<2>(v);
   v += row_ror<1>(v);
+  return v;
+}
+// sum over each group of 8 lanes (half a row), the same value in every lane
+// of the group: neighbour swap and pair swap within quads (quad_perm
+// [1,0,3,2] and [2,3,0,1]), then the other quad by row_half_mirror
+__device__ inline double row8_sum(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
   return v;
 }
 __device__ inline double row16_max(double v) {
