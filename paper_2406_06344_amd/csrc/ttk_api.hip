@@ -174,7 +174,7 @@ struct tt_kernel {
   int64_t ns = 0, nt = 0;
   int rs = 0, rt = 0, ldu = 0, ldv = 0;
   DBuf U, V, nodes, dct, stage[6], pcore[2], gtmp;
-  DBuf work, Mbuf, dMbuf, Wbuf, Zbuf, Abuf;
+  DBuf work, Mbuf, dMbuf, Wbuf, Zbuf, Abuf, Pbuf;   // Pbuf: partial sums of the reduces
   // Global-1 (Algorithm 4): Q (N x kg row-major, dtype), R (kg x kg FP64)
   int kg = 0;
   DBuf Q, Rg, Gwork, M64, Wg;
@@ -425,6 +425,15 @@ static tt_status prepare_M(tt_kernel_t h, const void* theta, int B, bool with_dM
   return tt_kernel_online_core(h, theta, B, h->Mbuf.p, with_dM ? h->dMbuf.p : nullptr, st);
 }
 
+// W (r x B) = F^T X with the handle's partial-sum workspace
+static tt_status reduce_into(tt_kernel_t h, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
+                             int B, void* W, hipStream_t st) {
+  const size_t wb = apply_reduce_work(N, r, B);
+  if (wb) TTK_TRY(h->Pbuf.alloc(wb));
+  apply_reduce(h->dtype, F, ldf, N, r, X, ldx, B, W, wb ? h->Pbuf.p : nullptr, st);
+  return TTK_OK;
+}
+
 tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y, int64_t ldy,
                           void* W_save, void* stream) {
   if (!h) return fail(TTK_ERR_ARG, "NULL handle");
@@ -439,7 +448,7 @@ tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X
     W = h->Wbuf.p;
   }
   TTK_TRY(h->Zbuf.alloc((size_t)h->rs * B * h->es));
-  apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, W, st);
+  TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, W, st));
   batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 0, W, B, h->Zbuf.p, st);
   apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, h->Zbuf.p, B, Y, ldy, st);
   TTK_HIP(hipGetLastError());
@@ -463,7 +472,7 @@ tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B, const v
     char* wb = h->Wbuf.as<char>() + (size_t)b * h->rt * es;
     char* zb = h->Zbuf.as<char>() + (size_t)b * h->rs * es;
     const char* Mb = h->Mbuf.as<char>() + (size_t)b * h->rs * h->rt * es;
-    apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, xb, ldx, 1, wb, st);
+    TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, xb, ldx, 1, wb, st));
     batched_matvec(h->dtype, Mb, h->rs, h->rt, 0, wb, 1, zb, st);
     apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, zb, 1, yb, ldy, st);
   }
@@ -484,7 +493,7 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   TTK_TRY(prepare_M(h, theta, B, want_dth, st));
   TTK_TRY(h->Abuf.alloc((size_t)h->rs * B * h->es));
-  apply_reduce(h->dtype, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, st);   // A = U^T G
+  TTK_TRY(reduce_into(h, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, st));   // A = U^T G
   if (dX) {
     TTK_TRY(h->Zbuf.alloc((size_t)std::max(h->rs, h->rt) * B * h->es));
     batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 1, h->Abuf.p, B, h->Zbuf.p, st);   // M^T a
@@ -494,7 +503,7 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
     const void* W = W_saved;
     if (!W) {
       TTK_TRY(h->Wbuf.alloc((size_t)h->rt * B * h->es));
-      apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, h->Wbuf.p, st);
+      TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, h->Wbuf.p, st));
       W = h->Wbuf.p;
     }
     batched_bilinear(h->dtype, h->Abuf.p, h->dMbuf.p, W, h->rs, h->rt, B, h->g.dt, dtheta, st);
@@ -542,7 +551,7 @@ tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W
   }
   TTK_TRY(h->Wbuf.alloc((size_t)k * B * h->es));
   TTK_TRY(h->Zbuf.alloc((size_t)k * B * h->es));
-  apply_reduce(h->dtype, h->Q.p, k, h->ns, k, X, ldx, B, h->Wbuf.p, st);          // Q^T x
+  TTK_TRY(reduce_into(h, h->Q.p, k, h->ns, k, X, ldx, B, h->Wbuf.p, st));        // Q^T x
   batched_matvec(h->dtype, W, k, k, 0, h->Wbuf.p, B, h->Zbuf.p, st);             // W (Q^T x)
   apply_expand(h->dtype, h->Q.p, k, h->ns, k, h->Zbuf.p, B, Y, ldy, st);          // Q (...)
   TTK_HIP(hipGetLastError());

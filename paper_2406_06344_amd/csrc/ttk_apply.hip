@@ -6,9 +6,13 @@
 // Plain (B = 1): a GEMV pair, bound by reading F once.  Batched: register-
 // tiled GEMMs that read F once for all B columns.  Products are formed in
 // the working precision and summed in double over point tiles (a float32
-// running sum over 10^5 points loses digits); partial sums of the reduce over
-// point chunks are combined with atomics (order not fixed).
+// running sum over 10^5 points loses digits).  The plain and skinny reduces
+// write one double partial sum per workgroup and a second launch adds them
+// in a fixed order (thousands of same-address atomics serialise); the wide
+// tiled reduce, with few workgroups per entry, combines its chunks by atomics
+// (order not fixed).
 #include "ttk_internal.h"
+#include "ttk_wave.h"
 
 namespace ttk {
 
@@ -26,8 +30,9 @@ constexpr int MAXF = 2 * MAXR;
 
 // w[c] += sum_p F[p, c] x[p]; one row per wave at a time, lanes over columns.
 template <class T>
-__global__ void __launch_bounds__(256) k_reduce_plain(const T* F, int ldf, int64_t N, int r, const T* x, T* w) {
-  __shared__ T red[4][MAXF];
+__global__ void __launch_bounds__(256) k_reduce_plain(const T* F, int ldf, int64_t N, int r, const T* x,
+                                                      double* part) {
+  __shared__ double red[4][MAXF];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // products in T, sums in double: a long reduction over points must not
   // accumulate the rounding of a float32 running sum
@@ -46,10 +51,29 @@ __global__ void __launch_bounds__(256) k_reduce_plain(const T* F, int ldf, int64
 #pragma unroll
   for (int q = 0; q < MAXF / 64; ++q) {
     const int c = lane + 64 * q;
-    if (c < r) red[wv][c] = (T)acc[q];
+    if (c < r) red[wv][c] = acc[q];
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < r; c += 256) atomicAdd(&w[c], red[0][c] + red[1][c] + red[2][c] + red[3][c]);
+  for (int c = threadIdx.x; c < r; c += 256)
+    part[(size_t)c * gridDim.x + blockIdx.x] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// out[e] = sum over workgroups w of part[e nw + w] (each entry's partials
+// contiguous), e < count, in a fixed order: one wave per entry, eight
+// interleaved sums per lane, then the wave's DPP sum.
+template <class T>
+__global__ void __launch_bounds__(256) k_sum_partials(const double* part, int nw, int count, T* out) {
+  const int e = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (e >= count) return;   // (whole waves)
+  const double* pe = part + (size_t)e * nw;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int w = lane;
+  for (; w + 7 * 64 < nw; w += 8 * 64)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += pe[w + 64 * u];
+  for (; w < nw; w += 64) a[0] += pe[w];
+  const double s = wave64_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+  if (lane == 0) out[e] = (T)s;
 }
 
 // y[p] = sum_c F[p, c] z[c]; 16 lanes per row, reduced by shuffles.
@@ -192,6 +216,107 @@ __global__ void __launch_bounds__(256) k_expand_tiled(const T* F, int ldf, int64
   }
 }
 
+// Skinny batches (2 <= B <= SB, r <= SR): the point dimension is long and the
+// rest is small, so both contractions are bound by reading F once.
+constexpr int SB = 16, SR = 128, ST = 64;   // batch, rank and point-tile limits
+
+// W (r x B) += F^T X over one chunk of points.  Thread (g, c), c = t % 128,
+// g = t / 128, owns column c of F and the rows g, g + 2, ... of every 64-row
+// tile: it loads those 32 values at once (the next tile's while the current
+// one is used) and multiplies them with the tile of X staged in LDS, summing
+// the tile in T and the tiles in double; the two row groups meet in LDS and
+// the chunk's sums go to part[(c + b r) nw + blockIdx.x] (nw workgroups).
+template <class T>
+__global__ void __launch_bounds__(256) k_reduce_skinny(const T* F, int ldf, int64_t N, int r, const T* X,
+                                                       int64_t ldx, int B, int64_t chunk, double* part) {
+  __shared__ T Xs[ST][SB + 1];
+  __shared__ double red[SR][SB + 1];
+  const int tid = threadIdx.x, c = tid & (SR - 1), g = tid >> 7;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = pbeg + chunk < N ? pbeg + chunk : N;
+  const bool cok = c < r;
+  double acc[SB];
+#pragma unroll
+  for (int b = 0; b < SB; ++b) acc[b] = 0.0;
+  T f[ST / 2];
+  auto load_f = [&](int64_t p0) {
+#pragma unroll
+    for (int u = 0; u < ST / 2; ++u) {
+      const int64_t p = p0 + g + 2 * u;
+      f[u] = (cok && p < pend) ? F[p * ldf + c] : (T)0;
+    }
+  };
+  load_f(pbeg);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += ST) {
+    __syncthreads();   // the previous tile of X is consumed
+    for (int e = tid; e < ST * SB; e += 256) {
+      const int row = e % ST, b = e / ST;
+      const int64_t p = p0 + row;
+      Xs[row][b] = (p < pend && b < B) ? X[p + (int64_t)b * ldx] : (T)0;
+    }
+    __syncthreads();
+    T cur[ST / 2];
+#pragma unroll
+    for (int u = 0; u < ST / 2; ++u) cur[u] = f[u];
+    if (p0 + ST < pend) load_f(p0 + ST);
+    T t[SB];
+#pragma unroll
+    for (int b = 0; b < SB; ++b) t[b] = (T)0;
+#pragma unroll
+    for (int u = 0; u < ST / 2; ++u) {
+      const T* xr = Xs[g + 2 * u];
+#pragma unroll
+      for (int b = 0; b < SB; ++b) t[b] += cur[u] * xr[b];
+    }
+#pragma unroll
+    for (int b = 0; b < SB; ++b) acc[b] += (double)t[b];
+  }
+  if (g == 1)
+#pragma unroll
+    for (int b = 0; b < SB; ++b) red[c][b] = acc[b];
+  __syncthreads();
+  if (g == 0 && cok)
+    for (int b = 0; b < B; ++b) part[(size_t)(c + b * r) * gridDim.x + blockIdx.x] = acc[b] + red[c][b];
+}
+
+// Y (N x B) = F Z for 64 points per block: the F tile (64 x r) is staged in
+// LDS with row-contiguous loads, Z (r x B) beside it; thread (q, i) computes
+// outputs 4 q .. 4 q + 3 of point i, summed in double.
+template <class T>
+__global__ void __launch_bounds__(256) k_expand_skinny(const T* F, int ldf, int64_t N, int r, const T* Z, int B,
+                                                       T* Y, int64_t ldy) {
+  __shared__ T Fs[ST][SR + 1];
+  __shared__ T Zs[SR][SB];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * ST;
+  for (int e = tid; e < r * SB; e += 256) {
+    const int k = e / SB, b = e % SB;
+    Zs[k][b] = b < B ? Z[k + (int64_t)b * r] : (T)0;
+  }
+  for (int e = tid; e < ST * r; e += 256) {
+    const int i = e / r, k = e - i * r;
+    const int64_t p = p0 + i;
+    Fs[i][k] = p < N ? F[p * ldf + k] : (T)0;
+  }
+  __syncthreads();
+  const int i = tid & (ST - 1), q = tid >> 6;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  for (int k = 0; k < r; ++k) {
+    const T fv = Fs[i][k];
+    a0 += (double)(fv * Zs[k][4 * q]);
+    a1 += (double)(fv * Zs[k][4 * q + 1]);
+    a2 += (double)(fv * Zs[k][4 * q + 2]);
+    a3 += (double)(fv * Zs[k][4 * q + 3]);
+  }
+  const int64_t p = p0 + i;
+  if (p < N) {
+    const double av[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (4 * q + j < B) Y[p + (int64_t)(4 * q + j) * ldy] = (T)av[j];
+  }
+}
+
 // y_b = op(M_b) x_b, M_b rows x cols column-major at M + b rows cols.
 template <class T>
 __global__ void __launch_bounds__(256) k_bmatvec(const T* M, int rows, int cols, int trans, const T* x, int B,
@@ -255,21 +380,53 @@ void fill_zero(void* p, size_t bytes, hipStream_t st) {
                      static_cast<float*>(p), n);
 }
 
+namespace {
+constexpr int64_t SKINNY_CHUNK = 4 * ST;   // points per workgroup of the skinny reduce
+unsigned plain_groups(int64_t N) { return grid_cap((N + 63) / 64, 4096); }
+unsigned skinny_groups(int64_t N) { return (unsigned)((N + SKINNY_CHUNK - 1) / SKINNY_CHUNK); }
+bool skinny(int r, int B) { return B >= 2 && B <= SB && r <= SR; }
+}  // namespace
+
+size_t apply_reduce_work(int64_t N, int r, int B) {
+  if (N <= 0) return 0;
+  if (B == 1) return (size_t)plain_groups(N) * r * sizeof(double);
+  if (skinny(r, B)) return (size_t)skinny_groups(N) * r * B * sizeof(double);
+  return 0;
+}
+
 void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx, int B, void* W,
-                  hipStream_t st) {
+                  void* work, hipStream_t st) {
   const size_t es = dtype == TTK_FP32 ? 4 : 8;
-  fill_zero(W, (size_t)r * B * es, st);
-  if (N <= 0) return;
-  if (B == 1) {
-    const unsigned g = grid_cap((N + 63) / 64, 4096);
-    if (dtype == TTK_FP32)
-      hipLaunchKernelGGL(k_reduce_plain<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
-                         static_cast<const float*>(X), static_cast<float*>(W));
-    else
-      hipLaunchKernelGGL(k_reduce_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
-                         r, static_cast<const double*>(X), static_cast<double*>(W));
+  if (N <= 0) {
+    fill_zero(W, (size_t)r * B * es, st);
     return;
   }
+  double* part = static_cast<double*>(work);
+  if (B == 1 || skinny(r, B)) {
+    const unsigned g = B == 1 ? plain_groups(N) : skinny_groups(N);
+    const int count = r * B;
+    if (dtype == TTK_FP32) {
+      if (B == 1)
+        hipLaunchKernelGGL(k_reduce_plain<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
+                           static_cast<const float*>(X), part);
+      else
+        hipLaunchKernelGGL(k_reduce_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N,
+                           r, static_cast<const float*>(X), ldx, B, SKINNY_CHUNK, part);
+      hipLaunchKernelGGL(k_sum_partials<float>, dim3((count + 3) / 4), dim3(256), 0, st, (const double*)part,
+                         (int)g, count, static_cast<float*>(W));
+    } else {
+      if (B == 1)
+        hipLaunchKernelGGL(k_reduce_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
+                           r, static_cast<const double*>(X), part);
+      else
+        hipLaunchKernelGGL(k_reduce_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf,
+                           N, r, static_cast<const double*>(X), ldx, B, SKINNY_CHUNK, part);
+      hipLaunchKernelGGL(k_sum_partials<double>, dim3((count + 3) / 4), dim3(256), 0, st, (const double*)part,
+                         (int)g, count, static_cast<double*>(W));
+    }
+    return;
+  }
+  fill_zero(W, (size_t)r * B * es, st);
   const int rt = (r + 63) / 64, bt = (B + 63) / 64;
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>((N + 511) / 512, (4096 + rt * bt - 1) / (rt * bt)));
   int64_t chunk = (N + nch - 1) / nch;
@@ -295,6 +452,16 @@ void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const voi
     else
       hipLaunchKernelGGL(k_expand_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
                          r, static_cast<const double*>(Z), static_cast<double*>(Y));
+    return;
+  }
+  if (B <= SB && r <= SR) {
+    const unsigned g = (unsigned)((N + ST - 1) / ST);
+    if (dtype == TTK_FP32)
+      hipLaunchKernelGGL(k_expand_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
+                         static_cast<const float*>(Z), B, static_cast<float*>(Y), ldy);
+    else
+      hipLaunchKernelGGL(k_expand_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
+                         r, static_cast<const double*>(Z), B, static_cast<double*>(Y), ldy);
     return;
   }
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((B + 63) / 64));

@@ -220,8 +220,11 @@ void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int 
                        void* M, void* dM, double* work, hipStream_t st);
 size_t online_work_doubles(const ParamCore* pc, int dt, int B);
 
+// W (r x B) = F^T X.  work: apply_reduce_work(N, r, B) bytes of device memory
+// for the per-workgroup partial sums (may be NULL when that is 0).
 void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
-                  int B, void* W, hipStream_t st);   // W (r x B) = F^T X
+                  int B, void* W, void* work, hipStream_t st);
+size_t apply_reduce_work(int64_t N, int r, int B);
 void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B,
                   void* Y, int64_t ldy, hipStream_t st);  // Y (N x B) = F Z
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
