@@ -317,24 +317,50 @@ __global__ void __launch_bounds__(256) k_expand_skinny(const T* F, int ldf, int6
   }
 }
 
-// y_b = op(M_b) x_b, M_b rows x cols column-major at M + b rows cols.
+// y_b = op(M_b) x_b, M_b rows x cols column-major at M + b rows cols, one
+// workgroup per b.  M x: 64 outputs per pass, the columns split over the four
+// waves (coalesced loads down each column, four sums per lane), the waves'
+// sums added in LDS.  M^T x: a wave per output, lanes down its column of M,
+// a DPP wave sum.
 template <class T>
 __global__ void __launch_bounds__(256) k_bmatvec(const T* M, int rows, int cols, int trans, const T* x, int B,
                                                  T* y) {
-  __shared__ T xs[MAXF];
+  __shared__ double xs[MAXF];
+  __shared__ double red[4][64];
   const int nin = trans ? rows : cols, nout = trans ? cols : rows;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const T* Mb = M + (size_t)b * rows * cols;
     __syncthreads();
-    for (int i = threadIdx.x; i < nin; i += 256) xs[i] = x[(size_t)b * nin + i];
+    for (int i = tid; i < nin; i += 256) xs[i] = (double)x[(size_t)b * nin + i];
     __syncthreads();
-    for (int o = threadIdx.x; o < nout; o += 256) {
-      double s = 0.0;
-      if (!trans)
-        for (int c = 0; c < cols; ++c) s += (double)Mb[o + (size_t)c * rows] * (double)xs[c];
-      else
-        for (int i = 0; i < rows; ++i) s += (double)Mb[i + (size_t)o * rows] * (double)xs[i];
-      y[(size_t)b * nout + o] = (T)s;
+    if (!trans) {
+      for (int o0 = 0; o0 < rows; o0 += 64) {
+        const int o = o0 + lane;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        if (o < rows) {
+          int c = wv;
+          for (; c + 12 < cols; c += 16) {
+            s0 += (double)Mb[o + (size_t)c * rows] * xs[c];
+            s1 += (double)Mb[o + (size_t)(c + 4) * rows] * xs[c + 4];
+            s2 += (double)Mb[o + (size_t)(c + 8) * rows] * xs[c + 8];
+            s3 += (double)Mb[o + (size_t)(c + 12) * rows] * xs[c + 12];
+          }
+          for (; c < cols; c += 4) s0 += (double)Mb[o + (size_t)c * rows] * xs[c];
+        }
+        red[wv][lane] = (s0 + s1) + (s2 + s3);
+        __syncthreads();
+        if (wv == 0 && o < rows) y[(size_t)b * nout + o] = (T)((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]));
+        __syncthreads();
+      }
+    } else {
+      for (int o = wv; o < cols; o += 4) {
+        const T* mc = Mb + (size_t)o * rows;
+        double s = 0.0;
+        for (int i = lane; i < rows; i += 64) s += (double)mc[i] * xs[i];
+        s = wave64_sum(s);
+        if (lane == 0) y[(size_t)b * nout + o] = (T)s;
+      }
     }
   }
 }
