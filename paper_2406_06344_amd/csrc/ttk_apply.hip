@@ -225,7 +225,8 @@ constexpr int SB = 16, SR = 128, ST = 64;   // batch, rank and point-tile limits
 // tile: it loads those 32 values at once (the next tile's while the current
 // one is used) and multiplies them with the tile of X staged in LDS, summing
 // the tile in T and the tiles in double; the two row groups meet in LDS and
-// the chunk's sums go to part[(c + b r) nw + blockIdx.x] (nw workgroups).
+// the chunk's sums go to part[blockIdx.x r B + c + b r] (contiguous per
+// workgroup; k_sum_ranges and k_sum_final add them up).
 template <class T>
 __global__ void __launch_bounds__(256) k_reduce_skinny(const T* F, int ldf, int64_t N, int r, const T* X,
                                                        int64_t ldx, int B, int64_t chunk, double* part) {
@@ -276,7 +277,43 @@ __global__ void __launch_bounds__(256) k_reduce_skinny(const T* F, int ldf, int6
     for (int b = 0; b < SB; ++b) red[c][b] = acc[b];
   __syncthreads();
   if (g == 0 && cok)
-    for (int b = 0; b < B; ++b) part[(size_t)(c + b * r) * gridDim.x + blockIdx.x] = acc[b] + red[c][b];
+    for (int b = 0; b < B; ++b) part[(size_t)blockIdx.x * r * B + c + (size_t)b * r] = acc[b] + red[c][b];
+}
+
+// First level of the skinny reduce's sum: for 64 outputs per block (lanes,
+// reads contiguous across them) and one of NRANGE ranges of workgroups
+// (blockIdx.y), the four waves take every fourth workgroup of the range;
+// the range's sum goes to sums[range count + e].
+constexpr int NRANGE = 8;
+__global__ void __launch_bounds__(256) k_sum_ranges(const double* part, int nw, int count, double* sums) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int per = (nw + NRANGE - 1) / NRANGE;
+  const int w0 = blockIdx.y * per, w1 = min(nw, w0 + per);
+  double a0 = 0.0, a1 = 0.0;
+  if (e < count) {
+    int w = w0 + wv;
+    for (; w + 4 < w1; w += 8) {
+      a0 += part[(size_t)w * count + e];
+      a1 += part[(size_t)(w + 4) * count + e];
+    }
+    for (; w < w1; w += 4) a0 += part[(size_t)w * count + e];
+  }
+  red[wv][lane] = a0 + a1;
+  __syncthreads();
+  if (wv == 0 && e < count)
+    sums[(size_t)blockIdx.y * count + e] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+// out[e] = the NRANGE range sums of entry e, in order.
+template <class T>
+__global__ void k_sum_final(const double* sums, int count, T* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double s = 0.0;
+  for (int k = 0; k < NRANGE; ++k) s += sums[(size_t)k * count + e];
+  out[e] = (T)s;
 }
 
 // Y (N x B) = F Z for 64 points per block: the F tile (64 x r) is staged in
@@ -416,7 +453,7 @@ bool skinny(int r, int B) { return B >= 2 && B <= SB && r <= SR; }
 size_t apply_reduce_work(int64_t N, int r, int B) {
   if (N <= 0) return 0;
   if (B == 1) return (size_t)plain_groups(N) * r * sizeof(double);
-  if (skinny(r, B)) return (size_t)skinny_groups(N) * r * B * sizeof(double);
+  if (skinny(r, B)) return ((size_t)skinny_groups(N) + NRANGE) * r * B * sizeof(double);
   return 0;
 }
 
@@ -428,28 +465,39 @@ void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const voi
     return;
   }
   double* part = static_cast<double*>(work);
-  if (B == 1 || skinny(r, B)) {
-    const unsigned g = B == 1 ? plain_groups(N) : skinny_groups(N);
-    const int count = r * B;
+  if (B == 1) {
+    const unsigned g = plain_groups(N);
     if (dtype == TTK_FP32) {
-      if (B == 1)
-        hipLaunchKernelGGL(k_reduce_plain<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
-                           static_cast<const float*>(X), part);
-      else
-        hipLaunchKernelGGL(k_reduce_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N,
-                           r, static_cast<const float*>(X), ldx, B, SKINNY_CHUNK, part);
-      hipLaunchKernelGGL(k_sum_partials<float>, dim3((count + 3) / 4), dim3(256), 0, st, (const double*)part,
-                         (int)g, count, static_cast<float*>(W));
+      hipLaunchKernelGGL(k_reduce_plain<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
+                         static_cast<const float*>(X), part);
+      hipLaunchKernelGGL(k_sum_partials<float>, dim3((r + 3) / 4), dim3(256), 0, st, (const double*)part, (int)g, r,
+                         static_cast<float*>(W));
     } else {
-      if (B == 1)
-        hipLaunchKernelGGL(k_reduce_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
-                           r, static_cast<const double*>(X), part);
-      else
-        hipLaunchKernelGGL(k_reduce_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf,
-                           N, r, static_cast<const double*>(X), ldx, B, SKINNY_CHUNK, part);
-      hipLaunchKernelGGL(k_sum_partials<double>, dim3((count + 3) / 4), dim3(256), 0, st, (const double*)part,
-                         (int)g, count, static_cast<double*>(W));
+      hipLaunchKernelGGL(k_reduce_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
+                         r, static_cast<const double*>(X), part);
+      hipLaunchKernelGGL(k_sum_partials<double>, dim3((r + 3) / 4), dim3(256), 0, st, (const double*)part, (int)g, r,
+                         static_cast<double*>(W));
     }
+    return;
+  }
+  if (skinny(r, B)) {
+    const unsigned g = skinny_groups(N);
+    const int count = r * B;
+    double* sums = part + (size_t)g * count;
+    if (dtype == TTK_FP32)
+      hipLaunchKernelGGL(k_reduce_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
+                         static_cast<const float*>(X), ldx, B, SKINNY_CHUNK, part);
+    else
+      hipLaunchKernelGGL(k_reduce_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
+                         r, static_cast<const double*>(X), ldx, B, SKINNY_CHUNK, part);
+    hipLaunchKernelGGL(k_sum_ranges, dim3((count + 63) / 64, NRANGE), dim3(256), 0, st, (const double*)part, (int)g,
+                       count, sums);
+    if (dtype == TTK_FP32)
+      hipLaunchKernelGGL(k_sum_final<float>, dim3((count + 255) / 256), dim3(256), 0, st, (const double*)sums, count,
+                         static_cast<float*>(W));
+    else
+      hipLaunchKernelGGL(k_sum_final<double>, dim3((count + 255) / 256), dim3(256), 0, st, (const double*)sums,
+                         count, static_cast<double*>(W));
     return;
   }
   fill_zero(W, (size_t)r * B * es, st);
