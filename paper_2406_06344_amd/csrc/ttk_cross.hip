@@ -1118,7 +1118,7 @@ class Cross {
   tt_status enqueue_finish(HostStep& h, const HostStep* next);
   tt_status collect(const HostStep& h, tt_kernel_decision* rec);
   tt_status stage_steps(int sweep, int k0, int k1);
-  tt_status run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added);
+  tt_status run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added, bool* next_staged);
   int first_half() const { return N_ / 2; }   // steps 1..first_half() are staged first
   tt_status build_cores(std::vector<double*>* C);
   tt_status refine_cores();
@@ -1157,20 +1157,21 @@ class Cross {
   HostMail mail_;
   uint32_t mail_seq_ = 0;
   tt_status wait_mail(int slot, uint32_t seq);
-  // upload arenas: host pinned + device mirror, bump-allocated between
-  // stream synchronisations, flushed with one copy before the kernels that
-  // read them.  Arena 0 holds the update steps of a sweep, arena 1 everything
-  // else, so the next sweep can be staged while the stopping test still
-  // reads its own uploads.
-  HBuf ar_h_[2];
-  DBuf ar_d_[2];
-  size_t ar_off_[2] = {0, 0}, ar_flushed_[2] = {0, 0}, ar_cap_ = 0;
-  int ar_ = 1;   // the arena in use
+  // upload arenas: host pinned + device mirror, bump-allocated, flushed with
+  // one copy before the kernels that read them.  Arenas 0 and 1 hold the
+  // update steps of even and odd sweeps, arena 2 everything else, so a sweep
+  // can be staged while the previous one and its stopping test still read
+  // their own uploads.  An arena is reset only once its readers have drained.
+  static constexpr int NAR = 3, AR_OTHER = 2;
+  HBuf ar_h_[NAR];
+  DBuf ar_d_[NAR];
+  size_t ar_off_[NAR] = {0, 0, 0}, ar_flushed_[NAR] = {0, 0, 0}, ar_cap_ = 0;
+  int ar_ = AR_OTHER;   // the arena in use
   const int16_t* cur_left_ = nullptr;
   const int16_t* cur_right_ = nullptr;
   tt_status arena_init(size_t bytes) {
     ar_cap_ = bytes;
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < NAR; ++i) {
       TTK_TRY(ar_h_[i].alloc(bytes));
       TTK_TRY(ar_d_[i].alloc(bytes));
     }
@@ -1619,24 +1620,28 @@ tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
   return TTK_OK;
 }
 
-// Stages steps k0..k1-1 of a sweep in arena 0 (reset at k0 = 1) and
-// uploads them in one copy.
+// Stages steps k0..k1-1 of a sweep in the sweep's arena (sweep & 1, reset
+// at k0 = 1) and uploads them in one copy.
 tt_status Cross::stage_steps(int sweep, int k0, int k1) {
-  struct Use {   // arena 0 while staging, arena 1 again on every return
+  struct Use {   // the sweep's arena while staging, the other arena again on every return
     int& a;
-    explicit Use(int& x) : a(x) { a = 0; }
-    ~Use() { a = 1; }
-  } use(ar_);
-  if (k0 == 1) arena_reset();   // the previous sweep has been collected
+    Use(int& x, int v) : a(x) { a = v; }
+    ~Use() { a = AR_OTHER; }
+  } use(ar_, sweep & 1);
+  if (k0 == 1) arena_reset();   // its last readers, two sweeps back, have drained
   for (int k = k0; k < k1; ++k) TTK_TRY(prepare_step(hs_[k], k, sweep, k > 1));
   return arena_flush();
 }
 
 // One sweep (Alg 6, k = 1..N-1).  The first steps are staged already (during
-// the previous stopping test) when `staged`; the rest are staged while the
-// first ones run.  All steps are queued without waiting, then the results
-// are read in order and applied to the host sets.
-tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added) {
+// the previous sweep) when `staged`; the rest are staged while the first
+// ones run.  All steps are queued without waiting, then the results are read
+// in order and applied to the host sets.  Steps 1..h of the next sweep read
+// only what steps 1..h+1 of this one change, so once those are applied the
+// next sweep's first half is staged while this sweep's last steps run
+// (*next_staged; discarded if the stopping test ends the cross).
+tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added,
+                           bool* next_staged) {
   const int N = N_, h = first_half();
   if (!staged) TTK_TRY(stage_steps(sweep, 1, h + 1));
   for (int k = 1; k <= h; ++k) {
@@ -1649,13 +1654,23 @@ tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decisio
     TTK_TRY(enqueue_finish(hs_[k], k + 1 < N ? &hs_[k + 1] : nullptr));
   }
   *added = 0;
+  *next_staged = false;
+  const int kn = std::min(h + 1, N - 1);   // the last step the next sweep's first half depends on
+  const int max_sweeps = P_.max_sweeps > 0 ? P_.max_sweeps : 200;
   for (int k = 1; k < N; ++k) {
     tt_kernel_decision rec{};
     TTK_TRY(collect(hs_[k], &rec));
     log->push_back(rec);
     *added += rec.added;
     if (k + 1 < N) hs_[k + 1].var = rec.added;
+    if (k == kn && sweep + 1 < max_sweeps) {
+      // (steps kn + 1.. of this sweep keep their staged records: the next
+      // sweep's first half only overwrites hs_[1..h], already collected)
+      TTK_TRY(stage_steps(sweep + 1, 1, h + 1));
+      *next_staged = true;
+    }
   }
+  if (*added == 0) *next_staged = false;
   return TTK_OK;
 }
 
@@ -1833,14 +1848,11 @@ tt_status Cross::run(CrossOut* out) {
   bool staged = false;
   while (err > P_.tol && sweep < max_sweeps) {
     int added = 0;
-    TTK_TRY(run_sweep(sweep, staged, &out->log, &added));
+    bool next = false;
+    TTK_TRY(run_sweep(sweep, staged, &out->log, &added, &next));
     ++sweep;
-    // the next sweep's first steps are staged while the stopping test runs
-    // (discarded if the test stops the cross)
-    staged = added > 0 && sweep < max_sweeps;
-    TTK_TRY(sampled_error(&err, [&]() -> tt_status {
-      return staged ? stage_steps(sweep, 1, first_half() + 1) : TTK_OK;
-    }));
+    staged = next;
+    TTK_TRY(sampled_error(&err));
     if (added == 0) break;
   }
   // the cores of the last stopping test, refined, are the result (C_k in
