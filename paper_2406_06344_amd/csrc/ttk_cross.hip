@@ -40,7 +40,6 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
-#include <functional>
 #include <unordered_map>
 
 #include "ttk_eval_dev.h"
@@ -926,6 +925,23 @@ __global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* de
   }
 }
 
+// The stopping test's result, published to a mailbox slot: the largest of
+// the error slots (one per lane) and the OR of the factor status flags of
+// P_1 .. P_{N-1}.
+__global__ void __launch_bounds__(64) k_test_publish(const double* err, const int32_t* info, int N, StepRes* mail,
+                                                     uint32_t* mail_seq, uint32_t seq) {
+  const int lane = threadIdx.x;
+  const double m = wave64_max(lane < TEST_SLOTS ? err[lane] : 0.0);
+  int flag = 0;
+  for (int k = 1; k < N; ++k) flag |= info[k];
+  if (lane == 0) {
+    mail->s_max = m;
+    mail->info = flag;
+    __threadfence_system();
+    __hip_atomic_store(mail_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // Every fibre F_k = X(I^{<=k-1}, i_k, I^{>k}) ((r_{k-1} n_k) x r_k,
 // column-major) of the stopping test in one launch; block ranges per core
 // (blk[j] .. blk[j + 1]) so that the core is uniform over a block.
@@ -1121,12 +1137,15 @@ class Cross {
   tt_status run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added, bool* next_staged);
   int first_half() const { return N_ / 2; }   // steps 1..first_half() are staged first
   tt_status build_cores(std::vector<double*>* C);
+  tt_status stage_core(int k);
+  CoreEval ce_{};
+  int ce_nb_ = 0, ce_next_ = 1;   // stopping-test staging: blocks so far, next core
   tt_status refine_cores();
   tt_status init_inverses();
   void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
   std::vector<int32_t> pls_[MAXD], pli_[MAXD], prf_[MAXD], prt_[MAXD];   // pivot (s, i_k), (i_{k+1}, t)
   tt_status solve_right(int k, int m, const double* F, double* C);
-  tt_status sampled_error(double* err, const std::function<tt_status()>& overlap = nullptr);
+  tt_status sampled_error(double* err);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
   // Working buffers that follow the growing ranks: grown by at least half
@@ -1663,6 +1682,8 @@ tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decisio
     log->push_back(rec);
     *added += rec.added;
     if (k + 1 < N) hs_[k + 1].var = rec.added;
+    TTK_TRY(stage_core(k));   // core k's sets are final for this sweep's test
+    if (k + 1 == N) TTK_TRY(stage_core(N));
     if (k == kn && sweep + 1 < max_sweeps) {
       // (steps kn + 1.. of this sweep keep their staged records: the next
       // sweep's first half only overwrites hs_[1..h], already collected)
@@ -1677,31 +1698,44 @@ tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decisio
 // Cores of the cross interpolant, column-major C_k ((r_{k-1} n_k) x r_k):
 // C_k = F_k P_k^{-1} with the kept factors, C_D = F_D.  One upload of the
 // index sets, one launch for every fibre, one for every product.
+// Stages the fibre of core k for the next stopping test (its index sets
+// uploaded, its entry in the CoreEval table): cores are staged in order, and
+// core k may be staged as soon as its sets are final (after step k of a
+// sweep), so a sweep stages them while its last steps still run.
+tt_status Cross::stage_core(int k) {
+  if (k != ce_next_) return fail(TTK_ERR_HIP, "cross: core %d staged out of order", k);
+  if (k == 1) {
+    arena_reset();   // the other-uses arena: its last reader, the previous test, has drained
+    ce_ = CoreEval{};
+    ce_.n = N_;
+    ce_nb_ = 0;
+  }
+  const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
+  const int m = r0 * n;
+  TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
+  TTK_TRY(ensure(d_core_[k - 1], (size_t)m * r1 * sizeof(double)));
+  ce_.a[k - 1] = fibre_addr(k);
+  ce_.out[k - 1] = d_core_[k - 1].as<double>();
+  ce_.nr[k - 1] = m;
+  ce_.size[k - 1] = (int64_t)m * r1;
+  ce_.blk[k - 1] = ce_nb_;
+  ce_nb_ += nblk(ce_.size[k - 1], 256);
+  evals_ += (int64_t)m * r1;
+  ce_next_ = k + 1;
+  return TTK_OK;
+}
+
 tt_status Cross::build_cores(std::vector<double*>* C) {
   const int N = N_;
   C->assign(N, nullptr);
-  arena_reset();
-  CoreEval ce{};
-  ce.n = N;
-  int nb = 0;
-  for (int k = 1; k <= N; ++k) {
-    const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
-    const int m = r0 * n;
-    TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
-    TTK_TRY(ensure(d_core_[k - 1], (size_t)m * r1 * sizeof(double)));
-    ce.a[k - 1] = fibre_addr(k);
-    ce.out[k - 1] = d_core_[k - 1].as<double>();
-    ce.nr[k - 1] = m;
-    ce.size[k - 1] = (int64_t)m * r1;
-    ce.blk[k - 1] = nb;
-    nb += nblk(ce.size[k - 1], 256);
-    evals_ += (int64_t)m * r1;
-  }
-  ce.blk[N] = nb;
+  for (int k = ce_next_; k <= N; ++k) TTK_TRY(stage_core(k));
+  ce_next_ = 1;   // the next test stages from core 1 again
+  ce_.blk[N] = ce_nb_;
+  const int nb = ce_nb_;
   TTK_TRY(arena_flush());
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
     hipLaunchKernelGGL((k_eval_cores<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(nb),
-                       dim3(256), 0, st_, ks_, ce, d_err_.as<double>());
+                       dim3(256), 0, st_, ks_, ce_, d_err_.as<double>());
   });
   CoreSolve cs{};
   cs.n = N - 1;
@@ -1763,9 +1797,10 @@ tt_status Cross::refine_cores() {
   return TTK_OK;
 }
 
-// The stopping test; `overlap`, if given, runs on the host while the test's
-// kernels run.
-tt_status Cross::sampled_error(double* err, const std::function<tt_status()>& overlap) {
+// The stopping test: the cores by the interpolation formula, the TT at the
+// test points against the stored values, and the result read from mailbox
+// slot 0 (the update steps use slots 1..N-1).
+tt_status Cross::sampled_error(double* err) {
   std::vector<double*> C;
   TTK_TRY(build_cores(&C));
   TTView tv{};
@@ -1774,18 +1809,23 @@ tt_status Cross::sampled_error(double* err, const std::function<tt_status()>& ov
   for (int k = 0; k <= N_; ++k) tv.r[k] = rank(k);
   hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(), n_test_,
                      (const double*)d_test_val_.as<double>(), d_err_.as<double>());
+  const uint32_t seq = ++mail_seq_;
+  hipLaunchKernelGGL(k_test_publish, dim3(1), dim3(64), 0, st_, (const double*)d_err_.as<double>(),
+                     (const int32_t*)luinfo(0), N_, mail_.dres, mail_.dseq, seq);
   TTK_HIP(hipGetLastError());
-  if (overlap) TTK_TRY(overlap());
-  // the error and the status of every P_k's factors in one copy each
-  double slots[TEST_SLOTS];
-  std::vector<int32_t> info(MAXD, 0);
-  TTK_HIP(hipMemcpyAsync(info.data(), luinfo(0), MAXD * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
-  TTK_HIP(hipMemcpyAsync(slots, d_err_.p, sizeof(slots), hipMemcpyDeviceToHost, st_));
-  TTK_TRY(sync());
-  for (int k = 1; k < N_; ++k)
-    if (info[k] != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
-  const double e = *std::max_element(slots, slots + TEST_SLOTS);
-  *err = test_max_ > 0 ? e / test_max_ : e;
+  TTK_TRY(wait_mail(0, seq));
+  StepRes r;
+  std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
+  if (r.info != 0) {
+    // which P_k: read the flags (rare; a failure path)
+    std::vector<int32_t> info(MAXD, 0);
+    TTK_HIP(hipMemcpyAsync(info.data(), luinfo(0), MAXD * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    TTK_TRY(sync());
+    for (int k = 1; k < N_; ++k)
+      if (info[k] != 0) return fail(TTK_ERR_SINGULAR_CROSS, "cross: P_%d singular in the interpolation formula", k);
+    return fail(TTK_ERR_SINGULAR_CROSS, "cross: an intersection matrix is singular");
+  }
+  *err = test_max_ > 0 ? r.s_max / test_max_ : r.s_max;
   return TTK_OK;
 }
 
