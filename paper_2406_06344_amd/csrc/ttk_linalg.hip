@@ -910,6 +910,25 @@ __global__ void k_zero_rows(double* A, int rows, int cols, int lda) {
   A[e % rows + (size_t)(e / rows) * lda] = 0.0;
 }
 
+// The rotation of a one-sided Jacobi step on columns (x, y) with squared
+// norms al, be and inner product ga: the angle that zeroes the rotated pair's
+// inner product, cot(2 theta) = (be - al) / (2 ga), taking the smaller root.
+// With d = be - al, g = 2 ga, h = sqrt(d^2 + g^2) and w = |d| + h, the
+// tangent is t = +-|g| / w and 1 + t^2 = 2h / w, so
+//   c = w / sqrt(2 h w),  s = +-|g| / sqrt(2 h w)
+// (one square root and one reciprocal square root on the dependent chain
+// instead of two divisions and two roots).  The sign is that of d / g, +1 at
+// d = 0.  d^2 and g^2 are fourth powers of the entries, far from overflow for
+// the matrices here, as the convergence tests already assume.
+__device__ inline void jacobi_rotation(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, g = 2.0 * ga;
+  const double h = sqrt(d * d + g * g);
+  const double w = fabs(d) + h;
+  const double q = rsqrt(2.0 * h * w);
+  c = w * q;
+  s = (d == 0.0 || (d > 0.0) == (g > 0.0) ? 1.0 : -1.0) * fabs(g) * q;
+}
+
 // Singular values (column norms), normalised left vectors, columns sorted
 // by decreasing sigma (stable in the column index); whole workgroup.
 __device__ void jacobi_finish(double* A, int n, int lda, double* V, int ldv, double* sigma, double* work,
@@ -1000,9 +1019,8 @@ __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double
         be = wave_sum(be);
         ga = wave_sum(ga);
         if (fabs(ga) <= 1e-15 * sqrt(al * be) || fabs(ga) <= gfloor || ga == 0.0) continue;
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        double c, s;
+        jacobi_rotation(al, be, ga, c, s);
         for (int i = lane; i < n; i += 64) {
           const double x = ap[i], y = aq[i];
           ap[i] = c * x - s * y;
@@ -1104,10 +1122,7 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
           // converged pair: |ga| <= 1e-15 sqrt(al be), compared squared (al,
           // be are squared column norms, far from the overflow range)
           if (!(ga * ga <= 1e-30 * (al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = rsqrt(1.0 + t * t);
-            sn = c * t;
+            jacobi_rotation(al, be, ga, c, sn);
 #pragma unroll
             for (int u = 0; u < E; ++u) {
               const int i = min(gl + G * u, n - 1);
@@ -1350,12 +1365,21 @@ bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* si
   const int np = (n + 1) & ~1;
   const size_t sh = (size_t)n * n * sizeof(double) + (size_t)(np / 2) * (2 * sizeof(double) + 2 * sizeof(int));
   if (n < 2 || sh + 64 > (size_t)lds_limit) return false;
-  // 16 lanes per pair (64 pairs per round at once), up to 9 entries per lane
-  if (n <= 32) return jacobi_lds_launch_e<16, 2>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
-  if (n <= 64) return jacobi_lds_launch_e<16, 4>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
-  if (n <= 96) return jacobi_lds_launch_e<16, 6>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
-  if (n <= 144) return jacobi_lds_launch_e<16, 9>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
-  return false;
+  // 16 lanes per pair (64 pairs per round at once), E = ceil(n / 16) <= 9
+  // entries per lane: the clamped entries past n are loaded and stored again,
+  // so E is not rounded up further
+  switch ((n + 15) / 16) {
+    case 1:
+    case 2: return jacobi_lds_launch_e<16, 2>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 3: return jacobi_lds_launch_e<16, 3>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 4: return jacobi_lds_launch_e<16, 4>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 5: return jacobi_lds_launch_e<16, 5>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 6: return jacobi_lds_launch_e<16, 6>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 7: return jacobi_lds_launch_e<16, 7>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 8: return jacobi_lds_launch_e<16, 8>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    case 9: return jacobi_lds_launch_e<16, 9>(A, n, lda, V, ldv, sigma, sh, lds_limit, st);
+    default: return false;
+  }
 }
 
 }  // namespace
