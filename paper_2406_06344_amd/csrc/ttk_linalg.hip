@@ -777,6 +777,130 @@ __global__ void __launch_bounds__(QAW * 64) k_qr_apply(const double* V, int mm, 
   }
 }
 
+// The same product split over row chunks of QRC rows as well as column tiles,
+// for tall panels, where one block per 16 columns leaves the chip idle:
+// k_qr_apply_w writes each chunk's W partial (V[chunk]^T C[chunk], 16 x 16,
+// FP64 MFMA as above), k_qr_apply_sum folds the partials of a tile in chunk
+// order when there are many, and k_qr_apply_c sums what is left in chunk
+// order, forms W2 = op(T) W and updates its chunk, C -= V W2.  Partials
+// live at Wp[(chunk * tiles + tile) * 256 + row * 16 + col].
+constexpr int QRC = 128;   // rows per chunk
+constexpr int QSW = 4;     // waves per block (QRC / 4 / QSW k-steps of four rows each)
+constexpr int QSUM = 16;   // the update sums at most this many partials itself
+static_assert(QSW * 64 == 256, "a thread per entry of the 16 x 16 products");
+__global__ void __launch_bounds__(QSW * 64) k_qr_apply_w(const double* V, int mm, int jb, const double* C, int nc,
+                                                          int lda, double* Wp) {
+  constexpr int STEPS = QRC / 4 / QSW;
+  __shared__ double Ws[QSW][16][17];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = blockIdx.x, ch = blockIdx.y;
+  const int c = ct * 16 + li;
+  const bool cok = c < nc, pok = li < jb;
+  const int r0 = ch * QRC + wv * (QRC / QSW);
+  double a[STEPS], b[STEPS];
+#pragma unroll
+  for (int u = 0; u < STEPS; ++u) {
+    const int i = r0 + 4 * u + lk;
+    const bool ok = i < mm;
+    a[u] = (ok && pok) ? V[i + (size_t)li * mm] : 0.0;
+    b[u] = (ok && cok) ? C[i + (size_t)c * lda] : 0.0;
+  }
+  qdbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < STEPS; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Ws[wv][lk + 4 * v][li] = acc[v];
+  __syncthreads();
+  double sum = 0.0;
+#pragma unroll
+  for (int w = 0; w < QSW; ++w) sum += Ws[w][tid >> 4][tid & 15];
+  Wp[((size_t)ch * gridDim.x + ct) * 256 + tid] = sum;
+}
+
+// Sum of a tile's nch partials in chunk order, into chunk 0's slot (each
+// thread reads and writes its own entry only).
+__global__ void __launch_bounds__(256) k_qr_apply_sum(double* Wp, int nch, int tiles) {
+  const int ct = blockIdx.x, e = threadIdx.x;
+  double sum = 0.0;
+  for (int r = 0; r < nch; ++r) sum += Wp[((size_t)r * tiles + ct) * 256 + e];
+  Wp[(size_t)ct * 256 + e] = sum;
+}
+
+__global__ void __launch_bounds__(QSW * 64) k_qr_apply_c(const double* V, int mm, int jb, const double* T, int trans,
+                                                          double* C, int nc, int lda, const double* Wp, int nparts) {
+  __shared__ double W[16][17], W2[16][17];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ct = blockIdx.x, ch = blockIdx.y;
+  const int c = ct * 16 + li;
+  const bool cok = c < nc;
+  {
+    double sum = 0.0;
+    for (int r = 0; r < nparts; ++r) sum += Wp[((size_t)r * gridDim.x + ct) * 256 + tid];
+    W[tid >> 4][tid & 15] = sum;
+  }
+  __syncthreads();
+  {
+    const int pr = tid >> 4, cc = tid & 15;
+    double sum = 0.0;
+    if (pr < jb)
+      for (int q = 0; q < jb; ++q) sum += (trans ? T[q + pr * jb] : T[pr + q * jb]) * W[q][cc];
+    W2[pr][cc] = sum;
+  }
+  __syncthreads();
+  // the chunk's QRC / 16 row tiles, QRC / 16 / QSW per wave with their loads in flight together
+  constexpr int TPW = QRC / 16 / QSW;
+  double av[TPW][4], cv[TPW][4];
+#pragma unroll
+  for (int h = 0; h < TPW; ++h) {
+    const int t0 = ch * QRC + (wv * TPW + h) * 16;
+    const int r = t0 + li;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int q = 4 * st + lk;
+      av[h][st] = (r < mm && q < jb) ? V[r + (size_t)q * mm] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = t0 + lk + 4 * v;
+      cv[h][v] = (row < mm && cok) ? C[row + (size_t)c * lda] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < TPW; ++h) {
+    const int t0 = ch * QRC + (wv * TPW + h) * 16;
+    qdbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][st], W2[4 * st + lk][li], d, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = t0 + lk + 4 * v;
+      if (row < mm && cok) C[row + (size_t)c * lda] = cv[h][v] - d[v];
+    }
+  }
+}
+
+// C <- (I - V op(T) V^T) C: one block per 16 columns for short panels, the
+// row-split kernels (partials in Wp) for tall ones.
+void qr_apply(const double* V, int mm, int jb, const double* T, int trans, double* C, int nc, int lda, double* Wp,
+              hipStream_t st) {
+  const int tiles = (nc + 15) / 16;
+  if (mm <= 4 * QRC) {
+    hipLaunchKernelGGL(k_qr_apply, dim3(tiles), dim3(QAW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda);
+    return;
+  }
+  const int nch = (mm + QRC - 1) / QRC;
+  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda, Wp);
+  int nparts = nch;
+  if (nch > QSUM) {
+    hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles), dim3(256), 0, st, Wp, nch, tiles);
+    nparts = 1;
+  }
+  hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
+                     (const double*)Wp, nparts);
+}
+
 // Columns of Q for one panel from its reflectors (backward accumulation, as
 // k_qr_panel_q), register-resident like k_qr_panel_reg: for j = jb-1 .. 0 the
 // products v_j^T q_c with the already formed columns c > j are one block
@@ -1270,9 +1394,9 @@ void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work,
 
 // Blocked Householder QR, compact WY with panels of 16: the panel factors in
 // one workgroup (registers when it has at most 2048 rows), the trailing update
-// and the formation of Q are one k_qr_apply launch per panel.
-// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) doubles (qr_blocked_work
-// keeps a spare 32 n).
+// and the formation of Q are one qr_apply per panel.
+// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) doubles, a spare 32 n + 64,
+// then 256 ceil(n/16) ceil(m/QRC) for the row-split partials (qr_blocked_work).
 tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
   constexpr int NB = 16;
   if (m < n) return fail(TTK_ERR_ARG, "qr_blocked needs m >= n");
@@ -1280,6 +1404,7 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
   double* V = tau + n;
   double* Tall = V + (size_t)NB * m;
   const int npan = (n + NB - 1) / NB;
+  double* Wp = Tall + (size_t)NB * NB * npan + 2 * (size_t)NB * n + 64;   // row-split partials
   for (int p = 0; p < npan; ++p) {
     const int j0 = p * NB, jb = std::min(NB, n - j0);
     const int mm = m - j0;
@@ -1295,8 +1420,7 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
     if (nc > 0) {
       double* A2 = A + j0 + (size_t)(j0 + jb) * lda;
       // A2 <- (I - V T^T V^T) A2
-      hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
-                         (const double*)T, 1, A2, nc, lda);
+      qr_apply(V, mm, jb, T, 1, A2, nc, lda, Wp, st);
     }
   }
   hipLaunchKernelGGL(k_extract_r, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, lda, R, ldr);
@@ -1312,8 +1436,7 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
                          lda, V);
       double* Q2 = A + j0 + (size_t)(j0 + jb) * lda;
       // Q2 <- (I - V T V^T) Q2
-      hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
-                         (const double*)T, 0, Q2, nc, lda);
+      qr_apply(V, mm, jb, T, 0, Q2, nc, lda, Wp, st);
     }
     if (!qr_panel_q_reg(Ap, mm, jb, lda, tau + j0, st))
       hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
@@ -1327,7 +1450,8 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
 
 size_t qr_blocked_work(int m, int n) {
   constexpr int NB = 16;
-  return (size_t)n + (size_t)NB * m + (size_t)NB * NB * ((n + NB - 1) / NB) + 2 * (size_t)NB * n + 64;
+  return (size_t)n + (size_t)NB * m + (size_t)NB * NB * ((n + NB - 1) / NB) + 2 * (size_t)NB * n + 64 +
+         (size_t)256 * ((n + NB - 1) / NB) * (((size_t)m + QRC - 1) / QRC);
 }
 
 namespace {
