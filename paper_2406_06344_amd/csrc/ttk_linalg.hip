@@ -542,9 +542,9 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
   for (int e = tid; e < jb * jb; e += BS) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
 }
 
-// Register-resident panel factorisation for panels of at most PB * RPT rows
-// (RPT <= 8) and 16 columns: thread t holds rows t + k PB (k < RPT) of every
-// column.
+// Register-resident panel factorisation for panels of at most PBT * RPT rows
+// and 16 columns, PBT threads: thread t holds rows t + k PBT (k < RPT) of
+// every column.
 // Per column j: the norm below the diagonal is one block reduction and the
 // sixteen products v_j^T a_c one more (both through LDS, no lane shuffles);
 // for c > j they update the trailing panel columns, for c < j they are
@@ -553,13 +553,13 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
 // Writes the reflectors below the diagonal of the panel (unit diagonal
 // implicit), R on and above it, tau, V explicit (mm x jb) and T (jb x jb).
 constexpr int PB = 256;
-template <int RPT>
-__global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V,
+template <int RPT, int PBT>
+__global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V,
                                                      double* T) {
-  constexpr int NB = 16, S = PB / NB;   // S strips per column in the first reduction stage
+  constexpr int NB = 16, S = PBT / NB;   // S strips per column in the first reduction stage
   // block sums through LDS: every thread's partials in P (conflict-free
   // columns), then S partial sums per column in Q, then the final sums
-  __shared__ double P[NB][PB], Q[NB][S];
+  __shared__ double P[NB][PBT], Q[NB][S];
   __shared__ double sd[NB], Ts[NB][NB];
   __shared__ double s_x0;
   const int tid = threadIdx.x;
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
   double a[RPT][NB];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * PB;
+    const int i = tid + k * PBT;
 #pragma unroll
     for (int c = 0; c < NB; ++c) a[k][c] = (i < mm && c < jb) ? A[i + (size_t)c * lda] : 0.0;
   }
@@ -578,14 +578,14 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < RPT; ++k)
-      if (tid + k * PB > j) part += a[k][j] * a[k][j];
+      if (tid + k * PBT > j) part += a[k][j] * a[k][j];
     P[0][tid] = part;
     if (tid == j) s_x0 = a[0][j];
     __syncthreads();
     if (tid < S) {
       double sum = 0.0;
 #pragma unroll
-      for (int u = 0; u < PB / S; ++u) sum += P[0][u * S + tid];
+      for (int u = 0; u < PBT / S; ++u) sum += P[0][u * S + tid];
       Q[0][tid] = sum;
     }
     __syncthreads();
@@ -604,7 +604,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
     double v[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int i = tid + k * PB;
+      const int i = tid + k * PBT;
       if (i > j && tj != 0.0) a[k][j] *= scale;
       v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
     }
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
       if (c != j && c < jb) {
 #pragma unroll
         for (int k = 0; k < RPT; ++k) {
-          const int i = tid + k * PB;
+          const int i = tid + k * PBT;
           const double x = (c > j) ? a[k][c] : ((i > c) ? a[k][c] : (i == c ? 1.0 : 0.0));
           sum += v[k] * x;
         }
@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
     {
       double sum = 0.0;
 #pragma unroll
-      for (int u = 0; u < PB / S; ++u) sum += P[rc][u * S + rj];
+      for (int u = 0; u < PBT / S; ++u) sum += P[rc][u * S + rj];
       Q[rc][rj] = sum;
     }
     __syncthreads();
@@ -664,7 +664,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
   }
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * PB;
+    const int i = tid + k * PBT;
     if (i < mm)
 #pragma unroll
       for (int c = 0; c < NB; ++c)
@@ -673,19 +673,22 @@ __global__ void __launch_bounds__(PB) k_qr_panel_reg(double* A, int mm, int jb, 
           V[i + (size_t)c * mm] = (i > c) ? a[k][c] : (i == c ? 1.0 : 0.0);
         }
   }
-  for (int e = tid; e < jb * jb; e += PB) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
+  for (int e = tid; e < jb * jb; e += PBT) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
 }
 
 // Launches the register panel for mm <= 8 PB rows; false if the panel is taller.
+// Above 4 PB rows the panel takes 2 PB threads, four rows each (eight rows of
+// sixteen columns overflow the registers); below, PB threads are faster (the
+// block reductions dominate).
 bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, double* T, hipStream_t st) {
   if (mm <= PB)
-    hipLaunchKernelGGL(k_qr_panel_reg<1>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<1, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
   else if (mm <= 2 * PB)
-    hipLaunchKernelGGL(k_qr_panel_reg<2>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<2, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
   else if (mm <= 4 * PB)
-    hipLaunchKernelGGL(k_qr_panel_reg<4>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<4, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
   else if (mm <= 8 * PB)
-    hipLaunchKernelGGL(k_qr_panel_reg<8>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<4, 2 * PB>), dim3(1), dim3(2 * PB), 0, st, A, mm, jb, lda, tau, V, T);
   else
     return false;
   return true;
@@ -906,17 +909,17 @@ void qr_apply(const double* V, int mm, int jb, const double* T, int trans, doubl
 // products v_j^T q_c with the already formed columns c > j are one block
 // reduction through LDS, then q_c -= tau_j (v_j^T q_c) v_j and column j
 // becomes H_j e_j.
-template <int RPT>
-__global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau) {
-  constexpr int NB = 16, S = PB / NB;
-  __shared__ double P[NB][PB], Q[NB][S];
+template <int RPT, int PBT>
+__global__ void __launch_bounds__(PBT) k_qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau) {
+  constexpr int NB = 16, S = PBT / NB;
+  __shared__ double P[NB][PBT], Q[NB][S];
   __shared__ double sd[NB];
   const int tid = threadIdx.x;
   const int rc = tid / S, rj = tid % S;
   double a[RPT][NB];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * PB;
+    const int i = tid + k * PBT;
 #pragma unroll
     for (int c = 0; c < NB; ++c) a[k][c] = (i < mm && c < jb) ? A[i + (size_t)c * lda] : 0.0;
   }
@@ -927,7 +930,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb
     double v[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int i = tid + k * PB;
+      const int i = tid + k * PBT;
       v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
     }
     if (j < jb - 1) {
@@ -943,7 +946,7 @@ __global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb
       {
         double sum = 0.0;
 #pragma unroll
-        for (int u = 0; u < PB / S; ++u) sum += P[rc][u * S + rj];
+        for (int u = 0; u < PBT / S; ++u) sum += P[rc][u * S + rj];
         Q[rc][rj] = sum;
       }
       __syncthreads();
@@ -966,13 +969,13 @@ __global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb
     }
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
-      const int i = tid + k * PB;
+      const int i = tid + k * PBT;
       a[k][j] = (i > j) ? -tj * v[k] : (i == j ? 1.0 - tj : 0.0);
     }
   }
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * PB;
+    const int i = tid + k * PBT;
     if (i < mm)
 #pragma unroll
       for (int c = 0; c < NB; ++c)
@@ -983,13 +986,13 @@ __global__ void __launch_bounds__(PB) k_qr_panel_q_reg(double* A, int mm, int jb
 // Launches the register form of the panel's Q for mm <= 8 PB rows; false otherwise.
 bool qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau, hipStream_t st) {
   if (mm <= PB)
-    hipLaunchKernelGGL(k_qr_panel_q_reg<1>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+    hipLaunchKernelGGL((k_qr_panel_q_reg<1, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
   else if (mm <= 2 * PB)
-    hipLaunchKernelGGL(k_qr_panel_q_reg<2>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+    hipLaunchKernelGGL((k_qr_panel_q_reg<2, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
   else if (mm <= 4 * PB)
-    hipLaunchKernelGGL(k_qr_panel_q_reg<4>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+    hipLaunchKernelGGL((k_qr_panel_q_reg<4, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
   else if (mm <= 8 * PB)
-    hipLaunchKernelGGL(k_qr_panel_q_reg<8>, dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+    hipLaunchKernelGGL((k_qr_panel_q_reg<8, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
   else
     return false;
   return true;
