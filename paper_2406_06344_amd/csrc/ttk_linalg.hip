@@ -1101,9 +1101,17 @@ __device__ void jacobi_finish(double* A, int n, int lda, double* V, int ldv, dou
 // One-sided (Hestenes) Jacobi on the columns of A (n x n): A V = U Sigma.
 // Pairs follow a round-robin tournament so each round's rotations are
 // disjoint; one wave per pair.
+// Stopping: a pair rotates while its cosine |ga| / sqrt(al be) exceeds 1e-15.
+// Cyclic Jacobi converges quadratically in the end, so after a sweep whose
+// largest cosine stayed below JACOBI_LAST the cosines are of order its square
+// (1e-12) or smaller, and the sweep that would follow rotates nothing or
+// nearly nothing: rotations that small move the singular values at second
+// order (1e-24 relative) and the columns' orthogonality at 1e-12.  The
+// iteration stops after such a sweep instead of running that one.
+constexpr double JACOBI_LAST = 1e-6;
 __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double* V, int ldv,
                                                double* sigma, size_t sA, size_t sV, size_t sS) {
-  __shared__ int rotated;
+  __shared__ int rotated, large;
   // one matrix per workgroup: A, V, sigma (+ its workspace) offset by the batch index
   A += blockIdx.x * sA;
   V += blockIdx.x * sV;
@@ -1125,7 +1133,7 @@ __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double
   const double gfloor = 1e-30 * block_sum(nf, red_nf);
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) rotated = large = 0;
     __syncthreads();
     for (int rnd = 0; rnd < np - 1; ++rnd) {
       for (int pr = w; pr < np / 2; pr += NW) {
@@ -1160,11 +1168,14 @@ __global__ void __launch_bounds__(BS) k_jacobi(double* A, int n, int lda, double
           vp[i] = c * x - s * y;
           vq[i] = s * x + c * y;
         }
-        if (lane == 0) rotated = 1;
+        if (lane == 0) {
+          rotated = 1;
+          if (fabs(ga) > JACOBI_LAST * sqrt(al * be)) large = 1;
+        }
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated || !large) break;
     __syncthreads();
   }
   jacobi_finish(A, n, lda, V, ldv, sigma, work, order);
@@ -1187,7 +1198,7 @@ template <int G, int E>
 __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, double* V, int ldv, double* sigma,
                                                    int want_v) {
   extern __shared__ double smj[];
-  __shared__ int rotated;
+  __shared__ int rotated, large;
   double* A = smj;                                  // n x n, leading dimension n
   const int np = (n + 1) & ~1;
   double* rc = A + (size_t)n * n;                   // np/2 cosines
@@ -1206,7 +1217,7 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
   const double gfloor = 1e-30 * block_sum(nf, red_nf);   // as in k_jacobi
   __syncthreads();
   for (int sweep = 0; sweep < 60; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) rotated = large = 0;
     __syncthreads();
     // a column pair per group of G lanes: a whole round of disjoint pairs
     // runs at once, with G-lane reductions
@@ -1257,7 +1268,10 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
               aq[i] = sn * xv[u] + c * yv[u];
             }
             keep = 1;
-            if (gl == 0) rotated = 1;
+            if (gl == 0) {
+              rotated = 1;
+              if (ga * ga > JACOBI_LAST * JACOBI_LAST * (al * be)) large = 1;
+            }
           }
         }
         if (gl == 0) {
@@ -1284,7 +1298,7 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
       }
       if (want_v) __syncthreads();
     }
-    if (!rotated) break;
+    if (!rotated || !large) break;
     __syncthreads();
   }
   for (int e = tid; e < n * n; e += BS) Ag[e % n + (size_t)(e / n) * lda] = A[e];
