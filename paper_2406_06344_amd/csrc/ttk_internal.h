@@ -139,6 +139,12 @@ void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work,
 // qr_blocked_work(m, n) doubles.
 tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st);
 size_t qr_blocked_work(int m, int n);
+// The factorisation alone: the reflectors stay below the diagonal of A and
+// their block factors in work (qr_blocked_work(m, n) doubles); R (n x n).
+tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st);
+// C (m x nc, ldc) <- Q C with the Q of a qr_factor of A (m x n) and its work.
+tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, double* C, int nc, int ldc,
+                     hipStream_t st);
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);

@@ -1411,55 +1411,93 @@ void qr_thin(double* A, int m, int n, int lda, double* R, int ldr, double* work,
 
 // Blocked Householder QR, compact WY with panels of 16: the panel factors in
 // one workgroup (registers when it has at most 2048 rows), the trailing update
-// and the formation of Q are one qr_apply per panel.
-// work: n (tau) + 16 m (V) + 16 * 16 * ceil(n/16) (T) doubles, a spare 32 n + 64,
-// then 256 ceil(n/16) ceil(m/QRC) for the row-split partials (qr_blocked_work).
-tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
+// and the formation of Q are one qr_apply per panel.  qr_factor keeps the
+// reflectors below the diagonal of A and the panels' T in work, for
+// qr_blocked (Q formed in A) or qr_apply_q (Q applied to other columns).
+namespace {
+// The workspace of qr_blocked / qr_factor: tau (n), V (16 m), the panels' T
+// (16 x 16 each), a spare 32 n + 64, then the row-split partials.
+struct QrWork {
+  double *tau, *V, *Tall, *Wp;
+  QrWork(double* work, int m, int n) {
+    tau = work;
+    V = tau + n;
+    Tall = V + (size_t)16 * m;
+    Wp = Tall + (size_t)256 * ((n + 15) / 16) + 32 * (size_t)n + 64;
+  }
+};
+}  // namespace
+
+tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
   constexpr int NB = 16;
-  if (m < n) return fail(TTK_ERR_ARG, "qr_blocked needs m >= n");
-  double* tau = work;
-  double* V = tau + n;
-  double* Tall = V + (size_t)NB * m;
+  if (m < n) return fail(TTK_ERR_ARG, "qr_factor needs m >= n");
+  const QrWork w(work, m, n);
   const int npan = (n + NB - 1) / NB;
-  double* Wp = Tall + (size_t)NB * NB * npan + 2 * (size_t)NB * n + 64;   // row-split partials
   for (int p = 0; p < npan; ++p) {
     const int j0 = p * NB, jb = std::min(NB, n - j0);
     const int mm = m - j0;
     double* Ap = A + j0 + (size_t)j0 * lda;
-    double* T = Tall + (size_t)p * NB * NB;
-    if (!qr_panel_reg(Ap, mm, jb, lda, tau + j0, V, T, st)) {
-      hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+    double* T = w.Tall + (size_t)p * NB * NB;
+    if (!qr_panel_reg(Ap, mm, jb, lda, w.tau + j0, w.V, T, st)) {
+      hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, w.tau + j0);
       hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
-                         lda, V);
-      hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, V, mm, jb, tau + j0, T);
+                         lda, w.V);
+      hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, w.V, mm, jb, w.tau + j0, T);
     }
     const int nc = n - j0 - jb;
     if (nc > 0) {
       double* A2 = A + j0 + (size_t)(j0 + jb) * lda;
       // A2 <- (I - V T^T V^T) A2
-      qr_apply(V, mm, jb, T, 1, A2, nc, lda, Wp, st);
+      qr_apply(w.V, mm, jb, T, 1, A2, nc, lda, w.Wp, st);
     }
   }
   hipLaunchKernelGGL(k_extract_r, dim3((n * n + 255) / 256), dim3(256), 0, st, A, n, lda, R, ldr);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, double* work, hipStream_t st) {
+  constexpr int NB = 16;
+  TTK_TRY(qr_factor(A, m, n, lda, R, ldr, work, st));
+  const QrWork w(work, m, n);
+  const int npan = (n + NB - 1) / NB;
   // Q = H_0 ... H_{n-1} [I; 0], panels from last to first
   for (int p = npan - 1; p >= 0; --p) {
     const int j0 = p * NB, jb = std::min(NB, n - j0);
     const int mm = m - j0;
     double* Ap = A + j0 + (size_t)j0 * lda;
-    const double* T = Tall + (size_t)p * NB * NB;
+    const double* T = w.Tall + (size_t)p * NB * NB;
     const int nc = n - j0 - jb;
     if (nc > 0) {
       hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
-                         lda, V);
+                         lda, w.V);
       double* Q2 = A + j0 + (size_t)(j0 + jb) * lda;
       // Q2 <- (I - V T V^T) Q2
-      qr_apply(V, mm, jb, T, 0, Q2, nc, lda, Wp, st);
+      qr_apply(w.V, mm, jb, T, 0, Q2, nc, lda, w.Wp, st);
     }
-    if (!qr_panel_q_reg(Ap, mm, jb, lda, tau + j0, st))
-      hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, tau + j0);
+    if (!qr_panel_q_reg(Ap, mm, jb, lda, w.tau + j0, st))
+      hipLaunchKernelGGL(k_qr_panel_q, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, w.tau + j0);
     if (j0 > 0)
       hipLaunchKernelGGL(k_zero_rows, dim3((j0 * jb + 255) / 256), dim3(256), 0, st, A + (size_t)j0 * lda, j0, jb,
                          lda);
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, double* C, int nc, int ldc,
+                     hipStream_t st) {
+  constexpr int NB = 16;
+  if (nc <= 0) return TTK_OK;
+  const QrWork w(work, m, n);
+  const int npan = (n + NB - 1) / NB;
+  // Q C = H_0 (H_1 (... H_{n-1} C)): the panels' block reflectors from last to first
+  for (int p = npan - 1; p >= 0; --p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0);
+    const int mm = m - j0;
+    hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st,
+                       A + j0 + (size_t)j0 * lda, mm, jb, lda, w.V);
+    qr_apply(w.V, mm, jb, w.Tall + (size_t)p * NB * NB, 0, C + j0, nc, ldc, w.Wp, st);
   }
   TTK_HIP(hipGetLastError());
   return TTK_OK;

@@ -73,6 +73,14 @@ __global__ void k_scale(double* A, int m, int c, int lda, const double* sg, int 
   A[i + (int64_t)j * lda] *= (mode == 0) ? sg[j] : sg[i];
 }
 
+// C (mc x nc, ldc) <- [S; 0] with S rows x nc (lds), rows <= mc.
+__global__ void k_pad_rows(const double* S, int rows, int lds, double* C, int mc, int nc, int ldc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)mc * nc) return;
+  const int i = (int)(e % mc), j = (int)(e / mc);
+  C[i + (int64_t)j * ldc] = i < rows ? S[i + (int64_t)j * lds] : 0.0;
+}
+
 inline int nb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 struct Cores {
@@ -126,7 +134,7 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     TTK_TRY(c.g[k].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
     TTK_HIP(hipMemcpyAsync(c.g[k].p, cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  DBuf A, R, T, tau, V, sig, W, nrm, sg;
+  DBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
   // right-to-left orthogonalisation
   for (int i = D - 1; i >= 1; --i) TTK_TRY(orth_right(c, i, A, R, T, tau, st));
   TTK_TRY(nrm.alloc(sizeof(double)));
@@ -150,7 +158,7 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     if (ma > m) fill_zero(A.p, (size_t)ma * r1 * sizeof(double), st);
     TTK_HIP(hipMemcpy2DAsync(A.p, (size_t)ma * sizeof(double), c.g[i].p, (size_t)m * sizeof(double),
                              (size_t)m * sizeof(double), (size_t)r1, hipMemcpyDeviceToDevice, st));
-    TTK_TRY(qr_blocked(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
+    TTK_TRY(qr_factor(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
     // SVD of R.  Sigma V^T, pushed into the next core, is U^T R: with a copy of R
     // kept, only the left vectors are needed (V stays unaccumulated)
     TTK_HIP(hipMemcpyAsync(V.p, R.p, (size_t)r1 * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -167,8 +175,21 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
         if (std::sqrt(tail[q]) <= delta) { rp = q; break; }
     }
     rp = std::min(rp, m);   // a wide unfolding has at most m singular values
-    // G_i^{2} <- Q[:m, :] U_R[:, :rp]
-    gemm64(0, 0, m, rp, r1, 1.0, A.as<double>(), ma, R.as<double>(), r1, 0.0, c.g[i].as<double>(), m, st);
+    // G_i^{2} <- Q[:m, :] U_R[:, :rp], the leading m rows of Q [U_R[:, :rp]; 0]: the
+    // reflectors applied to the rp kept columns (Q itself is never formed)
+    {
+      double* Cq = c.g[i].as<double>();   // m x rp fits the core's buffer
+      if (ma > m) {
+        TTK_TRY(Cw.alloc((size_t)ma * rp * sizeof(double)));
+        Cq = Cw.as<double>();
+      }
+      hipLaunchKernelGGL(k_pad_rows, dim3(nb((int64_t)ma * rp)), dim3(256), 0, st, (const double*)R.as<double>(),
+                         r1, r1, Cq, ma, rp, ma);
+      TTK_TRY(qr_apply_q(A.as<double>(), ma, r1, ma, tau.as<double>(), Cq, rp, ma, st));
+      if (ma > m)
+        TTK_HIP(hipMemcpy2DAsync(c.g[i].p, (size_t)m * sizeof(double), Cq, (size_t)ma * sizeof(double),
+                                 (size_t)m * sizeof(double), (size_t)rp, hipMemcpyDeviceToDevice, st));
+    }
     // G_{i+1}^{1} <- (Sigma V^T)[:rp, :] G_{i+1}^{1}
     const int n2 = c.n[i + 1], r2 = c.r[i + 2];
     TTK_TRY(W.alloc((size_t)rp * r1 * sizeof(double)));
