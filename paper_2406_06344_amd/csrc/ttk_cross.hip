@@ -1134,7 +1134,9 @@ class Cross {
   tt_status enqueue_finish(HostStep& h, const HostStep* next);
   tt_status collect(const HostStep& h, tt_kernel_decision* rec);
   tt_status stage_steps(int sweep, int k0, int k1);
-  tt_status run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added, bool* next_staged);
+  tt_status enqueue_first_half();
+  tt_status run_sweep(int sweep, bool staged, bool queued, std::vector<tt_kernel_decision>* log, int* added,
+                      bool* next_staged);
   int first_half() const { return N_ / 2; }   // steps 1..first_half() are staged first
   tt_status build_cores(std::vector<double*>* C);
   tt_status stage_core(int k);
@@ -1145,7 +1147,7 @@ class Cross {
   void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
   std::vector<int32_t> pls_[MAXD], pli_[MAXD], prf_[MAXD], prt_[MAXD];   // pivot (s, i_k), (i_{k+1}, t)
   tt_status solve_right(int k, int m, const double* F, double* C);
-  tt_status sampled_error(double* err);
+  tt_status sampled_error(double* err, bool queue_next = false);
   Addr fibre_addr(int k) const;   // F_k, k = 1..N
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
   // Working buffers that follow the growing ranks: grown by at least half
@@ -1659,13 +1661,25 @@ tt_status Cross::stage_steps(int sweep, int k0, int k1) {
 // only what steps 1..h+1 of this one change, so once those are applied the
 // next sweep's first half is staged while this sweep's last steps run
 // (*next_staged; discarded if the stopping test ends the cross).
-tt_status Cross::run_sweep(int sweep, bool staged, std::vector<tt_kernel_decision>* log, int* added,
-                           bool* next_staged) {
-  const int N = N_, h = first_half();
-  if (!staged) TTK_TRY(stage_steps(sweep, 1, h + 1));
+// Queues the staged first half of a sweep (steps 1..h, without the finish
+// of step h, whose successor is staged with the second half).
+tt_status Cross::enqueue_first_half() {
+  const int h = first_half();
   for (int k = 1; k <= h; ++k) {
     TTK_TRY(enqueue_front(hs_[k]));
     if (k < h) TTK_TRY(enqueue_finish(hs_[k], &hs_[k + 1]));
+  }
+  return TTK_OK;
+}
+
+// (`queued`: the first half is on the stream already, behind the previous
+// sweep's stopping test.)
+tt_status Cross::run_sweep(int sweep, bool staged, bool queued, std::vector<tt_kernel_decision>* log, int* added,
+                           bool* next_staged) {
+  const int N = N_, h = first_half();
+  if (!queued) {
+    if (!staged) TTK_TRY(stage_steps(sweep, 1, h + 1));
+    TTK_TRY(enqueue_first_half());
   }
   TTK_TRY(stage_steps(sweep, h + 1, N));
   for (int k = h; k < N; ++k) {
@@ -1799,8 +1813,13 @@ tt_status Cross::refine_cores() {
 
 // The stopping test: the cores by the interpolation formula, the TT at the
 // test points against the stored values, and the result read from mailbox
-// slot 0 (the update steps use slots 1..N-1).
-tt_status Cross::sampled_error(double* err) {
+// slot 0 (the update steps use slots 1..N-1).  With `queue_next`, the next
+// sweep's staged first half is queued behind the test before its result is
+// read, so the device does not wait for the host's decision; if the test
+// ends the cross those steps are never collected.  They change nothing the
+// result depends on: the returned cores are the test's, and bordering P_k
+// only appends a row and a column beyond the kept rank to its factors.
+tt_status Cross::sampled_error(double* err, bool queue_next) {
   std::vector<double*> C;
   TTK_TRY(build_cores(&C));
   TTView tv{};
@@ -1813,6 +1832,7 @@ tt_status Cross::sampled_error(double* err) {
   hipLaunchKernelGGL(k_test_publish, dim3(1), dim3(64), 0, st_, (const double*)d_err_.as<double>(),
                      (const int32_t*)luinfo(0), N_, mail_.dres, mail_.dseq, seq);
   TTK_HIP(hipGetLastError());
+  if (queue_next) TTK_TRY(enqueue_first_half());
   TTK_TRY(wait_mail(0, seq));
   StepRes r;
   std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
@@ -1885,14 +1905,16 @@ tt_status Cross::run(CrossOut* out) {
   TTK_TRY(sampled_error(&err));
   int sweep = 0;
   const int max_sweeps = P_.max_sweeps > 0 ? P_.max_sweeps : 200;
-  bool staged = false;
+  bool staged = false, queued = false;
   while (err > P_.tol && sweep < max_sweeps) {
     int added = 0;
     bool next = false;
-    TTK_TRY(run_sweep(sweep, staged, &out->log, &added, &next));
+    TTK_TRY(run_sweep(sweep, staged, queued, &out->log, &added, &next));
     ++sweep;
     staged = next;
-    TTK_TRY(sampled_error(&err));
+    // the next sweep starts behind the test unless nothing more can run
+    queued = staged && added > 0 && sweep < max_sweeps;
+    TTK_TRY(sampled_error(&err, queued));
     if (added == 0) break;
   }
   // the cores of the last stopping test, refined, are the result (C_k in
