@@ -2,6 +2,7 @@
 // and the orchestration of the offline stage (Algorithm 2), the online stage
 // (Algorithm 3) and the apply / backward calls on the caller's stream.
 #include <algorithm>
+#include <map>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -50,6 +51,78 @@ tt_status DBuf::alloc(size_t nbytes) {
   bytes = nbytes;
   return TTK_OK;
 }
+
+namespace {
+struct Pool {
+  std::multimap<size_t, void*> free;   // idle blocks by size
+  std::vector<std::pair<void*, size_t>> pending;   // released since the last synchronisation
+  size_t total = 0;
+};
+constexpr size_t POOL_CAP = (size_t)1 << 30;
+Pool& pool_of(bool host, int dev) {
+  thread_local std::map<std::pair<int, bool>, Pool> pools;
+  return pools[{dev, host}];
+}
+void pool_drop(void* p, bool host) {
+  if (host) (void)hipHostFree(p);
+  else (void)hipFree(p);
+}
+}  // namespace
+
+void* pool_take(size_t* bytes, bool host, int dev) {
+  Pool& pl = pool_of(host, dev);
+  if (!pl.pending.empty()) {
+    (void)hipDeviceSynchronize();   // every block released so far is idle after this (dev is current)
+    for (auto& e : pl.pending) {
+      pl.free.emplace(e.second, e.first);
+      pl.total += e.second;
+    }
+    pl.pending.clear();
+    while (pl.total > POOL_CAP && !pl.free.empty()) {   // the largest go first
+      auto it = std::prev(pl.free.end());
+      pl.total -= it->first;
+      pool_drop(it->second, host);
+      pl.free.erase(it);
+    }
+  }
+  // the smallest block that fits, if it wastes at most half of itself
+  auto it = pl.free.lower_bound(*bytes);
+  if (it == pl.free.end() || it->first > 2 * *bytes + 4096) return nullptr;
+  void* p = it->second;
+  *bytes = it->first;
+  pl.total -= it->first;
+  pl.free.erase(it);
+  return p;
+}
+
+void pool_give(void* p, size_t bytes, bool host, int dev) { pool_of(host, dev).pending.emplace_back(p, bytes); }
+
+template <bool HOST>
+tt_status WBuf<HOST>::alloc(size_t nbytes) {
+  if (nbytes <= bytes && p) return TTK_OK;
+  release();   // (to the pool: the next take synchronises before reusing it)
+  if (nbytes == 0) nbytes = 16;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(TTK_ERR_HIP, "no current device");
+  }
+  size_t got = nbytes;
+  if (void* q = pool_take(&got, HOST, dev)) {
+    p = q;
+    bytes = got;
+    return TTK_OK;
+  }
+  const hipError_t e = HOST ? hipHostMalloc(&p, nbytes, hipHostMallocDefault) : hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    return fail(TTK_ERR_OOM, "%s allocation of %zu bytes failed", HOST ? "pinned host" : "device", nbytes);
+  }
+  bytes = nbytes;
+  return TTK_OK;
+}
+template struct WBuf<false>;
+template struct WBuf<true>;
 
 tt_status HBuf::alloc(size_t nbytes) {
   if (nbytes <= bytes && p) return TTK_OK;
@@ -206,15 +279,20 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
   TTK_HIP(hipMemcpyAsync(h->dct.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, st));
   const double* Cs = h->dct.as<double>();
   const double* Cp = Cs + (size_t)ns_ * ns_;
-  size_t maxc = 1;
-  for (int k = 0; k < D; ++k) maxc = std::max(maxc, h->cores[k].size());
-  TTK_TRY(h->gtmp.alloc(maxc * sizeof(double)));
+  // all cores in one upload, each at its own offset of the staging buffer
+  std::vector<size_t> off(D + 1, 0);
+  for (int k = 0; k < D; ++k) off[k + 1] = off[k] + (size_t)h->ranks[k] * h->g.n[k] * h->ranks[k + 1];
+  std::vector<double> all(std::max<size_t>(off[D], 1));
+  for (int k = 0; k < D; ++k)
+    std::copy(h->cores[k].begin(), h->cores[k].begin() + (off[k + 1] - off[k]), all.begin() + off[k]);
+  TTK_TRY(h->gtmp.alloc(all.size() * sizeof(double)));
+  TTK_HIP(hipMemcpyAsync(h->gtmp.p, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, st));
   ChainStage* src = h->src;
   ChainStage* tgt = h->tgt;
   for (int k = 0; k < D; ++k) {
     const int r0 = h->ranks[k], n = h->g.n[k], r1 = h->ranks[k + 1];
     const size_t cnt = (size_t)r0 * n * r1;
-    TTK_HIP(hipMemcpyAsync(h->gtmp.p, h->cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
+    const double* gk = h->gtmp.as<double>() + off[k];
     const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((cnt + 255) / 256, 4096));
     if (k < d || k >= d + dt) {
       const int mode = (k < d) ? 0 : 1;
@@ -222,11 +300,9 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
       DBuf& sb = h->stage[(k < d) ? si : 3 + si];
       TTK_TRY(sb.alloc(cnt * es));
       if (h->dtype == TTK_FP32)
-        hipLaunchKernelGGL(k_dct_core<float>, dim3(nb), dim3(256), 0, st, h->gtmp.as<double>(), r0, n, r1, Cs, mode,
-                           sb.as<float>());
+        hipLaunchKernelGGL(k_dct_core<float>, dim3(nb), dim3(256), 0, st, gk, r0, n, r1, Cs, mode, sb.as<float>());
       else
-        hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, h->gtmp.as<double>(), r0, n, r1, Cs, mode,
-                           sb.as<double>());
+        hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, gk, r0, n, r1, Cs, mode, sb.as<double>());
       ChainStage& cs = (k < d) ? src[si] : tgt[si];
       cs.G2 = sb.p;
       cs.n = n;
@@ -237,13 +313,12 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
     } else {
       const int j = k - d;
       TTK_TRY(h->pcore[j].alloc(cnt * sizeof(double)));
-      hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, h->gtmp.as<double>(), r0, n, r1, Cp, 2,
+      hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, gk, r0, n, r1, Cp, 2,
                          h->pcore[j].as<double>());
       h->pc[j] = ParamCore{h->pcore[j].as<double>(), r0, n, r1, h->g.lo[k], h->g.hi[k]};
     }
-    // the staging buffer is overwritten by the next core
-    TTK_HIP(hipStreamSynchronize(st));
   }
+  TTK_HIP(hipStreamSynchronize(st));   // (Phase 3 is timed on its own below)
   h->rs = h->ranks[d];
   h->rt = h->ranks[d + dt];
   h->ldu = h->rs;

@@ -1127,8 +1127,18 @@ class Cross {
     uint32_t seq = 0;                   // mailbox sequence number of its finishing kernel
   };
   HostStep hs_[MAXD];
-  DBuf d_sel_;   // int32 [MAXD + 1]: variant selector of step k at k (k >= 2); 0 stays 0
+  WDBuf d_sel_;   // int32 [MAXD + 1]: variant selector of step k at k (k >= 2); 0 stays 0
   int max_rank() const { return std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR); }
+  // An upper bound of r_j: the rank cap, and the number of distinct index
+  // tuples on either side (I^{<=j} holds j-tuples, I^{>j} (N-j)-tuples).
+  int rank_cap(int j) const {
+    if (j == 0 || j == N_) return 1;
+    int64_t a = 1, b = 1;
+    for (int i = 0; i < j && a < MAXR; ++i) a *= g_.n[i];
+    for (int i = j; i < N_ && b < MAXR; ++i) b *= g_.n[i];
+    return (int)std::min<int64_t>({(int64_t)max_rank(), a, b});
+  }
+  tt_status reserve_buffers();
   tt_status prepare_step(HostStep& h, int k, int sweep, bool speculate);
   tt_status enqueue_front(const HostStep& h);
   tt_status enqueue_finish(HostStep& h, const HostStep* next);
@@ -1152,7 +1162,7 @@ class Cross {
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
   // Working buffers that follow the growing ranks: grown by at least half
   // their size at a time, so that the (synchronising) reallocations are few.
-  tt_status ensure(DBuf& b, size_t bytes) {
+  tt_status ensure(WDBuf& b, size_t bytes) {
     if (bytes <= b.bytes && b.p) return TTK_OK;
     return b.alloc(std::max(bytes, b.bytes + b.bytes / 2));
   }
@@ -1167,14 +1177,14 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_res_, d_R_, d_x_;
-  DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
+  WDBuf d_left_, d_right_, d_res_, d_R_, d_x_;
+  WDBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
-  DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
+  WDBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
-  HBuf h_stage_, h_res_;
+  WHBuf h_stage_, h_res_;
   HostMail mail_;
   uint32_t mail_seq_ = 0;
   tt_status wait_mail(int slot, uint32_t seq);
@@ -1184,8 +1194,8 @@ class Cross {
   // can be staged while the previous one and its stopping test still read
   // their own uploads.  An arena is reset only once its readers have drained.
   static constexpr int NAR = 3, AR_OTHER = 2;
-  HBuf ar_h_[NAR];
-  DBuf ar_d_[NAR];
+  WHBuf ar_h_[NAR];
+  WDBuf ar_d_[NAR];
   size_t ar_off_[NAR] = {0, 0, 0}, ar_flushed_[NAR] = {0, 0, 0}, ar_cap_ = 0;
   int ar_ = AR_OTHER;   // the arena in use
   const int16_t* cur_left_ = nullptr;
@@ -1435,6 +1445,25 @@ tt_status Cross::init_inverses() {
     TTK_TRY(sync());   // the arena is reused by the next k
   }
   TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+// The buffers whose size follows the ranks (the stopping test's fibres and
+// cores, the products of solve_right and refine_cores), reserved once at the
+// largest size the rank bounds allow: growing one later would reallocate it,
+// and a reallocation waits for all queued work, which would drain a queued
+// sweep.
+tt_status Cross::reserve_buffers() {
+  size_t cmax = 16;
+  for (int k = 1; k <= N_; ++k) {
+    const size_t c = (size_t)rank_cap(k - 1) * g_.n[k - 1] * rank_cap(k) * sizeof(double);
+    TTK_TRY(ensure(d_core_[k - 1], c));
+    if (k < N_) TTK_TRY(ensure(d_cint_[k - 1], c));
+    cmax = std::max(cmax, c);
+  }
+  TTK_TRY(ensure(d_E_, cmax));
+  TTK_TRY(ensure(d_ref_, 2 * cmax));
+  TTK_TRY(ensure(d_P_, (size_t)MAXR * MAXR * sizeof(double)));
   return TTK_OK;
 }
 
@@ -1795,8 +1824,8 @@ tt_status Cross::refine_cores() {
     TTK_TRY(arena_flush());
     const double* F = d_core_[k - 1].as<double>();
     double* C = d_cint_[k - 1].as<double>();
-    TTK_TRY(d_P_.alloc((size_t)r * r * sizeof(double)));
-    TTK_TRY(d_ref_.alloc((size_t)2 * m * r * sizeof(double)));
+    TTK_TRY(ensure(d_P_, (size_t)r * r * sizeof(double)));
+    TTK_TRY(ensure(d_ref_, (size_t)2 * m * r * sizeof(double)));
     double* P = d_P_.as<double>();
     double* E = d_ref_.as<double>();
     double* T = E + (size_t)m * r;
@@ -1855,6 +1884,7 @@ tt_status Cross::run(CrossOut* out) {
   TTK_TRY(d_luaux_.alloc(MAXD * (sizeof(double) + sizeof(int32_t))));
   fill_zero(d_luaux_.p, MAXD * (sizeof(double) + sizeof(int32_t)), st_);
   TTK_TRY(init_sets());
+  TTK_TRY(reserve_buffers());
   TTK_TRY(init_inverses());
   // fixed test multi-indices of the stopping rule
   int nmax = 0;
@@ -1928,7 +1958,7 @@ tt_status Cross::run(CrossOut* out) {
     const size_t cnt = (size_t)r0 * n * r1;
     // column-major C_k ((r0 n) x r1) is the little-endian core layout itself
     out->cores[k - 1].resize(cnt);
-    const DBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
+    const WDBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
     TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), src.p, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
   }
   TTK_TRY(sync());

@@ -73,6 +73,42 @@ struct HBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Workspace memory of one library call (the cross, the rounding): device or
+// pinned host memory that goes back to a per-thread pool when released, so
+// that the next call on the same thread and device takes it instead of
+// allocating.  A released block waits in the pool until the next take, which
+// first synchronises the device once for all blocks released since the last
+// one, so a block handed out is never still read or written by queued work,
+// whatever stream that work is on.  The pool keeps at most 1 GiB per device
+// and kind.
+// a block of at least *bytes for device dev (its size back in *bytes), or nullptr
+void* pool_take(size_t* bytes, bool host, int dev);
+void pool_give(void* p, size_t bytes, bool host, int dev);
+template <bool HOST>
+struct WBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int dev = 0;   // the device current when it was allocated (its pool)
+  WBuf() = default;
+  WBuf(const WBuf&) = delete;
+  WBuf& operator=(const WBuf&) = delete;
+  WBuf(WBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) { o.p = nullptr; o.bytes = 0; }
+  WBuf& operator=(WBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; dev = o.dev;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~WBuf() { release(); }
+  void release() { if (p) pool_give(p, bytes, HOST, dev); p = nullptr; bytes = 0; }
+  tt_status alloc(size_t nbytes);          // grows only; contents undefined
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+using WDBuf = WBuf<false>;
+using WHBuf = WBuf<true>;
+
 // ---------------------------------------------------------------- problem
 struct Grid {
   int d = 0, dt = 0, D = 0;

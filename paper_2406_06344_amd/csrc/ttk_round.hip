@@ -84,7 +84,7 @@ __global__ void k_pad_rows(const double* S, int rows, int lds, double* C, int mc
 inline int nb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 struct Cores {
-  std::vector<DBuf> g;        // device copies, core k as G^{2}/G^{1}-compatible memory
+  std::vector<WDBuf> g;       // device copies, core k as G^{2}/G^{1}-compatible memory
   std::vector<int> r;         // r_0..r_D
   std::vector<int> n;
 };
@@ -94,7 +94,7 @@ struct Cores {
 // padded with zero rows to r0 x r0, whose Householder QR leaves the padding
 // untouched (every reflector vanishes there), so the leading n r1 x n r1
 // block of Q and the leading n r1 rows of R are the thin factors.
-tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipStream_t st) {
+tt_status orth_right(Cores& c, int i, WDBuf& A, WDBuf& R, WDBuf& T, WDBuf& tau, hipStream_t st) {
   const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
   const int m = n * r1;
   const int ma = std::max(m, r0);   // rows of the (padded) QR input
@@ -134,7 +134,24 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     TTK_TRY(c.g[k].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
     TTK_HIP(hipMemcpyAsync(c.g[k].p, cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  DBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
+  WDBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
+  {
+    // every work buffer at the largest size any step needs (the ranks only
+    // fall from here), so that none is reallocated, which would wait for the
+    // queued work, between the steps
+    int rmax = 1, nmax = 1;
+    for (int k = 0; k <= D; ++k) rmax = std::max(rmax, c.r[k]);
+    for (int k = 0; k < D; ++k) nmax = std::max(nmax, c.n[k]);
+    const size_t big = (size_t)rmax * rmax * nmax * sizeof(double), sq = (size_t)rmax * rmax * sizeof(double);
+    TTK_TRY(A.alloc(big));
+    TTK_TRY(T.alloc(big));
+    TTK_TRY(Cw.alloc(big));
+    TTK_TRY(R.alloc(sq));
+    TTK_TRY(V.alloc(sq));
+    TTK_TRY(W.alloc(sq));
+    TTK_TRY(sig.alloc(sq + (3 * (size_t)rmax + 64) * sizeof(double)));
+    TTK_TRY(tau.alloc(qr_blocked_work(rmax * nmax, rmax) * sizeof(double)));
+  }
   // right-to-left orthogonalisation
   for (int i = D - 1; i >= 1; --i) TTK_TRY(orth_right(c, i, A, R, T, tau, st));
   TTK_TRY(nrm.alloc(sizeof(double)));
