@@ -37,21 +37,6 @@ tt_status fail(tt_status s, const char* fmt, ...) {
   return s;
 }
 
-tt_status DBuf::alloc(size_t nbytes) {
-  if (nbytes <= bytes && p) return TTK_OK;
-  // work queued earlier may still read the old buffer
-  if (p) (void)hipDeviceSynchronize();
-  release();
-  if (nbytes == 0) nbytes = 16;
-  if (hipMalloc(&p, nbytes) != hipSuccess) {
-    p = nullptr;
-    (void)hipGetLastError();
-    return fail(TTK_ERR_OOM, "device allocation of %zu bytes failed", nbytes);
-  }
-  bytes = nbytes;
-  return TTK_OK;
-}
-
 namespace {
 struct Pool {
   std::multimap<size_t, void*> free;   // idle blocks by size
@@ -97,8 +82,22 @@ void* pool_take(size_t* bytes, bool host, int dev) {
 
 void pool_give(void* p, size_t bytes, bool host, int dev) { pool_of(host, dev).pending.emplace_back(p, bytes); }
 
+namespace {
+// Frees every block of the pool (after the synchronisation that makes the
+// released ones idle), so that an allocation that failed can be retried.
+void pool_trim(bool host, int dev) {
+  Pool& pl = pool_of(host, dev);
+  if (!pl.pending.empty()) (void)hipDeviceSynchronize();
+  for (auto& e : pl.pending) pool_drop(e.first, host);
+  for (auto& e : pl.free) pool_drop(e.second, host);
+  pl.pending.clear();
+  pl.free.clear();
+  pl.total = 0;
+}
+}  // namespace
+
 template <bool HOST>
-tt_status WBuf<HOST>::alloc(size_t nbytes) {
+tt_status Buf<HOST>::alloc(size_t nbytes) {
   if (nbytes <= bytes && p) return TTK_OK;
   release();   // (to the pool: the next take synchronises before reusing it)
   if (nbytes == 0) nbytes = 16;
@@ -112,32 +111,22 @@ tt_status WBuf<HOST>::alloc(size_t nbytes) {
     bytes = got;
     return TTK_OK;
   }
-  const hipError_t e = HOST ? hipHostMalloc(&p, nbytes, hipHostMallocDefault) : hipMalloc(&p, nbytes);
-  if (e != hipSuccess) {
-    p = nullptr;
+  auto get = [&] { return HOST ? hipHostMalloc(&p, nbytes, hipHostMallocDefault) : hipMalloc(&p, nbytes); };
+  if (get() != hipSuccess) {   // the pool's idle blocks go back, then once more
     (void)hipGetLastError();
-    return fail(TTK_ERR_OOM, "%s allocation of %zu bytes failed", HOST ? "pinned host" : "device", nbytes);
+    pool_trim(HOST, dev);
+    if (get() != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(TTK_ERR_OOM, "%s allocation of %zu bytes failed", HOST ? "pinned host" : "device", nbytes);
+    }
   }
   bytes = nbytes;
   return TTK_OK;
 }
-template struct WBuf<false>;
-template struct WBuf<true>;
+template struct Buf<false>;
+template struct Buf<true>;
 
-tt_status HBuf::alloc(size_t nbytes) {
-  if (nbytes <= bytes && p) return TTK_OK;
-  if (p) (void)hipHostFree(p);
-  p = nullptr;
-  bytes = 0;
-  if (nbytes == 0) nbytes = 16;
-  if (hipHostMalloc(&p, nbytes, hipHostMallocDefault) != hipSuccess) {
-    p = nullptr;
-    (void)hipGetLastError();
-    return fail(TTK_ERR_OOM, "pinned host allocation of %zu bytes failed", nbytes);
-  }
-  bytes = nbytes;
-  return TTK_OK;
-}
 
 static int kind_dtheta(int kind) {
   switch (kind) {

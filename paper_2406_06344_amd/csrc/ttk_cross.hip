@@ -1127,7 +1127,7 @@ class Cross {
     uint32_t seq = 0;                   // mailbox sequence number of its finishing kernel
   };
   HostStep hs_[MAXD];
-  WDBuf d_sel_;   // int32 [MAXD + 1]: variant selector of step k at k (k >= 2); 0 stays 0
+  DBuf d_sel_;   // int32 [MAXD + 1]: variant selector of step k at k (k >= 2); 0 stays 0
   int max_rank() const { return std::min(P_.max_rank > 0 ? P_.max_rank : MAXR, MAXR); }
   // An upper bound of r_j: the rank cap, and the number of distinct index
   // tuples on either side (I^{<=j} holds j-tuples, I^{>j} (N-j)-tuples).
@@ -1162,7 +1162,7 @@ class Cross {
   Addr super_addr(int k) const;   // super-core k, k = 1..N-1
   // Working buffers that follow the growing ranks: grown by at least half
   // their size at a time, so that the (synchronising) reallocations are few.
-  tt_status ensure(WDBuf& b, size_t bytes) {
+  tt_status ensure(DBuf& b, size_t bytes) {
     if (bytes <= b.bytes && b.p) return TTK_OK;
     return b.alloc(std::max(bytes, b.bytes + b.bytes / 2));
   }
@@ -1177,14 +1177,14 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  WDBuf d_left_, d_right_, d_res_, d_R_, d_x_;
-  WDBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
+  DBuf d_left_, d_right_, d_res_, d_R_, d_x_;
+  DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
-  WDBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
+  DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
-  WHBuf h_stage_, h_res_;
+  HBuf h_stage_, h_res_;
   HostMail mail_;
   uint32_t mail_seq_ = 0;
   tt_status wait_mail(int slot, uint32_t seq);
@@ -1194,8 +1194,8 @@ class Cross {
   // can be staged while the previous one and its stopping test still read
   // their own uploads.  An arena is reset only once its readers have drained.
   static constexpr int NAR = 3, AR_OTHER = 2;
-  WHBuf ar_h_[NAR];
-  WDBuf ar_d_[NAR];
+  HBuf ar_h_[NAR];
+  DBuf ar_d_[NAR];
   size_t ar_off_[NAR] = {0, 0, 0}, ar_flushed_[NAR] = {0, 0, 0}, ar_cap_ = 0;
   int ar_ = AR_OTHER;   // the arena in use
   const int16_t* cur_left_ = nullptr;
@@ -1958,7 +1958,7 @@ tt_status Cross::run(CrossOut* out) {
     const size_t cnt = (size_t)r0 * n * r1;
     // column-major C_k ((r0 n) x r1) is the little-endian core layout itself
     out->cores[k - 1].resize(cnt);
-    const WDBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
+    const DBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
     TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), src.p, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
   }
   TTK_TRY(sync());

@@ -43,57 +43,28 @@ tt_status fail(tt_status s, const char* fmt, ...);
     if (s_ < 0) return s_;       \
   } while (0)
 
-// Owning device buffer.
-struct DBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  DBuf() = default;
-  DBuf(const DBuf&) = delete;
-  DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
-  DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
-    return *this;
-  }
-  ~DBuf() { release(); }
-  void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
-  tt_status alloc(size_t nbytes);          // grows only; contents undefined
-  template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
-// Pinned host staging buffer (allocated, never registered).
-struct HBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  HBuf() = default;
-  HBuf(const HBuf&) = delete;
-  HBuf& operator=(const HBuf&) = delete;
-  ~HBuf() { if (p) (void)hipHostFree(p); }
-  tt_status alloc(size_t nbytes);
-  template <class T> T* as() const { return static_cast<T*>(p); }
-};
-
-// Workspace memory of one library call (the cross, the rounding): device or
-// pinned host memory that goes back to a per-thread pool when released, so
-// that the next call on the same thread and device takes it instead of
-// allocating.  A released block waits in the pool until the next take, which
-// first synchronises the device once for all blocks released since the last
-// one, so a block handed out is never still read or written by queued work,
-// whatever stream that work is on.  The pool keeps at most 1 GiB per device
-// and kind.
+// Owning device buffer (DBuf) and pinned host staging buffer (HBuf,
+// allocated, never registered).  Released memory goes back to a per-thread
+// pool instead of being freed, and the next allocation on the same thread and
+// device takes it from there.  A released block waits in the pool until the
+// next take, which first synchronises the device once for all blocks
+// released since the last one, so a block handed out is never still read or
+// written by queued work, whatever stream that work is on.  The pool keeps
+// at most 1 GiB per thread, device and kind; beyond that the largest blocks
+// are freed.
 // a block of at least *bytes for device dev (its size back in *bytes), or nullptr
 void* pool_take(size_t* bytes, bool host, int dev);
 void pool_give(void* p, size_t bytes, bool host, int dev);
 template <bool HOST>
-struct WBuf {
+struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
   int dev = 0;   // the device current when it was allocated (its pool)
-  WBuf() = default;
-  WBuf(const WBuf&) = delete;
-  WBuf& operator=(const WBuf&) = delete;
-  WBuf(WBuf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) { o.p = nullptr; o.bytes = 0; }
-  WBuf& operator=(WBuf&& o) noexcept {
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : p(o.p), bytes(o.bytes), dev(o.dev) { o.p = nullptr; o.bytes = 0; }
+  Buf& operator=(Buf&& o) noexcept {
     if (this != &o) {
       release();
       p = o.p; bytes = o.bytes; dev = o.dev;
@@ -101,13 +72,13 @@ struct WBuf {
     }
     return *this;
   }
-  ~WBuf() { release(); }
+  ~Buf() { release(); }
   void release() { if (p) pool_give(p, bytes, HOST, dev); p = nullptr; bytes = 0; }
   tt_status alloc(size_t nbytes);          // grows only; contents undefined
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
-using WDBuf = WBuf<false>;
-using WHBuf = WBuf<true>;
+using DBuf = Buf<false>;
+using HBuf = Buf<true>;
 
 // ---------------------------------------------------------------- problem
 struct Grid {

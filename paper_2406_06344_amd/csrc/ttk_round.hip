@@ -84,7 +84,7 @@ __global__ void k_pad_rows(const double* S, int rows, int lds, double* C, int mc
 inline int nb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 struct Cores {
-  std::vector<WDBuf> g;       // device copies, core k as G^{2}/G^{1}-compatible memory
+  std::vector<DBuf> g;       // device copies, core k as G^{2}/G^{1}-compatible memory
   std::vector<int> r;         // r_0..r_D
   std::vector<int> n;
 };
@@ -94,7 +94,7 @@ struct Cores {
 // padded with zero rows to r0 x r0, whose Householder QR leaves the padding
 // untouched (every reflector vanishes there), so the leading n r1 x n r1
 // block of Q and the leading n r1 rows of R are the thin factors.
-tt_status orth_right(Cores& c, int i, WDBuf& A, WDBuf& R, WDBuf& T, WDBuf& tau, hipStream_t st) {
+tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipStream_t st) {
   const int r0 = c.r[i], n = c.n[i], r1 = c.r[i + 1];
   const int m = n * r1;
   const int ma = std::max(m, r0);   // rows of the (padded) QR input
@@ -134,7 +134,7 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
     TTK_TRY(c.g[k].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
     TTK_HIP(hipMemcpyAsync(c.g[k].p, cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  WDBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
+  DBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
   {
     // every work buffer at the largest size any step needs (the ranks only
     // fall from here), so that none is reallocated, which would wait for the
