@@ -1813,15 +1813,19 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
 // pivoted solve at the cost of three products per core.
 tt_status Cross::refine_cores() {
   const int N = N_;
+  // every core's pivot rows in one upload
+  arena_reset();
+  const int32_t* dIk[MAXD] = {nullptr};
+  for (int k = 1; k < N; ++k) {
+    std::vector<int32_t> I, J;
+    pivot_positions(k, &I, &J);
+    TTK_TRY(arena_push(I.data(), I.size(), &dIk[k]));
+  }
+  TTK_TRY(arena_flush());
   for (int k = 1; k < N; ++k) {
     const int r0 = rank(k - 1), r = rank(k), n = g_.n[k - 1];
     const int m = r0 * n;
-    std::vector<int32_t> I, J;
-    pivot_positions(k, &I, &J);
-    arena_reset();
-    const int32_t* dI = nullptr;
-    TTK_TRY(arena_push(I.data(), I.size(), &dI));
-    TTK_TRY(arena_flush());
+    const int32_t* dI = dIk[k];
     const double* F = d_core_[k - 1].as<double>();
     double* C = d_cint_[k - 1].as<double>();
     TTK_TRY(ensure(d_P_, (size_t)r * r * sizeof(double)));
@@ -1834,10 +1838,9 @@ tt_status Cross::refine_cores() {
     gemm64(0, 0, m, r, r, -1.0, C, m, P, r, 1.0, E, m, st_);
     gemm64(0, 0, m, r, r, 1.0, E, m, d_w_[k].as<double>(), MAXR, 0.0, T, m, st_);
     gemm64(0, 0, m, r, r, 1.0, T, m, d_li_[k].as<double>(), MAXR, 1.0, C, m, st_);
-    TTK_TRY(sync());   // the arena is reused by the next k
   }
   TTK_HIP(hipGetLastError());
-  return TTK_OK;
+  return sync();   // the arena's host side is reused after this
 }
 
 // The stopping test: the cores by the interpolation formula, the TT at the

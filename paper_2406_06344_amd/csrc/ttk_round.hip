@@ -115,8 +115,7 @@ tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipS
   gemm64(0, 1, q0 * qn, rp, r0, 1.0, c.g[i - 1].as<double>(), q0 * qn, R.as<double>(), r0, 0.0, T.as<double>(),
          q0 * qn, st);
   TTK_HIP(hipMemcpyAsync(c.g[i - 1].p, T.p, (size_t)q0 * qn * rp * sizeof(double), hipMemcpyDeviceToDevice, st));
-  c.r[i] = rp;
-  TTK_HIP(hipStreamSynchronize(st));   // A, R, T are resized by the next call
+  c.r[i] = rp;   // (the work buffers are reserved at their largest size: nothing to wait for)
   return TTK_OK;
 }
 
