@@ -45,8 +45,9 @@ struct Pool {
 };
 constexpr size_t POOL_CAP = (size_t)1 << 30;
 Pool& pool_of(bool host, int dev) {
-  thread_local std::map<std::pair<int, bool>, Pool> pools;
-  return pools[{dev, host}];
+  // never destroyed: a buffer released while the process exits still finds it
+  thread_local auto* pools = new std::map<std::pair<int, bool>, Pool>();
+  return (*pools)[{dev, host}];
 }
 void pool_drop(void* p, bool host) {
   if (host) (void)hipHostFree(p);
