@@ -104,14 +104,12 @@ __global__ void k_absmax(const double* a, int na, const double* b, int nb, const
   if (threadIdx.x == 0) *out = base ? fmax(*base, red[0]) : red[0];
 }
 
-// 2-norm condition numbers of the 2x2 probes of the index initialisation.
-// F (2-row-set fibre, (rl*n) x rr col-major) holds phi(left_s, j, right_t).
+// 2-norm condition number of the 2x2 probe e = j1 n + j2 of the index
+// initialisation.  F (2-row-set fibre, (rl*n) x rr col-major) holds
+// phi(left_s, j, right_t).
 // mode 0 (left-to-right): M = [[F(a,j1,c), F(a,j1,c')], [F(b,j2,c), F(b,j2,c')]]
 // mode 1 (right-to-left): M = [[F(a,j1,c), F(a,j2,c')], [F(b,j1,c), F(b,j2,c')]]
-__global__ void k_init_cond(const double* F, int rl, int rr, int n, int mode, int excl_diag,
-                            double* cond) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * n) return;
+__device__ inline double init_cond_at(const double* F, int rl, int rr, int n, int mode, int excl_diag, int e) {
   const int j1 = e / n, j2 = e % n;   // linear position j1 * n + j2
   const int m = rl * n;
   const int sa = 0, sb = rl > 1 ? 1 : 0;
@@ -131,39 +129,7 @@ __global__ void k_init_cond(const double* F, int rl, int rr, int n, int mode, in
   double cv = (s2 > 0.0) ? s1 / s2 : INFINITY;
   if (!(cv == cv)) cv = INFINITY;
   if (excl_diag && j1 == j2) cv = INFINITY;
-  cond[e] = cv;
-}
-
-// Lowest position within a relative band 1e-12 of the minimum (excluded
-// entries are +inf; if all are +inf, the lowest allowed position).
-__global__ void k_select_min(const double* v, int n, int excl_diag, int nn, int32_t* out_pos,
-                             double* out_val) {
-  __shared__ double sv[1024];
-  __shared__ int si[1024];
-  const int tid = threadIdx.x;
-  double m = INFINITY;
-  for (int i = tid; i < n; i += blockDim.x) m = fmin(m, v[i]);
-  sv[tid] = m;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) sv[tid] = fmin(sv[tid], sv[tid + s]);
-    __syncthreads();
-  }
-  const double mn = sv[0];
-  __syncthreads();
-  int pos = 0x7fffffff;
-  for (int i = tid; i < n; i += blockDim.x) {
-    const bool allowed = !(excl_diag && (i / nn) == (i % nn));
-    if (!allowed) continue;
-    if (isinf(mn) ? true : (v[i] <= mn * (1.0 + 1e-12))) { pos = i; break; }
-  }
-  si[tid] = pos;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (tid < s) si[tid] = min(si[tid], si[tid + s]);
-    __syncthreads();
-  }
-  if (tid == 0) { *out_pos = si[0]; *out_val = v[si[0]]; }
+  return cv;
 }
 
 // P[a + b*r] = F[rows[a] + b*ldf]  (rows of F at the given positions)
@@ -180,6 +146,131 @@ __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, i
   if (e >= (int64_t)m * n) return;
   const int i = (int)(e % m), j = (int)(e / m);
   B[j + (int64_t)i * ldb] = A[i + (int64_t)j * lda];
+}
+
+// The index initialisation in one block: max_it passes of 2-row probes,
+// left to right (k = 1..N-1, the new rows of I^{<=k}) then right to left
+// (k = N..2, the new rows of I^{>k-1}), each probe evaluating its fibre,
+// the condition numbers of all n^2 candidate 2x2 submatrices and the lowest
+// position within a relative band 1e-12 of the smallest (positions with
+// j1 = j2 excluded where one side has a single row; if every candidate is
+// +inf, the lowest allowed one).  The sets live in LDS (int16, row-major
+// like the upload arena), and after every pass they and the pass's largest
+// chosen condition number go to snapshot slot 2 it + pass:
+//   snap[slot * INIT_SNAP + k * 2 MAXD + e]            rows of I^{<=k} (2 k entries),
+//   snap[slot * INIT_SNAP + (MAXD + k) * 2 MAXD + e]   rows of I^{>k} (2 (N - k) entries).
+struct InitArgs {
+  int N, max_it;
+  int n[MAXD];
+  int32_t q1[MAXD], q2[MAXD];   // the two random points the right sets start from
+};
+constexpr int INIT_SNAP = 4 * MAXD * MAXD;
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(1024) k_init_sets(KSpec ks, InitArgs ia, int32_t* snap, double* snap_mc) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN], F[2 * MAXN * 2], sv[1024];
+  __shared__ int si[1024];
+  __shared__ int16_t Ls[MAXD][2 * MAXD], Rs[MAXD + 1][2 * MAXD];
+  const int tid = threadIdx.x, N = ia.N;
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  if (tid == 0)
+    for (int k = 1; k < N; ++k) {
+      const int len = N - k;
+      for (int j = 0; j < len; ++j) {
+        Rs[k][j] = (int16_t)ia.q1[k + j];
+        Rs[k][len + j] = (int16_t)ia.q2[k + j];
+      }
+    }
+  __syncthreads();
+  // one probe: kl = k - 1 left rows, kr = k right rows; the chosen (j1, j2) and its condition number
+  auto probe = [&](int k, int mode, int* j1, int* j2, double* cv) {
+    const int n = ia.n[k - 1];
+    Addr a{};
+    a.left = Ls[k - 1];
+    a.right = Rs[k];
+    a.rl = (k - 1 == 0) ? 1 : 2;
+    a.lk = k - 1;
+    a.rr = (k == N) ? 1 : 2;
+    a.lr = N - k;
+    a.nmid = 1;
+    a.nm0 = n;
+    a.nm1 = 1;
+    const int m = a.rl * n;
+    for (int e = tid; e < m * a.rr; e += 1024) F[e] = addr_eval<d, dt, G>(ks, a, sn, e % m, e / m);
+    __syncthreads();
+    const int excl = (mode == 0) ? (k == 1) : (k == N);
+    const int nn = n * n;
+    const double v = tid < nn ? init_cond_at(F, a.rl, a.rr, n, mode, excl, tid) : INFINITY;
+    sv[tid] = v;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+      if (tid < h) sv[tid] = fmin(sv[tid], sv[tid + h]);
+      __syncthreads();
+    }
+    const double mn = sv[0];
+    int pos = 0x7fffffff;
+    if (tid < nn && !(excl && tid / n == tid % n) && (isinf(mn) || v <= mn * (1.0 + 1e-12))) pos = tid;
+    si[tid] = pos;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+      if (tid < h) si[tid] = min(si[tid], si[tid + h]);
+      __syncthreads();
+    }
+    const int p = si[0] == 0x7fffffff ? 0 : si[0];   // (n >= 2 always leaves an allowed position)
+    *j1 = p / n;
+    *j2 = p % n;
+    if (tid == p) sv[0] = v;   // (every thread has read sv[0] before the second reduction)
+    __syncthreads();
+    *cv = sv[0];
+    __syncthreads();   // sv, si and F are reused by the next probe
+  };
+  auto snapshot = [&](int slot, double mc) {
+    int32_t* o = snap + (size_t)slot * INIT_SNAP;
+    for (int e = tid; e < MAXD * 2 * MAXD; e += 1024) {
+      const int k = e / (2 * MAXD), j = e % (2 * MAXD);
+      o[e] = (k >= 1 && k < N && j < 2 * k) ? Ls[k][j] : 0;
+      o[MAXD * 2 * MAXD + e] = (k >= 1 && k < N && j < 2 * (N - k)) ? Rs[k][j] : 0;
+    }
+    if (tid == 0) snap_mc[slot] = mc;
+  };
+  for (int it = 0; it < ia.max_it; ++it) {
+    double mc = 0.0;
+    for (int k = 1; k < N; ++k) {   // left to right: I^{<=k} = (I^{<=k-1} row 0, j1), (row 1, j2)
+      int j1, j2;
+      double cv;
+      probe(k, 0, &j1, &j2, &cv);
+      mc = fmax(mc, cv);
+      if (tid == 0) {
+        const int len = k - 1;
+        for (int j = 0; j < len; ++j) {
+          Ls[k][j] = Ls[k - 1][j];
+          Ls[k][k + j] = Ls[k - 1][len + j];
+        }
+        Ls[k][len] = (int16_t)j1;
+        Ls[k][k + len] = (int16_t)j2;
+      }
+      __syncthreads();
+    }
+    snapshot(2 * it, mc);
+    mc = 0.0;
+    for (int k = N; k >= 2; --k) {   // right to left: I^{>k-1} = (j1, I^{>k} row 0), (j2, row 1)
+      int j1, j2;
+      double cv;
+      probe(k, 1, &j1, &j2, &cv);
+      mc = fmax(mc, cv);
+      if (tid == 0) {
+        const int len = N - k;
+        Rs[k - 1][0] = (int16_t)j1;
+        Rs[k - 1][len + 1] = (int16_t)j2;
+        for (int j = 0; j < len; ++j) {
+          Rs[k - 1][1 + j] = Rs[k][j];
+          Rs[k - 1][len + 2 + j] = Rs[k][len + j];
+        }
+      }
+      __syncthreads();
+    }
+    snapshot(2 * it + 1, mc);
+  }
 }
 
 // TT value at test multi-indices: cores given column-major C_k
@@ -1177,14 +1268,13 @@ class Cross {
   double min_margin_ = 1.0;
 
   // device buffers
-  DBuf d_left_, d_right_, d_res_, d_R_, d_x_;
-  DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_fib_, d_tmp_, d_P_, d_err_, d_ref_;
+  DBuf d_res_, d_R_, d_x_;
+  DBuf d_test_idx_, d_test_val_, d_core_[MAXD], d_cint_[MAXD], d_P_, d_err_, d_ref_;
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
   DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
-  HBuf h_stage_, h_res_;
   HostMail mail_;
   uint32_t mail_seq_ = 0;
   tt_status wait_mail(int slot, uint32_t seq);
@@ -1290,85 +1380,48 @@ tt_status Cross::init_sets() {
   std::vector<int32_t> q1(N), q2(N);
   for (int j = 0; j < N; ++j) q1[j] = (int32_t)g.below((uint64_t)g_.n[j]);
   for (int j = 0; j < N; ++j) q2[j] = (int32_t)g.below((uint64_t)g_.n[j]);
-  for (int k = 1; k < N; ++k) {
-    R_[k].assign(q1.begin() + k, q1.end());
-    R_[k].insert(R_[k].end(), q2.begin() + k, q2.end());
+  // the probes run in one launch (k_init_sets); the host reads the snapshots
+  const int max_it = P_.init_max_it > 0 ? P_.init_max_it : 10;
+  InitArgs ia{};
+  ia.N = N;
+  ia.max_it = max_it;
+  for (int j = 0; j < N; ++j) {
+    ia.n[j] = g_.n[j];
+    ia.q1[j] = q1[j];
+    ia.q2[j] = q2[j];
+  }
+  const int nsnap = 2 * max_it;
+  DBuf d_snap;
+  TTK_TRY(d_snap.alloc((size_t)nsnap * (INIT_SNAP * sizeof(int32_t) + sizeof(double))));
+  int32_t* dsnap = d_snap.as<int32_t>();
+  double* dmc = reinterpret_cast<double*>(dsnap + (size_t)nsnap * INIT_SNAP);
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_init_sets<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
+                       dim3(1024), 0, st_, ks_, ia, dsnap, dmc);
+  });
+  TTK_HIP(hipGetLastError());
+  std::vector<int32_t> hsnap((size_t)nsnap * INIT_SNAP);
+  std::vector<double> hmc(nsnap);
+  TTK_HIP(hipMemcpyAsync(hsnap.data(), dsnap, hsnap.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+  TTK_HIP(hipMemcpyAsync(hmc.data(), dmc, hmc.size() * sizeof(double), hipMemcpyDeviceToHost, st_));
+  TTK_TRY(sync());
+  // the kernel entries the probes evaluated: (rows of I^{<=k-1}) n_k (rows of I^{>k}) each
+  for (int it = 0; it < max_it; ++it) {
+    for (int k = 1; k < N; ++k) evals_ += (int64_t)(k == 1 ? 1 : 2) * g_.n[k - 1] * 2;
+    for (int k = N; k >= 2; --k) evals_ += (int64_t)2 * g_.n[k - 1] * (k == N ? 1 : 2);
   }
   struct Snap { std::vector<std::vector<int32_t>> L, R; double maxc; };
-  std::vector<Snap> snaps;
-  TTK_TRY(d_left_.alloc(2 * MAXD * sizeof(int16_t)));
-  TTK_TRY(d_right_.alloc(2 * MAXD * sizeof(int16_t)));
-  TTK_TRY(d_fib_.alloc(2 * MAXN * 2 * sizeof(double)));
-  TTK_TRY(d_tmp_.alloc(MAXN * MAXN * sizeof(double) + 64));
-  TTK_TRY(d_res_.alloc(sizeof(StepRes)));
-  TTK_TRY(h_res_.alloc(sizeof(StepRes)));
-  double* cond = d_tmp_.as<double>();
-  int32_t* dpos = reinterpret_cast<int32_t*>(d_res_.as<char>());
-  double* dval = reinterpret_cast<double*>(d_res_.as<char>() + 8);
-  auto probe = [&](int k, int mode, int kl, int kr, int* j1, int* j2, double* cv) -> tt_status {
-    // two-row sets I^{<=kl} (kl = k-1) and I^{>kr} (kr = k): fibre of dimension k-1
-    arena_reset();
-    TTK_TRY(upload_sets(kl, kr, nullptr, nullptr));
-    TTK_TRY(arena_flush());
-    Addr a{};
-    a.left = cur_left_;
-    a.right = cur_right_;
-    a.rl = (kl == 0) ? 1 : 2;
-    a.lk = kl;
-    a.rr = (kr == N) ? 1 : 2;
-    a.lr = N - kr;
-    a.nmid = 1;
-    a.nm0 = g_.n[k - 1];
-    a.nm1 = 1;
-    const int n = g_.n[k - 1];
-    eval_product(ks_, a, nullptr, a.rl * n, nullptr, a.rr, d_fib_.as<double>(), st_);
-    evals_ += (int64_t)a.rl * n * a.rr;
-    const int excl = (mode == 0) ? (k == 1) : (k == N);
-    hipLaunchKernelGGL(k_init_cond, dim3(nblk(n * n, 256)), dim3(256), 0, st_, d_fib_.as<double>(), a.rl,
-                       a.rr, n, mode, excl, cond);
-    hipLaunchKernelGGL(k_select_min, dim3(1), dim3(1024), 0, st_, cond, n * n, excl, n, dpos, dval);
-    TTK_HIP(hipMemcpyAsync(h_res_.p, d_res_.p, 16, hipMemcpyDeviceToHost, st_));
-    TTK_TRY(sync());
-    const int pos = *h_res_.as<int32_t>();
-    *cv = *reinterpret_cast<double*>(h_res_.as<char>() + 8);
-    *j1 = pos / n;
-    *j2 = pos % n;
-    return TTK_OK;
-  };
-  const int max_it = P_.init_max_it > 0 ? P_.init_max_it : 10;
-  for (int it = 0; it < max_it; ++it) {
-    double mc = 0.0;
-    for (int k = 1; k < N; ++k) {            // left to right
-      int j1, j2;
-      double cv;
-      TTK_TRY(probe(k, 0, k - 1, k, &j1, &j2, &cv));
-      mc = std::max(mc, cv);
-      std::vector<int32_t> nl;
-      const std::vector<int32_t> emp;
-      const std::vector<int32_t>& prev = (k > 1) ? L_[k - 1] : emp;
-      const int len = k - 1;
-      nl.insert(nl.end(), prev.begin(), prev.begin() + len);
-      nl.push_back(j1);
-      nl.insert(nl.end(), prev.begin() + (k > 1 ? len : 0), prev.begin() + (k > 1 ? 2 * len : 0));
-      nl.push_back(j2);
-      L_[k] = nl;
+  std::vector<Snap> snaps(nsnap);
+  for (int sI = 0; sI < nsnap; ++sI) {
+    const int32_t* o = hsnap.data() + (size_t)sI * INIT_SNAP;
+    Snap& sp = snaps[sI];
+    sp.L.assign(N + 1, {});
+    sp.R.assign(N + 1, {});
+    for (int k = 1; k < N; ++k) {
+      sp.L[k].assign(o + k * 2 * MAXD, o + k * 2 * MAXD + 2 * k);
+      sp.R[k].assign(o + (MAXD + k) * 2 * MAXD, o + (MAXD + k) * 2 * MAXD + 2 * (N - k));
     }
-    snaps.push_back({L_, R_, mc});
-    mc = 0.0;
-    for (int k = N; k >= 2; --k) {           // right to left
-      int j1, j2;
-      double cv;
-      TTK_TRY(probe(k, 1, k - 1, k, &j1, &j2, &cv));
-      mc = std::max(mc, cv);
-      const int len = N - k;
-      std::vector<int32_t> nr;
-      nr.push_back(j1);
-      if (k < N) nr.insert(nr.end(), R_[k].begin(), R_[k].begin() + len);
-      nr.push_back(j2);
-      if (k < N) nr.insert(nr.end(), R_[k].begin() + len, R_[k].begin() + 2 * len);
-      R_[k - 1] = nr;
-    }
-    snaps.push_back({L_, R_, mc});
+    sp.maxc = hmc[sI];
   }
   // smallest maximum condition number, earliest within a relative band
   double best = INFINITY;
