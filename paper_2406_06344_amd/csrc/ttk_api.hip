@@ -231,12 +231,13 @@ struct tt_kernel {
   int dtype = TTK_FP32;
   size_t es = 4;
   std::vector<int> ranks, cross_ranks;
-  std::vector<std::vector<double>> cores;
+  std::vector<std::vector<double>> cores;   // host copy (read back on request for a device build)
+  std::vector<DBuf> dcores;                 // the rounded cores on the device
   CrossOut cross;
   tt_kernel_info info{};
   int64_t ns = 0, nt = 0;
   int rs = 0, rt = 0, ldu = 0, ldv = 0;
-  DBuf U, V, nodes, dct, stage[6], pcore[2], gtmp;
+  DBuf U, V, nodes, dct, stage[6], pcore[2];
   DBuf work, Mbuf, dMbuf, Wbuf, Zbuf, Abuf, Pbuf;   // Pbuf: partial sums of the reduces
   // Global-1 (Algorithm 4): Q (N x kg row-major, dtype), R (kg x kg FP64)
   int kg = 0;
@@ -269,20 +270,12 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
   TTK_HIP(hipMemcpyAsync(h->dct.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, st));
   const double* Cs = h->dct.as<double>();
   const double* Cp = Cs + (size_t)ns_ * ns_;
-  // all cores in one upload, each at its own offset of the staging buffer
-  std::vector<size_t> off(D + 1, 0);
-  for (int k = 0; k < D; ++k) off[k + 1] = off[k] + (size_t)h->ranks[k] * h->g.n[k] * h->ranks[k + 1];
-  std::vector<double> all(std::max<size_t>(off[D], 1));
-  for (int k = 0; k < D; ++k)
-    std::copy(h->cores[k].begin(), h->cores[k].begin() + (off[k + 1] - off[k]), all.begin() + off[k]);
-  TTK_TRY(h->gtmp.alloc(all.size() * sizeof(double)));
-  TTK_HIP(hipMemcpyAsync(h->gtmp.p, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, st));
   ChainStage* src = h->src;
   ChainStage* tgt = h->tgt;
   for (int k = 0; k < D; ++k) {
     const int r0 = h->ranks[k], n = h->g.n[k], r1 = h->ranks[k + 1];
     const size_t cnt = (size_t)r0 * n * r1;
-    const double* gk = h->gtmp.as<double>() + off[k];
+    const double* gk = h->dcores[k].as<double>();
     const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((cnt + 255) / 256, 4096));
     if (k < d || k >= d + dt) {
       const int mode = (k < d) ? 0 : 1;
@@ -415,10 +408,10 @@ tt_status tt_kernel_build_offline(const tt_kernel_params* p, const void* X, int6
   TTK_TRY(run_cross(&cp, h->g, h->ks, st, &h->cross));
   h->info.t_cross_ms = ms_since(t0);
   h->cross_ranks = h->cross.ranks;
-  h->cores = h->cross.cores;
+  h->dcores = std::move(h->cross.cores);
   h->ranks = h->cross.ranks;
   t0 = std::chrono::steady_clock::now();
-  TTK_TRY(round_gauge(h->cores, h->ranks, h->g, h->P.tol, st));
+  TTK_TRY(round_gauge(h->dcores, h->ranks, h->g, h->P.tol, st));
   h->info.t_round_ms = ms_since(t0);
   TTK_TRY(finish_build(h.get(), X, Y, st));
   TTK_TRY(finish_global(h.get(), st));
@@ -441,10 +434,14 @@ tt_status tt_kernel_build_from_cores(const tt_kernel_params* p, const int* ranks
   h->ranks.assign(ranks, ranks + D + 1);
   size_t off = 0;
   h->cores.resize(D);
+  h->dcores.clear();
+  h->dcores.resize(D);
   for (int k = 0; k < D; ++k) {
     if (ranks[k + 1] < 1 || ranks[k + 1] > MAXR) return fail(TTK_ERR_ARG, "rank %d out of range", ranks[k + 1]);
     const size_t cnt = (size_t)ranks[k] * h->g.n[k] * ranks[k + 1];
     h->cores[k].assign(cores + off, cores + off + cnt);
+    TTK_TRY(h->dcores[k].alloc(cnt * sizeof(double)));
+    TTK_HIP(hipMemcpyAsync(h->dcores[k].p, h->cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
     off += cnt;
   }
   h->cross_ranks = h->ranks;
@@ -694,6 +691,15 @@ tt_status tt_kernel_get_factors(tt_kernel_t h, void* U_out, void* V_out, void* s
 
 tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity) {
   if (!h || !cores) return fail(TTK_ERR_ARG, "NULL argument");
+  const int D = h->g.D;
+  if (h->cores.size() != (size_t)D) {   // a device build: read the rounded cores back once
+    h->cores.assign(D, {});
+    for (int k = 0; k < D; ++k) {
+      h->cores[k].resize((size_t)h->ranks[k] * h->g.n[k] * h->ranks[k + 1]);
+      TTK_HIP(hipMemcpy(h->cores[k].data(), h->dcores[k].p, h->cores[k].size() * sizeof(double),
+                        hipMemcpyDeviceToHost));
+    }
+  }
   size_t need = 0;
   for (auto& c : h->cores) need += c.size();
   if ((size_t)capacity < need) return fail(TTK_ERR_ARG, "capacity %lld < %zu", (long long)capacity, need);

@@ -2008,14 +2008,16 @@ tt_status Cross::run(CrossOut* out) {
   TTK_TRY(refine_cores());
   out->ranks.assign(N + 1, 1);
   for (int k = 0; k <= N; ++k) out->ranks[k] = rank(k);
-  out->cores.assign(N, {});
+  out->cores.clear();
+  out->cores.resize(N);
   for (int k = 1; k <= N; ++k) {
     const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
     const size_t cnt = (size_t)r0 * n * r1;
-    // column-major C_k ((r0 n) x r1) is the little-endian core layout itself
-    out->cores[k - 1].resize(cnt);
+    // column-major C_k ((r0 n) x r1) is the little-endian core layout itself;
+    // the cores stay on the device, in buffers of their own size
+    TTK_TRY(out->cores[k - 1].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
     const DBuf& src = (k == N) ? d_core_[k - 1] : d_cint_[k - 1];
-    TTK_HIP(hipMemcpyAsync(out->cores[k - 1].data(), src.p, cnt * sizeof(double), hipMemcpyDeviceToHost, st_));
+    TTK_HIP(hipMemcpyAsync(out->cores[k - 1].p, src.p, cnt * sizeof(double), hipMemcpyDeviceToDevice, st_));
   }
   TTK_TRY(sync());
   out->left.assign(N + 1, {});

@@ -172,7 +172,7 @@ void nrm2(const double* x, int64_t n, double* out, hipStream_t st);
 // ----------------------------------------------------------- the cross
 struct CrossOut {
   std::vector<int> ranks;                     // r_0..r_D
-  std::vector<std::vector<double>> cores;     // host FP64, little-endian r0 x n x r1
+  std::vector<DBuf> cores;                    // device FP64, little-endian r0 x n x r1
   std::vector<std::vector<int32_t>> left;     // I^{<=k}, k = 0..D
   std::vector<std::vector<int32_t>> right;    // I^{>k},  k = 0..D
   std::vector<tt_kernel_decision> log;
@@ -185,9 +185,10 @@ tt_status run_cross(const tt_kernel_params* p, const Grid& g, const KSpec& ks,
                     hipStream_t st, CrossOut* out);
 
 // -------------------------------------------------- rounding and gauge
-// TT-Round + gauge + signs of host FP64 cores, computed on the device.
-tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>& ranks,
-                      const Grid& g, double eps, hipStream_t st);
+// TT-Round + gauge + signs of device FP64 cores (little-endian r0 x n x r1),
+// in place: the buffers are reused for the rounded cores.
+tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const Grid& g, double eps,
+                      hipStream_t st);
 
 // ----------------------------------------------------------- Phase 3
 struct ChainStage {

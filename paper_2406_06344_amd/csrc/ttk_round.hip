@@ -121,18 +121,14 @@ tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipS
 
 }  // namespace
 
-tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>& ranks, const Grid& grid,
-                      double eps, hipStream_t st) {
+tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const Grid& grid, double eps,
+                      hipStream_t st) {
   const int D = (int)cores.size();
   Cores c;
   c.r = ranks;
   c.n.assign(grid.n, grid.n + D);
   c.g.resize(D);
-  for (int k = 0; k < D; ++k) {
-    const size_t cnt = (size_t)c.r[k] * c.n[k] * c.r[k + 1];
-    TTK_TRY(c.g[k].alloc(std::max<size_t>(cnt, 1) * sizeof(double)));
-    TTK_HIP(hipMemcpyAsync(c.g[k].p, cores[k].data(), cnt * sizeof(double), hipMemcpyHostToDevice, st));
-  }
+  for (int k = 0; k < D; ++k) c.g[k] = std::move(cores[k]);   // rounded in place (ranks only fall)
   DBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
   {
     // every work buffer at the largest size any step needs (the ranks only
@@ -250,11 +246,7 @@ tt_status round_gauge(std::vector<std::vector<double>>& cores, std::vector<int>&
                        q0 * qn, r0, q0 * qn, sg.as<double>(), 0);
   }
   TTK_HIP(hipGetLastError());
-  for (int k = 0; k < D; ++k) {
-    const size_t cnt = (size_t)c.r[k] * c.n[k] * c.r[k + 1];
-    cores[k].resize(cnt);
-    TTK_HIP(hipMemcpyAsync(cores[k].data(), c.g[k].p, cnt * sizeof(double), hipMemcpyDeviceToHost, st));
-  }
+  for (int k = 0; k < D; ++k) cores[k] = std::move(c.g[k]);
   TTK_HIP(hipStreamSynchronize(st));
   ranks = c.r;
   return TTK_OK;
