@@ -168,8 +168,8 @@ constexpr int INIT_SNAP = 4 * MAXD * MAXD;
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(1024) k_init_sets(KSpec ks, InitArgs ia, int32_t* snap, double* snap_mc) {
   constexpr int D = 2 * d + dt;
-  __shared__ double sn[D * MAXN], F[2 * MAXN * 2], sv[1024];
-  __shared__ int si[1024];
+  __shared__ double sn[D * MAXN], F[2 * MAXN * 2], sv[1024], wmin[16];
+  __shared__ int wpos[16];
   __shared__ int16_t Ls[MAXD][2 * MAXD], Rs[MAXD + 1][2 * MAXD];
   const int tid = threadIdx.x, N = ia.N;
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
@@ -199,30 +199,30 @@ __global__ void __launch_bounds__(1024) k_init_sets(KSpec ks, InitArgs ia, int32
     for (int e = tid; e < m * a.rr; e += 1024) F[e] = addr_eval<d, dt, G>(ks, a, sn, e % m, e / m);
     __syncthreads();
     const int excl = (mode == 0) ? (k == 1) : (k == N);
-    const int nn = n * n;
+    const int nn = n * n;   // <= 1024: one candidate per thread
     const double v = tid < nn ? init_cond_at(F, a.rl, a.rr, n, mode, excl, tid) : INFINITY;
     sv[tid] = v;
+    // the smallest condition number: per wave, then over the 16 waves
+    const double wm = -wave64_max(-v);
+    if ((tid & 63) == 0) wmin[tid >> 6] = wm;
     __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
-      if (tid < h) sv[tid] = fmin(sv[tid], sv[tid + h]);
-      __syncthreads();
-    }
-    const double mn = sv[0];
+    double mn = wmin[0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) mn = fmin(mn, wmin[w]);
+    // the lowest allowed position within the band (every allowed one if all are +inf)
     int pos = 0x7fffffff;
     if (tid < nn && !(excl && tid / n == tid % n) && (isinf(mn) || v <= mn * (1.0 + 1e-12))) pos = tid;
-    si[tid] = pos;
+    pos = wave64_min_i(pos);
+    if ((tid & 63) == 0) wpos[tid >> 6] = pos;
     __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
-      if (tid < h) si[tid] = min(si[tid], si[tid + h]);
-      __syncthreads();
-    }
-    const int p = si[0] == 0x7fffffff ? 0 : si[0];   // (n >= 2 always leaves an allowed position)
+    int p = wpos[0];
+#pragma unroll
+    for (int w = 1; w < 16; ++w) p = min(p, wpos[w]);
+    if (p == 0x7fffffff) p = 0;   // (n >= 2 always leaves an allowed position)
     *j1 = p / n;
     *j2 = p % n;
-    if (tid == p) sv[0] = v;   // (every thread has read sv[0] before the second reduction)
-    __syncthreads();
-    *cv = sv[0];
-    __syncthreads();   // sv, si and F are reused by the next probe
+    *cv = sv[p];
+    __syncthreads();   // sv, the wave slots and F are reused by the next probe
   };
   auto snapshot = [&](int slot, double mc) {
     int32_t* o = snap + (size_t)slot * INIT_SNAP;
@@ -1478,27 +1478,31 @@ void Cross::pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>
 // P_k^{-1} of the initial index sets (ranks 1 or 2).
 tt_status Cross::init_inverses() {
   TTK_TRY(d_P_.alloc(16 * sizeof(double)));
+  // every core's sets and pivot positions in one upload
+  arena_reset();
+  Addr ak[MAXD];
+  const int32_t* dIk[MAXD] = {nullptr};
   for (int k = 1; k < N_; ++k) {
-    const int rk = rank(k);
     std::vector<int32_t> I, J;
     pivot_positions(k, &I, &J);
-    arena_reset();
     TTK_TRY(upload_sets(k - 1, k + 1, nullptr, nullptr));
+    ak[k] = super_addr(k);
     std::vector<int32_t> hi(I);
     hi.insert(hi.end(), J.begin(), J.end());
-    const int32_t* dI = nullptr;
-    TTK_TRY(arena_push(hi.data(), hi.size(), &dI));
-    TTK_TRY(arena_flush());
+    TTK_TRY(arena_push(hi.data(), hi.size(), &dIk[k]));
+  }
+  TTK_TRY(arena_flush());
+  for (int k = 1; k < N_; ++k) {
+    const int rk = rank(k);
     TTK_TRY(d_li_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));   // Li, then Li^T
     TTK_TRY(d_w_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));    // W, then W^T
-    eval_product(ks_, super_addr(k), dI, rk, dI + rk, rk, d_P_.as<double>(), st_);
+    eval_product(ks_, ak[k], dIk[k], rk, dIk[k] + rk, rk, d_P_.as<double>(), st_);
     evals_ += (int64_t)rk * rk;
     hipLaunchKernelGGL(k_ldu_init, dim3(1), dim3(64), 0, st_, d_P_.as<double>(), rk, d_li_[k].as<double>(),
                        d_w_[k].as<double>(), luamax(k), luinfo(k));
-    TTK_TRY(sync());   // the arena is reused by the next k
   }
   TTK_HIP(hipGetLastError());
-  return TTK_OK;
+  return sync();   // the arena's host side is reused after this
 }
 
 // The buffers whose size follows the ranks (the stopping test's fibres and
