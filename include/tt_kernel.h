@@ -32,6 +32,13 @@
  *    X[j * n + p].
  *  - Matrices are column-major unless stated; "ld" arguments are leading
  *    dimensions in elements.
+ *  - Working memory the library allocates (device and pinned host) is not
+ *    returned to HIP when a call or a handle releases it: it goes to a pool
+ *    of the calling thread and device, at most 1 GiB per kind, and later
+ *    allocations on that thread take it from there.  A block is reused only
+ *    after a device synchronisation, so work still queued on any stream can
+ *    never see it change.  An allocation that fails first frees the pool's
+ *    idle blocks and retries.
  */
 #ifndef TT_KERNEL_H
 #define TT_KERNEL_H
