@@ -1004,13 +1004,16 @@ __global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* de
   if (tid == 0 && sel_next) *sel_next = s_added;
   if (s_added && next_left && tid <= a.lk) next_left[(size_t)next_row * (a.lk + 1) + tid] = lv;
   // publish the step's result to the host mailbox: the fields up to the
-  // fold slots, then (after a system-scope fence) the sequence number the
-  // host waits for
+  // fold slots, one 8-byte word per thread so that the copies to host memory
+  // overlap (a single thread's copy loop waited for every store), then, after
+  // a system-scope fence, the sequence number the host waits for
+  constexpr int MAIL_WORDS = (int)(offsetof(StepRes, s_slot) / 8);
+  static_assert(MAIL_WORDS <= 64, "the copying threads are those of wave 0, as is the fencing one");
+  __syncthreads();
+  if (tid < MAIL_WORDS)
+    reinterpret_cast<uint64_t*>(mail)[tid] = reinterpret_cast<const uint64_t*>(res)[tid];
   __syncthreads();
   if (tid == 0) {
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(res);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(mail);
-    for (int i = 0; i < (int)(offsetof(StepRes, s_slot) / 8); ++i) dst[i] = src[i];
     __threadfence_system();
     __hip_atomic_store(mail_seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
