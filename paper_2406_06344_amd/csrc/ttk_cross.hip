@@ -1036,9 +1036,8 @@ __global__ void __launch_bounds__(64) k_test_publish(const double* err, const in
   }
 }
 
-// Every fibre F_k = X(I^{<=k-1}, i_k, I^{>k}) ((r_{k-1} n_k) x r_k,
-// column-major) of the stopping test in one launch; block ranges per core
-// (blk[j] .. blk[j + 1]) so that the core is uniform over a block.
+// The fibres F_k = X(I^{<=k-1}, i_k, I^{>k}) ((r_{k-1} n_k) x r_k,
+// column-major) of the stopping test: their addresses, outputs and sizes.
 struct CoreEval {
   Addr a[MAXD];
   double* out[MAXD];
@@ -1047,19 +1046,6 @@ struct CoreEval {
   int blk[MAXD + 1];
   int n;
 };
-template <int d, int dt, bool G>
-__global__ void __launch_bounds__(256) k_eval_cores(KSpec ks, CoreEval ce, double* clear) {
-  constexpr int D = 2 * d + dt;
-  __shared__ double sn[D * MAXN];
-  if (blockIdx.x == 0 && threadIdx.x < TEST_SLOTS) clear[threadIdx.x] = 0.0;   // the stopping test's error slots
-  stage_nodes<D>(ks.nodes, sn);
-  int j = 0;
-  while (j + 1 < ce.n && (int)blockIdx.x >= ce.blk[j + 1]) ++j;
-  const int64_t e = (int64_t)(blockIdx.x - ce.blk[j]) * 256 + threadIdx.x;
-  if (e >= ce.size[j]) return;
-  const int nr = ce.nr[j];
-  ce.out[j][e] = addr_eval<d, dt, G>(ks, ce.a[j], sn, (int)(e % nr), (int)(e / nr));
-}
 
 // One 16 x 16 output tile of A B with FP64 MFMA: A (16 rows x 4 nst) in LDS in
 // lane order (step s, lane l at s * 64 + l), B(q, p) = Bt[p + q MAXR] for this
@@ -1083,7 +1069,7 @@ __device__ inline dbl4 mfma_tile_lds(const double* sa, int nst, const double* Bt
 }
 
 // Cores of the interpolation formula C_k = F_k P_k^{-1} = (F_k W) Li for
-// every k < D in one launch: one block per 16 rows of one core (tile ranges
+// every k < D: one block per 16 rows of one core (tile ranges
 // tile[j] .. tile[j + 1]); F rows and then T = F W are held in LDS in lane
 // order (dynamic, 2 x 64 x ceil(r / 4) doubles), W and Li read through their
 // transposes.
@@ -1096,30 +1082,56 @@ struct CoreSolve {
   int tile[MAXD + 1];
   int n;
 };
-constexpr int CW = 4;   // waves per block
-__global__ void __launch_bounds__(CW * 64) k_solve_cores(CoreSolve cs) {
+constexpr int CW = 4;   // waves per block of the solve
+
+// dynamic LDS of the core solve (k_eval_solve) for rank r
+inline size_t solve_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
+
+// The stopping test's fibres and cores in one launch: the solve tiles
+// evaluate their 16 rows of F_k themselves (straight into the lane order of
+// the first product, and into F_k in memory, which the refinement of the
+// returned cores reads), then blocks past the tiles evaluate the last fibre
+// F_D (C_D = F_D, no solve), 256 entries each.  Block 0 also clears the
+// test's error slots.  (One launch and one kernel boundary fewer per test
+// than a fibre launch followed by a solve launch.)
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(CW * 64) k_eval_solve(KSpec ks, CoreEval ce, CoreSolve cs, double* clear) {
+  constexpr int D = 2 * d + dt;
   extern __shared__ double lds[];
+  __shared__ double sn[D * MAXN];
+  if (blockIdx.x == 0 && threadIdx.x < TEST_SLOTS) clear[threadIdx.x] = 0.0;
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= cs.tile[cs.n]) {   // the last fibre
+    const int j = ce.n - 1;
+    const int64_t e = (int64_t)((int)blockIdx.x - cs.tile[cs.n]) * (CW * 64) + tid;
+    if (e < ce.size[j]) ce.out[j][e] = addr_eval<d, dt, G>(ks, ce.a[j], sn, (int)(e % ce.nr[j]), (int)(e / ce.nr[j]));
+    return;
+  }
   int j = 0;
   while (j + 1 < cs.n && (int)blockIdx.x >= cs.tile[j + 1]) ++j;
   const int m = cs.m[j], r = cs.r[j];
   const int row0 = ((int)blockIdx.x - cs.tile[j]) * 16;
   const int nst = (r + 3) / 4;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   double* sa = lds;
   double* sb = lds + 64 * nst;
-  const double* F = cs.F[j];
+  double* F = ce.out[j];
   for (int e = tid; e < 64 * nst; e += CW * 64) {
     const int ii = e & 15, q = e >> 4;
     const int i = row0 + ii;
-    sa[(q >> 2) * 64 + (q & 3) * 16 + ii] = (i < m && q < r) ? F[i + (int64_t)q * m] : 0.0;
+    double v = 0.0;
+    if (i < m && q < r) {
+      v = addr_eval<d, dt, G>(ks, ce.a[j], sn, i, q);
+      F[i + (int64_t)q * m] = v;
+    }
+    sa[(q >> 2) * 64 + (q & 3) * 16 + ii] = v;
     sb[e] = 0.0;
   }
   __syncthreads();
   const int ntile = (r + 15) / 16;
-  // T = F W, B(q, p) = W(q, p) = W^T[p + q MAXR]; T(i, p) goes to the lane-order
-  // slot of the next product, whose k-index is p
-  for (int jt = wv; jt < ntile; jt += CW) {
+  for (int jt = wv; jt < ntile; jt += CW) {   // T = F W
     const int p = jt * 16 + li;
     const dbl4 t = mfma_tile_lds(sa, nst, cs.W[j] + FT, p, r, lane);
     if (p < r)
@@ -1127,9 +1139,8 @@ __global__ void __launch_bounds__(CW * 64) k_solve_cores(CoreSolve cs) {
       for (int v = 0; v < 4; ++v) sb[(p >> 2) * 64 + (p & 3) * 16 + lk + 4 * v] = t[v];
   }
   __syncthreads();
-  // C = T Li, B(q, p) = Li(q, p) = Li^T[p + q MAXR]
   double* C = cs.C[j];
-  for (int jt = wv; jt < ntile; jt += CW) {
+  for (int jt = wv; jt < ntile; jt += CW) {   // C = T Li
     const int p = jt * 16 + li;
     const dbl4 c = mfma_tile_lds(sb, nst, cs.Li[j] + FT, p, r, lane);
     if (p < r)
@@ -1140,9 +1151,6 @@ __global__ void __launch_bounds__(CW * 64) k_solve_cores(CoreSolve cs) {
       }
   }
 }
-
-// dynamic LDS of k_solve_cores for rank r
-inline size_t solve_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
 
 inline int nblk(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
@@ -1834,12 +1842,7 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   for (int k = ce_next_; k <= N; ++k) TTK_TRY(stage_core(k));
   ce_next_ = 1;   // the next test stages from core 1 again
   ce_.blk[N] = ce_nb_;
-  const int nb = ce_nb_;
   TTK_TRY(arena_flush());
-  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_eval_cores<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(nb),
-                       dim3(256), 0, st_, ks_, ce_, d_err_.as<double>());
-  });
   CoreSolve cs{};
   cs.n = N - 1;
   int nt = 0, rmax = 1;
@@ -1859,8 +1862,12 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   }
   cs.tile[N - 1] = nt;
   (*C)[N - 1] = d_core_[N - 1].as<double>();
-  if (nt > 0)
-    hipLaunchKernelGGL(k_solve_cores, dim3(nt), dim3(CW * 64), solve_lds(rmax), st_, cs);
+  // the solve tiles (evaluating their own fibre rows), then the last fibre
+  const int nlast = nblk(ce_.size[N - 1], CW * 64);
+  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+    hipLaunchKernelGGL((k_eval_solve<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(nt + nlast), dim3(CW * 64), solve_lds(rmax), st_, ks_, ce_, cs, d_err_.as<double>());
+  });
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
@@ -1981,9 +1988,16 @@ tt_status Cross::run(CrossOut* out) {
     });
     TTK_HIP(e);
   }
-  if (solve_lds(MAXR) > 48 * 1024)
-    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_solve_cores),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
+  if (solve_lds(MAXR) > 48 * 1024) {
+    hipError_t e = hipSuccess;
+    with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+      e = hipFuncSetAttribute(
+          reinterpret_cast<const void*>(
+              &k_eval_solve<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR));
+    });
+    TTK_HIP(e);
+  }
   TTK_TRY(mail_.alloc());
   TTK_TRY(d_x_.alloc(MAXR * sizeof(double)));   // the search stage's P^{-1} u
   // the residuals of either stage: at most max(rows, cols) <= MAXR x MAXN
