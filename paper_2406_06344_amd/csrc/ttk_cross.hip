@@ -1043,7 +1043,6 @@ struct CoreEval {
   double* out[MAXD];
   int nr[MAXD];
   int64_t size[MAXD];
-  int blk[MAXD + 1];
   int n;
 };
 
@@ -1253,7 +1252,7 @@ class Cross {
   tt_status build_cores(std::vector<double*>* C);
   tt_status stage_core(int k);
   CoreEval ce_{};
-  int ce_nb_ = 0, ce_next_ = 1;   // stopping-test staging: blocks so far, next core
+  int ce_next_ = 1;   // stopping-test staging: the next core to stage
   tt_status refine_cores();
   tt_status init_inverses();
   void pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>* J);
@@ -1819,7 +1818,6 @@ tt_status Cross::stage_core(int k) {
     arena_reset();   // the other-uses arena: its last reader, the previous test, has drained
     ce_ = CoreEval{};
     ce_.n = N_;
-    ce_nb_ = 0;
   }
   const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
   const int m = r0 * n;
@@ -1829,8 +1827,6 @@ tt_status Cross::stage_core(int k) {
   ce_.out[k - 1] = d_core_[k - 1].as<double>();
   ce_.nr[k - 1] = m;
   ce_.size[k - 1] = (int64_t)m * r1;
-  ce_.blk[k - 1] = ce_nb_;
-  ce_nb_ += nblk(ce_.size[k - 1], 256);
   evals_ += (int64_t)m * r1;
   ce_next_ = k + 1;
   return TTK_OK;
@@ -1841,7 +1837,6 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   C->assign(N, nullptr);
   for (int k = ce_next_; k <= N; ++k) TTK_TRY(stage_core(k));
   ce_next_ = 1;   // the next test stages from core 1 again
-  ce_.blk[N] = ce_nb_;
   TTK_TRY(arena_flush());
   CoreSolve cs{};
   cs.n = N - 1;
