@@ -354,6 +354,16 @@ tt_status tt_kernel_get_factors(tt_kernel_t h, void* U_out, void* V_out, void* s
  * the layout of tt_kernel_build_from_cores; `capacity` doubles available. */
 tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity);
 
+/* Coefficient-basis cores: the rounded cores after the change of basis of
+ * mode 2 that turns the nodal (Lagrange) interpolant of Section 2.4 into a
+ * sum of Chebyshev polynomials, Ghat_k[:, j, :] = sum_i C[j, i] G_k[:, i, :]
+ * with C[j, i] = (c_j / n) T_j(zeta_i), c_0 = 1, c_j = 2 (regrouping the
+ * basis polynomials of Lemma 1).  These are the cores Phase 3 and the online
+ * stage contract.  Host, double precision, in the layout of
+ * tt_kernel_get_cores; spatial cores of a TTK_FP32 handle are the float32
+ * copies Phase 3 reads, widened.  Synchronous; `capacity` doubles available. */
+tt_status tt_kernel_get_coeff_cores(tt_kernel_t h, double* cores, int64_t capacity);
+
 /* Cross record: index sets I^{<=k} (k = 1..D-1) and I^{>k} as host int32
  * arrays.  left: capacity sum_k r_k k, rows of I^{<=k} concatenated for
  * k = 1..D-1, each row k indices.  right: same for I^{>k}, rows of D - k

@@ -94,3 +94,38 @@ def lagrange_derivs(x, a, b, n):
 def lebesgue_function(x, n):
     """sum_k |phi^[-1,1](zeta_k, x)| (Lemma 1)."""
     return np.abs(lagrange_values(x, -1.0, 1.0, n)).sum(axis=-1)
+
+
+# ----------------------------------------------- full coefficient tensor
+def coefficient_tensor(M):
+    """Chebyshev coefficient tensor of a grid tensor M (Section 2.4).
+
+    Regrouping the multivariate interpolant sum_i M[i] prod_j phi(eta_{i_j}, .)
+    by the Chebyshev-sum form of each basis polynomial gives
+    sum_k A[k] prod_j T_{k_j}(t_j) with A = M x_1 C_1 x_2 C_2 ... x_D C_D,
+    C_j = basis_change(n_j): a DCT-II along every mode.
+    """
+    A = np.asarray(M, dtype=np.float64)
+    for j, nj in enumerate(A.shape):
+        A = np.moveaxis(np.tensordot(basis_change(nj), A, axes=([1], [j])), 0, j)
+    return A
+
+
+def interpolant_coefficient_form(A, boxes, pts):
+    """sum_k A[k] prod_j T_{k_j}(t_j(pts[:, j])) at points pts (P, D)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.asarray(A, dtype=np.float64)[None]
+    for j, (a, b) in enumerate(boxes):
+        Tt = cheb_T_table(out.shape[1], affine_inv(pts[:, j], a, b))    # [k, p]
+        out = np.einsum("pk...,kp->p...", out, Tt)
+    return out
+
+
+def interpolant_lagrange_form(M, boxes, pts):
+    """sum_i M[i] prod_j phi^[a_j,b_j](eta_{i_j}, pts[:, j]) at points pts (P, D)."""
+    pts = np.asarray(pts, dtype=np.float64)
+    out = np.asarray(M, dtype=np.float64)[None]
+    for j, (a, b) in enumerate(boxes):
+        q = lagrange_values(pts[:, j], a, b, out.shape[1])               # [p, i]
+        out = np.einsum("pi...,pi->p...", out, q)
+    return out

@@ -32,13 +32,16 @@ Readings of the paper taken here (each written out in the design notes):
   error the stopping test measured last.  C_N = F_N.  (The QR form
   Q Q[J,:]^{-1} of F_k = Q R, equal in exact arithmetic, stays available.)
 * Replay of decisions taken by another computation of the same residuals
-  (the GPU path): a forced choice is accepted if its |R| here lies within the
-  tie band of this computation's maximum, widened by twice the disagreement
-  the two computations show on the same residuals (|sample max| there vs
-  here, and |R| at the forced pivot there vs here), which must itself stay
-  below 10 tau.  Algorithm 5 takes an argmax of computed residuals, so an
-  entry whose residual is within rounding of the band edge is an equally
-  valid choice; the add test |R| > tau is judged the same way.
+  (the GPU path): a forced choice is accepted if its |R|, computed here, lies
+  within the tie band of this computation's maximum widened by
+  2 (C_NOISE + r_k) times the rounding noise of the step's residuals, which
+  the oracle measures itself as the largest disagreement between three
+  backward-stable FP64 evaluation orders of the same skeleton formula (r_k:
+  the rank before the step, the length of the elimination).  Algorithm 5 takes an
+  argmax of computed residuals, so an entry within rounding of the band edge
+  is an equally valid choice; the add test |R| > tau is judged the same way.
+  Nothing the other computation reports (its residual values) enters the
+  check: only its choices.
 * Initialisation (Algorithm 7): q_1, q_2 are full random multi-indices; a
   snapshot (all sets, max condition number of the half-sweep) is kept after
   every half-sweep and the one with the smallest maximum is returned (earliest
@@ -52,6 +55,9 @@ from . import tt as ttmod
 
 TIE_REL = 1e-10
 COND_REL = 1e-12
+# rounding allowance of a replayed choice, in units of the measured residual
+# noise: C_NOISE + r_k (see update_cross)
+C_NOISE = 4.0
 
 
 class Entries:
@@ -93,14 +99,6 @@ def _argmin_band(vals, rel):
         return int(np.argmax(vals == m)) if np.any(vals == m) else 0
     cand = np.nonzero(vals <= m * (1.0 + rel))[0]
     return int(cand[0])
-
-
-def _forced_eps(forced, eps, here):
-    """Largest disagreement seen so far in the step between the forced
-    computation's residuals and this one's (|R| at the forced pivot)."""
-    if "pivot_abs" in forced:
-        eps = max(eps, abs(float(forced["pivot_abs"]) - here))
-    return eps
 
 
 def _argmax_band(absvals, tau):
@@ -222,97 +220,126 @@ def _supercore_index(L, R, k, n, rows, cols):
     return np.concatenate([left, ik, i1, right], axis=1)
 
 
+def _skeleton_residuals(P, AxJ, AIy, Axy):
+    """Skeleton error R(x, y) = A(x, J) A(I, J)^{-1} A(I, y) - A(x, y) of the
+    cross approximation (Appendix A) for paired positions (x_i, y_i).
+
+    P = A(I, J) (r x r), AxJ (m x r), AIy (r x m), Axy (m,).  The same formula
+    is evaluated in three FP64 orders, each backward stable:
+      right:  A(x, J) [P^{-1} A(I, y)]   (LU with partial pivoting)
+      left:   [A(x, J) P^{-1}] A(I, y)   (LU of P^T)
+      qr:     A(x, J) [R^{-1} Q^T A(I, y)]  (Householder QR of P)
+    Returns the right-order residuals and the largest disagreement between
+    the three orders, which measures the FP64 rounding noise of this step's
+    residuals (it grows with the conditioning of P).
+    """
+    right = np.einsum("mr,rm->m", AxJ, np.linalg.solve(P, AIy)) - Axy
+    left = np.einsum("mr,rm->m", np.linalg.solve(P.T, AxJ.T).T, AIy) - Axy
+    Q, Rq = np.linalg.qr(P)
+    qr = np.einsum("mr,rm->m", AxJ, np.linalg.solve(Rq, Q.T @ AIy)) - Axy
+    spread = max(float(np.max(np.abs(right - left))), float(np.max(np.abs(right - qr))),
+                 float(np.max(np.abs(left - qr))))
+    return right, spread
+
+
 def update_cross(ent, L, R, k, sweep, seed, max_rank, forced=None):
     """One update cross step (Algorithm 5) on super-core k (1-based).
 
-    Returns a decision record; mutates L[k], R[k] when a pivot is added.
-    With `forced` (a record produced elsewhere), the forced choices are used
-    after checking that each lies in this oracle's tie band.
+    The super-core unfolding A = [X(I^{<=k-1}, :, :, I^{>k+1})]^{2} is skeleton-
+    approximated on the rows I and columns J given by I^{<=k}, I^{>k}.  The
+    step (i) draws max(rows, cols) random positions, (ii) takes the one with
+    the largest |R|, (iii) draws a bit and searches the sample's row (bit 1)
+    or column (bit 0) of R for its largest |R|, and (iv) adds that position's
+    row and column to I and J when |R| there exceeds tau and both are new.
+
+    Returns a decision record and mutates L[k], R[k] when a pivot is added.
+    With `forced` (the pivots another computation chose: sample_pos,
+    pivot_row, pivot_col, added), the forced choices are taken instead, after
+    checking that each lies within this computation's tie band, widened by
+    (C_NOISE + r_k) times the rounding noise of the step's residuals measured
+    here (_skeleton_residuals); no value reported by the other computation
+    enters.
     """
-    N, n = ent.N, ent.n
-    rl = L[k - 1].shape[0]
-    rr = R[k + 1].shape[0]
-    nk, nk1 = n[k - 1], n[k]
-    rows, cols = rl * nk, nk1 * rr
+    n = ent.n
+    rl, rr = L[k - 1].shape[0], R[k + 1].shape[0]
+    nk1 = n[k]
+    rows, cols = rl * n[k - 1], nk1 * rr
     I = _positions_left(L, k, n)
-    J = _positions_right(R, k, n, N)
+    J = _positions_right(R, k, n, ent.N)
     rk = I.size
 
     def A(rr_, cc_):
-        rr_ = np.asarray(rr_, dtype=np.int64)
-        cc_ = np.asarray(cc_, dtype=np.int64)
-        return ent(_supercore_index(L, R, k, n, rr_, cc_))
+        return ent(_supercore_index(L, R, k, n, np.asarray(rr_, np.int64), np.asarray(cc_, np.int64)))
 
+    # (i) random positions of the unfolding (Floyd sample) and their residuals
     g = rngmod.keyed(seed, rngmod.TAG_UPDATE, sweep, k)
     ns = max(rows, cols)
     lin = np.array(g.floyd(rows * cols, ns), dtype=np.int64)
     srow, scol = lin // cols, lin % cols
-
-    # A(I,J), A(samples, J), A(I, samples), A(samples)
-    AIJ = A(np.repeat(I, rk), np.tile(J, rk)).reshape(rk, rk)
+    P = A(np.repeat(I, rk), np.tile(J, rk)).reshape(rk, rk)
     AsJ = A(np.repeat(srow, rk), np.tile(J, ns)).reshape(ns, rk)
     AIs = A(np.repeat(I, ns), np.tile(scol, rk)).reshape(rk, ns)
     As = A(srow, scol)
-    scale = max(np.max(np.abs(AIJ)), np.max(np.abs(AsJ)), np.max(np.abs(AIs)), np.max(np.abs(As)))
-    Y = np.linalg.solve(AIJ, AIs)                        # A(I,J)^{-1} A(I, s)
-    Rs = np.sum(AsJ * Y.T, axis=1) - As
-    tau = TIE_REL * scale
+    seen = max(np.max(np.abs(P)), np.max(np.abs(AsJ)), np.max(np.abs(AIs)), np.max(np.abs(As)))
+    Rs, noise = _skeleton_residuals(P, AsJ, AIs, As)
+    tau = TIE_REL * seen
     p, m0, margin0 = _argmax_band(np.abs(Rs), tau)
     rec = {"sweep": sweep, "k": k, "rank_before": rk,
            "sample_pos": int(lin[p]), "sample_max": m0, "sample_margin": margin0}
-    eps = 0.0   # disagreement between the forced computation's residuals and these
-    if forced is not None:
-        fpos = int(forced["sample_pos"])
-        where = np.nonzero(lin == fpos)[0]
-        if "sample_max" in forced:
-            eps = abs(float(forced["sample_max"]) - m0)
-        ok = where.size == 1 and abs(Rs[where[0]]) >= m0 - max(tau, 1e-9 * m0) - 2 * eps and eps <= 10 * tau
-        rec["replay_sample_ok"] = bool(ok)
-        if where.size == 1:
-            p = int(where[0])
-    l, t = int(srow[p]), int(scol[p])
+
+    # (iii) the searched fibre through the chosen sample
     bit = g.bit()
     rec["bit"] = int(bit)
-    if bit == 1:
-        allc = np.arange(cols)
-        AlJ = A(np.full(rk, l), J)
-        AIall = A(np.repeat(I, cols), np.tile(allc, rk)).reshape(rk, cols)
-        Alall = A(np.full(cols, l), allc)
-        scale = max(scale, np.max(np.abs(AlJ)), np.max(np.abs(AIall)), np.max(np.abs(Alall)))
-        tau = TIE_REL * scale
-        Rrow = AlJ @ np.linalg.solve(AIJ, AIall) - Alall
-        q, m1, margin1 = _argmax_band(np.abs(Rrow), tau)
-        if forced is not None:
-            fq = int(forced["pivot_col"])
-            eps = _forced_eps(forced, eps, abs(Rrow[fq]))
-            rec["replay_search_ok"] = bool(abs(Rrow[fq]) >= m1 - max(tau, 1e-9 * m1) - 2 * eps and eps <= 10 * tau)
-            q = fq
-        t = q
-        val = abs(Rrow[t])
-    else:
-        allr = np.arange(rows)
-        AallJ = A(np.repeat(allr, rk), np.tile(J, rows)).reshape(rows, rk)
-        AIt = A(I, np.full(rk, t))
-        Aallt = A(allr, np.full(rows, t))
-        scale = max(scale, np.max(np.abs(AallJ)), np.max(np.abs(AIt)), np.max(np.abs(Aallt)))
-        tau = TIE_REL * scale
-        Rcol = AallJ @ np.linalg.solve(AIJ, AIt) - Aallt
-        q, m1, margin1 = _argmax_band(np.abs(Rcol), tau)
-        if forced is not None:
-            fq = int(forced["pivot_row"])
-            eps = _forced_eps(forced, eps, abs(Rcol[fq]))
-            rec["replay_search_ok"] = bool(abs(Rcol[fq]) >= m1 - max(tau, 1e-9 * m1) - 2 * eps and eps <= 10 * tau)
-            q = fq
-        l = q
-        val = abs(Rcol[l])
-    fresh = (l not in set(I.tolist())) and (t not in set(J.tolist())) and rk < max_rank
-    add = (val > tau) and fresh
     if forced is not None:
-        # |R| > tau within rounding of the band edge may go either way
-        rec["replay_add_ok"] = bool(add == bool(forced["added"]) or (fresh and abs(val - tau) <= 2 * eps))
+        where = np.nonzero(lin == int(forced["sample_pos"]))[0]
+        p_forced = int(where[0]) if where.size == 1 else p
+    else:
+        where, p_forced = None, p
+    l, t = int(srow[p_forced]), int(scol[p_forced])
+    if bit == 1:
+        fib = np.arange(cols)
+        AfJ = np.tile(A(np.full(rk, l), J), (cols, 1))
+        AIf = A(np.repeat(I, cols), np.tile(fib, rk)).reshape(rk, cols)
+        Af = A(np.full(cols, l), fib)
+    else:
+        fib = np.arange(rows)
+        AfJ = A(np.repeat(fib, rk), np.tile(J, rows)).reshape(rows, rk)
+        AIf = np.tile(A(I, np.full(rk, t))[:, None], (1, rows))
+        Af = A(fib, np.full(rows, t))
+    seen = max(seen, np.max(np.abs(AfJ)), np.max(np.abs(AIf)), np.max(np.abs(Af)))
+    Rf, noise_f = _skeleton_residuals(P, AfJ, AIf, Af)
+    noise = max(noise, noise_f)
+    tau = TIE_REL * seen
+    q, m1, margin1 = _argmax_band(np.abs(Rf), tau)
+    # Rounding allowance of one FP64 computation of R by any elimination-based
+    # solve with P: the worst-case backward error of elimination grows
+    # linearly with its length r_k (gamma_{r_k} = r_k u / (1 - r_k u), Higham,
+    # "Accuracy and Stability of Numerical Algorithms", 2nd ed., Thm 9.3),
+    # while the measured spread of three orders reflects their typical error.
+    band = (C_NOISE + rk) * noise
+
+    def in_band(val, m):
+        return val >= m - max(tau, 1e-9 * m) - 2.0 * band
+
+    if forced is not None:
+        rec["replay_sample_ok"] = bool(where.size == 1 and in_band(abs(Rs[p_forced]), m0))
+        q_forced = int(forced["pivot_col"] if bit == 1 else forced["pivot_row"])
+        rec["replay_search_ok"] = bool(0 <= q_forced < fib.size and in_band(abs(Rf[q_forced]), m1))
+        q = q_forced if 0 <= q_forced < fib.size else q
+    if bit == 1:
+        t = q
+    else:
+        l = q
+    val = abs(Rf[q])
+    # (iv) add the pivot when it is significant and new
+    fresh = (l not in set(I.tolist())) and (t not in set(J.tolist())) and rk < max_rank
+    add = bool(val > tau and fresh)
+    if forced is not None:
+        # |R| within the rounding allowance of tau may be judged either way
+        rec["replay_add_ok"] = bool(add == bool(forced["added"]) or (fresh and abs(val - tau) <= 2.0 * band))
         add = bool(forced["added"])
-    rec.update({"pivot_row": l, "pivot_col": t, "pivot_abs": float(val),
-                "search_margin": margin1, "tau": float(tau), "added": bool(add)})
+    rec.update({"pivot_row": l, "pivot_col": t, "pivot_abs": float(val), "search_margin": margin1,
+                "tau": float(tau), "noise": float(noise), "added": add})
     if add:
         newL = np.concatenate([L[k - 1][l % rl], [l // rl]])
         newR = np.concatenate([[t % nk1], R[k + 1][t // nk1]])

@@ -84,7 +84,7 @@ EXPORTS = [
     "tt_kernel_batch_build", "tt_kernel_batch_configure", "tt_kernel_batch_factor", "tt_kernel_batch_get_info",
     "tt_kernel_batch_get_class", "tt_kernel_batch_get_factors", "tt_kernel_batch_apply", "tt_kernel_batch_destroy",
     "tt_kernel_eval_entries", "tt_kernel_eval_dense", "tt_kernel_get_info",
-    "tt_kernel_get_factors", "tt_kernel_get_cores", "tt_kernel_get_cross",
+    "tt_kernel_get_factors", "tt_kernel_get_cores", "tt_kernel_get_coeff_cores", "tt_kernel_get_cross",
     "tt_kernel_destroy", "tt_kernel_last_error",
 ]
 
@@ -125,6 +125,7 @@ def load():
     lib.tt_kernel_get_info.argtypes = [vp, P(Info)]
     lib.tt_kernel_get_factors.argtypes = [vp, vp, vp, vp]
     lib.tt_kernel_get_cores.argtypes = [vp, P(ctypes.c_double), i64]
+    lib.tt_kernel_get_coeff_cores.argtypes = [vp, P(ctypes.c_double), i64]
     lib.tt_kernel_get_cross.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(Decision), c_int]
     lib.tt_kernel_destroy.argtypes = [vp]
     lib.tt_kernel_last_error.argtypes = []

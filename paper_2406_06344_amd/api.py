@@ -66,9 +66,49 @@ def make_params(kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None,
     return p
 
 
-def _soa(P, dtype):
+def _soa(P, dtype, d=None, name="points"):
     """(N, d) points -> contiguous (d, N) on the current device."""
+    if P.dim() != 2 or (d is not None and P.shape[1] != d):
+        raise ValueError(f"{name}: expected shape (N, {d}), got {tuple(P.shape)}")
     return P.to(device="cuda", dtype=dtype).t().contiguous()
+
+
+def _chk(t, name, rows, cols):
+    """ValueError unless t is a (rows, cols) matrix (rows None: any); checked
+    before anything reaches the device, since the library trusts sizes."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if t.dim() != 2 or (rows is not None and t.shape[0] != rows) or t.shape[1] != cols:
+        raise ValueError(f"{name}: expected shape ({'B' if rows is None else rows}, {cols}), got {tuple(t.shape)}")
+    return t
+
+
+def _dev(t, dtype):
+    return None if t is None else t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _out(t, name, shape, dtype):
+    """A caller-supplied output: exactly this shape and dtype, contiguous, on the GPU."""
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous cuda {dtype} tensor of shape {tuple(shape)}, got "
+                         f"{tuple(t.shape)} {t.dtype} on {t.device} (contiguous={t.is_contiguous()})")
+    return t
+
+
+def _theta(theta, d_theta, dtype, B=None, convert=True):
+    """theta as a contiguous (B, max(d_theta, 1)) device tensor.  Accepts
+    (B, d_theta), or (B,) when d_theta <= 1; B must match when given.
+    convert=False: validate and reshape only."""
+    w = max(d_theta, 1)
+    if theta is None:
+        if d_theta == 0:
+            return None            # no parameters: M = I
+        raise ValueError("theta is required")
+    if theta.dim() == 1 and w == 1:
+        theta = theta.reshape(-1, 1)
+    if theta.dim() != 2 or theta.shape[1] != w or (B is not None and theta.shape[0] != B):
+        raise ValueError(f"theta: expected shape ({'B' if B is None else B}, {w}), got {tuple(theta.shape)}")
+    return theta.to(device="cuda", dtype=dtype).contiguous() if convert else theta
 
 
 class TTKernel:
@@ -92,8 +132,8 @@ class TTKernel:
         """Y = None (or Y is X) with symmetric_psd=True builds PTTK-Global-1."""
         lib = _lib.load()
         p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, tol, dtype, **kw)
-        Xs = _soa(X, dtype)
-        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype)
+        Xs = _soa(X, dtype, d, "X")
+        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype, d, "Y")
         h = ctypes.c_void_p()
         st = check(lib.tt_kernel_build_offline(ctypes.byref(p), _ptr(Xs), Xs.shape[1], _ptr(Ys), Ys.shape[1],
                                                _stream_ptr(stream), ctypes.byref(h)))
@@ -109,8 +149,10 @@ class TTKernel:
         flat = np.concatenate([np.asarray(c, np.float64).reshape(-1, order="F") for c in cores])
         r_arr = (ctypes.c_int * len(ranks))(*ranks)
         c_arr = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        Xs = _soa(X, dtype)
-        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype)
+        if len(cores) != 2 * int(d) + KIND_DTHETA[kind]:
+            raise ValueError(f"cores: expected {2 * int(d) + KIND_DTHETA[kind]} cores, got {len(cores)}")
+        Xs = _soa(X, dtype, d, "X")
+        Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype, d, "Y")
         h = ctypes.c_void_p()
         check(lib.tt_kernel_build_from_cores(ctypes.byref(p), r_arr, c_arr, _ptr(Xs), Xs.shape[1], _ptr(Ys),
                                              Ys.shape[1], _stream_ptr(stream), ctypes.byref(h)))
@@ -160,6 +202,22 @@ class TTKernel:
             off += s
         return out
 
+    def coeff_cores(self):
+        """Coefficient-basis cores (Chebyshev basis along mode 2), float64."""
+        inf = self.info()
+        r = inf["ranks"]
+        n = [self.params.n_spatial] * self.params.d + [self.params.n_param] * self.params.d_theta + \
+            [self.params.n_spatial] * self.params.d
+        sizes = [r[k] * n[k] * r[k + 1] for k in range(inf["D"])]
+        buf = np.zeros(sum(sizes))
+        check(_lib.load().tt_kernel_get_coeff_cores(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                    buf.size))
+        out, off = [], 0
+        for k, s in enumerate(sizes):
+            out.append(buf[off:off + s].reshape((r[k], n[k], r[k + 1]), order="F"))
+            off += s
+        return out
+
     def cross_record(self):
         inf = self.info()
         D = inf["D"]
@@ -186,23 +244,30 @@ class TTKernel:
 
     def factor_rows(self, P, side=0, out=None, stream=None):
         """Rows of U (side 0) or V (side 1) for points P (n, d) of the same box."""
-        Ps = _soa(P, self.dtype)
+        if side not in (0, 1):
+            raise ValueError("side must be 0 (sources) or 1 (targets)")
+        Ps = _soa(P, self.dtype, self.params.d, "P")
         n = Ps.shape[1]
         r = self.r_s if side == 0 else self.r_t
         if out is None:
             out = torch.empty((n, r), dtype=self.dtype, device="cuda")
+        _out(out, "out", (n, r), self.dtype)
         check(_lib.load().tt_kernel_factor_rows(self._h, side, _ptr(Ps), n, _ptr(out), _stream_ptr(stream)))
         return out
 
     def factor_rows_soa(self, Ps, side, out, stream=None):
         """As factor_rows for points already in (d, n) device layout; no allocation."""
+        if side not in (0, 1):
+            raise ValueError("side must be 0 (sources) or 1 (targets)")
+        _out(Ps, "Ps", (self.params.d, Ps.shape[1] if Ps.dim() == 2 else -1), self.dtype)
+        _out(out, "out", (Ps.shape[1], self.r_s if side == 0 else self.r_t), self.dtype)
         check(_lib.load().tt_kernel_factor_rows(self._h, side, _ptr(Ps), Ps.shape[1], _ptr(out),
                                                 _stream_ptr(stream)))
         return out
 
     # ------------------------------------------------------------ online
     def online_core(self, theta, deriv=False, stream=None):
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        theta = _theta(theta, self.d_theta, self.dtype)
         B = theta.shape[0]
         M = torch.empty((B, self.r_t, self.r_s), dtype=self.dtype, device="cuda")
         dM = torch.empty((B, max(self.d_theta, 1), self.r_t, self.r_s), dtype=self.dtype,
@@ -213,34 +278,39 @@ class TTKernel:
 
     def apply(self, theta, X, save_w=False, stream=None):
         """y_b = U M(theta_b) V^T x_b for every row x_b of X (B, N_t)."""
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
-        X = X.to(device="cuda", dtype=self.dtype).contiguous()
-        B = X.shape[0]
+        B = _chk(X, "X", None, self.n_tgt).shape[0]
+        theta = _dev(_theta(theta, self.d_theta, self.dtype, B, convert=False), self.dtype)
+        X = _dev(X, self.dtype)
         Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
         W = torch.empty((B, self.r_t), dtype=self.dtype, device="cuda") if save_w else None
-        check(_lib.load().tt_kernel_apply(self._h, _ptr(theta), B, _ptr(X), self.n_tgt, _ptr(Y), self.n_src,
+        check(_lib.load().tt_kernel_apply(self._h, _ptr(theta), B, _ptr(X), X.stride(0), _ptr(Y), Y.stride(0),
                                           _ptr(W), _stream_ptr(stream)))
         return (Y, W) if save_w else Y
 
     def apply_plain(self, theta, X, stream=None):
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
-        X = X.to(device="cuda", dtype=self.dtype).contiguous()
-        B = X.shape[0]
+        B = _chk(X, "X", None, self.n_tgt).shape[0]
+        theta = _dev(_theta(theta, self.d_theta, self.dtype, B, convert=False), self.dtype)
+        X = _dev(X, self.dtype)
         Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
-        check(_lib.load().tt_kernel_apply_plain(self._h, _ptr(theta), B, _ptr(X), self.n_tgt, _ptr(Y),
-                                                self.n_src, _stream_ptr(stream)))
+        check(_lib.load().tt_kernel_apply_plain(self._h, _ptr(theta), B, _ptr(X), X.stride(0), _ptr(Y),
+                                                Y.stride(0), _stream_ptr(stream)))
         return Y
 
     def apply_backward(self, theta, G, X=None, W=None, want_dx=True, want_dtheta=True, stream=None):
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
-        G = G.to(device="cuda", dtype=self.dtype).contiguous()
-        B = G.shape[0]
+        B = _chk(G, "G", None, self.n_src).shape[0]
+        theta = _theta(theta, self.d_theta, self.dtype, B, convert=False)
+        if X is not None:
+            _chk(X, "X", B, self.n_tgt)
+        want_dth = want_dtheta and self.d_theta > 0
+        if W is not None:
+            _out(W, "W", (B, self.r_t), self.dtype)
+        elif want_dth and X is None:
+            raise ValueError("dtheta needs X or the W saved by apply(save_w=True)")
+        theta, G, Xc = _dev(theta, self.dtype), _dev(G, self.dtype), _dev(X, self.dtype)
         dX = torch.empty((B, self.n_tgt), dtype=self.dtype, device="cuda") if want_dx else None
-        dth = torch.empty((B, max(self.d_theta, 1)), dtype=self.dtype,
-                          device="cuda") if (want_dtheta and self.d_theta > 0) else None
-        Xc = X.to(device="cuda", dtype=self.dtype).contiguous() if X is not None else None
+        dth = torch.empty((B, max(self.d_theta, 1)), dtype=self.dtype, device="cuda") if want_dth else None
         check(_lib.load().tt_kernel_apply_backward(self._h, _ptr(theta), B, _ptr(Xc), self.n_tgt, _ptr(W),
-                                                   _ptr(G), self.n_src, _ptr(dX), self.n_tgt, _ptr(dth),
+                                                   _ptr(G), G.stride(0), _ptr(dX), self.n_tgt, _ptr(dth),
                                                    _stream_ptr(stream)))
         return dX, dth
 
@@ -263,7 +333,7 @@ class TTKernel:
         k = ctypes.c_int()
         check(lib.tt_kernel_global_factors(self._h, ctypes.byref(k), None, None, _stream_ptr(stream)))
         k = k.value
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+        theta = _theta(theta, self.d_theta, self.dtype)
         B = theta.shape[0]
         W = torch.empty((B, k, k), dtype=self.dtype, device="cuda")
         check(lib.tt_kernel_global_online(self._h, _ptr(theta), B, _ptr(W), _stream_ptr(stream)))
@@ -273,15 +343,21 @@ class TTKernel:
         """y_b = Q W_b Q^T x_b for rows x_b of X (B, N); theta (B, d_theta) or W (B, k, k)."""
         if (theta is None) == (W is None):
             raise ValueError("give exactly one of theta and W")
-        X = X.to(device="cuda", dtype=self.dtype).contiguous()
-        B = X.shape[0]
+        B = _chk(X, "X", None, self.n_src).shape[0]
+        if theta is not None:
+            _theta(theta, self.d_theta, self.dtype, B, convert=False)
+        X = _dev(X, self.dtype)
         Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
         th = None
         Wc = None
         if theta is not None:
-            th = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
+            th = _theta(theta, self.d_theta, self.dtype, B)
         else:
-            Wc = W.transpose(1, 2).contiguous()   # column-major per matrix
+            k = ctypes.c_int()
+            check(_lib.load().tt_kernel_global_factors(self._h, ctypes.byref(k), None, None, _stream_ptr(stream)))
+            if W.dim() != 3 or tuple(W.shape) != (B, k.value, k.value):
+                raise ValueError(f"W: expected shape ({B}, {k.value}, {k.value}), got {tuple(W.shape)}")
+            Wc = W.to(device="cuda", dtype=self.dtype).transpose(1, 2).contiguous()   # column-major per matrix
         check(_lib.load().tt_kernel_global_apply(self._h, _ptr(th), _ptr(Wc), B, _ptr(X), self.n_src, _ptr(Y),
                                                  self.n_src, _stream_ptr(stream)))
         return Y
@@ -316,6 +392,12 @@ def eval_entries(idx, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param
     """f_kappa at grid multi-indices idx (P, D) int32, on the device, float64."""
     lib = _lib.load()
     p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, kernel_const=kernel_const)
+    D = 2 * int(d) + KIND_DTHETA[kind]
+    if idx.dim() != 2 or idx.shape[1] != D:
+        raise ValueError(f"idx: expected shape (P, {D}), got {tuple(idx.shape)}")
+    n = [p.n_spatial] * int(d) + [p.n_param] * KIND_DTHETA[kind] + [p.n_spatial] * int(d)
+    if idx.numel() and (int(idx.min()) < 0 or any(int(idx[:, j].max()) >= n[j] for j in range(D))):
+        raise ValueError("idx: node index out of range")
     idx = idx.to(device="cuda", dtype=torch.int32).contiguous()
     out = torch.empty(idx.shape[0], dtype=torch.float64, device="cuda")
     check(lib.tt_kernel_eval_entries(ctypes.byref(p), _ptr(idx), idx.shape[0], _ptr(out), _stream_ptr(stream)))
@@ -327,7 +409,9 @@ def eval_dense(X, Y, theta, kind, d, dtype=torch.float64, kernel_const=0.0, stre
     lib = _lib.load()
     p = make_params(kind, d, [[0, 1]] * d, [[0, 1]] * d, [[0, 1]] * KIND_DTHETA[kind], dtype=dtype,
                     kernel_const=kernel_const)
-    Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+    if np.size(theta) != KIND_DTHETA[kind]:
+        raise ValueError(f"theta: expected {KIND_DTHETA[kind]} values, got {np.size(theta)}")
+    Xs, Ys = _soa(X, dtype, d, "X"), _soa(Y, dtype, d, "Y")
     nx, ny = Xs.shape[1], Ys.shape[1]
     K = torch.empty((ny, nx), dtype=dtype, device="cuda")       # column-major nx x ny
     th = (ctypes.c_double * 2)(*([float(v) for v in np.ravel(theta)] + [0.0, 0.0])[:2])
@@ -365,7 +449,10 @@ class TTBatch:
                 arr[i].box_t[j] = bt[j]
             arr[i].src_off, arr[i].n_src = int(q["src_off"]), int(q["n_src"])
             arr[i].tgt_off, arr[i].n_tgt = int(q["tgt_off"]), int(q["n_tgt"])
-        Xs, Ys = _soa(X, dtype), _soa(Y, dtype)
+            if arr[i].src_off < 0 or arr[i].n_src < 0 or arr[i].src_off + arr[i].n_src > X.shape[0] or \
+                    arr[i].tgt_off < 0 or arr[i].n_tgt < 0 or arr[i].tgt_off + arr[i].n_tgt > Y.shape[0]:
+                raise ValueError(f"pair {i}: point range outside X ({X.shape[0]}) or Y ({Y.shape[0]})")
+        Xs, Ys = _soa(X, dtype, d, "X"), _soa(Y, dtype, d, "Y")
         h = ctypes.c_void_p()
         st = check(lib.tt_kernel_batch_build(ctypes.byref(p), arr, len(pairs), _ptr(Xs), Xs.shape[1], _ptr(Ys),
                                              Ys.shape[1], _stream_ptr(stream), ctypes.byref(h)))
@@ -386,11 +473,15 @@ class TTBatch:
 
     def refactor(self, X, Y, stream=None):
         """Phase 3 again for points (same layout); returns the SoA copies used."""
-        Xs, Ys = _soa(X, self.dtype), _soa(Y, self.dtype)
+        if X.shape[0] != self.n_x or Y.shape[0] != self.n_y:
+            raise ValueError(f"X, Y: expected {self.n_x} and {self.n_y} points")
+        Xs, Ys = _soa(X, self.dtype, self.params.d, "X"), _soa(Y, self.dtype, self.params.d, "Y")
         check(_lib.load().tt_kernel_batch_factor(self._h, _ptr(Xs), _ptr(Ys), _stream_ptr(stream)))
         return Xs, Ys
 
     def refactor_soa(self, Xs, Ys, stream=None):
+        _out(Xs, "Xs", (self.params.d, self.n_x), self.dtype)
+        _out(Ys, "Ys", (self.params.d, self.n_y), self.dtype)
         check(_lib.load().tt_kernel_batch_factor(self._h, _ptr(Xs), _ptr(Ys), _stream_ptr(stream)))
 
     def info(self):
@@ -432,18 +523,25 @@ class TTBatch:
     def apply(self, theta, X, G=None, want_dx=True, want_dtheta=True, out=None, stream=None):
         """Y (B, n_x) = sum over pairs; with G (B, n_x) also dX (B, n_y) and dtheta (B, d_theta).
         out: optional (Y, dX, dtheta) tensors to write into (keeps the captured graph valid)."""
-        theta = theta.to(device="cuda", dtype=self.dtype).reshape(-1, max(self.d_theta, 1)).contiguous()
-        X = X.to(device="cuda", dtype=self.dtype).contiguous()
-        B = X.shape[0]
+        B = _chk(X, "X", None, self.n_y).shape[0]
+        theta = _theta(theta, self.d_theta, self.dtype, B, convert=False)
+        if G is not None:
+            _chk(G, "G", B, self.n_x)
+        theta, X = _dev(theta, self.dtype), _dev(X, self.dtype)
         if out is not None:
             Y, dX, dth = out
+            _out(Y, "out[0] (Y)", (B, self.n_x), self.dtype)
+            if G is not None and dX is not None:
+                _out(dX, "out[1] (dX)", (B, self.n_y), self.dtype)
+            if G is not None and dth is not None and self.d_theta > 0:
+                _out(dth, "out[2] (dtheta)", (B, self.d_theta), self.dtype)
         else:
             Y = torch.empty((B, self.n_x), dtype=self.dtype, device="cuda")
             dX = torch.empty((B, self.n_y), dtype=self.dtype, device="cuda") if (G is not None and want_dx) \
                 else None
             dth = torch.empty((B, max(self.d_theta, 1)), dtype=self.dtype, device="cuda") \
                 if (G is not None and want_dtheta and self.d_theta > 0) else None
-        Gc = G.to(device="cuda", dtype=self.dtype).contiguous() if G is not None else None
+        Gc = _dev(G, self.dtype)
         check(_lib.load().tt_kernel_batch_apply(self._h, _ptr(theta), B, _ptr(X), self.n_y, _ptr(Y), self.n_x,
                                                 _ptr(Gc), self.n_x, _ptr(dX), self.n_y, _ptr(dth),
                                                 _stream_ptr(stream)))

@@ -711,6 +711,43 @@ tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity) {
   return TTK_OK;
 }
 
+tt_status tt_kernel_get_coeff_cores(tt_kernel_t h, double* cores, int64_t capacity) {
+  if (!h || !cores) return fail(TTK_ERR_ARG, "NULL argument");
+  const int d = h->g.d, dt = h->g.dt, D = h->g.D;
+  size_t need = 0;
+  for (int k = 0; k < D; ++k) need += (size_t)h->ranks[k] * h->g.n[k] * h->ranks[k + 1];
+  if ((size_t)capacity < need) return fail(TTK_ERR_ARG, "capacity %lld < %zu", (long long)capacity, need);
+  std::vector<double> tmp;
+  std::vector<float> tmpf;
+  size_t off = 0;
+  for (int k = 0; k < D; ++k) {
+    const int r0 = h->ranks[k], n = h->g.n[k], r1 = h->ranks[k + 1];
+    const size_t cnt = (size_t)r0 * n * r1;
+    if (k >= d && k < d + dt) {   // parameter core: FP64, little-endian already
+      TTK_HIP(hipMemcpy(cores + off, h->pcore[k - d].p, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      // Phase 3 layout: source stage (a + i r0) r1 + b, target stage (b + i r1) r0 + a
+      const DBuf& sb = h->stage[k < d ? k : 3 + (D - 1 - k)];
+      tmp.resize(cnt);
+      if (h->dtype == TTK_FP32) {
+        tmpf.resize(cnt);
+        TTK_HIP(hipMemcpy(tmpf.data(), sb.p, cnt * sizeof(float), hipMemcpyDeviceToHost));
+        for (size_t e = 0; e < cnt; ++e) tmp[e] = tmpf[e];
+      } else {
+        TTK_HIP(hipMemcpy(tmp.data(), sb.p, cnt * sizeof(double), hipMemcpyDeviceToHost));
+      }
+      for (int b = 0; b < r1; ++b)
+        for (int i = 0; i < n; ++i)
+          for (int a = 0; a < r0; ++a) {
+            const size_t src = k < d ? ((size_t)a + (size_t)i * r0) * r1 + b : ((size_t)b + (size_t)i * r1) * r0 + a;
+            cores[off + a + (size_t)i * r0 + (size_t)b * r0 * n] = tmp[src];
+          }
+    }
+    off += cnt;
+  }
+  return TTK_OK;
+}
+
 tt_status tt_kernel_get_cross(tt_kernel_t h, int32_t* left, int32_t* right, tt_kernel_decision* decisions,
                               int max_decisions) {
   if (!h) return fail(TTK_ERR_ARG, "NULL handle");

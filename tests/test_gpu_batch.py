@@ -201,9 +201,27 @@ def test_batch_argument_errors():
     from paper_2406_06344_amd._lib import TTKError
     ps, X, Y = make_pairs(2, [([0, 0], [2, 0])], 0.25, [(10, 10)], seed=1)
     bad = [dict(ps[0], n_src=11)]              # past the end of X
-    with pytest.raises(TTKError, match="ERR_ARG"):
+    # the binding refuses it before the library sees it ...
+    with pytest.raises(ValueError, match="point range"):
         pkg.TTBatch.build(bad, torch.tensor(X), torch.tensor(Y), "matern32", 2, [[0.5, 2.0]], n_spatial=6,
                           tol=1e-6, dtype=torch.float64)
+    # ... and so does the C ABI itself, called directly
+    import ctypes
+    from paper_2406_06344_amd import _lib, api
+    lib = _lib.load()
+    p = api.make_params("matern32", 2, [[0, 1]] * 2, [[2, 3]] * 2, [[0.5, 2.0]], 6, None, 1e-6, torch.float64)
+    arr = (_lib.Pair * 1)()
+    for j, v in enumerate(np.asarray(bad[0]["box_s"], float).reshape(-1)):
+        arr[0].box_s[j] = v
+    for j, v in enumerate(np.asarray(bad[0]["box_t"], float).reshape(-1)):
+        arr[0].box_t[j] = v
+    arr[0].src_off, arr[0].n_src, arr[0].tgt_off, arr[0].n_tgt = 0, 11, 0, 10
+    Xs = torch.tensor(X).cuda().t().contiguous()
+    Ys = torch.tensor(Y).cuda().t().contiguous()
+    h = ctypes.c_void_p()
+    st = lib.tt_kernel_batch_build(ctypes.byref(p), arr, 1, ctypes.c_void_p(Xs.data_ptr()), Xs.shape[1],
+                                   ctypes.c_void_p(Ys.data_ptr()), Ys.shape[1], None, ctypes.byref(h))
+    assert st == -1 and not h.value
     with pytest.raises(TTKError, match="ERR_ARG"):
         pkg.TTBatch.build([], torch.tensor(X), torch.tensor(Y), "matern32", 2, [[0.5, 2.0]], n_spatial=6,
                           tol=1e-6, dtype=torch.float64)

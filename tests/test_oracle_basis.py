@@ -115,3 +115,58 @@ def test_below_range():
     g = rng.keyed(3, 1)
     v = [g.below(7) for _ in range(2000)]
     assert min(v) == 0 and max(v) == 6
+
+
+# -------------------------------------------------- coefficient tensor
+def test_coefficient_route_equals_lagrange_route():
+    """The interpolant as sum_k A[k] prod T_k (A = DCT along every mode) equals
+    sum_i M[i] prod l_i at random off-grid points (Section 2.4's regrouping)."""
+    rng = np.random.default_rng(0)
+    n = (5, 6, 4, 7)
+    boxes = [(0.0, 1.0), (2.0, 3.5), (-1.0, 0.5), (0.5, 2.0)]
+    M = rng.standard_normal(n)
+    A = basis.coefficient_tensor(M)
+    pts = np.stack([rng.uniform(a, b, 200) for a, b in boxes], axis=1)
+    v_coef = basis.interpolant_coefficient_form(A, boxes, pts)
+    v_lag = basis.interpolant_lagrange_form(M, boxes, pts)
+    assert np.abs(v_coef - v_lag).max() <= 1e-13 * np.abs(v_lag).max()
+
+
+def test_coefficient_tensor_recovers_known_coefficients():
+    """Grid values of sum_k A0[k] prod T_k, formed with numpy's Chebyshev
+    Vandermonde matrices at the nodes (t(eta_i) = zeta_i), give back A0."""
+    rng = np.random.default_rng(1)
+    n = (4, 7, 5)
+    A0 = rng.standard_normal(n)
+    M = A0
+    for j, nj in enumerate(n):
+        V = npcheb.chebvander(basis.cheb_nodes(nj), nj - 1)        # V[i, k] = T_k(zeta_i)
+        M = np.moveaxis(np.tensordot(V, M, axes=([1], [j])), 0, j)
+    assert np.abs(basis.coefficient_tensor(M) - A0).max() <= 1e-13 * np.abs(A0).max()
+
+
+@pytest.mark.parametrize("n", [3, 8, 16])
+def test_coefficients_match_numpy_chebinterpolate(n):
+    """One mode against numpy's interpolation at first-kind Chebyshev points.
+    On [-1, 1] the printed map sends zeta to -zeta, so t = -x and the
+    coefficients differ by (-1)^k."""
+    f = lambda x: np.exp(0.7 * x) * np.cos(2.0 * x)
+    eta = basis.grid_nodes(-1.0, 1.0, n)
+    ours = basis.coefficient_tensor(f(eta))
+    ref = npcheb.chebinterpolate(f, n - 1)
+    assert np.abs(ours - ref * (-1.0) ** np.arange(n)).max() <= 1e-14 * np.abs(ref).max() * n
+
+
+def test_polynomial_kernel_has_no_high_coefficients():
+    """(1 + theta x.y)^3 has degree 3 in each variable: every coefficient with
+    an index above 3 in any mode vanishes (Proposition 2, exact case)."""
+    from oracle import kernels
+    P = kernels.Problem("poly", 1, [[0, 1]], [[2, 3]], [[0.5, 2.0]], 6)
+    A = basis.coefficient_tensor(P.full_tensor())
+    high = np.zeros(A.shape, bool)
+    for j in range(A.ndim):
+        idx = [slice(None)] * A.ndim
+        idx[j] = slice(4, None)
+        high[tuple(idx)] = True
+    assert np.abs(A[high]).max() <= 1e-13 * np.abs(A).max()
+    assert np.abs(A[3, 3, 3]) > 1e-7 * np.abs(A).max()     # degree exactly 3 in each mode

@@ -165,18 +165,50 @@ def test_prop1_tt_error_amplification_bound():
     assert worst <= lam ** 3 * np.abs(M - Mh).max() * (1 + 1e-12)
 
 
-def test_replay_band_widening_is_capped():
-    """The replay band widens by the disagreement the forced computation shows
-    on the same residuals, but a disagreement above 10 tau fails the check."""
+def test_replay_band_ignores_values_reported_by_the_replayed_computation():
+    """The replay judges a forced choice by the oracle's own residuals and
+    noise estimate: residual values carried in the forced record (however
+    wrong) change nothing, and a wrong pivot stays flagged."""
     P = kernels.Problem("matern32", 1, [[0, 1]], [[2, 3]], [[0.5, 2.0]], 8)
     ent = cross.Entries(P.entries, P.n)
     L, R, _ = cross.greedy_init(ent, 4)
     cp = lambda S: [None if x is None else x.copy() for x in S]
     good = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256)
-    tau = good["tau"]
-    near = dict(good, sample_max=good["sample_max"] + 5 * tau, pivot_abs=good["pivot_abs"] + 5 * tau)
-    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=near)
+    choice = {k: good[k] for k in ("sample_pos", "pivot_row", "pivot_col", "added")}
+    ref = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=choice)
+    junk = dict(choice, sample_max=1e30, pivot_abs=-5.0)
+    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=junk)
+    for key in ("replay_sample_ok", "replay_search_ok", "replay_add_ok", "noise", "tau"):
+        assert rec[key] == ref[key], key
     assert rec["replay_sample_ok"] and rec["replay_search_ok"] and rec["replay_add_ok"]
-    far = dict(good, sample_max=good["sample_max"] + 11 * tau)
-    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=far)
-    assert not rec["replay_sample_ok"] and not rec["replay_search_ok"]
+    bad = dict(choice)
+    if good["bit"] == 1:
+        bad["pivot_col"] = (good["pivot_col"] + 1) % 8
+    else:
+        bad["pivot_row"] = (good["pivot_row"] + 1) % 8
+    bad["pivot_abs"] = good["pivot_abs"]            # claiming the right value does not help
+    rec = cross.update_cross(ent, cp(L), cp(R), 1, 0, 4, 256, forced=bad)
+    assert not rec["replay_search_ok"]
+
+
+def test_residual_noise_estimate_is_rounding_sized():
+    """The three FP64 orders of the skeleton residual agree to rounding of a
+    well-conditioned intersection matrix, and the disagreement grows with its
+    condition number, as a forward-error bound of a linear solve does."""
+    rng = np.random.default_rng(3)
+    r, m = 12, 300
+    AxJ = rng.standard_normal((m, r))
+    AIy = rng.standard_normal((r, m))
+    Axy = rng.standard_normal(m)
+    Qa, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    Qb, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    spreads = []
+    for cond in (1.0, 1e6, 1e12):
+        P = Qa @ np.diag(np.logspace(0, -np.log10(cond), r)) @ Qb
+        Rr, spread = cross._skeleton_residuals(P, AxJ, AIy, Axy)
+        exact = np.einsum("mr,rm->m", AxJ, np.linalg.solve(P, AIy)) - Axy
+        assert np.array_equal(Rr, exact)
+        scale = np.abs(Rr).max()
+        assert spread <= 1e3 * np.finfo(float).eps * cond * scale
+        spreads.append(spread / scale)
+    assert spreads[0] < 1e-13 and spreads[2] > spreads[0]

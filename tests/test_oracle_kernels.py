@@ -61,16 +61,90 @@ def test_dkappa_dtheta_central_difference(kind, theta):
         assert np.allclose(g[:, j], fd, rtol=1e-7, atol=1e-12)
 
 
-def test_kernel_table_closed_forms():
-    r = np.array([0.5, 1.0, 2.0])
-    th = np.array([[2.0]] * 3)
-    assert np.allclose(kernels.kappa_r("se", r, th), np.exp(-(r / 2) ** 2))
-    assert np.allclose(kernels.kappa_r("mq", r, th), np.sqrt(1 + (r / 2) ** 2))
-    assert np.allclose(kernels.kappa_r("tps", r, th), (r / 2) ** 2 * np.log((r / 2) ** 2))
-    assert np.allclose(kernels.kappa_r("laplace3d", r, th), 1 / r)
-    assert np.allclose(kernels.kappa_r("laplace2d", r, th), -np.log(r))
-    assert np.allclose(kernels.kappa_r("biharmonic", r, th), r ** -2)
-    assert np.allclose(kernels.kappa_r("thinplate", r, th), r * r * np.log(r))
+def _laplacian(f, x, h=1e-3):
+    """Five-point-per-axis finite-difference Laplacian (fourth order) of f at x (P, dim)."""
+    out = np.zeros(x.shape[0])
+    for j in range(x.shape[1]):
+        e = np.zeros(x.shape[1])
+        e[j] = h
+        out += (-f(x + 2 * e) + 16 * f(x + e) - 30 * f(x) + 16 * f(x - e) - f(x - 2 * e)) / (12 * h * h)
+    return out
+
+
+@pytest.mark.parametrize("kind,dim", [("laplace3d", 3), ("laplace2d", 2), ("biharmonic", 4)])
+def test_potential_kernels_are_harmonic(kind, dim):
+    """Laplace-3D (1/r) and Laplace-2D (-log r) are the free-space Green's
+    functions of the Laplacian in 3 and 2 dimensions, and r^-2 is harmonic in
+    4 dimensions: their Laplacian vanishes away from r = 0.  A wrong power or
+    a wrong log would not be."""
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0.6, 1.4, (20, dim)) * rng.choice([-1, 1], (20, dim))
+    f = lambda z: kernels.kappa_r(kind, np.sqrt((z ** 2).sum(axis=1)), np.zeros((z.shape[0], 0)))
+    lap = _laplacian(f, x)
+    scale = np.abs(f(x)) / (np.sqrt((x ** 2).sum(axis=1)) ** 2)      # size of each second-derivative term
+    assert np.abs(lap).max() <= 1e-6 * scale.max()
+    # and not harmonic one dimension off (the check has teeth)
+    if dim > 2:
+        f_low = lambda z: kernels.kappa_r(kind, np.sqrt((z ** 2).sum(axis=1)), np.zeros((z.shape[0], 0)))
+        assert np.abs(_laplacian(f_low, x[:, :dim - 1])).max() > 1e-2 * scale.max()
+
+
+def test_thinplate_is_biharmonic_in_2d():
+    """r^2 log r is the Green's function of the biharmonic operator in 2-D:
+    Delta^2 vanishes away from 0 (Delta(r^2 log r) = 4 log r + 4)."""
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.7, 1.3, (15, 2)) * rng.choice([-1, 1], (15, 2))
+    f = lambda z: kernels.kappa_r("thinplate", np.sqrt((z ** 2).sum(axis=1)), np.zeros((z.shape[0], 0)))
+    lap = lambda z: _laplacian(f, z, h=2e-3)
+    r = np.sqrt((x ** 2).sum(axis=1))
+    assert np.allclose(lap(x), 4 * np.log(r) + 4, rtol=0, atol=1e-6)
+    assert np.abs(_laplacian(lap, x, h=2e-2)).max() <= 1e-3
+
+
+def test_tps_extremum_and_zeros():
+    """(r/l)^2 log((r/l)^2) = u log u with u = (r/l)^2: zero at r = l and at
+    r -> 0, minimum -1/e at u = 1/e."""
+    ell = 1.7
+    th = np.array([[ell]])
+    assert abs(kernels.kappa_r("tps", np.array([ell]), th)[0]) <= 1e-15
+    assert kernels.kappa_r("tps", np.array([0.0]), th)[0] == 0.0
+    r = np.linspace(1e-3, 2 * ell, 20001)
+    v = kernels.kappa_r("tps", r, np.full((r.size, 1), ell))
+    i = np.argmin(v)
+    assert abs(v[i] + 1 / math.e) <= 1e-7 and abs(r[i] - ell / math.sqrt(math.e)) <= 2 * (r[1] - r[0])
+
+
+def test_multiquadric_is_a_hyperbola():
+    """sqrt(1 + (r/l)^2): its square is a quadratic in r with value 1 at 0 and
+    2 at r = l (third differences of the square vanish)."""
+    ell = 0.8
+    r = np.linspace(0.0, 3.0, 31)
+    v2 = kernels.kappa_r("mq", r, np.full((31, 1), ell)) ** 2
+    assert np.abs(np.diff(v2, 3)).max() <= 1e-12
+    assert abs(kernels.kappa_r("mq", np.array([ell]), np.array([[ell]]))[0] - math.sqrt(2.0)) <= 1e-15
+    assert kernels.kappa_r("mq", np.array([0.0]), np.array([[ell]]))[0] == 1.0
+
+
+def test_se_gaussian_integral():
+    """The SE kernel integrates to (pi l^2)^(3/2) over R^3 (Gaussian integral),
+    by radial quadrature of the oracle's values."""
+    from scipy import integrate
+    ell = 0.7
+    val, _ = integrate.quad(lambda r: 4 * math.pi * r * r * kernels.kappa_r("se", np.array([r]),
+                                                                            np.array([[ell]]))[0], 0, 20 * ell)
+    assert abs(val - (math.pi * ell * ell) ** 1.5) <= 1e-10 * val
+
+
+@pytest.mark.parametrize("nu,z", [(0.5, 1e-4), (1.1, 1e-3), (2.5, 1e-3), (1.1, 0.05), (0.5, 0.02)])
+def test_bessel_small_argument(nu, z):
+    """K_nu at small z (where the Matern kernel of coincident or near points
+    sits) against mpmath at 30 digits, and the leading term
+    Gamma(nu)/2 (2/z)^nu of its expansion."""
+    mpmath.mp.dps = 30
+    ref = float(mpmath.besselk(nu, z))
+    assert abs(special.kv(nu, z) - ref) <= 1e-13 * ref
+    lead = math.gamma(nu) / 2 * (2 / z) ** nu
+    assert abs(ref / lead - 1) < 0.1
 
 
 def test_entry_order_is_x_theta_y():

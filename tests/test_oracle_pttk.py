@@ -204,9 +204,46 @@ def test_global_symmetric_part_identity_and_psd():
     assert dense.rel_error(A, Z @ np.diag(Lc) @ Z.T) <= 1e-6 * 1.01 * np.linalg.norm(A) / np.linalg.norm(A)
 
 
-def test_storage_formula():
-    ranks = [1, 5, 9, 7, 6, 4, 1]
-    assert pttk.storage_floats(100, 80, ranks, 12, 2, 2) == 100 * 9 + 80 * 6 + 12 * 9 * 7 + 12 * 7 * 6
+def test_storage_formula_counts_the_stored_arrays():
+    """Section 3.2's storage count equals the number of floats the offline
+    stage actually produces (S, T and the parameter cores)."""
+    P = _tiny("matern", d=2, n=5)
+    rng = np.random.default_rng(8)
+    X = rng.uniform(0, 1, (23, 2))
+    Y = rng.uniform(2, 3, (19, 2))
+    out = driver.offline(P, X, Y, 1e-6, seed=0)
+    stored = out["S"].size + out["T"].size + sum(G.size for G in out["param"])
+    assert pttk.storage_floats(23, 19, out["ranks"], 5, 2, 2) == stored
+
+
+def test_sign_rule_on_both_sides():
+    """R10: after the gauge, every column of a source/parameter core's G^{2}
+    and every row of a target core's G^{1} has its largest-|.| entry positive
+    (lowest index on ties); flipping signs by hand and re-applying the rule
+    restores the cores, and the represented tensor never changes."""
+    P = _tiny("matern", d=2, n=5)
+    M = P.full_tensor()
+    G = pttk.round_and_gauge(tt.tt_svd(M, 1e-10), 1e-12, 2, 2)
+    for g in G[4:]:
+        A = tt.g1(g)
+        piv = np.argmax(np.abs(A), axis=1)
+        assert np.all(A[np.arange(A.shape[0]), piv] > 0)
+    rng = np.random.default_rng(9)
+    s = rng.choice([-1.0, 1.0], G[5].shape[0])
+    s[0] = -1.0
+    flipped = G[5] * s[:, None, None]                   # flip rows of the last target core ...
+    prev = G[4] * s[None, None, :]                      # ... and compensate in its left neighbour
+    Gf = G[:4] + [prev, flipped]
+    assert np.linalg.norm(tt.full(Gf) - tt.full(G)) <= 1e-13 * np.linalg.norm(M)
+    g5, g4 = pttk.sign_fix_right(flipped, prev)
+    assert np.array_equal(g5, G[5]) and np.array_equal(g4, G[4])
+    # ties go to the lowest index: a row whose two largest entries are +-m
+    T = np.zeros((2, 3, 1))
+    T[0, :, 0] = [-2.0, 2.0, 1.0]
+    T[1, :, 0] = [1.0, 3.0, -3.0]
+    Pv = np.ones((1, 2, 2))
+    Tf, Pf = pttk.sign_fix_right(T, Pv)
+    assert Tf[0, 0, 0] == 2.0 and Tf[1, 1, 0] == 3.0 and Pf[0, 0, 0] == -1.0 and Pf[0, 0, 1] == 1.0
 
 
 def test_paper_phase4_preserves_product():
