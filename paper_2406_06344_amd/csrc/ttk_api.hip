@@ -304,8 +304,10 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
   TTK_HIP(hipStreamSynchronize(st));   // (Phase 3 is timed on its own below)
   h->rs = h->ranks[d];
   h->rt = h->ranks[d + dt];
-  h->ldu = h->rs;
-  h->ldv = h->rt;
+  // float32 rows padded for the matrix-core apply (columns past r are never
+  // read into a result); float64 rows packed
+  h->ldu = h->dtype == TTK_FP32 ? mfma_ld(h->rs) : h->rs;
+  h->ldv = h->dtype == TTK_FP32 ? mfma_ld(h->rt) : h->rt;
   TTK_TRY(h->U.alloc((size_t)std::max<int64_t>(h->ns, 1) * h->ldu * es));
   TTK_TRY(h->V.alloc((size_t)std::max<int64_t>(h->nt, 1) * h->ldv * es));
   auto t0 = std::chrono::steady_clock::now();
@@ -492,8 +494,7 @@ static tt_status reduce_into(tt_kernel_t h, const void* F, int ldf, int64_t N, i
                              int B, void* W, hipStream_t st) {
   const size_t wb = apply_reduce_work(N, r, B);
   if (wb) TTK_TRY(h->Pbuf.alloc(wb));
-  apply_reduce(h->dtype, F, ldf, N, r, X, ldx, B, W, wb ? h->Pbuf.p : nullptr, st);
-  return TTK_OK;
+  return apply_reduce(h->dtype, F, ldf, N, r, X, ldx, B, W, wb ? h->Pbuf.p : nullptr, st);
 }
 
 tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y, int64_t ldy,
@@ -512,7 +513,7 @@ tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X
   TTK_TRY(h->Zbuf.alloc((size_t)h->rs * B * h->es));
   TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, W, st));
   batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 0, W, B, h->Zbuf.p, st);
-  apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, h->Zbuf.p, B, Y, ldy, st);
+  TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, h->Zbuf.p, B, Y, ldy, st));
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
@@ -536,7 +537,7 @@ tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B, const v
     const char* Mb = h->Mbuf.as<char>() + (size_t)b * h->rs * h->rt * es;
     TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, xb, ldx, 1, wb, st));
     batched_matvec(h->dtype, Mb, h->rs, h->rt, 0, wb, 1, zb, st);
-    apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, zb, 1, yb, ldy, st);
+    TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, zb, 1, yb, ldy, st));
   }
   TTK_HIP(hipGetLastError());
   return TTK_OK;
@@ -559,7 +560,7 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
   if (dX) {
     TTK_TRY(h->Zbuf.alloc((size_t)std::max(h->rs, h->rt) * B * h->es));
     batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 1, h->Abuf.p, B, h->Zbuf.p, st);   // M^T a
-    apply_expand(h->dtype, h->V.p, h->ldv, h->nt, h->rt, h->Zbuf.p, B, dX, lddx, st);
+    TTK_TRY(apply_expand(h->dtype, h->V.p, h->ldv, h->nt, h->rt, h->Zbuf.p, B, dX, lddx, st));
   }
   if (want_dth) {
     const void* W = W_saved;
@@ -615,7 +616,7 @@ tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W
   TTK_TRY(h->Zbuf.alloc((size_t)k * B * h->es));
   TTK_TRY(reduce_into(h, h->Q.p, k, h->ns, k, X, ldx, B, h->Wbuf.p, st));        // Q^T x
   batched_matvec(h->dtype, W, k, k, 0, h->Wbuf.p, B, h->Zbuf.p, st);             // W (Q^T x)
-  apply_expand(h->dtype, h->Q.p, k, h->ns, k, h->Zbuf.p, B, Y, ldy, st);          // Q (...)
+  TTK_TRY(apply_expand(h->dtype, h->Q.p, k, h->ns, k, h->Zbuf.p, B, Y, ldy, st));          // Q (...)
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }

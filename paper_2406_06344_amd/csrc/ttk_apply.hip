@@ -3,8 +3,10 @@
 //     reduce:  W = F^T X   (r x B, F = S or T, N x r row-major, X N x B)
 //     expand:  Y = F Z     (N x B)
 // and small per-theta products done by batched_matvec / batched_bilinear.
-// Plain (B = 1): a GEMV pair, bound by reading F once.  Batched: register-
-// tiled GEMMs that read F once for all B columns.  Products are formed in
+// Plain (B = 1): a GEMV pair, bound by reading F once.  Batched: GEMMs that
+// read F once for all B columns: skinny kernels for B <= 16, the float32
+// matrix-core kernels of ttk_apply_mfma.hip for wider batches (r <= 128),
+// register-tiled VALU kernels otherwise (float64).  Products are formed in
 // the working precision and summed in double over point tiles (a float32
 // running sum over 10^5 points loses digits).  The plain and skinny reduces
 // write one double partial sum per workgroup and a second launch adds them
@@ -454,15 +456,15 @@ size_t apply_reduce_work(int64_t N, int r, int B) {
   if (N <= 0) return 0;
   if (B == 1) return (size_t)plain_groups(N) * r * sizeof(double);
   if (skinny(r, B)) return ((size_t)skinny_groups(N) + NRANGE) * r * B * sizeof(double);
-  return 0;
+  return apply_mfma_ok(r, B) ? apply_reduce_mfma_work(N, r, B) : 0;   // (float32 only; float64 needs none)
 }
 
-void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx, int B, void* W,
-                  void* work, hipStream_t st) {
+tt_status apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx, int B,
+                       void* W, void* work, hipStream_t st) {
   const size_t es = dtype == TTK_FP32 ? 4 : 8;
   if (N <= 0) {
     fill_zero(W, (size_t)r * B * es, st);
-    return;
+    return TTK_OK;
   }
   double* part = static_cast<double*>(work);
   if (B == 1) {
@@ -478,7 +480,7 @@ void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const voi
       hipLaunchKernelGGL(k_sum_partials<double>, dim3((r + 3) / 4), dim3(256), 0, st, (const double*)part, (int)g, r,
                          static_cast<double*>(W));
     }
-    return;
+    return TTK_OK;
   }
   if (skinny(r, B)) {
     const unsigned g = skinny_groups(N);
@@ -498,8 +500,11 @@ void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const voi
     else
       hipLaunchKernelGGL(k_sum_final<double>, dim3((count + 255) / 256), dim3(256), 0, st, (const double*)sums,
                          count, static_cast<double*>(W));
-    return;
+    return TTK_OK;
   }
+  if (dtype == TTK_FP32 && apply_mfma_ok(r, B))
+    return apply_reduce_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(X), ldx, B,
+                             static_cast<float*>(W), part, st);
   fill_zero(W, (size_t)r * B * es, st);
   const int rt = (r + 63) / 64, bt = (B + 63) / 64;
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>((N + 511) / 512, (4096 + rt * bt - 1) / (rt * bt)));
@@ -513,11 +518,12 @@ void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const voi
   else
     hipLaunchKernelGGL(k_reduce_tiled<double>, grid, dim3(256), 0, st, static_cast<const double*>(F), ldf, N, r,
                        static_cast<const double*>(X), ldx, B, chunk, static_cast<double*>(W));
+  return TTK_OK;
 }
 
-void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B, void* Y, int64_t ldy,
-                  hipStream_t st) {
-  if (N <= 0) return;
+tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B, void* Y,
+                       int64_t ldy, hipStream_t st) {
+  if (N <= 0) return TTK_OK;
   if (B == 1) {
     const unsigned g = grid_cap((N + 15) / 16, 8192);
     if (dtype == TTK_FP32)
@@ -526,7 +532,7 @@ void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const voi
     else
       hipLaunchKernelGGL(k_expand_plain<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
                          r, static_cast<const double*>(Z), static_cast<double*>(Y));
-    return;
+    return TTK_OK;
   }
   if (B <= SB && r <= SR) {
     const unsigned g = (unsigned)((N + ST - 1) / ST);
@@ -536,8 +542,11 @@ void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const voi
     else
       hipLaunchKernelGGL(k_expand_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N,
                          r, static_cast<const double*>(Z), B, static_cast<double*>(Y), ldy);
-    return;
+    return TTK_OK;
   }
+  if (dtype == TTK_FP32 && apply_mfma_ok(r, B))
+    return apply_expand_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(Z), B,
+                             static_cast<float*>(Y), ldy, st);
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((B + 63) / 64));
   if (dtype == TTK_FP32)
     hipLaunchKernelGGL(k_expand_tiled<float>, grid, dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
@@ -545,6 +554,7 @@ void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const voi
   else
     hipLaunchKernelGGL(k_expand_tiled<double>, grid, dim3(256), 0, st, static_cast<const double*>(F), ldf, N, r,
                        static_cast<const double*>(Z), B, static_cast<double*>(Y), ldy);
+  return TTK_OK;
 }
 
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x, int B, void* y,

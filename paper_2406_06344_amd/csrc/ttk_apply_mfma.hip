@@ -1,0 +1,478 @@
+// The two tall contractions of the batched apply and its backward pass
+// (the low-rank form of Section 1, y_b = S H(theta_b) T^T x_b, and its
+// adjoint) on the matrix cores, float32 in, float32 accumulate:
+//     expand:  Y (N x B) = F Z,    F = S or T (N x r row-major), Z r x B
+//     reduce:  W (r x B) = F^T X,  X N x B
+// Both are dense (N x r) by (r x B) products with N ~ 10^6, r <= 128 and B
+// in the thousands, so they are bound by the matrix cores (2 r flops per
+// byte of X or Y).  v_mfma_f32_16x16x4f32: lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and D[4 (l / 16) + v][l % 16] in register v.
+//
+// expand: a wave owns 64 points and keeps their rows of F as A operands in
+//   registers for the whole launch; the workgroup (4 waves, 256 points)
+//   walks the thetas in blocks of 64, each block of Z fetched into LDS by
+//   direct global->LDS loads while the previous block is multiplied.  Each
+//   K-step reads 4 B operands from LDS for 16 MFMAs.
+//   Output: register v of a lane is 4 consecutive points of one column of
+//   the column-major Y, stored as one 16-byte write.
+// reduce: a workgroup owns 128 thetas and one chunk of the points; blocks of
+//   64 points of X (column segments, 16-byte loads) and of F (contiguous
+//   rows) go through LDS; each wave owns 32 thetas by all r.  The float32
+//   MFMA sums of a 64-point block are folded into float64 accumulators, the
+//   chunk's sums are written as float64 partials, and k_sum_chunks adds the
+//   chunks in a fixed order (deterministic, no atomics).
+#include "ttk_internal.h"
+
+namespace ttk {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// ------------------------------------------------------------------ expand
+constexpr int EX_PW = 64;             // points per wave
+constexpr int EX_P = 4 * EX_PW;       // points per workgroup
+constexpr int EX_TB = 64;             // thetas per staged block of Z
+
+// LDS of the expand: two buffers of a Z block (EX_TB columns of r values, as
+// they lie in memory) plus KP floats of padding, so K-step reads past r of
+// the last column stay inside the buffer.
+inline size_t expand_lds_floats(int r, int kp) { return (size_t)2 * (EX_TB * r + kp); }
+
+// KS = K-steps = ceil(r / 4).  VEC: Y's columns are 16-byte aligned (ldy
+// and the base a multiple of 4 floats), so a lane's 4 points go as one store.
+// Blocks of Z are fetched by direct global->LDS loads (4 bytes per lane,
+// lane l to the wave's base + 4 l), double-buffered: the next block is in
+// flight while this one is multiplied.  A operands past r are zero, so the
+// padding reads (finite values: LDS starts zeroed, later blocks overwrite
+// with Z) contribute nothing.
+template <int KS, bool VEC>
+__global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict__ F, int ldf, int64_t N, int r,
+                                                        const float* __restrict__ Z, int B, float* __restrict__ Y,
+                                                        int64_t ldy) {
+  extern __shared__ float zsm[];
+  constexpr int KP = 4 * KS;                     // r rounded up to 4
+  const int stage = EX_TB * r + KP;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * EX_P + (int64_t)w * EX_PW;
+  for (int e = tid; e < 2 * stage; e += 256) zsm[e] = 0.0f;
+  // A operands: F[p0 + 16 s + i16, 4 t + kq], zero past N or r
+  float af[4][KS];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t p = p0 + 16 * s + i16;
+    const float* row = F + (p < N ? p : 0) * (int64_t)ldf;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      const int c = 4 * t + kq;
+      af[s][t] = (p < N && c < r) ? row[c] : 0.0f;
+    }
+  }
+  const int nb = (B + EX_TB - 1) / EX_TB;
+  auto issue = [&](int b0, float* buf) {
+    const int total = min(EX_TB, B - b0) * r;    // the block's columns are contiguous in Z
+    const float* zb = Z + (int64_t)b0 * r;
+    for (int j = w; 64 * j < total; j += 4)
+      if (64 * j + lane < total) __builtin_amdgcn_global_load_lds(zb + 64 * j + lane, buf + 64 * j, 4, 0, 0);
+  };
+  __syncthreads();                               // the zero fill is done before any load lands
+  issue(0, zsm);
+  for (int ib = 0; ib < nb; ++ib) {
+    const int b0 = ib * EX_TB;
+    const float* zs = zsm + (size_t)(ib & 1) * stage;
+    __builtin_amdgcn_s_waitcnt(0);               // this wave's loads of block ib have landed
+    __syncthreads();                             // everyone's; and block ib - 1 is consumed
+    asm volatile("" ::: "memory");               // LDS reads below see the DMA writes
+    if (ib + 1 < nb) issue(b0 + EX_TB, zsm + (size_t)((ib + 1) & 1) * stage);
+    f4 acc[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+    // B[c][theta] = Z[c + (b0 + theta) r] = zs[theta r + c]
+    const float* zrow = zs + i16 * r + kq;
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+      float bz[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bz[q] = zrow[16 * q * r + 4 * t];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[s][q] = mfma4(af[s][t], bz[q], acc[s][q]);
+    }
+    // D[4 kq + v][i16]: points p0 + 16 s + 4 kq + v, theta b0 + 16 q + i16
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int th = b0 + 16 * q + i16;
+      if (th >= B) continue;
+      float* ycol = Y + (int64_t)th * ldy;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t p = p0 + 16 * s + 4 * kq;
+        if (VEC && p + 3 < N) {
+          *reinterpret_cast<f4*>(ycol + p) = acc[s][q];
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (p + v < N) ycol[p + v] = acc[s][q][v];
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ reduce
+constexpr int RD_P = 64;              // points per staged block
+constexpr int RD_TB = 128;            // thetas per workgroup
+constexpr int RD_XLD = RD_P + 4;      // LDS row stride of X (4 mod 32 banks): conflict-free B reads
+
+// Row stride of the staged F block for CT 16-column tiles: 16 mod 32 banks,
+// so the 4 rows of a K-step land on disjoint banks.
+__host__ __device__ constexpr int rd_fld(int ct) { return (16 * ct) % 32 == 16 ? 16 * ct : 16 * ct + 16; }
+template <int CT>
+constexpr size_t reduce_lds_floats() { return (size_t)RD_TB * RD_XLD + (size_t)RD_P * rd_fld(CT); }
+
+// part[chunk * r * B + b * r + c] = sum over the chunk's points p of
+// F[p, c] X[p, b] for this workgroup's 128 thetas; r <= 16 CT.  VEC: X's
+// columns are 16-byte aligned (ldx and the base a multiple of 4 floats).
+template <int CT, bool VEC>
+__global__ void __launch_bounds__(256, 2) k_reduce_mfma(const float* __restrict__ F, int ldf, int64_t N, int r,
+                                                     const float* __restrict__ X, int64_t ldx, int B, int64_t chunk,
+                                                     double* __restrict__ part) {
+  extern __shared__ float rsm[];
+  constexpr int FLD = rd_fld(CT);
+  constexpr int FC = 16 * CT;                    // staged columns of F
+  float* Xs = rsm;                               // [theta][point], RD_TB x RD_XLD
+  float* Fs = rsm + RD_TB * RD_XLD;              // [point][column], RD_P x FLD
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int b0 = blockIdx.y * RD_TB;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = pbeg + chunk < N ? pbeg + chunk : N;
+  double out[CT][2][4];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[ct][q][v] = 0.0;
+  for (int64_t q0 = pbeg; q0 < pend; q0 += RD_P) {
+    __syncthreads();                             // the previous block is consumed
+    // X block: theta 16 u + tid / 16, points q0 + 4 (tid % 16) .. + 3
+    {
+      const int seg = tid & 15;
+      const int64_t p = q0 + 4 * seg;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int th = 16 * u + (tid >> 4);
+        const int bb = b0 + th;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        if (bb < B) {
+          const float* xc = X + (int64_t)bb * ldx;
+          if (VEC && p + 3 < pend) {
+            v = *reinterpret_cast<const f4*>(xc + p);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (p + k < pend) v[k] = xc[p + k];
+          }
+        }
+        *reinterpret_cast<f4*>(Xs + th * RD_XLD + 4 * seg) = v;
+      }
+    }
+    // F block: wave w takes rows w, w + 4, ..., lanes the columns
+    {
+#pragma unroll
+      for (int u = 0; u < RD_P / 4; ++u) {
+        const int pt = 4 * u + w;
+        const int64_t p = q0 + pt;
+        const float* row = F + (p < pend ? p : q0) * (int64_t)ldf;
+#pragma unroll
+        for (int h = 0; h < (FC + 63) / 64; ++h) {
+          const int c = lane + 64 * h;
+          if (c < FC) Fs[pt * FLD + c] = (p < pend && c < r) ? row[c] : 0.0f;
+        }
+      }
+    }
+    __syncthreads();
+    f4 acc[CT][2];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct][0] = acc[ct][1] = f4{0.f, 0.f, 0.f, 0.f};
+    // A[c][point] = Fs[point][c], B[point][theta] = Xs[theta][point]
+    const float* xa = Xs + (32 * w + i16) * RD_XLD + kq;
+    const float* fa = Fs + kq * FLD + i16;
+#pragma unroll 4
+    for (int t = 0; t < RD_P / 4; ++t) {
+      const float bx0 = xa[4 * t], bx1 = xa[16 * RD_XLD + 4 * t];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const float a = fa[4 * t * FLD + 16 * ct];
+        acc[ct][0] = mfma4(a, bx0, acc[ct][0]);
+        acc[ct][1] = mfma4(a, bx1, acc[ct][1]);
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[ct][q][v] += (double)acc[ct][q][v];
+  }
+  // D[4 kq + v][i16]: column c = 16 ct + 4 kq + v, theta b0 + 32 w + 16 q + i16
+  double* pc = part + (size_t)blockIdx.x * r * B;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int bb = b0 + 32 * w + 16 * q + i16;
+    if (bb >= B) continue;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * ct + 4 * kq + v;
+        if (c < r) pc[(size_t)bb * r + c] = out[ct][q][v];
+      }
+  }
+}
+
+// The same reduction with both staged blocks fetched by direct global->LDS
+// loads (global_load_lds_dwordx4, no registers), double-buffered: the loads
+// of block i + 1 are in flight while block i is multiplied.  A lane's 16
+// bytes land at the wave's LDS base + 16 lane, so the layouts are:
+//   X: row theta of 64 points, its 16-byte runs rotated by theta (run j of
+//      row theta at slot (j - theta) mod 16), so the 16 thetas of a B operand
+//      read fall on 16 different bank groups;
+//   F: the 64 rows of the block copied as they lie in memory (row stride ldf,
+//      which must be 16 mod 32 so the 4 rows of a K-step hit disjoint banks).
+// Needs ldf % 32 == 16, ldx % 4 == 0 and 16-byte aligned F and X.  Only whole
+// 64-point blocks go through the DMA; a chunk's ragged tail is staged by
+// ordinary loads with zero fill.
+template <int CT>
+__global__ void __launch_bounds__(256) k_reduce_mfma_dma(const float* __restrict__ F, int ldf, int64_t N, int r,
+                                                         const float* __restrict__ X, int64_t ldx, int B,
+                                                         int64_t chunk, double* __restrict__ part) {
+  extern __shared__ float dsm[];
+  const int stage = RD_TB * RD_P + RD_P * ldf;   // floats per buffer
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int b0 = blockIdx.y * RD_TB;
+  const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+  const int64_t pend = pbeg + chunk < N ? pbeg + chunk : N;
+  const int64_t nfull = (pend - pbeg) / RD_P;
+  const int64_t nblk = nfull + ((pend - pbeg) % RD_P != 0);
+  auto issue = [&](int64_t q0, float* buf) {
+    float* xs = buf;
+    float* fs = buf + RD_TB * RD_P;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int th = 32 * w + 4 * u + kq;                      // row of this lane
+      const int bb = min(b0 + th, B - 1);                       // rows past B: any valid column, discarded
+      const int seg = (i16 + th) & 15;                          // the run stored at slot i16
+      __builtin_amdgcn_global_load_lds(X + (int64_t)bb * ldx + q0 + 4 * seg, xs + (32 * w + 4 * u) * RD_P, 16, 0,
+                                       0);
+    }
+    const float* fb = F + q0 * ldf;
+    for (int j = w; j < ldf / 4; j += 4)                        // 16 ldf bytes-runs = ldf / 4 wave loads
+      __builtin_amdgcn_global_load_lds(fb + 4 * (64 * j + lane), fs + 256 * j, 16, 0, 0);
+  };
+  double out[CT][2][4];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[ct][q][v] = 0.0;
+  if (nfull > 0) issue(pbeg, dsm);
+  for (int64_t i = 0; i < nblk; ++i) {
+    float* cur = dsm + (size_t)(i & 1) * stage;
+    const int64_t q0 = pbeg + i * RD_P;
+    __builtin_amdgcn_s_waitcnt(0);                 // this wave's loads of block i have landed
+    __syncthreads();                               // everyone's; and block i - 1 is consumed
+    asm volatile("" ::: "memory");                 // LDS reads below see the DMA writes
+    if (i >= nfull) {                              // the ragged tail: ordinary loads, zero fill
+      for (int e = tid; e < RD_TB * RD_P; e += 256) {
+        const int th = e / RD_P, k = e % RD_P;
+        const int64_t p = q0 + k;
+        const int bb = b0 + th;
+        cur[th * RD_P + 4 * (((k >> 2) - th) & 15) + (k & 3)] =
+            (p < pend && bb < B) ? X[(int64_t)bb * ldx + p] : 0.0f;
+      }
+      for (int e = tid; e < RD_P * ldf; e += 256) {
+        const int pt = e / ldf, c = e % ldf;
+        const int64_t p = q0 + pt;
+        cur[RD_TB * RD_P + e] = (p < pend && c < r) ? F[p * ldf + c] : 0.0f;
+      }
+      __syncthreads();
+    }
+    if (i + 1 < nfull) issue(q0 + RD_P, dsm + (size_t)((i + 1) & 1) * stage);
+    const float* xs = cur;
+    const float* fa = cur + RD_TB * RD_P + kq * ldf + i16;
+    const int th0 = 32 * w + i16, th1 = th0 + 16;
+    f4 acc[CT][2];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[ct][0] = acc[ct][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int t = 0; t < RD_P / 4; ++t) {
+      const float bx0 = xs[th0 * RD_P + 4 * ((t - th0) & 15) + kq];
+      const float bx1 = xs[th1 * RD_P + 4 * ((t - th1) & 15) + kq];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const float a = fa[4 * t * ldf + 16 * ct];
+        acc[ct][0] = mfma4(a, bx0, acc[ct][0]);
+        acc[ct][1] = mfma4(a, bx1, acc[ct][1]);
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[ct][q][v] += (double)acc[ct][q][v];
+  }
+  double* pc = part + (size_t)blockIdx.x * r * B;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int bb = b0 + 32 * w + 16 * q + i16;
+    if (bb >= B) continue;
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = 16 * ct + 4 * kq + v;
+        if (c < r) pc[(size_t)bb * r + c] = out[ct][q][v];
+      }
+  }
+}
+
+// W[e] = sum over chunks of part[chunk * count + e], in chunk order.
+__global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ part, int nch, int64_t count,
+                                                    float* __restrict__ W) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int k = 0; k < nch; ++k) s += part[(size_t)k * count + e];
+    W[e] = (float)s;
+  }
+}
+
+// Chunking of the reduce: enough workgroups to fill the chip (RD_WG_TARGET
+// over the theta blocks), every chunk a whole number of 64-point blocks.
+constexpr int RD_WG_TARGET = 512;
+void reduce_shape(int64_t N, int B, int64_t* chunk, int* nch) {
+  const int tb = (B + RD_TB - 1) / RD_TB;
+  const int64_t blocks = (N + RD_P - 1) / RD_P;
+  int64_t want = std::max<int64_t>(1, (RD_WG_TARGET + tb - 1) / tb);
+  want = std::min<int64_t>(want, blocks);
+  const int64_t per = (blocks + want - 1) / want;   // 64-point blocks per chunk
+  *chunk = per * RD_P;
+  *nch = (int)((N + *chunk - 1) / *chunk);
+}
+
+template <class K>
+tt_status set_lds(K kern, size_t bytes) {
+  static_assert(sizeof(K) > 0, "");
+  if (bytes > 64 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes));
+  return TTK_OK;
+}
+
+template <int KS>
+tt_status launch_expand(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
+                        hipStream_t st) {
+  const size_t sh = expand_lds_floats(r, 4 * KS) * sizeof(float);
+  const bool vec = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  const dim3 grid((unsigned)((N + EX_P - 1) / EX_P));
+  if (vec) {
+    TTK_TRY(set_lds(&k_expand_mfma<KS, true>, sh));
+    hipLaunchKernelGGL((k_expand_mfma<KS, true>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+  } else {
+    TTK_TRY(set_lds(&k_expand_mfma<KS, false>, sh));
+    hipLaunchKernelGGL((k_expand_mfma<KS, false>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+  }
+  return TTK_OK;
+}
+
+template <int CT>
+tt_status launch_reduce(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B, float* W,
+                        double* part, hipStream_t st) {
+  int64_t chunk;
+  int nch;
+  reduce_shape(N, B, &chunk, &nch);
+  const dim3 grid((unsigned)nch, (unsigned)((B + RD_TB - 1) / RD_TB));
+  const bool xal = (ldx % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+  const bool dma = xal && ldf % 32 == 16 && ldf >= 16 * CT && reinterpret_cast<uintptr_t>(F) % 16 == 0;
+  if (dma) {
+    const size_t sh = (size_t)2 * (RD_TB * RD_P + RD_P * ldf) * sizeof(float);
+    TTK_TRY(set_lds(&k_reduce_mfma_dma<CT>, sh));
+    hipLaunchKernelGGL((k_reduce_mfma_dma<CT>), grid, dim3(256), sh, st, F, ldf, N, r, X, ldx, B, chunk, part);
+  } else {
+    const size_t sh = reduce_lds_floats<CT>() * sizeof(float);
+    if (xal) {
+      TTK_TRY(set_lds(&k_reduce_mfma<CT, true>, sh));
+      hipLaunchKernelGGL((k_reduce_mfma<CT, true>), grid, dim3(256), sh, st, F, ldf, N, r, X, ldx, B, chunk, part);
+    } else {
+      TTK_TRY(set_lds(&k_reduce_mfma<CT, false>, sh));
+      hipLaunchKernelGGL((k_reduce_mfma<CT, false>), grid, dim3(256), sh, st, F, ldf, N, r, X, ldx, B, chunk,
+                         part);
+    }
+  }
+  const int64_t count = (int64_t)r * B;
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 4096)), dim3(256), 0, st,
+                     (const double*)part, nch, count, W);
+  return TTK_OK;
+}
+
+}  // namespace
+
+bool apply_mfma_ok(int r, int B) { return r >= 1 && r <= MFMA_APPLY_MAXR && B > 16; }
+
+int mfma_ld(int r) {
+  int ld = r < 16 ? 16 : r;
+  while (ld % 32 != 16) ++ld;
+  return ld;
+}
+
+size_t apply_reduce_mfma_work(int64_t N, int r, int B) {
+  if (N <= 0) return 0;
+  int64_t chunk;
+  int nch;
+  reduce_shape(N, B, &chunk, &nch);
+  return (size_t)nch * r * B * sizeof(double);
+}
+
+tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B, float* W,
+                            double* part, hipStream_t st) {
+  switch ((r + 15) / 16) {
+    case 1: return launch_reduce<1>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 2: return launch_reduce<2>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 3: return launch_reduce<3>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 4: return launch_reduce<4>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 5: return launch_reduce<5>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 6: return launch_reduce<6>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 7: return launch_reduce<7>(F, ldf, N, r, X, ldx, B, W, part, st);
+    case 8: return launch_reduce<8>(F, ldf, N, r, X, ldx, B, W, part, st);
+    default: return fail(TTK_ERR_UNSUPPORTED, "MFMA reduce: rank %d > %d", r, MFMA_APPLY_MAXR);
+  }
+}
+
+tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
+                            hipStream_t st) {
+  switch ((r + 3) / 4) {
+#define TTK_EXPAND_CASE(k) \
+  case k: return launch_expand<k>(F, ldf, N, r, Z, B, Y, ldy, st);
+    TTK_EXPAND_CASE(1) TTK_EXPAND_CASE(2) TTK_EXPAND_CASE(3) TTK_EXPAND_CASE(4) TTK_EXPAND_CASE(5)
+    TTK_EXPAND_CASE(6) TTK_EXPAND_CASE(7) TTK_EXPAND_CASE(8) TTK_EXPAND_CASE(9) TTK_EXPAND_CASE(10)
+    TTK_EXPAND_CASE(11) TTK_EXPAND_CASE(12) TTK_EXPAND_CASE(13) TTK_EXPAND_CASE(14) TTK_EXPAND_CASE(15)
+    TTK_EXPAND_CASE(16) TTK_EXPAND_CASE(17) TTK_EXPAND_CASE(18) TTK_EXPAND_CASE(19) TTK_EXPAND_CASE(20)
+    TTK_EXPAND_CASE(21) TTK_EXPAND_CASE(22) TTK_EXPAND_CASE(23) TTK_EXPAND_CASE(24) TTK_EXPAND_CASE(25)
+    TTK_EXPAND_CASE(26) TTK_EXPAND_CASE(27) TTK_EXPAND_CASE(28) TTK_EXPAND_CASE(29) TTK_EXPAND_CASE(30)
+    TTK_EXPAND_CASE(31) TTK_EXPAND_CASE(32)
+#undef TTK_EXPAND_CASE
+    default: return fail(TTK_ERR_UNSUPPORTED, "MFMA expand: rank %d > %d", r, MFMA_APPLY_MAXR);
+  }
+}
+
+}  // namespace ttk

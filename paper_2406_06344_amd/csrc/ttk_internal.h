@@ -235,12 +235,25 @@ void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int 
 size_t online_work_doubles(const ParamCore* pc, int dt, int B);
 
 // W (r x B) = F^T X.  work: apply_reduce_work(N, r, B) bytes of device memory
-// for the per-workgroup partial sums (may be NULL when that is 0).
-void apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
-                  int B, void* W, void* work, hipStream_t st);
+// for the per-workgroup partial sums (may be NULL when that is 0); every
+// byte the reduction reads from it is written first by the same call.
+tt_status apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
+                       int B, void* W, void* work, hipStream_t st);
 size_t apply_reduce_work(int64_t N, int r, int B);
-void apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B,
-                  void* Y, int64_t ldy, hipStream_t st);  // Y (N x B) = F Z
+tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, const void* Z, int B,
+                       void* Y, int64_t ldy, hipStream_t st);  // Y (N x B) = F Z
+// Float32 matrix-core forms of the two wide contractions (ttk_apply_mfma.hip),
+// taken for B > 16 and r <= MFMA_APPLY_MAXR.
+constexpr int MFMA_APPLY_MAXR = 128;
+bool apply_mfma_ok(int r, int B);
+// Leading dimension for float32 U and V rows: the smallest ld >= r with
+// ld % 32 == 16 (16-byte rows whose K-step reads hit disjoint LDS banks).
+int mfma_ld(int r);
+size_t apply_reduce_mfma_work(int64_t N, int r, int B);
+tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
+                            float* W, double* part, hipStream_t st);
+tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
+                            int64_t ldy, hipStream_t st);
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
                     int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,

@@ -1,0 +1,90 @@
+"""GPU parity of the wide batched apply and backward (B > 16: the float32
+matrix-core kernels for ranks up to 128, the register-tiled kernels above)
+against the FP64 oracle on the same cores and float32-rounded inputs.
+
+Cores are random TT cores with the ranks under test (d = 2, one parameter):
+the apply, its backward pass and the online core depend on the cores only
+through S, T and H(theta), which the oracle forms from the same cores
+(Phase 3 of Algorithm 2, Algorithm 3).  Bars: relative Frobenius <= 1e-5 and
+largest entry error <= 1e-5 of the largest entry, per output."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import dense as odense
+from oracle import pttk as opttk
+
+BOX_S = [[0.0, 1.0], [0.0, 1.0]]
+BOX_T = [[2.0, 3.0], [0.0, 1.0]]
+BOX_TH = [[0.5, 2.0]]
+N_SP, N_PA = 16, 12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def random_cores(rs, rt, seed):
+    """Nodal cores G_1..G_5 with ranks (1, 16, rs, rt, 16, 1), entries scaled
+    so every chain product stays of order one."""
+    rng = np.random.default_rng(seed)
+    r = [1, N_SP, rs, rt, N_SP, 1]
+    n = [N_SP, N_SP, N_PA, N_SP, N_SP]
+    return [rng.standard_normal((r[k], n[k], r[k + 1])) / np.sqrt(r[k] * n[k]) for k in range(5)]
+
+
+def errs(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return odense.rel_fro(got, ref), float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("rs,rt,ns,nt,B", [
+    (100, 90, 3001, 2999, 200),     # MFMA path, ragged N (unaligned columns), ragged theta tiles
+    (72, 75, 4096, 2048, 64),       # MFMA path, aligned columns (16-byte stores and loads)
+    (128, 17, 1500, 2100, 513),     # the widest MFMA rank and a narrow one, 5 theta blocks + 1
+    (130, 70, 1200, 1000, 80),      # rank above 128: the register-tiled float32 kernels
+])
+def test_wide_apply_and_backward_match_oracle(rs, rt, ns, nt, B):
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    say(f"[wide] r_s {rs} r_t {rt} N {ns} x {nt} B {B}")
+    cores = random_cores(rs, rt, seed=rs + rt)
+    rng = np.random.default_rng(7)
+    X = rng.uniform(0, 1, (ns, 2)).astype(np.float32).astype(np.float64)
+    Y = rng.uniform([2, 0], [3, 1], (nt, 2)).astype(np.float32).astype(np.float64)
+    th = rng.uniform(0.5, 2.0, (B, 1)).astype(np.float32).astype(np.float64)
+    xb = rng.standard_normal((nt, B)).astype(np.float32).astype(np.float64)
+    gb = rng.standard_normal((ns, B)).astype(np.float32).astype(np.float64)
+    kern = pkg.TTKernel.from_cores(cores, torch.tensor(X), torch.tensor(Y), "matern32", 2, BOX_S, BOX_T, BOX_TH,
+                                   n_spatial=N_SP, n_param=N_PA, dtype=torch.float32)
+    assert (kern.r_s, kern.r_t) == (rs, rt)
+    bs, bt, bth = np.array(BOX_S), np.array(BOX_T), np.array(BOX_TH)
+    S = opttk.phase3_source(opttk.factor_values(X, bs, N_SP), cores[:2])
+    T = opttk.phase3_target(opttk.factor_values(Y, bt, N_SP), cores[3:])
+    Hs = [opttk.online_H(cores[2:3], t, bth, N_PA) for t in th]
+    dHs = [opttk.online_dH(cores[2:3], t, bth, N_PA) for t in th]
+    y_o, W_o = opttk.apply_batched(S, Hs, T, xb)
+    dX_o, dth_o = opttk.backward_batched(S, Hs, dHs, T, xb, gb)
+    tht = torch.tensor(th, dtype=torch.float32)
+    Yg, Wg = kern.apply(tht, torch.tensor(xb.T.copy(), dtype=torch.float32), save_w=True)
+    dXg, dthg = kern.apply_backward(tht, torch.tensor(gb.T.copy(), dtype=torch.float32), W=Wg)
+    res = {"W": errs(Wg.cpu().numpy().T, W_o), "y": errs(Yg.cpu().numpy().T, y_o),
+           "dX": errs(dXg.cpu().numpy().T, dX_o), "dtheta": errs(dthg.cpu().numpy(), dth_o)}
+    say("  (rel Frobenius, max entry):", {k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in res.items()})
+    for k, (fro, mx) in res.items():
+        assert fro <= 1e-5 and mx <= 1e-5, (k, fro, mx)
+    # the plain per-theta apply (other kernels) agrees with the batched one
+    Yp = kern.apply_plain(tht[:5], torch.tensor(xb[:, :5].T.copy(), dtype=torch.float32))
+    assert errs(Yp.cpu().numpy(), Yg[:5].cpu().numpy())[0] <= 1e-5
