@@ -196,6 +196,24 @@ tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B,
                           const void* X, int64_t ldx, void* Y, int64_t ldy,
                           void* W_save, void* stream);
 
+/* The batched apply of tt_kernel_apply, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation).  Same arguments, kernels and result; the working
+ * memory (M(theta_b), W, Z, the partial sums of the reduction over points and
+ * the online-core workspace) is carved from a fixed scratch array of 64 MiB
+ * that the library holds on every device it runs on until the process ends;
+ * its address is looked up on the first call on a device.  Nothing is
+ * allocated, by the library or through any other library.  A call whose
+ * working memory exceeds the scratch returns TTK_ERR_ARG (naming the bytes
+ * needed) before launching anything: roughly B * (r_s r_t * sizeof(dtype)
+ * + 2 * (r_d r_m + r_m r_t) * 8) bytes plus the partial sums, so at ranks
+ * near 75 a call takes a few hundred thetas; split larger batches.  All calls
+ * on one device share the scratch: calls that overlap in time on one device
+ * (on different streams or host threads) race and must not be issued. */
+tt_status tt_kernel_apply_noalloc(tt_kernel_t h, const void* theta, int B,
+                                  const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                  void* W_save, void* stream);
+
 /* Plain per-theta apply for all b: B independent two-pass applies (reads V and
  * U once per theta).  The reference point for the batched form. */
 tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B,

@@ -287,6 +287,20 @@ class TTKernel:
                                           _ptr(W), _stream_ptr(stream)))
         return (Y, W) if save_w else Y
 
+    def apply_noalloc(self, theta, X, out, W=None, stream=None):
+        """apply() through tt_kernel_apply_noalloc: the library allocates
+        nothing (its working memory is a fixed per-device scratch).  out
+        (B, N_s) and W (B, r_t, optional) are caller-owned device tensors."""
+        B = _chk(X, "X", None, self.n_tgt).shape[0]
+        theta = _theta(theta, self.d_theta, self.dtype, B, convert=False)
+        _out(out, "out", (B, self.n_src), self.dtype)
+        if W is not None:
+            _out(W, "W", (B, self.r_t), self.dtype)
+        theta, X = _dev(theta, self.dtype), _dev(X, self.dtype)
+        check(_lib.load().tt_kernel_apply_noalloc(self._h, _ptr(theta), B, _ptr(X), X.stride(0), _ptr(out),
+                                                  out.stride(0), _ptr(W), _stream_ptr(stream)))
+        return out
+
     def apply_plain(self, theta, X, stream=None):
         B = _chk(X, "X", None, self.n_tgt).shape[0]
         theta = _dev(_theta(theta, self.d_theta, self.dtype, B, convert=False), self.dtype)

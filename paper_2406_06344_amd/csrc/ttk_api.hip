@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "ttk_internal.h"
 
@@ -392,6 +393,81 @@ static void fill_info(tt_kernel* h) {
   I.dtype = h->dtype;
 }
 
+// ---------------------------------------------------------- batched apply
+// Scratch of one batched apply: M(theta_b) for all b, W = V^T X (unless the
+// caller keeps it), Z = M W, the reduction's partial sums and the online
+// core's workspace.  Each piece is written before it is read within a call,
+// so nothing has to start at zero.
+struct ApplyScratch {
+  void* M = nullptr;
+  void* W = nullptr;
+  void* Z = nullptr;
+  void* part = nullptr;
+  double* owork = nullptr;
+};
+struct ApplySizes {
+  size_t M = 0, W = 0, Z = 0, part = 0, owork = 0;   // bytes, each rounded up to 256
+};
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+static void apply_sizes(const tt_kernel* h, int B, bool need_w, ApplySizes* z) {
+  z->M = up256((size_t)h->rs * h->rt * B * h->es);
+  z->W = need_w ? up256((size_t)h->rt * B * h->es) : 0;
+  z->Z = up256((size_t)h->rs * B * h->es);
+  z->part = up256(apply_reduce_work(h->nt, h->rt, B));
+  z->owork = h->g.dt > 0 ? up256(online_work_doubles(h->pc, h->g.dt, B) * sizeof(double)) : 0;
+}
+
+static tt_status check_apply_args(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, const void* Y,
+                                  int64_t ldy) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (B < 0) return fail(TTK_ERR_ARG, "B < 0");
+  if (B == 0) return TTK_OK;
+  if (!X || !Y) return fail(TTK_ERR_ARG, "X or Y is NULL");
+  if (ldx < h->nt || ldy < h->ns) return fail(TTK_ERR_ARG, "leading dimension too small");
+  if (h->g.dt > 0 && !theta) return fail(TTK_ERR_ARG, "theta is NULL");
+  return TTK_OK;
+}
+
+// y_b = U M(theta_b) V^T x_b for b < B with the given scratch (no allocation).
+static tt_status apply_core(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
+                            int64_t ldy, const ApplyScratch& s, hipStream_t st) {
+  const int dt = h->g.dt;
+  if (dt == 0)
+    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, s.M, h->rs, B, h->dtype == TTK_FP32);
+  else
+    online_core(h->dtype, h->pc, dt, theta, B, s.M, nullptr, s.owork, st);
+  TTK_TRY(apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, s.W, s.part, st));
+  batched_matvec(h->dtype, s.M, h->rs, h->rt, 0, s.W, B, s.Z, st);
+  TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, s.Z, B, Y, ldy, st));
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+// The fixed scratch of tt_kernel_apply_noalloc: one array per device, for
+// the life of the process.  Host code never passes the array's name to a
+// kernel (in host code it is only a stand-in for the symbol): its device
+// address is looked up once per device and kept.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static tt_status noalloc_scratch(void** out) {
+  int dev = 0;
+  TTK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(TTK_ERR_UNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    TTK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(TTK_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TTK_OK;
+}
+
 extern "C" {
 
 const char* tt_kernel_last_error(void) { return g_err.c_str(); }
@@ -499,23 +575,62 @@ static tt_status reduce_into(tt_kernel_t h, const void* F, int ldf, int64_t N, i
 
 tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y, int64_t ldy,
                           void* W_save, void* stream) {
-  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
-  if (B <= 0) return B == 0 ? TTK_OK : fail(TTK_ERR_ARG, "B < 0");
-  if (!X || !Y) return fail(TTK_ERR_ARG, "X or Y is NULL");
-  if (ldx < h->nt || ldy < h->ns) return fail(TTK_ERR_ARG, "leading dimension too small");
+  TTK_TRY(check_apply_args(h, theta, B, X, ldx, Y, ldy));
+  if (B == 0) return TTK_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  TTK_TRY(prepare_M(h, theta, B, false, st));
-  void* W = W_save;
-  if (!W) {
-    TTK_TRY(h->Wbuf.alloc((size_t)h->rt * B * h->es));
-    W = h->Wbuf.p;
+  ApplySizes z;
+  apply_sizes(h, B, W_save == nullptr, &z);
+  ApplyScratch s{};
+  TTK_TRY(h->Mbuf.alloc(z.M));
+  s.M = h->Mbuf.p;
+  s.W = W_save;
+  if (!W_save) {
+    TTK_TRY(h->Wbuf.alloc(z.W));
+    s.W = h->Wbuf.p;
   }
-  TTK_TRY(h->Zbuf.alloc((size_t)h->rs * B * h->es));
-  TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, W, st));
-  batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 0, W, B, h->Zbuf.p, st);
-  TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, h->Zbuf.p, B, Y, ldy, st));
-  TTK_HIP(hipGetLastError());
-  return TTK_OK;
+  TTK_TRY(h->Zbuf.alloc(z.Z));
+  s.Z = h->Zbuf.p;
+  if (z.part) {
+    TTK_TRY(h->Pbuf.alloc(z.part));
+    s.part = h->Pbuf.p;
+  }
+  if (z.owork) {
+    TTK_TRY(h->work.alloc(z.owork));
+    s.owork = h->work.as<double>();
+  }
+  return apply_core(h, theta, B, X, ldx, Y, ldy, s, st);
+}
+
+tt_status tt_kernel_apply_noalloc(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
+                                  int64_t ldy, void* W_save, void* stream) {
+  TTK_TRY(check_apply_args(h, theta, B, X, ldx, Y, ldy));
+  if (B == 0) return TTK_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ApplySizes z;
+  apply_sizes(h, B, W_save == nullptr, &z);
+  const size_t need = z.M + z.W + z.Z + z.part + z.owork;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(TTK_ERR_ARG,
+                "tt_kernel_apply_noalloc: B = %d needs %zu bytes of scratch (M(theta), W, Z, partial sums and the "
+                "online workspace); the fixed scratch holds %zu bytes: split the thetas into smaller calls",
+                B, need, (size_t)NOALLOC_SCRATCH_BYTES);
+  char* base = nullptr;
+  TTK_TRY(noalloc_scratch(reinterpret_cast<void**>(&base)));
+  ApplyScratch s{};
+  size_t off = 0;
+  s.M = base + off;
+  off += z.M;
+  s.W = W_save;
+  if (!W_save) {
+    s.W = base + off;
+    off += z.W;
+  }
+  s.Z = base + off;
+  off += z.Z;
+  if (z.part) s.part = base + off;
+  off += z.part;
+  if (z.owork) s.owork = reinterpret_cast<double*>(base + off);
+  return apply_core(h, theta, B, X, ldx, Y, ldy, s, st);
 }
 
 tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
