@@ -5,16 +5,19 @@ One step = the whole hot path on one batch of synthetic input:
   rounding of the cores, Phase 3 for all sources and targets), the online
   core for B theta samples, the batched apply y_b = U M(theta_b) V^T x_b and
   its backward pass (dX, dtheta).
-Workload (default): d = 3, 100k + 100k points uniform in separated unit
-cubes (target cube offset by 2 along axis 1), Matern nu = 3/2 in the length
-scale l in [0.5, 2], 16 nodes per dimension, tol 7e-7, 16 theta samples,
-float32 bulk with float64 cross / factorisations.
+Workload (default, matern_batched): d = 3, 1M + 1M points uniform in
+separated unit cubes (target cube offset by 2 along axis 1), Matern in
+theta = (l, nu), l in [0.5, 2], nu in [0.5, 2.5], 16 nodes per dimension,
+tol 7e-7, B = 4096 theta samples each with its own x_b and cotangent g_b,
+float32 bulk with float64 cross / factorisations.  Inputs are resident in HBM
+before the timed steps.
 
 Prints one JSON line.  value = whole-step offline U/V rows per second,
 (N_s + N_t) / seconds per step.  Extra fields report Phase 3 alone, the
-apply + gradient and plain apply bandwidths, accuracy against dense K and
-the roofline of the dominant kernel (timed with HIP events on the stream it
-runs on).
+apply + gradient against the plain per-theta apply, kernel evaluations,
+accuracy against dense float64 K and the roofline of the projection kernel
+(timed with HIP events on the stream it runs on).  Other workloads:
+--workload matern32_d3 | se_d2_fp64 | matern_global | uneven_pairs.
 """
 import argparse
 import json
@@ -40,6 +43,11 @@ HBM_PEAK_GBPS = 8000.0
 # None whenever the kernel has changed since the counters were taken.
 TRAFFIC = 31133312
 FP32_PEAK_TFLOPS = 157.3
+# HBM bytes per launch of the projection kernel on the 1M-point workload
+# (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a plain
+# copy); None until the counters are taken for the current kernel.
+PROJECT_TRAFFIC = None
+PROJECT_TRAFFIC_NOTE = "not measured for this kernel"
 
 
 def phase3_flops_per_point(ranks, n):
@@ -162,8 +170,54 @@ def bench_global(args, torch, pkg):
     return res
 
 
+def oracle_baseline(w, ranks, n_pts, n_theta, threads_note=True):
+    """The oracle, as it stands, on a bounded sample of the workload: Phase 3
+    (Algorithm 2) for n_pts sources and n_pts targets, and the batched apply +
+    backward (the low-rank form and its adjoint) for n_theta thetas on those
+    points.  Its timings depend only on the shapes, so the cores are random
+    with the ranks of the GPU build; the oracle's own cross for this workload
+    (N-independent, minutes of CPU) is not part of the sample."""
+    import threadpoolctl
+
+    from oracle import pttk as opttk
+
+    rng = np.random.default_rng(21)
+    n = [w.n_spatial] * w.d + [w.n_param] * w.d_theta + [w.n_spatial] * w.d
+    cores = [rng.standard_normal((ranks[k], n[k], ranks[k + 1])) / np.sqrt(ranks[k] * n[k]) for k in range(len(n))]
+    bs, bt, bth = (np.asarray(b, float) for b in (w.box_s, w.box_t, w.box_theta))
+    X = rng.uniform(bs[:, 0], bs[:, 1], (n_pts, w.d))
+    Y = rng.uniform(bt[:, 0], bt[:, 1], (n_pts, w.d))
+    d, dt = w.d, w.d_theta
+    t0 = time.perf_counter()
+    S = opttk.phase3_source(opttk.factor_values(X, bs, w.n_spatial), cores[:d])
+    T = opttk.phase3_target(opttk.factor_values(Y, bt, w.n_spatial), cores[d + dt:])
+    t_p3 = time.perf_counter() - t0
+    th = rng.uniform(bth[:, 0], bth[:, 1], (n_theta, dt))
+    xb = rng.standard_normal((n_pts, n_theta))
+    gb = rng.standard_normal((n_pts, n_theta))
+    t0 = time.perf_counter()
+    Hs = [opttk.online_H(cores[d:d + dt], t, bth, w.n_param) for t in th]
+    dHs = [opttk.online_dH(cores[d:d + dt], t, bth, w.n_param) for t in th]
+    opttk.apply_batched(S, Hs, T, xb)
+    opttk.backward_batched(S, Hs, dHs, T, xb, gb)
+    t_ag = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+    # scaled to the workload: Phase 3 linear in N, the apply + backward in N * B
+    t_p3_full = t_p3 * (w.n_src + w.n_tgt) / (2 * n_pts)
+    t_ag_full = t_ag * (w.n_src / n_pts) * (w.n_theta / n_theta)
+    return {"value": round((w.n_src + w.n_tgt) / (t_p3_full + t_ag_full), 3), "unit": "rows/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle Phase 3 on {n_pts} + {n_pts} points ({t_p3:.1f} s) and batched apply + backward "
+                      f"for {n_theta} thetas on them ({t_ag:.1f} s), float64 NumPy, cores random with the GPU "
+                      f"build's ranks {list(ranks)}; scaled linearly to {w.n_src} + {w.n_tgt} points and "
+                      f"{w.n_theta} thetas.  Excludes the N-independent cross (the GPU step includes it).",
+            "phase3_rows_per_s": round(2 * n_pts / t_p3, 1),
+            "apply_grad_theta_per_s": round(n_theta * (n_pts / w.n_src) / t_ag, 4),
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
 def bench_batched(args, torch, pkg):
-    """Batched + differentiated apply at 1M + 1M points and B = 4096 theta samples."""
+    """The whole hot path at 1M + 1M points and B = 4096 theta samples."""
     w = synth.WORKLOADS["matern_batched"]
     X, Y = synth.points(w, seed=0)
     th = synth.thetas(w, seed=1)
@@ -176,7 +230,7 @@ def bench_batched(args, torch, pkg):
     xb = torch.randn((B, w.n_tgt), generator=gen, device="cuda", dtype=torch.float32)
     gb = torch.randn((B, w.n_src), generator=gen, device="cuda", dtype=torch.float32)
     kw = dict(kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta, n_spatial=w.n_spatial,
-              n_param=w.n_param, tol=w.tol, dtype=torch.float32, seed=0)
+              n_param=w.n_param, tol=w.tol, dtype=torch.float32, seed=0, max_sweeps=w.extra["max_sweeps"])
 
     def step():
         kern = pkg.TTKernel.build_offline(Xd, Yd, **kw)
@@ -186,27 +240,98 @@ def bench_batched(args, torch, pkg):
 
     for i in range(args.warmup):
         kern = step()
-        print(f"warmup {i} done: ranks {kern.info()['ranks']}", file=sys.stderr, flush=True)
-    ms = time_wall(step, args.steps, torch)
-    kern = step()
+        print(f"warmup {i} done: status {kern.status} ranks {kern.info()['ranks']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        kern = step()
+        print(f"step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
     inf = kern.info()
     rs, rt = kern.r_s, kern.r_t
-    ms_ag = time_events(lambda: kern.apply_backward(thd, gb, W=kern.apply(thd, xb, save_w=True)[1]), 3, torch)
+    res = base_result(w, args, (w.n_src + w.n_tgt) / (ms / 1000.0), "rows/s", ms, B,
+                      {"max_sweeps": w.extra["max_sweeps"]})
+    res.update({"build_status": "converged" if kern.status == 0 else "not converged (sweep or rank cap)",
+                "ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
+                "sampled_error": float(f"{inf['sampled_error']:.3e}"), "kernel_evals": inf["kernel_evals"],
+                "kernel_evals_per_s": round(inf["kernel_evals"] / (inf["t_cross_ms"] * 1e-3), 1),
+                "t_cross_ms": round(inf["t_cross_ms"], 2), "t_round_ms": round(inf["t_round_ms"], 2)})
+    if args.steps_only:
+        return res
+    print("timing the phases", file=sys.stderr, flush=True)
+    # ---- Phase 3 alone (one launch per side), HIP events on the current stream
+    Xs, Ys = Xd.t().contiguous(), Yd.t().contiguous()
+    U_out = torch.empty((w.n_src, rs), dtype=torch.float32, device="cuda")
+    V_out = torch.empty((w.n_tgt, rt), dtype=torch.float32, device="cuda")
+    ms_u = time_events(lambda: kern.factor_rows_soa(Xs, 0, U_out), 10, torch)
+    ms_v = time_events(lambda: kern.factor_rows_soa(Ys, 1, V_out), 10, torch)
+    r = inf["ranks"]
+    d, dth = w.d, w.d_theta
+    fl_u = w.n_src * phase3_flops_per_point(r[:d + 1], w.n_spatial)
+    fl_v = w.n_tgt * phase3_flops_per_point(r[d + dth:][::-1], w.n_spatial)
+    # ---- the projection W = F^T X (the roofline kernel), one launch per call
+    Wv = torch.empty((B, rt), dtype=torch.float32, device="cuda")
+    Av = torch.empty((B, rs), dtype=torch.float32, device="cuda")
+    ms_pv = time_events(lambda: kern.project(xb, side=1, out=Wv), 5, torch)
+    ms_pu = time_events(lambda: kern.project(gb, side=0, out=Av), 5, torch)
+    fl_proj = 2.0 * B * (w.n_tgt * rt + w.n_src * rs) / 2          # average of the two launches
+    ms_proj = (ms_pv + ms_pu) / 2
+    # ---- batched apply + backward, and the plain per-theta apply
+    def fwd_bwd():
+        Yo, W_ = kern.apply(thd, xb, save_w=True)
+        kern.apply_backward(thd, gb, W=W_)
+    ms_ag = time_events(fwd_bwd, 5, torch)
     bytes_ag = 2 * 4 * (w.n_src * rs + w.n_tgt * rt) + 2 * 4 * B * (w.n_src + w.n_tgt)
-    flops_ag = 4 * B * (w.n_src * rs + w.n_tgt * rt)   # four tall products, 2 N r B each
+    flops_ag = 4 * B * (w.n_src * rs + w.n_tgt * rt)        # four tall products, 2 N r B each
     nplain = 64
     ms_plain = time_events(lambda: kern.apply_plain(thd[:nplain], xb[:nplain]), 2, torch)
-    gbps = bytes_ag / (ms_ag * 1e-3) / 1e9
-    res = base_result(w, args, (w.n_src + w.n_tgt) / (ms / 1000.0), "rows/s", ms, B)
-    res.update({"ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
-                "t_cross_ms": round(inf["t_cross_ms"], 2), "t_round_ms": round(inf["t_round_ms"], 2),
-                "t_factor_ms": round(inf["t_factor_ms"], 3), "apply_grad_ms": round(ms_ag, 3),
-                "apply_grad_GBps": round(gbps, 1), "apply_grad_TFLOPs": round(flops_ag / (ms_ag * 1e-3) / 1e12, 2),
-                "batched_vs_plain_theta_per_s": round((B / ms_ag) / (nplain / ms_plain), 3),
-                "plain_note": f"plain per-theta apply timed on {nplain} of the {B} thetas"})
-    res["roofline"] = {"kernel": "batched apply + backward (four tall contractions)", "bound": "hbm",
-                       "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                       "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None}
+    bytes_plain = nplain * 4 * (w.n_tgt * (rt + 1) + w.n_src * (rs + 1))
+    # ---- accuracy against dense float64 K: 64 thetas x a 4000 x 4000 subsample
+    print("accuracy against dense K", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(11)
+    si = np.sort(rng.choice(w.n_src, 4000, replace=False))
+    ti = np.sort(rng.choice(w.n_tgt, 4000, replace=False))
+    cols = np.linspace(0, B - 1, 64).astype(int)
+    U, V = kern.factors()
+    M = kern.online_core(thd[torch.tensor(cols, device="cuda")])
+    Us, Vs = U[si].double(), V[ti].double()
+    Xsub, Ysub = torch.tensor(X[si]), torch.tensor(Y[ti])
+    errs = []
+    for j, b in enumerate(cols):
+        K = pkg.eval_dense(Xsub, Ysub, th[b], w.kind, w.d, dtype=torch.float64)
+        errs.append((torch.linalg.norm(K - Us @ M[j].double() @ Vs.t()) / torch.linalg.norm(K)).item())
+    errs = np.array(errs)
+    res.update({
+        "phase3_rows_per_s": round((w.n_src + w.n_tgt) / ((ms_u + ms_v) * 1e-3), 1),
+        "phase3_ms": {"sources": round(ms_u, 4), "targets": round(ms_v, 4)},
+        "phase3_tflops": round((fl_u + fl_v) / ((ms_u + ms_v) * 1e-3) / 1e12, 2),
+        "apply_grad_ms": round(ms_ag, 3), "apply_grad_GBps": round(bytes_ag / (ms_ag * 1e-3) / 1e9, 1),
+        "apply_grad_TFLOPs": round(flops_ag / (ms_ag * 1e-3) / 1e12, 2),
+        "apply_grad_frac_fp32_mfma": round(flops_ag / (ms_ag * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4),
+        "plain_apply_GBps": round(bytes_plain / (ms_plain * 1e-3) / 1e9, 1),
+        "batched_vs_plain_theta_per_s": round((B / ms_ag) / (nplain / ms_plain), 3),
+        "plain_note": f"plain per-theta forward apply timed on {nplain} of the {B} thetas; the batched figure "
+                      "is forward + backward",
+        "max_rel_err_vs_dense_fp64": float(f"{errs.max():.3e}"),
+        "median_rel_err_vs_dense_fp64": float(f"{np.median(errs):.3e}"),
+        "accuracy_note": "relative Frobenius error of U M(theta) V^T against dense float64 K on a 4000 x 4000 "
+                         "subsample, for 64 of the thetas (evenly spaced in the sample)",
+    })
+    achieved = fl_proj / (ms_proj * 1e-3) / 1e12
+    res["roofline"] = {
+        "kernel": "k_reduce_mfma_dma<5> (tt_kernel_project: W = V^T X and A = U^T G, float32 MFMA)",
+        "bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": PROJECT_TRAFFIC,
+        "avg_launch_ms": round(ms_proj, 4),
+        "algorithmic": f"2 N r B flops per launch: N = {w.n_tgt} points, B = {B}, r = {rt} (W = V^T X) and "
+                       f"r = {rs} (A = U^T G), averaged; each call also runs a {B * max(rs, rt)}-entry "
+                       "fixed-order sum of the chunk partials (about 0.1% of its time), inside the timing",
+        "traffic_note": PROJECT_TRAFFIC_NOTE,
+    }
+    if not args.no_cpu_baseline:
+        print("cpu baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = oracle_baseline(w, inf["ranks"], args.cpu_points or 200_000, 256)
     return res
 
 
@@ -278,10 +403,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="matern32_d3")
+    ap.add_argument("--workload", default="matern_batched",
+                    help="matern_batched (default), matern32_d3, se_d2_fp64, matern_global, uneven_pairs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-only", action="store_true", help="time the steps only (profiling runs)")
-    ap.add_argument("--cpu-points", type=int, default=2000)
+    ap.add_argument("--cpu-points", type=int, default=None,
+                    help="points per side of the oracle's sample (default: 200000 for matern_batched, 2000 "
+                         "otherwise)")
     ap.add_argument("--tol", type=float, default=None, help="override the workload's tolerance")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy (reference for the HBM byte counters)")
@@ -437,7 +565,7 @@ def main():
                        f"{w.n_src} and {w.n_tgt} points per launch",
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, X, Y, th, args.cpu_points)
+        result["cpu_baseline"] = cpu_baseline(w, X, Y, th, args.cpu_points or 2000)
     print(json.dumps(result), flush=True)
 
 

@@ -214,6 +214,14 @@ tt_status tt_kernel_apply_noalloc(tt_kernel_t h, const void* theta, int B,
                                   const void* X, int64_t ldx, void* Y, int64_t ldy,
                                   void* W_save, void* stream);
 
+/* Projection onto the factor basis, the first contraction of the apply and
+ * of its backward pass (T^T x and S^T g in the low-rank form of Section 1):
+ * W = U^T X (side 0, X: n_src x B) or W = V^T X (side 1, X: n_tgt x B).
+ * X: device, dtype, column-major, ldx >= the side's point count.  W: device,
+ * dtype, r x B column-major (r = r_s or r_t).  Sums over points are formed
+ * per point chunk and added in a fixed order (deterministic). */
+tt_status tt_kernel_project(tt_kernel_t h, int side, const void* X, int64_t ldx, int B, void* W, void* stream);
+
 /* Plain per-theta apply for all b: B independent two-pass applies (reads V and
  * U once per theta).  The reference point for the batched form. */
 tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B,

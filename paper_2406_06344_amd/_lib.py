@@ -79,7 +79,8 @@ class BatchInfo(ctypes.Structure):
 
 EXPORTS = [
     "tt_kernel_build_offline", "tt_kernel_build_from_cores", "tt_kernel_factor_rows", "tt_kernel_online_core",
-    "tt_kernel_apply", "tt_kernel_apply_noalloc", "tt_kernel_apply_plain", "tt_kernel_apply_backward",
+    "tt_kernel_apply", "tt_kernel_apply_noalloc", "tt_kernel_project", "tt_kernel_apply_plain",
+    "tt_kernel_apply_backward",
     "tt_kernel_global_online", "tt_kernel_global_apply", "tt_kernel_global_factors",
     "tt_kernel_batch_build", "tt_kernel_batch_configure", "tt_kernel_batch_factor", "tt_kernel_batch_get_info",
     "tt_kernel_batch_get_class", "tt_kernel_batch_get_factors", "tt_kernel_batch_apply", "tt_kernel_batch_destroy",
@@ -108,6 +109,7 @@ def load():
     lib.tt_kernel_online_core.argtypes = [vp, vp, c_int, vp, vp, vp]
     lib.tt_kernel_apply.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp, vp]
     lib.tt_kernel_apply_noalloc.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp, vp]
+    lib.tt_kernel_project.argtypes = [vp, c_int, vp, i64, c_int, vp, vp]
     lib.tt_kernel_apply_plain.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp]
     lib.tt_kernel_apply_backward.argtypes = [vp, vp, c_int, vp, i64, vp, vp, i64, vp, i64, vp, vp]
     lib.tt_kernel_global_online.argtypes = [vp, vp, c_int, vp, vp]

@@ -301,6 +301,19 @@ class TTKernel:
                                                   out.stride(0), _ptr(W), _stream_ptr(stream)))
         return out
 
+    def project(self, X, side=1, out=None, stream=None):
+        """W (B, r) with row b = F^T x_b: F = V for side 1 (X (B, N_t)), U for side 0 (X (B, N_s))."""
+        if side not in (0, 1):
+            raise ValueError("side must be 0 (U) or 1 (V)")
+        n, r = (self.n_src, self.r_s) if side == 0 else (self.n_tgt, self.r_t)
+        B = _chk(X, "X", None, n).shape[0]
+        if out is None:
+            out = torch.empty((B, r), dtype=self.dtype, device="cuda")
+        _out(out, "out", (B, r), self.dtype)
+        X = _dev(X, self.dtype)
+        check(_lib.load().tt_kernel_project(self._h, side, _ptr(X), X.stride(0), B, _ptr(out), _stream_ptr(stream)))
+        return out
+
     def apply_plain(self, theta, X, stream=None):
         B = _chk(X, "X", None, self.n_tgt).shape[0]
         theta = _dev(_theta(theta, self.d_theta, self.dtype, B, convert=False), self.dtype)

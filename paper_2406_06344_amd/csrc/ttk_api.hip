@@ -244,6 +244,8 @@ struct tt_kernel {
   int kg = 0;
   DBuf Q, Rg, Gwork, M64, Wg;
   ParamCore pc[2];
+  DBuf Cgemm;        // d_theta = 2, float32: the products C_{k1 k2} of the parameter cores
+  OnlineGemm og;
   ChainStage src[3], tgt[3];
   KSpec ks{};
 };
@@ -301,6 +303,12 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
                          h->pcore[j].as<double>());
       h->pc[j] = ParamCore{h->pcore[j].as<double>(), r0, n, r1, h->g.lo[k], h->g.hi[k]};
     }
+  }
+  if (dt == 2 && h->dtype == TTK_FP32) {
+    const size_t cnt = (size_t)h->pc[0].r0 * h->pc[1].r1 * h->pc[0].n * h->pc[1].n;
+    TTK_TRY(h->Cgemm.alloc(cnt * sizeof(float)));
+    TTK_TRY(online_gemm_prepare(h->pc, h->Cgemm.as<float>(), st));
+    h->og = OnlineGemm{h->Cgemm.as<float>(), h->pc[0].n * h->pc[1].n, h->pc[0].r0, h->pc[1].r1};
   }
   TTK_HIP(hipStreamSynchronize(st));   // (Phase 3 is timed on its own below)
   h->rs = h->ranks[d];
@@ -393,6 +401,32 @@ static void fill_info(tt_kernel* h) {
   I.dtype = h->dtype;
 }
 
+// ---------------------------------------------------------- online core
+// M(theta_b) (and dM/dtheta when dM is not NULL) for b < B into the given
+// workspace: the matrix-core product with the precomputed C_{k1 k2} for
+// float32 handles with d_theta = 2 and B >= ONLINE_GEMM_MIN_B, the per-theta
+// kernels otherwise.  online_work_bytes gives the workspace either needs.
+static bool online_uses_gemm(const tt_kernel* h, int B) { return h->og.C != nullptr && B >= ONLINE_GEMM_MIN_B; }
+static size_t online_work_bytes(const tt_kernel* h, int B, bool want_d) {
+  if (h->g.dt == 0) return 0;
+  if (online_uses_gemm(h, B)) return online_gemm_work_floats(h->og, B, want_d) * sizeof(float);
+  return online_work_doubles(h->pc, h->g.dt, B) * sizeof(double);
+}
+static tt_status online_into(const tt_kernel* h, const void* theta, int B, void* M, void* dM, void* work,
+                             hipStream_t st) {
+  const int dt = h->g.dt;
+  if (dt == 0) {
+    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, M, h->rs, B, h->dtype == TTK_FP32);
+  } else if (online_uses_gemm(h, B)) {
+    TTK_TRY(online_core_gemm(h->pc, h->og, static_cast<const float*>(theta), B, static_cast<float*>(M),
+                             static_cast<float*>(dM), static_cast<float*>(work), st));
+  } else {
+    online_core(h->dtype, h->pc, dt, theta, B, M, dM, static_cast<double*>(work), st);
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
 // ---------------------------------------------------------- batched apply
 // Scratch of one batched apply: M(theta_b) for all b, W = V^T X (unless the
 // caller keeps it), Z = M W, the reduction's partial sums and the online
@@ -403,7 +437,7 @@ struct ApplyScratch {
   void* W = nullptr;
   void* Z = nullptr;
   void* part = nullptr;
-  double* owork = nullptr;
+  void* owork = nullptr;
 };
 struct ApplySizes {
   size_t M = 0, W = 0, Z = 0, part = 0, owork = 0;   // bytes, each rounded up to 256
@@ -414,7 +448,7 @@ static void apply_sizes(const tt_kernel* h, int B, bool need_w, ApplySizes* z) {
   z->W = need_w ? up256((size_t)h->rt * B * h->es) : 0;
   z->Z = up256((size_t)h->rs * B * h->es);
   z->part = up256(apply_reduce_work(h->nt, h->rt, B));
-  z->owork = h->g.dt > 0 ? up256(online_work_doubles(h->pc, h->g.dt, B) * sizeof(double)) : 0;
+  z->owork = up256(online_work_bytes(h, B, false));
 }
 
 static tt_status check_apply_args(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, const void* Y,
@@ -431,11 +465,7 @@ static tt_status check_apply_args(tt_kernel_t h, const void* theta, int B, const
 // y_b = U M(theta_b) V^T x_b for b < B with the given scratch (no allocation).
 static tt_status apply_core(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
                             int64_t ldy, const ApplyScratch& s, hipStream_t st) {
-  const int dt = h->g.dt;
-  if (dt == 0)
-    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, s.M, h->rs, B, h->dtype == TTK_FP32);
-  else
-    online_core(h->dtype, h->pc, dt, theta, B, s.M, nullptr, s.owork, st);
+  TTK_TRY(online_into(h, theta, B, s.M, nullptr, s.owork, st));
   TTK_TRY(apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, s.W, s.part, st));
   batched_matvec(h->dtype, s.M, h->rs, h->rt, 0, s.W, B, s.Z, st);
   TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, s.Z, B, Y, ldy, st));
@@ -545,17 +575,10 @@ tt_status tt_kernel_online_core(tt_kernel_t h, const void* theta, int B, void* M
   if (B < 0 || (B > 0 && !M_out)) return fail(TTK_ERR_ARG, "bad B or M_out");
   if (B == 0) return TTK_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const int dt = h->g.dt;
-  if (dt == 0) {
-    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, M_out, h->rs, B, h->dtype == TTK_FP32);
-    TTK_HIP(hipGetLastError());
-    return TTK_OK;
-  }
-  if (!theta) return fail(TTK_ERR_ARG, "theta is NULL");
-  TTK_TRY(h->work.alloc(online_work_doubles(h->pc, dt, B) * sizeof(double)));
-  online_core(h->dtype, h->pc, dt, theta, B, M_out, dM_out, h->work.as<double>(), st);
-  TTK_HIP(hipGetLastError());
-  return TTK_OK;
+  if (h->g.dt > 0 && !theta) return fail(TTK_ERR_ARG, "theta is NULL");
+  const size_t wb = online_work_bytes(h, B, dM_out != nullptr);
+  if (wb) TTK_TRY(h->work.alloc(wb));
+  return online_into(h, theta, B, M_out, h->g.dt > 0 ? dM_out : nullptr, h->work.p, st);
 }
 
 static tt_status prepare_M(tt_kernel_t h, const void* theta, int B, bool with_dM, hipStream_t st) {
@@ -596,7 +619,7 @@ tt_status tt_kernel_apply(tt_kernel_t h, const void* theta, int B, const void* X
   }
   if (z.owork) {
     TTK_TRY(h->work.alloc(z.owork));
-    s.owork = h->work.as<double>();
+    s.owork = h->work.p;
   }
   return apply_core(h, theta, B, X, ldx, Y, ldy, s, st);
 }
@@ -629,8 +652,21 @@ tt_status tt_kernel_apply_noalloc(tt_kernel_t h, const void* theta, int B, const
   off += z.Z;
   if (z.part) s.part = base + off;
   off += z.part;
-  if (z.owork) s.owork = reinterpret_cast<double*>(base + off);
+  if (z.owork) s.owork = base + off;
   return apply_core(h, theta, B, X, ldx, Y, ldy, s, st);
+}
+
+tt_status tt_kernel_project(tt_kernel_t h, int side, const void* X, int64_t ldx, int B, void* W, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (side != 0 && side != 1) return fail(TTK_ERR_ARG, "side must be 0 (U) or 1 (V)");
+  if (B < 0) return fail(TTK_ERR_ARG, "B < 0");
+  if (B == 0) return TTK_OK;
+  const int64_t n = side == 0 ? h->ns : h->nt;
+  if (!X || !W) return fail(TTK_ERR_ARG, "X or W is NULL");
+  if (ldx < n) return fail(TTK_ERR_ARG, "ldx too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return side == 0 ? reduce_into(h, h->U.p, h->ldu, h->ns, h->rs, X, ldx, B, W, st)
+                   : reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, W, st);
 }
 
 tt_status tt_kernel_apply_plain(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,

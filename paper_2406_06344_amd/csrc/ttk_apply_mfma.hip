@@ -43,15 +43,16 @@ inline size_t expand_lds_floats(int r, int kp) { return (size_t)2 * (EX_TB * r +
 
 // KS = K-steps = ceil(r / 4).  VEC: Y's columns are 16-byte aligned (ldy
 // and the base a multiple of 4 floats), so a lane's 4 points go as one store.
+// ACC: Y += F Z instead of Y = F Z (a K dimension above 128 in passes).
 // Blocks of Z are fetched by direct global->LDS loads (4 bytes per lane,
 // lane l to the wave's base + 4 l), double-buffered: the next block is in
 // flight while this one is multiplied.  A operands past r are zero, so the
 // padding reads (finite values: LDS starts zeroed, later blocks overwrite
 // with Z) contribute nothing.
-template <int KS, bool VEC>
+template <int KS, bool VEC, bool ACC>
 __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict__ F, int ldf, int64_t N, int r,
                                                         const float* __restrict__ Z, int B, float* __restrict__ Y,
-                                                        int64_t ldy) {
+                                                        int64_t ldy, int bpw) {
   extern __shared__ float zsm[];
   constexpr int KP = 4 * KS;                     // r rounded up to 4
   const int stage = EX_TB * r + KP;
@@ -71,7 +72,10 @@ __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict_
       af[s][t] = (p < N && c < r) ? row[c] : 0.0f;
     }
   }
-  const int nb = (B + EX_TB - 1) / EX_TB;
+  // this workgroup's theta blocks: bpw of them from blockIdx.y * bpw
+  const int bfirst = blockIdx.y * bpw;
+  const int nb = min(bpw, (B + EX_TB - 1) / EX_TB - bfirst);
+  if (nb <= 0) return;                           // (whole workgroup: no barrier is skipped by part of it)
   auto issue = [&](int b0, float* buf) {
     const int total = min(EX_TB, B - b0) * r;    // the block's columns are contiguous in Z
     const float* zb = Z + (int64_t)b0 * r;
@@ -79,9 +83,9 @@ __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict_
       if (64 * j + lane < total) __builtin_amdgcn_global_load_lds(zb + 64 * j + lane, buf + 64 * j, 4, 0, 0);
   };
   __syncthreads();                               // the zero fill is done before any load lands
-  issue(0, zsm);
+  issue(bfirst * EX_TB, zsm);
   for (int ib = 0; ib < nb; ++ib) {
-    const int b0 = ib * EX_TB;
+    const int b0 = (bfirst + ib) * EX_TB;
     const float* zs = zsm + (size_t)(ib & 1) * stage;
     __builtin_amdgcn_s_waitcnt(0);               // this wave's loads of block ib have landed
     __syncthreads();                             // everyone's; and block ib - 1 is consumed
@@ -114,11 +118,15 @@ __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict_
       for (int s = 0; s < 4; ++s) {
         const int64_t p = p0 + 16 * s + 4 * kq;
         if (VEC && p + 3 < N) {
-          *reinterpret_cast<f4*>(ycol + p) = acc[s][q];
+          if (ACC) *reinterpret_cast<f4*>(ycol + p) += acc[s][q];
+          else *reinterpret_cast<f4*>(ycol + p) = acc[s][q];
         } else {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (p + v < N) ycol[p + v] = acc[s][q][v];
+            if (p + v < N) {
+              if (ACC) ycol[p + v] += acc[s][q][v];
+              else ycol[p + v] = acc[s][q][v];
+            }
         }
       }
     }
@@ -379,18 +387,30 @@ tt_status set_lds(K kern, size_t bytes) {
   return TTK_OK;
 }
 
+// Workgroups over the points; when those are few (a short, wide product such
+// as the online core's) the theta blocks are split over grid.y as well, so
+// about EX_WG_TARGET workgroups run.
+constexpr int EX_WG_TARGET = 512;
+
 template <int KS>
 tt_status launch_expand(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
-                        hipStream_t st) {
+                        bool acc, hipStream_t st) {
   const size_t sh = expand_lds_floats(r, 4 * KS) * sizeof(float);
   const bool vec = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
-  const dim3 grid((unsigned)((N + EX_P - 1) / EX_P));
-  if (vec) {
-    TTK_TRY(set_lds(&k_expand_mfma<KS, true>, sh));
-    hipLaunchKernelGGL((k_expand_mfma<KS, true>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+  const int64_t gx = (N + EX_P - 1) / EX_P;
+  const int nb = (B + EX_TB - 1) / EX_TB;
+  const int gy_want = (int)std::min<int64_t>(nb, std::max<int64_t>(1, (EX_WG_TARGET + gx - 1) / gx));
+  const int bpw = (nb + gy_want - 1) / gy_want;
+  const dim3 grid((unsigned)gx, (unsigned)((nb + bpw - 1) / bpw));
+  if (acc) {
+    TTK_TRY(set_lds(&k_expand_mfma<KS, false, true>, sh));
+    hipLaunchKernelGGL((k_expand_mfma<KS, false, true>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy, bpw);
+  } else if (vec) {
+    TTK_TRY(set_lds(&k_expand_mfma<KS, true, false>, sh));
+    hipLaunchKernelGGL((k_expand_mfma<KS, true, false>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy, bpw);
   } else {
-    TTK_TRY(set_lds(&k_expand_mfma<KS, false>, sh));
-    hipLaunchKernelGGL((k_expand_mfma<KS, false>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+    TTK_TRY(set_lds(&k_expand_mfma<KS, false, false>, sh));
+    hipLaunchKernelGGL((k_expand_mfma<KS, false, false>), grid, dim3(256), sh, st, F, ldf, N, r, Z, B, Y, ldy, bpw);
   }
   return TTK_OK;
 }
@@ -459,10 +479,10 @@ tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const flo
 }
 
 tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
-                            hipStream_t st) {
+                            hipStream_t st, bool accumulate) {
   switch ((r + 3) / 4) {
 #define TTK_EXPAND_CASE(k) \
-  case k: return launch_expand<k>(F, ldf, N, r, Z, B, Y, ldy, st);
+  case k: return launch_expand<k>(F, ldf, N, r, Z, B, Y, ldy, accumulate, st);
     TTK_EXPAND_CASE(1) TTK_EXPAND_CASE(2) TTK_EXPAND_CASE(3) TTK_EXPAND_CASE(4) TTK_EXPAND_CASE(5)
     TTK_EXPAND_CASE(6) TTK_EXPAND_CASE(7) TTK_EXPAND_CASE(8) TTK_EXPAND_CASE(9) TTK_EXPAND_CASE(10)
     TTK_EXPAND_CASE(11) TTK_EXPAND_CASE(12) TTK_EXPAND_CASE(13) TTK_EXPAND_CASE(14) TTK_EXPAND_CASE(15)

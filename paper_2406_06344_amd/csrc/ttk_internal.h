@@ -233,6 +233,20 @@ void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int 
 void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
                        void* M, void* dM, double* work, hipStream_t st);
 size_t online_work_doubles(const ParamCore* pc, int dt, int B);
+// d_theta = 2, float32 outputs, as one matrix-core product: with the
+// coefficient-basis parameter cores Ghat_1 (rs x n1 x rm) and Ghat_2
+// (rm x n2 x rt), M(theta) = sum_{k1,k2} T_k1(t_1) T_k2(t_2) C_{k1 k2}, where
+// C_{k1 k2} = Ghat_1[:, k1, :] Ghat_2[:, k2, :] is formed once per build
+// (online_gemm_prepare), and the derivatives replace T_kj by T_kj'.
+struct OnlineGemm {
+  const float* C = nullptr;   // device, (rs rt) x nk row-major, row e = a + c rs, column k1 n2 + k2
+  int nk = 0, rs = 0, rt = 0;
+};
+constexpr int ONLINE_GEMM_MIN_B = 32;   // below this the per-theta kernels are faster
+tt_status online_gemm_prepare(const ParamCore* pc, float* C, hipStream_t st);   // C: rs rt n1 n2 floats
+size_t online_gemm_work_floats(const OnlineGemm& og, int B, bool want_d);
+tt_status online_core_gemm(const ParamCore* pc, const OnlineGemm& og, const float* theta, int B, float* M,
+                           float* dM, float* work, hipStream_t st);
 
 // W (r x B) = F^T X.  work: apply_reduce_work(N, r, B) bytes of device memory
 // for the per-workgroup partial sums (may be NULL when that is 0); every
@@ -252,8 +266,9 @@ int mfma_ld(int r);
 size_t apply_reduce_mfma_work(int64_t N, int r, int B);
 tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
                             float* W, double* part, hipStream_t st);
+// Y (N x B, ldy) = F Z (or += with accumulate), Z: r x B with leading dimension r.
 tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
-                            int64_t ldy, hipStream_t st);
+                            int64_t ldy, hipStream_t st, bool accumulate = false);
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
                     int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,

@@ -12,6 +12,8 @@
 // launch forms the products H_1 H_2, dH_1 H_2 and H_1 dH_2, one thread per
 // entry.  Everything is accumulated in double precision and rounded once on
 // store.
+#include <algorithm>
+
 #include "ttk_internal.h"
 
 namespace ttk {
@@ -139,6 +141,67 @@ void launch_online(const OnlineArgs& oa, const TT* theta, int B, T* M, T* dM, do
   }
 }
 
+// C[e, k1 n2 + k2] = sum_m Ghat_1[a, k1, m] Ghat_2[m, k2, c], e = a + c rs,
+// accumulated in double, stored as float; one thread per entry.
+__global__ void __launch_bounds__(256) k_online_cprod(const double* G1, const double* G2, int rs, int n1, int rm,
+                                                      int n2, int rt, float* C) {
+  const int nk = n1 * n2;
+  const int64_t total = (int64_t)rs * rt * nk;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int kk = (int)(idx % nk);
+    const int64_t e = idx / nk;
+    const int a = (int)(e % rs), c = (int)(e / rs);
+    const int k1 = kk / n2, k2 = kk % n2;
+    const double* g1 = G1 + a + (int64_t)k1 * rs;            // stride rs n1 over m
+    const double* g2 = G2 + (int64_t)k2 * rm + (int64_t)c * rm * n2;
+    double s = 0.0;
+    for (int m = 0; m < rm; ++m) s += g1[(int64_t)m * rs * n1] * g2[m];
+    C[idx] = (float)s;
+  }
+}
+
+// Coefficients of one theta: column b of coefM holds T_k1(t_1) T_k2(t_2) at
+// row k1 n2 + k2; columns 2 b + j of coefD the products with T_kj replaced by
+// dT_kj/dtheta_j.  Rows are split in passes of 128 (pass p, row kk at
+// p * 128 * cols + b * 128 + kk % 128) so every pass is a contiguous 128 x cols
+// block.  One thread per (b, kk).
+__global__ void __launch_bounds__(256) k_online_coef(const float* theta, int B, int n1, int n2, double lo1,
+                                                     double hi1, double lo2, double hi2, int want_d, float* coefM,
+                                                     float* coefD) {
+  const int nk = n1 * n2;
+  const int64_t total = (int64_t)B * nk;
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+    const int kk = (int)(idx % nk);
+    const int b = (int)(idx / nk);
+    const int k1 = kk / n2, k2 = kk % n2;
+    double v[2], dv[2];
+    const int kj[2] = {k1, k2};
+    const double lo[2] = {lo1, lo2}, hi[2] = {hi1, hi2};
+    for (int j = 0; j < 2; ++j) {
+      const double t = (2.0 * (double)theta[2 * (int64_t)b + j] - (lo[j] + hi[j])) / (lo[j] - hi[j]);
+      double tm = 1.0, tc = t, dm = 0.0, dc = 1.0;   // T_0, T_1 and their derivatives
+      double tk = 1.0, dk = 0.0;
+      if (kj[j] == 1) { tk = t; dk = 1.0; }
+      for (int k = 2; k <= kj[j]; ++k) {
+        const double tn = 2.0 * t * tc - tm;
+        const double dn = 2.0 * tc + 2.0 * t * dc - dm;
+        tm = tc; tc = tn; dm = dc; dc = dn;
+        tk = tn; dk = dn;
+      }
+      v[j] = tk;
+      dv[j] = dk * 2.0 / (lo[j] - hi[j]);
+    }
+    const int p = kk / 128, kr = kk % 128;
+    const int prow = min(128, nk - 128 * p);
+    coefM[(size_t)p * 128 * B + (size_t)b * prow + kr] = (float)(v[0] * v[1]);
+    if (want_d) {
+      float* cd = coefD + (size_t)p * 128 * 2 * B;
+      cd[(size_t)(2 * b) * prow + kr] = (float)(dv[0] * v[1]);
+      cd[(size_t)(2 * b + 1) * prow + kr] = (float)(v[0] * dv[1]);
+    }
+  }
+}
+
 }  // namespace
 
 void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int dt, const void* theta, int B,
@@ -162,6 +225,43 @@ void online_core_mixed(int theta_dtype, int out_dtype, const ParamCore* pc, int 
 void online_core(int dtype, const ParamCore* pc, int dt, const void* theta, int B, void* M, void* dM,
                  double* work, hipStream_t st) {
   online_core_mixed(dtype, dtype, pc, dt, theta, B, M, dM, work, st);
+}
+
+tt_status online_gemm_prepare(const ParamCore* pc, float* C, hipStream_t st) {
+  const int rs = pc[0].r0, n1 = pc[0].n, rm = pc[0].r1, n2 = pc[1].n, rt = pc[1].r1;
+  if (pc[1].r0 != rm) return fail(TTK_ERR_ARG, "parameter cores do not chain");
+  const int64_t total = (int64_t)rs * rt * n1 * n2;
+  hipLaunchKernelGGL(k_online_cprod, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256), 0, st,
+                     pc[0].Ghat, pc[1].Ghat, rs, n1, rm, n2, rt, C);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+size_t online_gemm_work_floats(const OnlineGemm& og, int B, bool want_d) {
+  const size_t passes = (size_t)(og.nk + 127) / 128;
+  return passes * 128 * (size_t)B * (want_d ? 3 : 1);
+}
+
+tt_status online_core_gemm(const ParamCore* pc, const OnlineGemm& og, const float* theta, int B, float* M, float* dM,
+                           float* work, hipStream_t st) {
+  if (B <= 0) return TTK_OK;
+  const int nk = og.nk, n1 = pc[0].n, n2 = pc[1].n;
+  const size_t passes = (size_t)(nk + 127) / 128;
+  float* coefM = work;
+  float* coefD = work + passes * 128 * (size_t)B;
+  const int64_t total = (int64_t)B * nk;
+  hipLaunchKernelGGL(k_online_coef, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256), 0, st,
+                     theta, B, n1, n2, pc[0].lo, pc[0].hi, pc[1].lo, pc[1].hi, dM != nullptr ? 1 : 0, coefM, coefD);
+  const int64_t ne = (int64_t)og.rs * og.rt;
+  for (size_t p = 0; p < passes; ++p) {
+    const int kr = std::min(128, nk - (int)(128 * p));
+    const float* Cp = og.C + 128 * p;
+    TTK_TRY(apply_expand_mfma(Cp, nk, ne, kr, coefM + p * 128 * (size_t)B, B, M, ne, st, p > 0));
+    if (dM)
+      TTK_TRY(apply_expand_mfma(Cp, nk, ne, kr, coefD + p * 128 * 2 * (size_t)B, 2 * B, dM, ne, st, p > 0));
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
 }
 
 size_t online_work_doubles(const ParamCore* pc, int dt, int B) {

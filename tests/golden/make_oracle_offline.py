@@ -5,7 +5,8 @@ cross does not depend on the points; the stored cores, ranks, index sets,
 decision log and per-sweep errors are the oracle's alone (this script calls
 only oracle/ and synth/).
 
-usage: python tests/golden/make_oracle_offline.py matern32_d3
+usage: python tests/golden/make_oracle_offline.py matern32_d3   (about 30 s of CPU)
+       python tests/golden/make_oracle_offline.py matern_batched (tens of minutes)
 """
 import os
 import sys
@@ -25,7 +26,7 @@ def main(name):
     P = kernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param, w.const or None)
     x0 = np.asarray(w.box_s, float)[:, :1].T
     y0 = np.asarray(w.box_t, float)[:, :1].T
-    out = driver.offline(P, x0, y0, w.tol, seed=0)
+    out = driver.offline(P, x0, y0, w.tol, seed=0, max_sweeps=w.extra.get("max_sweeps", 200))
     info = out["info"]
     arrays = {"ranks": np.array(out["ranks"]), "cross_ranks": np.array(info["ranks"]),
               "sweeps": np.array(info["sweeps"]), "error": np.array(info["error"])}
@@ -42,6 +43,7 @@ def main(name):
                                    dtype=np.int64).reshape(-1, 3)
     arrays["log_margin"] = np.array(margins, dtype=np.float64)
     arrays["errors"] = np.array(info["errors"], dtype=np.float64)
+    arrays["converged"] = np.array(bool(info["converged"]))
     path = os.path.join(HERE, f"{name}_oracle.npz")
     np.savez_compressed(path, **arrays)
     print(path, out["ranks"], info["ranks"], info["sweeps"])

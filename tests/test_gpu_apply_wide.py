@@ -88,3 +88,30 @@ def test_wide_apply_and_backward_match_oracle(rs, rt, ns, nt, B):
     # the plain per-theta apply (other kernels) agrees with the batched one
     Yp = kern.apply_plain(tht[:5], torch.tensor(xb[:, :5].T.copy(), dtype=torch.float32))
     assert errs(Yp.cpu().numpy(), Yg[:5].cpu().numpy())[0] <= 1e-5
+
+
+@pytest.mark.parametrize("B,npar", [(300, 16), (40, 12), (1000, 8)])
+def test_online_core_two_parameters_matches_oracle(B, npar):
+    """M(theta) and dM/dtheta for d_theta = 2 in float32 with B >= 32 (the
+    matrix-core form: M = sum_{k1,k2} T_k1 T_k2 C_{k1 k2} with C the products of
+    the parameter cores, in passes of 128 rows when n1 n2 > 128) against the
+    oracle's Algorithm 3 on the same cores."""
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    rng = np.random.default_rng(B)
+    r = [1, N_SP, 80, 150, 70, N_SP, 1]
+    n = [N_SP, N_SP, npar, npar, N_SP, N_SP]
+    cores = [rng.standard_normal((r[k], n[k], r[k + 1])) / np.sqrt(r[k] * n[k]) for k in range(6)]
+    bth = np.array([[0.5, 2.0], [0.5, 2.5]])
+    X = rng.uniform(0, 1, (50, 2))
+    Y = rng.uniform([2, 0], [3, 1], (40, 2))
+    kern = pkg.TTKernel.from_cores(cores, torch.tensor(X), torch.tensor(Y), "matern", 2, BOX_S, BOX_T, bth,
+                                   n_spatial=N_SP, n_param=npar, dtype=torch.float32)
+    th = rng.uniform(bth[:, 0], bth[:, 1], (B, 2)).astype(np.float32).astype(np.float64)
+    M, dM = kern.online_core(torch.tensor(th, dtype=torch.float32), deriv=True)
+    M, dM = M.double().cpu().numpy(), dM.double().cpu().numpy()
+    Mo = np.stack([opttk.online_H(cores[2:4], t, bth, npar) for t in th])
+    dMo = np.stack([np.stack(opttk.online_dH(cores[2:4], t, bth, npar)) for t in th])
+    em, edm = errs(M, Mo), errs(dM, dMo)
+    say(f"[online] B {B} n_param {npar}: M {em}, dM {edm}")
+    assert em[0] <= 1e-6 and em[1] <= 2e-6 and edm[0] <= 1e-5 and edm[1] <= 1e-5
