@@ -35,19 +35,19 @@ import synth  # noqa: E402
 
 METRIC = "offline U/V rows/s + batched apply+grad GB/s vs plain apply, at ≤1e-5 rel err"
 HBM_PEAK_GBPS = 8000.0
-# HBM bytes per launch of the roofline kernel (k_factor_mfma on matern32_d3,
-# rounded ranks 1,6,23,71 | 72,30,7,1) from rocprofv3 counter runs
-# (FETCH_SIZE and WRITE_SIZE, separate runs): (2 x 1066.75 + 27734.375) KiB
-# and (2 x 1214.4375 + 28125.0) KiB for the two launches, averaged, with the
-# scales 2.000 and 1.000 read off the same counters on a plain 1 GiB copy.
-# None whenever the kernel has changed since the counters were taken.
-TRAFFIC = 31133312
+# HBM bytes per launch of k_factor_mfma on matern32_d3 (the roofline of that
+# workload's line): None, the kernel's output rows are padded since the
+# counters in profiles/ were taken.
+TRAFFIC = None
 FP32_PEAK_TFLOPS = 157.3
-# HBM bytes per launch of the projection kernel on the 1M-point workload
-# (FETCH_SIZE and WRITE_SIZE runs, scaled by the same counters on a plain
-# copy); None until the counters are taken for the current kernel.
-PROJECT_TRAFFIC = None
-PROJECT_TRAFFIC_NOTE = "not measured for this kernel"
+# HBM bytes per launch of the projection kernel k_reduce_mfma_dma<5> on the
+# 1M-point workload from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
+# separate runs): (2.000 x 8312822.9 + 1.000 x 39688.8) KiB, averaged over its
+# two launches, with the scales 2.000 and 1.000 read off the same counters on
+# a plain 1 GiB copy.  None whenever the kernel has changed since.
+PROJECT_TRAFFIC = 17065302528
+PROJECT_TRAFFIC_NOTE = ("HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a plain 1 GiB "
+                        "copy), average of the two launches; algorithmic 16.75 GB (X, F, float64 chunk partials)")
 
 
 def phase3_flops_per_point(ranks, n):
