@@ -86,7 +86,8 @@ typedef enum { TTK_FP64 = 0, TTK_FP32 = 1 } tt_dtype;
 /* Build parameters (inputs of the offline stage, Algorithm 2). */
 typedef struct {
   int d;                 /* spatial dimension, 1..3                                  */
-  int d_theta;           /* parameter dimension, 0..2 (must match `kind`)            */
+  int d_theta;           /* parameter dimension, 0..2: the kind's parameter count, or
+                            0 with theta_fixed (non-parametric TTK)                 */
   int n_spatial;         /* Chebyshev nodes per spatial dimension, 2..32             */
   int n_param;           /* Chebyshev nodes per parameter dimension, 2..32           */
   int kind;              /* tt_kernel_kind                                           */
@@ -106,6 +107,11 @@ typedef struct {
   int dtype;             /* tt_dtype of U, V, M and the apply                        */
   int symmetric_psd;     /* 1 = PTTK-Global-1 (Algorithm 4), X = Y and box_t = box_s,
                             and the build also computes the thin QR [U V] = Q R      */
+  double theta_fixed[2]; /* d_theta = 0 for a kind that has parameters: the
+                            non-parametric TTK method (Section 4.1, H = I) for the
+                            kernel at theta = theta_fixed (e.g. l = 1, or (l, nu)
+                            for TTK_MATERN); every value must be positive.
+                            Ignored when d_theta equals the kind's parameter count */
 } tt_kernel_params;
 
 typedef struct {

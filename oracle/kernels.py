@@ -148,13 +148,20 @@ def dkappa_dtheta(kind, x, y, theta, const=None):
 
 class Problem:
     """A parametric kernel on boxes B_s x B_theta x B_t with per-dimension
-    node counts, in the variable order xi = (x, theta, y)."""
+    node counts, in the variable order xi = (x, theta, y).
+
+    theta_fixed: the kernel's parameters held at these values, d_theta = 0
+    (the non-parametric TTK method of Section 4.1, where H = I)."""
 
     def __init__(self, kind, d, box_s, box_t, box_theta, n_spatial, n_param=None,
-                 const=None):
+                 const=None, theta_fixed=None):
         self.kind = kind
         self.d = int(d)
-        self.dt = PARAM_DIMS[kind]
+        self.theta_fixed = None if theta_fixed is None else np.asarray(theta_fixed, float).reshape(-1)
+        if self.theta_fixed is not None:
+            assert self.theta_fixed.size == PARAM_DIMS[kind]
+            box_theta = []
+        self.dt = 0 if self.theta_fixed is not None else PARAM_DIMS[kind]
         self.const = const
         self.box_s = np.asarray(box_s, float).reshape(self.d, 2)
         self.box_t = np.asarray(box_t, float).reshape(self.d, 2)
@@ -176,6 +183,8 @@ class Problem:
     def entries(self, idx):
         """f_kappa at the Chebyshev grid multi-indices idx (P, D)."""
         x, th, y = self.coords(idx)
+        if self.theta_fixed is not None:
+            th = np.broadcast_to(self.theta_fixed, (x.shape[0], self.theta_fixed.size))
         return kappa(self.kind, x, y, th, self.const)
 
     def full_tensor(self):

@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
         ("box_theta", ctypes.c_double * 4), ("tol", ctypes.c_double),
         ("max_rank", ctypes.c_int), ("max_sweeps", ctypes.c_int), ("init_card", ctypes.c_int),
         ("init_max_it", ctypes.c_int), ("n_test", ctypes.c_int), ("seed", ctypes.c_uint64),
-        ("dtype", ctypes.c_int), ("symmetric_psd", ctypes.c_int),
+        ("dtype", ctypes.c_int), ("symmetric_psd", ctypes.c_int), ("theta_fixed", ctypes.c_double * 2),
     ]
 
 

@@ -37,10 +37,18 @@ def _dtype_code(dtype):
 
 def make_params(kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None, tol=1e-6,
                 dtype=torch.float32, seed=0, max_rank=256, max_sweeps=200, init_card=2,
-                init_max_it=10, n_test=0, kernel_const=0.0, symmetric_psd=False):
+                init_max_it=10, n_test=0, kernel_const=0.0, symmetric_psd=False, theta_fixed=None):
+    """theta_fixed: the kind's parameters held fixed (non-parametric TTK, d_theta = 0)."""
     p = Params()
     p.d = int(d)
     p.d_theta = KIND_DTHETA[kind]
+    if theta_fixed is not None:
+        tf = [float(v) for v in np.ravel(theta_fixed)]
+        if len(tf) != KIND_DTHETA[kind]:
+            raise ValueError(f"theta_fixed: {kind} has {KIND_DTHETA[kind]} parameters, got {len(tf)}")
+        p.d_theta = 0
+        for i, v in enumerate(tf):
+            p.theta_fixed[i] = v
     p.n_spatial = int(n_spatial)
     p.n_param = int(n_spatial if n_param is None else n_param)
     p.kind = KINDS[kind]
@@ -149,8 +157,8 @@ class TTKernel:
         flat = np.concatenate([np.asarray(c, np.float64).reshape(-1, order="F") for c in cores])
         r_arr = (ctypes.c_int * len(ranks))(*ranks)
         c_arr = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        if len(cores) != 2 * int(d) + KIND_DTHETA[kind]:
-            raise ValueError(f"cores: expected {2 * int(d) + KIND_DTHETA[kind]} cores, got {len(cores)}")
+        if len(cores) != 2 * int(d) + p.d_theta:
+            raise ValueError(f"cores: expected {2 * int(d) + p.d_theta} cores, got {len(cores)}")
         Xs = _soa(X, dtype, d, "X")
         Ys = Xs if (Y is None or Y is X) else _soa(Y, dtype, d, "Y")
         h = ctypes.c_void_p()
@@ -415,14 +423,15 @@ def kernel_apply(kern: TTKernel, theta, X):
 
 
 def eval_entries(idx, kind, d, box_s, box_t, box_theta=(), n_spatial=16, n_param=None, kernel_const=0.0,
-                 stream=None):
+                 theta_fixed=None, stream=None):
     """f_kappa at grid multi-indices idx (P, D) int32, on the device, float64."""
     lib = _lib.load()
-    p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, kernel_const=kernel_const)
-    D = 2 * int(d) + KIND_DTHETA[kind]
+    p = make_params(kind, d, box_s, box_t, box_theta, n_spatial, n_param, kernel_const=kernel_const,
+                    theta_fixed=theta_fixed)
+    D = 2 * int(d) + p.d_theta
     if idx.dim() != 2 or idx.shape[1] != D:
         raise ValueError(f"idx: expected shape (P, {D}), got {tuple(idx.shape)}")
-    n = [p.n_spatial] * int(d) + [p.n_param] * KIND_DTHETA[kind] + [p.n_spatial] * int(d)
+    n = [p.n_spatial] * int(d) + [p.n_param] * p.d_theta + [p.n_spatial] * int(d)
     if idx.numel() and (int(idx.min()) < 0 or any(int(idx[:, j].max()) >= n[j] for j in range(D))):
         raise ValueError("idx: node index out of range")
     idx = idx.to(device="cuda", dtype=torch.int32).contiguous()

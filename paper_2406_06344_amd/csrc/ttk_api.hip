@@ -145,15 +145,20 @@ static tt_status check_params(const tt_kernel_params* p) {
   if (p->d < 1 || p->d > 3) return fail(TTK_ERR_ARG, "d = %d outside 1..3", p->d);
   const int dt = kind_dtheta(p->kind);
   if (dt < 0) return fail(TTK_ERR_ARG, "unknown kernel kind %d", p->kind);
-  if (p->d_theta != dt) return fail(TTK_ERR_ARG, "kernel kind %d needs d_theta = %d (got %d)", p->kind, dt, p->d_theta);
+  if (p->d_theta != dt && p->d_theta != 0)
+    return fail(TTK_ERR_ARG, "kernel kind %d needs d_theta = %d, or 0 with theta_fixed (got %d)", p->kind, dt,
+                p->d_theta);
+  if (p->d_theta == 0)   // non-parametric TTK at fixed theta: every parameter positive
+    for (int j = 0; j < dt; ++j)
+      if (!(p->theta_fixed[j] > 0)) return fail(TTK_ERR_ARG, "theta_fixed[%d] must be positive", j);
   if (p->n_spatial < 2 || p->n_spatial > MAXN) return fail(TTK_ERR_ARG, "n_spatial = %d outside 2..%d", p->n_spatial, MAXN);
-  if (dt > 0 && (p->n_param < 2 || p->n_param > MAXN))
+  if (p->d_theta > 0 && (p->n_param < 2 || p->n_param > MAXN))
     return fail(TTK_ERR_ARG, "n_param = %d outside 2..%d", p->n_param, MAXN);
   for (int j = 0; j < p->d; ++j) {
     if (!(p->box_s[2 * j] < p->box_s[2 * j + 1])) return fail(TTK_ERR_ARG, "source box dimension %d is empty", j);
     if (!(p->box_t[2 * j] < p->box_t[2 * j + 1])) return fail(TTK_ERR_ARG, "target box dimension %d is empty", j);
   }
-  for (int j = 0; j < dt; ++j)
+  for (int j = 0; j < p->d_theta; ++j)
     if (!(p->box_theta[2 * j] < p->box_theta[2 * j + 1])) return fail(TTK_ERR_ARG, "parameter box %d is empty", j);
   if (p->dtype != TTK_FP32 && p->dtype != TTK_FP64) return fail(TTK_ERR_ARG, "dtype %d unknown", p->dtype);
   if (p->max_rank > MAXR) return fail(TTK_ERR_ARG, "max_rank %d above %d", p->max_rank, MAXR);
@@ -344,7 +349,8 @@ static tt_status begin_build(const tt_kernel_params* p, const void* X, int64_t n
   make_grid(p, &h->g);
   TTK_TRY(h->nodes.alloc((size_t)MAXD * MAXN * sizeof(double)));
   TTK_HIP(hipMemcpyAsync(h->nodes.p, h->g.nodes, sizeof(h->g.nodes), hipMemcpyHostToDevice, st));
-  h->ks = KSpec{p->kind, p->d, p->d_theta, h->g.D, p->kernel_const, h->nodes.as<double>()};
+  h->ks = KSpec{p->kind, p->d, p->d_theta, h->g.D, p->kernel_const, h->nodes.as<double>(),
+                {p->theta_fixed[0], p->theta_fixed[1]}};
   *hh = std::move(h);
   return TTK_OK;
 }
@@ -796,7 +802,7 @@ tt_status tt_kernel_eval_entries(const tt_kernel_params* p, const int32_t* idx, 
   DBuf nodes;
   TTK_TRY(nodes.alloc(sizeof(g.nodes)));
   TTK_HIP(hipMemcpyAsync(nodes.p, g.nodes, sizeof(g.nodes), hipMemcpyHostToDevice, st));
-  KSpec ks{p->kind, p->d, p->d_theta, g.D, p->kernel_const, nodes.as<double>()};
+  KSpec ks{p->kind, p->d, p->d_theta, g.D, p->kernel_const, nodes.as<double>(), {p->theta_fixed[0], p->theta_fixed[1]}};
   eval_multi32(ks, idx, P, out, st);
   TTK_HIP(hipGetLastError());
   TTK_HIP(hipStreamSynchronize(st));   // nodes is freed on return
@@ -812,7 +818,7 @@ tt_status tt_kernel_eval_dense(const tt_kernel_params* p, const void* X, int64_t
   hipStream_t st = static_cast<hipStream_t>(stream);
   Grid g;
   make_grid(p, &g);
-  KSpec ks{p->kind, p->d, p->d_theta, g.D, p->kernel_const, nullptr};
+  KSpec ks{p->kind, p->d, p->d_theta, g.D, p->kernel_const, nullptr, {p->theta_fixed[0], p->theta_fixed[1]}};
   if (p->dtype == TTK_FP32)
     eval_dense_f32(ks, static_cast<const float*>(X), nx, static_cast<const float*>(Y), ny, theta,
                    static_cast<float*>(K), ldk, st);

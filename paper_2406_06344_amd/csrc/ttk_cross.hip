@@ -656,8 +656,8 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
       cg[j] = j <= ad.lk ? sj : qj;   // A(s_i, J_q)
       ct[j] = j <= ad.lk ? qj : sj;   // A(I_q, s_i)
     }
-    const double vg = kappa_eval<d, dt, G>(ks.kind, ks.kconst, cg);
-    const double vt = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ct);
+    const double vg = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], cg);
+    const double vt = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], ct);
     const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
     sa[slot] = vg;
     sa[64 * nst + slot] = vt;
@@ -667,7 +667,7 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
     double c[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = S[tid * D + j];
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
     sAs[tid] = v;
     m = fmax(m, fabs(v));
   }
@@ -772,7 +772,7 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
     double c[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = sn[j * MAXN + (((j <= a.lk) == (bit != 0)) ? nf[j] : nq[j])];
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
     su[tid] = v;
     m = fabs(v);
   }
@@ -840,7 +840,7 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
       double c[D];
 #pragma unroll
       for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[q * D + j] : vc[j];
-      const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+      const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
       acc += v * sx[q];
       m = fmax(m, fabs(v));
     }

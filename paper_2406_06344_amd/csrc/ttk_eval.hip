@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(EB) k_eval_product(KSpec ks, Addr a, const int
     const int col = cols ? cols[jj] : jj;
     double c[D];
     addr_coords<D>(a, sn, row, col, c);
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
     out[e] = v;
     m = fmax(m, fabs(v));
   }
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(EB) k_eval_list(KSpec ks, Addr a, const int32_
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x) {
     double c[D];
     addr_coords<D>(a, sn, rows[i], cols[i], c);
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
     out[i] = v;
     m = fmax(m, fabs(v));
   }
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(EB) k_eval_segs(KSpec ks, Addr a, EvalSeg s0, 
     }
     double c[D];
     addr_coords<D>(a, sn, row, col, c);
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
     sg.out[e] = v;
     m = fmax(m, fabs(v));
   }
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(EB) k_eval_multi(KSpec ks, const I* idx, int64
     double c[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = sn[j * MAXN + (int)idx[i * D + j]];
-    out[i] = kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    out[i] = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
   }
 }
 
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(EB) k_eval_dense(KSpec ks, const T* X, int64_t
     if (dt > 1) c[d + (dt > 1 ? 1 : 0)] = th1;
 #pragma unroll
     for (int q = 0; q < d; ++q) c[d + dt + q] = (double)Y[q * ny + j];
-    K[i + j * ldk] = (T)kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+    K[i + j * ldk] = (T)kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
   }
 }
 

@@ -100,7 +100,7 @@ template <int d, int dt, bool G>
 __device__ inline double addr_eval(const KSpec& ks, const Addr& a, const double* sn, int row, int col) {
   double c[2 * d + dt];
   addr_coords<2 * d + dt>(a, sn, row, col, c);
-  return kappa_eval<d, dt, G>(ks.kind, ks.kconst, c);
+  return kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
 }
 
 template <int V>

@@ -23,6 +23,7 @@ struct KSpec {
   int d, dt, D;
   double kconst;
   const double* nodes;  // device, D x MAXN: node eta_i of dimension j at j*MAXN + i
+  double thfix[2];      // the kind's parameters when dt = 0 (non-parametric TTK)
 };
 
 // Thread-local error message behind tt_kernel_last_error().

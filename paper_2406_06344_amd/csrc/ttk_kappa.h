@@ -39,13 +39,16 @@ __device__ inline double matern_general(double r, double ell, double nu) {
 
 // kappa(x, y; theta) for the kind in tt_kernel_kind, at the coordinates
 // c = (x_1..x_d, theta_1..theta_dt, y_1..y_d).  d and dt are compile-time so
-// that c stays in registers (every index below is a constant).  The general
-// Matern kinds (Bessel integral) are compiled in only when G is set, so the
-// closed-form kinds keep a small register footprint.
+// that c stays in registers (every index below is a constant).  With dt = 0
+// a kind that has parameters takes them from tf0, tf1 (fixed theta: the
+// non-parametric TTK method).  The general Matern kinds (Bessel integral) are
+// compiled in only when G is set, so the closed-form kinds keep a small
+// register footprint.
 template <int d, int dt, bool G>
-__device__ inline double kappa_eval(int kind, double kconst, const double (&c)[2 * d + dt]) {
-  const double th0 = c[dt > 0 ? d : 0];       // meaningless when dt == 0
-  const double th1 = c[dt > 1 ? d + 1 : 0];   // meaningless when dt < 2
+__device__ inline double kappa_eval(int kind, double kconst, double tf0, double tf1,
+                                    const double (&c)[2 * d + dt]) {
+  const double th0 = dt > 0 ? c[dt > 0 ? d : 0] : tf0;
+  const double th1 = dt > 1 ? c[dt > 1 ? d + 1 : 0] : tf1;
   if (kind == TTK_TEST_POLY) {
     double dot = 0.0;
 #pragma unroll

@@ -10,12 +10,15 @@
   with the oracle computing those entries one by one from the replay's cores.
 - se_d2_fp64 (2000 + 2000 points, float64): everything against a live oracle
   run, including U M V^T on the full 2000 x 2000 block.
-- The Global-1 (200k points), batched (1M + 1M points, 4096 thetas) and
-  uneven-pair (512 pairs, 15M points, 256 thetas) workloads: properties that
-  hold at any size (orthonormal Q, Q R = [U V], PSD W, the adjoint identity of
-  the backward, batched = plain apply), since the oracle's cross for them takes
-  far longer than a test.  Their oracle parity is checked at reduced sizes in
-  test_gpu_global.py and test_gpu_batch.py.
+- matern_batched (1M + 1M points, 4096 thetas, the default benchmark):
+  against the stored free-running oracle (decisions up to the first tie,
+  sampled TT entries, U M V^T, apply, dX and dtheta on sampled rows), the
+  error against dense K, the adjoint identity and batched = plain apply.
+- The Global-1 (200k points) and uneven-pair (512 pairs, 15M points, 256
+  thetas) workloads: properties that hold at any size (orthonormal Q,
+  Q R = [U V], PSD W, the adjoint identity of the backward), since the
+  oracle's cross for them takes far longer than a test.  Their oracle parity
+  is checked at reduced sizes in test_gpu_global.py and test_gpu_batch.py.
 """
 import os
 import sys
@@ -224,35 +227,125 @@ def test_global_workload_full_size_properties():
             torch.linalg.eigvalsh(W[b]).abs().max().item()
 
 
-def test_batched_workload_full_size_properties():
+def test_batched_workload_full_size_matches_oracle():
+    """The 1M + 1M point, 4096-theta workload (Matern in (l, nu)) in bench.py's
+    launch configuration, against the free-running oracle's offline stage
+    stored in tests/golden (written by make_oracle_offline.py from oracle/
+    alone; the oracle's cross for it takes about 25 minutes of CPU):
+    identical decisions up to the first one that is a tie within rounding
+    (R6), then both TTs agree at sampled grid entries to the approximation
+    level, and U M V^T, y, dX and dtheta agree with the oracle's S H T^T at
+    sampled rows.  Also: converged build, the error against dense K (64
+    thetas, 4000 x 4000 subsample) <= 1e-5, the adjoint identity and batched
+    = plain apply."""
     torch = _torch()
     import paper_2406_06344_amd as pkg
     w = synth.WORKLOADS["matern_batched"]
     say(f"[full] {w.name}: {w.n_src} + {w.n_tgt} points, {w.n_theta} thetas")
+    g = np.load(os.path.join(GOLDEN, "matern_batched_oracle.npz"))
     X, Y = synth.points(w, seed=0)
     th = synth.thetas(w, seed=1)
     B = th.shape[0]
+    d, dt = w.d, w.d_theta
     kern = pkg.TTKernel.build_offline(torch.tensor(X, dtype=torch.float32), torch.tensor(Y, dtype=torch.float32),
                                       kind=w.kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=w.box_theta,
                                       n_spatial=w.n_spatial, n_param=w.n_param, tol=w.tol, dtype=torch.float32,
-                                      seed=0)
+                                      seed=0, max_sweeps=w.extra["max_sweeps"])
+    inf = kern.info()
+    say(f"  status {kern.status} ranks {inf['ranks']} cross {inf['cross_ranks']} sweeps {inf['sweeps']} "
+        f"error {inf['sampled_error']:.3e}; oracle: ranks {list(g['ranks'])} cross {list(g['cross_ranks'])} "
+        f"sweeps {int(g['sweeps'])} error {float(g['error']):.3e}")
+    assert kern.status == 0 and bool(g["converged"])
+    # 1. decisions against the free-running oracle
+    L, R, log = kern.cross_record()
+    lp, lm = g["log_pivot"], g["log_margin"]
+    n_same = 0
+    for a, r in zip(lp, log):
+        if (int(a[0]), int(a[1]), int(a[2])) != (r["pivot_row"], r["pivot_col"], int(r["added"])):
+            say(f"  first differing decision {n_same} (sweep {r['sweep']}, k {r['k']}): oracle margin "
+                f"{lm[n_same]:.2e}, gpu margins {r['sample_margin']:.2e} / {r['search_margin']:.2e}")
+            assert min(lm[n_same], r["sample_margin"], r["search_margin"]) < 1e-9, n_same
+            break
+        n_same += 1
+    say(f"  decisions identical to the free-running oracle: {n_same} of {len(log)} (oracle {len(lp)})")
+    if n_same == len(lp) == len(log):
+        assert inf["cross_ranks"] == list(g["cross_ranks"]) and inf["ranks"] == list(g["ranks"])
+    # 2. the two rounded TTs approximate the same grid tensor: sampled entries
+    P = okernels.Problem(w.kind, w.d, w.box_s, w.box_t, w.box_theta, w.n_spatial, w.n_param)
+    Go = [g[f"core{k}"] for k in range(P.D)]
+    Gg = kern.cores()
+    rng = np.random.default_rng(21)
+    idx = np.stack([rng.integers(0, nj, 4000) for nj in P.n], axis=1)
+    exact = P.entries(idx)
+    vo, vg = ott.evaluate(Go, idx), ott.evaluate(Gg, idx)
+    eo = np.abs(vo - exact).max() / np.abs(exact).max()
+    eg = np.abs(vg - exact).max() / np.abs(exact).max()
+    say(f"  sampled grid entries, max error / max entry: gpu {eg:.2e} oracle {eo:.2e} (tol {w.tol:g})")
+    assert eg <= 10 * w.tol and eo <= 10 * w.tol
+    # 3. U M V^T against the oracle's S H T^T at sampled rows, for a few thetas
+    si = np.sort(rng.choice(w.n_src, 1500, replace=False))
+    ti = np.sort(rng.choice(w.n_tgt, 1500, replace=False))
+    S = opttk.phase3_source(opttk.factor_values(X[si], P.box_s, w.n_spatial), Go[:d])
+    T = opttk.phase3_target(opttk.factor_values(Y[ti], P.box_t, w.n_spatial), Go[d + dt:])
+    U, V = kern.factors()
+    sel = [0, 1, 17, 1234, 4095, int(np.argmin(th[:, 0]))]
+    M = kern.online_core(torch.tensor(th[sel], dtype=torch.float32, device="cuda"))
+    worst = 0.0
+    for j, b in enumerate(sel):
+        Ko = S @ opttk.online_H(Go[d:d + dt], th[b], P.box_theta, w.n_param) @ T.T
+        Kg = U[si].double().cpu().numpy() @ M[j].double().cpu().numpy() @ V[ti].double().cpu().numpy().T
+        worst = max(worst, rel(Kg, Ko))
+    say(f"  |U M V^T - S H T^T| / |S H T^T| on 1500 x 1500 sampled rows, worst of {len(sel)} thetas: {worst:.2e}")
+    assert worst <= 1e-5
+    # 4. error against dense K (the accuracy bar of the workload)
+    si2 = np.sort(np.random.default_rng(11).choice(w.n_src, 4000, replace=False))
+    ti2 = np.sort(np.random.default_rng(12).choice(w.n_tgt, 4000, replace=False))
+    cols = np.linspace(0, B - 1, 64).astype(int)
+    M64 = kern.online_core(torch.tensor(th[cols], dtype=torch.float32, device="cuda"))
+    Us, Vs = U[si2].double(), V[ti2].double()
+    errs = []
+    for j, b in enumerate(cols):
+        K = pkg.eval_dense(torch.tensor(X[si2]), torch.tensor(Y[ti2]), th[b], w.kind, w.d, dtype=torch.float64)
+        errs.append((torch.linalg.norm(K - Us @ M64[j].double() @ Vs.t()) / torch.linalg.norm(K)).item())
+    say(f"  error against dense K (64 thetas, 4000 x 4000): max {max(errs):.2e}, median {np.median(errs):.2e}")
+    assert max(errs) <= 1e-5
+    # 5. apply and backward at full size: adjoint identity, batched = plain, and
+    #    the oracle's y, dX, dtheta for inputs supported on the sampled rows
     gen = torch.Generator(device="cuda").manual_seed(2)
     xb = torch.randn((B, w.n_tgt), generator=gen, device="cuda")
     gb = torch.randn((B, w.n_src), generator=gen, device="cuda")
     thd = torch.tensor(th, dtype=torch.float32, device="cuda")
     Yo, Wv = kern.apply(thd, xb, save_w=True)
     dX, dth = kern.apply_backward(thd, gb, W=Wv)
-    # adjoint identity per theta: <dX_b, x_b> = <g_b, y_b>
     adj = adjoint_gap(dX, xb, gb, Yo)
     say(f"  adjoint identity: max |<dX,x> - <g,y>| / (|g||y|) = {adj:.2e}")
     assert adj <= 1e-5
-    # the batched apply equals the plain per-theta apply (other kernels) on a few thetas
-    sel = [0, 1, 2047, 4095]
-    Yp = kern.apply_plain(thd[sel], xb[sel])
-    e = (torch.linalg.norm(Yp.double() - Yo[sel].double()) / torch.linalg.norm(Yo[sel].double())).item()
+    Yp = kern.apply_plain(thd[[0, 1, 2047, 4095]], xb[[0, 1, 2047, 4095]])
+    e = (torch.linalg.norm(Yp.double() - Yo[[0, 1, 2047, 4095]].double()) /
+         torch.linalg.norm(Yo[[0, 1, 2047, 4095]].double())).item()
     say(f"  batched vs plain apply: {e:.2e}")
-    assert e <= 1e-5
-    assert torch.isfinite(dth).all()
+    assert e <= 1e-5 and torch.isfinite(dth).all()
+    nb = 8
+    xs = synth.rhs(1500, nb, seed=2)
+    gs = synth.rhs(1500, nb, seed=3)
+    xr = torch.zeros((nb, w.n_tgt), device="cuda")
+    gr = torch.zeros((nb, w.n_src), device="cuda")
+    xr[:, torch.tensor(ti)] = torch.tensor(xs.T, dtype=torch.float32, device="cuda")
+    gr[:, torch.tensor(si)] = torch.tensor(gs.T, dtype=torch.float32, device="cuda")
+    thb = thd[torch.tensor(sel[:nb] + [3, 5], device="cuda")][:nb]
+    tho = thb.double().cpu().numpy()
+    Yr, Wr = kern.apply(thb, xr, save_w=True)
+    dXr, dthr = kern.apply_backward(thb, gr, W=Wr)
+    Hs = [opttk.online_H(Go[d:d + dt], t, P.box_theta, w.n_param) for t in tho]
+    dHs = [opttk.online_dH(Go[d:d + dt], t, P.box_theta, w.n_param) for t in tho]
+    y_o = np.stack([S @ (Hs[b] @ (T.T @ xs[:, b])) for b in range(nb)])
+    dx_o = np.stack([T @ (Hs[b].T @ (S.T @ gs[:, b])) for b in range(nb)])
+    dth_o = np.array([[(S.T @ gs[:, b]) @ dHs[b][j] @ (T.T @ xs[:, b]) for j in range(dt)] for b in range(nb)])
+    ey = rel(Yr[:, torch.tensor(si)].double().cpu().numpy(), y_o)
+    ex = rel(dXr[:, torch.tensor(ti)].double().cpu().numpy(), dx_o)
+    et = rel(dthr.double().cpu().numpy(), dth_o)
+    say(f"  apply {ey:.2e} dX {ex:.2e} dtheta {et:.2e} (against the oracle's cores on the sampled rows)")
+    assert ey <= 1e-5 and ex <= 1e-5 and et <= 1e-5
 
 
 def test_uneven_pairs_full_size_properties():

@@ -331,3 +331,68 @@ def test_coefficient_cores_match_oracle_dct(name, dtype):
     v_dev = obasis.interpolant_coefficient_form(A_dev, boxes, pts)
     v_ref = obasis.interpolant_lagrange_form(M_nodal, boxes, pts)
     assert np.abs(v_dev - v_ref).max() <= (1e-12 if dtype == "f64" else 2e-6) * np.abs(v_ref).max()
+
+
+# ------------------------------------------------------------- TTK (d_theta = 0)
+@pytest.mark.parametrize("kind,d,theta_fixed", [("laplace2d", 2, None), ("biharmonic", 3, None),
+                                                ("thinplate", 2, None), ("laplace3d", 1, None),
+                                                ("exp", 3, [1.0]), ("matern", 2, [1.0, 1.5]),
+                                                ("mq", 2, [1.0]), ("tps", 3, [1.0])])
+def test_ttk_entries_match_oracle(kind, d, theta_fixed):
+    """Entries of the non-parametric grid tensors (Section 4.1: the kernels of
+    Table 1 without parameters, and those with parameters held fixed)."""
+    torch = _torch()
+    pkg = _lib()
+    say("ttk entries", kind, theta_fixed)
+    bs = [[0, 1]] * d
+    bt = [[2, 3]] + [[0, 1]] * (d - 1)
+    n = 9
+    P = okernels.Problem(kind, d, bs, bt, [], n, theta_fixed=theta_fixed)
+    rng = np.random.default_rng(13)
+    idx = np.stack([rng.integers(0, n, 3000) for _ in range(P.D)], axis=1)
+    ref = P.entries(idx)
+    got = pkg.eval_entries(torch.tensor(idx, dtype=torch.int32), kind, d, bs, bt, [], n_spatial=n,
+                           theta_fixed=theta_fixed).cpu().numpy()
+    # -log r and r^2 log r (and u log u) cross zero at r = 1 inside these boxes:
+    # compare against the largest entry there, entrywise elsewhere
+    if kind in ("laplace2d", "thinplate", "tps"):
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    else:
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+    say("  max rel err", err)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("kind,theta_fixed,n,tol", [("laplace3d", None, 8, 1e-9), ("exp", [1.0], 8, 1e-9),
+                                                    ("matern", [1.0, 2.5], 8, 1e-9), ("se", [1.0], 10, 1e-9)])
+def test_ttk_full_build_matches_oracle(kind, theta_fixed, n, tol):
+    """TTK, the d_theta = 0 case of the method (H = I): the whole device build
+    against the free-running oracle (decisions, index sets, ranks), the low-rank
+    form U V^T and the apply y = U V^T x, float64."""
+    torch = _torch()
+    pkg = _lib()
+    say("ttk build", kind, theta_fixed)
+    d = 2
+    bs, bt = [[0, 1], [0, 1]], [[2, 3], [0, 1]]
+    P = okernels.Problem(kind, d, bs, bt, [], n, theta_fixed=theta_fixed)
+    rng = np.random.default_rng(14)
+    X = rng.uniform(0, 1, (401, d))
+    Y = rng.uniform([2, 0], [3, 1], (377, d))
+    out = odriver.offline(P, X, Y, tol, seed=0)
+    kern = pkg.TTKernel.build_offline(torch.tensor(X), torch.tensor(Y), kind, d, bs, bt, [], n_spatial=n,
+                                      tol=tol, dtype=torch.float64, seed=0, theta_fixed=theta_fixed)
+    inf = kern.info()
+    L, R, log = kern.cross_record()
+    info, cross_cores, n_same = _replay_and_compare(P, tol, L, R, log, 0)
+    assert inf["cross_ranks"] == out["info"]["ranks"] and inf["ranks"] == out["ranks"]
+    assert kern.d_theta == 0 and kern.r_s == kern.r_t
+    U, V = kern.factors()
+    U, V = U.cpu().numpy(), V.cpu().numpy()
+    e = rel(U @ V.T, out["S"] @ out["T"].T)
+    x = rng.standard_normal((377, 3))
+    y = kern.apply(None, torch.tensor(x.T.copy())).cpu().numpy().T
+    ey = rel(y, out["S"] @ (out["T"].T @ x))
+    K = odense.dense_K(kind, X, Y, theta_fixed if theta_fixed is not None else [])
+    say(f"  ranks {inf['ranks']}, |U V^T - S T^T| {e:.2e}, apply {ey:.2e}, "
+        f"error vs dense K: gpu {odense.rel_error(K, U @ V.T):.2e} (2-norm {odense.rel_error(K, U @ V.T, 2):.2e})")
+    assert e <= 1e-10 and ey <= 1e-10

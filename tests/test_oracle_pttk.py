@@ -273,3 +273,22 @@ def test_dense_brute_force_small_se():
         H = pttk.online_H(out["param"], [th], P.box_theta, 12)
         K = dense.dense_K("se", X, Y, [th])
         assert dense.rel_error(K, out["S"] @ H @ out["T"].T) < 1e-4
+
+
+def test_ttk_at_fixed_theta_is_the_parametric_tensor_at_a_node():
+    """Non-parametric TTK (Section 4.1) for a kernel with a parameter: the grid
+    tensor at theta fixed to a parameter node is the parametric grid tensor's
+    slice at that node, and S T^T interpolates K at fixed theta (H = I)."""
+    Pp = kernels.Problem("exp", 2, [[0, 1]] * 2, [[2, 3], [0, 1]], [[0.5, 2.0]], 6)
+    Mp = Pp.full_tensor()
+    j = 4
+    Pf = kernels.Problem("exp", 2, [[0, 1]] * 2, [[2, 3], [0, 1]], [], 6, theta_fixed=[Pp.nodes[2][j]])
+    assert Pf.dt == 0 and Pf.D == 4
+    assert np.array_equal(Pf.full_tensor(), Mp[:, :, j, :, :])
+    rng = np.random.default_rng(2)
+    X = rng.uniform(0, 1, (30, 2))
+    Y = rng.uniform([2, 0], [3, 1], (25, 2))
+    out = driver.offline(Pf, X, Y, 1e-10, seed=0)
+    assert out["param"] == []
+    K = dense.dense_K("exp", X, Y, [Pp.nodes[2][j]])
+    assert dense.rel_error(K, out["S"] @ out["T"].T) < 1e-5       # interpolation level at n = 6
