@@ -17,7 +17,7 @@ Prints one JSON line.  value = whole-step offline U/V rows per second,
 apply + gradient against the plain per-theta apply, kernel evaluations,
 accuracy against dense float64 K and the roofline of the projection kernel
 (timed with HIP events on the stream it runs on).  Other workloads:
---workload matern32_d3 | se_d2_fp64 | matern_global | uneven_pairs.
+--workload matern32_d3 | se_d2_fp64 | matern_global | uneven_pairs | ttk_e1.
 """
 import argparse
 import json
@@ -335,6 +335,62 @@ def bench_batched(args, torch, pkg):
     return res
 
 
+def bench_ttk_e1(args, torch, pkg):
+    """The non-parametric TTK experiment (Section 4.1): every kernel of Table 1
+    at fixed l = 1 on 10^4 + 10^4 points in [0,1]^3 and [2,3]^3, n = 27,
+    tol 1e-9, float64.  Per kernel: the compression rank, the offline build
+    time, the 2-norm relative error of U V^T against dense K (power
+    iteration) and, for context, the error of the truncated SVD at the same
+    rank (sigma_{r+1} / sigma_1 from a randomized range finder)."""
+    w = synth.WORKLOADS["ttk_e1"]
+    X, Y = synth.points(w, seed=0)
+    Xd, Yd = torch.tensor(X, device="cuda"), torch.tensor(Y, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    rows, total_ms = [], 0.0
+    for kind, tf in w.extra["kernels"]:
+        kw = dict(kind=kind, d=w.d, box_s=w.box_s, box_t=w.box_t, box_theta=[], n_spatial=w.n_spatial, tol=w.tol,
+                  dtype=torch.float64, seed=0, theta_fixed=tf)
+        for _ in range(args.warmup):
+            pkg.TTKernel.build_offline(Xd, Yd, **kw)
+        ms = time_wall(lambda: pkg.TTKernel.build_offline(Xd, Yd, **kw), max(args.steps, 1), torch)
+        kern = pkg.TTKernel.build_offline(Xd, Yd, **kw)
+        total_ms += ms
+        inf = kern.info()
+        U, V = kern.factors()
+        K = pkg.eval_dense(Xd, Yd, tf if tf is not None else [], kind, w.d, dtype=torch.float64)
+        E = K - U @ V.t()
+
+        def norm2(A, its=40):
+            v = torch.randn((A.shape[1],), generator=gen, device="cuda", dtype=torch.float64)
+            s = 0.0
+            for _ in range(its):
+                u = A @ v
+                v = A.t() @ u
+                s = torch.linalg.norm(v).sqrt().item()
+                v = v / torch.linalg.norm(v)
+            return s
+        r = kern.r_s
+        Om = torch.randn((K.shape[1], r + 20), generator=gen, device="cuda", dtype=torch.float64)
+        Q, _ = torch.linalg.qr(K @ Om)
+        for _ in range(2):
+            Q, _ = torch.linalg.qr(K @ (K.t() @ Q))
+        sv = torch.linalg.svdvals(Q.t() @ K)
+        rows.append({"kernel": kind, "theta": tf, "rank": r, "ranks": inf["ranks"], "build_ms": round(ms, 2),
+                     "tt_error_2norm": float(f"{norm2(E) / norm2(K):.3e}"),
+                     "svd_error_2norm_same_rank": float(f"{(sv[r] / sv[0]).item():.3e}"),
+                     "kernel_evals": inf["kernel_evals"], "status": kern.status})
+        print(f"{kind}: rank {r} build {ms:.1f} ms error {rows[-1]['tt_error_2norm']:.2e}", file=sys.stderr,
+              flush=True)
+        del K, E
+    n_k = len(rows)
+    res = base_result(w, args, n_k * (w.n_src + w.n_tgt) / (total_ms / 1000.0), "rows/s", total_ms / n_k, 1,
+                      {"variant": "TTK (d_theta = 0)", "kernels": n_k})
+    res["note"] = ("value: offline U/V rows per second, (N_s + N_t) per kernel over the mean build time of the "
+                   f"{n_k} kernels; ms_per_step is that mean")
+    res["per_kernel"] = rows
+    return res
+
+
 def bench_pairs(args, torch, pkg):
     """Uneven batch: 512 box pairs of an FMM-like interaction list, 256 thetas."""
     base = synth.WORKLOADS["matern_batched"]
@@ -404,7 +460,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="matern_batched",
-                    help="matern_batched (default), matern32_d3, se_d2_fp64, matern_global, uneven_pairs")
+                    help="matern_batched (default), matern32_d3, se_d2_fp64, matern_global, uneven_pairs, ttk_e1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--steps-only", action="store_true", help="time the steps only (profiling runs)")
     ap.add_argument("--cpu-points", type=int, default=None,
@@ -435,7 +491,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "dispatches": 3}), flush=True)
         return
-    other = {"matern_global": bench_global, "matern_batched": bench_batched, "uneven_pairs": bench_pairs}
+    other = {"matern_global": bench_global, "matern_batched": bench_batched, "uneven_pairs": bench_pairs,
+             "ttk_e1": bench_ttk_e1}
     if args.workload in other:
         print(json.dumps(other[args.workload](args, torch, pkg)), flush=True)
         return

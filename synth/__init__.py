@@ -59,6 +59,14 @@ WORKLOADS = {
     "matern_batched": Workload("matern_batched", "matern", 3, UNIT3, [[2, 3], [0, 1], [0, 1]],
                                [[0.5, 2.0], [0.5, 2.5]], 16, 16, 1_000_000, 1_000_000, 7e-7, 4096, False,
                                extra={"max_sweeps": 400}),
+    # The non-parametric experiment of Section 4.1 (TTK, d_theta = 0): every
+    # kernel of Table 1 with l = 1 (and Matern at nu = 3/2, 5/2), separated unit
+    # cubes, 27 nodes per dimension, 10^4 points per side, tol 1e-9, float64.
+    "ttk_e1": Workload("ttk_e1", "exp", 3, UNIT3, [[2, 3], [2, 3], [2, 3]], [], 27, 27, 10_000, 10_000, 1e-9,
+                       1, True, extra={"kernels": [("exp", [1.0]), ("thinplate", None), ("biharmonic", None),
+                                                   ("mq", [1.0]), ("tps", [1.0]), ("laplace2d", None),
+                                                   ("laplace3d", None), ("matern32", [1.0]),
+                                                   ("matern52", [1.0]), ("se", [1.0])]}),
 }
 
 
