@@ -84,6 +84,30 @@ struct StepDesc {
   int rows, cols, ns, bit;
 };
 
+// The fibre cache.  Every value a step reads besides its own samples and
+// its searched fibre is an entry of a fibre core
+//   F_k(a, i, b) = X(I^{<=k-1}[a], i, I^{>k}[b]),   a < r_{k-1}, i < n_k, b < r_k:
+// A(s, J_q) of super-core k is F_k(s, i_k, q) and A(I_q, s) is
+// F_{k+1}(q, i_{k+1}, t) for a position s = (row s + i_k r_{k-1}, column
+// i_{k+1} + t n_{k+1}); the intersection matrix P_k is F_k at its pivot rows,
+// and F_k is the fibre of the interpolation formula.  The index sets only
+// grow at their ends, so F_k only gains rows (when step k - 1 adds a pivot:
+// the row of super-core k - 1 through that pivot) and columns (when step k
+// adds one: the column of super-core k through it).  Each F_k is kept on the
+// device twice, with capacity MAXR in both ranks:
+//   FL_k[(i MAXR + a) MAXR + b]   (rows of the unfolding contiguous in b), and
+//   FR_k[(i MAXR + b) MAXR + a]   (contiguous in a),
+// so that the gathers of either side of a super-core read contiguous runs.
+// A step writes the fibre it searched into the slot a pivot would occupy
+// (row r_k of F_{k+1} or column r_k of F_k) before it knows whether the pivot
+// is added: the slot lies past every extent read until an addition makes it
+// part of the core.  The entries are the same numbers a fresh evaluation
+// gives, so the cache changes no decision, only the count of evaluations
+// (the O(D n r^2) of the interpolation itself, plus the samples and the
+// searched fibres).
+__device__ inline int64_t fibre_left_row(int a, int i) { return ((int64_t)i * MAXR + a) * MAXR; }
+__device__ inline int64_t fibre_right_col(int i, int b) { return ((int64_t)i * MAXR + b) * MAXR; }
+
 __device__ inline double wsum(double v) { return wave64_sum(v); }
 
 // Largest |value| over up to four buffers, combined with *base (if non-NULL).
@@ -567,44 +591,37 @@ __device__ inline double slots_max(const double* sl) {
 
 // Sample stage: residuals R_i = A(s_i, J) P^{-1} A(I, s_i) - A(s_i) of the
 // sampled entries, written as the row-wise dot product of G = A(s, J) W and
-// T = (Li A(I, s))^T, both formed with FP64 MFMA on 16-row tiles that hold
-// SPB samples
-// (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16], D row
-// l / 16 + 4 v, column l % 16 in lane l, slot v).  The block evaluates its
-// samples' entries A(s_i, J_q), A(I_q, s_i) and A(s_i) itself, straight into
-// LDS in MFMA lane order, and folds their max |.| into the sample-stage
-// slots.  The coordinates are staged in LDS first: per q the row half of
-// I_q and the column half of J_q in one D-vector (the halves occupy
-// disjoint positions), per sample the coordinates of the sample itself, so
-// every entry combines two LDS vectors.  Each wave owns one 16-column tile
-// of G and T at a time; the B operands of its first tile (rows of W^T and
-// Li) are loaded into registers before the entries are evaluated, which
-// hides their latency behind the evaluation.
+// T = (Li A(I, s))^T, both formed with FP64 MFMA on 16-row tiles of 16
+// samples (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16],
+// D row l / 16 + 4 v, column l % 16 in lane l, slot v).  A(s_i, J_q) and
+// A(I_q, s_i) are entries of the fibre cores F_k and F_{k+1} (the fibre
+// cache, see FibreCache), gathered straight into LDS in MFMA lane order; only
+// A(s_i) itself is evaluated.  The max |.| of all of them folds into the
+// sample-stage slots.  Each wave owns one 16-column tile of G and T at a
+// time; the B operands of its first tile (rows of W^T and Li) are loaded into
+// registers before the gathers.
 constexpr int SW = 8;    // waves per block
-constexpr int SPB = 8;   // samples per block (MFMA rows SPB..15 are zero): twice the blocks of a
-                         // full 16-row tile, so the entry evaluations spread over more CUs
+constexpr int SPB = 16;  // samples per block: one full MFMA row tile
 constexpr int SB = 32;   // MFMA steps of B operands held in registers (r <= 128: one batch)
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDesc* desc, const int32_t* sel, int r,
-                                                          const double* Li, const double* W, double* R,
-                                                          double* slots) {
+                                                          const double* Li, const double* W, const double* FLk,
+                                                          const double* FRk1, double* R, double* slots) {
   constexpr int D = 2 * d + dt;
   const StepDesc& sd = desc[*sel];
   const Addr ad = sd.a;
   const int32_t* srow = sd.srow;
   const int32_t* scol = sd.scol;
-  const int32_t* I = sd.I;
-  const int32_t* J = sd.J;
   const int ns = sd.ns;
-  extern __shared__ double sa[];   // A operands (2 x 64 x nst), then IJ (r x D)
+  extern __shared__ double sa[];   // A operands (2 x 64 x nst)
   __shared__ double red[SW][16], sn[D * MAXN], sAs[16], redm[SW], S[SPB * D];
+  __shared__ int64_t offL[SPB], offR[SPB];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int i0 = blockIdx.x * SPB;
   const int nv = min(SPB, ns - i0);   // samples of this block (none past the variant's extent)
   const int nst = (r + 3) / 4;
   const int ntile = (r + 15) / 16;
-  double* IJ = sa + 2 * 64 * nst;
   const double* Wt = W + FT;
   double bg[SB], bt[SB];
   {
@@ -618,23 +635,22 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
     }
   }
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
-  for (int q = tid; q < r; q += SW * 64) {
-    double c[D];
-    addr_row_part<D>(ad, sn, I[q], c);
-    addr_col_part<D>(ad, sn, J[q], c);
-#pragma unroll
-    for (int j = 0; j < D; ++j) IJ[q * D + j] = c[j];
-  }
   if (tid < SPB) {
     double c[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = 0.0;
+    int64_t oL = 0, oR = 0;
     if (tid < nv) {
-      addr_row_part<D>(ad, sn, srow[i0 + tid], c);
-      addr_col_part<D>(ad, sn, scol[i0 + tid], c);
+      const int row = srow[i0 + tid], col = scol[i0 + tid];
+      addr_row_part<D>(ad, sn, row, c);
+      addr_col_part<D>(ad, sn, col, c);
+      oL = fibre_left_row(row % ad.rl, row / ad.rl);
+      oR = fibre_right_col(col % ad.nm1, col / ad.nm1);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j) S[tid * D + j] = c[j];
+    offL[tid] = oL;
+    offR[tid] = oR;
   }
   for (int e = tid; e < 64 * nst; e += SW * 64) {   // operand rows without a sample or a q
     const int ii = e & 15, q = e >> 4;
@@ -646,18 +662,10 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
   }
   __syncthreads();
   double m = 0.0;
-  for (int e = tid; e < SPB * r; e += SW * 64) {
-    const int ii = e & (SPB - 1), q = e / SPB;
-    if (ii >= nv) continue;
-    double cg[D], ct[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const double sj = S[ii * D + j], qj = IJ[q * D + j];
-      cg[j] = j <= ad.lk ? sj : qj;   // A(s_i, J_q)
-      ct[j] = j <= ad.lk ? qj : sj;   // A(I_q, s_i)
-    }
-    const double vg = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], cg);
-    const double vt = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], ct);
+  for (int e = tid; e < nv * r; e += SW * 64) {   // q fastest: contiguous cache rows
+    const int ii = e / r, q = e - ii * r;
+    const double vg = FLk[offL[ii] + q];    // A(s_i, J_q) = F_k(s, i_k, q)
+    const double vt = FRk1[offR[ii] + q];   // A(I_q, s_i) = F_{k+1}(q, i_{k+1}, t)
     const int slot = (q >> 2) * 64 + (q & 3) * 16 + ii;
     sa[slot] = vg;
     sa[64 * nst + slot] = vt;
@@ -720,59 +728,36 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
   }
 }
 
-// dynamic LDS of k_sample_resid for rank r and D coordinates per entry
-inline size_t sample_lds(int r, int D) {
-  return ((size_t)2 * 64 * ((r + 3) / 4) + (size_t)r * D) * sizeof(double);
-}
+// dynamic LDS of k_sample_resid for rank r
+inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
 
 // Sample-stage selection over the residuals of k_sample_resid (one block),
 // then the search stage's solve: u = A(l, J) for a row search (bit 1) or
-// u = A(I, t) for a column search (bit 0) is evaluated here and
+// u = A(I, t) for a column search (bit 0), read from the fibre cache, and
 // x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search
 // (P^{-1} applied to one vector, through the rows of the factors or of their
-// transposes).  |u| folds into the search-stage scale.  The loads that do
-// not depend on the selection (node table, the node indices of J_q or I_q)
-// are issued before it.
+// transposes).  |u| folds into the search-stage scale.
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc* desc, const int32_t* sel,
                                                         const double* R, const double* luamax, StepRes* res, int r,
-                                                        const double* Li, const double* W, double* x) {
-  constexpr int D = 2 * d + dt;
+                                                        const double* Li, const double* W, const double* FLk,
+                                                        const double* FRk1, double* x) {
   const StepDesc& sdv = desc[*sel];
   const Addr a = sdv.a;
   const int32_t* srow = sdv.srow;
   const int32_t* scol = sdv.scol;
   const int ns = sdv.ns, cols = sdv.cols, bit = sdv.bit;
-  __shared__ double sn[D * MAXN], su[MAXR], sy[MAXR], scr[1024], red[16];
+  __shared__ double su[MAXR], sy[MAXR], scr[1024], red[16];
   const int tid = threadIdx.x;
-  const double ndv = tid < D * MAXN ? ks.nodes[tid] : 0.0;
-  int nq[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) nq[j] = 0;
-  if (tid < r) {
-    if (bit) addr_col_nodes<D>(a, sdv.J[tid], nq);
-    else addr_row_nodes<D>(a, sdv.I[tid], nq);
-  }
   int key;
   double val;
   select_block<1024, (MAXR * MAXN + 1023) / 1024>(R, ns, srow, scol, cols, 0,
                                                   fmax(slots_max(res->s_slot), *luamax), res, &key, &val);
   const int l = key / cols, t = key - l * cols;
-  if (tid < D * MAXN) sn[tid] = ndv;
-  int nf[D];   // the sample's own half: the row of l (bit 1) or the column of t (bit 0)
-#pragma unroll
-  for (int j = 0; j < D; ++j) nf[j] = 0;
-  if (tid < r) {
-    if (bit) addr_row_nodes<D>(a, l, nf);
-    else addr_col_nodes<D>(a, t, nf);
-  }
-  __syncthreads();
   double m = 0.0;
   if (tid < r) {
-    double c[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) c[j] = sn[j * MAXN + (((j <= a.lk) == (bit != 0)) ? nf[j] : nq[j])];
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
+    const double v = bit ? FLk[fibre_left_row(l % a.rl, l / a.rl) + tid]      // A(l, J_q)
+                         : FRk1[fibre_right_col(t % a.nm1, t / a.nm1) + tid];  // A(I_q, t)
     su[tid] = v;
     m = fabs(v);
   }
@@ -797,19 +782,21 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
 // Search stage: the residual over the searched fibre,
 //   R_i = sum_q A(I_q, i) x_q - A(l, i)   (row search, bit 1, i < cols), or
 //   R_i = sum_q A(i, J_q) x_q - A(i, t)   (column search, bit 0, i < rows),
-// with (l, t) the chosen sample and x = P^{-1} u from k_sample_select.  The
-// entries are evaluated where they are used and never stored: sixteen
-// fibre entries per block, one 16-lane row per entry with the q terms
-// strided over its lanes and summed by DPP.  The fixed side's coordinates
-// (rows I_q and l, or columns J_q and t) are staged in LDS once per block.
-// The entries' max |.| folds into the search-stage slots.
+// with (l, t) the chosen sample and x = P^{-1} u from k_sample_select.
+// A(I_q, i) = F_{k+1}(q, i_{k+1}, t_i) and A(i, J_q) = F_k(s_i, i_k, q) come
+// from the fibre cache; the fibre entries A(l, i) or A(i, t) are evaluated
+// and stored in the slot the pivot would occupy: row r of F_{k+1} (bit 1) or
+// column r of F_k (bit 0), when r < MAXR.  Sixteen fibre entries per block,
+// one 16-lane row per entry with the q terms strided over its lanes (the
+// fibre entry as term q = r, weight -1) and summed by DPP.  Every value's
+// max |.| folds into the search-stage slots.
 constexpr int QE = 16;   // fibre entries per block
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, const int32_t* sel,
-                                                const StepRes* res, const double* x, int r, double* R,
-                                                double* slots) {
+                                                const StepRes* res, const double* x, int r, double* FLk, double* FRk,
+                                                double* FLk1, double* FRk1, double* R, double* slots) {
   constexpr int D = 2 * d + dt;
-  __shared__ double sn[D * MAXN], sx[MAXR + 1], fc[(MAXR + 1) * D], redm[4];
+  __shared__ double sn[D * MAXN], sx[MAXR + 1], fc[D], redm[4];
   const StepDesc& sd = desc[*sel];
   const Addr a = sd.a;
   const int bit = sd.bit;
@@ -817,30 +804,47 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
   const int tid = threadIdx.x;
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
   const int l = res->l, t = res->t;
-  for (int q = tid; q <= r; q += 256) {
+  if (tid == 0) {   // the fixed half of the fibre: the row of l or the column of t
     double c[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) c[j] = 0.0;
-    if (bit) addr_row_part<D>(a, sn, q < r ? sd.I[q] : l, c);
-    else addr_col_part<D>(a, sn, q < r ? sd.J[q] : t, c);
+    if (bit) addr_row_part<D>(a, sn, l, c);
+    else addr_col_part<D>(a, sn, t, c);
 #pragma unroll
-    for (int j = 0; j < D; ++j) fc[q * D + j] = c[j];
-    sx[q] = q < r ? x[q] : -1.0;   // the fibre's own entry enters with weight -1
+    for (int j = 0; j < D; ++j) fc[j] = c[j];
   }
+  for (int q = tid; q <= r; q += 256) sx[q] = q < r ? x[q] : -1.0;   // the fibre's own entry enters with weight -1
   __syncthreads();
   const int i = blockIdx.x * QE + (tid >> 4), lj = tid & 15;
   double acc = 0.0, m = 0.0;
   if (i < n) {
-    double vc[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) vc[j] = 0.0;
-    if (bit) addr_col_part<D>(a, sn, i, vc);
-    else addr_row_part<D>(a, sn, i, vc);
+    // the entry's position in the cache: column (i_{k+1}, t_i) of F_{k+1}
+    // (bit 1) or row (s_i, i_k) of F_k (bit 0)
+    const int ia = bit ? i % a.nm1 : i % a.rl, ib = bit ? i / a.nm1 : i / a.rl;
+    const double* crow = bit ? FRk1 + fibre_right_col(ia, ib) : FLk + fibre_left_row(ia, ib);
     for (int q = lj; q <= r; q += 16) {
-      double c[D];
+      double v;
+      if (q < r) {
+        v = crow[q];
+      } else {
+        double c[D], vc[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[q * D + j] : vc[j];
-      const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
+        for (int j = 0; j < D; ++j) vc[j] = 0.0;
+        if (bit) addr_col_part<D>(a, sn, i, vc);
+        else addr_row_part<D>(a, sn, i, vc);
+#pragma unroll
+        for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[j] : vc[j];
+        v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
+        if (r < MAXR) {
+          if (bit) {   // row r of F_{k+1}: F_{k+1}(r, i_{k+1}, t_i)
+            FLk1[fibre_left_row(r, ia) + ib] = v;
+            FRk1[fibre_right_col(ia, ib) + r] = v;
+          } else {     // column r of F_k: F_k(s_i, i_k, r)
+            FLk[fibre_left_row(ia, ib) + r] = v;
+            FRk[fibre_right_col(ib, r) + ia] = v;
+          }
+        }
+      }
       acc += v * sx[q];
       m = fmax(m, fabs(v));
     }
@@ -858,25 +862,26 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
 }
 
 // The border of P_k's factors for the pivot (row, col) added by step k:
-// b = A(I, t), c = A(l, J) and d = A(l, t) are evaluated here, then
+// b = A(I, t), c = A(l, J) and d = A(l, t) are read from the fibre cache
+// (d from the fibre the search stage stored), then
 // u = Li b, g = W^T c, s = d - g^T u,
 //   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
-// (leading dimension MAXR, transposes alongside).  I and J are in LDS,
-// amax0 is the value of *amax read at the start of the kernel.  Every thread
-// of the block calls it.
+// (leading dimension MAXR, transposes alongside).  amax0 is the value of
+// *amax read at the start of the kernel.  Every thread of the block calls it.
 constexpr int FB = 1024;   // threads of the finishing kernel
-template <int d, int dt, bool G>
-__device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn, StepRes* res, const int32_t* I,
-                               const int32_t* J, int r, int row, int col, double* Li, double* W, double* amax,
-                               double amax0, int32_t* info) {
+__device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int row, int col, double* Li, double* W,
+                               double* amax, double amax0, int32_t* info, const double* FLk, const double* FLk1,
+                               const double* FRk1) {
   constexpr int NW = FB / 64;
   __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[2 * FB];
   __shared__ double s_d, s_s;
   const int tid = threadIdx.x;
+  const int sl = row % a.rl, il = row / a.rl;     // the pivot row: (s, i_k)
+  const int it = col % a.nm1, tt = col / a.nm1;   // the pivot column: (i_{k+1}, t)
   for (int e = tid; e <= 2 * r; e += FB) {
-    if (e < r) bv[e] = addr_eval<d, dt, G>(ks, a, sn, I[e], col);
-    else if (e < 2 * r) cv[e - r] = addr_eval<d, dt, G>(ks, a, sn, row, J[e - r]);
-    else s_d = addr_eval<d, dt, G>(ks, a, sn, row, col);
+    if (e < r) bv[e] = FRk1[fibre_right_col(it, tt) + e];            // F_{k+1}(e, i_{k+1}, t)
+    else if (e < 2 * r) cv[e - r] = FLk[fibre_left_row(sl, il) + (e - r)];   // F_k(s, i_k, e)
+    else s_d = bit ? FLk1[fibre_left_row(r, it) + tt] : FLk[fibre_left_row(sl, il) + r];
   }
   __syncthreads();
   double* Lit = Li + FT;
@@ -939,23 +944,18 @@ __device__ void border_factors(const KSpec& ks, const Addr& a, const double* sn,
 // Clears the fold slots for the next step and publishes the result to the
 // host mailbox.
 static_assert(MAXR <= FB, "k_finish_step holds one pivot per thread");
-template <int d, int dt, bool G>
-__global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* desc, const int32_t* sel,
-                                                     const double* R, StepRes* res, int r, int max_rank,
-                                                     double* Li, double* W,
+__global__ void __launch_bounds__(FB) k_finish_step(const StepDesc* desc, const int32_t* sel, const double* R,
+                                                     StepRes* res, int r, int max_rank, double* Li, double* W,
                                                      double* amax, int32_t* info, StepRes* mail, uint32_t* mail_seq,
                                                      uint32_t seq, int32_t* sel_next, int16_t* next_left,
-                                                     int next_row) {
-  constexpr int D = 2 * d + dt;
+                                                     int next_row, const double* FLk, const double* FLk1,
+                                                     const double* FRk1) {
   const StepDesc& sd = desc[*sel];
   const Addr a = sd.a;
   const int bit = sd.bit;
-  __shared__ double sn[D * MAXN];
-  __shared__ int32_t sI[MAXR], sJ[MAXR];
   __shared__ int s_added;
   const int tid = threadIdx.x;
   // loads that do not depend on the selection, issued before it
-  const double ndv = tid < D * MAXN ? ks.nodes[tid] : 0.0;
   int32_t iq = -1, jq = -1;
   if (tid < r) {
     iq = sd.I[tid];
@@ -978,11 +978,6 @@ __global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* de
     const int s = row % a.rl;
     lv = tid < a.lk ? a.left[(size_t)s * a.lk + tid] : (int16_t)(row / a.rl);
   }
-  if (tid < D * MAXN) sn[tid] = ndv;
-  if (tid < r) {
-    sI[tid] = iq;
-    sJ[tid] = jq;
-  }
   const int stale = __syncthreads_or(tid < r && (iq == row || jq == col));
   if (tid == 0) {
     const int added = (pabs > TIE_REL * scale && !stale && r < max_rank) ? 1 : 0;
@@ -997,7 +992,7 @@ __global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* de
     res->q_slot[tid] = 0.0;
   }
   __syncthreads();
-  if (s_added) border_factors<d, dt, G>(ks, a, sn, res, sI, sJ, r, row, col, Li, W, amax, amax0, info);
+  if (s_added) border_factors(a, bit, res, r, row, col, Li, W, amax, amax0, info, FLk, FLk1, FRk1);
   // the next step of the sweep runs on variant s_added; if the pivot was
   // added, I^{<=k} gains the row (left row s of the pivot, node i_k), which
   // the next step's left set receives after its r_k current rows
@@ -1019,6 +1014,73 @@ __global__ void __launch_bounds__(FB) k_finish_step(KSpec ks, const StepDesc* de
   }
 }
 
+// After a step that added its pivot (l, t): the fibre the search stage did
+// not evaluate goes into the fibre cache, the column of super-core k through
+// t as column r of F_k (after a row search, bit 1) or its row through l as
+// row r of F_{k+1} (after a column search, bit 0).  Nothing happens when the
+// pivot was not added (the flag is read by every block alike).
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_add_fibre(KSpec ks, const StepDesc* desc, const int32_t* sel,
+                                                   const StepRes* res, int r, double* FLk, double* FRk, double* FLk1,
+                                                   double* FRk1) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN], fc[D];
+  if (!res->added) return;
+  const StepDesc& sd = desc[*sel];
+  const Addr a = sd.a;
+  const int bit = sd.bit;
+  const int n = bit ? sd.rows : sd.cols;
+  if ((int)blockIdx.x * 256 >= n) return;
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  const int row = res->pivot_row, col = res->pivot_col;
+  const int tid = threadIdx.x;
+  if (tid == 0) {   // the fixed half: the pivot's column (bit 1) or row (bit 0)
+    double c[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c[j] = 0.0;
+    if (bit) addr_col_part<D>(a, sn, col, c);
+    else addr_row_part<D>(a, sn, row, c);
+#pragma unroll
+    for (int j = 0; j < D; ++j) fc[j] = c[j];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + tid;
+  if (i >= n) return;
+  double c[D], vc[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) vc[j] = 0.0;
+  if (bit) addr_row_part<D>(a, sn, i, vc);
+  else addr_col_part<D>(a, sn, i, vc);
+#pragma unroll
+  for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? vc[j] : fc[j];
+  const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
+  if (bit) {   // F_k(s_i, i_k, r)
+    const int sa = i % a.rl, ia = i / a.rl;
+    FLk[fibre_left_row(sa, ia) + r] = v;
+    FRk[fibre_right_col(ia, r) + sa] = v;
+  } else {     // F_{k+1}(r, i_{k+1}, t_i)
+    const int ia = i % a.nm1, tb = i / a.nm1;
+    FLk1[fibre_left_row(r, ia) + tb] = v;
+    FRk1[fibre_right_col(ia, tb) + r] = v;
+  }
+}
+
+// The fibre cores of the initial index sets (ranks <= 2) into the cache:
+// F_k(a, i, b) for the fibre address of core k (rows a + i r_{k-1}, columns b).
+template <int d, int dt, bool G>
+__global__ void __launch_bounds__(256) k_fill_fibre(KSpec ks, Addr a, int rows, int rk, double* FL, double* FR) {
+  constexpr int D = 2 * d + dt;
+  __shared__ double sn[D * MAXN];
+  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * rk) return;
+  const int row = e % rows, b = e / rows;
+  const double v = addr_eval<d, dt, G>(ks, a, sn, row, b);
+  const int sa = row % a.rl, ia = row / a.rl;
+  FL[fibre_left_row(sa, ia) + b] = v;
+  FR[fibre_right_col(ia, b) + sa] = v;
+}
+
 // The stopping test's result, published to a mailbox slot: the largest of
 // the error slots (one per lane) and the OR of the factor status flags of
 // P_1 .. P_{N-1}.
@@ -1037,11 +1099,12 @@ __global__ void __launch_bounds__(64) k_test_publish(const double* err, const in
 }
 
 // The fibres F_k = X(I^{<=k-1}, i_k, I^{>k}) ((r_{k-1} n_k) x r_k,
-// column-major) of the stopping test: their addresses, outputs and sizes.
+// column-major) of the stopping test: the cache they are read from (FL_k),
+// the column-major copies written, and their sizes.
 struct CoreEval {
-  Addr a[MAXD];
+  const double* FL[MAXD];
   double* out[MAXD];
-  int nr[MAXD];
+  int nr[MAXD], rl[MAXD];
   int64_t size[MAXD];
   int n;
 };
@@ -1086,30 +1149,28 @@ constexpr int CW = 4;   // waves per block of the solve
 // dynamic LDS of the core solve (k_eval_solve) for rank r
 inline size_t solve_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof(double); }
 
-// The stopping test's fibres and cores in one launch: the solve tiles
-// evaluate their 16 rows of F_k themselves (straight into the lane order of
-// the first product, and into F_k in memory, which the refinement of the
-// returned cores reads), then blocks past the tiles evaluate the last fibre
-// F_D (C_D = F_D, no solve), 256 entries each.  Block 0 also clears the
-// test's error slots.  (One launch and one kernel boundary fewer per test
-// than a fibre launch followed by a solve launch.)
-template <int d, int dt, bool G>
-__global__ void __launch_bounds__(CW * 64) k_eval_solve(KSpec ks, CoreEval ce, CoreSolve cs, double* clear) {
-  constexpr int D = 2 * d + dt;
+// The stopping test's fibres and cores in one launch: the solve tiles read
+// their 16 rows of F_k from the fibre cache (straight into the lane order of
+// the first product, and into the column-major F_k in memory, which the
+// refinement of the returned cores reads), then blocks past the tiles copy
+// the last fibre F_D (C_D = F_D, no solve), 256 entries each.  Block 0 also
+// clears the test's error slots.
+__global__ void __launch_bounds__(CW * 64) k_eval_solve(CoreEval ce, CoreSolve cs, double* clear) {
   extern __shared__ double lds[];
-  __shared__ double sn[D * MAXN];
   if (blockIdx.x == 0 && threadIdx.x < TEST_SLOTS) clear[threadIdx.x] = 0.0;
-  stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
   const int tid = threadIdx.x;
   if ((int)blockIdx.x >= cs.tile[cs.n]) {   // the last fibre
     const int j = ce.n - 1;
     const int64_t e = (int64_t)((int)blockIdx.x - cs.tile[cs.n]) * (CW * 64) + tid;
-    if (e < ce.size[j]) ce.out[j][e] = addr_eval<d, dt, G>(ks, ce.a[j], sn, (int)(e % ce.nr[j]), (int)(e / ce.nr[j]));
+    if (e < ce.size[j]) {
+      const int row = (int)(e % ce.nr[j]), b = (int)(e / ce.nr[j]);
+      ce.out[j][e] = ce.FL[j][fibre_left_row(row % ce.rl[j], row / ce.rl[j]) + b];
+    }
     return;
   }
   int j = 0;
   while (j + 1 < cs.n && (int)blockIdx.x >= cs.tile[j + 1]) ++j;
-  const int m = cs.m[j], r = cs.r[j];
+  const int m = cs.m[j], r = cs.r[j], rl = ce.rl[j];
   const int row0 = ((int)blockIdx.x - cs.tile[j]) * 16;
   const int nst = (r + 3) / 4;
   const int lane = tid & 63, wv = tid >> 6;
@@ -1117,12 +1178,13 @@ __global__ void __launch_bounds__(CW * 64) k_eval_solve(KSpec ks, CoreEval ce, C
   double* sa = lds;
   double* sb = lds + 64 * nst;
   double* F = ce.out[j];
+  const double* FL = ce.FL[j];
   for (int e = tid; e < 64 * nst; e += CW * 64) {
     const int ii = e & 15, q = e >> 4;
     const int i = row0 + ii;
     double v = 0.0;
     if (i < m && q < r) {
-      v = addr_eval<d, dt, G>(ks, ce.a[j], sn, i, q);
+      v = FL[fibre_left_row(i % rl, i / rl) + q];
       F[i + (int64_t)q * m] = v;
     }
     sa[(q >> 2) * 64 + (q & 3) * 16 + ii] = v;
@@ -1283,6 +1345,11 @@ class Cross {
   // factors Li, W of P_k per k (MAXR x MAXR, leading dimension MAXR), max
   // |entry| of P_k and the factors' status
   DBuf d_li_[MAXD], d_w_[MAXD], d_luaux_, d_E_;
+  // the fibre cache of core k (1-based): FL_k and FR_k, n_k x MAXR x MAXR each
+  DBuf d_fl_[MAXD], d_fr_[MAXD];
+  double* fl(int k) { return d_fl_[k - 1].as<double>(); }
+  double* fr(int k) { return d_fr_[k - 1].as<double>(); }
+  tt_status fill_fibres();
   double* luamax(int k) { return d_luaux_.as<double>() + k; }
   int32_t* luinfo(int k) { return reinterpret_cast<int32_t*>(d_luaux_.as<double>() + MAXD) + k; }
   HostMail mail_;
@@ -1515,6 +1582,28 @@ tt_status Cross::init_inverses() {
   return sync();   // the arena's host side is reused after this
 }
 
+// The fibre cores of the initial index sets into the fibre cache (every
+// later entry is added by the update steps).
+tt_status Cross::fill_fibres() {
+  arena_reset();
+  Addr ak[MAXD + 1];
+  for (int k = 1; k <= N_; ++k) {
+    TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
+    ak[k] = fibre_addr(k);
+  }
+  TTK_TRY(arena_flush());
+  for (int k = 1; k <= N_; ++k) {
+    const int rows = rank(k - 1) * g_.n[k - 1], rk = rank(k);
+    with_dims(ks_, [&](auto dd, auto tt, auto gg) {
+      hipLaunchKernelGGL((k_fill_fibre<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                         dim3(nblk((int64_t)rows * rk, 256)), dim3(256), 0, st_, ks_, ak[k], rows, rk, fl(k), fr(k));
+    });
+    evals_ += (int64_t)rows * rk;
+  }
+  TTK_HIP(hipGetLastError());
+  return sync();   // the arena's host side is reused after this
+}
+
 // The buffers whose size follows the ranks (the stopping test's fibres and
 // cores, the products of solve_right and refine_cores), reserved once at the
 // largest size the rank bounds allow: growing one later would reallocate it,
@@ -1530,6 +1619,11 @@ tt_status Cross::reserve_buffers() {
   }
   TTK_TRY(ensure(d_E_, cmax));
   TTK_TRY(ensure(d_ref_, 2 * cmax));
+  for (int k = 1; k <= N_; ++k) {
+    const size_t c = (size_t)g_.n[k - 1] * MAXR * MAXR * sizeof(double);
+    TTK_TRY(ensure(d_fl_[k - 1], c));
+    TTK_TRY(ensure(d_fr_[k - 1], c));
+  }
   TTK_TRY(ensure(d_P_, (size_t)MAXR * MAXR * sizeof(double)));
   return TTK_OK;
 }
@@ -1657,12 +1751,14 @@ tt_status Cross::enqueue_front(const HostStep& h) {
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
     constexpr int D_ = decltype(dd)::value, T_ = decltype(tt)::value;
     constexpr bool G_ = decltype(gg)::value;
-    hipLaunchKernelGGL((k_sample_resid<D_, T_, G_>), dim3(nblk(nsm, SPB)), dim3(SW * 64), sample_lds(rk, 2 * D_ + T_), st_, ks_,
-                       h.desc, h.sel, rk, Li, W, R, dres->s_slot);
+    hipLaunchKernelGGL((k_sample_resid<D_, T_, G_>), dim3(nblk(nsm, SPB)), dim3(SW * 64), sample_lds(rk), st_, ks_,
+                       h.desc, h.sel, rk, Li, W, (const double*)fl(k), (const double*)fr(k + 1), R, dres->s_slot);
     hipLaunchKernelGGL((k_sample_select<D_, T_, G_>), dim3(1), dim3(1024), 0, st_, ks_, h.desc, h.sel,
-                       (const double*)R, (const double*)luamax(k), dres, rk, Li, W, x);
+                       (const double*)R, (const double*)luamax(k), dres, rk, Li, W, (const double*)fl(k),
+                       (const double*)fr(k + 1), x);
     hipLaunchKernelGGL((k_search<D_, T_, G_>), dim3(nblk(nqm, QE)), dim3(256), 0, st_, ks_, h.desc, h.sel,
-                       (const StepRes*)dres, (const double*)x, rk, R, dres->q_slot);
+                       (const StepRes*)dres, (const double*)x, rk, fl(k), fr(k), fl(k + 1), fr(k + 1), R,
+                       dres->q_slot);
   });
   TTK_HIP(hipGetLastError());
   return TTK_OK;
@@ -1676,12 +1772,17 @@ tt_status Cross::enqueue_finish(HostStep& h, const HostStep* next) {
   int32_t* sel_next = next ? const_cast<int32_t*>(next->sel) : nullptr;
   int16_t* next_left = (next && next->nvar == 2) ? next->left : nullptr;
   StepRes* dres = d_res_.as<StepRes>();
+  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(FB), 0, st_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres,
+                     h.rk, max_rank(), d_li_[k].as<double>(), d_w_[k].as<double>(), luamax(k), luinfo(k),
+                     mail_.dres + k, mail_.dseq + k, h.seq, sel_next, next_left, h.rk, (const double*)fl(k),
+                     (const double*)fl(k + 1), (const double*)fr(k + 1));
+  // the fibre the search did not evaluate, when the pivot is added
+  int nf = 0;
+  for (int v = 0; v < h.nvar; ++v) nf = std::max(nf, h.bit[v] ? h.rows[v] : h.cols);
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_finish_step<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>), dim3(1),
-                       dim3(FB), 0, st_, ks_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres, h.rk,
-                       max_rank(), d_li_[k].as<double>(),
-                       d_w_[k].as<double>(), luamax(k), luinfo(k), mail_.dres + k, mail_.dseq + k, h.seq, sel_next,
-                       next_left, h.rk);
+    hipLaunchKernelGGL((k_add_fibre<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
+                       dim3(nblk(nf, 256)), dim3(256), 0, st_, ks_, h.desc, h.sel, (const StepRes*)dres, h.rk, fl(k),
+                       fr(k), fl(k + 1), fr(k + 1));
   });
   TTK_HIP(hipGetLastError());
   return TTK_OK;
@@ -1700,8 +1801,7 @@ tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
     return fail(TTK_ERR_SINGULAR_CROSS, "cross: intersection matrix of super-core %d singular (sweep %d)", k,
                 h.sweep);
   const int rows = h.rows[v], cols = h.cols, ns = h.ns[v], bit = h.bit[v];
-  evals_ += 2 * (int64_t)ns * rk + ns;
-  evals_ += bit ? (int64_t)rk + (int64_t)rk * cols + cols : (int64_t)rows * rk + rk + rows;
+  evals_ += ns + (bit ? cols : rows);   // the samples and the searched fibre (the rest is cached)
   rec->sweep = h.sweep;
   rec->k = k;
   rec->rank_before = rk;
@@ -1718,7 +1818,7 @@ tt_status Cross::collect(const HostStep& h, tt_kernel_decision* rec) {
   if (r.s_max > 0) min_margin_ = std::min(min_margin_, r.s_margin);
   if (r.q_max > 0) min_margin_ = std::min(min_margin_, r.q_margin);
   if (r.added) {
-    evals_ += 2 * (int64_t)rk + 1;                 // the border entries
+    evals_ += bit ? rows : cols;                  // the other fibre through the pivot
     const int l = r.pivot_row, t = r.pivot_col;   // the factors of P_k are already bordered
     const int s = l % rl, ik = l / rl;
     pls_[k].push_back(s);
@@ -1821,13 +1921,12 @@ tt_status Cross::stage_core(int k) {
   }
   const int r0 = rank(k - 1), r1 = rank(k), n = g_.n[k - 1];
   const int m = r0 * n;
-  TTK_TRY(upload_sets(k - 1, k, nullptr, nullptr));
   TTK_TRY(ensure(d_core_[k - 1], (size_t)m * r1 * sizeof(double)));
-  ce_.a[k - 1] = fibre_addr(k);
+  ce_.FL[k - 1] = fl(k);
   ce_.out[k - 1] = d_core_[k - 1].as<double>();
   ce_.nr[k - 1] = m;
+  ce_.rl[k - 1] = r0;
   ce_.size[k - 1] = (int64_t)m * r1;
-  evals_ += (int64_t)m * r1;
   ce_next_ = k + 1;
   return TTK_OK;
 }
@@ -1857,12 +1956,10 @@ tt_status Cross::build_cores(std::vector<double*>* C) {
   }
   cs.tile[N - 1] = nt;
   (*C)[N - 1] = d_core_[N - 1].as<double>();
-  // the solve tiles (evaluating their own fibre rows), then the last fibre
+  // the solve tiles (reading their own fibre rows), then the last fibre
   const int nlast = nblk(ce_.size[N - 1], CW * 64);
-  with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-    hipLaunchKernelGGL((k_eval_solve<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-                       dim3(nt + nlast), dim3(CW * 64), solve_lds(rmax), st_, ks_, ce_, cs, d_err_.as<double>());
-  });
+  hipLaunchKernelGGL(k_eval_solve, dim3(nt + nlast), dim3(CW * 64), solve_lds(rmax), st_, ce_, cs,
+                     d_err_.as<double>());
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
@@ -1951,6 +2048,7 @@ tt_status Cross::run(CrossOut* out) {
   TTK_TRY(init_sets());
   TTK_TRY(reserve_buffers());
   TTK_TRY(init_inverses());
+  TTK_TRY(fill_fibres());
   // fixed test multi-indices of the stopping rule
   int nmax = 0;
   for (int j = 0; j < N; ++j) nmax = std::max(nmax, g_.n[j]);
@@ -1972,27 +2070,20 @@ tt_status Cross::run(CrossOut* out) {
     TTK_HIP(hipMemcpyAsync(&test_max_, d_err_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
     TTK_TRY(sync());
   }
-  // the sample stage stages up to 2 x 64 x MAXR / 4 + MAXR x MAXD doubles of LDS per block
-  if (sample_lds(MAXR, MAXD) > 48 * 1024) {
+  // the sample stage stages up to 2 x 64 x MAXR / 4 doubles of LDS per block
+  if (sample_lds(MAXR) > 48 * 1024) {
     hipError_t e = hipSuccess;
     with_dims(ks_, [&](auto dd, auto tt, auto gg) {
       e = hipFuncSetAttribute(
           reinterpret_cast<const void*>(
               &k_sample_resid<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR, MAXD));
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sample_lds(MAXR));
     });
     TTK_HIP(e);
   }
-  if (solve_lds(MAXR) > 48 * 1024) {
-    hipError_t e = hipSuccess;
-    with_dims(ks_, [&](auto dd, auto tt, auto gg) {
-      e = hipFuncSetAttribute(
-          reinterpret_cast<const void*>(
-              &k_eval_solve<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR));
-    });
-    TTK_HIP(e);
-  }
+  if (solve_lds(MAXR) > 48 * 1024)
+    TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_solve),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
   TTK_TRY(mail_.alloc());
   TTK_TRY(d_x_.alloc(MAXR * sizeof(double)));   // the search stage's P^{-1} u
   // the residuals of either stage: at most max(rows, cols) <= MAXR x MAXN
