@@ -156,8 +156,10 @@ tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, doubl
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);
-// Same without the right vectors (A <- U Sigma normalised to U, sigma); false
-// (nothing launched) when A does not fit the workgroup's LDS.
+// Same without the right vectors (A <- U Sigma normalised to U, sigma): in
+// one workgroup's LDS when A fits, else by the block iteration over many
+// workgroups (n <= 256; it waits for the stream between batches of sweeps).
+// sigma's buffer holds jacobi_sigma_doubles(n).  false: nothing launched.
 bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st);
 // count independent SVDs, one workgroup each; matrix b at A + b sA, V + b sV,
 // sigma (and its workspace) at sigma + b sS, sS >= jacobi_sigma_doubles(n).

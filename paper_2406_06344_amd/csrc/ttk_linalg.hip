@@ -1308,6 +1308,141 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
   jacobi_finish(Ag, n, lda, want_v ? V : nullptr, ldv, sigma, work, order);
 }
 
+// Block form of the one-sided Jacobi iteration, for matrices whose n x n
+// doubles do not fit one workgroup's LDS: the columns are split into blocks
+// of JB_W, and the blocks meet in a round-robin tournament (the circle
+// method over blocks, one dummy block when their number is odd).  Each
+// meeting is one workgroup: it copies the 2 JB_W columns of its two blocks
+// into LDS, runs one sweep of the column iteration over them (the circle
+// method over the 2 JB_W columns, a pair per 16-lane group, rotations and
+// convergence tests as in k_jacobi_lds), and writes them back.  A round of
+// meetings is one launch; an outer sweep, in which every pair of columns
+// meets at least once, is n_blocks - 1 launches followed by k_jb_check.
+// The stopping rule is k_jacobi's, taken over the outer sweep: stop after a
+// sweep with no rotation, or none whose cosine exceeded JACOBI_LAST.  The
+// per-sweep flags and the squared Frobenius norm (the floor of the inner
+// products) live past the workspace of jacobi_finish in sigma's buffer.
+constexpr int JB_W = 16;    // columns per block
+constexpr int JB_T = 256;   // threads: 16 pairs of 2 JB_W columns, 16 lanes each
+__global__ void __launch_bounds__(BS) k_jb_init(const double* A, int n, int lda, double* aux) {
+  __shared__ double red[NW];
+  double nf = 0.0;
+  for (int e = threadIdx.x; e < n * n; e += BS) {
+    const double a = A[e % n + (size_t)(e / n) * lda];
+    nf += a * a;
+  }
+  nf = block_sum(nf, red);
+  if (threadIdx.x == 0) {
+    aux[0] = nf;
+    int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
+    fl[0] = fl[1] = fl[2] = 0;   // done, rotated, large
+  }
+}
+
+__global__ void k_jb_check(double* aux) {
+  int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
+  if (threadIdx.x == 0) {
+    if (!fl[1] || !fl[2]) fl[0] = 1;
+    fl[1] = fl[2] = 0;
+  }
+}
+
+template <int E>
+__global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda, int nbp, int rnd, double* aux) {
+  int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
+  if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;   // converged
+  extern __shared__ double sj[];   // the 2 JB_W columns, leading dimension n
+  __shared__ int s_rot, s_large;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_rot = s_large = 0;
+  // this workgroup's pair of blocks in round rnd
+  int P = 0;
+  if (blockIdx.x != 0) P = 1 + ((int)blockIdx.x - 1 + rnd) % (nbp - 1);
+  int Q = 1 + (nbp - 2 - (int)blockIdx.x + rnd) % (nbp - 1);
+  if (P > Q) { const int t = P; P = Q; Q = t; }
+  const int nb = (n + JB_W - 1) / JB_W;
+  auto gcol = [&](int c) {   // global column of local column c, -1 if none
+    const int b = c < JB_W ? P : Q;
+    const int g = b * JB_W + (c & (JB_W - 1));
+    return (b < nb && g < n) ? g : -1;
+  };
+  for (int e = tid; e < 2 * JB_W * n; e += JB_T) {
+    const int c = e / n, i = e - c * n;
+    const int g = gcol(c);
+    sj[e] = g >= 0 ? A[i + (size_t)g * lda] : 0.0;
+  }
+  const double gfloor = 1e-30 * aux[0];
+  __syncthreads();
+  constexpr int NP = 2 * JB_W;
+  const int grp = tid >> 4, gl = tid & 15;
+  int rot = 0, large = 0;
+  for (int lr = 0; lr < NP - 1; ++lr) {
+    int p = 0;
+    if (grp != 0) {
+      const int x = grp - 1 + lr;
+      p = 1 + (x >= NP - 1 ? x - (NP - 1) : x);
+    }
+    const int y = NP - 2 - grp + lr;
+    int q = 1 + (y >= NP - 1 ? y - (NP - 1) : y);
+    if (p > q) { const int t = p; p = q; q = t; }
+    if (gcol(p) >= 0 && gcol(q) >= 0) {
+      double* ap = sj + (size_t)p * n;
+      double* aq = sj + (size_t)q * n;
+      double xv[E], yv[E];
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int i = min(gl + 16 * u, n - 1);
+        xv[u] = ap[i];
+        yv[u] = aq[i];
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const bool in = gl + 16 * u < n;
+        al += in ? xv[u] * xv[u] : 0.0;
+        be += in ? yv[u] * yv[u] : 0.0;
+        ga += in ? xv[u] * yv[u] : 0.0;
+      }
+      al = row16_sum(al);
+      be = row16_sum(be);
+      ga = row16_sum(ga);
+      if (!(ga * ga <= 1e-30 * (al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
+        double c, sn;
+        jacobi_rotation(al, be, ga, c, sn);
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+          const int i = min(gl + 16 * u, n - 1);
+          ap[i] = c * xv[u] - sn * yv[u];
+          aq[i] = sn * xv[u] + c * yv[u];
+        }
+        rot = 1;
+        if (ga * ga > JACOBI_LAST * JACOBI_LAST * (al * be)) large = 1;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 2 * JB_W * n; e += JB_T) {
+    const int c = e / n, i = e - c * n;
+    const int g = gcol(c);
+    if (g >= 0) A[i + (size_t)g * lda] = sj[e];
+  }
+  if (rot) s_rot = 1;
+  if (large) s_large = 1;
+  __syncthreads();
+  if (tid == 0) {
+    if (s_rot) atomicOr(fl + 1, 1);
+    if (s_large) atomicOr(fl + 2, 1);
+  }
+}
+
+// Singular values, normalised left vectors and the ordering (jacobi_finish)
+// of a matrix the block iteration has orthogonalised.
+__global__ void __launch_bounds__(BS) k_jb_finish(double* A, int n, int lda, double* sigma) {
+  double* work = sigma + n;
+  int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
+  jacobi_finish(A, n, lda, nullptr, 0, sigma, work, order);
+}
+
 // ----------------------------------------------------------------- GEMM
 template <int TILE>
 __global__ void k_gemm64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda,
@@ -1561,6 +1696,50 @@ bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* si
   }
 }
 
+template <int E>
+void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux, size_t sh, hipStream_t st) {
+  static size_t attr = 48 * 1024;   // dynamic LDS the instantiation is allowed so far
+  if (sh > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_block<E>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
+      return;   // (the launch then fails and the error is reported by the caller's next check)
+    attr = sh;
+  }
+  hipLaunchKernelGGL((k_jacobi_block<E>), dim3(nbp / 2), dim3(JB_T), sh, st, A, n, lda, nbp, rnd, aux);
+}
+
+// The block iteration: sweeps queued in batches, the host reading the
+// convergence flag between batches (the sweeps queued past convergence
+// return at once).
+bool jacobi_block_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
+  if (n < 2 || n > 16 * 16) return false;
+  const size_t sh = (size_t)2 * JB_W * n * sizeof(double);
+  const int nb = (n + JB_W - 1) / JB_W, nbp = nb + (nb & 1);
+  double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
+  const int32_t* done = reinterpret_cast<const int32_t*>(aux + 1);
+  hipLaunchKernelGGL(k_jb_init, dim3(1), dim3(BS), 0, st, (const double*)A, n, lda, aux);
+  const int E = (n + 15) / 16;
+  int sweeps = 0;
+  for (int batch = 6; sweeps < 60; batch = 2) {
+    for (int b = 0; b < batch && sweeps < 60; ++b, ++sweeps) {
+      for (int rnd = 0; rnd < nbp - 1; ++rnd) {
+        if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, st);
+        else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, st);
+        else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, st);
+        else jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, st);
+      }
+      hipLaunchKernelGGL(k_jb_check, dim3(1), dim3(64), 0, st, aux);
+    }
+    int32_t h = 0;
+    if (hipMemcpyAsync(&h, done, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      break;   // (the error stays pending for the caller's next check)
+    if (h) break;
+  }
+  hipLaunchKernelGGL(k_jb_finish, dim3(1), dim3(BS), 0, st, A, n, lda, sigma);
+  return true;
+}
+
 }  // namespace
 
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st) {
@@ -1571,7 +1750,8 @@ void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hi
 }
 
 bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
-  return jacobi_lds_launch(A, n, lda, nullptr, 0, sigma, st);
+  if (jacobi_lds_launch(A, n, lda, nullptr, 0, sigma, st)) return true;
+  return jacobi_block_left(A, n, lda, sigma, st);
 }
 
 void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,
@@ -1580,7 +1760,7 @@ void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv
   hipLaunchKernelGGL(k_jacobi, dim3(count), dim3(BS), 0, st, A, n, lda, V, ldv, sigma, sA, sV, sS);
 }
 
-size_t jacobi_sigma_doubles(int n) { return (size_t)n * n + 3 * (size_t)n + 2; }
+size_t jacobi_sigma_doubles(int n) { return (size_t)n * n + 3 * (size_t)n + 8; }
 
 void gemm64(int ta, int tb, int m, int n, int k, double alpha, const double* A, int lda, const double* B,
             int ldb, double beta, double* C, int ldc, hipStream_t st) {
