@@ -164,6 +164,15 @@ __global__ void k_gather_rows(const double* F, int ldf, const int32_t* rows, int
   P[a + b * r] = F[rows[a] + (int64_t)b * ldf];
 }
 
+// P[a + b r] = F_k(s_a, i_a, b) for the pivot rows I[a] = s_a + i_a rl of
+// super-core k (a, b < r <= 4): the intersection matrix from the fibre cache.
+__global__ void k_gather_pivots(const double* FL, const int32_t* I, int rl, int r, double* P) {
+  const int e = threadIdx.x;
+  if (e >= r * r) return;
+  const int a = e % r, b = e / r;
+  P[e] = FL[fibre_left_row(I[a] % rl, I[a] / rl) + b];
+}
+
 // B (n x m) = A^T for A (m x n)
 __global__ void k_transpose(const double* A, int m, int n, int lda, double* B, int ldb) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -220,7 +229,10 @@ __global__ void __launch_bounds__(1024) k_init_sets(KSpec ks, InitArgs ia, int32
     a.nm0 = n;
     a.nm1 = 1;
     const int m = a.rl * n;
-    for (int e = tid; e < m * a.rr; e += 1024) F[e] = addr_eval<d, dt, G>(ks, a, sn, e % m, e / m);
+    for (int e = tid >> 4; e < m * a.rr; e += 64) {   // one entry per row of 16 lanes
+      const double v = addr_eval_row16<d, dt, G>(ks, a, sn, e % m, e / m, tid & 15);
+      if ((tid & 15) == 0) F[e] = v;
+    }
     __syncthreads();
     const int excl = (mode == 0) ? (k == 1) : (k == N);
     const int nn = n * n;   // <= 1024: one candidate per thread
@@ -595,8 +607,8 @@ __device__ inline double slots_max(const double* sl) {
 // samples (v_mfma_f64_16x16x4: A at [l % 16][l / 16], B at [l / 16][l % 16],
 // D row l / 16 + 4 v, column l % 16 in lane l, slot v).  A(s_i, J_q) and
 // A(I_q, s_i) are entries of the fibre cores F_k and F_{k+1} (the fibre
-// cache, see FibreCache), gathered straight into LDS in MFMA lane order; only
-// A(s_i) itself is evaluated.  The max |.| of all of them folds into the
+// cache), gathered straight into LDS in MFMA lane order; only A(s_i) itself
+// is evaluated, by a row of 16 lanes per sample.  The max |.| of all of them folds into the
 // sample-stage slots.  Each wave owns one 16-column tile of G and T at a
 // time; the B operands of its first tile (rows of W^T and Li) are loaded into
 // registers before the gathers.
@@ -671,13 +683,16 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
     sa[64 * nst + slot] = vt;
     m = fmax(m, fmax(fabs(vg), fabs(vt)));
   }
-  if (tid < nv) {
-    double c[D];
+  {   // A(s_i): one sample per row of 16 lanes, which share its evaluation
+    const int g = tid >> 4, l16 = tid & 15;
+    if (g < nv) {
+      double c[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) c[j] = S[tid * D + j];
-    const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
-    sAs[tid] = v;
-    m = fmax(m, fabs(v));
+      for (int j = 0; j < D; ++j) c[j] = S[g * D + j];
+      const double v = kappa_eval<d, dt, G, true>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c, l16);
+      if (l16 == 0) sAs[g] = v;
+      m = fmax(m, fabs(v));
+    }
   }
   m = wave64_max(m);
   if (lane == 0) redm[wv] = m;
@@ -785,10 +800,11 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
 // with (l, t) the chosen sample and x = P^{-1} u from k_sample_select.
 // A(I_q, i) = F_{k+1}(q, i_{k+1}, t_i) and A(i, J_q) = F_k(s_i, i_k, q) come
 // from the fibre cache; the fibre entries A(l, i) or A(i, t) are evaluated
-// and stored in the slot the pivot would occupy: row r of F_{k+1} (bit 1) or
-// column r of F_k (bit 0), when r < MAXR.  Sixteen fibre entries per block,
-// one 16-lane row per entry with the q terms strided over its lanes (the
-// fibre entry as term q = r, weight -1) and summed by DPP.  Every value's
+// (by the entry's 16 lanes together) and stored in the slot the pivot would
+// occupy: row r of F_{k+1} (bit 1) or column r of F_k (bit 0), when r < MAXR.
+// Sixteen fibre entries per block, one 16-lane row per entry with the q
+// terms strided over its lanes (the fibre entry as term q = r, weight -1)
+// and summed by DPP.  Every value's
 // max |.| folds into the search-stage slots.
 constexpr int QE = 16;   // fibre entries per block
 template <int d, int dt, bool G>
@@ -822,29 +838,28 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
     // (bit 1) or row (s_i, i_k) of F_k (bit 0)
     const int ia = bit ? i % a.nm1 : i % a.rl, ib = bit ? i / a.nm1 : i / a.rl;
     const double* crow = bit ? FRk1 + fibre_right_col(ia, ib) : FLk + fibre_left_row(ia, ib);
-    for (int q = lj; q <= r; q += 16) {
-      double v;
-      if (q < r) {
-        v = crow[q];
-      } else {
-        double c[D], vc[D];
+    double vf;   // the fibre entry, evaluated by the entry's 16 lanes together
+    {
+      double c[D], vc[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) vc[j] = 0.0;
-        if (bit) addr_col_part<D>(a, sn, i, vc);
-        else addr_row_part<D>(a, sn, i, vc);
+      for (int j = 0; j < D; ++j) vc[j] = 0.0;
+      if (bit) addr_col_part<D>(a, sn, i, vc);
+      else addr_row_part<D>(a, sn, i, vc);
 #pragma unroll
-        for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[j] : vc[j];
-        v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
-        if (r < MAXR) {
-          if (bit) {   // row r of F_{k+1}: F_{k+1}(r, i_{k+1}, t_i)
-            FLk1[fibre_left_row(r, ia) + ib] = v;
-            FRk1[fibre_right_col(ia, ib) + r] = v;
-          } else {     // column r of F_k: F_k(s_i, i_k, r)
-            FLk[fibre_left_row(ia, ib) + r] = v;
-            FRk[fibre_right_col(ib, r) + ia] = v;
-          }
-        }
+      for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? fc[j] : vc[j];
+      vf = kappa_eval<d, dt, G, true>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c, lj);
+    }
+    if (lj == 0 && r < MAXR) {
+      if (bit) {   // row r of F_{k+1}: F_{k+1}(r, i_{k+1}, t_i)
+        FLk1[fibre_left_row(r, ia) + ib] = vf;
+        FRk1[fibre_right_col(ia, ib) + r] = vf;
+      } else {     // column r of F_k: F_k(s_i, i_k, r)
+        FLk[fibre_left_row(ia, ib) + r] = vf;
+        FRk[fibre_right_col(ib, r) + ia] = vf;
       }
+    }
+    for (int q = lj; q <= r; q += 16) {
+      const double v = q < r ? crow[q] : vf;
       acc += v * sx[q];
       m = fmax(m, fabs(v));
     }
@@ -1017,8 +1032,9 @@ __global__ void __launch_bounds__(FB) k_finish_step(const StepDesc* desc, const 
 // After a step that added its pivot (l, t): the fibre the search stage did
 // not evaluate goes into the fibre cache, the column of super-core k through
 // t as column r of F_k (after a row search, bit 1) or its row through l as
-// row r of F_{k+1} (after a column search, bit 0).  Nothing happens when the
-// pivot was not added (the flag is read by every block alike).
+// row r of F_{k+1} (after a column search, bit 0), 16 entries per block, one
+// per row of 16 lanes.  Nothing happens when the pivot was not added (the
+// flag is read by every block alike).
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(256) k_add_fibre(KSpec ks, const StepDesc* desc, const int32_t* sel,
                                                    const StepRes* res, int r, double* FLk, double* FRk, double* FLk1,
@@ -1030,10 +1046,10 @@ __global__ void __launch_bounds__(256) k_add_fibre(KSpec ks, const StepDesc* des
   const Addr a = sd.a;
   const int bit = sd.bit;
   const int n = bit ? sd.rows : sd.cols;
-  if ((int)blockIdx.x * 256 >= n) return;
+  if ((int)blockIdx.x * 16 >= n) return;
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
   const int row = res->pivot_row, col = res->pivot_col;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, l16 = tid & 15;
   if (tid == 0) {   // the fixed half: the pivot's column (bit 1) or row (bit 0)
     double c[D];
 #pragma unroll
@@ -1044,7 +1060,7 @@ __global__ void __launch_bounds__(256) k_add_fibre(KSpec ks, const StepDesc* des
     for (int j = 0; j < D; ++j) fc[j] = c[j];
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + tid;
+  const int i = blockIdx.x * 16 + (tid >> 4);   // one entry per row of 16 lanes
   if (i >= n) return;
   double c[D], vc[D];
 #pragma unroll
@@ -1053,7 +1069,8 @@ __global__ void __launch_bounds__(256) k_add_fibre(KSpec ks, const StepDesc* des
   else addr_col_part<D>(a, sn, i, vc);
 #pragma unroll
   for (int j = 0; j < D; ++j) c[j] = ((j <= a.lk) == (bit != 0)) ? vc[j] : fc[j];
-  const double v = kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
+  const double v = kappa_eval<d, dt, G, true>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c, l16);
+  if (l16 != 0) return;
   if (bit) {   // F_k(s_i, i_k, r)
     const int sa = i % a.rl, ia = i / a.rl;
     FLk[fibre_left_row(sa, ia) + r] = v;
@@ -1072,10 +1089,11 @@ __global__ void __launch_bounds__(256) k_fill_fibre(KSpec ks, Addr a, int rows, 
   constexpr int D = 2 * d + dt;
   __shared__ double sn[D * MAXN];
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
-  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int e = blockIdx.x * 16 + (threadIdx.x >> 4);   // one entry per row of 16 lanes
   if (e >= rows * rk) return;
   const int row = e % rows, b = e / rows;
-  const double v = addr_eval<d, dt, G>(ks, a, sn, row, b);
+  const double v = addr_eval_row16<d, dt, G>(ks, a, sn, row, b, threadIdx.x & 15);
+  if ((threadIdx.x & 15) != 0) return;
   const int sa = row % a.rl, ia = row / a.rl;
   FL[fibre_left_row(sa, ia) + b] = v;
   FR[fibre_right_col(ia, b) + sa] = v;
@@ -1552,29 +1570,25 @@ void Cross::pivot_positions(int k, std::vector<int32_t>* I, std::vector<int32_t>
   }
 }
 
-// P_k^{-1} of the initial index sets (ranks 1 or 2).
+// P_k^{-1} of the initial index sets (ranks 1 or 2), with P_k gathered from
+// the fibre cache (F_k at the pivot rows).
 tt_status Cross::init_inverses() {
   TTK_TRY(d_P_.alloc(16 * sizeof(double)));
-  // every core's sets and pivot positions in one upload
+  // every core's pivot positions in one upload
   arena_reset();
-  Addr ak[MAXD];
   const int32_t* dIk[MAXD] = {nullptr};
   for (int k = 1; k < N_; ++k) {
     std::vector<int32_t> I, J;
     pivot_positions(k, &I, &J);
-    TTK_TRY(upload_sets(k - 1, k + 1, nullptr, nullptr));
-    ak[k] = super_addr(k);
-    std::vector<int32_t> hi(I);
-    hi.insert(hi.end(), J.begin(), J.end());
-    TTK_TRY(arena_push(hi.data(), hi.size(), &dIk[k]));
+    TTK_TRY(arena_push(I.data(), I.size(), &dIk[k]));
   }
   TTK_TRY(arena_flush());
   for (int k = 1; k < N_; ++k) {
     const int rk = rank(k);
     TTK_TRY(d_li_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));   // Li, then Li^T
     TTK_TRY(d_w_[k].alloc((size_t)2 * MAXR * MAXR * sizeof(double)));    // W, then W^T
-    eval_product(ks_, ak[k], dIk[k], rk, dIk[k] + rk, rk, d_P_.as<double>(), st_);
-    evals_ += (int64_t)rk * rk;
+    hipLaunchKernelGGL(k_gather_pivots, dim3(1), dim3(64), 0, st_, (const double*)fl(k), dIk[k], rank(k - 1), rk,
+                       d_P_.as<double>());
     hipLaunchKernelGGL(k_ldu_init, dim3(1), dim3(64), 0, st_, d_P_.as<double>(), rk, d_li_[k].as<double>(),
                        d_w_[k].as<double>(), luamax(k), luinfo(k));
   }
@@ -1596,7 +1610,7 @@ tt_status Cross::fill_fibres() {
     const int rows = rank(k - 1) * g_.n[k - 1], rk = rank(k);
     with_dims(ks_, [&](auto dd, auto tt, auto gg) {
       hipLaunchKernelGGL((k_fill_fibre<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-                         dim3(nblk((int64_t)rows * rk, 256)), dim3(256), 0, st_, ks_, ak[k], rows, rk, fl(k), fr(k));
+                         dim3(nblk((int64_t)rows * rk, 16)), dim3(256), 0, st_, ks_, ak[k], rows, rk, fl(k), fr(k));
     });
     evals_ += (int64_t)rows * rk;
   }
@@ -1781,7 +1795,7 @@ tt_status Cross::enqueue_finish(HostStep& h, const HostStep* next) {
   for (int v = 0; v < h.nvar; ++v) nf = std::max(nf, h.bit[v] ? h.rows[v] : h.cols);
   with_dims(ks_, [&](auto dd, auto tt, auto gg) {
     hipLaunchKernelGGL((k_add_fibre<decltype(dd)::value, decltype(tt)::value, (bool)decltype(gg)::value>),
-                       dim3(nblk(nf, 256)), dim3(256), 0, st_, ks_, h.desc, h.sel, (const StepRes*)dres, h.rk, fl(k),
+                       dim3(nblk(nf, 16)), dim3(256), 0, st_, ks_, h.desc, h.sel, (const StepRes*)dres, h.rk, fl(k),
                        fr(k), fl(k + 1), fr(k + 1));
   });
   TTK_HIP(hipGetLastError());
@@ -2047,8 +2061,8 @@ tt_status Cross::run(CrossOut* out) {
   fill_zero(d_luaux_.p, MAXD * (sizeof(double) + sizeof(int32_t)), st_);
   TTK_TRY(init_sets());
   TTK_TRY(reserve_buffers());
-  TTK_TRY(init_inverses());
   TTK_TRY(fill_fibres());
+  TTK_TRY(init_inverses());
   // fixed test multi-indices of the stopping rule
   int nmax = 0;
   for (int j = 0; j < N; ++j) nmax = std::max(nmax, g_.n[j]);

@@ -102,6 +102,14 @@ __device__ inline double addr_eval(const KSpec& ks, const Addr& a, const double*
   addr_coords<2 * d + dt>(a, sn, row, col, c);
   return kappa_eval<d, dt, G>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c);
 }
+// The same entry evaluated by the 16 lanes of a DPP row together (every lane
+// of the row with the same row and col; l16 = the lane in the row).
+template <int d, int dt, bool G>
+__device__ inline double addr_eval_row16(const KSpec& ks, const Addr& a, const double* sn, int row, int col, int l16) {
+  double c[2 * d + dt];
+  addr_coords<2 * d + dt>(a, sn, row, col, c);
+  return kappa_eval<d, dt, G, true>(ks.kind, ks.kconst, ks.thfix[0], ks.thfix[1], c, l16);
+}
 
 template <int V>
 using IC = std::integral_constant<int, V>;
