@@ -2,7 +2,7 @@
 FP64 oracle in oracle/pairs.py on the same seeded pairs and points.
 
 Checked: the class assignment and class ranks, every pair's factor rows,
-the batched apply, dX and dtheta (float64: <= 1e-10, float32: <= 2e-5
+the batched apply, dX and dtheta (float64: <= 1e-10, float32: <= 1e-5
 relative Frobenius), graph replays against direct launches, the autotuned
 launch shapes against fixed ones, ragged and empty pairs."""
 import functools
@@ -106,7 +106,7 @@ def test_batch_matches_oracle(name, dtype):
     assert inf["num_classes"] == len(ob["builds"])
     for c, (P, out) in enumerate(ob["builds"]):
         assert inf["class_ranks"][c] == out["ranks"]
-    tolr = 1e-10 if dtype == "f64" else 2e-5
+    tolr = 1e-10 if dtype == "f64" else 1e-5
     # apply + backward (graph path: first call captures, later calls replay):
     # products that do not depend on the gauge of the rounded cores
     tht = torch.tensor(th, dtype=tdt, device="cuda")
@@ -133,6 +133,9 @@ def test_batch_matches_oracle(name, dtype):
             ef = max(ef, rel(g, O_ @ (w @ zt)))
     say(f"  rel err y {ey:.2e} dX {ex:.2e} dtheta {et:.2e}; factor rows up to gauge {ef:.2e}")
     assert ey <= tolr and ex <= tolr and et <= tolr
+    for got, ref in ((Yg.double().cpu().numpy().T, yv), (dXg.double().cpu().numpy().T, dXo),
+                     (dthg.double().cpu().numpy(), dtho)):
+        assert np.abs(got - ref).max() <= tolr * np.abs(ref).max()
 
 
 def test_batch_graph_replays_match_direct_launches():
@@ -174,7 +177,7 @@ def test_batch_autotuned_shapes_match_fixed_shapes():
         tht = torch.tensor(th, dtype=tdt, device="cuda")
         xt = torch.tensor(xv.T.copy(), dtype=tdt, device="cuda")
         Yg = bt.apply(tht, xt)
-        assert rel(Yg.double().cpu().numpy().T, yv) <= 2e-5
+        assert rel(Yg.double().cpu().numpy().T, yv) <= 1e-5
 
 
 def test_batch_test_kernel_has_one_class_per_pair():

@@ -54,6 +54,12 @@ def rel(a, b):
     return odense.rel_fro(np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64))
 
 
+def mx(a, b):
+    """largest entry error over the largest entry of the reference"""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def adjoint_gap(dX, x, g, y, chunk=256):
     """max over b of |<dX_b, x_b> - <g_b, y_b>| / (|g_b| |y_b|), in float64, by chunks of thetas."""
     worst = 0.0
@@ -136,9 +142,11 @@ def test_benchmark_workload_full_size_matches_oracle():
     S = opttk.phase3_source(opttk.factor_values(X[si], P.box_s, w.n_spatial), Go[:d])
     T = opttk.phase3_target(opttk.factor_values(Y[ti], P.box_t, w.n_spatial), Go[d + dt:])
     U, V = kern.factors()
-    eu, ev = rel(U[si].double().cpu().numpy(), S), rel(V[ti].double().cpu().numpy(), T)
-    say(f"  sampled rows: U {eu:.2e} V {ev:.2e}")
-    assert eu <= 2e-5 and ev <= 2e-5
+    Ug, Vg = U[si].double().cpu().numpy(), V[ti].double().cpu().numpy()
+    eu, ev = rel(Ug, S), rel(Vg, T)
+    mu, mv = mx(Ug, S), mx(Vg, T)
+    say(f"  sampled rows: U {eu:.2e} (max entry {mu:.2e}) V {ev:.2e} (max entry {mv:.2e})")
+    assert max(eu, ev, mu, mv) <= 1e-5
     # apply + backward in the benchmark's configuration, inputs supported on the samples
     xs = synth.rhs(2000, B, seed=2)
     gs = synth.rhs(2000, B, seed=3)
@@ -154,11 +162,12 @@ def test_benchmark_workload_full_size_matches_oracle():
     y_o = np.stack([S @ (Hs[b] @ (T.T @ xs[:, b])) for b in range(B)])
     dx_o = np.stack([T @ (Hs[b].T @ (S.T @ gs[:, b])) for b in range(B)])
     dth_o = np.array([[(S.T @ gs[:, b]) @ dHs[b][j] @ (T.T @ xs[:, b]) for j in range(dt)] for b in range(B)])
-    ey = rel(Yo[:, torch.tensor(si)].double().cpu().numpy(), y_o)
-    ex = rel(dX[:, torch.tensor(ti)].double().cpu().numpy(), dx_o)
-    et = rel(dth.double().cpu().numpy(), dth_o)
-    say(f"  apply {ey:.2e} dX {ex:.2e} dtheta {et:.2e}")
-    assert ey <= 2e-5 and ex <= 2e-5 and et <= 2e-5
+    yg = Yo[:, torch.tensor(si)].double().cpu().numpy()
+    xg = dX[:, torch.tensor(ti)].double().cpu().numpy()
+    tg = dth.double().cpu().numpy()
+    errs = [rel(yg, y_o), rel(xg, dx_o), rel(tg, dth_o), mx(yg, y_o), mx(xg, dx_o), mx(tg, dth_o)]
+    say("  apply, dX, dtheta: rel Frobenius %.2e %.2e %.2e, max entry %.2e %.2e %.2e" % tuple(errs))
+    assert max(errs) <= 1e-5
 
 
 def test_fp64_workload_full_size_matches_oracle():

@@ -2,10 +2,13 @@
 
 Both sides start from the same rounded cores (the oracle's), so the test
 isolates the Global-1 steps: QR of [U V], the PSD part of R Hhat R^T and the
-apply Q W Q^T x.  The factorisations differ (the oracle uses Householder QR,
-the GPU shifted Cholesky QR), so the comparison is made on what does not
-depend on the basis of range([U V]): the applied operator and the spectrum
-of W.  A full symmetric build (cross included) is checked the same way."""
+apply Q W Q^T x.  The two Householder QRs need not give the same basis of
+range([U V]) (their column signs and the treatment of its numerically
+rank-deficient directions differ), so the comparison is made on what does
+not depend on that basis: the applied operator and the spectrum of W.  Full
+symmetric builds (cross included, X = Y) are checked the same way, one of
+them with the general Matern kernel in (l, nu) against the free-running
+oracle's decisions."""
 import functools
 import sys
 
@@ -85,7 +88,7 @@ def oracle_apply(out, Q, R, P, ths, xs):
 
 
 @pytest.mark.parametrize("name,dtype,tol", [("matern32_d2", "f64", 1e-10), ("matern_d1", "f64", 1e-10),
-                                            ("matern32_d2", "f32", 2e-5), ("matern_d1", "f32", 2e-5)])
+                                            ("matern32_d2", "f32", 1e-5), ("matern_d1", "f32", 1e-5)])
 def test_global_qr_and_apply(name, dtype, tol):
     torch = _torch()
     say(f"[global] {name} {dtype}")
@@ -113,8 +116,9 @@ def test_global_qr_and_apply(name, dtype, tol):
     x_t = torch.tensor(xs, dtype=tdt, device="cuda")
     y_g = kern.global_apply(x_t, theta=th_t).double().cpu().numpy()
     e = rel(y_g, y_o)
-    say(f"  apply rel err {e:.2e}")
-    assert e <= tol
+    em = np.abs(y_g - y_o).max() / np.abs(y_o).max()
+    say(f"  apply rel err {e:.2e} (max entry {em:.2e})")
+    assert e <= tol and em <= tol
     Wg = kern.global_online(th_t)
     y_w = kern.global_apply(x_t, W=Wg).double().cpu().numpy()
     assert rel(y_w, y_g) <= (1e-14 if dtype == "f64" else 1e-6)
@@ -187,3 +191,72 @@ def test_global_argument_errors():
                                    dtype=torch.float64)
     with pytest.raises(TTKError, match="ERR_ARG"):
         kern.global_factors()
+
+
+def test_global_general_matern_build_matches_oracle():
+    """X = Y with the general Matern kernel in (l, nu) over the parameter box of
+    the 200k-point Global-1 workload, cross included (entries at r = 0, where
+    the kernel has its kink for nu near 1/2): every cross decision equals the
+    free-running oracle's, the ranks agree, and Q W Q^T x agrees with the
+    oracle's Global-1 apply.  Both sides stop at the same sweep cap: at n = 8
+    the interpolation does not resolve the kink, and the error against dense
+    K (reported) is the approximation's, identical on both sides."""
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    kind, d, bx, bth, n, tol, sweeps = "matern", 2, [[0, 1], [0, 1]], [[0.5, 2.0], [0.5, 2.5]], 8, 1e-6, 40
+    P = okernels.Problem(kind, d, bx, bx, bth, n)
+    X = np.random.default_rng(0).uniform(0, 1, (300, 2)).astype(np.float32).astype(np.float64)
+    say("[global] general Matern, X = Y, cross included")
+    out = odriver.offline(P, X, X, tol, seed=0, max_sweeps=sweeps)
+    Xt = torch.tensor(X)
+    kern = pkg.TTKernel.build_offline(Xt, None, kind, d, bx, bx, bth, n_spatial=n, n_param=n, tol=tol,
+                                      dtype=torch.float64, symmetric_psd=True, max_sweeps=sweeps, seed=0)
+    inf = kern.info()
+    L, R, log = kern.cross_record()
+    free = out["info"]
+    n_same = 0
+    for a, b in zip(free["log"], log):
+        if (a["sample_pos"], a["pivot_row"], a["pivot_col"], a["added"]) != \
+                (b["sample_pos"], b["pivot_row"], b["pivot_col"], b["added"]):
+            break
+        n_same += 1
+    say(f"  decisions identical: {n_same} of {len(log)} (oracle {len(free['log'])}); ranks {inf['ranks']}")
+    assert n_same == len(log) == len(free["log"])
+    for k in range(1, len(P.n)):
+        assert np.array_equal(free["L"][k], L[k]) and np.array_equal(free["R"][k], R[k]), k
+    assert inf["cross_ranks"] == free["ranks"] and inf["ranks"] == out["ranks"]
+    Q, Rq = opttk.global_offline(out["S"], out["T"])
+    ths = thetas(bth, 3, seed=11)
+    xs = np.random.default_rng(12).standard_normal((3, X.shape[0]))
+    y_o, W_o = oracle_apply(out, Q, Rq, P, ths, xs)
+    y_g = kern.global_apply(torch.tensor(xs, device="cuda"), theta=torch.tensor(ths, device="cuda"))
+    e = rel(y_g.cpu().numpy(), y_o)
+    say(f"  Q W Q^T x rel err {e:.2e}")
+    assert e <= 1e-9
+    K = odense.dense_K(kind, X, X, ths[0])
+    Wg = kern.global_online(torch.tensor(ths[:1], device="cuda")).cpu().numpy()[0]
+    Qg = kern.global_factors()[0].cpu().numpy()
+    err_g, err_o = rel(Qg @ Wg @ Qg.T, K), rel(Q @ W_o[0] @ Q.T, K)
+    say(f"  |QWQ^T - K|/|K| at theta {ths[0]}: gpu {err_g:.3e} oracle {err_o:.3e}")
+    assert abs(err_g - err_o) <= 1e-8 + 1e-6 * err_o
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.1, 2.5])
+def test_matern_bessel_at_small_argument(nu):
+    """The device's z^nu K_nu(z) (trapezoidal sum) at small z, where the sum
+    needs the most terms and K_nu is largest: general Matern entries at
+    distances 1e-4..1e-1 against the oracle (SciPy's kv), FP64."""
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    rng = np.random.default_rng(int(nu * 10))
+    X = rng.uniform(0, 1, (64, 3))
+    dirs = rng.standard_normal((64, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    Y = X + dirs * np.exp(rng.uniform(np.log(1e-4), np.log(1e-1), 64))[:, None]
+    for ell in (0.5, 2.0):
+        th = np.array([ell, nu])
+        Kg = pkg.eval_dense(torch.tensor(X), torch.tensor(Y), th, "matern", 3, dtype=torch.float64).cpu().numpy()
+        Ko = odense.dense_K("matern", X, Y, th)
+        err = np.abs(Kg - Ko).max() / np.abs(Ko).max()
+        say(f"[bessel] nu {nu} l {ell}: max rel err {err:.2e}")
+        assert err <= 1e-13
