@@ -267,6 +267,30 @@ tt_status tt_kernel_global_online(tt_kernel_t h, const void* theta, int B, void*
 tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W, int B,
                                  const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
 
+/* PTTK-Global-2: Algorithm 4 with Compress = true, for one theta.  The
+ * positive eigenpairs of R Hhat R^T (Hhat as for Global-1), in decreasing
+ * order of eigenvalue, are kept up to the smallest r_c whose discarded tail
+ * sqrt(sum_{i > r_c} lambda_i^2) is at most eps ||R Hhat R^T||_F (the
+ * Frobenius norm of the symmetric part of S H(theta) T^T, Q being
+ * orthonormal); then Z = Q Uhat (the O(N r^2) product of the Compress
+ * branch), so that K(X, X; theta) ~ Z diag(lambda) Z^T.
+ * theta: device, dtype, d_theta values (NULL if d_theta = 0).  Z_out:
+ * device, dtype, N x r_c row-major with leading dimension ldz >= r_s + r_t
+ * (the caller sizes it for the largest r_c, r_s + r_t).  lam_out: device,
+ * dtype, r_s + r_t values (the first r_c written).  *rc: host, r_c (0 if no
+ * eigenvalue is positive).  Synchronises `stream` (r_c is decided on the
+ * host).  TTK_ERR_ARG: not a Global handle, eps <= 0, a NULL output or
+ * ldz < r_s + r_t. */
+tt_status tt_kernel_global2_online(tt_kernel_t h, const void* theta, double eps, void* Z_out, int64_t ldz,
+                                   void* lam_out, int* rc, void* stream);
+
+/* Global-2 apply y_b = Z diag(lam) Z^T x_b for the (Z, lam, r_c) of
+ * tt_kernel_global2_online (one theta) and B right-hand sides.  Z: device,
+ * dtype, N x rc row-major (ldz >= rc); lam: device, dtype, rc.  X, Y:
+ * device, dtype, N x B column-major (ldx, ldy >= N).  rc = 0 gives Y = 0. */
+tt_status tt_kernel_global2_apply(tt_kernel_t h, const void* Z, int64_t ldz, const void* lam, int rc, int B,
+                                  const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
+
 /* Global-1 factors: *k = r_s + r_t (k may be NULL); Q_out: NULL or device,
  * dtype, N x k row-major; R_out: NULL or host FP64 k x k column-major
  * (synchronises `stream` when given). */

@@ -374,6 +374,41 @@ class TTKernel:
         check(lib.tt_kernel_global_online(self._h, _ptr(theta), B, _ptr(W), _stream_ptr(stream)))
         return W.transpose(1, 2)   # stored column-major
 
+    def global2_online(self, theta, eps, stream=None):
+        """PTTK-Global-2 for one theta (d_theta values): (Z (N, r_c), lam (r_c,))
+        with K(X, X; theta) ~ Z diag(lam) Z^T, Z = Q Uhat."""
+        lib = _lib.load()
+        if not eps > 0:
+            raise ValueError("eps must be positive")
+        k = ctypes.c_int()
+        check(lib.tt_kernel_global_factors(self._h, ctypes.byref(k), None, None, _stream_ptr(stream)))
+        k = k.value
+        th = None
+        if self.d_theta:
+            th = _theta(torch.as_tensor(theta, dtype=torch.float64).reshape(1, -1), self.d_theta, self.dtype, 1)
+        Z = torch.empty((self.n_src, k), dtype=self.dtype, device="cuda")
+        lam = torch.empty((k,), dtype=self.dtype, device="cuda")
+        rc = ctypes.c_int()
+        check(lib.tt_kernel_global2_online(self._h, _ptr(th), float(eps), _ptr(Z), k, _ptr(lam), ctypes.byref(rc),
+                                           _stream_ptr(stream)))
+        r = rc.value
+        return Z[:, :r], lam[:r]
+
+    def global2_apply(self, Z, lam, X, stream=None):
+        """y_b = Z diag(lam) Z^T x_b for rows x_b of X (B, N), (Z, lam) from global2_online."""
+        lib = _lib.load()
+        rc = int(lam.shape[0])
+        if Z.dim() != 2 or tuple(Z.shape) != (self.n_src, rc):
+            raise ValueError(f"Z: expected shape ({self.n_src}, {rc}), got {tuple(Z.shape)}")
+        B = _chk(X, "X", None, self.n_src).shape[0]
+        X = _dev(X, self.dtype)
+        Zc = Z.to(device="cuda", dtype=self.dtype).contiguous()
+        lc = lam.to(device="cuda", dtype=self.dtype).contiguous()
+        Y = torch.empty((B, self.n_src), dtype=self.dtype, device="cuda")
+        check(lib.tt_kernel_global2_apply(self._h, _ptr(Zc), max(rc, 1), _ptr(lc), rc, B, _ptr(X), self.n_src,
+                                          _ptr(Y), self.n_src, _stream_ptr(stream)))
+        return Y
+
     def global_apply(self, X, theta=None, W=None, stream=None):
         """y_b = Q W_b Q^T x_b for rows x_b of X (B, N); theta (B, d_theta) or W (B, k, k)."""
         if (theta is None) == (W is None):

@@ -225,6 +225,35 @@ __global__ void k_identity_batch(void* M, int r, int B, int fp32) {
   }
 }
 
+// out (k x rc, dtype, column-major) = U[:, :rc] (FP64, leading dimension k);
+// lam_out (rc, dtype) = lam[:rc].
+template <class T>
+__global__ void k_g2_convert(const double* U, int k, int rc, const double* lam, T* out, T* lam_out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)k * rc;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (T)U[e];
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < rc; i += blockDim.x) lam_out[i] = (T)lam[i];
+}
+
+// Z (N x rc row-major, leading dimension ldz) = Y (N x rc column-major, ld N).
+template <class T>
+__global__ void k_g2_rows(const T* Y, int64_t N, int rc, T* Z, int64_t ldz) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * rc; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / rc;
+    const int c = (int)(e - p * rc);
+    Z[p * ldz + c] = Y[p + (int64_t)c * N];
+  }
+}
+
+// W[i + b rc] *= lam[i]  (rc x B)
+template <class T>
+__global__ void k_g2_scale(T* W, const T* lam, int rc, int B) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)rc * B;
+       e += (int64_t)gridDim.x * blockDim.x)
+    W[e] *= lam[e % rc];
+}
+
 }  // namespace
 
 }  // namespace ttk
@@ -774,6 +803,81 @@ tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W
   TTK_TRY(reduce_into(h, h->Q.p, k, h->ns, k, X, ldx, B, h->Wbuf.p, st));        // Q^T x
   batched_matvec(h->dtype, W, k, k, 0, h->Wbuf.p, B, h->Zbuf.p, st);             // W (Q^T x)
   TTK_TRY(apply_expand(h->dtype, h->Q.p, k, h->ns, k, h->Zbuf.p, B, Y, ldy, st));          // Q (...)
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tt_kernel_global2_online(tt_kernel_t h, const void* theta, double eps, void* Z_out, int64_t ldz,
+                                   void* lam_out, int* rc, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
+  if (!(eps > 0.0)) return fail(TTK_ERR_ARG, "eps must be positive");
+  if (!Z_out || !lam_out || !rc) return fail(TTK_ERR_ARG, "Z_out, lam_out or rc is NULL");
+  const int k = h->kg;
+  if (ldz < k) return fail(TTK_ERR_ARG, "ldz (%lld) below r_s + r_t = %d", (long long)ldz, k);
+  if (h->g.dt > 0 && !theta) return fail(TTK_ERR_ARG, "theta is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TTK_TRY(h->M64.alloc((size_t)h->rs * h->rt * sizeof(double)));
+  if (h->g.dt == 0) {
+    hipLaunchKernelGGL(k_identity_batch, dim3(256), dim3(256), 0, st, h->M64.p, h->rs, 1, false);
+  } else {
+    TTK_TRY(h->work.alloc(online_work_doubles(h->pc, h->g.dt, 1) * sizeof(double)));
+    online_core_mixed(h->dtype, TTK_FP64, h->pc, h->g.dt, theta, 1, h->M64.p, nullptr, h->work.as<double>(), st);
+  }
+  TTK_TRY(h->Gwork.alloc(global2_work(h->rs, h->rt) * sizeof(double)));
+  double *Uh = nullptr, *lam = nullptr;
+  int r = 0;
+  TTK_TRY(global2_online(h->Rg.as<double>(), h->rs, h->rt, h->M64.as<double>(), eps, h->Gwork.as<double>(), &Uh,
+                         &lam, &r, st));
+  *rc = r;
+  if (r == 0) return TTK_OK;
+  // Z = Q Uhat: Q (N x k row-major) times Uhat[:, :rc] (k x rc), through the
+  // apply's expand (column-major N x rc), then to rows
+  const int64_t N = h->ns;
+  TTK_TRY(h->Zbuf.alloc((size_t)k * r * h->es));
+  TTK_TRY(h->Wbuf.alloc((size_t)std::max<int64_t>(N, 1) * r * h->es));
+  const unsigned g1 = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)k * r + 255) / 256));
+  if (h->dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_g2_convert<float>, dim3(g1), dim3(256), 0, st, (const double*)Uh, k, r, (const double*)lam,
+                       h->Zbuf.as<float>(), static_cast<float*>(lam_out));
+  else
+    hipLaunchKernelGGL(k_g2_convert<double>, dim3(g1), dim3(256), 0, st, (const double*)Uh, k, r,
+                       (const double*)lam, h->Zbuf.as<double>(), static_cast<double*>(lam_out));
+  TTK_TRY(apply_expand(h->dtype, h->Q.p, k, N, k, h->Zbuf.p, r, h->Wbuf.p, N, st));
+  const unsigned g2 = (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (N * r + 255) / 256));
+  if (h->dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_g2_rows<float>, dim3(g2), dim3(256), 0, st, (const float*)h->Wbuf.p, N, r,
+                       static_cast<float*>(Z_out), ldz);
+  else
+    hipLaunchKernelGGL(k_g2_rows<double>, dim3(g2), dim3(256), 0, st, (const double*)h->Wbuf.p, N, r,
+                       static_cast<double*>(Z_out), ldz);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tt_kernel_global2_apply(tt_kernel_t h, const void* Z, int64_t ldz, const void* lam, int rc, int B,
+                                  const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
+  if (B < 0 || rc < 0 || rc > h->kg) return fail(TTK_ERR_ARG, "bad B or rc");
+  if (B == 0) return TTK_OK;
+  if (!X || !Y || (rc > 0 && (!Z || !lam))) return fail(TTK_ERR_ARG, "NULL argument");
+  if (ldx < h->ns || ldy < h->ns || (rc > 0 && ldz < rc)) return fail(TTK_ERR_ARG, "leading dimension too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (rc == 0) {
+    for (int b = 0; b < B; ++b) fill_zero(static_cast<char*>(Y) + (size_t)b * ldy * h->es, (size_t)h->ns * h->es, st);
+    return TTK_OK;
+  }
+  TTK_TRY(h->Wbuf.alloc((size_t)rc * B * h->es));
+  TTK_TRY(reduce_into(h, Z, (int)ldz, h->ns, rc, X, ldx, B, h->Wbuf.p, st));   // Z^T x
+  const unsigned g = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, ((int64_t)rc * B + 255) / 256));
+  if (h->dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_g2_scale<float>, dim3(g), dim3(256), 0, st, h->Wbuf.as<float>(), static_cast<const float*>(lam),
+                       rc, B);
+  else
+    hipLaunchKernelGGL(k_g2_scale<double>, dim3(g), dim3(256), 0, st, h->Wbuf.as<double>(),
+                       static_cast<const double*>(lam), rc, B);
+  TTK_TRY(apply_expand(h->dtype, Z, (int)ldz, h->ns, rc, h->Wbuf.p, B, Y, ldy, st));   // Z (lam Z^T x)
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }

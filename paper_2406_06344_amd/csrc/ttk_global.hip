@@ -13,7 +13,17 @@
 // non-negative spectral part is formed as (Mh + |Mh|) / 2 with |Mh| = V Sigma
 // V^T from a one-sided Jacobi SVD Mh = U' Sigma V^T (for symmetric Mh the
 // right singular vectors are eigenvectors and Sigma = |Lambda|).
+//
+// PTTK-Global-2 (Algorithm 4 with Compress) keeps, for one theta, only the
+// leading positive eigenpairs (Uhat, Lambdahat) and returns Z = Q Uhat.  The
+// positive eigenpairs of Mh are the eigenpairs of the PSD matrix W_+ above
+// with non-zero eigenvalue, so they are taken from a second one-sided
+// Jacobi, on W_+: for a PSD matrix the left singular vectors are the
+// eigenvectors and Sigma = Lambda, already sorted, and a pair of eigenvalues
+// +-lambda of Mh (which a singular value decomposition of Mh itself cannot
+// separate) never meets in W_+.
 #include <cmath>
+#include <vector>
 
 #include "ttk_internal.h"
 
@@ -154,6 +164,50 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
     hipLaunchKernelGGL(k_psd_part<float>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<float*>(W));
   else
     hipLaunchKernelGGL(k_psd_part<double>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<double*>(W));
+}
+
+size_t global2_work(int rs, int rt) {
+  const size_t k = (size_t)rs + rt;
+  return global_online_work(rs, rt, 1) + 2 * k * k + jacobi_sigma_doubles((int)k) + 64;
+}
+
+tt_status global2_online(const double* R, int rs, int rt, const double* M, double eps, double* work, double** Uhat,
+                         double** lam, int* rc, hipStream_t st) {
+  const int k = rs + rt;
+  const size_t kk = (size_t)k * k;
+  double* gw = work;                                    // global_online's workspace (B = 1)
+  double* Wp = gw + global_online_work(rs, rt, 1);      // W_+ (k x k), FP64
+  double* J = Wp + kk;                                  // its Jacobi input, then the eigenvectors
+  double* sig = J + kk;                                 // eigenvalues, then the SVD workspace
+  global_online(R, rs, rt, M, 1, TTK_FP64, Wp, gw, st);
+  const double* Mh = gw + (size_t)k * rt;               // R Hhat R^T, symmetrised (global_online's layout)
+  double* nrm = sig + jacobi_sigma_doubles(k);          // ||Mh||_F
+  nrm2(Mh, (int64_t)kk, nrm, st);
+  TTK_HIP(hipMemcpyAsync(J, Wp, kk * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (!jacobi_svd_left(J, k, k, sig, st)) {   // (k above 256: the single-workgroup form, with V)
+    DBuf V;
+    TTK_TRY(V.alloc(kk * sizeof(double)));
+    jacobi_svd(J, k, k, V.as<double>(), k, sig, st);
+    TTK_HIP(hipStreamSynchronize(st));        // V is released on return
+  }
+  TTK_HIP(hipGetLastError());
+  std::vector<double> ev(k + 1);
+  TTK_HIP(hipMemcpyAsync(ev.data(), sig, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, st));
+  TTK_HIP(hipMemcpyAsync(ev.data() + k, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+  TTK_HIP(hipStreamSynchronize(st));
+  // the smallest r whose discarded tail sqrt(sum_{i > r} lambda_i^2) is within
+  // eps ||Mh||_F (eigenvalues already in decreasing order); k if none is
+  const double bound = eps * ev[k];
+  std::vector<double> tail(k + 1, 0.0);
+  for (int i = k - 1; i >= 0; --i) tail[i] = tail[i + 1] + ev[i] * ev[i];
+  int r = k;
+  for (int q = 1; q <= k; ++q)
+    if (std::sqrt(tail[q]) <= bound) { r = q; break; }
+  if (!(ev[0] > 0.0)) r = 0;   // no positive eigenvalue
+  *rc = r;
+  *Uhat = J;
+  *lam = sig;
+  return TTK_OK;
 }
 
 }  // namespace ttk

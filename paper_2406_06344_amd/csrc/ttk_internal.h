@@ -315,5 +315,14 @@ tt_status global_qr(int dtype, const void* U, int ldu, int rs, const void* V, in
 void global_online(const double* R, int rs, int rt, const double* M, int B, int out_dtype, void* W,
                    double* work, hipStream_t st);
 size_t global_online_work(int rs, int rt, int B);
+// Global-2 (Compress) for one theta, M (FP64 rs x rt): W_+ as above, its
+// eigenpairs by a one-sided Jacobi (decreasing eigenvalues), and the
+// truncation rank rc (the smallest r with sqrt(sum_{i > r} lambda_i^2) <=
+// eps ||Mh||_F; 0 when no eigenvalue is positive).  On return *Uhat (k x k,
+// column-major, inside work) holds the eigenvectors and *lam (inside work)
+// the eigenvalues.  work: global2_work(rs, rt) doubles.  Synchronises st.
+tt_status global2_online(const double* R, int rs, int rt, const double* M, double eps, double* work, double** Uhat,
+                         double** lam, int* rc, hipStream_t st);
+size_t global2_work(int rs, int rt);
 
 }  // namespace ttk

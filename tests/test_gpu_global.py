@@ -134,6 +134,40 @@ def test_global_qr_and_apply(name, dtype, tol):
         assert np.abs(lg[top] - lo[top]).max() <= (1e-9 if dtype == "f64" else 1e-5) * lo.max()
 
 
+@pytest.mark.parametrize("name,dtype,eps", [("matern32_d2", "f64", 1e-6), ("matern_d1", "f64", 1e-4),
+                                            ("matern32_d2", "f32", 1e-4), ("matern_d1", "f32", 1e-3)])
+def test_global2_matches_oracle(name, dtype, eps):
+    """PTTK-Global-2 (Algorithm 4, Compress): the truncation rank r_c, the kept
+    eigenvalues, and the operator Z diag(lam) Z^T (basis independent: the two
+    QRs need not share Q) against the oracle's global_online(compress=True)
+    on the same cores, for three thetas; Z has orthonormal columns; the
+    apply y = Z diag(lam) Z^T x equals the operator applied densely."""
+    torch = _torch()
+    say(f"[global2] {name} {dtype} eps {eps}")
+    kern, P, X, out, Q, R = gpu_sym(name, dtype)
+    rs = out["S"].shape[1]
+    f64 = dtype == "f64"
+    tdt = torch.float64 if f64 else torch.float32
+    xs = np.random.default_rng(14).standard_normal((2, X.shape[0]))
+    for th in thetas(P.box_theta, 3, seed=13):
+        H = opttk.online_H(out["param"], th, P.box_theta, P.n[P.d])
+        (Uo, lo), _ = opttk.global_online(R, H, rs, compress=True, eps=eps)
+        Z, lam = kern.global2_online(torch.tensor(th), eps)
+        Zn, ln = Z.double().cpu().numpy(), lam.double().cpu().numpy()
+        say(f"  theta {th}: r_c gpu {ln.size} oracle {lo.size}")
+        assert ln.size == lo.size
+        assert np.abs(ln - lo).max() <= (1e-10 if f64 else 1e-5) * lo.max()
+        assert np.abs(Zn.T @ Zn - np.eye(ln.size)).max() <= (1e-12 if f64 else 1e-5)
+        Zo = Q @ Uo
+        Ko = (Zo * lo) @ Zo.T
+        Kg = (Zn * ln) @ Zn.T
+        e = rel(Kg, Ko)
+        say(f"  operator rel err {e:.2e}")
+        assert e <= (1e-9 if f64 else 1e-5)
+        y = kern.global2_apply(Z, lam, torch.tensor(xs, dtype=tdt, device="cuda")).double().cpu().numpy()
+        assert rel(y, xs @ Kg) <= (1e-12 if f64 else 1e-5)
+
+
 def test_global_full_build_matches_oracle():
     """build_offline with symmetric_psd: cross, rounding, Phase 3 and QR on the GPU."""
     torch = _torch()
