@@ -267,6 +267,20 @@ tt_status tt_kernel_global_online(tt_kernel_t h, const void* theta, int B, void*
 tt_status tt_kernel_global_apply(tt_kernel_t h, const void* theta, const void* W, int B,
                                  const void* X, int64_t ldx, void* Y, int64_t ldy, void* stream);
 
+/* Phase 4 of Algorithm 2: TT-Round (Algorithm 1, tolerance eps) of the TT
+ * [T^(1)(S), G_{d+1}, ..., G_{d+d_theta}, T^(3)(T^T)] whose outer cores hold
+ * the factor matrices S = U and T = V of the points.  With S = Q_S R_S and
+ * T = Q_T R_T (tall-skinny QR, float64), rounding that TT is rounding the
+ * small TT [R_S, G_{d+1}, ..., R_T^T] and multiplying Q_S and Q_T back in,
+ * since Q_S and Q_T have orthonormal columns; the handle then holds the
+ * rounded U (N_s x r_s'), V (N_t x r_t') and parameter cores, and every
+ * online call and apply uses them.  The spatial cores no longer describe U
+ * and V afterwards: tt_kernel_factor_rows, tt_kernel_get_cores and
+ * tt_kernel_get_coeff_cores return TTK_ERR_UNSUPPORTED.  Synchronises
+ * `stream`.  TTK_ERR_ARG: eps <= 0 or a Global-1 handle;
+ * TTK_ERR_UNSUPPORTED: r_s or r_t above 128, or fewer points than columns. */
+tt_status tt_kernel_phase4_round(tt_kernel_t h, double eps, void* stream);
+
 /* PTTK-Global-2: Algorithm 4 with Compress = true, for one theta.  The
  * positive eigenpairs of R Hhat R^T (Hhat as for Global-1), in decreasing
  * order of eigenvalue, are kept up to the smallest r_c whose discarded tail

@@ -82,7 +82,7 @@ EXPORTS = [
     "tt_kernel_apply", "tt_kernel_apply_noalloc", "tt_kernel_project", "tt_kernel_apply_plain",
     "tt_kernel_apply_backward",
     "tt_kernel_global_online", "tt_kernel_global_apply", "tt_kernel_global_factors",
-    "tt_kernel_global2_online", "tt_kernel_global2_apply",
+    "tt_kernel_global2_online", "tt_kernel_global2_apply", "tt_kernel_phase4_round",
     "tt_kernel_batch_build", "tt_kernel_batch_configure", "tt_kernel_batch_factor", "tt_kernel_batch_get_info",
     "tt_kernel_batch_get_class", "tt_kernel_batch_get_factors", "tt_kernel_batch_apply", "tt_kernel_batch_destroy",
     "tt_kernel_eval_entries", "tt_kernel_eval_dense", "tt_kernel_get_info",
@@ -118,6 +118,7 @@ def load():
     lib.tt_kernel_global_factors.argtypes = [vp, P(c_int), vp, P(ctypes.c_double), vp]
     lib.tt_kernel_global2_online.argtypes = [vp, vp, ctypes.c_double, vp, i64, vp, P(c_int), vp]
     lib.tt_kernel_global2_apply.argtypes = [vp, vp, i64, vp, c_int, c_int, vp, i64, vp, i64, vp]
+    lib.tt_kernel_phase4_round.argtypes = [vp, ctypes.c_double, vp]
     lib.tt_kernel_batch_build.argtypes = [P(Params), P(Pair), c_int, vp, i64, vp, i64, vp, P(vp)]
     lib.tt_kernel_batch_configure.argtypes = [vp, c_int, c_int, c_int]
     lib.tt_kernel_batch_factor.argtypes = [vp, vp, vp, vp]

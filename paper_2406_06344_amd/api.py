@@ -374,6 +374,16 @@ class TTKernel:
         check(lib.tt_kernel_global_online(self._h, _ptr(theta), B, _ptr(W), _stream_ptr(stream)))
         return W.transpose(1, 2)   # stored column-major
 
+    def phase4_round(self, eps, stream=None):
+        """Phase 4 of Algorithm 2 in place: TT-Round of [S, parameter cores, T^T]
+        with tolerance eps; U, V and the parameter cores become the rounded ones."""
+        if not eps > 0:
+            raise ValueError("eps must be positive")
+        check(_lib.load().tt_kernel_phase4_round(self._h, float(eps), _stream_ptr(stream)))
+        inf = self.info()
+        self.r_s, self.r_t = inf["r_s"], inf["r_t"]
+        return self
+
     def global2_online(self, theta, eps, stream=None):
         """PTTK-Global-2 for one theta (d_theta values): (Z (N, r_c), lam (r_c,))
         with K(X, X; theta) ~ Z diag(lam) Z^T, Z = Q Uhat."""

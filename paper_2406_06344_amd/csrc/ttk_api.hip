@@ -246,6 +246,14 @@ __global__ void k_g2_rows(const T* Y, int64_t N, int rc, T* Z, int64_t ldz) {
   }
 }
 
+// B (n x m, ldb = n) = A^T for A (m x n, lda = m), FP64
+__global__ void k_transpose_small(const double* A, int m, int n, double* B) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m * n; e += gridDim.x * blockDim.x) {
+    const int i = e % m, j = e / m;
+    B[j + (size_t)i * n] = A[e];
+  }
+}
+
 // W[i + b rc] *= lam[i]  (rc x B)
 template <class T>
 __global__ void k_g2_scale(T* W, const T* lam, int rc, int B) {
@@ -282,10 +290,40 @@ struct tt_kernel {
   OnlineGemm og;
   ChainStage src[3], tgt[3];
   KSpec ks{};
+  // after Phase 4 (tt_kernel_phase4_round) U, V and the parameter cores are
+  // the rounded ones; the spatial cores no longer match them
+  bool phase4 = false;
 };
 
 static double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// The parameter cores in the coefficient basis (Algorithm 3 contracts them
+// with T_k(t(theta))) from the nodal ones in h->dcores, and for d_theta = 2 in
+// float32 the products C_{k1 k2} of the online core's matrix-core form.
+static tt_status prepare_param_cores(tt_kernel* h, hipStream_t st) {
+  const int d = h->g.d, dt = h->g.dt;
+  const int ns_ = h->P.n_spatial;
+  const double* Cp = h->dct.as<double>() + (size_t)ns_ * ns_;
+  for (int j = 0; j < dt; ++j) {
+    const int k = d + j;
+    const int r0 = h->ranks[k], n = h->g.n[k], r1 = h->ranks[k + 1];
+    const size_t cnt = (size_t)r0 * n * r1;
+    const unsigned nb = (unsigned)std::max<size_t>(1, std::min<size_t>((cnt + 255) / 256, 4096));
+    TTK_TRY(h->pcore[j].alloc(cnt * sizeof(double)));
+    hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, h->dcores[k].as<double>(), r0, n, r1, Cp, 2,
+                       h->pcore[j].as<double>());
+    h->pc[j] = ParamCore{h->pcore[j].as<double>(), r0, n, r1, h->g.lo[k], h->g.hi[k]};
+  }
+  if (dt == 2 && h->dtype == TTK_FP32) {
+    const size_t cnt = (size_t)h->pc[0].r0 * h->pc[1].r1 * h->pc[0].n * h->pc[1].n;
+    TTK_TRY(h->Cgemm.alloc(cnt * sizeof(float)));
+    TTK_TRY(online_gemm_prepare(h->pc, h->Cgemm.as<float>(), st));
+    h->og = OnlineGemm{h->Cgemm.as<float>(), h->pc[0].n * h->pc[1].n, h->pc[0].r0, h->pc[1].r1};
+  }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
 }
 
 // DCT the cores on the device, lay them out for Phase 3 and the online stage,
@@ -306,7 +344,6 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
   TTK_TRY(h->dct.alloc(C.size() * sizeof(double)));
   TTK_HIP(hipMemcpyAsync(h->dct.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, st));
   const double* Cs = h->dct.as<double>();
-  const double* Cp = Cs + (size_t)ns_ * ns_;
   ChainStage* src = h->src;
   ChainStage* tgt = h->tgt;
   for (int k = 0; k < D; ++k) {
@@ -330,20 +367,9 @@ static tt_status finish_build(tt_kernel* h, const void* X, const void* Y, hipStr
       else { cs.r_in = r1; cs.r_out = r0; cs.coord = k - d - dt; }
       cs.lo = h->g.lo[k];
       cs.hi = h->g.hi[k];
-    } else {
-      const int j = k - d;
-      TTK_TRY(h->pcore[j].alloc(cnt * sizeof(double)));
-      hipLaunchKernelGGL(k_dct_core<double>, dim3(nb), dim3(256), 0, st, gk, r0, n, r1, Cp, 2,
-                         h->pcore[j].as<double>());
-      h->pc[j] = ParamCore{h->pcore[j].as<double>(), r0, n, r1, h->g.lo[k], h->g.hi[k]};
     }
   }
-  if (dt == 2 && h->dtype == TTK_FP32) {
-    const size_t cnt = (size_t)h->pc[0].r0 * h->pc[1].r1 * h->pc[0].n * h->pc[1].n;
-    TTK_TRY(h->Cgemm.alloc(cnt * sizeof(float)));
-    TTK_TRY(online_gemm_prepare(h->pc, h->Cgemm.as<float>(), st));
-    h->og = OnlineGemm{h->Cgemm.as<float>(), h->pc[0].n * h->pc[1].n, h->pc[0].r0, h->pc[1].r1};
-  }
+  TTK_TRY(prepare_param_cores(h, st));
   TTK_HIP(hipStreamSynchronize(st));   // (Phase 3 is timed on its own below)
   h->rs = h->ranks[d];
   h->rt = h->ranks[d + dt];
@@ -600,6 +626,7 @@ tt_status tt_kernel_factor_rows(tt_kernel_t h, int side, const void* P, int64_t 
   if (side != 0 && side != 1) return fail(TTK_ERR_ARG, "side must be 0 (sources) or 1 (targets)");
   if (n < 0 || (n > 0 && (!P || !out))) return fail(TTK_ERR_ARG, "bad points or output");
   if (n == 0) return TTK_OK;
+  if (h->phase4) return fail(TTK_ERR_UNSUPPORTED, "after Phase 4 the spatial cores no longer give U and V");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int r = side == 0 ? h->rs : h->rt;
   return factor_contract(h->dtype, side == 0 ? h->src : h->tgt, h->g.d, P, n, out, r, st);
@@ -882,6 +909,88 @@ tt_status tt_kernel_global2_apply(tt_kernel_t h, const void* Z, int64_t ldz, con
   return TTK_OK;
 }
 
+tt_status tt_kernel_phase4_round(tt_kernel_t h, double eps, void* stream) {
+  if (!h) return fail(TTK_ERR_ARG, "NULL handle");
+  if (!(eps > 0.0)) return fail(TTK_ERR_ARG, "eps must be positive");
+  if (h->kg) return fail(TTK_ERR_ARG, "Phase 4 is for the U, V of the low-rank form, not a Global-1 handle");
+  const int d = h->g.d, dt = h->g.dt, rs = h->rs, rt = h->rt;
+  if (rs > 128 || rt > 128)
+    return fail(TTK_ERR_UNSUPPORTED, "Phase 4: ranks %d, %d above the tall-skinny QR's 128", rs, rt);
+  if (h->ns < rs || h->nt < rt)
+    return fail(TTK_ERR_UNSUPPORTED, "Phase 4 needs at least r_s sources and r_t targets");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto t0 = std::chrono::steady_clock::now();
+  // S = Q_S R_S, T = Q_T R_T (tall-skinny QR, float64)
+  TsqrState qs, qt;
+  DBuf Rs, Rt;
+  TTK_TRY(Rs.alloc((size_t)rs * rs * sizeof(double)));
+  TTK_TRY(Rt.alloc((size_t)rt * rt * sizeof(double)));
+  TTK_TRY(tsqr_factor(h->dtype, h->U.p, h->ldu, 1, h->ns, rs, &qs, Rs.as<double>(), rs, st));
+  TTK_TRY(tsqr_factor(h->dtype, h->V.p, h->ldv, 1, h->nt, rt, &qt, Rt.as<double>(), rt, st));
+  // the small TT [R_S, G_{d+1}, ..., G_{d+d_theta}, R_T^T]: the TT of Phase 4
+  // with its first and last cores' point index replaced by the columns of
+  // Q_S and Q_T (orthonormal, so TT-Round of either is the same rounding)
+  const int D2 = dt + 2;
+  std::vector<DBuf> sc(D2);
+  std::vector<int> sr(D2 + 1);
+  sr[0] = 1;
+  sr[1] = rs;
+  for (int j = 0; j < dt; ++j) sr[2 + j] = h->ranks[d + j + 1];
+  sr[D2] = 1;
+  Grid g2 = h->g;
+  g2.d = 1;
+  g2.dt = dt;
+  g2.D = D2;
+  g2.n[0] = rs;
+  for (int j = 0; j < dt; ++j) g2.n[1 + j] = h->g.n[d + j];
+  g2.n[D2 - 1] = rt;
+  TTK_TRY(sc[0].alloc((size_t)rs * rs * sizeof(double)));
+  TTK_HIP(hipMemcpyAsync(sc[0].p, Rs.p, (size_t)rs * rs * sizeof(double), hipMemcpyDeviceToDevice, st));
+  for (int j = 0; j < dt; ++j) {
+    const size_t cnt = (size_t)h->ranks[d + j] * h->g.n[d + j] * h->ranks[d + j + 1];
+    TTK_TRY(sc[1 + j].alloc(cnt * sizeof(double)));
+    TTK_HIP(hipMemcpyAsync(sc[1 + j].p, h->dcores[d + j].p, cnt * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  TTK_TRY(sc[D2 - 1].alloc((size_t)rt * rt * sizeof(double)));   // (a, b) = R_T(b, a)
+  hipLaunchKernelGGL(k_transpose_small, dim3((rt * rt + 255) / 256), dim3(256), 0, st, (const double*)Rt.as<double>(),
+                     rt, rt, sc[D2 - 1].as<double>());
+  TTK_HIP(hipGetLastError());
+  TTK_TRY(round_gauge(sc, sr, g2, eps, st));
+  const int rs2 = sr[1], rt2 = sr[D2 - 1];
+  // U' = Q_S A_S (A_S = the first core, rs x rs2) and V' = Q_T A_T^T (the last
+  // core, rt2 x rt)
+  const int ldu2 = h->dtype == TTK_FP32 ? mfma_ld(rs2) : rs2;
+  const int ldv2 = h->dtype == TTK_FP32 ? mfma_ld(rt2) : rt2;
+  DBuf U2, V2, CT;
+  TTK_TRY(U2.alloc((size_t)std::max<int64_t>(h->ns, 1) * ldu2 * h->es));
+  TTK_TRY(V2.alloc((size_t)std::max<int64_t>(h->nt, 1) * ldv2 * h->es));
+  TTK_TRY(CT.alloc((size_t)rt * rt2 * sizeof(double)));
+  if (ldu2 > rs2) fill_zero(U2.p, (size_t)std::max<int64_t>(h->ns, 1) * ldu2 * h->es, st);
+  if (ldv2 > rt2) fill_zero(V2.p, (size_t)std::max<int64_t>(h->nt, 1) * ldv2 * h->es, st);
+  TTK_TRY(tsqr_apply(&qs, sc[0].as<double>(), rs, rs2, h->dtype, U2.p, ldu2, 1, st));
+  hipLaunchKernelGGL(k_transpose_small, dim3((rt * rt2 + 255) / 256), dim3(256), 0, st,
+                     (const double*)sc[D2 - 1].as<double>(), rt2, rt, CT.as<double>());
+  TTK_TRY(tsqr_apply(&qt, CT.as<double>(), rt, rt2, h->dtype, V2.p, ldv2, 1, st));
+  // the handle takes the rounded parameter cores, U' and V'
+  for (int j = 0; j < dt; ++j) h->dcores[d + j] = std::move(sc[1 + j]);
+  for (int j = 0; j <= dt; ++j) h->ranks[d + j] = sr[1 + j];
+  TTK_TRY(prepare_param_cores(h, st));
+  TTK_HIP(hipStreamSynchronize(st));   // the old U, V, cores and the QR state are released below
+  h->U = std::move(U2);
+  h->V = std::move(V2);
+  h->rs = rs2;
+  h->rt = rt2;
+  h->ldu = ldu2;
+  h->ldv = ldv2;
+  h->phase4 = true;
+  h->cores.clear();
+  h->info.r_s = rs2;
+  h->info.r_t = rt2;
+  for (int k = 0; k <= h->g.D && k < 9; ++k) h->info.ranks[k] = h->ranks[k];
+  h->info.t_factor_ms += ms_since(t0);
+  return TTK_OK;
+}
+
 tt_status tt_kernel_global_factors(tt_kernel_t h, int* k, void* Q_out, double* R_out, void* stream) {
   if (!h) return fail(TTK_ERR_ARG, "NULL handle");
   if (!h->kg) return fail(TTK_ERR_ARG, "handle was not built with symmetric_psd");
@@ -953,6 +1062,7 @@ tt_status tt_kernel_get_factors(tt_kernel_t h, void* U_out, void* V_out, void* s
 
 tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity) {
   if (!h || !cores) return fail(TTK_ERR_ARG, "NULL argument");
+  if (h->phase4) return fail(TTK_ERR_UNSUPPORTED, "after Phase 4 the cores are U, the parameter cores and V");
   const int D = h->g.D;
   if (h->cores.size() != (size_t)D) {   // a device build: read the rounded cores back once
     h->cores.assign(D, {});
@@ -975,6 +1085,7 @@ tt_status tt_kernel_get_cores(tt_kernel_t h, double* cores, int64_t capacity) {
 
 tt_status tt_kernel_get_coeff_cores(tt_kernel_t h, double* cores, int64_t capacity) {
   if (!h || !cores) return fail(TTK_ERR_ARG, "NULL argument");
+  if (h->phase4) return fail(TTK_ERR_UNSUPPORTED, "after Phase 4 the cores are U, the parameter cores and V");
   const int d = h->g.d, dt = h->g.dt, D = h->g.D;
   size_t need = 0;
   for (int k = 0; k < D; ++k) need += (size_t)h->ranks[k] * h->g.n[k] * h->ranks[k + 1];

@@ -153,6 +153,24 @@ tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double
 // C (m x nc, ldc) <- Q C with the Q of a qr_factor of A (m x n) and its work.
 tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, double* C, int nc, int ldc,
                      hipStream_t st);
+// Tall-skinny QR of an N x r matrix (r <= 128, N >= r): A(p, c) at
+// A[p sp + c sc] in dtype.  tsqr_factor writes R (r x r upper, FP64, device,
+// leading dimension ldr) and keeps the blocks' reflectors in *ts;
+// tsqr_apply writes Q [C; 0] (N x c, c <= 128; C FP64 r x c on the device,
+// leading dimension ldc) to Y(p, j) = Y[p sp + j sc] in out_dtype.
+constexpr int TSQR_MAXLEV = 16;
+struct TsqrState {
+  int r = 0, nlev = 0;
+  int64_t N = 0;
+  int nb[TSQR_MAXLEV] = {0};
+  int64_t rows[TSQR_MAXLEV] = {0};
+  DBuf A[TSQR_MAXLEV], tau[TSQR_MAXLEV], T[TSQR_MAXLEV];
+  DBuf V, D[2];
+};
+tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,
+                      int ldr, hipStream_t st);
+tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dtype, void* Y, int64_t sp, int64_t sc,
+                     hipStream_t st);
 // One-sided Jacobi SVD of A (n x n, lda): A <- U Sigma (columns), V (n x n),
 // sigma (n); columns sorted by decreasing sigma.
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);

@@ -500,7 +500,9 @@ __global__ void __launch_bounds__(BS) k_qr_panel(double* A, int m, int jb, int l
 }
 
 // V (m x jb, explicit): unit diagonal, reflectors below, zeros above.
-__global__ void k_build_v(const double* A, int m, int jb, int lda, double* V) {
+__global__ void k_build_v(const double* A, int m, int jb, int lda, double* V, size_t sA, size_t sV) {
+  A += blockIdx.y * sA;
+  V += blockIdx.y * sV;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)m * jb) return;
   const int i = (int)(e % m), q = (int)(e / m);
@@ -553,9 +555,15 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
 // Writes the reflectors below the diagonal of the panel (unit diagonal
 // implicit), R on and above it, tau, V explicit (mm x jb) and T (jb x jb).
 constexpr int PB = 256;
+// Batched (TSQR): blockIdx.y picks the matrix; A, tau, V and T are offset by
+// their strides (0 for a single matrix).
 template <int RPT, int PBT>
 __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V,
-                                                     double* T) {
+                                                     double* T, size_t sA, size_t sTau, size_t sV, size_t sT) {
+  A += blockIdx.y * sA;
+  tau += blockIdx.y * sTau;
+  V += blockIdx.y * sV;
+  T += blockIdx.y * sT;
   constexpr int NB = 16, S = PBT / NB;   // S strips per column in the first reduction stage
   // block sums through LDS: every thread's partials in P (conflict-free
   // columns), then S partial sums per column in Q, then the final sums
@@ -680,15 +688,18 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
 // Above 4 PB rows the panel takes 2 PB threads, four rows each (eight rows of
 // sixteen columns overflow the registers); below, PB threads are faster (the
 // block reductions dominate).
-bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, double* T, hipStream_t st) {
+bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, double* T, hipStream_t st,
+                  int batch = 1, size_t sA = 0, size_t sTau = 0, size_t sV = 0, size_t sT = 0) {
+  const dim3 g(1, batch);
   if (mm <= PB)
-    hipLaunchKernelGGL((k_qr_panel_reg<1, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<1, PB>), g, dim3(PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV, sT);
   else if (mm <= 2 * PB)
-    hipLaunchKernelGGL((k_qr_panel_reg<2, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<2, PB>), g, dim3(PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV, sT);
   else if (mm <= 4 * PB)
-    hipLaunchKernelGGL((k_qr_panel_reg<4, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<4, PB>), g, dim3(PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV, sT);
   else if (mm <= 8 * PB)
-    hipLaunchKernelGGL((k_qr_panel_reg<4, 2 * PB>), dim3(1), dim3(2 * PB), 0, st, A, mm, jb, lda, tau, V, T);
+    hipLaunchKernelGGL((k_qr_panel_reg<4, 2 * PB>), g, dim3(2 * PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV,
+                       sT);
   else
     return false;
   return true;
@@ -704,9 +715,14 @@ typedef double qdbl4 __attribute__((ext_vector_type(4)));
 // sixteen waves, eight steps of loads in flight), W2 = op(T) W in LDS, and
 // C -= V W2 by 16-row tiles (A at [l % 16][l / 16], B at [l / 16][l % 16],
 // D row l / 16 + 4 v, column l % 16 in lane l, slot v).
+// Batched (TSQR): blockIdx.y picks the matrix, V, T and C offset by their
+// strides (0 for one matrix).
 constexpr int QAW = 16;   // waves of k_qr_apply
 __global__ void __launch_bounds__(QAW * 64) k_qr_apply(const double* V, int mm, int jb, const double* T, int trans,
-                                                        double* C, int nc, int lda) {
+                                                        double* C, int nc, int lda, size_t sV, size_t sT, size_t sC) {
+  V += blockIdx.y * sV;
+  T += blockIdx.y * sT;
+  C += blockIdx.y * sC;
   constexpr int SBQ = 8;
   __shared__ double Wp[QAW][16][17], W2[16][17];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -890,7 +906,8 @@ void qr_apply(const double* V, int mm, int jb, const double* T, int trans, doubl
               hipStream_t st) {
   const int tiles = (nc + 15) / 16;
   if (mm <= 4 * QRC) {
-    hipLaunchKernelGGL(k_qr_apply, dim3(tiles), dim3(QAW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda);
+    hipLaunchKernelGGL(k_qr_apply, dim3(tiles), dim3(QAW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda, (size_t)0,
+                       (size_t)0, (size_t)0);
     return;
   }
   const int nch = (mm + QRC - 1) / QRC;
@@ -1576,7 +1593,7 @@ tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double
     if (!qr_panel_reg(Ap, mm, jb, lda, w.tau + j0, w.V, T, st)) {
       hipLaunchKernelGGL(k_qr_panel, dim3(1), dim3(BS), 0, st, Ap, mm, jb, lda, w.tau + j0);
       hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
-                         lda, w.V);
+                         lda, w.V, (size_t)0, (size_t)0);
       hipLaunchKernelGGL(k_larft, dim3(1), dim3(BS), 0, st, w.V, mm, jb, w.tau + j0, T);
     }
     const int nc = n - j0 - jb;
@@ -1605,7 +1622,7 @@ tt_status qr_blocked(double* A, int m, int n, int lda, double* R, int ldr, doubl
     const int nc = n - j0 - jb;
     if (nc > 0) {
       hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st, Ap, mm, jb,
-                         lda, w.V);
+                         lda, w.V, (size_t)0, (size_t)0);
       double* Q2 = A + j0 + (size_t)(j0 + jb) * lda;
       // Q2 <- (I - V T V^T) Q2
       qr_apply(w.V, mm, jb, T, 0, Q2, nc, lda, w.Wp, st);
@@ -1631,9 +1648,215 @@ tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, doubl
     const int j0 = p * NB, jb = std::min(NB, n - j0);
     const int mm = m - j0;
     hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256)), dim3(256), 0, st,
-                       A + j0 + (size_t)j0 * lda, mm, jb, lda, w.V);
+                       A + j0 + (size_t)j0 * lda, mm, jb, lda, w.V, (size_t)0, (size_t)0);
     qr_apply(w.V, mm, jb, w.Tall + (size_t)p * NB * NB, 0, C + j0, nc, ldc, w.Wp, st);
   }
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+// ------------------------------------------------------------------ TSQR
+namespace {
+
+// Tall-skinny QR (Demmel, Grigori, Hoemmen & Langou, SIAM J. Sci. Comput.
+// 2012) for N x r matrices with r <= 128: the rows are cut into blocks of
+// TSQR_H, every block is factored by the blocked Householder QR above (one
+// batched launch per panel: the register panel and the trailing update with
+// blockIdx.y = block), the blocks' R factors are stacked and cut again, until
+// one block is left; its R is the R of the whole matrix.  Q is never formed:
+// Q [C; 0] is applied top-down, each level's reflectors (batched again) to
+// the rows the level above hands down.  Each block's factorisation is
+// Householder, so Q is orthonormal to working precision whatever the
+// conditioning (a Gram-matrix route would square it).
+constexpr int TSQR_H = 512;   // rows per block: >= r, and one k_qr_apply per update (mm <= 4 QRC)
+constexpr int TSQR_TR = 32;   // rows per tile of the strided copies
+
+// Level 0: the blocks Ab[b H r + i + c H] = A(g, c) for g = b H + i < N (A(g, c)
+// at A[g sp + c sc]), 0 past N.  A tile of TSQR_TR rows x r columns goes through
+// LDS so both sides are read and written along their contiguous direction.
+template <class T>
+__global__ void __launch_bounds__(256) k_tsqr_load(const T* A, int64_t sp, int64_t sc, int64_t N, int r,
+                                                   double* Ab) {
+  __shared__ double t[TSQR_TR][129];
+  const int64_t g0 = (int64_t)blockIdx.x * TSQR_TR;
+  for (int e = threadIdx.x; e < TSQR_TR * r; e += 256) {
+    const int i = e / r, c = e - i * r;
+    const int64_t g = g0 + i;
+    t[i][c] = g < N ? (double)A[g * sp + c * sc] : 0.0;
+  }
+  __syncthreads();
+  const int64_t b = g0 / TSQR_H;
+  const int i0 = (int)(g0 - b * TSQR_H);
+  double* out = Ab + b * TSQR_H * r;
+  for (int e = threadIdx.x; e < TSQR_TR * r; e += 256) {
+    const int c = e / TSQR_TR, i = e - c * TSQR_TR;
+    out[i0 + i + (int64_t)c * TSQR_H] = t[i][c];
+  }
+}
+
+// The output Y(p, j) = D0[p / H][p % H + j H] (p < N, j < c), to Y[p sp + j sc].
+template <class T>
+__global__ void __launch_bounds__(256) k_tsqr_store(const double* D, int64_t N, int c, T* Y, int64_t sp, int64_t sc) {
+  __shared__ double t[TSQR_TR][129];
+  const int64_t g0 = (int64_t)blockIdx.x * TSQR_TR;
+  const int64_t b = g0 / TSQR_H;
+  const int i0 = (int)(g0 - b * TSQR_H);
+  const double* in = D + b * TSQR_H * c;
+  for (int e = threadIdx.x; e < TSQR_TR * c; e += 256) {
+    const int j = e / TSQR_TR, i = e - j * TSQR_TR;
+    t[i][j] = in[i0 + i + (int64_t)j * TSQR_H];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TSQR_TR * c; e += 256) {
+    const int i = e / c, j = e - i * c;
+    const int64_t g = g0 + i;
+    if (g < N) Y[g * sp + j * sc] = (T)t[i][j];
+  }
+}
+
+// Level l + 1 from level l: the stacked R factors (block b's R as rows
+// b r .. b r + r - 1), cut into blocks of H rows, zero past `rows`.
+__global__ void k_tsqr_stack(const double* Al, int r, int64_t rows, int nbn, double* An) {
+  const int64_t total = (int64_t)nbn * TSQR_H * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bn = e / ((int64_t)TSQR_H * r);
+    const int64_t rem = e - bn * TSQR_H * r;
+    const int c = (int)(rem / TSQR_H), i = (int)(rem % TSQR_H);
+    const int64_t g = bn * TSQR_H + i;
+    double v = 0.0;
+    if (g < rows) {
+      const int64_t b = g / r;
+      const int ii = (int)(g - b * r);
+      if (ii <= c) v = Al[b * TSQR_H * r + ii + (int64_t)c * TSQR_H];
+    }
+    An[e] = v;
+  }
+}
+
+// Level l - 1's input from level l's result: block b gets rows b r .. b r + r - 1
+// of the level above (which lie in its blocks of H rows), then zeros.
+__global__ void k_tsqr_down(const double* Du, int c, int nb, int r, double* Dl) {
+  const int64_t total = (int64_t)nb * TSQR_H * c;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / ((int64_t)TSQR_H * c);
+    const int64_t rem = e - b * TSQR_H * c;
+    const int j = (int)(rem / TSQR_H), i = (int)(rem % TSQR_H);
+    double v = 0.0;
+    if (i < r) {
+      const int64_t g = b * r + i;
+      v = Du[(g / TSQR_H) * TSQR_H * c + (g % TSQR_H) + (int64_t)j * TSQR_H];
+    }
+    Dl[e] = v;
+  }
+}
+
+// The top level's input [C; 0] (one block of H x c; C r x c, leading dimension ldc).
+__global__ void k_tsqr_top(const double* C, int ldc, int r, int c, double* D) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < TSQR_H * c; e += gridDim.x * blockDim.x) {
+    const int j = e / TSQR_H, i = e % TSQR_H;
+    D[e] = i < r ? C[i + (size_t)j * ldc] : 0.0;
+  }
+}
+
+inline unsigned tsqr_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
+
+}  // namespace
+
+tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,
+                      int ldr, hipStream_t st) {
+  constexpr int H = TSQR_H, NB = 16;
+  if (r < 1 || r > 128) return fail(TTK_ERR_UNSUPPORTED, "tsqr: r = %d outside 1..128", r);
+  if (N < r) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %lld rows for %d columns", (long long)N, r);
+  ts->r = r;
+  ts->N = N;
+  const int npan = (r + NB - 1) / NB;
+  int64_t rows = N;
+  int l = 0;
+  for (;; ++l) {
+    if (l >= TSQR_MAXLEV) return fail(TTK_ERR_UNSUPPORTED, "tsqr: too many levels");
+    const int64_t nb64 = (rows + H - 1) / H;
+    if (nb64 > 65535) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %lld row blocks (at most 65535)", (long long)nb64);
+    const int nb = (int)nb64;
+    ts->nb[l] = nb;
+    ts->rows[l] = rows;
+    TTK_TRY(ts->A[l].alloc((size_t)nb * H * r * sizeof(double)));
+    TTK_TRY(ts->tau[l].alloc((size_t)nb * r * sizeof(double)));
+    TTK_TRY(ts->T[l].alloc((size_t)nb * npan * NB * NB * sizeof(double)));
+    double* Al = ts->A[l].as<double>();
+    if (l == 0) {
+      const unsigned g = (unsigned)((N + TSQR_TR - 1) / TSQR_TR);
+      // blocks past N (the last one's tail) are zero: clear them first
+      fill_zero(Al, (size_t)nb * H * r * sizeof(double), st);
+      if (dtype == TTK_FP32)
+        hipLaunchKernelGGL(k_tsqr_load<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(A), sp, sc, N, r,
+                           Al);
+      else
+        hipLaunchKernelGGL(k_tsqr_load<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(A), sp, sc, N,
+                           r, Al);
+    } else {
+      hipLaunchKernelGGL(k_tsqr_stack, dim3(tsqr_grid((int64_t)nb * H * r)), dim3(256), 0, st,
+                         (const double*)ts->A[l - 1].as<double>(), r, rows, nb, Al);
+    }
+    TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
+    double* V = ts->V.as<double>();
+    double* tau = ts->tau[l].as<double>();
+    double* T = ts->T[l].as<double>();
+    for (int p = 0; p < npan; ++p) {
+      const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
+      if (!qr_panel_reg(Al + j0 + (size_t)j0 * H, mm, jb, H, tau + j0, V, T + (size_t)p * NB * NB, st, nb,
+                        (size_t)H * r, (size_t)r, (size_t)H * NB, (size_t)npan * NB * NB))
+        return fail(TTK_ERR_UNSUPPORTED, "tsqr: panel of %d rows", mm);
+      const int nc = r - j0 - jb;
+      if (nc > 0)
+        hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16, nb), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
+                           (const double*)(T + (size_t)p * NB * NB), 1, Al + j0 + (size_t)(j0 + jb) * H, nc, H,
+                           (size_t)H * NB, (size_t)npan * NB * NB, (size_t)H * r);
+    }
+    if (nb == 1) break;
+    rows = (int64_t)nb * r;
+  }
+  ts->nlev = l + 1;
+  hipLaunchKernelGGL(k_extract_r, dim3((r * r + 255) / 256), dim3(256), 0, st,
+                     (const double*)ts->A[l].as<double>(), r, H, R, ldr);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
+tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dtype, void* Y, int64_t sp, int64_t sc,
+                     hipStream_t st) {
+  constexpr int H = TSQR_H, NB = 16;
+  if (c < 1 || c > 128) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %d columns to apply Q to (1..128)", c);
+  const int r = ts->r, npan = (r + NB - 1) / NB;
+  DBuf* D = ts->D;
+  for (int l = ts->nlev - 1; l >= 0; --l) {
+    const int nb = ts->nb[l];
+    DBuf& Dl = D[l & 1];
+    TTK_TRY(Dl.alloc((size_t)nb * H * c * sizeof(double)));
+    if (l == ts->nlev - 1)
+      hipLaunchKernelGGL(k_tsqr_top, dim3(tsqr_grid((int64_t)H * c)), dim3(256), 0, st, C, ldc, r, c, Dl.as<double>());
+    else
+      hipLaunchKernelGGL(k_tsqr_down, dim3(tsqr_grid((int64_t)nb * H * c)), dim3(256), 0, st,
+                         (const double*)D[(l + 1) & 1].as<double>(), c, nb, r, Dl.as<double>());
+    TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
+    double* V = ts->V.as<double>();
+    const double* Al = ts->A[l].as<double>();
+    const double* T = ts->T[l].as<double>();
+    for (int p = npan - 1; p >= 0; --p) {   // Q [C; 0] = H_0 (H_1 (... [C; 0])), panels last to first
+      const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
+      hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256), nb), dim3(256), 0, st,
+                         Al + j0 + (size_t)j0 * H, mm, jb, H, V, (size_t)H * r, (size_t)H * NB);
+      hipLaunchKernelGGL(k_qr_apply, dim3((c + 15) / 16, nb), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
+                         T + (size_t)p * NB * NB, 0, Dl.as<double>() + j0, c, H, (size_t)H * NB,
+                         (size_t)npan * NB * NB, (size_t)H * c);
+    }
+  }
+  const unsigned g = (unsigned)((ts->N + TSQR_TR - 1) / TSQR_TR);
+  if (out_dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_tsqr_store<float>, dim3(g), dim3(256), 0, st, (const double*)D[0].as<double>(), ts->N, c,
+                       static_cast<float*>(Y), sp, sc);
+  else
+    hipLaunchKernelGGL(k_tsqr_store<double>, dim3(g), dim3(256), 0, st, (const double*)D[0].as<double>(), ts->N, c,
+                       static_cast<double*>(Y), sp, sc);
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
