@@ -400,6 +400,62 @@ tt_status tt_kernel_batch_apply(tt_kernel_batch_t b, const void* theta, int B, c
 
 tt_status tt_kernel_batch_destroy(tt_kernel_batch_t b);
 
+/* ------------------------------------------------------------------------
+ * A parametric hierarchical matrix for K(X, X; theta) (Section 1: the
+ * admissible blocks of fast multipole and hierarchical-matrix methods are the
+ * separated boxes the method targets; the Conclusions name hierarchical
+ * parametric approximations).  The root box (box_s of the parameters) is
+ * refined uniformly to the leaf level L, the smallest level with at most
+ * leaf_points points per leaf on average (L d <= 30).  At every level k >= 2
+ * a cell's far blocks are its interaction list: the cells whose parents are
+ * neighbours of its parent (or the parent itself) but which are not its own
+ * neighbours (max_j |i_j - i'_j| >= 2).  Every far block is a pair of the
+ * pair batch above (one TT per geometry class, Phase 3 for all pairs in one
+ * launch, the apply as one captured graph); the blocks between neighbouring
+ * leaves (a leaf with itself included) are summed directly on the device in
+ * double precision.  Points are sorted by the Morton code of their leaf, so
+ * every cell is one contiguous range of the sorted points.  Kernels that are
+ * unbounded at r = 0 (Laplace 2-D/3-D, biharmonic, thin-plate) leave the
+ * self terms i = j out. */
+typedef struct tt_kernel_hmat* tt_kernel_hmat_t;
+
+typedef struct {
+  int levels;               /* leaf level L                                           */
+  int num_classes;          /* TT builds (geometry classes) of the far blocks          */
+  int64_t leaves, nonempty_leaves;
+  int64_t far_pairs;        /* far blocks (interaction-list pairs over all levels)     */
+  int64_t near_pairs;       /* (leaf, neighbouring leaf) blocks summed directly        */
+  int64_t kernel_evals;     /* device kernel evaluations of the class builds           */
+  double t_tree_ms, t_build_ms;
+} tt_kernel_hmat_info;
+
+/* p: kernel, grid sizes, tolerance, dtype; box_s = the root box (box_t is
+ * ignored).  X: device, dtype, SoA d x N, inside the root box.  Synchronises
+ * `stream`.  TTK_ERR_ARG: no points, leaf_points < 1, an empty root box or a
+ * parameter error of the pair batch. */
+tt_status tt_kernel_hmat_build(const tt_kernel_params* p, const void* X, int64_t N, int leaf_points, void* stream,
+                               tt_kernel_hmat_t* out);
+
+/* Y[:, b] = H(theta_b) X[:, b] for b = 0..B-1: theta device, dtype,
+ * B x d_theta; X, Y device, dtype, N x B column-major (ldx, ldy >= N), in the
+ * order of the points given to the build. */
+tt_status tt_kernel_hmat_apply(tt_kernel_hmat_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
+                               int64_t ldy, void* stream);
+
+tt_status tt_kernel_hmat_get_info(tt_kernel_hmat_t h, tt_kernel_hmat_info* info);
+
+/* Host outputs, each NULL or sized from the info: far, 7 ints per far block
+ * (level, source cell i_0 i_1 i_2, target cell i_0 i_1 i_2, unused
+ * coordinates 0); near, 6 ints per near block (the two leaves); perm, N ints
+ * (sorted position -> index of the point as given). */
+tt_status tt_kernel_hmat_get_lists(tt_kernel_hmat_t h, int32_t* far, int32_t* near, int32_t* perm);
+
+/* The pair batch of the far blocks (owned by the hierarchical matrix; NULL
+ * when there is no far block). */
+tt_status tt_kernel_hmat_get_batch(tt_kernel_hmat_t h, tt_kernel_batch_t* b);
+
+tt_status tt_kernel_hmat_destroy(tt_kernel_hmat_t h);
+
 /* f_kappa at P grid multi-indices (Section 2.4, entries of the grid tensor),
  * in double precision on the device.  idx: device int32, P x D row-major,
  * 0-based node indices in the (x, theta, y) order.  out: device double, P. */

@@ -5,4 +5,4 @@ low-rank method (Khan & Saibaba, arXiv 2406.06344).
 The work runs in libttk.so (HIP kernels behind the C ABI of
 include/tt_kernel.h); this package only marshals arguments.
 """
-from .api import TTBatch, TTKernel, eval_dense, eval_entries, kernel_apply, make_params  # noqa: F401
+from .api import HMatrix, TTBatch, TTKernel, eval_dense, eval_entries, kernel_apply, make_params  # noqa: F401

@@ -77,6 +77,14 @@ class BatchInfo(ctypes.Structure):
     ]
 
 
+class HmatInfo(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int), ("num_classes", ctypes.c_int), ("leaves", ctypes.c_int64),
+        ("nonempty_leaves", ctypes.c_int64), ("far_pairs", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+        ("kernel_evals", ctypes.c_int64), ("t_tree_ms", ctypes.c_double), ("t_build_ms", ctypes.c_double),
+    ]
+
+
 EXPORTS = [
     "tt_kernel_build_offline", "tt_kernel_build_from_cores", "tt_kernel_factor_rows", "tt_kernel_online_core",
     "tt_kernel_apply", "tt_kernel_apply_noalloc", "tt_kernel_project", "tt_kernel_apply_plain",
@@ -85,6 +93,8 @@ EXPORTS = [
     "tt_kernel_global2_online", "tt_kernel_global2_apply", "tt_kernel_phase4_round",
     "tt_kernel_batch_build", "tt_kernel_batch_configure", "tt_kernel_batch_factor", "tt_kernel_batch_get_info",
     "tt_kernel_batch_get_class", "tt_kernel_batch_get_factors", "tt_kernel_batch_apply", "tt_kernel_batch_destroy",
+    "tt_kernel_hmat_build", "tt_kernel_hmat_apply", "tt_kernel_hmat_get_info", "tt_kernel_hmat_get_lists",
+    "tt_kernel_hmat_get_batch", "tt_kernel_hmat_destroy",
     "tt_kernel_eval_entries", "tt_kernel_eval_dense", "tt_kernel_get_info",
     "tt_kernel_get_factors", "tt_kernel_get_cores", "tt_kernel_get_coeff_cores", "tt_kernel_get_cross",
     "tt_kernel_destroy", "tt_kernel_last_error",
@@ -123,6 +133,12 @@ def load():
     lib.tt_kernel_batch_configure.argtypes = [vp, c_int, c_int, c_int]
     lib.tt_kernel_batch_factor.argtypes = [vp, vp, vp, vp]
     lib.tt_kernel_batch_get_info.argtypes = [vp, P(BatchInfo), P(c_int), P(c_int)]
+    lib.tt_kernel_hmat_build.argtypes = [P(Params), vp, i64, c_int, vp, P(vp)]
+    lib.tt_kernel_hmat_apply.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp]
+    lib.tt_kernel_hmat_get_info.argtypes = [vp, P(HmatInfo)]
+    lib.tt_kernel_hmat_get_lists.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int32)]
+    lib.tt_kernel_hmat_get_batch.argtypes = [vp, P(vp)]
+    lib.tt_kernel_hmat_destroy.argtypes = [vp]
     lib.tt_kernel_batch_get_class.argtypes = [vp, c_int, P(vp)]
     lib.tt_kernel_batch_get_factors.argtypes = [vp, c_int, vp, vp, vp]
     lib.tt_kernel_batch_apply.argtypes = [vp, vp, c_int, vp, i64, vp, i64, vp, i64, vp, i64, vp, vp]

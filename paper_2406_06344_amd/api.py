@@ -627,3 +627,65 @@ class TTBatch:
                                                 _ptr(Gc), self.n_x, _ptr(dX), self.n_y, _ptr(dth),
                                                 _stream_ptr(stream)))
         return (Y, dX, dth) if G is not None else Y
+
+
+class HMatrix:
+    """A parametric hierarchical matrix for K(X, X; theta): far blocks (the
+    interaction lists of a uniform tree over the root box, every level >= 2)
+    in the PTTK low-rank form through a pair batch, near blocks (neighbouring
+    leaves) summed directly.  X: (N, d) points in the root box."""
+
+    def __init__(self, handle, params, dtype, n):
+        self._h = handle
+        self.params = params
+        self.dtype = dtype
+        self.n = n
+        self.d_theta = params.d_theta
+
+    @classmethod
+    def build(cls, X, kind, d, box, box_theta=(), leaf_points=64, n_spatial=16, n_param=None, tol=1e-6,
+              dtype=torch.float32, stream=None, **kw):
+        lib = _lib.load()
+        if int(leaf_points) < 1:
+            raise ValueError("leaf_points must be positive")
+        p = make_params(kind, d, box, box, box_theta, n_spatial, n_param, tol, dtype, **kw)
+        Xs = _soa(X, dtype, d, "X")
+        h = ctypes.c_void_p()
+        check(lib.tt_kernel_hmat_build(ctypes.byref(p), _ptr(Xs), Xs.shape[1], int(leaf_points), _stream_ptr(stream),
+                                       ctypes.byref(h)))
+        return cls(h, p, dtype, Xs.shape[1])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().tt_kernel_hmat_destroy(h)
+            except Exception:
+                pass
+
+    def info(self):
+        inf = _lib.HmatInfo()
+        check(_lib.load().tt_kernel_hmat_get_info(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _lib.HmatInfo._fields_}
+
+    def lists(self):
+        """(far (F, 7): level, source cell, target cell; near (M, 6); perm (N,))
+        as numpy int32 arrays."""
+        inf = self.info()
+        far = np.zeros((max(inf["far_pairs"], 1), 7), dtype=np.int32)
+        near = np.zeros((max(inf["near_pairs"], 1), 6), dtype=np.int32)
+        perm = np.zeros(self.n, dtype=np.int32)
+        P32 = ctypes.POINTER(ctypes.c_int32)
+        check(_lib.load().tt_kernel_hmat_get_lists(self._h, far.ctypes.data_as(P32), near.ctypes.data_as(P32),
+                                                   perm.ctypes.data_as(P32)))
+        return far[:inf["far_pairs"]], near[:inf["near_pairs"]], perm
+
+    def apply(self, theta, X, stream=None):
+        """Y[b] = H(theta_b) X[b] for rows of X (B, N) and theta (B, d_theta)."""
+        B = _chk(X, "X", None, self.n).shape[0]
+        th = _theta(theta, self.d_theta, self.dtype, B) if self.d_theta else None
+        X = _dev(X, self.dtype)
+        Y = torch.empty((B, self.n), dtype=self.dtype, device="cuda")
+        check(_lib.load().tt_kernel_hmat_apply(self._h, _ptr(th), B, _ptr(X), self.n, _ptr(Y), self.n,
+                                               _stream_ptr(stream)))
+        return Y
