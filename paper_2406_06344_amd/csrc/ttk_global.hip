@@ -12,7 +12,7 @@
 // Section 3.5), W = U Lambda_+ U^T for R Hhat R^T = U Lambda U^T.  The
 // non-negative spectral part is formed as (Mh + |Mh|) / 2 with |Mh| = V Sigma
 // V^T from a one-sided Jacobi SVD Mh = U' Sigma V^T (for symmetric Mh the
-// right singular vectors are eigenvectors and Sigma = |Lambda|).
+// singular vectors are eigenvectors up to sign and Sigma = |Lambda|).
 //
 // PTTK-Global-2 (Algorithm 4 with Compress) keeps, for one theta, only the
 // leading positive eigenpairs (Uhat, Lambdahat) and returns Z = Q Uhat.  The
@@ -158,12 +158,27 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
     gemm64(0, 1, k, k, rt, 1.0, P + (size_t)b * k * rt, k, R2, k, 0.0, Mh + (size_t)b * kk, k, st);
   }
   hipLaunchKernelGGL(k_sym_copy, dim3(B), dim3(256), 0, st, Mh, J, k, kk);
-  jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);
-  hipLaunchKernelGGL(k_scale_cols, dim3(B), dim3(256), 0, st, V, sig, sS, k, kk, VS);
+  // |Mh| = V Sigma V^T from the right singular vectors; equally U Sigma U^T
+  // from the left ones, since for a symmetric matrix the left and right
+  // singular subspaces of every singular value coincide (also where +lambda
+  // and -lambda share it).  Small k: all thetas at once, one workgroup each,
+  // with V.  Large k (past one workgroup's LDS): per theta, the left vectors
+  // by the block iteration over many workgroups.
+  const double* Vuse = V;
+  if (k <= 141) {
+    jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);
+  } else {
+    for (int b = 0; b < B; ++b)
+      if (!jacobi_svd_left(J + (size_t)b * kk, k, k, sig + (size_t)b * sS, st))
+        jacobi_svd(J + (size_t)b * kk, k, k, V + (size_t)b * kk, k, sig + (size_t)b * sS, st);
+    Vuse = J;   // normalised left vectors on either path
+  }
+  hipLaunchKernelGGL(k_scale_cols, dim3(B), dim3(256), 0, st, Vuse, sig, sS, k, kk, VS);
   if (out_dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_psd_part<float>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<float*>(W));
+    hipLaunchKernelGGL(k_psd_part<float>, dim3(B), dim3(256), 0, st, Mh, VS, Vuse, k, kk, static_cast<float*>(W));
   else
-    hipLaunchKernelGGL(k_psd_part<double>, dim3(B), dim3(256), 0, st, Mh, VS, V, k, kk, static_cast<double*>(W));
+    hipLaunchKernelGGL(k_psd_part<double>, dim3(B), dim3(256), 0, st, Mh, VS, Vuse, k, kk,
+                       static_cast<double*>(W));
 }
 
 size_t global2_work(int rs, int rt) {

@@ -176,7 +176,7 @@ tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dty
 void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hipStream_t st);
 // Same without the right vectors (A <- U Sigma normalised to U, sigma): in
 // one workgroup's LDS when A fits, else by the block iteration over many
-// workgroups (n <= 256; it waits for the stream between batches of sweeps).
+// workgroups (n <= 512; it waits for the stream between batches of sweeps).
 // sigma's buffer holds jacobi_sigma_doubles(n).  false: nothing launched.
 bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st);
 // count independent SVDs, one workgroup each; matrix b at A + b sA, V + b sV,

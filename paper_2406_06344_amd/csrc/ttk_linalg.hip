@@ -1935,7 +1935,7 @@ void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux
 // convergence flag between batches (the sweeps queued past convergence
 // return at once).
 bool jacobi_block_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
-  if (n < 2 || n > 16 * 16) return false;
+  if (n < 2 || n > 16 * 32) return false;   // E <= 32 entries per lane; 2 JB_W n doubles of LDS (128 KB at 512)
   const size_t sh = (size_t)2 * JB_W * n * sizeof(double);
   const int nb = (n + JB_W - 1) / JB_W, nbp = nb + (nb & 1);
   double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
@@ -1949,7 +1949,9 @@ bool jacobi_block_left(double* A, int n, int lda, double* sigma, hipStream_t st)
         if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, st);
         else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, st);
         else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, st);
-        else jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, st);
+        else if (E <= 16) jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, st);
+        else if (E <= 24) jacobi_block_round<24>(A, n, lda, nbp, rnd, aux, sh, st);
+        else jacobi_block_round<32>(A, n, lda, nbp, rnd, aux, sh, st);
       }
       hipLaunchKernelGGL(k_jb_check, dim3(1), dim3(64), 0, st, aux);
     }

@@ -294,3 +294,45 @@ def test_matern_bessel_at_small_argument(nu):
         err = np.abs(Kg - Ko).max() / np.abs(Ko).max()
         say(f"[bessel] nu {nu} l {ell}: max rel err {err:.2e}")
         assert err <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_global_wide_rank_matches_oracle(dtype):
+    """Global-1 and Global-2 at k = r_s + r_t = 200, past one workgroup's LDS:
+    the eigen-steps take the left vectors from the block Jacobi over many
+    workgroups (|Mh| = U Sigma U^T).  Random cores (d = 2, one parameter) on
+    600 points with X = Y; the operator Q W Q^T, the spectrum of W, and
+    Global-2's r_c and operator against the oracle's (numpy eigh) routes."""
+    torch = _torch()
+    import paper_2406_06344_amd as pkg
+    rng = np.random.default_rng(31)
+    n, rs, rt = 10, 100, 100
+    r = [1, n, rs, rt, n, 1]
+    cores = [rng.standard_normal((r[k], n, r[k + 1])) / np.sqrt(r[k] * n) for k in range(5)]
+    bx, bth = [[0.0, 1.0], [0.0, 1.0]], [[0.5, 2.0]]
+    X = rng.uniform(0, 1, (600, 2)).astype(np.float32).astype(np.float64)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    Xt = torch.tensor(X)
+    kern = pkg.TTKernel.from_cores(cores, Xt, Xt, "matern32", 2, bx, bx, bth, n_spatial=n, n_param=n, dtype=tdt,
+                                   symmetric_psd=True)
+    S = opttk.phase3_source(opttk.factor_values(X, np.array(bx), n), cores[:2])
+    T = opttk.phase3_target(opttk.factor_values(X, np.array(bx), n), cores[3:])
+    Q, R = opttk.global_offline(S, T)
+    th = np.array([[0.8], [1.7]])
+    xs = rng.standard_normal((2, 600))
+    y = kern.global_apply(torch.tensor(xs, dtype=tdt, device="cuda"),
+                          theta=torch.tensor(th, dtype=tdt, device="cuda")).double().cpu().numpy()
+    f64 = dtype == "f64"
+    for b in range(2):
+        H = opttk.online_H(cores[2:3], th[b], np.array(bth), n)
+        W, _ = opttk.global_online(R, H, rs)
+        e = rel(y[b], Q @ (W @ (Q.T @ xs[b])))
+        say(f"[global wide] {dtype} theta {th[b]}: Q W Q^T x rel err {e:.2e}")
+        assert e <= (1e-9 if f64 else 1e-5)
+        (Uo, lo), _ = opttk.global_online(R, H, rs, compress=True, eps=1e-3)
+        Z, lam = kern.global2_online(torch.tensor(th[b]), 1e-3)
+        Zn, ln = Z.double().cpu().numpy(), lam.double().cpu().numpy()
+        say(f"  Global-2 r_c gpu {ln.size} oracle {lo.size}")
+        assert ln.size == lo.size
+        Zo = Q @ Uo
+        assert rel((Zn * ln) @ Zn.T, (Zo * lo) @ Zo.T) <= (1e-9 if f64 else 1e-5)
