@@ -1,12 +1,12 @@
 // PTTK-Global-1 (Algorithm 4, Section 3.5) for the symmetric case X = Y.
 //
-// Offline: thin QR of A = [U V] (N x k, k = r_s + r_t) by blocked Householder
-// QR in double precision.  For one point set the source and target factors
-// span nearly the same subspace (for d = 2, n = 8 and ranks n^d they span
-// exactly the same 64-dimensional space), so [U V] is numerically rank
-// deficient; Householder reflections keep Q orthonormal regardless, which a
-// Gram-matrix (Cholesky QR) route cannot.  The panel factorisation runs in
-// one workgroup; the trailing updates and the formation of Q are GEMMs.
+// Offline: thin QR of A = [U V] (N x k, k = r_s + r_t) in double precision by
+// the tall-skinny Householder QR (k <= 512; blocked Householder on the whole
+// matrix above that).  For one point set the source and target factors span
+// nearly the same subspace (for d = 2, n = 8 and ranks n^d they span exactly
+// the same 64-dimensional space), so [U V] is numerically rank deficient;
+// Householder reflections keep Q orthonormal regardless, which a
+// Gram-matrix (Cholesky QR) route cannot.
 //
 // Online: with Hhat = [[0, M/2], [M^T/2, 0]] (the symmetric-part identity of
 // Section 3.5), W = U Lambda_+ U^T for R Hhat R^T = U Lambda U^T.  The
@@ -41,6 +41,13 @@ __global__ void k_concat_cm(const T* U, int ldu, int rs, const T* V, int ldv, in
     const int c = (int)(e / N);
     A[e] = c < rs ? (double)U[p * ldu + c] : (double)V[p * ldv + (c - rs)];
   }
+}
+
+// I (k x k, FP64) = the identity.
+__global__ void k_identity(int k, double* I) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)k * k;
+       e += (int64_t)gridDim.x * blockDim.x)
+    I[e] = (e % k == e / k) ? 1.0 : 0.0;
 }
 
 // out (N x k row-major, dtype) = Q (N x k column-major, FP64).
@@ -112,7 +119,7 @@ tt_status global_qr(int dtype, const void* U, int ldu, int rs, const void* V, in
   if (N > INT32_MAX) return fail(TTK_ERR_UNSUPPORTED, "Global-1 QR supports at most 2^31 - 1 points");
   DBuf A, work;
   TTK_TRY(A.alloc((size_t)N * k * sizeof(double)));
-  TTK_TRY(work.alloc(qr_blocked_work((int)N, k) * sizeof(double)));
+  if (k > 512) TTK_TRY(work.alloc(qr_blocked_work((int)N, k) * sizeof(double)));
   if (dtype == TTK_FP32)
     hipLaunchKernelGGL(k_concat_cm<float>, dim3(nblocks(N * k)), dim3(256), 0, st, static_cast<const float*>(U), ldu,
                        rs, static_cast<const float*>(V), ldv, rt, N, A.as<double>());
@@ -120,6 +127,18 @@ tt_status global_qr(int dtype, const void* U, int ldu, int rs, const void* V, in
     hipLaunchKernelGGL(k_concat_cm<double>, dim3(nblocks(N * k)), dim3(256), 0, st, static_cast<const double*>(U),
                        ldu, rs, static_cast<const double*>(V), ldv, rt, N, A.as<double>());
   TTK_HIP(hipGetLastError());
+  if (k <= 512) {
+    // tall-skinny QR: R, then Q = Q [I; 0] written row-major in the dtype
+    TsqrState ts;
+    TTK_TRY(tsqr_factor(TTK_FP64, A.as<double>(), 1, N, N, k, &ts, R, k, st));
+    DBuf I;
+    TTK_TRY(I.alloc((size_t)k * k * sizeof(double)));
+    hipLaunchKernelGGL(k_identity, dim3(nblocks((int64_t)k * k)), dim3(256), 0, st, k, I.as<double>());
+    TTK_TRY(tsqr_apply(&ts, I.as<double>(), k, k, dtype, Q, k, 1, st));
+    TTK_HIP(hipGetLastError());
+    TTK_HIP(hipStreamSynchronize(st));   // the local buffers are freed on return
+    return TTK_OK;
+  }
   TTK_TRY(qr_blocked(A.as<double>(), (int)N, k, (int)N, R, k, work.as<double>(), st));
   if (dtype == TTK_FP32)
     hipLaunchKernelGGL(k_q_rowmajor<float>, dim3(nblocks(N * k)), dim3(256), 0, st, A.as<double>(), N, k,
@@ -168,9 +187,8 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
   if (k <= 141) {
     jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);
   } else {
-    for (int b = 0; b < B; ++b)
-      if (!jacobi_svd_left(J + (size_t)b * kk, k, k, sig + (size_t)b * sS, st))
-        jacobi_svd(J + (size_t)b * kk, k, k, V + (size_t)b * kk, k, sig + (size_t)b * sS, st);
+    if (!jacobi_svd_left_batched(J, k, k, kk, sig, sS, B, st))
+      jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);   // (k above 512)
     Vuse = J;   // normalised left vectors on either path
   }
   hipLaunchKernelGGL(k_scale_cols, dim3(B), dim3(256), 0, st, Vuse, sig, sS, k, kk, VS);

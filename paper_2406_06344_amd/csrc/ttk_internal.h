@@ -153,19 +153,19 @@ tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double
 // C (m x nc, ldc) <- Q C with the Q of a qr_factor of A (m x n) and its work.
 tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, double* C, int nc, int ldc,
                      hipStream_t st);
-// Tall-skinny QR of an N x r matrix (r <= 128, N >= r): A(p, c) at
+// Tall-skinny QR of an N x r matrix (r <= 512, N >= r): A(p, c) at
 // A[p sp + c sc] in dtype.  tsqr_factor writes R (r x r upper, FP64, device,
 // leading dimension ldr) and keeps the blocks' reflectors in *ts;
-// tsqr_apply writes Q [C; 0] (N x c, c <= 128; C FP64 r x c on the device,
+// tsqr_apply writes Q [C; 0] (N x c, c <= 512; C FP64 r x c on the device,
 // leading dimension ldc) to Y(p, j) = Y[p sp + j sc] in out_dtype.
-constexpr int TSQR_MAXLEV = 16;
+constexpr int TSQR_MAXLEV = 24;
 struct TsqrState {
-  int r = 0, nlev = 0;
+  int r = 0, nlev = 0, H = 0;
   int64_t N = 0;
   int nb[TSQR_MAXLEV] = {0};
   int64_t rows[TSQR_MAXLEV] = {0};
   DBuf A[TSQR_MAXLEV], tau[TSQR_MAXLEV], T[TSQR_MAXLEV];
-  DBuf V, D[2];
+  DBuf V, Wp, D[2];
 };
 tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,
                       int ldr, hipStream_t st);
@@ -179,6 +179,12 @@ void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hi
 // workgroups (n <= 512; it waits for the stream between batches of sweeps).
 // sigma's buffer holds jacobi_sigma_doubles(n).  false: nothing launched.
 bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st);
+// count independent left-only SVDs by the block iteration together (one grid
+// over every matrix's meetings; n <= 512): matrix b at A + b sA, its sigma
+// and workspace at sigma + b sS (sS >= jacobi_sigma_doubles(n)).  false:
+// nothing launched.
+bool jacobi_svd_left_batched(double* A, int n, int lda, size_t sA, double* sigma, size_t sS, int count,
+                             hipStream_t st);
 // count independent SVDs, one workgroup each; matrix b at A + b sA, V + b sV,
 // sigma (and its workspace) at sigma + b sS, sS >= jacobi_sigma_doubles(n).
 void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,

@@ -5,6 +5,8 @@
 // TT-Round) and a small tiled GEMM.  Matrices are column-major.  The
 // factorisations run in one workgroup: they are sequential in the column
 // index and their sizes (<= 8192 x 256) keep them in L2.
+#include <cstring>
+
 #include "ttk_internal.h"
 #include "ttk_wave.h"
 
@@ -808,7 +810,10 @@ constexpr int QSW = 4;     // waves per block (QRC / 4 / QSW k-steps of four row
 constexpr int QSUM = 16;   // the update sums at most this many partials itself
 static_assert(QSW * 64 == 256, "a thread per entry of the 16 x 16 products");
 __global__ void __launch_bounds__(QSW * 64) k_qr_apply_w(const double* V, int mm, int jb, const double* C, int nc,
-                                                          int lda, double* Wp) {
+                                                          int lda, double* Wp, size_t sV, size_t sC, size_t sW) {
+  V += blockIdx.z * sV;   // (batched: blockIdx.z picks the matrix)
+  C += blockIdx.z * sC;
+  Wp += blockIdx.z * sW;
   constexpr int STEPS = QRC / 4 / QSW;
   __shared__ double Ws[QSW][16][17];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -847,7 +852,12 @@ __global__ void __launch_bounds__(256) k_qr_apply_sum(double* Wp, int nch, int t
 }
 
 __global__ void __launch_bounds__(QSW * 64) k_qr_apply_c(const double* V, int mm, int jb, const double* T, int trans,
-                                                          double* C, int nc, int lda, const double* Wp, int nparts) {
+                                                          double* C, int nc, int lda, const double* Wp, int nparts,
+                                                          size_t sV, size_t sT, size_t sC, size_t sW) {
+  V += blockIdx.z * sV;   // (batched: blockIdx.z picks the matrix)
+  T += blockIdx.z * sT;
+  C += blockIdx.z * sC;
+  Wp += blockIdx.z * sW;
   __shared__ double W[16][17], W2[16][17];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -911,14 +921,15 @@ void qr_apply(const double* V, int mm, int jb, const double* T, int trans, doubl
     return;
   }
   const int nch = (mm + QRC - 1) / QRC;
-  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda, Wp);
+  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda, Wp,
+                     (size_t)0, (size_t)0, (size_t)0);
   int nparts = nch;
   if (nch > QSUM) {
     hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles), dim3(256), 0, st, Wp, nch, tiles);
     nparts = 1;
   }
   hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
-                     (const double*)Wp, nparts);
+                     (const double*)Wp, nparts, (size_t)0, (size_t)0, (size_t)0, (size_t)0);
 }
 
 // Columns of Q for one panel from its reflectors (backward accumulation, as
@@ -1341,7 +1352,9 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
 // products) live past the workspace of jacobi_finish in sigma's buffer.
 constexpr int JB_W = 16;    // columns per block
 constexpr int JB_T = 256;   // threads: 16 pairs of 2 JB_W columns, 16 lanes each
-__global__ void __launch_bounds__(BS) k_jb_init(const double* A, int n, int lda, double* aux) {
+__global__ void __launch_bounds__(BS) k_jb_init(const double* A, int n, int lda, double* aux, size_t sA, size_t sS) {
+  A += blockIdx.x * sA;   // (batched: one matrix per workgroup)
+  aux += blockIdx.x * sS;
   __shared__ double red[NW];
   double nf = 0.0;
   for (int e = threadIdx.x; e < n * n; e += BS) {
@@ -1356,7 +1369,8 @@ __global__ void __launch_bounds__(BS) k_jb_init(const double* A, int n, int lda,
   }
 }
 
-__global__ void k_jb_check(double* aux) {
+__global__ void k_jb_check(double* aux, size_t sS) {
+  aux += blockIdx.x * sS;
   int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
   if (threadIdx.x == 0) {
     if (!fl[1] || !fl[2]) fl[0] = 1;
@@ -1365,7 +1379,10 @@ __global__ void k_jb_check(double* aux) {
 }
 
 template <int E>
-__global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda, int nbp, int rnd, double* aux) {
+__global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda, int nbp, int rnd, double* aux,
+                                                        size_t sA, size_t sS) {
+  A += blockIdx.y * sA;   // (batched: blockIdx.y picks the matrix, with its own flags)
+  aux += blockIdx.y * sS;
   int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
   if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;   // converged
   extern __shared__ double sj[];   // the 2 JB_W columns, leading dimension n
@@ -1454,7 +1471,9 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
 
 // Singular values, normalised left vectors and the ordering (jacobi_finish)
 // of a matrix the block iteration has orthogonalised.
-__global__ void __launch_bounds__(BS) k_jb_finish(double* A, int n, int lda, double* sigma) {
+__global__ void __launch_bounds__(BS) k_jb_finish(double* A, int n, int lda, double* sigma, size_t sA, size_t sS) {
+  A += blockIdx.x * sA;
+  sigma += blockIdx.x * sS;
   double* work = sigma + n;
   int32_t* order = reinterpret_cast<int32_t*>(work + (size_t)n * n + n);
   jacobi_finish(A, n, lda, nullptr, 0, sigma, work, order);
@@ -1659,75 +1678,80 @@ tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, doubl
 namespace {
 
 // Tall-skinny QR (Demmel, Grigori, Hoemmen & Langou, SIAM J. Sci. Comput.
-// 2012) for N x r matrices with r <= 128: the rows are cut into blocks of
-// TSQR_H, every block is factored by the blocked Householder QR above (one
-// batched launch per panel: the register panel and the trailing update with
-// blockIdx.y = block), the blocks' R factors are stacked and cut again, until
-// one block is left; its R is the R of the whole matrix.  Q is never formed:
+// 2012) for N x r matrices with r <= 512: the rows are cut into blocks of H,
+// every block is factored by the blocked Householder QR above (one batched
+// launch per panel: the register panel and the trailing update with a
+// batch index), the blocks' R factors are stacked and cut again, until one
+// block is left; its R is the R of the whole matrix.  Q is never formed:
 // Q [C; 0] is applied top-down, each level's reflectors (batched again) to
 // the rows the level above hands down.  Each block's factorisation is
 // Householder, so Q is orthonormal to working precision whatever the
-// conditioning (a Gram-matrix route would square it).
-constexpr int TSQR_H = 512;   // rows per block: >= r, and one k_qr_apply per update (mm <= 4 QRC)
-constexpr int TSQR_TR = 32;   // rows per tile of the strided copies
+// conditioning (a Gram-matrix route would square it; [U V] of Global-1 is
+// numerically rank deficient).  H = 512 up to 128 columns (one k_qr_apply
+// per trailing update), 2048 above (the register panel's limit; the update
+// split over row chunks, at most 16, so their partials are summed in place).
+inline int tsqr_h(int r) { return r <= 128 ? 512 : 2048; }
+inline int tsqr_tr(int c) { return c <= 128 ? 32 : 8; }   // rows per LDS tile of the strided copies
 
 // Level 0: the blocks Ab[b H r + i + c H] = A(g, c) for g = b H + i < N (A(g, c)
-// at A[g sp + c sc]), 0 past N.  A tile of TSQR_TR rows x r columns goes through
-// LDS so both sides are read and written along their contiguous direction.
+// at A[g sp + c sc]), 0 past N.  A tile of TR rows x r columns goes through
+// LDS (TR (r + 1) doubles) so both sides are read and written along their
+// contiguous direction.
 template <class T>
-__global__ void __launch_bounds__(256) k_tsqr_load(const T* A, int64_t sp, int64_t sc, int64_t N, int r,
-                                                   double* Ab) {
-  __shared__ double t[TSQR_TR][129];
-  const int64_t g0 = (int64_t)blockIdx.x * TSQR_TR;
-  for (int e = threadIdx.x; e < TSQR_TR * r; e += 256) {
+__global__ void __launch_bounds__(256) k_tsqr_load(const T* A, int64_t sp, int64_t sc, int64_t N, int r, int H,
+                                                   int TR, double* Ab) {
+  extern __shared__ double tl[];
+  const int64_t g0 = (int64_t)blockIdx.x * TR;
+  for (int e = threadIdx.x; e < TR * r; e += 256) {
     const int i = e / r, c = e - i * r;
     const int64_t g = g0 + i;
-    t[i][c] = g < N ? (double)A[g * sp + c * sc] : 0.0;
+    tl[i * (r + 1) + c] = g < N ? (double)A[g * sp + c * sc] : 0.0;
   }
   __syncthreads();
-  const int64_t b = g0 / TSQR_H;
-  const int i0 = (int)(g0 - b * TSQR_H);
-  double* out = Ab + b * TSQR_H * r;
-  for (int e = threadIdx.x; e < TSQR_TR * r; e += 256) {
-    const int c = e / TSQR_TR, i = e - c * TSQR_TR;
-    out[i0 + i + (int64_t)c * TSQR_H] = t[i][c];
+  const int64_t b = g0 / H;
+  const int i0 = (int)(g0 - b * H);
+  double* out = Ab + b * H * r;
+  for (int e = threadIdx.x; e < TR * r; e += 256) {
+    const int c = e / TR, i = e - c * TR;
+    out[i0 + i + (int64_t)c * H] = tl[i * (r + 1) + c];
   }
 }
 
 // The output Y(p, j) = D0[p / H][p % H + j H] (p < N, j < c), to Y[p sp + j sc].
 template <class T>
-__global__ void __launch_bounds__(256) k_tsqr_store(const double* D, int64_t N, int c, T* Y, int64_t sp, int64_t sc) {
-  __shared__ double t[TSQR_TR][129];
-  const int64_t g0 = (int64_t)blockIdx.x * TSQR_TR;
-  const int64_t b = g0 / TSQR_H;
-  const int i0 = (int)(g0 - b * TSQR_H);
-  const double* in = D + b * TSQR_H * c;
-  for (int e = threadIdx.x; e < TSQR_TR * c; e += 256) {
-    const int j = e / TSQR_TR, i = e - j * TSQR_TR;
-    t[i][j] = in[i0 + i + (int64_t)j * TSQR_H];
+__global__ void __launch_bounds__(256) k_tsqr_store(const double* D, int64_t N, int c, int H, int TR, T* Y, int64_t sp,
+                                                    int64_t sc) {
+  extern __shared__ double tl[];
+  const int64_t g0 = (int64_t)blockIdx.x * TR;
+  const int64_t b = g0 / H;
+  const int i0 = (int)(g0 - b * H);
+  const double* in = D + b * H * c;
+  for (int e = threadIdx.x; e < TR * c; e += 256) {
+    const int j = e / TR, i = e - j * TR;
+    tl[i * (c + 1) + j] = in[i0 + i + (int64_t)j * H];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TSQR_TR * c; e += 256) {
+  for (int e = threadIdx.x; e < TR * c; e += 256) {
     const int i = e / c, j = e - i * c;
     const int64_t g = g0 + i;
-    if (g < N) Y[g * sp + j * sc] = (T)t[i][j];
+    if (g < N) Y[g * sp + j * sc] = (T)tl[i * (c + 1) + j];
   }
 }
 
 // Level l + 1 from level l: the stacked R factors (block b's R as rows
 // b r .. b r + r - 1), cut into blocks of H rows, zero past `rows`.
-__global__ void k_tsqr_stack(const double* Al, int r, int64_t rows, int nbn, double* An) {
-  const int64_t total = (int64_t)nbn * TSQR_H * r;
+__global__ void k_tsqr_stack(const double* Al, int r, int H, int64_t rows, int nbn, double* An) {
+  const int64_t total = (int64_t)nbn * H * r;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t bn = e / ((int64_t)TSQR_H * r);
-    const int64_t rem = e - bn * TSQR_H * r;
-    const int c = (int)(rem / TSQR_H), i = (int)(rem % TSQR_H);
-    const int64_t g = bn * TSQR_H + i;
+    const int64_t bn = e / ((int64_t)H * r);
+    const int64_t rem = e - bn * H * r;
+    const int c = (int)(rem / H), i = (int)(rem % H);
+    const int64_t g = bn * H + i;
     double v = 0.0;
     if (g < rows) {
       const int64_t b = g / r;
       const int ii = (int)(g - b * r);
-      if (ii <= c) v = Al[b * TSQR_H * r + ii + (int64_t)c * TSQR_H];
+      if (ii <= c) v = Al[b * H * r + ii + (int64_t)c * H];
     }
     An[e] = v;
   }
@@ -1735,41 +1759,75 @@ __global__ void k_tsqr_stack(const double* Al, int r, int64_t rows, int nbn, dou
 
 // Level l - 1's input from level l's result: block b gets rows b r .. b r + r - 1
 // of the level above (which lie in its blocks of H rows), then zeros.
-__global__ void k_tsqr_down(const double* Du, int c, int nb, int r, double* Dl) {
-  const int64_t total = (int64_t)nb * TSQR_H * c;
+__global__ void k_tsqr_down(const double* Du, int c, int nb, int r, int H, double* Dl) {
+  const int64_t total = (int64_t)nb * H * c;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = e / ((int64_t)TSQR_H * c);
-    const int64_t rem = e - b * TSQR_H * c;
-    const int j = (int)(rem / TSQR_H), i = (int)(rem % TSQR_H);
+    const int64_t b = e / ((int64_t)H * c);
+    const int64_t rem = e - b * H * c;
+    const int j = (int)(rem / H), i = (int)(rem % H);
     double v = 0.0;
     if (i < r) {
       const int64_t g = b * r + i;
-      v = Du[(g / TSQR_H) * TSQR_H * c + (g % TSQR_H) + (int64_t)j * TSQR_H];
+      v = Du[(g / H) * H * c + (g % H) + (int64_t)j * H];
     }
     Dl[e] = v;
   }
 }
 
 // The top level's input [C; 0] (one block of H x c; C r x c, leading dimension ldc).
-__global__ void k_tsqr_top(const double* C, int ldc, int r, int c, double* D) {
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < TSQR_H * c; e += gridDim.x * blockDim.x) {
-    const int j = e / TSQR_H, i = e % TSQR_H;
+__global__ void k_tsqr_top(const double* C, int ldc, int r, int c, int H, double* D) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < H * c; e += gridDim.x * blockDim.x) {
+    const int j = e / H, i = e % H;
     D[e] = i < r ? C[i + (size_t)j * ldc] : 0.0;
   }
 }
 
 inline unsigned tsqr_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
+// (I - V op(T) V^T) on the nb blocks' C: one k_qr_apply per block for
+// mm <= 4 QRC, else the row-chunked pair with each block's partials at
+// Wp + b sW (at most 16 chunks, summed by k_qr_apply_c in chunk order).
+void tsqr_update(const double* V, int mm, int jb, const double* T, int trans, double* C, int nc, int lda, int nb,
+                 size_t sV, size_t sT, size_t sC, double* Wp, size_t sW, hipStream_t st) {
+  const int tiles = (nc + 15) / 16;
+  if (mm <= 4 * QRC) {
+    hipLaunchKernelGGL(k_qr_apply, dim3(tiles, nb), dim3(QAW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda, sV, sT,
+                       sC);
+    return;
+  }
+  const int nch = (mm + QRC - 1) / QRC;
+  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda,
+                     Wp, sV, sC, sW);
+  hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
+                     (const double*)Wp, nch, sV, sT, sC, sW);
+}
+
+// LDS of the strided copies: TR (c + 1) doubles, with the attribute raised once past 48 KB.
+template <class F>
+bool tsqr_lds(F kern, size_t sh) {
+  static size_t attr = 48 * 1024;
+  if (sh <= attr) return true;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) !=
+      hipSuccess)
+    return false;
+  attr = sh;
+  return true;
+}
+
 }  // namespace
 
 tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,
                       int ldr, hipStream_t st) {
-  constexpr int H = TSQR_H, NB = 16;
-  if (r < 1 || r > 128) return fail(TTK_ERR_UNSUPPORTED, "tsqr: r = %d outside 1..128", r);
+  constexpr int NB = 16;
+  if (r < 1 || r > 512) return fail(TTK_ERR_UNSUPPORTED, "tsqr: r = %d outside 1..512", r);
   if (N < r) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %lld rows for %d columns", (long long)N, r);
+  const int H = tsqr_h(r);
   ts->r = r;
   ts->N = N;
+  ts->H = H;
   const int npan = (r + NB - 1) / NB;
+  const int tiles_max = (r + 15) / 16;
+  const int nch_max = (H + QRC - 1) / QRC;
   int64_t rows = N;
   int l = 0;
   for (;; ++l) {
@@ -1784,20 +1842,29 @@ tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t 
     TTK_TRY(ts->T[l].alloc((size_t)nb * npan * NB * NB * sizeof(double)));
     double* Al = ts->A[l].as<double>();
     if (l == 0) {
-      const unsigned g = (unsigned)((N + TSQR_TR - 1) / TSQR_TR);
-      // blocks past N (the last one's tail) are zero: clear them first
-      fill_zero(Al, (size_t)nb * H * r * sizeof(double), st);
-      if (dtype == TTK_FP32)
-        hipLaunchKernelGGL(k_tsqr_load<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(A), sp, sc, N, r,
-                           Al);
-      else
-        hipLaunchKernelGGL(k_tsqr_load<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(A), sp, sc, N,
-                           r, Al);
+      const int TR = tsqr_tr(r);
+      const size_t sh = (size_t)TR * (r + 1) * sizeof(double);
+      const unsigned g = (unsigned)((N + TR - 1) / TR);
+      fill_zero(Al, (size_t)nb * H * r * sizeof(double), st);   // the last block's tail
+      bool ok;
+      if (dtype == TTK_FP32) {
+        ok = tsqr_lds(&k_tsqr_load<float>, sh);
+        if (ok)
+          hipLaunchKernelGGL(k_tsqr_load<float>, dim3(g), dim3(256), sh, st, static_cast<const float*>(A), sp, sc, N,
+                             r, H, TR, Al);
+      } else {
+        ok = tsqr_lds(&k_tsqr_load<double>, sh);
+        if (ok)
+          hipLaunchKernelGGL(k_tsqr_load<double>, dim3(g), dim3(256), sh, st, static_cast<const double*>(A), sp, sc,
+                             N, r, H, TR, Al);
+      }
+      if (!ok) return fail(TTK_ERR_HIP, "tsqr: LDS of %zu bytes refused", sh);
     } else {
       hipLaunchKernelGGL(k_tsqr_stack, dim3(tsqr_grid((int64_t)nb * H * r)), dim3(256), 0, st,
-                         (const double*)ts->A[l - 1].as<double>(), r, rows, nb, Al);
+                         (const double*)ts->A[l - 1].as<double>(), r, H, rows, nb, Al);
     }
     TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
+    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles_max * nch_max * 256 * sizeof(double)));
     double* V = ts->V.as<double>();
     double* tau = ts->tau[l].as<double>();
     double* T = ts->T[l].as<double>();
@@ -1808,9 +1875,9 @@ tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t 
         return fail(TTK_ERR_UNSUPPORTED, "tsqr: panel of %d rows", mm);
       const int nc = r - j0 - jb;
       if (nc > 0)
-        hipLaunchKernelGGL(k_qr_apply, dim3((nc + 15) / 16, nb), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
-                           (const double*)(T + (size_t)p * NB * NB), 1, Al + j0 + (size_t)(j0 + jb) * H, nc, H,
-                           (size_t)H * NB, (size_t)npan * NB * NB, (size_t)H * r);
+        tsqr_update(V, mm, jb, T + (size_t)p * NB * NB, 1, Al + j0 + (size_t)(j0 + jb) * H, nc, H, nb, (size_t)H * NB,
+                    (size_t)npan * NB * NB, (size_t)H * r, H > 4 * QRC ? ts->Wp.as<double>() : nullptr,
+                    (size_t)tiles_max * nch_max * 256, st);
     }
     if (nb == 1) break;
     rows = (int64_t)nb * r;
@@ -1824,20 +1891,23 @@ tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t 
 
 tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dtype, void* Y, int64_t sp, int64_t sc,
                      hipStream_t st) {
-  constexpr int H = TSQR_H, NB = 16;
-  if (c < 1 || c > 128) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %d columns to apply Q to (1..128)", c);
-  const int r = ts->r, npan = (r + NB - 1) / NB;
+  constexpr int NB = 16;
+  if (c < 1 || c > 512) return fail(TTK_ERR_UNSUPPORTED, "tsqr: %d columns to apply Q to (1..512)", c);
+  const int r = ts->r, H = ts->H, npan = (r + NB - 1) / NB;
+  const int tiles = (c + 15) / 16, nch = (H + QRC - 1) / QRC;
   DBuf* D = ts->D;
   for (int l = ts->nlev - 1; l >= 0; --l) {
     const int nb = ts->nb[l];
     DBuf& Dl = D[l & 1];
     TTK_TRY(Dl.alloc((size_t)nb * H * c * sizeof(double)));
     if (l == ts->nlev - 1)
-      hipLaunchKernelGGL(k_tsqr_top, dim3(tsqr_grid((int64_t)H * c)), dim3(256), 0, st, C, ldc, r, c, Dl.as<double>());
+      hipLaunchKernelGGL(k_tsqr_top, dim3(tsqr_grid((int64_t)H * c)), dim3(256), 0, st, C, ldc, r, c, H,
+                         Dl.as<double>());
     else
       hipLaunchKernelGGL(k_tsqr_down, dim3(tsqr_grid((int64_t)nb * H * c)), dim3(256), 0, st,
-                         (const double*)D[(l + 1) & 1].as<double>(), c, nb, r, Dl.as<double>());
+                         (const double*)D[(l + 1) & 1].as<double>(), c, nb, r, H, Dl.as<double>());
     TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
+    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles * nch * 256 * sizeof(double)));
     double* V = ts->V.as<double>();
     const double* Al = ts->A[l].as<double>();
     const double* T = ts->T[l].as<double>();
@@ -1845,18 +1915,27 @@ tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dty
       const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
       hipLaunchKernelGGL(k_build_v, dim3((unsigned)(((int64_t)mm * jb + 255) / 256), nb), dim3(256), 0, st,
                          Al + j0 + (size_t)j0 * H, mm, jb, H, V, (size_t)H * r, (size_t)H * NB);
-      hipLaunchKernelGGL(k_qr_apply, dim3((c + 15) / 16, nb), dim3(QAW * 64), 0, st, (const double*)V, mm, jb,
-                         T + (size_t)p * NB * NB, 0, Dl.as<double>() + j0, c, H, (size_t)H * NB,
-                         (size_t)npan * NB * NB, (size_t)H * c);
+      tsqr_update(V, mm, jb, T + (size_t)p * NB * NB, 0, Dl.as<double>() + j0, c, H, nb, (size_t)H * NB,
+                  (size_t)npan * NB * NB, (size_t)H * c, H > 4 * QRC ? ts->Wp.as<double>() : nullptr,
+                  (size_t)tiles * nch * 256, st);
     }
   }
-  const unsigned g = (unsigned)((ts->N + TSQR_TR - 1) / TSQR_TR);
-  if (out_dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_tsqr_store<float>, dim3(g), dim3(256), 0, st, (const double*)D[0].as<double>(), ts->N, c,
-                       static_cast<float*>(Y), sp, sc);
-  else
-    hipLaunchKernelGGL(k_tsqr_store<double>, dim3(g), dim3(256), 0, st, (const double*)D[0].as<double>(), ts->N, c,
-                       static_cast<double*>(Y), sp, sc);
+  const int TR = tsqr_tr(c);
+  const size_t sh = (size_t)TR * (c + 1) * sizeof(double);
+  const unsigned g = (unsigned)((ts->N + TR - 1) / TR);
+  bool ok;
+  if (out_dtype == TTK_FP32) {
+    ok = tsqr_lds(&k_tsqr_store<float>, sh);
+    if (ok)
+      hipLaunchKernelGGL(k_tsqr_store<float>, dim3(g), dim3(256), sh, st, (const double*)D[0].as<double>(), ts->N, c,
+                         H, TR, static_cast<float*>(Y), sp, sc);
+  } else {
+    ok = tsqr_lds(&k_tsqr_store<double>, sh);
+    if (ok)
+      hipLaunchKernelGGL(k_tsqr_store<double>, dim3(g), dim3(256), sh, st, (const double*)D[0].as<double>(), ts->N, c,
+                         H, TR, static_cast<double*>(Y), sp, sc);
+  }
+  if (!ok) return fail(TTK_ERR_HIP, "tsqr: LDS of %zu bytes refused", sh);
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
@@ -1920,7 +1999,8 @@ bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* si
 }
 
 template <int E>
-void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux, size_t sh, hipStream_t st) {
+void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux, size_t sh, int count, size_t sA,
+                        size_t sS, hipStream_t st) {
   static size_t attr = 48 * 1024;   // dynamic LDS the instantiation is allowed so far
   if (sh > attr) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_block<E>),
@@ -1928,41 +2008,55 @@ void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux
       return;   // (the launch then fails and the error is reported by the caller's next check)
     attr = sh;
   }
-  hipLaunchKernelGGL((k_jacobi_block<E>), dim3(nbp / 2), dim3(JB_T), sh, st, A, n, lda, nbp, rnd, aux);
+  hipLaunchKernelGGL((k_jacobi_block<E>), dim3(nbp / 2, count), dim3(JB_T), sh, st, A, n, lda, nbp, rnd, aux, sA,
+                     sS);
 }
 
-// The block iteration: sweeps queued in batches, the host reading the
-// convergence flag between batches (the sweeps queued past convergence
-// return at once).
-bool jacobi_block_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
-  if (n < 2 || n > 16 * 32) return false;   // E <= 32 entries per lane; 2 JB_W n doubles of LDS (128 KB at 512)
+// The block iteration on `count` matrices at once (matrix b at A + b sA,
+// its sigma and workspace at sigma + b sS): sweeps queued in batches, the
+// host reading the convergence flags between batches (launches queued past a
+// matrix's convergence return at once for it).
+bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, size_t sS, int count, hipStream_t st) {
+  if (n < 2 || n > 16 * 32 || count < 1 || count > 65535) return false;   // E <= 32; 2 JB_W n doubles of LDS
   const size_t sh = (size_t)2 * JB_W * n * sizeof(double);
   const int nb = (n + JB_W - 1) / JB_W, nbp = nb + (nb & 1);
   double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
-  const int32_t* done = reinterpret_cast<const int32_t*>(aux + 1);
-  hipLaunchKernelGGL(k_jb_init, dim3(1), dim3(BS), 0, st, (const double*)A, n, lda, aux);
+  hipLaunchKernelGGL(k_jb_init, dim3(count), dim3(BS), 0, st, (const double*)A, n, lda, aux, sA, sS);
   const int E = (n + 15) / 16;
+  std::vector<double> flags((size_t)count);
   int sweeps = 0;
   for (int batch = 6; sweeps < 60; batch = 2) {
     for (int b = 0; b < batch && sweeps < 60; ++b, ++sweeps) {
       for (int rnd = 0; rnd < nbp - 1; ++rnd) {
-        if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, st);
-        else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, st);
-        else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, st);
-        else if (E <= 16) jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, st);
-        else if (E <= 24) jacobi_block_round<24>(A, n, lda, nbp, rnd, aux, sh, st);
-        else jacobi_block_round<32>(A, n, lda, nbp, rnd, aux, sh, st);
+        if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 16) jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 24) jacobi_block_round<24>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else jacobi_block_round<32>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
       }
-      hipLaunchKernelGGL(k_jb_check, dim3(1), dim3(64), 0, st, aux);
+      hipLaunchKernelGGL(k_jb_check, dim3(count), dim3(64), 0, st, aux, sS);
     }
-    int32_t h = 0;
-    if (hipMemcpyAsync(&h, done, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    // every matrix's done flag (the int32 after its norm, read as the
+    // double-aligned word that holds it)
+    if (hipMemcpy2DAsync(flags.data(), sizeof(double), aux + 1, std::max<size_t>(sS, 1) * sizeof(double),
+                         sizeof(double), (size_t)count, hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       break;   // (the error stays pending for the caller's next check)
-    if (h) break;
+    bool all = true;
+    for (int b = 0; b < count; ++b) {
+      int32_t f;
+      std::memcpy(&f, &flags[(size_t)b], sizeof(f));
+      all = all && f != 0;
+    }
+    if (all) break;
   }
-  hipLaunchKernelGGL(k_jb_finish, dim3(1), dim3(BS), 0, st, A, n, lda, sigma);
+  hipLaunchKernelGGL(k_jb_finish, dim3(count), dim3(BS), 0, st, A, n, lda, sigma, sA, sS);
   return true;
+}
+
+bool jacobi_block_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
+  return jacobi_block_left_n(A, n, lda, 0, sigma, 0, 1, st);
 }
 
 }  // namespace
@@ -1977,6 +2071,11 @@ void jacobi_svd(double* A, int n, int lda, double* V, int ldv, double* sigma, hi
 bool jacobi_svd_left(double* A, int n, int lda, double* sigma, hipStream_t st) {
   if (jacobi_lds_launch(A, n, lda, nullptr, 0, sigma, st)) return true;
   return jacobi_block_left(A, n, lda, sigma, st);
+}
+
+bool jacobi_svd_left_batched(double* A, int n, int lda, size_t sA, double* sigma, size_t sS, int count,
+                             hipStream_t st) {
+  return jacobi_block_left_n(A, n, lda, sA, sigma, sS, count, st);
 }
 
 void jacobi_svd_batched(double* A, int n, int lda, size_t sA, double* V, int ldv, size_t sV, double* sigma,
