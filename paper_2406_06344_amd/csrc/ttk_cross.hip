@@ -309,60 +309,68 @@ __global__ void __launch_bounds__(1024) k_init_sets(KSpec ks, InitArgs ia, int32
   }
 }
 
-// TT value at test multi-indices: cores given column-major C_k
-// ((r_{k-1} n_k) x r_k), entry C_k[s, i, t] = C_k[(s + i r_{k-1}) + t r_{k-1} n_k].
-// One block of 256 threads per point.  Per core the block forms
-// v C_k[:, i_k, :] with 16 lanes along r_{k-1} (contiguous in memory, so a
-// wave's load covers 4 cache lines) and 16 lane groups along r_k; the 16
-// partial sums of a column are reduced by shuffles.  The running vector sits
-// in LDS between cores and in registers (v[l + 16 c] in lane l's slot c)
-// during a core.
+// The stopping test's TT values at the fixed test multi-indices, one core at
+// a time: the running row vectors of the P test points (P x r_{k-1}) times
+// the slice C_k[:, i_p, :] of each point's index.  The points are grouped
+// by their index at core k once for the whole cross (the test points never
+// change), so every group is one product (rows: its points, K = r_{k-1},
+// N = r_k) whose slice is read once per 16 points instead of once per
+// point.  A block takes 16 points of one group and every column: their rows
+// of V go to LDS, then each wave forms 16 x 16 output tiles with
+// v_mfma_f64_16x16x4 (A at [l % 16][l / 16], B at [l / 16][l % 16], D row
+// l / 16 + 4 v, column l % 16 in lane l, slot v).  C_k is column-major
+// ((r_{k-1} n_k) x r_k): entry (s, i, t) at C[(s + i r_{k-1}) + t m].
 constexpr int TEST_SLOTS = 64;
-struct TTView {
-  const double* C[MAXD];
-  int r[MAXD + 1];
-  int m[MAXD];
-  int D;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+struct TTTile {
+  int32_t i, start, count, pad;   // the group's index, first position in perm, points (<= 16)
 };
-__global__ void __launch_bounds__(256) k_tt_points(TTView tv, const int16_t* idx, int P, const double* vals,
-                                                   double* err) {
-  __shared__ double v[MAXR];
-  const int p = blockIdx.x;
-  if (p >= P) return;
-  const int lq = threadIdx.x & 15, lt = threadIdx.x >> 4;
-  if (threadIdx.x == 0) v[0] = 1.0;
-  __syncthreads();
-  for (int k = 0; k < tv.D; ++k) {
-    const int r0 = tv.r[k], r1 = tv.r[k + 1];
-    const int64_t m = tv.m[k];
-    const int i = idx[(int64_t)p * tv.D + k];
-    const double* blk = tv.C[k] + (int64_t)i * r0;     // rows s + i r0
-    double vr[MAXR / 16];
-#pragma unroll
-    for (int c = 0; c < MAXR / 16; ++c) vr[c] = (lq + 16 * c < r0) ? v[lq + 16 * c] : 0.0;
-    __syncthreads();   // every thread holds its slice of v before v is overwritten
-    for (int t0 = 0; t0 < r1; t0 += 16) {
-      const int t = t0 + lt;
-      double s = 0.0;
-      if (t < r1) {
-        const double* col = blk + t * m;
-#pragma unroll
-        for (int c = 0; c < MAXR / 16; ++c) {
-          if (16 * c >= r0) break;
-          if (lq + 16 * c < r0) s += col[lq + 16 * c] * vr[c];
-        }
-      }
-      s = row16_sum(s);
-      if (lq == 0 && t < r1) v[t] = s;
-    }
-    __syncthreads();
+constexpr int TTW = 4;   // waves per block of k_tt_core
+__global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, int r1, int m, const double* Vin,
+                                                      int ldin, double* Vout, int ldout, const int32_t* perm,
+                                                      const TTTile* tiles) {
+  __shared__ double As[16][MAXR + 1];
+  const TTTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < 16 * r0; e += TTW * 64) {
+    const int row = e / r0, kk = e - row * r0;
+    As[row][kk] = row < t.count ? Vin[(int64_t)perm[t.start + row] * ldin + kk] : 0.0;
   }
-  // |vals[p] - v| folded into err[p mod TEST_SLOTS] (cleared beforehand;
-  // non-negative doubles order like their bit patterns, so an integer atomic
-  // max is exact); the host takes the max of the slots
-  if (threadIdx.x == 0)
-    atomicMax(reinterpret_cast<unsigned long long*>(err + p % TEST_SLOTS),
-              (unsigned long long)__double_as_longlong(fabs(vals[p] - v[0])));
+  __syncthreads();
+  const int li = lane & 15, lk = lane >> 4;
+  const int nst = (r0 + 3) / 4;
+  const double* Ci = C + (int64_t)t.i * r0;
+  for (int ct = wv; ct < (r1 + 15) / 16; ct += TTW) {
+    const int col = ct * 16 + li;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int st = 0; st < nst; ++st) {
+      const int kk = 4 * st + lk;
+      const double a = kk < r0 ? As[li][kk] : 0.0;
+      const double b = (kk < r0 && col < r1) ? Ci[kk + (int64_t)col * m] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = lk + 4 * v;
+      if (row < t.count && col < r1) Vout[(int64_t)perm[t.start + row] * ldout + col] = acc[v];
+    }
+  }
+}
+
+// |vals[p] - V[p]| (the TT value after the last core) folded into
+// err[p mod TEST_SLOTS] (cleared beforehand; non-negative doubles order like
+// their bit patterns, so an integer atomic max is exact); the host takes the
+// max of the slots.
+__global__ void k_tt_err(const double* V, int ldv, const double* vals, int P, double* err) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  atomicMax(reinterpret_cast<unsigned long long*>(err + p % TEST_SLOTS),
+            (unsigned long long)__double_as_longlong(fabs(vals[p] - V[(int64_t)p * ldv])));
+}
+
+__global__ void k_fill1(double* p, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 1.0;
 }
 
 __global__ void k_zero1(double* p) {
@@ -418,7 +426,6 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
   store_transposes(Li, W, 2);
 }
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
 // MAXR, so a wave's loads are contiguous).  With r rounded up to 64 as ru,
@@ -1414,6 +1421,10 @@ class Cross {
   }
   int n_test_ = 0;
   double test_max_ = 0.0;
+  // the test points grouped by their index at each core: perm (N x n_test,
+  // int32) and the 16-point tiles of every group (offsets per core)
+  DBuf d_tperm_, d_ttiles_, d_tv_[2], d_ones_;
+  int ttile_off_[MAXD + 1] = {0};
   double init_max_cond_ = 0.0;
 };
 
@@ -2027,12 +2038,22 @@ tt_status Cross::refine_cores() {
 tt_status Cross::sampled_error(double* err, bool queue_next) {
   std::vector<double*> C;
   TTK_TRY(build_cores(&C));
-  TTView tv{};
-  tv.D = N_;
-  for (int k = 0; k < N_; ++k) { tv.C[k] = C[k]; tv.m[k] = rank(k) * g_.n[k]; }
-  for (int k = 0; k <= N_; ++k) tv.r[k] = rank(k);
-  hipLaunchKernelGGL(k_tt_points, dim3(n_test_), dim3(256), 0, st_, tv, d_test_idx_.as<int16_t>(), n_test_,
-                     (const double*)d_test_val_.as<double>(), d_err_.as<double>());
+  {
+    const double* vin = d_ones_.as<double>();
+    int ldin = 1;
+    const TTTile* tiles = reinterpret_cast<const TTTile*>(d_ttiles_.as<int32_t>());
+    for (int k = 0; k < N_; ++k) {
+      double* vout = d_tv_[k & 1].as<double>();
+      const int nt = ttile_off_[k + 1] - ttile_off_[k];
+      hipLaunchKernelGGL(k_tt_core, dim3(nt), dim3(TTW * 64), 0, st_, (const double*)C[k], rank(k), rank(k + 1),
+                         rank(k) * g_.n[k], vin, ldin, vout, MAXR,
+                         (const int32_t*)d_tperm_.as<int32_t>() + (size_t)k * n_test_, tiles + ttile_off_[k]);
+      vin = vout;
+      ldin = MAXR;
+    }
+    hipLaunchKernelGGL(k_tt_err, dim3((n_test_ + 255) / 256), dim3(256), 0, st_, vin, ldin,
+                       (const double*)d_test_val_.as<double>(), n_test_, d_err_.as<double>());
+  }
   const uint32_t seq = ++mail_seq_;
   hipLaunchKernelGGL(k_test_publish, dim3(1), dim3(64), 0, st_, (const double*)d_err_.as<double>(),
                      (const int32_t*)luinfo(0), N_, mail_.dres, mail_.dseq, seq);
@@ -2072,6 +2093,29 @@ tt_status Cross::run(CrossOut* out) {
     std::vector<int16_t> idx((size_t)n_test_ * N);
     for (int p = 0; p < n_test_; ++p)
       for (int j = 0; j < N; ++j) idx[(size_t)p * N + j] = (int16_t)g.below((uint64_t)g_.n[j]);
+    {   // the points grouped by their index at each core, in tiles of at most 16
+      std::vector<int32_t> perm((size_t)N * n_test_);
+      std::vector<TTTile> tl;
+      for (int k = 0; k < N; ++k) {
+        ttile_off_[k] = (int)tl.size();
+        std::vector<int> cnt(g_.n[k] + 1, 0);
+        for (int p = 0; p < n_test_; ++p) cnt[idx[(size_t)p * N + k] + 1]++;
+        for (int i = 0; i < g_.n[k]; ++i) cnt[i + 1] += cnt[i];
+        std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+        for (int p = 0; p < n_test_; ++p) perm[(size_t)k * n_test_ + pos[idx[(size_t)p * N + k]]++] = p;
+        for (int i = 0; i < g_.n[k]; ++i)
+          for (int o = cnt[i]; o < cnt[i + 1]; o += 16) tl.push_back(TTTile{i, o, std::min(16, cnt[i + 1] - o), 0});
+      }
+      ttile_off_[N] = (int)tl.size();
+      TTK_TRY(d_tperm_.alloc(perm.size() * sizeof(int32_t)));
+      TTK_TRY(d_ttiles_.alloc(std::max<size_t>(tl.size(), 1) * sizeof(TTTile)));
+      TTK_HIP(hipMemcpyAsync(d_tperm_.p, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice, st_));
+      TTK_HIP(hipMemcpyAsync(d_ttiles_.p, tl.data(), tl.size() * sizeof(TTTile), hipMemcpyHostToDevice, st_));
+      for (int b = 0; b < 2; ++b) TTK_TRY(d_tv_[b].alloc((size_t)n_test_ * MAXR * sizeof(double)));
+      TTK_TRY(d_ones_.alloc((size_t)n_test_ * sizeof(double)));
+      hipLaunchKernelGGL(k_fill1, dim3((n_test_ + 255) / 256), dim3(256), 0, st_, d_ones_.as<double>(), n_test_);
+      TTK_TRY(sync());   // (the host vectors are released at the end of this block)
+    }
     TTK_TRY(d_test_idx_.alloc(idx.size() * sizeof(int16_t)));
     TTK_TRY(d_test_val_.alloc((size_t)n_test_ * sizeof(double)));
     TTK_TRY(d_err_.alloc(TEST_SLOTS * sizeof(double)));
