@@ -686,10 +686,12 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
   for (int e = tid; e < jb * jb; e += PBT) T[e % jb + (e / jb) * jb] = Ts[e % jb][e / jb];
 }
 
-// Launches the register panel for mm <= 8 PB rows; false if the panel is taller.
+// Launches the register panel for mm <= 16 PB rows; false if the panel is taller.
 // Above 4 PB rows the panel takes 2 PB threads, four rows each (eight rows of
-// sixteen columns overflow the registers); below, PB threads are faster (the
-// block reductions dominate).
+// sixteen columns per thread spill, slower at these heights); below, PB
+// threads are faster (the block reductions dominate).  Above 8 PB rows, 2 PB
+// threads of eight rows: the spills cost less than the single-workgroup
+// panel without registers that those heights used before.
 bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, double* T, hipStream_t st,
                   int batch = 1, size_t sA = 0, size_t sTau = 0, size_t sV = 0, size_t sT = 0) {
   const dim3 g(1, batch);
@@ -701,6 +703,9 @@ bool qr_panel_reg(double* A, int mm, int jb, int lda, double* tau, double* V, do
     hipLaunchKernelGGL((k_qr_panel_reg<4, PB>), g, dim3(PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV, sT);
   else if (mm <= 8 * PB)
     hipLaunchKernelGGL((k_qr_panel_reg<4, 2 * PB>), g, dim3(2 * PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV,
+                       sT);
+  else if (mm <= 16 * PB)   // (the rounding's unfoldings of 16 x 255 rows)
+    hipLaunchKernelGGL((k_qr_panel_reg<8, 2 * PB>), g, dim3(2 * PB), 0, st, A, mm, jb, lda, tau, V, T, sA, sTau, sV,
                        sT);
   else
     return false;
@@ -1021,6 +1026,8 @@ bool qr_panel_q_reg(double* A, int mm, int jb, int lda, const double* tau, hipSt
     hipLaunchKernelGGL((k_qr_panel_q_reg<4, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
   else if (mm <= 8 * PB)
     hipLaunchKernelGGL((k_qr_panel_q_reg<8, PB>), dim3(1), dim3(PB), 0, st, A, mm, jb, lda, tau);
+  else if (mm <= 16 * PB)
+    hipLaunchKernelGGL((k_qr_panel_q_reg<8, 2 * PB>), dim3(1), dim3(2 * PB), 0, st, A, mm, jb, lda, tau);
   else
     return false;
   return true;
