@@ -155,6 +155,14 @@ def bench_global(args, torch, pkg):
         K = pkg.eval_dense(torch.tensor(X[si]), torch.tensor(X[si]), th[b], w.kind, w.d, dtype=torch.float64)
         Kh = Qs @ W[b].double() @ Qs.t()
         errs.append((torch.linalg.norm(K - Kh) / torch.linalg.norm(K)).item())
+    # Global-2 (Compress, eps = the build's tolerance) for the first theta:
+    # the eigen-truncation and Z = Q Uhat, then its apply
+    ms_g2 = time_wall(lambda: kern.global2_online(thd[0], w.tol), 3, torch)
+    Z, lam = kern.global2_online(thd[0], w.tol)
+    ms_g2_apply = time_events(lambda: kern.global2_apply(Z, lam, xb), 10, torch)
+    K0 = pkg.eval_dense(torch.tensor(X[si]), torch.tensor(X[si]), th[0], w.kind, w.d, dtype=torch.float64)
+    Zs = Z[si].double()
+    err_g2 = (torch.linalg.norm(K0 - (Zs * lam.double()) @ Zs.t()) / torch.linalg.norm(K0)).item()
     rows = 2 * w.n_src
     res = base_result(w, args, rows / (ms / 1000.0), "rows/s", ms, B, {"variant": "Global-1", "X=Y": True})
     res.update({"ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
@@ -163,6 +171,11 @@ def bench_global(args, torch, pkg):
                 "online_ms_per_theta": round(ms_online / B, 4), "global_apply_ms": round(ms_apply, 4),
                 "global_apply_GBps": round(bytes_apply / (ms_apply * 1e-3) / 1e9, 1),
                 "max_rel_err_vs_dense_fp64": float(f"{max(errs):.3e}"), "status": kern.status,
+                "global2": {"eps": w.tol, "r_c": int(lam.shape[0]), "online_ms": round(ms_g2, 3),
+                            "apply_ms": round(ms_g2_apply, 4), "rel_err_vs_dense_fp64": float(f"{err_g2:.3e}"),
+                            "note": "Global-2 for the first theta: eigen-truncation of R Hhat R^T and Z = Q Uhat "
+                                    "(online, host-synchronised), then y = Z diag(lam) Z^T x for all right-hand "
+                                    "sides"},
                 "accuracy_note": "Q W Q^T against dense float64 K(X, X) on a 4000-point subsample, worst theta"})
     res["roofline"] = {"kernel": "Global-1 apply (Q^T x, W, Q z)", "bound": "hbm",
                        "achieved": res["global_apply_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -329,6 +342,30 @@ def bench_batched(args, torch, pkg):
                        "fixed-order sum of the chunk partials (about 0.1% of its time), inside the timing",
         "traffic_note": PROJECT_TRAFFIC_NOTE,
     }
+    # ---- the paper's Phase 4 (TT-Round through S and T, on a tall-skinny QR)
+    # on this build, after every other measurement (it replaces U, V and the
+    # parameter cores of the handle)
+    print("phase 4", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    kern.phase4_round(w.tol)
+    torch.cuda.synchronize()
+    ms4 = (time.perf_counter() - t4) * 1000.0
+    inf4 = kern.info()
+    U4, V4 = kern.factors()
+    M4 = kern.online_core(thd[torch.tensor(cols, device="cuda")])
+    U4s, V4s = U4[si].double(), V4[ti].double()
+    errs4 = []
+    for j, b in enumerate(cols):
+        K = pkg.eval_dense(Xsub, Ysub, th[b], w.kind, w.d, dtype=torch.float64)
+        errs4.append((torch.linalg.norm(K - U4s @ M4[j].double() @ V4s.t()) / torch.linalg.norm(K)).item())
+    res["phase4"] = {
+        "ms": round(ms4, 2), "ranks": inf4["ranks"][w.d:w.d + w.d_theta + 1],
+        "ranks_before": r[w.d:w.d + w.d_theta + 1],
+        "max_rel_err_vs_dense_fp64": float(f"{max(errs4):.3e}"),
+        "note": "Phase 4 of Algorithm 2 at eps = tol on the final build: tall-skinny QR of U and V (1M rows "
+                "each), TT-Round of the small TT, U' = Q_S A_S and V' = Q_T A_T^T; error on the same subsample "
+                "and thetas as above; not part of the timed step"}
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         res["cpu_baseline"] = oracle_baseline(w, inf["ranks"], args.cpu_points or 200_000, 256)
