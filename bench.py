@@ -40,14 +40,14 @@ HBM_PEAK_GBPS = 8000.0
 # counters in profiles/ were taken.
 TRAFFIC = None
 FP32_PEAK_TFLOPS = 157.3
-# HBM bytes per launch of the projection kernel k_reduce_mfma_dma<5> on the
-# 1M-point workload from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
-# separate runs): (2.000 x 8312822.9 + 1.000 x 39688.8) KiB, averaged over its
+# HBM bytes per launch of the projection kernel k_reduce_mfma_dma<5, 1> on
+# the 1M-point workload from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
+# separate runs): (2.000 x 8311093.1 + 1.000 x 19840.4) KiB, averaged over its
 # two launches, with the scales 2.000 and 1.000 read off the same counters on
 # a plain 1 GiB copy.  None whenever the kernel has changed since.
-PROJECT_TRAFFIC = 17065302528
+PROJECT_TRAFFIC = 17041435184
 PROJECT_TRAFFIC_NOTE = ("HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a plain 1 GiB "
-                        "copy), average of the two launches; algorithmic 16.75 GB (X, F, float64 chunk partials)")
+                        "copy), average of the two launches; algorithmic 16.72 GB (X, F, float64 chunk partials)")
 
 
 def phase3_flops_per_point(ranks, n):
@@ -333,7 +333,7 @@ def bench_batched(args, torch, pkg):
     })
     achieved = fl_proj / (ms_proj * 1e-3) / 1e12
     res["roofline"] = {
-        "kernel": "k_reduce_mfma_dma<5> (tt_kernel_project: W = V^T X and A = U^T G, float32 MFMA)",
+        "kernel": "k_reduce_mfma_dma<5, 1> (tt_kernel_project: W = V^T X and A = U^T G, float32 MFMA)",
         "bound": "mfma", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": PROJECT_TRAFFIC,
         "avg_launch_ms": round(ms_proj, 4),

@@ -258,39 +258,43 @@ __global__ void __launch_bounds__(256, 2) k_reduce_mfma(const float* __restrict_
 // Needs ldf % 32 == 16, ldx % 4 == 0 and 16-byte aligned F and X.  Only whole
 // 64-point blocks go through the DMA; a chunk's ragged tail is staged by
 // ordinary loads with zero fill.
-template <int CT>
-__global__ void __launch_bounds__(256) k_reduce_mfma_dma(const float* __restrict__ F, int ldf, int64_t N, int r,
-                                                         const float* __restrict__ X, int64_t ldx, int B,
-                                                         int64_t chunk, double* __restrict__ part) {
+// NH: 16-theta halves per wave; the workgroup takes TBD = 64 NH thetas.  With
+// NH = 1 a stage is half as large, so two workgroups share a CU's LDS and
+// one can multiply while the other waits at its barrier.
+template <int CT, int NH>
+__global__ void __launch_bounds__(256, 2) k_reduce_mfma_dma(const float* __restrict__ F, int ldf, int64_t N, int r,
+                                                            const float* __restrict__ X, int64_t ldx, int B,
+                                                            int64_t chunk, double* __restrict__ part) {
+  constexpr int TBD = 64 * NH;                   // thetas per workgroup
   extern __shared__ float dsm[];
-  const int stage = RD_TB * RD_P + RD_P * ldf;   // floats per buffer
+  const int stage = TBD * RD_P + RD_P * ldf;     // floats per buffer
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i16 = lane & 15, kq = lane >> 4;
-  const int b0 = blockIdx.y * RD_TB;
+  const int b0 = blockIdx.y * TBD;
   const int64_t pbeg = (int64_t)blockIdx.x * chunk;
   const int64_t pend = pbeg + chunk < N ? pbeg + chunk : N;
   const int64_t nfull = (pend - pbeg) / RD_P;
   const int64_t nblk = nfull + ((pend - pbeg) % RD_P != 0);
   auto issue = [&](int64_t q0, float* buf) {
     float* xs = buf;
-    float* fs = buf + RD_TB * RD_P;
+    float* fs = buf + TBD * RD_P;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int th = 32 * w + 4 * u + kq;                      // row of this lane
+    for (int u = 0; u < 4 * NH; ++u) {
+      const int th = 16 * NH * w + 4 * u + kq;                 // row of this lane
       const int bb = min(b0 + th, B - 1);                       // rows past B: any valid column, discarded
       const int seg = (i16 + th) & 15;                          // the run stored at slot i16
-      __builtin_amdgcn_global_load_lds(X + (int64_t)bb * ldx + q0 + 4 * seg, xs + (32 * w + 4 * u) * RD_P, 16, 0,
-                                       0);
+      __builtin_amdgcn_global_load_lds(X + (int64_t)bb * ldx + q0 + 4 * seg, xs + (16 * NH * w + 4 * u) * RD_P, 16,
+                                       0, 0);
     }
     const float* fb = F + q0 * ldf;
     for (int j = w; j < ldf / 4; j += 4)                        // 16 ldf bytes-runs = ldf / 4 wave loads
       __builtin_amdgcn_global_load_lds(fb + 4 * (64 * j + lane), fs + 256 * j, 16, 0, 0);
   };
-  double out[CT][2][4];
+  double out[CT][NH][4];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < NH; ++q)
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[ct][q][v] = 0.0;
   if (nfull > 0) issue(pbeg, dsm);
@@ -301,7 +305,7 @@ __global__ void __launch_bounds__(256) k_reduce_mfma_dma(const float* __restrict
     __syncthreads();                               // everyone's; and block i - 1 is consumed
     asm volatile("" ::: "memory");                 // LDS reads below see the DMA writes
     if (i >= nfull) {                              // the ragged tail: ordinary loads, zero fill
-      for (int e = tid; e < RD_TB * RD_P; e += 256) {
+      for (int e = tid; e < TBD * RD_P; e += 256) {
         const int th = e / RD_P, k = e % RD_P;
         const int64_t p = q0 + k;
         const int bb = b0 + th;
@@ -311,39 +315,44 @@ __global__ void __launch_bounds__(256) k_reduce_mfma_dma(const float* __restrict
       for (int e = tid; e < RD_P * ldf; e += 256) {
         const int pt = e / ldf, c = e % ldf;
         const int64_t p = q0 + pt;
-        cur[RD_TB * RD_P + e] = (p < pend && c < r) ? F[p * ldf + c] : 0.0f;
+        cur[TBD * RD_P + e] = (p < pend && c < r) ? F[p * ldf + c] : 0.0f;
       }
       __syncthreads();
     }
     if (i + 1 < nfull) issue(q0 + RD_P, dsm + (size_t)((i + 1) & 1) * stage);
     const float* xs = cur;
-    const float* fa = cur + RD_TB * RD_P + kq * ldf + i16;
-    const int th0 = 32 * w + i16, th1 = th0 + 16;
-    f4 acc[CT][2];
+    const float* fa = cur + TBD * RD_P + kq * ldf + i16;
+    f4 acc[CT][NH];
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) acc[ct][0] = acc[ct][1] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+      for (int q = 0; q < NH; ++q) acc[ct][q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int t = 0; t < RD_P / 4; ++t) {
-      const float bx0 = xs[th0 * RD_P + 4 * ((t - th0) & 15) + kq];
-      const float bx1 = xs[th1 * RD_P + 4 * ((t - th1) & 15) + kq];
+      float bx[NH];
+#pragma unroll
+      for (int q = 0; q < NH; ++q) {
+        const int th = 16 * NH * w + 16 * q + i16;
+        bx[q] = xs[th * RD_P + 4 * ((t - th) & 15) + kq];
+      }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
         const float a = fa[4 * t * ldf + 16 * ct];
-        acc[ct][0] = mfma4(a, bx0, acc[ct][0]);
-        acc[ct][1] = mfma4(a, bx1, acc[ct][1]);
+#pragma unroll
+        for (int q = 0; q < NH; ++q) acc[ct][q] = mfma4(a, bx[q], acc[ct][q]);
       }
     }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < NH; ++q)
 #pragma unroll
         for (int v = 0; v < 4; ++v) out[ct][q][v] += (double)acc[ct][q][v];
   }
   double* pc = part + (size_t)blockIdx.x * r * B;
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int bb = b0 + 32 * w + 16 * q + i16;
+  for (int q = 0; q < NH; ++q) {
+    const int bb = b0 + 16 * NH * w + 16 * q + i16;
     if (bb >= B) continue;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
@@ -368,8 +377,8 @@ __global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ p
 // Chunking of the reduce: enough workgroups to fill the chip (RD_WG_TARGET
 // over the theta blocks), every chunk a whole number of 64-point blocks.
 constexpr int RD_WG_TARGET = 512;
-void reduce_shape(int64_t N, int B, int64_t* chunk, int* nch) {
-  const int tb = (B + RD_TB - 1) / RD_TB;
+void reduce_shape(int64_t N, int B, int64_t* chunk, int* nch, int tbd = RD_TB) {
+  const int tb = (B + tbd - 1) / tbd;
   const int64_t blocks = (N + RD_P - 1) / RD_P;
   int64_t want = std::max<int64_t>(1, (RD_WG_TARGET + tb - 1) / tb);
   want = std::min<int64_t>(want, blocks);
@@ -425,9 +434,16 @@ tt_status launch_reduce(const float* F, int ldf, int64_t N, int r, const float* 
   const bool xal = (ldx % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
   const bool dma = xal && ldf % 32 == 16 && ldf >= 16 * CT && reinterpret_cast<uintptr_t>(F) % 16 == 0;
   if (dma) {
-    const size_t sh = (size_t)2 * (RD_TB * RD_P + RD_P * ldf) * sizeof(float);
-    TTK_TRY(set_lds(&k_reduce_mfma_dma<CT>, sh));
-    hipLaunchKernelGGL((k_reduce_mfma_dma<CT>), grid, dim3(256), sh, st, F, ldf, N, r, X, ldx, B, chunk, part);
+    // 64 thetas per workgroup: two workgroups per CU (half the LDS each)
+    int64_t chunk1;
+    int nch1;
+    reduce_shape(N, B, &chunk1, &nch1, 64);
+    if (nch1 > nch) return fail(TTK_ERR_ARG, "reduce: chunk partials exceed the workspace");
+    const dim3 grid1((unsigned)nch1, (unsigned)((B + 63) / 64));
+    const size_t sh = (size_t)2 * (64 * RD_P + RD_P * ldf) * sizeof(float);
+    TTK_TRY(set_lds(&k_reduce_mfma_dma<CT, 1>, sh));
+    hipLaunchKernelGGL((k_reduce_mfma_dma<CT, 1>), grid1, dim3(256), sh, st, F, ldf, N, r, X, ldx, B, chunk1, part);
+    nch = nch1;
   } else {
     const size_t sh = reduce_lds_floats<CT>() * sizeof(float);
     if (xal) {
