@@ -1385,6 +1385,16 @@ __global__ void k_jb_check(double* aux, size_t sS) {
   }
 }
 
+// Whether every matrix of a batch has converged, as one int32 in the first
+// matrix's spare aux word (aux[3]), so the host reads a single 4-byte word.
+__global__ void __launch_bounds__(BS) k_jb_all_done(double* aux, size_t sS, int count) {
+  int all = 1;
+  for (int b = threadIdx.x; b < count; b += BS)
+    all &= reinterpret_cast<const int32_t*>(aux + (size_t)b * sS + 1)[0] != 0;
+  all = __syncthreads_and(all);
+  if (threadIdx.x == 0) reinterpret_cast<int32_t*>(aux + 3)[0] = all;
+}
+
 template <int E>
 __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda, int nbp, int rnd, double* aux,
                                                         size_t sA, size_t sS) {
@@ -2030,7 +2040,6 @@ bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, si
   double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
   hipLaunchKernelGGL(k_jb_init, dim3(count), dim3(BS), 0, st, (const double*)A, n, lda, aux, sA, sS);
   const int E = (n + 15) / 16;
-  std::vector<double> flags((size_t)count);
   int sweeps = 0;
   for (int batch = 6; sweeps < 60; batch = 2) {
     for (int b = 0; b < batch && sweeps < 60; ++b, ++sweeps) {
@@ -2044,18 +2053,12 @@ bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, si
       }
       hipLaunchKernelGGL(k_jb_check, dim3(count), dim3(64), 0, st, aux, sS);
     }
-    // every matrix's done flag (the int32 after its norm, read as the
-    // double-aligned word that holds it)
-    if (hipMemcpy2DAsync(flags.data(), sizeof(double), aux + 1, std::max<size_t>(sS, 1) * sizeof(double),
-                         sizeof(double), (size_t)count, hipMemcpyDeviceToHost, st) != hipSuccess ||
+    // every matrix's done flag, folded on the device into one word
+    hipLaunchKernelGGL(k_jb_all_done, dim3(1), dim3(BS), 0, st, aux, sS, count);
+    int32_t all = 0;
+    if (hipMemcpyAsync(&all, aux + 3, sizeof(all), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       break;   // (the error stays pending for the caller's next check)
-    bool all = true;
-    for (int b = 0; b < count; ++b) {
-      int32_t f;
-      std::memcpy(&f, &flags[(size_t)b], sizeof(f));
-      all = all && f != 0;
-    }
     if (all) break;
   }
   hipLaunchKernelGGL(k_jb_finish, dim3(count), dim3(BS), 0, st, A, n, lda, sigma, sA, sS);

@@ -129,7 +129,7 @@ tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const G
   c.n.assign(grid.n, grid.n + D);
   c.g.resize(D);
   for (int k = 0; k < D; ++k) c.g[k] = std::move(cores[k]);   // rounded in place (ranks only fall)
-  DBuf A, R, T, tau, V, sig, W, nrm, sg, Cw;
+  DBuf A, R, T, tau, tw, V, sig, W, nrm, sg, Cw;
   {
     // every work buffer at the largest size any step needs (the ranks only
     // fall from here), so that none is reallocated, which would wait for the
@@ -146,6 +146,7 @@ tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const G
     TTK_TRY(W.alloc(sq));
     TTK_TRY(sig.alloc(sq + (3 * (size_t)rmax + 64) * sizeof(double)));
     TTK_TRY(tau.alloc(qr_blocked_work(rmax * nmax, rmax) * sizeof(double)));
+    TTK_TRY(tw.alloc(qr_blocked_work(rmax, rmax) * sizeof(double)));
   }
   // right-to-left orthogonalisation
   for (int i = D - 1; i >= 1; --i) TTK_TRY(orth_right(c, i, A, R, T, tau, st));
@@ -174,8 +175,21 @@ tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const G
     // SVD of R.  Sigma V^T, pushed into the next core, is U^T R: with a copy of R
     // kept, only the left vectors are needed (V stays unaccumulated)
     TTK_HIP(hipMemcpyAsync(V.p, R.p, (size_t)r1 * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // The iteration runs on L = R2^T, where R^T = Q2 R2: R = L Q2^T, so L has
+    // R's singular values and left vectors, and one QR step leaves L's
+    // columns far closer to orthogonal (on these cores a few sweeps instead
+    // of tens; the QR preconditioning of Drmac and Veselic without the
+    // column pivoting)
+    hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r1 * r1)), dim3(256), 0, st, (const double*)R.as<double>(),
+                       r1, r1, r1, T.as<double>(), r1);
+    TTK_TRY(qr_factor(T.as<double>(), r1, r1, r1, W.as<double>(), r1, tw.as<double>(), st));
+    hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r1 * r1)), dim3(256), 0, st, (const double*)W.as<double>(),
+                       r1, r1, r1, R.as<double>(), r1);
     const bool left_only = jacobi_svd_left(R.as<double>(), r1, r1, sig.as<double>(), st);
-    if (!left_only) jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
+    if (!left_only) {   // (nothing was launched: the full SVD of R itself)
+      TTK_HIP(hipMemcpyAsync(R.p, V.p, (size_t)r1 * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      jacobi_svd(R.as<double>(), r1, r1, V.as<double>(), r1, sig.as<double>(), st);
+    }
     hs.resize(r1);
     TTK_HIP(hipMemcpyAsync(hs.data(), sig.p, (size_t)r1 * sizeof(double), hipMemcpyDeviceToHost, st));
     TTK_HIP(hipStreamSynchronize(st));
