@@ -325,7 +325,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 struct TTTile {
   int32_t i, start, count, pad;   // the group's index, first position in perm, points (<= 16)
 };
-constexpr int TTW = 4;   // waves per block of k_tt_core
+constexpr int TTW = 8;   // waves per block of k_tt_core
+constexpr int TTB = 8;   // MFMA steps whose B operands are loaded together
 __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, int r1, int m, const double* Vin,
                                                       int ldin, double* Vout, int ldout, const int32_t* perm,
                                                       const TTTile* tiles) {
@@ -343,11 +344,19 @@ __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, i
   for (int ct = wv; ct < (r1 + 15) / 16; ct += TTW) {
     const int col = ct * 16 + li;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int st = 0; st < nst; ++st) {
-      const int kk = 4 * st + lk;
-      const double a = kk < r0 ? As[li][kk] : 0.0;
-      const double b = (kk < r0 && col < r1) ? Ci[kk + (int64_t)col * m] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int s0 = 0; s0 < nst; s0 += TTB) {
+      double b[TTB];   // the batch's B operands, loaded before its products
+#pragma unroll
+      for (int u = 0; u < TTB; ++u) {
+        const int kk = 4 * (s0 + u) + lk;
+        b[u] = (kk < r0 && col < r1) ? Ci[kk + (int64_t)col * m] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < TTB; ++u) {
+        const int kk = 4 * (s0 + u) + lk;
+        if (s0 + u < nst)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kk < r0 ? As[li][kk] : 0.0, b[u], acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -427,15 +436,29 @@ __global__ void k_ldu_init(const double* P, int r, double* Li, double* W, double
 }
 
 
+// Which entries of a factor can be non-zero: M(t, q) with q <= t (TRI_LO:
+// Li and W^T), q >= t (TRI_UP: W and Li^T), or all (TRI_ALL), except that
+// the leading 2 x 2 block is full (the initial factors put the larger
+// diagonal entry first, which permutes their first two pivots; every later
+// pivot borders them triangularly).  The entries outside are zeros by
+// construction, so they are neither loaded nor added (their products would
+// add exact zeros).
+constexpr int TRI_ALL = 0, TRI_LO = 1, TRI_UP = 2;
+__device__ inline int tri_qmax(int t) { return t > 1 ? t : 1; }   // TRI_LO: q <= tri_qmax(t)
+__device__ inline int tri_qmin(int t) { return t > 1 ? t : 0; }   // TRI_UP: q >= tri_qmin(t)
+__device__ inline bool tri_in(int tri, int t, int q) {
+  return tri == TRI_LO ? q <= tri_qmax(t) : (tri == TRI_UP ? q >= tri_qmin(t) : true);
+}
+
 // out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
 // MAXR, so a wave's loads are contiguous).  With r rounded up to 64 as ru,
 // min(8, BS / ru) threads share a row, each over a contiguous range of q in
 // batches of 32 loads issued together (one batch covers r <= 128 for
 // BS = 256 and r <= 256 for BS = 1024); the partial sums meet in scratch (BS
-// doubles).  Every thread of the block calls it; out is visible to all on
-// return.
+// doubles).  tri: the triangle of M that holds its non-zeros.  Every thread
+// of the block calls it; out is visible to all on return.
 template <int BS>
-__device__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch) {
+__device__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch, int tri) {
   constexpr int RB = 32;
   const int ru = (r + 63) & ~63;
   const int S = min(8, BS / ru);
@@ -446,9 +469,12 @@ __device__ void row_dots(const double* M, const double* v, int r, double* out, d
     const int q0 = h * chunk, q1 = min(r, q0 + chunk);
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int q = q0; q < q1; q += RB) {
+      if (tri == TRI_LO && q > tri_qmax(t)) break;             // the rest of the row is zero
+      if (tri == TRI_UP && q + RB <= tri_qmin(t)) continue;    // this batch is zero
       double mv[RB];
 #pragma unroll
-      for (int u = 0; u < RB; ++u) mv[u] = q + u < q1 ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
+      for (int u = 0; u < RB; ++u)
+        mv[u] = (q + u < q1 && tri_in(tri, t, q + u)) ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
 #pragma unroll
       for (int u = 0; u < RB; ++u) a[u & 7] += q + u < q1 ? mv[u] * v[q + u] : 0.0;
     }
@@ -556,51 +582,6 @@ __device__ int select_block(const double* R, int n, const int32_t* srow, const i
   return p;
 }
 
-// Fused pair of row_dots: out1 = M1 v1 and out2 = M2 v2 in one pass, batches
-// of RB loads of each matrix (scratch: 2 BS doubles).
-template <int BS, int RB>
-__device__ void row_dots2(const double* M1, const double* v1, double* out1, const double* M2, const double* v2,
-                          double* out2, int r, double* scratch) {
-  const int ru = (r + 63) & ~63;
-  const int S = min(8, BS / ru);
-  const int tid = threadIdx.x, t = tid % ru, h = tid / ru;
-  double acc1 = 0.0, acc2 = 0.0;
-  if (h < S && t < r) {
-    const int chunk = (r + S - 1) / S;
-    const int q0 = h * chunk, q1 = min(r, q0 + chunk);
-    double a1[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double a2[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int q = q0; q < q1; q += RB) {
-      double m1[RB], m2[RB];
-#pragma unroll
-      for (int u = 0; u < RB; ++u) {
-        m1[u] = q + u < q1 ? M1[t + (int64_t)(q + u) * MAXR] : 0.0;
-        m2[u] = q + u < q1 ? M2[t + (int64_t)(q + u) * MAXR] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < RB; ++u) {
-        a1[u & 7] += q + u < q1 ? m1[u] * v1[q + u] : 0.0;
-        a2[u & 7] += q + u < q1 ? m2[u] * v2[q + u] : 0.0;
-      }
-    }
-    acc1 = ((a1[0] + a1[1]) + (a1[2] + a1[3])) + ((a1[4] + a1[5]) + (a1[6] + a1[7]));
-    acc2 = ((a2[0] + a2[1]) + (a2[2] + a2[3])) + ((a2[4] + a2[5]) + (a2[6] + a2[7]));
-  }
-  scratch[tid] = acc1;
-  scratch[BS + tid] = acc2;
-  __syncthreads();
-  if (tid < r) {
-    double s1 = scratch[tid], s2 = scratch[BS + tid];
-    for (int k = 1; k < S; ++k) {
-      s1 += scratch[tid + k * ru];
-      s2 += scratch[BS + tid + k * ru];
-    }
-    out1[tid] = s1;
-    out2[tid] = s2;
-  }
-  __syncthreads();
-}
-
 // max of the AMAX_SLOTS slots of a fold
 __device__ inline double slots_max(const double* sl) {
   double m = 0.0;
@@ -622,6 +603,13 @@ __device__ inline double slots_max(const double* sl) {
 constexpr int SW = 8;    // waves per block
 constexpr int SPB = 16;  // samples per block: one full MFMA row tile
 constexpr int SB = 32;   // MFMA steps of B operands held in registers (r <= 128: one batch)
+
+// The it-th 16-column tile of wave wv among nw waves, in snake order (wv,
+// 2 nw - 1 - wv, 2 nw + wv, ...): the products with a triangular factor cost
+// more for later tiles, and the snake spreads them evenly over the waves.
+__device__ inline int snake_tile(int it, int wv, int nw) {
+  return (it & 1) ? (it + 1) * nw - 1 - wv : it * nw + wv;
+}
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDesc* desc, const int32_t* sel, int r,
                                                           const double* Li, const double* W, const double* FLk,
@@ -711,11 +699,16 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
               (unsigned long long)__double_as_longlong(m));
   }
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int jt = wv; jt < ntile; jt += SW) {
+  for (int it = 0; it * SW < ntile; ++it) {
+    const int jt = snake_tile(it, wv, SW);
+    if (jt >= ntile) continue;
     const int p = jt * 16 + li;
     const bool pok = p < r;
+    // W (upper) and Li (lower) hold W(q, p) and Li(p, q) only for q <= p:
+    // the tile's products end at the step holding its last column
+    const int nst_t = min(nst, 4 * jt + 4);
     dbl4 g = {0.0, 0.0, 0.0, 0.0}, t = {0.0, 0.0, 0.0, 0.0};
-    for (int s0 = 0; s0 < nst; s0 += SB) {
+    for (int s0 = 0; s0 < nst_t; s0 += SB) {
       if (jt != wv || s0 != 0) {   // (the first batch of the first tile is already loaded)
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
@@ -727,7 +720,7 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
       }
 #pragma unroll
       for (int u = 0; u < SB; ++u) {
-        if (s0 + u < nst) {
+        if (s0 + u < nst_t) {
           g = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], bg[u], g, 0, 0, 0);
           t = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[64 * nst + (s0 + u) * 64 + lane], bt[u], t, 0, 0, 0);
         }
@@ -758,7 +751,8 @@ inline size_t sample_lds(int r) { return (size_t)2 * 64 * ((r + 3) / 4) * sizeof
 // u = A(I, t) for a column search (bit 0), read from the fibre cache, and
 // x = (u W) Li = Li^T (W^T u), or x = W (Li u), is written for k_search
 // (P^{-1} applied to one vector, through the rows of the factors or of their
-// transposes).  |u| folds into the search-stage scale.
+// transposes), followed at x + MAXR by the intermediate W^T u or Li u.  |u|
+// folds into the search-stage scale.
 template <int d, int dt, bool G>
 __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc* desc, const int32_t* sel,
                                                         const double* R, const double* luamax, StepRes* res, int r,
@@ -792,13 +786,16 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
     res->q_slot[0] = fmax(res->q_slot[0], m);
   }
   if (bit) {
-    row_dots<1024>(W + FT, su, r, sy, scr);    // W^T u
-    row_dots<1024>(Li + FT, sy, r, su, scr);   // Li^T (W^T u), into su (u is consumed)
+    row_dots<1024>(W + FT, su, r, sy, scr, TRI_LO);    // W^T u
+    row_dots<1024>(Li + FT, sy, r, su, scr, TRI_UP);   // Li^T (W^T u), into su (u is consumed)
   } else {
-    row_dots<1024>(Li, su, r, sy, scr);        // Li u
-    row_dots<1024>(W, sy, r, su, scr);         // W (Li u)
+    row_dots<1024>(Li, su, r, sy, scr, TRI_LO);        // Li u
+    row_dots<1024>(W, sy, r, su, scr, TRI_UP);         // W (Li u)
   }
-  for (int q = tid; q < r; q += 1024) x[q] = su[q];
+  for (int q = tid; q < r; q += 1024) {
+    x[q] = su[q];
+    x[MAXR + q] = sy[q];   // the intermediate vector, which the border reuses
+  }
 }
 
 // Search stage: the residual over the searched fibre,
@@ -888,14 +885,17 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
 // (d from the fibre the search stage stored), then
 // u = Li b, g = W^T c, s = d - g^T u,
 //   Li' = [[Li, 0], [-g^T Li, 1]],  W' = [[W, -W u / s], [0, 1 / s]]
-// (leading dimension MAXR, transposes alongside).  amax0 is the value of
-// *amax read at the start of the kernel.  Every thread of the block calls it.
+// (leading dimension MAXR, transposes alongside).  One side is already at
+// xs (k_sample_select): after a row search the pivot row's c was the solved
+// vector, so g = xs[MAXR..] and Li^T g = xs[..]; after a column search b
+// was, so u and W u are.  amax0 is the value of *amax read at the start of
+// the kernel.  Every thread of the block calls it.
 constexpr int FB = 1024;   // threads of the finishing kernel
 __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int row, int col, double* Li, double* W,
                                double* amax, double amax0, int32_t* info, const double* FLk, const double* FLk1,
-                               const double* FRk1) {
+                               const double* FRk1, const double* xs) {
   constexpr int NW = FB / 64;
-  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[2 * FB];
+  __shared__ double bv[MAXR], cv[MAXR], u[MAXR], gv[MAXR], nl[MAXR], nw[MAXR], scr[FB];
   __shared__ double s_d, s_s;
   const int tid = threadIdx.x;
   const int sl = row % a.rl, il = row / a.rl;     // the pivot row: (s, i_k)
@@ -905,10 +905,20 @@ __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int 
     else if (e < 2 * r) cv[e - r] = FLk[fibre_left_row(sl, il) + (e - r)];   // F_k(s, i_k, e)
     else s_d = bit ? FLk1[fibre_left_row(r, it) + tt] : FLk[fibre_left_row(sl, il) + r];
   }
+  for (int e = tid; e < r; e += FB) {
+    if (bit) {
+      gv[e] = xs[MAXR + e];
+      nl[e] = xs[e];
+    } else {
+      u[e] = xs[MAXR + e];
+      nw[e] = xs[e];
+    }
+  }
   __syncthreads();
   double* Lit = Li + FT;
   double* Wt = W + FT;
-  row_dots2<FB, 16>(Li, bv, u, Wt, cv, gv, r, scr);   // Li b, W^T c
+  if (bit) row_dots<FB>(Li, bv, r, u, scr, TRI_LO);    // Li b
+  else row_dots<FB>(Wt, cv, r, gv, scr, TRI_LO);       // W^T c
   {
     double gu = 0.0, m = 0.0;
     for (int p = tid; p < r; p += FB) {
@@ -917,14 +927,14 @@ __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int 
     }
     gu = wsum(gu);
     m = wave64_max(m);
-    if ((tid & 63) == 0) { nl[tid >> 6] = gu; nw[tid >> 6] = m; }
+    if ((tid & 63) == 0) { scr[tid >> 6] = gu; scr[NW + (tid >> 6)] = m; }   // (nl or nw holds x)
     __syncthreads();
     if (tid == 0) {
       gu = 0.0;
       m = 0.0;
       for (int w = 0; w < NW; ++w) {
-        gu += nl[w];
-        m = fmax(m, nw[w]);
+        gu += scr[w];
+        m = fmax(m, scr[NW + w]);
       }
       s_s = s_d - gu;
       *amax = fmax(fmax(amax0, m), fabs(s_d));
@@ -936,7 +946,8 @@ __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int 
     __syncthreads();
   }
   const double is = 1.0 / s_s;
-  row_dots2<FB, 16>(Lit, gv, nl, W, u, nw, r, scr);   // Li^T g (i.e. g^T Li, old factors), W u
+  if (bit) row_dots<FB>(W, u, r, nw, scr, TRI_UP);     // W u
+  else row_dots<FB>(Lit, gv, r, nl, scr, TRI_UP);      // Li^T g (i.e. g^T Li, old factors)
   for (int e = tid; e <= 2 * r + 1; e += FB) {
     if (e < r) {
       Li[r + (int64_t)e * MAXR] = -nl[e];    // row r, column e
@@ -971,7 +982,7 @@ __global__ void __launch_bounds__(FB) k_finish_step(const StepDesc* desc, const 
                                                      double* amax, int32_t* info, StepRes* mail, uint32_t* mail_seq,
                                                      uint32_t seq, int32_t* sel_next, int16_t* next_left,
                                                      int next_row, const double* FLk, const double* FLk1,
-                                                     const double* FRk1) {
+                                                     const double* FRk1, const double* xs) {
   const StepDesc& sd = desc[*sel];
   const Addr a = sd.a;
   const int bit = sd.bit;
@@ -1014,7 +1025,7 @@ __global__ void __launch_bounds__(FB) k_finish_step(const StepDesc* desc, const 
     res->q_slot[tid] = 0.0;
   }
   __syncthreads();
-  if (s_added) border_factors(a, bit, res, r, row, col, Li, W, amax, amax0, info, FLk, FLk1, FRk1);
+  if (s_added) border_factors(a, bit, res, r, row, col, Li, W, amax, amax0, info, FLk, FLk1, FRk1, xs);
   // the next step of the sweep runs on variant s_added; if the pivot was
   // added, I^{<=k} gains the row (left row s of the pivot, node i_k), which
   // the next step's left set receives after its r_k current rows
@@ -1136,12 +1147,13 @@ struct CoreEval {
 
 // One 16 x 16 output tile of A B with FP64 MFMA: A (16 rows x 4 nst) in LDS in
 // lane order (step s, lane l at s * 64 + l), B(q, p) = Bt[p + q MAXR] for this
-// lane's column p; SB steps of B loads in flight per batch.
-__device__ inline dbl4 mfma_tile_lds(const double* sa, int nst, const double* Bt, int p, int r, int lane) {
+// lane's column p, over the steps [sb, se) (B is zero outside them); SB
+// steps of B loads in flight per batch.
+__device__ inline dbl4 mfma_tile_lds(const double* sa, int sb, int se, const double* Bt, int p, int r, int lane) {
   const int lk = lane >> 4;
   const bool pok = p < r;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s0 = 0; s0 < nst; s0 += SB) {
+  for (int s0 = sb; s0 < se; s0 += SB) {
     double b[SB];
 #pragma unroll
     for (int u = 0; u < SB; ++u) {
@@ -1150,7 +1162,7 @@ __device__ inline dbl4 mfma_tile_lds(const double* sa, int nst, const double* Bt
     }
 #pragma unroll
     for (int u = 0; u < SB; ++u)
-      if (s0 + u < nst) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], b[u], acc, 0, 0, 0);
+      if (s0 + u < se) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], b[u], acc, 0, 0, 0);
   }
   return acc;
 }
@@ -1217,18 +1229,22 @@ __global__ void __launch_bounds__(CW * 64) k_eval_solve(CoreEval ce, CoreSolve c
   }
   __syncthreads();
   const int ntile = (r + 15) / 16;
-  for (int jt = wv; jt < ntile; jt += CW) {   // T = F W
+  for (int it = 0; it * CW < ntile; ++it) {   // T = F W (W upper: rows q <= p of column p)
+    const int jt = snake_tile(it, wv, CW);
+    if (jt >= ntile) continue;
     const int p = jt * 16 + li;
-    const dbl4 t = mfma_tile_lds(sa, nst, cs.W[j] + FT, p, r, lane);
+    const dbl4 t = mfma_tile_lds(sa, 0, min(nst, 4 * jt + 4), cs.W[j] + FT, p, r, lane);
     if (p < r)
 #pragma unroll
       for (int v = 0; v < 4; ++v) sb[(p >> 2) * 64 + (p & 3) * 16 + lk + 4 * v] = t[v];
   }
   __syncthreads();
   double* C = cs.C[j];
-  for (int jt = wv; jt < ntile; jt += CW) {   // C = T Li
+  for (int it = 0; it * CW < ntile; ++it) {   // C = T Li (Li lower: rows q >= p of column p)
+    const int jt = snake_tile(it, wv, CW);
+    if (jt >= ntile) continue;
     const int p = jt * 16 + li;
-    const dbl4 c = mfma_tile_lds(sb, nst, cs.Li[j] + FT, p, r, lane);
+    const dbl4 c = mfma_tile_lds(sb, 4 * jt, nst, cs.Li[j] + FT, p, r, lane);
     if (p < r)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -1800,7 +1816,7 @@ tt_status Cross::enqueue_finish(HostStep& h, const HostStep* next) {
   hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(FB), 0, st_, h.desc, h.sel, (const double*)d_R_.as<double>(), dres,
                      h.rk, max_rank(), d_li_[k].as<double>(), d_w_[k].as<double>(), luamax(k), luinfo(k),
                      mail_.dres + k, mail_.dseq + k, h.seq, sel_next, next_left, h.rk, (const double*)fl(k),
-                     (const double*)fl(k + 1), (const double*)fr(k + 1));
+                     (const double*)fl(k + 1), (const double*)fr(k + 1), (const double*)d_x_.as<double>());
   // the fibre the search did not evaluate, when the pivot is added
   int nf = 0;
   for (int v = 0; v < h.nvar; ++v) nf = std::max(nf, h.bit[v] ? h.rows[v] : h.cols);
@@ -2143,7 +2159,7 @@ tt_status Cross::run(CrossOut* out) {
     TTK_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_eval_solve),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)solve_lds(MAXR)));
   TTK_TRY(mail_.alloc());
-  TTK_TRY(d_x_.alloc(MAXR * sizeof(double)));   // the search stage's P^{-1} u
+  TTK_TRY(d_x_.alloc(2 * MAXR * sizeof(double)));   // the search stage's P^{-1} u and its intermediate
   // the residuals of either stage: at most max(rows, cols) <= MAXR x MAXN
   // entries, allocated once so that no queued step ever sees it move
   TTK_TRY(d_R_.alloc((size_t)MAXR * MAXN * sizeof(double)));
