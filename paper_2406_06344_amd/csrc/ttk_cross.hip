@@ -453,13 +453,13 @@ __device__ inline bool tri_in(int tri, int t, int q) {
 // out[t] = sum_q M(t, q) v[q] for t < r (row t of M, leading dimension
 // MAXR, so a wave's loads are contiguous).  With r rounded up to 64 as ru,
 // min(8, BS / ru) threads share a row, each over a contiguous range of q in
-// batches of 32 loads issued together (one batch covers r <= 128 for
-// BS = 256 and r <= 256 for BS = 1024); the partial sums meet in scratch (BS
-// doubles).  tri: the triangle of M that holds its non-zeros.  Every thread
+// batches of 16 loads issued together (the callers run 1024 threads, whose
+// register budget holds no more without spilling); the partial sums meet in
+// scratch (BS doubles).  TRI: the triangle of M that holds its non-zeros.  Every thread
 // of the block calls it; out is visible to all on return.
-template <int BS>
-__device__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch, int tri) {
-  constexpr int RB = 32;
+template <int BS, int TRI>
+__device__ __forceinline__ void row_dots(const double* M, const double* v, int r, double* out, double* scratch) {
+  constexpr int RB = 16;
   const int ru = (r + 63) & ~63;
   const int S = min(8, BS / ru);
   const int tid = threadIdx.x, t = tid % ru, h = tid / ru;
@@ -469,12 +469,12 @@ __device__ void row_dots(const double* M, const double* v, int r, double* out, d
     const int q0 = h * chunk, q1 = min(r, q0 + chunk);
     double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int q = q0; q < q1; q += RB) {
-      if (tri == TRI_LO && q > tri_qmax(t)) break;             // the rest of the row is zero
-      if (tri == TRI_UP && q + RB <= tri_qmin(t)) continue;    // this batch is zero
+      if (TRI == TRI_LO && q > tri_qmax(t)) break;             // the rest of the row is zero
+      if (TRI == TRI_UP && q + RB <= tri_qmin(t)) continue;    // this batch is zero
       double mv[RB];
 #pragma unroll
       for (int u = 0; u < RB; ++u)
-        mv[u] = (q + u < q1 && tri_in(tri, t, q + u)) ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
+        mv[u] = (q + u < q1 && tri_in(TRI, t, q + u)) ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
 #pragma unroll
       for (int u = 0; u < RB; ++u) a[u & 7] += q + u < q1 ? mv[u] * v[q + u] : 0.0;
     }
@@ -786,11 +786,11 @@ __global__ void __launch_bounds__(1024) k_sample_select(KSpec ks, const StepDesc
     res->q_slot[0] = fmax(res->q_slot[0], m);
   }
   if (bit) {
-    row_dots<1024>(W + FT, su, r, sy, scr, TRI_LO);    // W^T u
-    row_dots<1024>(Li + FT, sy, r, su, scr, TRI_UP);   // Li^T (W^T u), into su (u is consumed)
+    row_dots<1024, TRI_LO>(W + FT, su, r, sy, scr);    // W^T u
+    row_dots<1024, TRI_UP>(Li + FT, sy, r, su, scr);   // Li^T (W^T u), into su (u is consumed)
   } else {
-    row_dots<1024>(Li, su, r, sy, scr, TRI_LO);        // Li u
-    row_dots<1024>(W, sy, r, su, scr, TRI_UP);         // W (Li u)
+    row_dots<1024, TRI_LO>(Li, su, r, sy, scr);        // Li u
+    row_dots<1024, TRI_UP>(W, sy, r, su, scr);         // W (Li u)
   }
   for (int q = tid; q < r; q += 1024) {
     x[q] = su[q];
@@ -917,8 +917,8 @@ __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int 
   __syncthreads();
   double* Lit = Li + FT;
   double* Wt = W + FT;
-  if (bit) row_dots<FB>(Li, bv, r, u, scr, TRI_LO);    // Li b
-  else row_dots<FB>(Wt, cv, r, gv, scr, TRI_LO);       // W^T c
+  if (bit) row_dots<FB, TRI_LO>(Li, bv, r, u, scr);    // Li b
+  else row_dots<FB, TRI_LO>(Wt, cv, r, gv, scr);       // W^T c
   {
     double gu = 0.0, m = 0.0;
     for (int p = tid; p < r; p += FB) {
@@ -946,8 +946,8 @@ __device__ void border_factors(const Addr& a, int bit, StepRes* res, int r, int 
     __syncthreads();
   }
   const double is = 1.0 / s_s;
-  if (bit) row_dots<FB>(W, u, r, nw, scr, TRI_UP);     // W u
-  else row_dots<FB>(Lit, gv, r, nl, scr, TRI_UP);      // Li^T g (i.e. g^T Li, old factors)
+  if (bit) row_dots<FB, TRI_UP>(W, u, r, nw, scr);     // W u
+  else row_dots<FB, TRI_UP>(Lit, gv, r, nl, scr);      // Li^T g (i.e. g^T Li, old factors)
   for (int e = tid; e <= 2 * r + 1; e += FB) {
     if (e < r) {
       Li[r + (int64_t)e * MAXR] = -nl[e];    // row r, column e
