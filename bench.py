@@ -163,6 +163,7 @@ def bench_global(args, torch, pkg):
     K0 = pkg.eval_dense(torch.tensor(X[si]), torch.tensor(X[si]), th[0], w.kind, w.d, dtype=torch.float64)
     Zs = Z[si].double()
     err_g2 = (torch.linalg.norm(K0 - (Zs * lam.double()) @ Zs.t()) / torch.linalg.norm(K0)).item()
+    hm = bench_hmatrix(w, X, th, si, torch, pkg)
     rows = 2 * w.n_src
     res = base_result(w, args, rows / (ms / 1000.0), "rows/s", ms, B, {"variant": "Global-1", "X=Y": True})
     res.update({"ranks": inf["ranks"], "cross_ranks": inf["cross_ranks"], "cross_sweeps": inf["sweeps"],
@@ -176,11 +177,54 @@ def bench_global(args, torch, pkg):
                             "note": "Global-2 for the first theta: eigen-truncation of R Hhat R^T and Z = Q Uhat "
                                     "(online, host-synchronised), then y = Z diag(lam) Z^T x for all right-hand "
                                     "sides"},
-                "accuracy_note": "Q W Q^T against dense float64 K(X, X) on a 4000-point subsample, worst theta"})
+                "accuracy_note": "Q W Q^T against dense float64 K(X, X) on a 4000-point subsample, worst theta",
+                "hmatrix": hm})
     res["roofline"] = {"kernel": "Global-1 apply (Q^T x, W, Q z)", "bound": "hbm",
                        "achieved": res["global_apply_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                        "frac": round(res["global_apply_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None}
     return res
+
+
+def bench_hmatrix(w, X, th, si, torch, pkg, n_theta=4, leaf=400, tol=1e-6):
+    """The X = Y problem through the hierarchical form of Section 5: the far
+    blocks of a uniform tree over the unit cube (interaction lists of every
+    level >= 2) as PTTK low-rank blocks, one TT per geometry class, the near
+    blocks (neighbouring leaves) summed directly.  Build time, apply time for
+    n_theta thetas at once, and the error of H(theta) x against dense float64
+    K(X, X) x on the subsampled rows si (K's rows summed over all N columns
+    in chunks)."""
+    N = X.shape[0]
+    Xt = torch.tensor(X, dtype=torch.float32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = pkg.HMatrix.build(Xt, w.kind, w.d, w.box_s, w.box_theta, leaf_points=leaf, n_spatial=w.n_spatial,
+                          n_param=w.n_param, tol=tol, dtype=torch.float32, max_sweeps=400)
+    torch.cuda.synchronize()
+    ms_build = (time.perf_counter() - t0) * 1000.0
+    inf = H.info()
+    print(f"hmatrix built: {inf['far_pairs']} far pairs, {inf['num_classes']} classes, {ms_build:.0f} ms",
+          file=sys.stderr, flush=True)
+    thb = torch.tensor(th[:n_theta], dtype=torch.float32, device="cuda")
+    xs = synth.rhs(N, n_theta, seed=4).T.copy()
+    xd = torch.tensor(xs, dtype=torch.float32, device="cuda")
+    ms_apply = time_events(lambda: H.apply(thb, xd), 3, torch)
+    Y = H.apply(thb, xd).double()
+    Xs = torch.tensor(X[si])
+    errs = []
+    for b in range(n_theta):
+        ref = torch.zeros(len(si), dtype=torch.float64, device="cuda")
+        xb = torch.tensor(xs[b], dtype=torch.float64, device="cuda")
+        for c0 in range(0, N, 25000):
+            K = pkg.eval_dense(Xs, torch.tensor(X[c0:c0 + 25000]), th[b], w.kind, w.d, dtype=torch.float64)
+            ref += K @ xb[c0:c0 + 25000]
+        got = Y[b][torch.tensor(si, device="cuda")]
+        errs.append((torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item())
+    return {"levels": inf["levels"], "classes": inf["num_classes"], "far_pairs": inf["far_pairs"],
+            "near_pairs": inf["near_pairs"], "leaf_points": leaf, "tol": tol, "build_ms": round(ms_build, 1),
+            "apply_ms_per_theta": round(ms_apply / n_theta, 3), "thetas": n_theta, "status": H.status,
+            "max_rel_err_vs_dense_fp64": float(f"{max(errs):.3e}"),
+            "note": "H(theta) x against dense float64 K(X, X) x, rows of the 4000-point subsample summed over all "
+                    "N columns; far blocks PTTK (float32 bulk), near blocks direct"}
 
 
 def oracle_baseline(w, ranks, n_pts, n_theta, threads_note=True):

@@ -432,7 +432,8 @@ typedef struct {
 /* p: kernel, grid sizes, tolerance, dtype; box_s = the root box (box_t is
  * ignored).  X: device, dtype, SoA d x N, inside the root box.  Synchronises
  * `stream`.  TTK_ERR_ARG: no points, leaf_points < 1, an empty root box or a
- * parameter error of the pair batch. */
+ * parameter error of the pair batch.  TTK_WARN_NOT_CONVERGED: the cross of at
+ * least one geometry class stopped above tol; *out is set and usable. */
 tt_status tt_kernel_hmat_build(const tt_kernel_params* p, const void* X, int64_t N, int leaf_points, void* stream,
                                tt_kernel_hmat_t* out);
 

@@ -641,6 +641,7 @@ class HMatrix:
         self.dtype = dtype
         self.n = n
         self.d_theta = params.d_theta
+        self.status = 0
 
     @classmethod
     def build(cls, X, kind, d, box, box_theta=(), leaf_points=64, n_spatial=16, n_param=None, tol=1e-6,
@@ -651,9 +652,11 @@ class HMatrix:
         p = make_params(kind, d, box, box, box_theta, n_spatial, n_param, tol, dtype, **kw)
         Xs = _soa(X, dtype, d, "X")
         h = ctypes.c_void_p()
-        check(lib.tt_kernel_hmat_build(ctypes.byref(p), _ptr(Xs), Xs.shape[1], int(leaf_points), _stream_ptr(stream),
-                                       ctypes.byref(h)))
-        return cls(h, p, dtype, Xs.shape[1])
+        st = check(lib.tt_kernel_hmat_build(ctypes.byref(p), _ptr(Xs), Xs.shape[1], int(leaf_points),
+                                            _stream_ptr(stream), ctypes.byref(h)))
+        H = cls(h, p, dtype, Xs.shape[1])
+        H.status = st   # 0, or TTK_WARN_NOT_CONVERGED (1): a class's cross stopped above tol
+        return H
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -197,6 +197,7 @@ tt_status tt_kernel_hmat_build(const tt_kernel_params* p, const void* X, int64_t
   h->dtype = P.dtype;
   h->es = P.dtype == TTK_FP32 ? 4 : 8;
   const int d = P.d;
+  tt_status warn = TTK_OK;
   // the leaf level: the smallest L with N / 2^{L d} <= leaf_points (Morton codes in 30 bits)
   int L = 0;
   while ((double)N / std::ldexp(1.0, L * d) > leaf_points && (L + 1) * d <= 30) ++L;
@@ -355,7 +356,8 @@ tt_status tt_kernel_hmat_build(const tt_kernel_params* p, const void* X, int64_t
     if (!pairs.empty()) {
       const tt_status s = tt_kernel_batch_build(&P, pairs.data(), (int)pairs.size(), h->Xs.p, N, h->Xs.p, N, stream,
                                                 &h->far);
-      if (s != TTK_OK) return s;
+      if (s < 0) return s;
+      if (s == TTK_WARN_NOT_CONVERGED) warn = s;   // (a class's cross stopped above tol: kept, and reported)
       tt_kernel_batch_info bi{};
       TTK_TRY(tt_kernel_batch_get_info(h->far, &bi, nullptr, nullptr));
       h->info.num_classes = bi.num_classes;
@@ -367,7 +369,8 @@ tt_status tt_kernel_hmat_build(const tt_kernel_params* p, const void* X, int64_t
   TTK_TRY(make_grid(&P, &g));
   h->ks = KSpec{P.kind, P.d, P.d_theta, g.D, P.kernel_const, nullptr, {P.theta_fixed[0], P.theta_fixed[1]}};
   *out = h.release();
-  return TTK_OK;
+  if (warn != TTK_OK) set_error("the cross of at least one geometry class stopped above tol");
+  return warn;
 }
 
 tt_status tt_kernel_hmat_apply(tt_kernel_hmat_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
