@@ -63,6 +63,17 @@ __global__ void k_q_rowmajor(const double* Q, int64_t N, int k, T* out) {
 
 // Mh_b <- Mh_b + Mh_b^T (in place, k x k, one block per b) and copies to Jb
 // (the Jacobi input, overwritten by the SVD).
+// B_b = A_b^T for square k x k matrices, b = blockIdx.y (stride s)
+__global__ void k_transpose_batched(const double* A, int k, size_t s, double* B) {
+  A += blockIdx.y * s;
+  B += blockIdx.y * s;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)k * k;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    B[j + (size_t)i * k] = A[i + (size_t)j * k];
+  }
+}
+
 __global__ void k_sym_copy(double* Mh, double* J, int k, size_t stride) {
   double* M = Mh + blockIdx.x * stride;
   double* Jb = J + blockIdx.x * stride;
@@ -187,6 +198,15 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
   if (k <= 141) {
     jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);
   } else {
+    // The block iteration runs on L_b = R2_b^T from J_b = Q2_b R2_b: J_b is
+    // symmetric, so J_b = L_b Q2_b^T and L_b has its singular values and left
+    // vectors, and one QR step leaves L_b's columns far closer to orthogonal
+    // (fewer sweeps).  R2_b goes to V_b (unused on this path), the QR's
+    // workspace to VS (used only after the iteration).
+    if (qr_r_batched_work(k, B) <= (size_t)B * kk &&
+        qr_r_batched(J, k, k, kk, V, k, kk, VS, B, st) == TTK_OK)
+      hipLaunchKernelGGL(k_transpose_batched, dim3(nblocks((int64_t)k * k), B), dim3(256), 0, st, (const double*)V,
+                         k, kk, J);
     if (!jacobi_svd_left_batched(J, k, k, kk, sig, sS, B, st))
       jacobi_svd_batched(J, k, k, kk, V, k, kk, sig, sS, B, st);   // (k above 512)
     Vuse = J;   // normalised left vectors on either path
@@ -201,7 +221,8 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
 
 size_t global2_work(int rs, int rt) {
   const size_t k = (size_t)rs + rt;
-  return global_online_work(rs, rt, 1) + 2 * k * k + jacobi_sigma_doubles((int)k) + 64;
+  return global_online_work(rs, rt, 1) + 2 * k * k + jacobi_sigma_doubles((int)k) + 64 + k * k +
+         qr_r_batched_work((int)k, 1);
 }
 
 tt_status global2_online(const double* R, int rs, int rt, const double* M, double eps, double* work, double** Uhat,
@@ -215,9 +236,15 @@ tt_status global2_online(const double* R, int rs, int rt, const double* M, doubl
   global_online(R, rs, rt, M, 1, TTK_FP64, Wp, gw, st);
   const double* Mh = gw + (size_t)k * rt;               // R Hhat R^T, symmetrised (global_online's layout)
   double* nrm = sig + jacobi_sigma_doubles(k);          // ||Mh||_F
+  double* R2 = nrm + 64;                                // QR preconditioning: R2, then the QR's workspace
   nrm2(Mh, (int64_t)kk, nrm, st);
   TTK_HIP(hipMemcpyAsync(J, Wp, kk * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (!jacobi_svd_left(J, k, k, sig, st)) {   // (k above 256: the single-workgroup form, with V)
+  // as in global_online: the iteration on L = R2^T from W_+ = Q2 R2 (W_+ symmetric)
+  if (k > 141 && qr_r_batched(J, k, k, kk, R2, k, kk, R2 + kk, 1, st) == TTK_OK)
+    hipLaunchKernelGGL(k_transpose_batched, dim3(nblocks((int64_t)k * k), 1), dim3(256), 0, st, (const double*)R2, k,
+                       kk, J);
+  if (!jacobi_svd_left(J, k, k, sig, st)) {   // (k above 512: the single-workgroup form, with V, of W_+ itself)
+    TTK_HIP(hipMemcpyAsync(J, Wp, kk * sizeof(double), hipMemcpyDeviceToDevice, st));
     DBuf V;
     TTK_TRY(V.alloc(kk * sizeof(double)));
     jacobi_svd(J, k, k, V.as<double>(), k, sig, st);

@@ -153,6 +153,12 @@ tt_status qr_factor(double* A, int m, int n, int lda, double* R, int ldr, double
 // C (m x nc, ldc) <- Q C with the Q of a qr_factor of A (m x n) and its work.
 tt_status qr_apply_q(const double* A, int m, int n, int lda, double* work, double* C, int nc, int ldc,
                      hipStream_t st);
+// R factors (n x n upper, ld ldr, at R + b sR) of `count` square matrices
+// (A + b sA, ld lda, n <= 512, overwritten by their reflectors), all in one
+// sequence of batched launches; work holds qr_r_batched_work(n, count).
+size_t qr_r_batched_work(int n, int count);
+tt_status qr_r_batched(double* A, int n, int lda, size_t sA, double* R, int ldr, size_t sR, double* work, int count,
+                       hipStream_t st);
 // Tall-skinny QR of an N x r matrix (r <= 512, N >= r): A(p, c) at
 // A[p sp + c sc] in dtype.  tsqr_factor writes R (r x r upper, FP64, device,
 // leading dimension ldr) and keeps the blocks' reflectors in *ts;

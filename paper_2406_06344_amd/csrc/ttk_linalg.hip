@@ -1833,6 +1833,51 @@ bool tsqr_lds(F kern, size_t sh) {
 
 }  // namespace
 
+// R factors of `count` square n x n matrices at once (matrix b at A + b sA,
+// overwritten by its reflectors; R_b at R + b sR, ld ldr): the register
+// panels and the trailing updates of the tall-skinny QR, batched over the
+// matrices.  work: qr_r_batched_work(n, count) doubles.
+size_t qr_r_batched_work(int n, int count) {
+  constexpr int NB = 16;
+  const size_t npan = (size_t)(n + NB - 1) / NB;
+  return (size_t)count * ((size_t)n + (size_t)n * NB + npan * NB * NB);
+}
+
+__global__ void k_extract_r_batched(const double* A, int n, int lda, size_t sA, double* R, int ldr, size_t sR) {
+  A += blockIdx.y * sA;
+  R += blockIdx.y * sR;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)n * n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    R[i + (size_t)c * ldr] = (i <= c) ? A[i + (size_t)c * lda] : 0.0;
+  }
+}
+
+tt_status qr_r_batched(double* A, int n, int lda, size_t sA, double* R, int ldr, size_t sR, double* work, int count,
+                       hipStream_t st) {
+  constexpr int NB = 16;
+  if (n < 1 || n > 4 * QRC || count < 1 || count > 65535)
+    return fail(TTK_ERR_UNSUPPORTED, "batched QR of %d matrices of order %d", count, n);
+  const int npan = (n + NB - 1) / NB;
+  double* tau = work;
+  double* V = tau + (size_t)count * n;
+  double* T = V + (size_t)count * n * NB;
+  for (int p = 0; p < npan; ++p) {
+    const int j0 = p * NB, jb = std::min(NB, n - j0), mm = n - j0;
+    if (!qr_panel_reg(A + j0 + (size_t)j0 * lda, mm, jb, lda, tau + j0, V, T + (size_t)p * NB * NB, st, count, sA,
+                      (size_t)n, (size_t)n * NB, (size_t)npan * NB * NB))
+      return fail(TTK_ERR_UNSUPPORTED, "batched QR: panel of %d rows", mm);
+    const int nc = n - j0 - jb;
+    if (nc > 0)
+      tsqr_update(V, mm, jb, T + (size_t)p * NB * NB, 1, A + j0 + (size_t)(j0 + jb) * lda, nc, lda, count,
+                  (size_t)n * NB, (size_t)npan * NB * NB, sA, nullptr, 0, st);
+  }
+  hipLaunchKernelGGL(k_extract_r_batched, dim3(tsqr_grid((int64_t)n * n), count), dim3(256), 0, st,
+                     (const double*)A, n, lda, sA, R, ldr, sR);
+  TTK_HIP(hipGetLastError());
+  return TTK_OK;
+}
+
 tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,
                       int ldr, hipStream_t st) {
   constexpr int NB = 16;
