@@ -100,19 +100,11 @@ __global__ void k_scale_cols(const double* V, const double* sig, size_t sS, int 
   for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) out[e] = Vb[e] * sb[e / k];
 }
 
-// W_b = (Mh_b + VS_b V_b^T) / 2 in the output precision.
+// out[e] = C[e] in the output precision
 template <class T>
-__global__ void k_psd_part(const double* Mh, const double* VS, const double* V, int k, size_t stride, T* W) {
-  const double* M = Mh + blockIdx.x * stride;
-  const double* A = VS + blockIdx.x * stride;
-  const double* B = V + blockIdx.x * stride;
-  T* out = W + blockIdx.x * (size_t)k * k;
-  for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
-    const int i = (int)(e % k), j = (int)(e / k);
-    double s = 0.0;
-    for (int q = 0; q < k; ++q) s += A[i + (size_t)q * k] * B[j + (size_t)q * k];
-    out[e] = (T)(0.5 * (M[e] + s));
-  }
+__global__ void k_store(const double* C, int64_t n, T* out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = (T)C[e];
 }
 
 inline unsigned nblocks(int64_t n, int64_t cap = 8192) {
@@ -212,11 +204,18 @@ void global_online(const double* R, int rs, int rt, const double* M, int B, int 
     Vuse = J;   // normalised left vectors on either path
   }
   hipLaunchKernelGGL(k_scale_cols, dim3(B), dim3(256), 0, st, Vuse, sig, sS, k, kk, VS);
+  // W_b = (Mh_b + VS_b Vuse_b^T) / 2, one product per theta into whichever
+  // of J and V does not hold the vectors, then in the output precision
+  double* C = Vuse == J ? V : J;
+  (void)hipMemcpyAsync(C, Mh, (size_t)B * kk * sizeof(double), hipMemcpyDeviceToDevice, st);
+  for (int b = 0; b < B; ++b)
+    gemm64(0, 1, k, k, k, 0.5, VS + (size_t)b * kk, k, Vuse + (size_t)b * kk, k, 0.5, C + (size_t)b * kk, k, st);
   if (out_dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_psd_part<float>, dim3(B), dim3(256), 0, st, Mh, VS, Vuse, k, kk, static_cast<float*>(W));
+    hipLaunchKernelGGL(k_store<float>, dim3(nblocks((int64_t)B * kk)), dim3(256), 0, st, (const double*)C,
+                       (int64_t)B * kk, static_cast<float*>(W));
   else
-    hipLaunchKernelGGL(k_psd_part<double>, dim3(B), dim3(256), 0, st, Mh, VS, Vuse, k, kk,
-                       static_cast<double*>(W));
+    hipLaunchKernelGGL(k_store<double>, dim3(nblocks((int64_t)B * kk)), dim3(256), 0, st, (const double*)C,
+                       (int64_t)B * kk, static_cast<double*>(W));
 }
 
 size_t global2_work(int rs, int rt) {
