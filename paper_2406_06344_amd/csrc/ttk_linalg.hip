@@ -848,8 +848,10 @@ __global__ void __launch_bounds__(QSW * 64) k_qr_apply_w(const double* V, int mm
 }
 
 // Sum of a tile's nch partials in chunk order, into chunk 0's slot (each
-// thread reads and writes its own entry only).
-__global__ void __launch_bounds__(256) k_qr_apply_sum(double* Wp, int nch, int tiles) {
+// thread reads and writes its own entry only; batched: blockIdx.y picks the
+// matrix, its partials at Wp + b sW).
+__global__ void __launch_bounds__(256) k_qr_apply_sum(double* Wp, int nch, int tiles, size_t sW = 0) {
+  Wp += blockIdx.y * sW;
   const int ct = blockIdx.x, e = threadIdx.x;
   double sum = 0.0;
   for (int r = 0; r < nch; ++r) sum += Wp[((size_t)r * tiles + ct) * 256 + e];
@@ -930,7 +932,7 @@ void qr_apply(const double* V, int mm, int jb, const double* T, int trans, doubl
                      (size_t)0, (size_t)0, (size_t)0);
   int nparts = nch;
   if (nch > QSUM) {
-    hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles), dim3(256), 0, st, Wp, nch, tiles);
+    hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles), dim3(256), 0, st, Wp, nch, tiles, (size_t)0);
     nparts = 1;
   }
   hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
@@ -1815,8 +1817,12 @@ void tsqr_update(const double* V, int mm, int jb, const double* T, int trans, do
   const int nch = (mm + QRC - 1) / QRC;
   hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda,
                      Wp, sV, sC, sW);
+  // the partials summed once per tile (in chunk order, as k_qr_apply_c
+  // would), so that the nch chunks of a tile each read one 16 x 16 sum
+  // instead of all nch partials
+  hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles, nb), dim3(256), 0, st, Wp, nch, tiles, sW);
   hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
-                     (const double*)Wp, nch, sV, sT, sC, sW);
+                     (const double*)Wp, 1, sV, sT, sC, sW);
 }
 
 // LDS of the strided copies: TR (c + 1) doubles, with the attribute raised once past 48 KB.
