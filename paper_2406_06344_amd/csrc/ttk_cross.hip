@@ -40,6 +40,10 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <condition_variable>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 #include "ttk_eval_dev.h"
@@ -1256,6 +1260,102 @@ __global__ void __launch_bounds__(CW * 64) k_eval_solve(CoreEval ce, CoreSolve c
 
 inline int nblk(int64_t n, int bs) { return (int)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
+// A few host threads for the update steps' sample draws (Floyd's algorithm
+// over millions of positions, the host's largest cost per step), which run
+// for all staged steps and both variants at once.  run(n, f) calls f(i) for
+// i < n on the workers and the calling thread and returns when all are
+// done.  Workers spin briefly for the next batch (batches come every few
+// hundred microseconds during a cross), then sleep.  One batch at a time.
+class DrawPool {
+ public:
+  static DrawPool& get() {
+    static DrawPool pool;
+    return pool;
+  }
+  template <class F>
+  void run(int n, F&& f) {
+    if (n <= 1 || th_.empty()) {
+      for (int i = 0; i < n; ++i) f(i);
+      return;
+    }
+    std::lock_guard<std::mutex> one(batch_);
+    Task t{[](void* c, int i) { (*static_cast<F*>(c))(i); }, &f, n, 0};
+    done_.store(0, std::memory_order_relaxed);
+    {
+      std::lock_guard<std::mutex> g(m_);
+      t.gen = (uint32_t)(gen_.load(std::memory_order_relaxed) + 1);
+      ticket_.store((uint64_t)t.gen << 32, std::memory_order_relaxed);
+      task_ = t;
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    work(t);
+    while (done_.load(std::memory_order_acquire) < n) std::this_thread::yield();
+  }
+  ~DrawPool() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      stop_ = true;
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+
+ private:
+  struct Task {
+    void (*call)(void*, int) = nullptr;
+    void* ctx = nullptr;
+    int n = 0;
+    uint32_t gen = 0;
+  };
+  DrawPool() {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nw = (int)std::min<unsigned>(hw > 1 ? hw - 1 : 0, 7);
+    for (int i = 0; i < nw; ++i) th_.emplace_back([this] { loop(); });
+  }
+  // takes indices of batch t.gen while any are left: the ticket holds the
+  // batch's generation (high half) and its next index (low half), and an
+  // index is taken only by a compare-exchange that sees t's generation, so a
+  // worker late for a finished batch takes nothing from the next one
+  void work(const Task& t) {
+    for (;;) {
+      uint64_t cur = ticket_.load(std::memory_order_acquire);
+      if ((uint32_t)(cur >> 32) != t.gen || (int)(uint32_t)cur >= t.n) return;
+      if (!ticket_.compare_exchange_weak(cur, cur + 1, std::memory_order_acq_rel)) continue;
+      t.call(t.ctx, (int)(uint32_t)cur);
+      done_.fetch_add(1, std::memory_order_acq_rel);
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      // spin for about a millisecond for the next batch, then sleep
+      const auto t0 = std::chrono::steady_clock::now();
+      while (gen_.load(std::memory_order_acquire) == seen &&
+             std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(1))
+        std::this_thread::yield();
+      Task t;
+      {
+        std::unique_lock<std::mutex> g(m_);
+        cv_.wait(g, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+        seen = gen_.load(std::memory_order_acquire);
+        if (stop_) return;
+        t = task_;
+      }
+      work(t);
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex m_, batch_;
+  std::condition_variable cv_;
+  std::atomic<uint64_t> gen_{0}, ticket_{0};
+  std::atomic<int> done_{0};
+  Task task_;
+  bool stop_ = false;
+};
+
+
 // Key of a multi-index (node indices < 32, at most 8 dims: 5 bits each).
 inline uint64_t mkey(const int32_t* e, int len) {
   uint64_t k = (uint64_t)len;
@@ -1325,6 +1425,7 @@ class Cross {
     int k = 0, sweep = 0, rk = 0, nvar = 1, var = 0, cols = 0;
     int rows[2] = {0, 0}, ns[2] = {0, 0}, bit[2] = {0, 0};
     std::vector<int64_t> lin[2];        // samples (linear positions), generation order
+    std::vector<int32_t> hi[2];         // the variant's pivot rows/columns and sample rows/columns
     const StepDesc* desc = nullptr;     // device, two entries
     const int32_t* sel = nullptr;       // device: the entry the kernels read
     int16_t* left = nullptr;            // device I^{<=k-1}, spare row after rank(k-1) rows
@@ -1344,6 +1445,8 @@ class Cross {
   }
   tt_status reserve_buffers();
   tt_status prepare_step(HostStep& h, int k, int sweep, bool speculate);
+  void draw_variant(HostStep& h, int v);   // the samples of variant v (thread-safe across steps and variants)
+  tt_status upload_step(HostStep& h);
   tt_status enqueue_front(const HostStep& h);
   tt_status enqueue_finish(HostStep& h, const HostStep* next);
   tt_status collect(const HostStep& h, tt_kernel_decision* rec);
@@ -1352,7 +1455,9 @@ class Cross {
   tt_status run_sweep(int sweep, bool staged, bool queued, std::vector<tt_kernel_decision>* log, int* added,
                       bool* next_staged);
   int first_half() const { return N_ / 2; }   // steps 1..first_half() are staged first
-  tt_status build_cores(std::vector<double*>* C);
+  tt_status test_launch(int j0, int j1, bool last);
+  bool test_queued_ = false;   // the sweep queued its stopping test already
+  uint32_t test_seq_ = 0;      // mailbox sequence number of the queued test
   tt_status stage_core(int k);
   CoreEval ce_{};
   int ce_next_ = 1;   // stopping-test staging: the next core to stage
@@ -1703,8 +1808,9 @@ tt_status Cross::wait_mail(int slot, uint32_t seq) {
 // kernel writes), the right set I^{>k+1}, and per variant the pivot
 // positions, the samples (drawn from the step's own keyed stream, so both
 // variants draw as the oracle does for its r_{k-1}) and the descriptor.
+// Host set-up of step k before its draws: its shape and variant count (and
+// the pivots' positions in the neighbouring sets, looked up on first use).
 tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
-  const int N = N_;
   const int rl0 = rank(k - 1), rr = rank(k + 1), rk = rank(k);
   const int nk = g_.n[k - 1], nk1 = g_.n[k];
   if ((int)pls_[k].size() != rk) {
@@ -1717,6 +1823,39 @@ tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
   h.var = 0;
   h.nvar = (speculate && rl0 < max_rank()) ? 2 : 1;
   h.cols = nk1 * rr;
+  if ((int64_t)(rl0 + h.nvar - 1) * nk > (int64_t)MAXR * MAXN || h.cols > MAXR * MAXN)
+    return fail(TTK_ERR_ARG, "cross: super-core %d unfolding exceeds %d rows or columns", k, MAXR * MAXN);
+  return TTK_OK;
+}
+
+// The samples of variant v of step h (Floyd's algorithm on the step's keyed
+// stream) and the rows and columns the step's kernels read: the pivots'
+// (pivot row, pivot column) positions, then the samples' rows and columns.
+// Reads only host sets that no step changes while the draws run.
+void Cross::draw_variant(HostStep& h, int v) {
+  const int k = h.k, rk = h.rk;
+  const int rl = rank(k - 1) + v, rows = rl * g_.n[k - 1], nk1 = g_.n[k];
+  SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)h.sweep, (uint64_t)k);
+  const int ns = std::max(rows, h.cols);
+  h.lin[v] = g.floyd_unsorted((int64_t)rows * h.cols, ns);
+  h.bit[v] = g.bit();
+  h.rows[v] = rows;
+  h.ns[v] = ns;
+  std::vector<int32_t>& hi = h.hi[v];
+  hi.resize((size_t)2 * rk + 2 * (size_t)ns);
+  for (int q = 0; q < rk; ++q) {
+    hi[q] = pls_[k][q] + pli_[k][q] * rl;
+    hi[rk + q] = prf_[k][q] + prt_[k][q] * nk1;
+  }
+  for (int i = 0; i < ns; ++i) {
+    hi[2 * rk + i] = (int32_t)(h.lin[v][i] / h.cols);
+    hi[2 * rk + ns + i] = (int32_t)(h.lin[v][i] % h.cols);
+  }
+}
+
+// Uploads step k's sets, samples and descriptors to the current arena.
+tt_status Cross::upload_step(HostStep& h) {
+  const int N = N_, k = h.k, rk = h.rk, rr = rank(k + 1), nk = g_.n[k - 1], nk1 = g_.n[k];
   {
     const size_t lk = (size_t)k - 1, nl = (k == 1) ? 0 : L_[k - 1].size();
     const size_t nr = (k + 1 == N) ? 0 : R_[k + 1].size();
@@ -1729,31 +1868,14 @@ tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
     h.left = const_cast<int16_t*>(dl);
   }
   StepDesc hd[2];
-  if ((int64_t)(rl0 + h.nvar - 1) * nk > (int64_t)MAXR * MAXN || h.cols > MAXR * MAXN)
-    return fail(TTK_ERR_ARG, "cross: super-core %d unfolding exceeds %d rows or columns", k, MAXR * MAXN);
   for (int v = 0; v < h.nvar; ++v) {
-    const int rl = rl0 + v, rows = rl * nk;
-    SplitMix64 g = SplitMix64::keyed(P_.seed, RNG_TAG_UPDATE, (uint64_t)sweep, (uint64_t)k);
-    const int ns = std::max(rows, h.cols);
-    h.lin[v] = g.floyd_unsorted((int64_t)rows * h.cols, ns);
-    h.bit[v] = g.bit();
-    h.rows[v] = rows;
-    h.ns[v] = ns;
-    std::vector<int32_t> hi((size_t)2 * rk + 2 * (size_t)ns);
-    for (int q = 0; q < rk; ++q) {
-      hi[q] = pls_[k][q] + pli_[k][q] * rl;
-      hi[rk + q] = prf_[k][q] + prt_[k][q] * nk1;
-    }
-    for (int i = 0; i < ns; ++i) {
-      hi[2 * rk + i] = (int32_t)(h.lin[v][i] / h.cols);
-      hi[2 * rk + ns + i] = (int32_t)(h.lin[v][i] % h.cols);
-    }
+    const int ns = h.ns[v];
     const int32_t* dI = nullptr;
-    TTK_TRY(arena_push(hi.data(), hi.size(), &dI));
+    TTK_TRY(arena_push(h.hi[v].data(), h.hi[v].size(), &dI));
     StepDesc& sd = hd[v];
     sd.a.left = h.left;
     sd.a.right = cur_right_;
-    sd.a.rl = rl;
+    sd.a.rl = rank(k - 1) + v;
     sd.a.lk = k - 1;
     sd.a.rr = rr;
     sd.a.lr = N - k - 1;
@@ -1764,14 +1886,14 @@ tt_status Cross::prepare_step(HostStep& h, int k, int sweep, bool speculate) {
     sd.J = dI + rk;
     sd.srow = dI + 2 * rk;
     sd.scol = dI + 2 * rk + ns;
-    sd.rows = rows;
+    sd.rows = h.rows[v];
     sd.cols = h.cols;
     sd.ns = ns;
     sd.bit = h.bit[v];
   }
   if (h.nvar == 1) hd[1] = hd[0];   // a selector of 1 cannot occur, but stays in bounds
   TTK_TRY(arena_push(hd, 2, &h.desc));
-  h.sel = d_sel_.as<int32_t>() + (speculate ? k : 0);
+  h.sel = d_sel_.as<int32_t>() + (k > 1 ? k : 0);   // (steps after the first select their variant)
   return TTK_OK;
 }
 
@@ -1887,7 +2009,18 @@ tt_status Cross::stage_steps(int sweep, int k0, int k1) {
     ~Use() { a = AR_OTHER; }
   } use(ar_, sweep & 1);
   if (k0 == 1) arena_reset();   // its last readers, two sweeps back, have drained
-  for (int k = k0; k < k1; ++k) TTK_TRY(prepare_step(hs_[k], k, sweep, k > 1));
+  // the steps' shapes, then every step's and variant's draws at once on the
+  // host pool, then the uploads in order
+  int tk[2 * MAXD], tv[2 * MAXD], nt = 0;
+  for (int k = k0; k < k1; ++k) {
+    TTK_TRY(prepare_step(hs_[k], k, sweep, k > 1));
+    for (int v = 0; v < hs_[k].nvar; ++v) {
+      tk[nt] = k;
+      tv[nt++] = v;
+    }
+  }
+  DrawPool::get().run(nt, [&](int i) { draw_variant(hs_[tk[i]], tv[i]); });
+  for (int k = k0; k < k1; ++k) TTK_TRY(upload_step(hs_[k]));
   return arena_flush();
 }
 
@@ -1935,6 +2068,12 @@ tt_status Cross::run_sweep(int sweep, bool staged, bool queued, std::vector<tt_k
     if (k + 1 < N) hs_[k + 1].var = rec.added;
     TTK_TRY(stage_core(k));   // core k's sets are final for this sweep's test
     if (k + 1 == N) TTK_TRY(stage_core(N));
+    // the stopping test, queued in two parts behind the steps still running
+    if (k == N - 2) TTK_TRY(test_launch(0, N - 2, false));
+    if (k == N - 1) {
+      TTK_TRY(test_launch(N >= 3 ? N - 2 : 0, N - 1, true));
+      test_queued_ = true;
+    }
     if (k == kn && sweep + 1 < max_sweeps) {
       // (steps kn + 1.. of this sweep keep their staged records: the next
       // sweep's first half only overwrites hs_[1..h], already collected)
@@ -1972,35 +2111,75 @@ tt_status Cross::stage_core(int k) {
   return TTK_OK;
 }
 
-tt_status Cross::build_cores(std::vector<double*>* C) {
+// The stopping test for cores j0 + 1 .. j1 (C_{j+1} = F_{j+1} P_{j+1}^{-1}
+// by k_eval_solve, then their grouped products with the running test rows,
+// V_{j+1} = V_j C_{j+1}); with `last`, also the last core (C_D = F_D, copied
+// by the same launch), the error fold and its publication to mailbox slot
+// 0.  A sweep queues cores 1 .. N-2 as soon as its step N-2 is collected
+// (their ranks and factors are final), while step N-1 still runs, and the
+// rest after step N-1, so the device waits only for the last part's launch.
+tt_status Cross::test_launch(int j0, int j1, bool last) {
   const int N = N_;
-  C->assign(N, nullptr);
-  for (int k = ce_next_; k <= N; ++k) TTK_TRY(stage_core(k));
-  ce_next_ = 1;   // the next test stages from core 1 again
-  TTK_TRY(arena_flush());
+  for (int k = ce_next_; k <= (last ? N : j1); ++k) TTK_TRY(stage_core(k));
+  if (last) ce_next_ = 1;   // the next test stages from core 1 again
+  if (j0 == 0) TTK_TRY(arena_flush());
   CoreSolve cs{};
-  cs.n = N - 1;
+  CoreEval ce{};
+  cs.n = j1 - j0;
   int nt = 0, rmax = 1;
-  for (int k = 1; k < N; ++k) {
+  for (int j = j0; j < j1; ++j) {
+    const int k = j + 1, q = j - j0;
     const int m = rank(k - 1) * g_.n[k - 1], r = rank(k);
-    TTK_TRY(ensure(d_cint_[k - 1], (size_t)m * r * sizeof(double)));
-    cs.F[k - 1] = d_core_[k - 1].as<double>();
-    cs.C[k - 1] = d_cint_[k - 1].as<double>();
-    cs.Li[k - 1] = d_li_[k].as<double>();
-    cs.W[k - 1] = d_w_[k].as<double>();
-    cs.m[k - 1] = m;
-    cs.r[k - 1] = r;
-    cs.tile[k - 1] = nt;
+    TTK_TRY(ensure(d_cint_[j], (size_t)m * r * sizeof(double)));
+    cs.F[q] = d_core_[j].as<double>();
+    cs.C[q] = d_cint_[j].as<double>();
+    cs.Li[q] = d_li_[k].as<double>();
+    cs.W[q] = d_w_[k].as<double>();
+    cs.m[q] = m;
+    cs.r[q] = r;
+    cs.tile[q] = nt;
     nt += nblk(m, 16);
     rmax = std::max(rmax, r);
-    (*C)[k - 1] = d_cint_[k - 1].as<double>();
+    ce.FL[q] = ce_.FL[j];
+    ce.out[q] = ce_.out[j];
+    ce.nr[q] = ce_.nr[j];
+    ce.rl[q] = ce_.rl[j];
+    ce.size[q] = ce_.size[j];
   }
-  cs.tile[N - 1] = nt;
-  (*C)[N - 1] = d_core_[N - 1].as<double>();
-  // the solve tiles (reading their own fibre rows), then the last fibre
-  const int nlast = nblk(ce_.size[N - 1], CW * 64);
-  hipLaunchKernelGGL(k_eval_solve, dim3(nt + nlast), dim3(CW * 64), solve_lds(rmax), st_, ce_, cs,
-                     d_err_.as<double>());
+  cs.tile[cs.n] = nt;
+  ce.n = cs.n;
+  int nlast = 0;
+  if (last) {   // the last fibre, copied by the blocks past the solve tiles
+    const int q = cs.n;
+    ce.FL[q] = ce_.FL[N - 1];
+    ce.out[q] = ce_.out[N - 1];
+    ce.nr[q] = ce_.nr[N - 1];
+    ce.rl[q] = ce_.rl[N - 1];
+    ce.size[q] = ce_.size[N - 1];
+    ce.n = q + 1;
+    nlast = nblk(ce_.size[N - 1], CW * 64);
+  }
+  if (nt + nlast > 0)
+    hipLaunchKernelGGL(k_eval_solve, dim3(nt + nlast), dim3(CW * 64), solve_lds(rmax), st_, ce, cs,
+                       d_err_.as<double>());
+  const TTTile* tiles = reinterpret_cast<const TTTile*>(d_ttiles_.as<int32_t>());
+  const int jend = last ? N : j1;
+  for (int j = j0; j < jend; ++j) {
+    const double* vin = j == 0 ? d_ones_.as<double>() : d_tv_[(j - 1) & 1].as<double>();
+    const double* C = j < N - 1 ? d_cint_[j].as<double>() : d_core_[N - 1].as<double>();
+    const int nt_j = ttile_off_[j + 1] - ttile_off_[j];
+    hipLaunchKernelGGL(k_tt_core, dim3(nt_j), dim3(TTW * 64), 0, st_, C, rank(j), rank(j + 1), rank(j) * g_.n[j], vin,
+                       j == 0 ? 1 : MAXR, d_tv_[j & 1].as<double>(), MAXR,
+                       (const int32_t*)d_tperm_.as<int32_t>() + (size_t)j * n_test_, tiles + ttile_off_[j]);
+  }
+  if (last) {
+    hipLaunchKernelGGL(k_tt_err, dim3((n_test_ + 255) / 256), dim3(256), 0, st_,
+                       (const double*)d_tv_[(N - 1) & 1].as<double>(), MAXR, (const double*)d_test_val_.as<double>(),
+                       n_test_, d_err_.as<double>());
+    test_seq_ = ++mail_seq_;
+    hipLaunchKernelGGL(k_test_publish, dim3(1), dim3(64), 0, st_, (const double*)d_err_.as<double>(),
+                       (const int32_t*)luinfo(0), N_, mail_.dres, mail_.dseq, test_seq_);
+  }
   TTK_HIP(hipGetLastError());
   return TTK_OK;
 }
@@ -2052,30 +2231,10 @@ tt_status Cross::refine_cores() {
 // result depends on: the returned cores are the test's, and bordering P_k
 // only appends a row and a column beyond the kept rank to its factors.
 tt_status Cross::sampled_error(double* err, bool queue_next) {
-  std::vector<double*> C;
-  TTK_TRY(build_cores(&C));
-  {
-    const double* vin = d_ones_.as<double>();
-    int ldin = 1;
-    const TTTile* tiles = reinterpret_cast<const TTTile*>(d_ttiles_.as<int32_t>());
-    for (int k = 0; k < N_; ++k) {
-      double* vout = d_tv_[k & 1].as<double>();
-      const int nt = ttile_off_[k + 1] - ttile_off_[k];
-      hipLaunchKernelGGL(k_tt_core, dim3(nt), dim3(TTW * 64), 0, st_, (const double*)C[k], rank(k), rank(k + 1),
-                         rank(k) * g_.n[k], vin, ldin, vout, MAXR,
-                         (const int32_t*)d_tperm_.as<int32_t>() + (size_t)k * n_test_, tiles + ttile_off_[k]);
-      vin = vout;
-      ldin = MAXR;
-    }
-    hipLaunchKernelGGL(k_tt_err, dim3((n_test_ + 255) / 256), dim3(256), 0, st_, vin, ldin,
-                       (const double*)d_test_val_.as<double>(), n_test_, d_err_.as<double>());
-  }
-  const uint32_t seq = ++mail_seq_;
-  hipLaunchKernelGGL(k_test_publish, dim3(1), dim3(64), 0, st_, (const double*)d_err_.as<double>(),
-                     (const int32_t*)luinfo(0), N_, mail_.dres, mail_.dseq, seq);
-  TTK_HIP(hipGetLastError());
+  if (!test_queued_) TTK_TRY(test_launch(0, N_ - 1, true));
+  test_queued_ = false;
   if (queue_next) TTK_TRY(enqueue_first_half());
-  TTK_TRY(wait_mail(0, seq));
+  TTK_TRY(wait_mail(0, test_seq_));
   StepRes r;
   std::memcpy(&r, mail_.res, offsetof(StepRes, s_slot));
   if (r.info != 0) {

@@ -83,6 +83,18 @@ __global__ void k_pad_rows(const double* S, int rows, int lds, double* C, int mc
 
 inline int nb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
+// Unfoldings taller than this are factored by the tall-skinny QR (blocks of
+// at most 2048 rows, whose register panels hold a whole column block),
+// shorter ones by the blocked Householder QR of one block.
+constexpr int ROUND_TALL = 2048;
+
+// I[:, :c] of an r x r identity (column-major, ld r)
+__global__ void k_eye_cols(double* I, int r, int c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)r * c) return;
+  I[e] = (e % r) == (e / r) ? 1.0 : 0.0;
+}
+
 struct Cores {
   std::vector<DBuf> g;       // device copies, core k as G^{2}/G^{1}-compatible memory
   std::vector<int> r;         // r_0..r_D
@@ -106,7 +118,16 @@ tt_status orth_right(Cores& c, int i, DBuf& A, DBuf& R, DBuf& T, DBuf& tau, hipS
   if (ma > m) fill_zero(A.p, (size_t)ma * r0 * sizeof(double), st);
   hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)r0 * m)), dim3(256), 0, st, G, r0, m, r0, A.as<double>(),
                      ma);
-  TTK_TRY(qr_blocked(A.as<double>(), ma, r0, ma, R.as<double>(), r0, tau.as<double>(), st));
+  if (ma > ROUND_TALL) {   // Q[:, :rp] = Q [I[:, :rp]; 0] into A
+    TsqrState ts;
+    TTK_TRY(tsqr_factor(TTK_FP64, A.as<double>(), 1, ma, ma, r0, &ts, R.as<double>(), r0, st));
+    DBuf E;
+    TTK_TRY(E.alloc((size_t)r0 * rp * sizeof(double)));
+    hipLaunchKernelGGL(k_eye_cols, dim3(nb((int64_t)r0 * rp)), dim3(256), 0, st, E.as<double>(), r0, rp);
+    TTK_TRY(tsqr_apply(&ts, E.as<double>(), r0, rp, TTK_FP64, A.as<double>(), 1, ma, st));
+  } else {
+    TTK_TRY(qr_blocked(A.as<double>(), ma, r0, ma, R.as<double>(), r0, tau.as<double>(), st));
+  }
   // G_i^{1} (rp x m) = Q[:m, :rp]^T
   hipLaunchKernelGGL(k_transpose64, dim3(nb((int64_t)rp * m)), dim3(256), 0, st, A.as<double>(), m, rp, ma, G, rp);
   const int q0 = c.r[i - 1], qn = c.n[i - 1];
@@ -171,7 +192,10 @@ tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const G
     if (ma > m) fill_zero(A.p, (size_t)ma * r1 * sizeof(double), st);
     TTK_HIP(hipMemcpy2DAsync(A.p, (size_t)ma * sizeof(double), c.g[i].p, (size_t)m * sizeof(double),
                              (size_t)m * sizeof(double), (size_t)r1, hipMemcpyDeviceToDevice, st));
-    TTK_TRY(qr_factor(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
+    const bool tall = ma > ROUND_TALL;
+    TsqrState ts;
+    if (tall) TTK_TRY(tsqr_factor(TTK_FP64, A.as<double>(), 1, ma, ma, r1, &ts, R.as<double>(), r1, st));
+    else TTK_TRY(qr_factor(A.as<double>(), ma, r1, ma, R.as<double>(), r1, tau.as<double>(), st));
     // SVD of R.  Sigma V^T, pushed into the next core, is U^T R: with a copy of R
     // kept, only the left vectors are needed (V stays unaccumulated)
     TTK_HIP(hipMemcpyAsync(V.p, R.p, (size_t)r1 * r1 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -209,9 +233,13 @@ tt_status round_gauge(std::vector<DBuf>& cores, std::vector<int>& ranks, const G
         TTK_TRY(Cw.alloc((size_t)ma * rp * sizeof(double)));
         Cq = Cw.as<double>();
       }
-      hipLaunchKernelGGL(k_pad_rows, dim3(nb((int64_t)ma * rp)), dim3(256), 0, st, (const double*)R.as<double>(),
-                         r1, r1, Cq, ma, rp, ma);
-      TTK_TRY(qr_apply_q(A.as<double>(), ma, r1, ma, tau.as<double>(), Cq, rp, ma, st));
+      if (tall) {
+        TTK_TRY(tsqr_apply(&ts, R.as<double>(), r1, rp, TTK_FP64, Cq, 1, ma, st));
+      } else {
+        hipLaunchKernelGGL(k_pad_rows, dim3(nb((int64_t)ma * rp)), dim3(256), 0, st, (const double*)R.as<double>(),
+                           r1, r1, Cq, ma, rp, ma);
+        TTK_TRY(qr_apply_q(A.as<double>(), ma, r1, ma, tau.as<double>(), Cq, rp, ma, st));
+      }
       if (ma > m)
         TTK_HIP(hipMemcpy2DAsync(c.g[i].p, (size_t)m * sizeof(double), Cq, (size_t)ma * sizeof(double),
                                  (size_t)m * sizeof(double), (size_t)rp, hipMemcpyDeviceToDevice, st));
