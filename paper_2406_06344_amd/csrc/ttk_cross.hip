@@ -348,20 +348,34 @@ __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, i
   for (int ct = wv; ct < (r1 + 15) / 16; ct += TTW) {
     const int col = ct * 16 + li;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int s0 = 0; s0 < nst; s0 += TTB) {
-      double b[TTB];   // the batch's B operands, loaded before its products
+    // batches of TTB steps; the B operands of the next batch are loaded
+    // while the current batch's products issue (two register sets)
+    auto loadb = [&](int s0, double (&b)[TTB]) {
 #pragma unroll
       for (int u = 0; u < TTB; ++u) {
         const int kk = 4 * (s0 + u) + lk;
         b[u] = (kk < r0 && col < r1) ? Ci[kk + (int64_t)col * m] : 0.0;
       }
+    };
+    auto mma = [&](int s0, const double (&b)[TTB]) {
 #pragma unroll
       for (int u = 0; u < TTB; ++u) {
         const int kk = 4 * (s0 + u) + lk;
         if (s0 + u < nst)
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kk < r0 ? As[li][kk] : 0.0, b[u], acc, 0, 0, 0);
       }
+    };
+    const int nbat = (nst + TTB - 1) / TTB;
+    double bA[TTB], bB[TTB];
+    loadb(0, bA);
+    int bi = 0;
+    for (; bi + 1 < nbat; bi += 2) {
+      loadb((bi + 1) * TTB, bB);
+      mma(bi * TTB, bA);
+      if (bi + 2 < nbat) loadb((bi + 2) * TTB, bA);
+      mma((bi + 1) * TTB, bB);
     }
+    if (bi < nbat) mma(bi * TTB, bA);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = lk + 4 * v;
@@ -634,17 +648,21 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
   const int nst = (r + 3) / 4;
   const int ntile = (r + 15) / 16;
   const double* Wt = W + FT;
-  double bg[SB], bt[SB];
-  {
-    const int p = wv * 16 + li;
+  // B operands in batches of HB steps, two register sets: the next batch
+  // loads while the current one multiplies; the first tile's first batch
+  // loads before the gathers
+  constexpr int HB = SB / 2;
+  double bgA[HB], btA[HB], bgB[HB], btB[HB];
+  auto loadb = [&](int p, int s0, double (&bg)[HB], double (&bt)[HB]) {
 #pragma unroll
-    for (int u = 0; u < SB; ++u) {
-      const int q = 4 * u + lg;
+    for (int u = 0; u < HB; ++u) {
+      const int q = 4 * (s0 + u) + lg;
       const bool ok = p < r && q < r;
       bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
       bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
     }
-  }
+  };
+  loadb(wv * 16 + li, 0, bgA, btA);
   stage_nodes<D>(ks.nodes, sn);   // (synchronises the block)
   if (tid < SPB) {
     double c[D];
@@ -707,29 +725,29 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
     const int jt = snake_tile(it, wv, SW);
     if (jt >= ntile) continue;
     const int p = jt * 16 + li;
-    const bool pok = p < r;
     // W (upper) and Li (lower) hold W(q, p) and Li(p, q) only for q <= p:
     // the tile's products end at the step holding its last column
     const int nst_t = min(nst, 4 * jt + 4);
     dbl4 g = {0.0, 0.0, 0.0, 0.0}, t = {0.0, 0.0, 0.0, 0.0};
-    for (int s0 = 0; s0 < nst_t; s0 += SB) {
-      if (jt != wv || s0 != 0) {   // (the first batch of the first tile is already loaded)
+    auto mma = [&](int s0, const double (&bg)[HB], const double (&bt)[HB]) {
 #pragma unroll
-        for (int u = 0; u < SB; ++u) {
-          const int q = 4 * (s0 + u) + lg;
-          const bool ok = pok && q < r;
-          bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
-          bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < SB; ++u) {
+      for (int u = 0; u < HB; ++u) {
         if (s0 + u < nst_t) {
           g = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], bg[u], g, 0, 0, 0);
           t = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[64 * nst + (s0 + u) * 64 + lane], bt[u], t, 0, 0, 0);
         }
       }
+    };
+    const int nbat = (nst_t + HB - 1) / HB;
+    if (it != 0) loadb(p, 0, bgA, btA);   // (the first tile's first batch is loaded already)
+    int bi = 0;
+    for (; bi + 1 < nbat; bi += 2) {
+      loadb(p, (bi + 1) * HB, bgB, btB);
+      mma(bi * HB, bgA, btA);
+      if (bi + 2 < nbat) loadb(p, (bi + 2) * HB, bgA, btA);
+      mma((bi + 1) * HB, bgB, btB);
     }
+    if (bi < nbat) mma(bi * HB, bgA, btA);
 #pragma unroll
     for (int v = 0; v < 4; ++v) part[v] += g[v] * t[v];
   }
@@ -1151,23 +1169,38 @@ struct CoreEval {
 
 // One 16 x 16 output tile of A B with FP64 MFMA: A (16 rows x 4 nst) in LDS in
 // lane order (step s, lane l at s * 64 + l), B(q, p) = Bt[p + q MAXR] for this
-// lane's column p, over the steps [sb, se) (B is zero outside them); SB
-// steps of B loads in flight per batch.
+// lane's column p, over the steps [sb, se) (B is zero outside them); the B
+// loads of the next SB / 2 steps are in flight while the current ones
+// multiply.
 __device__ inline dbl4 mfma_tile_lds(const double* sa, int sb, int se, const double* Bt, int p, int r, int lane) {
+  constexpr int HB = SB / 2;   // steps per batch: the next batch loads while this one multiplies
   const int lk = lane >> 4;
   const bool pok = p < r;
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int s0 = sb; s0 < se; s0 += SB) {
-    double b[SB];
+  auto loadb = [&](int s0, double (&b)[HB]) {
 #pragma unroll
-    for (int u = 0; u < SB; ++u) {
+    for (int u = 0; u < HB; ++u) {
       const int q = 4 * (s0 + u) + lk;
       b[u] = (pok && q < r) ? Bt[p + (int64_t)q * MAXR] : 0.0;
     }
+  };
+  auto mma = [&](int s0, const double (&b)[HB]) {
 #pragma unroll
-    for (int u = 0; u < SB; ++u)
+    for (int u = 0; u < HB; ++u)
       if (s0 + u < se) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[(s0 + u) * 64 + lane], b[u], acc, 0, 0, 0);
+  };
+  if (se <= sb) return acc;
+  const int nbat = (se - sb + HB - 1) / HB;
+  double bA[HB], bB[HB];
+  loadb(sb, bA);
+  int bi = 0;
+  for (; bi + 1 < nbat; bi += 2) {
+    loadb(sb + (bi + 1) * HB, bB);
+    mma(sb + bi * HB, bA);
+    if (bi + 2 < nbat) loadb(sb + (bi + 2) * HB, bA);
+    mma(sb + (bi + 1) * HB, bB);
   }
+  if (bi < nbat) mma(sb + bi * HB, bA);
   return acc;
 }
 
