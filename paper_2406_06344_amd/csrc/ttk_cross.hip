@@ -2057,15 +2057,8 @@ tt_status Cross::stage_steps(int sweep, int k0, int k1) {
   return arena_flush();
 }
 
-// One sweep (Alg 6, k = 1..N-1).  The first steps are staged already (during
-// the previous sweep) when `staged`; the rest are staged while the first
-// ones run.  All steps are queued without waiting, then the results are read
-// in order and applied to the host sets.  Steps 1..h of the next sweep read
-// only what steps 1..h+1 of this one change, so once those are applied the
-// next sweep's first half is staged while this sweep's last steps run
-// (*next_staged; discarded if the stopping test ends the cross).
 // Queues the staged first half of a sweep (steps 1..h, without the finish
-// of step h, whose successor is staged with the second half).
+// of step h, whose successor is queued with the second half).
 tt_status Cross::enqueue_first_half() {
   const int h = first_half();
   for (int k = 1; k <= h; ++k) {
@@ -2075,8 +2068,14 @@ tt_status Cross::enqueue_first_half() {
   return TTK_OK;
 }
 
-// (`queued`: the first half is on the stream already, behind the previous
-// sweep's stopping test.)
+// One sweep (Alg 6, k = 1..N-1).  Every step is staged already (while the
+// previous sweep's stopping test ran) when `staged`; otherwise the first half
+// is staged, queued, and the second half staged while it runs.  All steps
+// are queued without waiting, then the results are read in order and applied
+// to the host sets; the stopping test is queued in two parts behind them,
+// and the whole next sweep is staged while it runs (*next_staged; discarded
+// if the test ends the cross).  (`queued`: the first half is on the stream
+// already, behind the previous sweep's stopping test.)
 tt_status Cross::run_sweep(int sweep, bool staged, bool queued, std::vector<tt_kernel_decision>* log, int* added,
                            bool* next_staged) {
   const int N = N_, h = first_half();
@@ -2084,14 +2083,13 @@ tt_status Cross::run_sweep(int sweep, bool staged, bool queued, std::vector<tt_k
     if (!staged) TTK_TRY(stage_steps(sweep, 1, h + 1));
     TTK_TRY(enqueue_first_half());
   }
-  TTK_TRY(stage_steps(sweep, h + 1, N));
+  if (!staged) TTK_TRY(stage_steps(sweep, h + 1, N));
   for (int k = h; k < N; ++k) {
     if (k > h) TTK_TRY(enqueue_front(hs_[k]));
     TTK_TRY(enqueue_finish(hs_[k], k + 1 < N ? &hs_[k + 1] : nullptr));
   }
   *added = 0;
   *next_staged = false;
-  const int kn = std::min(h + 1, N - 1);   // the last step the next sweep's first half depends on
   const int max_sweeps = P_.max_sweeps > 0 ? P_.max_sweeps : 200;
   for (int k = 1; k < N; ++k) {
     tt_kernel_decision rec{};
@@ -2106,12 +2104,12 @@ tt_status Cross::run_sweep(int sweep, bool staged, bool queued, std::vector<tt_k
     if (k == N - 1) {
       TTK_TRY(test_launch(N >= 3 ? N - 2 : 0, N - 1, true));
       test_queued_ = true;
-    }
-    if (k == kn && sweep + 1 < max_sweeps) {
-      // (steps kn + 1.. of this sweep keep their staged records: the next
-      // sweep's first half only overwrites hs_[1..h], already collected)
-      TTK_TRY(stage_steps(sweep + 1, 1, h + 1));
-      *next_staged = true;
+      // the whole next sweep, staged while the test runs (every step of this
+      // sweep is collected, so its records are free)
+      if (sweep + 1 < max_sweeps) {
+        TTK_TRY(stage_steps(sweep + 1, 1, N));
+        *next_staged = true;
+      }
     }
   }
   if (*added == 0) *next_staged = false;
