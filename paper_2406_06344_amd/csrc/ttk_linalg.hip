@@ -814,19 +814,22 @@ constexpr int QRC = 128;   // rows per chunk
 constexpr int QSW = 4;     // waves per block (QRC / 4 / QSW k-steps of four rows each)
 constexpr int QSUM = 16;   // the update sums at most this many partials itself
 static_assert(QSW * 64 == 256, "a thread per entry of the 16 x 16 products");
+// (RC: rows per chunk, QRC by default; the batched tall-skinny QR takes
+// 4 QRC, so a 2048-row block is 4 chunks and the grid four times smaller)
+template <int RC = QRC>
 __global__ void __launch_bounds__(QSW * 64) k_qr_apply_w(const double* V, int mm, int jb, const double* C, int nc,
                                                           int lda, double* Wp, size_t sV, size_t sC, size_t sW) {
   V += blockIdx.z * sV;   // (batched: blockIdx.z picks the matrix)
   C += blockIdx.z * sC;
   Wp += blockIdx.z * sW;
-  constexpr int STEPS = QRC / 4 / QSW;
+  constexpr int STEPS = RC / 4 / QSW;
   __shared__ double Ws[QSW][16][17];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ct = blockIdx.x, ch = blockIdx.y;
   const int c = ct * 16 + li;
   const bool cok = c < nc, pok = li < jb;
-  const int r0 = ch * QRC + wv * (QRC / QSW);
+  const int r0 = ch * RC + wv * (RC / QSW);
   double a[STEPS], b[STEPS];
 #pragma unroll
   for (int u = 0; u < STEPS; ++u) {
@@ -858,6 +861,7 @@ __global__ void __launch_bounds__(256) k_qr_apply_sum(double* Wp, int nch, int t
   Wp[(size_t)ct * 256 + e] = sum;
 }
 
+template <int RC = QRC>
 __global__ void __launch_bounds__(QSW * 64) k_qr_apply_c(const double* V, int mm, int jb, const double* T, int trans,
                                                           double* C, int nc, int lda, const double* Wp, int nparts,
                                                           size_t sV, size_t sT, size_t sC, size_t sW) {
@@ -885,12 +889,12 @@ __global__ void __launch_bounds__(QSW * 64) k_qr_apply_c(const double* V, int mm
     W2[pr][cc] = sum;
   }
   __syncthreads();
-  // the chunk's QRC / 16 row tiles, QRC / 16 / QSW per wave with their loads in flight together
-  constexpr int TPW = QRC / 16 / QSW;
+  // the chunk's RC / 16 row tiles, RC / 16 / QSW per wave with their loads in flight together
+  constexpr int TPW = RC / 16 / QSW;
   double av[TPW][4], cv[TPW][4];
 #pragma unroll
   for (int h = 0; h < TPW; ++h) {
-    const int t0 = ch * QRC + (wv * TPW + h) * 16;
+    const int t0 = ch * RC + (wv * TPW + h) * 16;
     const int r = t0 + li;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -905,7 +909,7 @@ __global__ void __launch_bounds__(QSW * 64) k_qr_apply_c(const double* V, int mm
   }
 #pragma unroll
   for (int h = 0; h < TPW; ++h) {
-    const int t0 = ch * QRC + (wv * TPW + h) * 16;
+    const int t0 = ch * RC + (wv * TPW + h) * 16;
     qdbl4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h][st], W2[4 * st + lk][li], d, 0, 0, 0);
@@ -928,14 +932,14 @@ void qr_apply(const double* V, int mm, int jb, const double* T, int trans, doubl
     return;
   }
   const int nch = (mm + QRC - 1) / QRC;
-  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda, Wp,
+  hipLaunchKernelGGL(k_qr_apply_w<QRC>, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda, Wp,
                      (size_t)0, (size_t)0, (size_t)0);
   int nparts = nch;
   if (nch > QSUM) {
     hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles), dim3(256), 0, st, Wp, nch, tiles, (size_t)0);
     nparts = 1;
   }
-  hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
+  hipLaunchKernelGGL(k_qr_apply_c<QRC>, dim3(tiles, nch), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
                      (const double*)Wp, nparts, (size_t)0, (size_t)0, (size_t)0, (size_t)0);
 }
 
@@ -1814,15 +1818,27 @@ void tsqr_update(const double* V, int mm, int jb, const double* T, int trans, do
                        sC);
     return;
   }
-  const int nch = (mm + QRC - 1) / QRC;
-  hipLaunchKernelGGL(k_qr_apply_w, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C, nc, lda,
-                     Wp, sV, sC, sW);
+  // rows per chunk: QRC, or 4 QRC when that still leaves at least 16 blocks
+  // per CU (many blocks of the batch: fewer, larger blocks schedule faster)
+  const bool big = (int64_t)nb * tiles * ((mm + 4 * QRC - 1) / (4 * QRC)) >= 16 * 256;
+  const int rc = big ? 4 * QRC : QRC;
+  const int nch = (mm + rc - 1) / rc;
+  if (big)
+    hipLaunchKernelGGL(k_qr_apply_w<4 * QRC>, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb,
+                       (const double*)C, nc, lda, Wp, sV, sC, sW);
+  else
+    hipLaunchKernelGGL(k_qr_apply_w<QRC>, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, (const double*)C,
+                       nc, lda, Wp, sV, sC, sW);
   // the partials summed once per tile (in chunk order, as k_qr_apply_c
   // would), so that the nch chunks of a tile each read one 16 x 16 sum
   // instead of all nch partials
   hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles, nb), dim3(256), 0, st, Wp, nch, tiles, sW);
-  hipLaunchKernelGGL(k_qr_apply_c, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc, lda,
-                     (const double*)Wp, 1, sV, sT, sC, sW);
+  if (big)
+    hipLaunchKernelGGL(k_qr_apply_c<4 * QRC>, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C,
+                       nc, lda, (const double*)Wp, 1, sV, sT, sC, sW);
+  else
+    hipLaunchKernelGGL(k_qr_apply_c<QRC>, dim3(tiles, nch, nb), dim3(QSW * 64), 0, st, V, mm, jb, T, trans, C, nc,
+                       lda, (const double*)Wp, 1, sV, sT, sC, sW);
 }
 
 // LDS of the strided copies: TR (c + 1) doubles, with the attribute raised once past 48 KB.
