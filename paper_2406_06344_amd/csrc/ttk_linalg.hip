@@ -1289,11 +1289,12 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
           }
           double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-          for (int u = 0; u < E; ++u) {
+          for (int u = 0; u < E; ++u) {   // (rows past n enter as zeros)
             const bool in = gl + G * u < n;
-            al += in ? xv[u] * xv[u] : 0.0;
-            be += in ? yv[u] * yv[u] : 0.0;
-            ga += in ? xv[u] * yv[u] : 0.0;
+            const double x = in ? xv[u] : 0.0, y = in ? yv[u] : 0.0;
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
           }
           al = group_sum<G>(al);
           be = group_sum<G>(be);
@@ -1454,11 +1455,12 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
       }
       double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
+      for (int u = 0; u < E; ++u) {   // (rows past n enter as zeros)
         const bool in = gl + 16 * u < n;
-        al += in ? xv[u] * xv[u] : 0.0;
-        be += in ? yv[u] * yv[u] : 0.0;
-        ga += in ? xv[u] * yv[u] : 0.0;
+        const double x = in ? xv[u] : 0.0, y = in ? yv[u] : 0.0;
+        al = fma(x, x, al);
+        be = fma(y, y, be);
+        ga = fma(x, y, ga);
       }
       al = row16_sum(al);
       be = row16_sum(be);
