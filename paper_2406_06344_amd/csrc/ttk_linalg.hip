@@ -1356,7 +1356,7 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
 // method over blocks, one dummy block when their number is odd).  Each
 // meeting is one workgroup: it copies the 2 JB_W columns of its two blocks
 // into LDS, runs one sweep of the column iteration over them (the circle
-// method over the 2 JB_W columns, a pair per 16-lane group, rotations and
+// method over the 2 JB_W columns, a pair per 32-lane group, rotations and
 // convergence tests as in k_jacobi_lds), and writes them back.  A round of
 // meetings is one launch; an outer sweep, in which every pair of columns
 // meets at least once, is n_blocks - 1 launches followed by k_jb_check.
@@ -1365,7 +1365,8 @@ __global__ void __launch_bounds__(BS) k_jacobi_lds(double* Ag, int n, int lda, d
 // per-sweep flags and the squared Frobenius norm (the floor of the inner
 // products) live past the workspace of jacobi_finish in sigma's buffer.
 constexpr int JB_W = 16;    // columns per block
-constexpr int JB_T = 256;   // threads: 16 pairs of 2 JB_W columns, 16 lanes each
+constexpr int JB_L = 32;    // lanes per column pair (E = ceil(n / 32) rows each)
+constexpr int JB_T = JB_W * JB_L;   // threads: the JB_W pairs of 2 JB_W columns
 __global__ void __launch_bounds__(BS) k_jb_init(const double* A, int n, int lda, double* aux, size_t sA, size_t sS) {
   A += blockIdx.x * sA;   // (batched: one matrix per workgroup)
   aux += blockIdx.x * sS;
@@ -1432,7 +1433,7 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
   const double gfloor = 1e-30 * aux[0];
   __syncthreads();
   constexpr int NP = 2 * JB_W;
-  const int grp = tid >> 4, gl = tid & 15;
+  const int grp = tid / JB_L, gl = tid % JB_L;
   int rot = 0, large = 0;
   for (int lr = 0; lr < NP - 1; ++lr) {
     int p = 0;
@@ -1449,28 +1450,28 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
       double xv[E], yv[E];
 #pragma unroll
       for (int u = 0; u < E; ++u) {
-        const int i = min(gl + 16 * u, n - 1);
+        const int i = min(gl + JB_L * u, n - 1);
         xv[u] = ap[i];
         yv[u] = aq[i];
       }
       double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
       for (int u = 0; u < E; ++u) {   // (rows past n enter as zeros)
-        const bool in = gl + 16 * u < n;
+        const bool in = gl + JB_L * u < n;
         const double x = in ? xv[u] : 0.0, y = in ? yv[u] : 0.0;
         al = fma(x, x, al);
         be = fma(y, y, be);
         ga = fma(x, y, ga);
       }
-      al = row16_sum(al);
-      be = row16_sum(be);
-      ga = row16_sum(ga);
+      al = row32_sum(al);
+      be = row32_sum(be);
+      ga = row32_sum(ga);
       if (!(ga * ga <= 1e-30 * (al * be) || fabs(ga) <= gfloor || ga == 0.0)) {
         double c, sn;
         jacobi_rotation(al, be, ga, c, sn);
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-          const int i = min(gl + 16 * u, n - 1);
+          const int i = min(gl + JB_L * u, n - 1);
           ap[i] = c * xv[u] - sn * yv[u];
           aq[i] = sn * xv[u] + c * yv[u];
         }
@@ -2103,22 +2104,22 @@ void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux
 // host reading the convergence flags between batches (launches queued past a
 // matrix's convergence return at once for it).
 bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, size_t sS, int count, hipStream_t st) {
-  if (n < 2 || n > 16 * 32 || count < 1 || count > 65535) return false;   // E <= 32; 2 JB_W n doubles of LDS
+  if (n < 2 || n > JB_L * 16 || count < 1 || count > 65535) return false;   // E <= 16; 2 JB_W n doubles of LDS
   const size_t sh = (size_t)2 * JB_W * n * sizeof(double);
   const int nb = (n + JB_W - 1) / JB_W, nbp = nb + (nb & 1);
   double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
   hipLaunchKernelGGL(k_jb_init, dim3(count), dim3(BS), 0, st, (const double*)A, n, lda, aux, sA, sS);
-  const int E = (n + 15) / 16;
+  const int E = (n + JB_L - 1) / JB_L;
   int sweeps = 0;
   for (int batch = 6; sweeps < 60; batch = 2) {
     for (int b = 0; b < batch && sweeps < 60; ++b, ++sweeps) {
       for (int rnd = 0; rnd < nbp - 1; ++rnd) {
-        if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        if (E <= 2) jacobi_block_round<2>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else if (E <= 6) jacobi_block_round<6>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
         else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
         else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 16) jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 24) jacobi_block_round<24>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else jacobi_block_round<32>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        else jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
       }
       hipLaunchKernelGGL(k_jb_check, dim3(count), dim3(64), 0, st, aux, sS);
     }

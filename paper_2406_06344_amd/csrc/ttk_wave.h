@@ -46,6 +46,12 @@ __device__ inline double row16_sum(double v) {
   v += row_ror<1>(v);
   return v;
 }
+// sum over each group of 32 lanes (two DPP rows), the same value in every
+// lane of the group: the row sums, then the other row's by a lane swap
+__device__ inline double row32_sum(double v) {
+  v = row16_sum(v);
+  return v + __shfl_xor(v, 16, 64);
+}
 // sum over each group of 8 lanes (half a row), the same value in every lane
 // of the group: neighbour swap and pair swap within quads (quad_perm
 // [1,0,3,2] and [2,3,0,1]), then the other quad by row_half_mirror
