@@ -171,6 +171,8 @@ struct TsqrState {
   int nb[TSQR_MAXLEV] = {0};
   int64_t rows[TSQR_MAXLEV] = {0};
   DBuf A[TSQR_MAXLEV], tau[TSQR_MAXLEV], T[TSQR_MAXLEV];
+  DBuf T64[TSQR_MAXLEV];   // 64-column block reflectors' T (levels of many 2048-row blocks)
+  bool wide[TSQR_MAXLEV] = {false};
   DBuf V, Wp, D[2];
 };
 tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t N, int r, TsqrState* ts, double* R,

@@ -1810,6 +1810,250 @@ __global__ void k_tsqr_top(const double* C, int ldc, int r, int c, int H, double
 
 inline unsigned tsqr_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 8192)); }
 
+// ---- 64-column block reflectors for the 2048-row blocks
+// An outer panel of OB columns (up to four 16-column register panels) is
+// applied to the columns right of it, and in the application of Q, as one
+// block reflector I - V op(T) V^T: V the outer panel's reflectors (kept
+// below the diagonal of A by the register panels, unit diagonal) and T
+// (OB x OB, upper triangular) built from the panels' own T and the products
+// V_a^T V_b of their reflectors, so the trailing columns are read and
+// written once per 64 columns instead of once per 16.
+constexpr int OB = 64;
+
+// V[i, c] of an outer panel whose diagonal starts at Vp (leading dimension
+// ldv, mm rows, ob columns): the stored reflector below the diagonal, 1 on
+// it, 0 above and past the extent
+__device__ inline double vpan(const double* Vp, int ldv, int i, int c, int mm, int ob) {
+  if (i >= mm || c >= ob || i < c) return 0.0;
+  return i == c ? 1.0 : Vp[i + (size_t)c * ldv];
+}
+
+// T of the outer panel, one workgroup per block (blockIdx.x, strides sV,
+// sT, s64): the panels' T_s (p0 + s, js x js column-major) on the diagonal,
+// and column block s above it -T_(s) (V_(s)^T V_s) T_s, T_(s) the part
+// already built (the forward, column-wise combination of compact-WY
+// factors).  The products V_a^T V_b (a < b) run on FP64 MFMA.
+__global__ void __launch_bounds__(256) k_qr_t64(const double* Vp, int ldv, size_t sV, int mm, int ob, const double* T,
+                                                size_t sT, int p0, double* T64, size_t s64) {
+  Vp += blockIdx.x * sV;
+  T += blockIdx.x * sT;
+  T64 += blockIdx.x * s64;
+  __shared__ double G[OB][OB + 1], Tt[OB][OB + 1], Y[OB][17];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ns = (ob + 15) / 16;
+  // the products V_a^T V_b (a < b, up to 6 pairs): the waves take the rows'
+  // 4-row steps in turn, each step's 4 column blocks loaded once for all
+  // pairs; the waves' sums then meet in G one wave at a time
+  qdbl4 g[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) g[q] = qdbl4{0.0, 0.0, 0.0, 0.0};
+  constexpr int TB = 4;
+  const int nsteps = (mm + 3) / 4;
+  for (int k0 = wv * TB; k0 < nsteps; k0 += 4 * TB) {
+    double v[TB][4];
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[u][a] = a < ns ? vpan(Vp, ldv, 4 * (k0 + u) + lk, 16 * a + li, mm, ob) : 0.0;
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b, ++q)
+          if (b < ns) g[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][a], v[u][b], g[q], 0, 0, 0);
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b, ++q)
+#pragma unroll
+          for (int vv = 0; vv < 4; ++vv) {
+            double& dst = G[16 * a + lk + 4 * vv][16 * b + li];
+            dst = (w == 0 ? 0.0 : dst) + g[q][vv];
+          }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < OB * OB; e += 256) Tt[e / OB][e % OB] = 0.0;
+  __syncthreads();
+  for (int s = 0; s < ns; ++s) {
+    const int js = min(16, ob - 16 * s);
+    const double* Ts = T + (size_t)(p0 + s) * 256;
+    for (int e = tid; e < js * js; e += 256) Tt[16 * s + e % js][16 * s + e / js] = Ts[e];
+  }
+  __syncthreads();
+  for (int s = 1; s < ns; ++s) {
+    const int js = min(16, ob - 16 * s), ms = 16 * s;
+    for (int e = tid; e < ms * js; e += 256) {   // Y = (V_(s)^T V_s) T_s
+      const int i = e % ms, j = e / ms;
+      double y = 0.0;
+      for (int q = 0; q <= j; ++q) y += G[i][ms + q] * Tt[ms + q][ms + j];
+      Y[i][j] = y;
+    }
+    __syncthreads();
+    for (int e = tid; e < ms * js; e += 256) {   // column block s: -T_(s) Y (T_(s) upper triangular)
+      const int i = e % ms, j = e / ms;
+      double x = 0.0;
+      for (int q = i; q < ms; ++q) x += Tt[i][q] * Y[q][j];
+      Tt[i][ms + j] = -x;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < ob * ob; e += 256) T64[e % ob + (size_t)(e / ob) * OB] = Tt[e % ob][e / ob];
+}
+
+// The block reflector's products walk the rows in chunks of QRC: a
+// workgroup takes one chunk of one block, stages the chunk's V (QRC x 64,
+// masked as vpan) in LDS once, and its waves take the 16-column tiles of C
+// in turn, so V is read once per chunk whatever the width of C.
+constexpr int WQ = QRC;   // rows per chunk of the wide products
+
+// W partials: Wp[((chunk * tiles + tile) * 4 + s) * 256 + m * 16 + n] =
+// sum over the chunk's rows of V[i, 16 s + m] C[i, 16 tile + n].
+__global__ void __launch_bounds__(256) k_qr_w64(const double* Vp, int ldv, size_t sV, int mm, int ob, const double* C,
+                                                int nc, int ldc, size_t sC, double* Wp, size_t sW) {
+  Vp += blockIdx.y * sV;
+  C += blockIdx.y * sC;
+  Wp += blockIdx.y * sW;
+  __shared__ double Vs[WQ][OB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ch = blockIdx.x, r0 = ch * WQ;
+  const int tiles = (nc + 15) / 16, ns = (ob + 15) / 16;
+  for (int e = tid; e < WQ * OB; e += 256) {
+    const int i = e % WQ, c = e / WQ;
+    Vs[i][c] = vpan(Vp, ldv, r0 + i, c, mm, ob);
+  }
+  __syncthreads();
+  for (int t = wv; t < tiles; t += 4) {
+    const int c = t * 16 + li;
+    const bool cok = c < nc;
+    qdbl4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = qdbl4{0.0, 0.0, 0.0, 0.0};
+    // the tile's 32 K-steps in two batches, the second loading while the
+    // first multiplies
+    constexpr int TB = WQ / 8;
+    double b0[TB], b1[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int i = r0 + 4 * u + lk, i1 = i + 4 * TB;
+      b0[u] = (i < mm && cok) ? C[i + (size_t)c * ldc] : 0.0;
+      b1[u] = (i1 < mm && cok) ? C[i1 + (size_t)c * ldc] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s < ns) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[4 * u + lk][16 * s + li], b0[u], acc[s], 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s < ns)
+          acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[4 * (TB + u) + lk][16 * s + li], b1[u], acc[s], 0, 0, 0);
+    // D[m][n] at lane (n = li, m = lk + 4 v)
+    double* wp = Wp + ((size_t)ch * tiles + t) * 1024;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) wp[s * 256 + (lk + 4 * v) * 16 + li] = acc[s][v];
+  }
+}
+
+// W2 = op(T) W for every tile (W: the chunk-0 slots, summed beforehand),
+// into W2p[tile * 1024 + k * 16 + n] (k < 64), one workgroup per tile and block.
+__global__ void __launch_bounds__(256) k_qr_w2(const double* T64, size_t s64, int trans, int ob, const double* Wp,
+                                               size_t sW, double* W2p, size_t s2) {
+  T64 += blockIdx.y * s64;
+  Wp += blockIdx.y * sW + (size_t)blockIdx.x * 1024;
+  W2p += blockIdx.y * s2 + (size_t)blockIdx.x * 1024;
+  __shared__ double W[OB][17];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) W[16 * s + (tid >> 4)][tid & 15] = Wp[s * 256 + tid];
+  __syncthreads();
+  for (int e = tid; e < OB * 16; e += 256) {
+    const int i = e >> 4, n = e & 15;
+    double sum = 0.0;
+    if (i < ob)
+      for (int k = 0; k < ob; ++k) sum += (trans ? T64[k + (size_t)i * OB] : T64[i + (size_t)k * OB]) * W[k][n];
+    W2p[e] = sum;
+  }
+}
+
+// C <- C - V W2 on one chunk of one block: V's chunk in LDS, the waves take
+// the 16-column tiles in turn, per tile the chunk's 16-row tiles with
+// ob / 4 MFMA steps each.
+__global__ void __launch_bounds__(256) k_qr_c64(const double* Vp, int ldv, size_t sV, int mm, int ob, double* C,
+                                                int nc, int ldc, size_t sC, const double* W2p, size_t s2) {
+  Vp += blockIdx.y * sV;
+  C += blockIdx.y * sC;
+  W2p += blockIdx.y * s2;
+  __shared__ double Vs[WQ][OB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int ch = blockIdx.x, r0 = ch * WQ;
+  const int tiles = (nc + 15) / 16, nst = (ob + 3) / 4;
+  for (int e = tid; e < WQ * OB; e += 256) {
+    const int i = e % WQ, c = e / WQ;
+    Vs[i][c] = vpan(Vp, ldv, r0 + i, c, mm, ob);
+  }
+  __syncthreads();
+  for (int t = wv; t < tiles; t += 4) {
+    const int c = t * 16 + li;
+    const bool cok = c < nc;
+    // the tile's W2 rows and all of the chunk's C values load together
+    double bw[16], cv[WQ / 16][4];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) bw[st] = W2p[(size_t)t * 1024 + (4 * st + lk) * 16 + li];
+#pragma unroll
+    for (int h = 0; h < WQ / 16; ++h)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * h + lk + 4 * v;
+        cv[h][v] = (row < mm && cok) ? C[row + (size_t)c * ldc] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < WQ / 16; ++h) {
+      qdbl4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < 16; ++st)
+        if (st < nst) d = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[16 * h + li][4 * st + lk], bw[st], d, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * h + lk + 4 * v;
+        if (row < mm && cok) C[row + (size_t)c * ldc] = cv[h][v] - d[v];
+      }
+    }
+  }
+}
+
+// (I - V op(T) V^T) C for the outer panel at Vp (mm rows, ob columns) on the
+// nb blocks' C (nc columns, leading dimension ldc, block strides sV, s64,
+// sC).  Wp holds the partials and W2 (at least nb * tiles * (ceil(mm /
+// 128) + 1) * 1024 doubles).
+void tsqr_update64(const double* Vp, int ldv, size_t sV, int mm, int ob, const double* T64, size_t s64, int trans,
+                   double* C, int nc, int ldc, size_t sC, int nb, double* Wp, hipStream_t st) {
+  const int tiles = (nc + 15) / 16;
+  const int nch = (mm + WQ - 1) / WQ;
+  const size_t sW = (size_t)tiles * (nch + 1) * 1024;   // the partials, then W2 at chunk slot nch
+  double* W2p = Wp + (size_t)tiles * nch * 1024;
+  hipLaunchKernelGGL(k_qr_w64, dim3(nch, nb), dim3(256), 0, st, Vp, ldv, sV, mm, ob, (const double*)C, nc, ldc, sC,
+                     Wp, sW);
+  hipLaunchKernelGGL(k_qr_apply_sum, dim3(tiles * 4, nb), dim3(256), 0, st, Wp, nch, tiles * 4, sW);
+  hipLaunchKernelGGL(k_qr_w2, dim3(tiles, nb), dim3(256), 0, st, T64, s64, trans, ob, (const double*)Wp, sW, W2p, sW);
+  hipLaunchKernelGGL(k_qr_c64, dim3(nch, nb), dim3(256), 0, st, Vp, ldv, sV, mm, ob, C, nc, ldc, sC,
+                     (const double*)W2p, sW);
+}
+
 // (I - V op(T) V^T) on the nb blocks' C: one k_qr_apply per block for
 // mm <= 4 QRC, else the row-chunked pair with each block's partials at
 // Wp + b sW (at most 16 chunks, summed by k_qr_apply_c in chunk order).
@@ -1951,20 +2195,45 @@ tt_status tsqr_factor(int dtype, const void* A, int64_t sp, int64_t sc, int64_t 
                          (const double*)ts->A[l - 1].as<double>(), r, H, rows, nb, Al);
     }
     TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
-    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles_max * nch_max * 256 * sizeof(double)));
+    // many 2048-row blocks: outer panels of OB columns, each applied to the
+    // columns right of it as one block reflector (partials: 4 x 256 per tile
+    // and chunk); otherwise the whole matrix is one outer panel (a level of
+    // few blocks gives the chunked 16-column updates more workgroups)
+    const bool wide = H > 4 * QRC && nb >= 16;
+    ts->wide[l] = wide;
+    const int nout = (r + OB - 1) / OB;
+    // partials of the chunked updates of 2048-row blocks, 16-column (256 per
+    // tile and chunk) or 64-column (1024, plus W2)
+    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles_max * (nch_max + 1) * 1024 * sizeof(double)));
+    if (wide) TTK_TRY(ts->T64[l].alloc((size_t)nb * nout * OB * OB * sizeof(double)));
     double* V = ts->V.as<double>();
     double* tau = ts->tau[l].as<double>();
     double* T = ts->T[l].as<double>();
-    for (int p = 0; p < npan; ++p) {
-      const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
-      if (!qr_panel_reg(Al + j0 + (size_t)j0 * H, mm, jb, H, tau + j0, V, T + (size_t)p * NB * NB, st, nb,
-                        (size_t)H * r, (size_t)r, (size_t)H * NB, (size_t)npan * NB * NB))
-        return fail(TTK_ERR_UNSUPPORTED, "tsqr: panel of %d rows", mm);
-      const int nc = r - j0 - jb;
-      if (nc > 0)
-        tsqr_update(V, mm, jb, T + (size_t)p * NB * NB, 1, Al + j0 + (size_t)(j0 + jb) * H, nc, H, nb, (size_t)H * NB,
-                    (size_t)npan * NB * NB, (size_t)H * r, H > 4 * QRC ? ts->Wp.as<double>() : nullptr,
-                    (size_t)tiles_max * nch_max * 256, st);
+    const int OW = wide ? OB : r;
+    for (int c0 = 0; c0 < r; c0 += OW) {
+      const int ob = std::min(OW, r - c0);
+      for (int p = c0 / NB; p * NB < c0 + ob; ++p) {
+        const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
+        if (!qr_panel_reg(Al + j0 + (size_t)j0 * H, mm, jb, H, tau + j0, V, T + (size_t)p * NB * NB, st, nb,
+                          (size_t)H * r, (size_t)r, (size_t)H * NB, (size_t)npan * NB * NB))
+          return fail(TTK_ERR_UNSUPPORTED, "tsqr: panel of %d rows", mm);
+        const int nc = c0 + ob - j0 - jb;   // the outer panel's columns right of this panel
+        if (nc > 0)
+          tsqr_update(V, mm, jb, T + (size_t)p * NB * NB, 1, Al + j0 + (size_t)(j0 + jb) * H, nc, H, nb,
+                      (size_t)H * NB, (size_t)npan * NB * NB, (size_t)H * r,
+                      H > 4 * QRC ? ts->Wp.as<double>() : nullptr,
+                      (size_t)tiles_max * nch_max * 256, st);
+      }
+      if (wide) {
+        double* T64 = ts->T64[l].as<double>() + (size_t)(c0 / OB) * OB * OB;
+        const double* Vp = Al + c0 + (size_t)c0 * H;
+        hipLaunchKernelGGL(k_qr_t64, dim3(nb), dim3(256), 0, st, Vp, H, (size_t)H * r, H - c0, ob,
+                           (const double*)T, (size_t)npan * NB * NB, c0 / NB, T64, (size_t)nout * OB * OB);
+        const int nc = r - c0 - ob;
+        if (nc > 0)
+          tsqr_update64(Vp, H, (size_t)H * r, H - c0, ob, T64, (size_t)nout * OB * OB, 1,
+                        Al + c0 + (size_t)(c0 + ob) * H, nc, H, (size_t)H * r, nb, ts->Wp.as<double>(), st);
+      }
     }
     if (nb == 1) break;
     rows = (int64_t)nb * r;
@@ -1993,10 +2262,20 @@ tt_status tsqr_apply(TsqrState* ts, const double* C, int ldc, int c, int out_dty
     else
       hipLaunchKernelGGL(k_tsqr_down, dim3(tsqr_grid((int64_t)nb * H * c)), dim3(256), 0, st,
                          (const double*)D[(l + 1) & 1].as<double>(), c, nb, r, H, Dl.as<double>());
-    TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
-    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles * nch * 256 * sizeof(double)));
-    double* V = ts->V.as<double>();
     const double* Al = ts->A[l].as<double>();
+    if (H > 4 * QRC) TTK_TRY(ts->Wp.alloc((size_t)nb * tiles * (nch + 1) * 1024 * sizeof(double)));
+    if (ts->wide[l]) {   // the outer panels' block reflectors, last to first
+      const int nout = (r + OB - 1) / OB;
+      for (int P = nout - 1; P >= 0; --P) {
+        const int c0 = P * OB, ob = std::min(OB, r - c0);
+        tsqr_update64(Al + c0 + (size_t)c0 * H, H, (size_t)H * r, H - c0, ob,
+                      ts->T64[l].as<double>() + (size_t)P * OB * OB, (size_t)nout * OB * OB, 0,
+                      Dl.as<double>() + c0, c, H, (size_t)H * c, nb, ts->Wp.as<double>(), st);
+      }
+      continue;
+    }
+    TTK_TRY(ts->V.alloc((size_t)nb * H * NB * sizeof(double)));
+    double* V = ts->V.as<double>();
     const double* T = ts->T[l].as<double>();
     for (int p = npan - 1; p >= 0; --p) {   // Q [C; 0] = H_0 (H_1 (... [C; 0])), panels last to first
       const int j0 = p * NB, jb = std::min(NB, r - j0), mm = H - j0;
