@@ -4,9 +4,10 @@
 //     expand:  Y = F Z     (N x B)
 // and small per-theta products done by batched_matvec / batched_bilinear.
 // Plain (B = 1): a GEMV pair, bound by reading F once.  Batched: GEMMs that
-// read F once for all B columns: skinny kernels for B <= 16, the float32
-// matrix-core kernels of ttk_apply_mfma.hip for wider batches (r <= 128),
-// register-tiled VALU kernels otherwise (float64).  Products are formed in
+// read F once for all B columns: for B <= 16 the float32 skinny matrix-core
+// kernels of ttk_apply_mfma.hip (aligned rows of F) or the skinny kernels
+// here, for wider batches (r <= 128) the float32 matrix-core kernels of
+// ttk_apply_mfma.hip, register-tiled VALU kernels otherwise (float64).  Products are formed in
 // the working precision and summed in double over point tiles (a float32
 // running sum over 10^5 points loses digits).  The plain and skinny reduces
 // write one double partial sum per workgroup and a second launch adds them
@@ -486,7 +487,10 @@ tt_status apply_reduce(int dtype, const void* F, int ldf, int64_t N, int r, cons
     const unsigned g = skinny_groups(N);
     const int count = r * B;
     double* sums = part + (size_t)g * count;
-    if (dtype == TTK_FP32)
+    if (dtype == TTK_FP32 && skinny_mfma_ok(F, ldf, r, B))
+      TTK_TRY(reduce_skinny_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(X), ldx, B,
+                                 part, g, st));
+    else if (dtype == TTK_FP32)
       hipLaunchKernelGGL(k_reduce_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
                          static_cast<const float*>(X), ldx, B, SKINNY_CHUNK, part);
     else
@@ -535,6 +539,9 @@ tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, cons
     return TTK_OK;
   }
   if (B <= SB && r <= SR) {
+    if (dtype == TTK_FP32 && skinny_mfma_ok(F, ldf, r, B))
+      return expand_skinny_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(Z), B,
+                                static_cast<float*>(Y), ldy, st);
     const unsigned g = (unsigned)((N + ST - 1) / ST);
     if (dtype == TTK_FP32)
       hipLaunchKernelGGL(k_expand_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,

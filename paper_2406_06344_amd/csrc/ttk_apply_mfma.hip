@@ -374,6 +374,181 @@ __global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ p
   }
 }
 
+// ------------------------------------------------------------------ skinny
+// Short batches (2 <= B <= 16 thetas, r <= 128) with F rows 16-byte aligned
+// (ldf % 4 == 0): one 16 x 16 theta tile, so a wave keeps every operand in
+// registers and nothing is staged in LDS.  Each lane loads 4 consecutive
+// columns of a row of F (16 bytes) and the MFMA K index is permuted to
+// match: within a 16-row step of the reduce, lane group kq = l / 16 takes
+// rows 4 kq .. 4 kq + 3, the four MFMAs of the step one row each; in the
+// expand, the four MFMAs of a 16-column step take one column each of the
+// lane's 4-column load.  The permutation is the same on both operands, so
+// the sums are those of the plain product.
+
+// W (r x B) = F^T X over 256 rows per workgroup (64 per wave, in 16-row
+// steps), float32 MFMA sums over the wave's rows, the four waves' sums added
+// in float64 and written as the workgroup's partial
+// part[blockIdx.x r B + c + theta r] (k_sum_ranges / k_sum_final add them).
+// Columns: G groups of 64 read as 16-byte loads (group g, element e of lane
+// i16 is column 64 g + 4 i16 + e: four MFMA tiles per group, tile (g, e)
+// holding the columns 64 g + 4 m + e, m < 16), then TT tiles of 16 columns
+// read one float per lane (column 64 G + 16 t + i16).  VEC: X's columns are
+// 16-byte aligned, so a lane's 4 rows of one theta are one load.
+constexpr int SK_P = 256;   // rows per workgroup of the skinny reduce, points per workgroup of the expand
+
+template <int G, int TT, bool VEC>
+__global__ void __launch_bounds__(256, 2) k_reduce_skinny_mfma(const float* __restrict__ F, int ldf, int64_t N,
+                                                               int r, const float* __restrict__ X, int64_t ldx,
+                                                               int B, double* __restrict__ part) {
+  constexpr int NT = 4 * G + TT;
+  __shared__ float red[3][NT][4][64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t base = (int64_t)blockIdx.x * SK_P + (int64_t)w * 64;
+  // operands of the wave's four 16-row steps: rows base + 16 st + 4 kq + j
+  f4 xv[4];
+  f4 fg[4][4][G > 0 ? G : 1];
+  float ft[4][4][TT > 0 ? TT : 1];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int64_t p = base + 16 * st + 4 * kq;
+    f4 x = f4{0.f, 0.f, 0.f, 0.f};
+    if (i16 < B) {
+      const float* xc = X + (int64_t)i16 * ldx;
+      if (VEC && p + 3 < N) {
+        x = *reinterpret_cast<const f4*>(xc + p);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (p + j < N) x[j] = xc[p + j];
+      }
+    }
+    xv[st] = x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const bool pin = p + j < N;
+      const float* row = F + (pin ? p + j : 0) * (int64_t)ldf;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int c = 64 * g + 4 * i16;
+        f4 v = f4{0.f, 0.f, 0.f, 0.f};
+        if (pin && c < r) {
+          v = *reinterpret_cast<const f4*>(row + c);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c + e >= r) v[e] = 0.f;
+        }
+        fg[st][j][g < G ? g : 0] = v;
+      }
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const int c = 64 * G + 16 * t + i16;
+        ft[st][j][t < TT ? t : 0] = (pin && c < r) ? row[c] : 0.f;
+      }
+    }
+  }
+  f4 acc[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) acc[k] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float b = xv[st][j];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[4 * g + e] = mfma4(fg[st][j][g < G ? g : 0][e], b, acc[4 * g + e]);
+#pragma unroll
+      for (int t = 0; t < TT; ++t) acc[4 * G + t] = mfma4(ft[st][j][t < TT ? t : 0], b, acc[4 * G + t]);
+    }
+  if (w > 0) {
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w - 1][k][v][lane] = acc[k][v];
+  }
+  __syncthreads();
+  if (w > 0 || i16 >= B) return;
+  const int64_t count = (int64_t)r * B;
+  double* pw = part + (int64_t)blockIdx.x * count + (int64_t)i16 * r;
+  // D[4 kq + v][i16] of tile k: column c below, theta i16
+#pragma unroll
+  for (int k = 0; k < NT; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = k < 4 * G ? 64 * (k / 4) + 16 * kq + 4 * v + (k % 4) : 64 * G + 16 * (k - 4 * G) + 4 * kq + v;
+      if (c < r)
+        pw[c] = (double)acc[k][v] + (double)red[0][k][v][lane] + (double)red[1][k][v][lane] +
+                (double)red[2][k][v][lane];
+    }
+}
+
+// Y (N x B) = F Z, 64 points per wave in four 16-point tiles.  Z (r x B,
+// leading dimension r) is held in registers: lane (i16, kq) keeps
+// Z[16 u + 4 kq + e][i16]; the lane's A operand for step (u, e) is element e
+// of its 16-byte load F[p][16 u + 4 kq ..].  U = ceil(r / 16).  VEC: Y's
+// columns are 16-byte aligned, a lane's 4 consecutive points go as one store.
+template <int U, bool VEC>
+__global__ void __launch_bounds__(256, 2) k_expand_skinny_mfma(const float* __restrict__ F, int ldf, int64_t N,
+                                                               int r, const float* __restrict__ Z, int B,
+                                                               float* __restrict__ Y, int64_t ldy) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i16 = lane & 15, kq = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * SK_P + (int64_t)w * 64;
+  if (p0 >= N) return;                           // (no barrier below)
+  f4 fv[4][U];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t p = p0 + 16 * s + i16;
+    const bool pin = p < N;
+    const float* row = F + (pin ? p : 0) * (int64_t)ldf;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = 16 * u + 4 * kq;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (pin && c < r) {
+        v = *reinterpret_cast<const f4*>(row + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (c + e >= r) v[e] = 0.f;
+      }
+      fv[s][u] = v;
+    }
+  }
+  float zr[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = 16 * u + 4 * kq + e;
+      zr[u][e] = (i16 < B && c < r) ? Z[c + (int64_t)i16 * r] : 0.f;
+    }
+  f4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = mfma4(fv[s][u][e], zr[u][e], acc[s]);
+  if (i16 >= B) return;
+  // D[4 kq + v][i16]: point p0 + 16 s + 4 kq + v, theta i16
+  float* ycol = Y + (int64_t)i16 * ldy;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t p = p0 + 16 * s + 4 * kq;
+    if (VEC && p + 3 < N) {
+      *reinterpret_cast<f4*>(ycol + p) = acc[s];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (p + v < N) ycol[p + v] = acc[s][v];
+    }
+  }
+}
+
 // Chunking of the reduce: enough workgroups to fill the chip (RD_WG_TARGET
 // over the theta blocks), every chunk a whole number of 64-point blocks.
 constexpr int RD_WG_TARGET = 512;
@@ -461,6 +636,28 @@ tt_status launch_reduce(const float* F, int ldf, int64_t N, int r, const float* 
   return TTK_OK;
 }
 
+
+template <int G, int TT>
+void launch_reduce_skinny(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
+                          double* part, unsigned groups, hipStream_t st) {
+  if ((ldx % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0))
+    hipLaunchKernelGGL((k_reduce_skinny_mfma<G, TT, true>), dim3(groups), dim3(256), 0, st, F, ldf, N, r, X, ldx, B,
+                       part);
+  else
+    hipLaunchKernelGGL((k_reduce_skinny_mfma<G, TT, false>), dim3(groups), dim3(256), 0, st, F, ldf, N, r, X, ldx,
+                       B, part);
+}
+
+template <int U>
+void launch_expand_skinny(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
+                          hipStream_t st) {
+  const dim3 grid((unsigned)((N + SK_P - 1) / SK_P));
+  if ((ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0))
+    hipLaunchKernelGGL((k_expand_skinny_mfma<U, true>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_expand_skinny_mfma<U, false>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
+}
+
 }  // namespace
 
 bool apply_mfma_ok(int r, int B) { return r >= 1 && r <= MFMA_APPLY_MAXR && B > 16; }
@@ -492,6 +689,52 @@ tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const flo
     case 8: return launch_reduce<8>(F, ldf, N, r, X, ldx, B, W, part, st);
     default: return fail(TTK_ERR_UNSUPPORTED, "MFMA reduce: rank %d > %d", r, MFMA_APPLY_MAXR);
   }
+}
+
+bool skinny_mfma_ok(const void* F, int ldf, int r, int B) {
+  return B >= 2 && B <= 16 && r >= 1 && r <= MFMA_APPLY_MAXR && ldf >= r && ldf % 4 == 0 &&
+         reinterpret_cast<uintptr_t>(F) % 16 == 0;
+}
+
+tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
+                             double* part, unsigned groups, hipStream_t st) {
+  if (N <= 0) return TTK_OK;
+  if (!skinny_mfma_ok(F, ldf, r, B) || (int64_t)groups * SK_P < N)
+    return fail(TTK_ERR_ARG, "skinny MFMA reduce: unsupported shape (r %d, ldf %d, B %d)", r, ldf, B);
+  // G 64-column groups of 16-byte loads, then TT 16-column tiles
+  int G = r / 64, rem = r - 64 * G, TT = (rem + 15) / 16;
+  if (rem > 48) ++G, TT = 0;
+  switch (4 * G + TT) {
+    case 1: launch_reduce_skinny<0, 1>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 2: launch_reduce_skinny<0, 2>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 3: launch_reduce_skinny<0, 3>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 4: launch_reduce_skinny<1, 0>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 5: launch_reduce_skinny<1, 1>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 6: launch_reduce_skinny<1, 2>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 7: launch_reduce_skinny<1, 3>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    case 8: launch_reduce_skinny<2, 0>(F, ldf, N, r, X, ldx, B, part, groups, st); break;
+    default: return fail(TTK_ERR_UNSUPPORTED, "skinny MFMA reduce: rank %d", r);
+  }
+  return TTK_OK;
+}
+
+tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
+                             int64_t ldy, hipStream_t st) {
+  if (N <= 0) return TTK_OK;
+  if (!skinny_mfma_ok(F, ldf, r, B))
+    return fail(TTK_ERR_ARG, "skinny MFMA expand: unsupported shape (r %d, ldf %d, B %d)", r, ldf, B);
+  switch ((r + 15) / 16) {
+    case 1: launch_expand_skinny<1>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 2: launch_expand_skinny<2>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 3: launch_expand_skinny<3>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 4: launch_expand_skinny<4>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 5: launch_expand_skinny<5>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 6: launch_expand_skinny<6>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 7: launch_expand_skinny<7>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    case 8: launch_expand_skinny<8>(F, ldf, N, r, Z, B, Y, ldy, st); break;
+    default: return fail(TTK_ERR_UNSUPPORTED, "skinny MFMA expand: rank %d", r);
+  }
+  return TTK_OK;
 }
 
 tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,

@@ -304,6 +304,14 @@ tt_status apply_reduce_mfma(const float* F, int ldf, int64_t N, int r, const flo
 // Y (N x B, ldy) = F Z (or += with accumulate), Z: r x B with leading dimension r.
 tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
                             int64_t ldy, hipStream_t st, bool accumulate = false);
+// Float32 forms for 2 <= B <= 16 and r <= MFMA_APPLY_MAXR with 16-byte aligned
+// rows of F (ldf % 4 == 0).  The reduce writes one float64 partial of W
+// (r x B) per 256 rows, part[g r B + c + b r] for g < groups, groups >= N / 256.
+bool skinny_mfma_ok(const void* F, int ldf, int r, int B);
+tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
+                             double* part, unsigned groups, hipStream_t st);
+tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
+                             int64_t ldy, hipStream_t st);
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
                     int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,

@@ -1,5 +1,7 @@
-"""GPU parity of the wide batched apply and backward (B > 16: the float32
-matrix-core kernels for ranks up to 128, the register-tiled kernels above)
+"""GPU parity of the batched apply and backward beyond the small ranks of
+the main parity test (B > 16: the float32 matrix-core kernels for ranks up
+to 128, the register-tiled kernels above; 2 <= B <= 16: the skinny
+matrix-core kernels)
 against the FP64 oracle on the same cores and float32-rounded inputs.
 
 Cores are random TT cores with the ranks under test (d = 2, one parameter):
@@ -57,6 +59,22 @@ def errs(got, ref):
     (130, 70, 1200, 1000, 80),      # rank above 128: the register-tiled float32 kernels
 ])
 def test_wide_apply_and_backward_match_oracle(rs, rt, ns, nt, B):
+    _check_apply_and_backward(rs, rt, ns, nt, B)
+
+
+@pytest.mark.parametrize("rs,rt,ns,nt,B", [
+    (100, 90, 3001, 2999, 16),      # 64-column group + 3 / 2 tail tiles, unaligned X and Y columns
+    (72, 75, 4096, 2048, 16),       # group + 1 tail tile, aligned columns (16-byte X loads, Y stores)
+    (128, 17, 1500, 2100, 5),       # two 64-column groups; two tail tiles only
+    (40, 60, 999, 1001, 2),         # three tail tiles; a part-filled 64-column group
+])
+def test_skinny_apply_and_backward_match_oracle(rs, rt, ns, nt, B):
+    """2 <= B <= 16: the float32 skinny matrix-core reduce and expand (every
+    rank-dependent shape of their column split), same bars."""
+    _check_apply_and_backward(rs, rt, ns, nt, B)
+
+
+def _check_apply_and_backward(rs, rt, ns, nt, B):
     torch = _torch()
     import paper_2406_06344_amd as pkg
     say(f"[wide] r_s {rs} r_t {rt} N {ns} x {nt} B {B}")
