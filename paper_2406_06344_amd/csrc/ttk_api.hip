@@ -527,8 +527,8 @@ static tt_status check_apply_args(tt_kernel_t h, const void* theta, int B, const
 static tt_status apply_core(tt_kernel_t h, const void* theta, int B, const void* X, int64_t ldx, void* Y,
                             int64_t ldy, const ApplyScratch& s, hipStream_t st) {
   TTK_TRY(online_into(h, theta, B, s.M, nullptr, s.owork, st));
-  TTK_TRY(apply_reduce(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, s.W, s.part, st));
-  batched_matvec(h->dtype, s.M, h->rs, h->rt, 0, s.W, B, s.Z, st);
+  TTK_TRY(apply_reduce_matvec(h->dtype, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, s.W, s.M, h->rs, h->rt, 0, s.Z,
+                              s.part, st));
   TTK_TRY(apply_expand(h->dtype, h->U.p, h->ldu, h->ns, h->rs, s.Z, B, Y, ldy, st));
   TTK_HIP(hipGetLastError());
   return TTK_OK;
@@ -769,11 +769,16 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   TTK_TRY(prepare_M(h, theta, B, want_dth, st));
   TTK_TRY(h->Abuf.alloc((size_t)h->rs * B * h->es));
-  TTK_TRY(reduce_into(h, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, st));   // A = U^T G
   if (dX) {
+    // A = U^T G, then M^T a
     TTK_TRY(h->Zbuf.alloc((size_t)std::max(h->rs, h->rt) * B * h->es));
-    batched_matvec(h->dtype, h->Mbuf.p, h->rs, h->rt, 1, h->Abuf.p, B, h->Zbuf.p, st);   // M^T a
+    const size_t wb = apply_reduce_work(h->ns, h->rs, B);
+    if (wb) TTK_TRY(h->Pbuf.alloc(wb));
+    TTK_TRY(apply_reduce_matvec(h->dtype, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, h->Mbuf.p, h->rs,
+                                h->rt, 1, h->Zbuf.p, wb ? h->Pbuf.p : nullptr, st));
     TTK_TRY(apply_expand(h->dtype, h->V.p, h->ldv, h->nt, h->rt, h->Zbuf.p, B, dX, lddx, st));
+  } else {
+    TTK_TRY(reduce_into(h, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, st));   // A = U^T G
   }
   if (want_dth) {
     const void* W = W_saved;

@@ -435,6 +435,109 @@ __global__ void __launch_bounds__(256) k_bilinear(const T* A, const T* dM, const
   }
 }
 
+// Small per-theta products whose matrix fits in LDS (SMALL_LDS_BYTES): the
+// workgroup copies its matrix by direct global->LDS loads (every load in
+// flight at once, one round trip to memory) and multiplies from LDS, sums
+// in double.  Lane l of a wave's copy instruction writes dword base + l.
+constexpr int SMALL_LDS_BYTES = 48 * 1024;
+__device__ inline void copy_to_lds(const void* src, int ndw, float* dst, int lane, int wv) {
+  const float* s = static_cast<const float*>(src);
+  for (int j = wv; 64 * j < ndw; j += 4)
+    if (64 * j + lane < ndw) __builtin_amdgcn_global_load_lds(s + 64 * j + lane, dst + 64 * j, 4, 0, 0);
+}
+
+// y_b = op(M_b) x_b, one workgroup per b (grid-stride).  With `sums`, x_b is
+// first formed as the fixed-order sum of the NRANGE range sums of the skinny
+// reduce (entry i of x_b at sums[k count + b nin + i]) and also written to
+// xout.  op = transpose: output o reads column o of M_b, the start of its
+// walk down the column rotated by o so the lanes' LDS reads spread over
+// the banks.
+template <class T>
+__global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int cols, int trans, const T* x,
+                                                     const double* sums, int64_t count, T* xout, int B, T* y) {
+  extern __shared__ float smem[];
+  const int nin = trans ? rows : cols, nout = trans ? cols : rows;
+  const int ndw = (int)((size_t)rows * cols * sizeof(T) / 4);
+  const T* ms = reinterpret_cast<const T*>(smem);
+  double* xs = reinterpret_cast<double*>(smem + ((ndw + 1) & ~1));
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    __syncthreads();                             // the previous b is consumed
+    copy_to_lds(M + (size_t)b * rows * cols, ndw, smem, lane, wv);
+    for (int i = tid; i < nin; i += 256) {
+      double v;
+      if (sums) {
+        v = 0.0;
+        for (int k = 0; k < NRANGE; ++k) v += sums[(size_t)k * count + (size_t)b * nin + i];
+        xout[(size_t)b * nin + i] = (T)v;
+      } else {
+        v = (double)x[(size_t)b * nin + i];
+      }
+      xs[i] = v;
+    }
+    __builtin_amdgcn_s_waitcnt(0);               // this wave's copies have landed
+    __syncthreads();                             // and everyone's
+    asm volatile("" ::: "memory");
+    for (int o = tid; o < nout; o += 256) {
+      double s0 = 0.0, s1 = 0.0;
+      if (!trans) {
+        int c = 0;
+        for (; c + 1 < cols; c += 2) {
+          s0 += (double)ms[o + (size_t)c * rows] * xs[c];
+          s1 += (double)ms[o + (size_t)(c + 1) * rows] * xs[c + 1];
+        }
+        if (c < cols) s0 += (double)ms[o + (size_t)c * rows] * xs[c];
+      } else {
+        const T* col = ms + (size_t)o * rows;
+        int i = o % rows;
+        for (int k = 0; k < rows; ++k) {
+          s0 += (double)col[i] * xs[i];
+          if (++i == rows) i = 0;
+        }
+      }
+      y[(size_t)b * nout + o] = (T)(s0 + s1);
+    }
+  }
+}
+
+// dtheta[b, j] = a_b^T dM_{b,j} w_b, one workgroup per (b, j) (grid-stride):
+// dM_{b,j} copied to LDS as above; thread c forms (a_b^T dM)[c] (rotated
+// walk down column c) times w_b[c]; a block sum.
+template <class T>
+__global__ void __launch_bounds__(256) k_bilinear_lds(const T* A, const T* dM, const T* W, int rs, int rt, int B,
+                                                      int dt, T* dth) {
+  extern __shared__ float smem[];
+  const int ndw = (int)((size_t)rs * rt * sizeof(T) / 4);
+  const T* ds = reinterpret_cast<const T*>(smem);
+  double* as = reinterpret_cast<double*>(smem + ((ndw + 1) & ~1));
+  double* red = as + rs;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int q = blockIdx.x; q < B * dt; q += gridDim.x) {
+    const int b = q / dt;
+    __syncthreads();
+    copy_to_lds(dM + (size_t)q * rs * rt, ndw, smem, lane, wv);
+    for (int i = tid; i < rs; i += 256) as[i] = (double)A[(size_t)b * rs + i];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    asm volatile("" ::: "memory");
+    double s = 0.0;
+    for (int c = tid; c < rt; c += 256) {
+      const T* col = ds + (size_t)c * rs;
+      double t = 0.0;
+      int i = c % rs;
+      for (int k = 0; k < rs; ++k) {
+        t += (double)col[i] * as[i];
+        if (++i == rs) i = 0;
+      }
+      s += t * (double)W[(size_t)b * rt + c];
+    }
+    s = wave64_sum(s);
+    if (lane == 0) red[wv] = s;
+    __syncthreads();
+    if (tid == 0) dth[q] = (T)((red[0] + red[1]) + (red[2] + red[3]));
+  }
+}
+
 inline unsigned grid_cap(int64_t want, int64_t cap) { return (unsigned)std::max<int64_t>(1, std::min(want, cap)); }
 
 }  // namespace
@@ -564,30 +667,96 @@ tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, cons
   return TTK_OK;
 }
 
+namespace {
+size_t matvec_lds_bytes(int rows, int cols, size_t es) {
+  const size_t ndw = (size_t)rows * cols * es / 4;
+  return ((ndw + 1) & ~(size_t)1) * 4 + (size_t)std::max(rows, cols) * sizeof(double);
+}
+bool matvec_lds_ok(int rows, int cols, size_t es) { return matvec_lds_bytes(rows, cols, es) <= SMALL_LDS_BYTES; }
+
+template <class T>
+void launch_bmatvec(const T* M, int rows, int cols, int trans, const T* x, const double* sums, int64_t count, T* xout,
+                    int B, T* y, hipStream_t st) {
+  const unsigned g = grid_cap(B, 2048);
+  if (matvec_lds_ok(rows, cols, sizeof(T)))
+    hipLaunchKernelGGL(k_bmatvec_lds<T>, dim3(g), dim3(256), matvec_lds_bytes(rows, cols, sizeof(T)), st, M, rows,
+                       cols, trans, x, sums, count, xout, B, y);
+  else
+    hipLaunchKernelGGL(k_bmatvec<T>, dim3(g), dim3(256), 0, st, M, rows, cols, trans, x, B, y);
+}
+}  // namespace
+
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x, int B, void* y,
                     hipStream_t st) {
   if (B <= 0) return;
-  const unsigned g = grid_cap(B, 2048);
   if (dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_bmatvec<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(M), rows, cols, trans,
-                       static_cast<const float*>(x), B, static_cast<float*>(y));
+    launch_bmatvec(static_cast<const float*>(M), rows, cols, trans, static_cast<const float*>(x), nullptr, 0,
+                   static_cast<float*>(nullptr), B, static_cast<float*>(y), st);
   else
-    hipLaunchKernelGGL(k_bmatvec<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(M), rows, cols,
-                       trans, static_cast<const double*>(x), B, static_cast<double*>(y));
+    launch_bmatvec(static_cast<const double*>(M), rows, cols, trans, static_cast<const double*>(x), nullptr, 0,
+                   static_cast<double*>(nullptr), B, static_cast<double*>(y), st);
 }
+
+tt_status apply_reduce_matvec(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx, int B,
+                              void* W, const void* M, int rows, int cols, int trans, void* Z, void* work,
+                              hipStream_t st) {
+  if (B <= 0) return TTK_OK;
+  if ((trans ? rows : cols) != r)
+    return fail(TTK_ERR_ARG, "reduce_matvec: op(M) takes %d inputs, W has %d", trans ? rows : cols, r);
+  const size_t es = dtype == TTK_FP32 ? 4 : 8;
+  if (N <= 0 || !skinny(r, B) || !matvec_lds_ok(rows, cols, es)) {
+    TTK_TRY(apply_reduce(dtype, F, ldf, N, r, X, ldx, B, W, work, st));
+    batched_matvec(dtype, M, rows, cols, trans, W, B, Z, st);
+    return TTK_OK;
+  }
+  // the skinny reduce's partials and range sums, then one launch that adds
+  // the ranges (writing W) and multiplies
+  const unsigned g = skinny_groups(N);
+  const int count = r * B;
+  double* part = static_cast<double*>(work);
+  double* sums = part + (size_t)g * count;
+  if (dtype == TTK_FP32 && skinny_mfma_ok(F, ldf, r, B))
+    TTK_TRY(reduce_skinny_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(X), ldx, B, part,
+                               g, st));
+  else if (dtype == TTK_FP32)
+    hipLaunchKernelGGL(k_reduce_skinny<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(F), ldf, N, r,
+                       static_cast<const float*>(X), ldx, B, SKINNY_CHUNK, part);
+  else
+    hipLaunchKernelGGL(k_reduce_skinny<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(F), ldf, N, r,
+                       static_cast<const double*>(X), ldx, B, SKINNY_CHUNK, part);
+  hipLaunchKernelGGL(k_sum_ranges, dim3((count + 63) / 64, NRANGE), dim3(256), 0, st, (const double*)part, (int)g,
+                     count, sums);
+  if (dtype == TTK_FP32)
+    launch_bmatvec(static_cast<const float*>(M), rows, cols, trans, static_cast<const float*>(nullptr), sums, count,
+                   static_cast<float*>(W), B, static_cast<float*>(Z), st);
+  else
+    launch_bmatvec(static_cast<const double*>(M), rows, cols, trans, static_cast<const double*>(nullptr), sums,
+                   count, static_cast<double*>(W), B, static_cast<double*>(Z), st);
+  return TTK_OK;
+}
+
+namespace {
+template <class T>
+void launch_bilinear(const T* A, const T* dM, const T* W, int rs, int rt, int B, int dt, T* dth, hipStream_t st) {
+  const size_t ndw = (size_t)rs * rt * sizeof(T) / 4;
+  const size_t sh = ((ndw + 1) & ~(size_t)1) * 4 + (size_t)(rs + 4) * sizeof(double);
+  if (sh <= SMALL_LDS_BYTES)
+    hipLaunchKernelGGL(k_bilinear_lds<T>, dim3(grid_cap((int64_t)B * dt, 4096)), dim3(256), sh, st, A, dM, W, rs, rt,
+                       B, dt, dth);
+  else
+    hipLaunchKernelGGL(k_bilinear<T>, dim3(grid_cap(B, 2048)), dim3(256), 0, st, A, dM, W, rs, rt, B, dt, dth);
+}
+}  // namespace
 
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt, int B, int dt,
                       void* dtheta, hipStream_t st) {
   if (B <= 0 || dt <= 0) return;
-  const unsigned g = grid_cap(B, 2048);
   if (dtype == TTK_FP32)
-    hipLaunchKernelGGL(k_bilinear<float>, dim3(g), dim3(256), 0, st, static_cast<const float*>(A),
-                       static_cast<const float*>(dM), static_cast<const float*>(W), rs, rt, B, dt,
-                       static_cast<float*>(dtheta));
+    launch_bilinear(static_cast<const float*>(A), static_cast<const float*>(dM), static_cast<const float*>(W), rs, rt,
+                    B, dt, static_cast<float*>(dtheta), st);
   else
-    hipLaunchKernelGGL(k_bilinear<double>, dim3(g), dim3(256), 0, st, static_cast<const double*>(A),
-                       static_cast<const double*>(dM), static_cast<const double*>(W), rs, rt, B, dt,
-                       static_cast<double*>(dtheta));
+    launch_bilinear(static_cast<const double*>(A), static_cast<const double*>(dM), static_cast<const double*>(W), rs,
+                    rt, B, dt, static_cast<double*>(dtheta), st);
 }
 
 }  // namespace ttk

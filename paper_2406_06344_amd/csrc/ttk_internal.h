@@ -312,6 +312,13 @@ tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const fl
                              double* part, unsigned groups, hipStream_t st);
 tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
                              int64_t ldy, hipStream_t st);
+// W (r x B) = F^T X, then Z_b = op(M_b) W_b (r = the number of inputs of
+// op(M)); work as for apply_reduce.  For skinny batches with M_b small
+// enough for LDS the sum of the reduce's partials and the product are one
+// launch.
+tt_status apply_reduce_matvec(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
+                              int B, void* W, const void* M, int rows, int cols, int trans, void* Z, void* work,
+                              hipStream_t st);
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
                     int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,
