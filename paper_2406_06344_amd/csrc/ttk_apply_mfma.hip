@@ -549,6 +549,73 @@ __global__ void __launch_bounds__(256, 2) k_expand_skinny_mfma(const float* __re
   }
 }
 
+// The same product with the rows of F staged in LDS first: one wave per
+// workgroup copies its 64 rows (contiguous in memory, ldf apart) by 16-byte
+// direct global->LDS loads, lane l to dword 4 l of each 1 KB piece, so every
+// quarter-wave reads 256 contiguous bytes; the A operands are then 16-byte
+// LDS reads in the layout above.  Of the last row only the first
+// ceil(r / 4) 16-byte pieces are copied.  ldf <= SK_DMA_MAXLD.
+constexpr int SK_DMA_MAXLD = 160;
+template <int U, bool VEC>
+__global__ void __launch_bounds__(64) k_expand_skinny_dma(const float* __restrict__ F, int ldf, int64_t N, int r,
+                                                          const float* __restrict__ Z, int B, float* __restrict__ Y,
+                                                          int64_t ldy) {
+  extern __shared__ __attribute__((aligned(16))) float fsm[];
+  const int lane = threadIdx.x, i16 = lane & 15, kq = lane >> 4;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int rows = (int)(N - p0 < 64 ? N - p0 : 64);
+  const int ndw = (rows - 1) * ldf + ((r + 3) & ~3);
+  const float* src = F + p0 * (int64_t)ldf;
+  for (int j = 0; 256 * j < ndw; ++j)
+    if (256 * j + 4 * lane < ndw) __builtin_amdgcn_global_load_lds(src + 256 * j + 4 * lane, fsm + 256 * j, 16, 0, 0);
+  float zr[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = 16 * u + 4 * kq + e;
+      zr[u][e] = (i16 < B && c < r) ? Z[c + (int64_t)i16 * r] : 0.f;
+    }
+  __builtin_amdgcn_s_waitcnt(0);                 // the wave's copies have landed (LDS is private to the wave)
+  asm volatile("" ::: "memory");
+  f4 acc[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    f4 fv[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int row = 16 * s + i16, c = 16 * u + 4 * kq;
+      f4 v = f4{0.f, 0.f, 0.f, 0.f};
+      if (row < rows && c < r) {
+        v = *reinterpret_cast<const f4*>(fsm + row * ldf + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (c + e >= r) v[e] = 0.f;
+      }
+      fv[s] = v;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc[s] = mfma4(fv[s][e], zr[u][e], acc[s]);
+  }
+  if (i16 >= B) return;
+  float* ycol = Y + (int64_t)i16 * ldy;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t p = p0 + 16 * s + 4 * kq;
+    if (VEC && p + 3 < N) {
+      *reinterpret_cast<f4*>(ycol + p) = acc[s];
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (p + v < N) ycol[p + v] = acc[s][v];
+    }
+  }
+}
+
 // Chunking of the reduce: enough workgroups to fill the chip (RD_WG_TARGET
 // over the theta blocks), every chunk a whole number of 64-point blocks.
 constexpr int RD_WG_TARGET = 512;
@@ -651,8 +718,18 @@ void launch_reduce_skinny(const float* F, int ldf, int64_t N, int r, const float
 template <int U>
 void launch_expand_skinny(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
                           hipStream_t st) {
+  const bool vec = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
+  if (ldf <= SK_DMA_MAXLD) {
+    const dim3 grid((unsigned)((N + 63) / 64));
+    const size_t sh = (size_t)64 * ldf * sizeof(float);
+    if (vec)
+      hipLaunchKernelGGL((k_expand_skinny_dma<U, true>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+    else
+      hipLaunchKernelGGL((k_expand_skinny_dma<U, false>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
+    return;
+  }
   const dim3 grid((unsigned)((N + SK_P - 1) / SK_P));
-  if ((ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0))
+  if (vec)
     hipLaunchKernelGGL((k_expand_skinny_mfma<U, true>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
   else
     hipLaunchKernelGGL((k_expand_skinny_mfma<U, false>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
