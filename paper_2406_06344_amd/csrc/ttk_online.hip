@@ -43,21 +43,32 @@ __global__ void __launch_bounds__(256) k_online_factor(OnlineArgs oa, const TT* 
   const double dtdth = 2.0 / (lo - hi);
   const int a = e % r0, c = e / r0;
   const double* G = oa.G[j] + a + (int64_t)c * r0 * n;
-  // T_0 = 1, T_1 = t; T'_0 = 0, T'_1 = 1
+  // T_0 = 1, T_1 = t; T'_0 = 0, T'_1 = 1.  The coefficients are loaded in
+  // chunks of OCH, all of a chunk's loads in flight before its terms.
+  constexpr int OCH = 8;
   double tm = 1.0, tc = t, dm = 0.0, dc = 1.0;
-  double s = G[0], ds = 0.0;
-  if (n > 1) {
-    const double g1 = G[(int64_t)r0];
-    s += t * g1;
-    ds += g1;
-  }
-  for (int k = 2; k < n; ++k) {
-    const double tn = 2.0 * t * tc - tm;
-    const double dn = 2.0 * tc + 2.0 * t * dc - dm;
-    tm = tc; tc = tn; dm = dc; dc = dn;
-    const double g = G[(int64_t)k * r0];
-    s += tn * g;
-    ds += dn * g;
+  double s = 0.0, ds = 0.0;
+  for (int k0 = 0; k0 < n; k0 += OCH) {
+    double g[OCH];
+#pragma unroll
+    for (int q = 0; q < OCH; ++q) g[q] = k0 + q < n ? G[(int64_t)(k0 + q) * r0] : 0.0;
+#pragma unroll
+    for (int q = 0; q < OCH; ++q) {
+      const int k = k0 + q;
+      if (k >= n) break;
+      if (k == 0) {
+        s = g[q];
+      } else if (k == 1) {
+        s += t * g[q];
+        ds += g[q];
+      } else {
+        const double tn = 2.0 * t * tc - tm;
+        const double dn = 2.0 * tc + 2.0 * t * dc - dm;
+        tm = tc; tc = tn; dm = dc; dc = dn;
+        s += tn * g[q];
+        ds += dn * g[q];
+      }
+    }
   }
   ds *= dtdth;
   if (oa.dt == 1) {
