@@ -769,27 +769,24 @@ tt_status tt_kernel_apply_backward(tt_kernel_t h, const void* theta, int B, cons
   hipStream_t st = static_cast<hipStream_t>(stream);
   TTK_TRY(prepare_M(h, theta, B, want_dth, st));
   TTK_TRY(h->Abuf.alloc((size_t)h->rs * B * h->es));
+  const void* W = W_saved;
+  if (want_dth && !W) {
+    TTK_TRY(h->Wbuf.alloc((size_t)h->rt * B * h->es));
+    TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, h->Wbuf.p, st));   // W = V^T x
+    W = h->Wbuf.p;
+  }
   if (dX) {
-    // A = U^T G, then M^T a
+    // A = U^T G, M^T a and (with dtheta) a^T dM w in one pass over the partial sums
     TTK_TRY(h->Zbuf.alloc((size_t)std::max(h->rs, h->rt) * B * h->es));
     const size_t wb = apply_reduce_work(h->ns, h->rs, B);
     if (wb) TTK_TRY(h->Pbuf.alloc(wb));
     TTK_TRY(apply_reduce_matvec(h->dtype, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, h->Mbuf.p, h->rs,
-                                h->rt, 1, h->Zbuf.p, wb ? h->Pbuf.p : nullptr, st));
+                                h->rt, 1, h->Zbuf.p, wb ? h->Pbuf.p : nullptr, st, want_dth ? h->dMbuf.p : nullptr,
+                                W, h->g.dt, dtheta));
     TTK_TRY(apply_expand(h->dtype, h->V.p, h->ldv, h->nt, h->rt, h->Zbuf.p, B, dX, lddx, st));
   } else {
     TTK_TRY(reduce_into(h, h->U.p, h->ldu, h->ns, h->rs, G, ldg, B, h->Abuf.p, st));   // A = U^T G
-  }
-  if (want_dth) {
-    const void* W = W_saved;
-    if (!W) {
-      TTK_TRY(h->Wbuf.alloc((size_t)h->rt * B * h->es));
-      TTK_TRY(reduce_into(h, h->V.p, h->ldv, h->nt, h->rt, X, ldx, B, h->Wbuf.p, st));
-      W = h->Wbuf.p;
-    }
-    batched_bilinear(h->dtype, h->Abuf.p, h->dMbuf.p, W, h->rs, h->rt, B, h->g.dt, dtheta, st);
-  } else if (dtheta && h->g.dt == 0) {
-    // no parameters: nothing to write
+    if (want_dth) batched_bilinear(h->dtype, h->Abuf.p, h->dMbuf.p, W, h->rs, h->rt, B, h->g.dt, dtheta, st);
   }
   TTK_HIP(hipGetLastError());
   return TTK_OK;

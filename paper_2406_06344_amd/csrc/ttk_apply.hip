@@ -451,15 +451,20 @@ __device__ inline void copy_to_lds(const void* src, int ndw, float* dst, int lan
 // reduce (entry i of x_b at sums[k count + b nin + i]) and also written to
 // xout.  op = transpose: output o reads column o of M_b, the start of its
 // walk down the column rotated by o so the lanes' LDS reads spread over
-// the banks.
+// the banks.  With dM (op = transpose, x_b = a_b): also
+// dth[b, j] = a_b^T dM_{b,j} w_b for j < dt, each dM_{b,j} copied over M_b
+// in LDS in turn, w_b = Wv[b cols ..].
 template <class T>
 __global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int cols, int trans, const T* x,
-                                                     const double* sums, int64_t count, T* xout, int B, T* y) {
+                                                     const double* sums, int64_t count, T* xout, int B, T* y,
+                                                     const T* dM, const T* Wv, int dt, T* dth) {
   extern __shared__ float smem[];
-  const int nin = trans ? rows : cols, nout = trans ? cols : rows;
+  const int nin = trans ? rows : cols, nout = trans ? cols : rows, nmax = rows > cols ? rows : cols;
   const int ndw = (int)((size_t)rows * cols * sizeof(T) / 4);
   const T* ms = reinterpret_cast<const T*>(smem);
   double* xs = reinterpret_cast<double*>(smem + ((ndw + 1) & ~1));
+  double* ws = xs + nmax;
+  double* red = ws + nmax;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     __syncthreads();                             // the previous b is consumed
@@ -475,6 +480,8 @@ __global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int c
       }
       xs[i] = v;
     }
+    if (dM)
+      for (int c = tid; c < cols; c += 256) ws[c] = (double)Wv[(size_t)b * cols + c];
     __builtin_amdgcn_s_waitcnt(0);               // this wave's copies have landed
     __syncthreads();                             // and everyone's
     asm volatile("" ::: "memory");
@@ -496,6 +503,29 @@ __global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int c
         }
       }
       y[(size_t)b * nout + o] = (T)(s0 + s1);
+    }
+    if (!dM) continue;
+    for (int j = 0; j < dt; ++j) {
+      __syncthreads();                           // M_b (or the last dM) is consumed
+      copy_to_lds(dM + ((size_t)b * dt + j) * rows * cols, ndw, smem, lane, wv);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      asm volatile("" ::: "memory");
+      double sb = 0.0;
+      for (int c = tid; c < cols; c += 256) {
+        const T* col = ms + (size_t)c * rows;
+        double t = 0.0;
+        int i = c % rows;
+        for (int k = 0; k < rows; ++k) {
+          t += (double)col[i] * xs[i];
+          if (++i == rows) i = 0;
+        }
+        sb += t * ws[c];
+      }
+      sb = wave64_sum(sb);
+      if (lane == 0) red[wv] = sb;
+      __syncthreads();
+      if (tid == 0) dth[(size_t)b * dt + j] = (T)((red[0] + red[1]) + (red[2] + red[3]));
     }
   }
 }
@@ -670,17 +700,18 @@ tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, cons
 namespace {
 size_t matvec_lds_bytes(int rows, int cols, size_t es) {
   const size_t ndw = (size_t)rows * cols * es / 4;
-  return ((ndw + 1) & ~(size_t)1) * 4 + (size_t)std::max(rows, cols) * sizeof(double);
+  return ((ndw + 1) & ~(size_t)1) * 4 + ((size_t)2 * std::max(rows, cols) + 4) * sizeof(double);
 }
 bool matvec_lds_ok(int rows, int cols, size_t es) { return matvec_lds_bytes(rows, cols, es) <= SMALL_LDS_BYTES; }
 
 template <class T>
 void launch_bmatvec(const T* M, int rows, int cols, int trans, const T* x, const double* sums, int64_t count, T* xout,
-                    int B, T* y, hipStream_t st) {
+                    int B, T* y, hipStream_t st, const T* dM = nullptr, const T* Wv = nullptr, int dt = 0,
+                    T* dth = nullptr) {
   const unsigned g = grid_cap(B, 2048);
   if (matvec_lds_ok(rows, cols, sizeof(T)))
     hipLaunchKernelGGL(k_bmatvec_lds<T>, dim3(g), dim3(256), matvec_lds_bytes(rows, cols, sizeof(T)), st, M, rows,
-                       cols, trans, x, sums, count, xout, B, y);
+                       cols, trans, x, sums, count, xout, B, y, dM, Wv, dt, dth);
   else
     hipLaunchKernelGGL(k_bmatvec<T>, dim3(g), dim3(256), 0, st, M, rows, cols, trans, x, B, y);
 }
@@ -699,14 +730,17 @@ void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, con
 
 tt_status apply_reduce_matvec(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx, int B,
                               void* W, const void* M, int rows, int cols, int trans, void* Z, void* work,
-                              hipStream_t st) {
+                              hipStream_t st, const void* dM, const void* Wv, int dt, void* dtheta) {
   if (B <= 0) return TTK_OK;
   if ((trans ? rows : cols) != r)
     return fail(TTK_ERR_ARG, "reduce_matvec: op(M) takes %d inputs, W has %d", trans ? rows : cols, r);
+  const bool bil = dM && dt > 0;
+  if (bil && (!trans || !Wv || !dtheta)) return fail(TTK_ERR_ARG, "reduce_matvec: bad bilinear arguments");
   const size_t es = dtype == TTK_FP32 ? 4 : 8;
   if (N <= 0 || !skinny(r, B) || !matvec_lds_ok(rows, cols, es)) {
     TTK_TRY(apply_reduce(dtype, F, ldf, N, r, X, ldx, B, W, work, st));
     batched_matvec(dtype, M, rows, cols, trans, W, B, Z, st);
+    if (bil) batched_bilinear(dtype, W, dM, Wv, rows, cols, B, dt, dtheta, st);
     return TTK_OK;
   }
   // the skinny reduce's partials and range sums, then one launch that adds
@@ -728,10 +762,13 @@ tt_status apply_reduce_matvec(int dtype, const void* F, int ldf, int64_t N, int 
                      count, sums);
   if (dtype == TTK_FP32)
     launch_bmatvec(static_cast<const float*>(M), rows, cols, trans, static_cast<const float*>(nullptr), sums, count,
-                   static_cast<float*>(W), B, static_cast<float*>(Z), st);
+                   static_cast<float*>(W), B, static_cast<float*>(Z), st, static_cast<const float*>(bil ? dM : nullptr),
+                   static_cast<const float*>(Wv), dt, static_cast<float*>(dtheta));
   else
     launch_bmatvec(static_cast<const double*>(M), rows, cols, trans, static_cast<const double*>(nullptr), sums,
-                   count, static_cast<double*>(W), B, static_cast<double*>(Z), st);
+                   count, static_cast<double*>(W), B, static_cast<double*>(Z), st,
+                   static_cast<const double*>(bil ? dM : nullptr), static_cast<const double*>(Wv), dt,
+                   static_cast<double*>(dtheta));
   return TTK_OK;
 }
 

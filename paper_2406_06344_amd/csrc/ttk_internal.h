@@ -313,12 +313,14 @@ tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const fl
 tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
                              int64_t ldy, hipStream_t st);
 // W (r x B) = F^T X, then Z_b = op(M_b) W_b (r = the number of inputs of
-// op(M)); work as for apply_reduce.  For skinny batches with M_b small
-// enough for LDS the sum of the reduce's partials and the product are one
-// launch.
+// op(M)); work as for apply_reduce.  With dM (op = transpose only): also
+// dtheta[b, j] = W_b^T dM_{b,j} Wv_b for j < dt (Wv: cols x B).  For skinny
+// batches with M_b small enough for LDS the sum of the reduce's partials,
+// the product and the bilinear forms are one launch.
 tt_status apply_reduce_matvec(int dtype, const void* F, int ldf, int64_t N, int r, const void* X, int64_t ldx,
                               int B, void* W, const void* M, int rows, int cols, int trans, void* Z, void* work,
-                              hipStream_t st);
+                              hipStream_t st, const void* dM = nullptr, const void* Wv = nullptr, int dt = 0,
+                              void* dtheta = nullptr);
 void batched_matvec(int dtype, const void* M, int rows, int cols, int trans, const void* x,
                     int B, void* y, hipStream_t st);    // y_b = op(M_b) x_b
 void batched_bilinear(int dtype, const void* A, const void* dM, const void* W, int rs, int rt,

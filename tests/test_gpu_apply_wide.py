@@ -103,6 +103,14 @@ def _check_apply_and_backward(rs, rt, ns, nt, B):
     say("  (rel Frobenius, max entry):", {k: (f"{a:.2e}", f"{b:.2e}") for k, (a, b) in res.items()})
     for k, (fro, mx) in res.items():
         assert fro <= 1e-5 and mx <= 1e-5, (k, fro, mx)
+    # the backward without the saved W (W formed from X) and without dX
+    gt = torch.tensor(gb.T.copy(), dtype=torch.float32)
+    dX2, dth2 = kern.apply_backward(tht, gt, X=torch.tensor(xb.T.copy(), dtype=torch.float32))
+    _, dth3 = kern.apply_backward(tht, gt, W=Wg, want_dx=False)
+    assert errs(dX2.cpu().numpy().T, dX_o)[0] <= 1e-5
+    for d in (dth2, dth3):
+        fro, mx = errs(d.cpu().numpy(), dth_o)
+        assert fro <= 1e-5 and mx <= 1e-5, (fro, mx)
     # the plain per-theta apply (other kernels) agrees with the batched one
     Yp = kern.apply_plain(tht[:5], torch.tensor(xb[:, :5].T.copy(), dtype=torch.float32))
     assert errs(Yp.cpu().numpy(), Yg[:5].cpu().numpy())[0] <= 1e-5
