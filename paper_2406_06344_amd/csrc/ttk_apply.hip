@@ -446,6 +446,30 @@ __device__ inline void copy_to_lds(const void* src, int ndw, float* dst, int lan
     if (64 * j + lane < ndw) __builtin_amdgcn_global_load_lds(s + 64 * j + lane, dst + 64 * j, 4, 0, 0);
 }
 
+// sum_i col[i] x[i] over i < n, the walk starting at `start` and wrapping
+// (lanes with consecutive starts read consecutive LDS banks), in four
+// interleaved partial sums so the loads and FMAs of successive terms
+// overlap.
+template <class T>
+__device__ inline double dot_rotated(const T* col, const double* x, int n, int start) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int k = 0;
+  for (; k + 3 < n; k += 4) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int i = start + k + q;
+      i -= i >= n ? n : 0;
+      s[q] += (double)col[i] * x[i];
+    }
+  }
+  for (; k < n; ++k) {
+    int i = start + k;
+    i -= i >= n ? n : 0;
+    s[0] += (double)col[i] * x[i];
+  }
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 // y_b = op(M_b) x_b, one workgroup per b (grid-stride).  With `sums`, x_b is
 // first formed as the fixed-order sum of the NRANGE range sums of the skinny
 // reduce (entry i of x_b at sums[k count + b nin + i]) and also written to
@@ -488,19 +512,19 @@ __global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int c
     for (int o = tid; o < nout; o += 256) {
       double s0 = 0.0, s1 = 0.0;
       if (!trans) {
+        double s2 = 0.0, s3 = 0.0;
         int c = 0;
-        for (; c + 1 < cols; c += 2) {
+        for (; c + 3 < cols; c += 4) {
           s0 += (double)ms[o + (size_t)c * rows] * xs[c];
           s1 += (double)ms[o + (size_t)(c + 1) * rows] * xs[c + 1];
+          s2 += (double)ms[o + (size_t)(c + 2) * rows] * xs[c + 2];
+          s3 += (double)ms[o + (size_t)(c + 3) * rows] * xs[c + 3];
         }
-        if (c < cols) s0 += (double)ms[o + (size_t)c * rows] * xs[c];
+        for (; c < cols; ++c) s0 += (double)ms[o + (size_t)c * rows] * xs[c];
+        s0 += s2;
+        s1 += s3;
       } else {
-        const T* col = ms + (size_t)o * rows;
-        int i = o % rows;
-        for (int k = 0; k < rows; ++k) {
-          s0 += (double)col[i] * xs[i];
-          if (++i == rows) i = 0;
-        }
+        s0 = dot_rotated(ms + (size_t)o * rows, xs, rows, o % rows);
       }
       y[(size_t)b * nout + o] = (T)(s0 + s1);
     }
@@ -512,16 +536,7 @@ __global__ void __launch_bounds__(256) k_bmatvec_lds(const T* M, int rows, int c
       __syncthreads();
       asm volatile("" ::: "memory");
       double sb = 0.0;
-      for (int c = tid; c < cols; c += 256) {
-        const T* col = ms + (size_t)c * rows;
-        double t = 0.0;
-        int i = c % rows;
-        for (int k = 0; k < rows; ++k) {
-          t += (double)col[i] * xs[i];
-          if (++i == rows) i = 0;
-        }
-        sb += t * ws[c];
-      }
+      for (int c = tid; c < cols; c += 256) sb += dot_rotated(ms + (size_t)c * rows, xs, rows, c % rows) * ws[c];
       sb = wave64_sum(sb);
       if (lane == 0) red[wv] = sb;
       __syncthreads();
@@ -551,16 +566,7 @@ __global__ void __launch_bounds__(256) k_bilinear_lds(const T* A, const T* dM, c
     __syncthreads();
     asm volatile("" ::: "memory");
     double s = 0.0;
-    for (int c = tid; c < rt; c += 256) {
-      const T* col = ds + (size_t)c * rs;
-      double t = 0.0;
-      int i = c % rs;
-      for (int k = 0; k < rs; ++k) {
-        t += (double)col[i] * as[i];
-        if (++i == rs) i = 0;
-      }
-      s += t * (double)W[(size_t)b * rt + c];
-    }
+    for (int c = tid; c < rt; c += 256) s += dot_rotated(ds + (size_t)c * rs, as, rs, c % rs) * (double)W[(size_t)b * rt + c];
     s = wave64_sum(s);
     if (lane == 0) red[wv] = s;
     __syncthreads();
