@@ -549,11 +549,15 @@ __global__ void __launch_bounds__(BS) k_larft(const double* V, int m, int jb, co
 // Register-resident panel factorisation for panels of at most PBT * RPT rows
 // and 16 columns, PBT threads: thread t holds rows t + k PBT (k < RPT) of
 // every column.
-// Per column j: the norm below the diagonal is one block reduction and the
-// sixteen products v_j^T a_c one more (both through LDS, no lane shuffles);
-// for c > j they update the trailing panel columns, for c < j they are
-// v_c^T v_j, from which column j of T (H_0 ... H_{jb-1} = I - V T V^T) follows
-// by the forward recurrence T(r, j) = -tau_j sum_{r <= q < j} T(r, q) v_q^T v_j.
+// Per column j, one block reduction (through LDS, no lane shuffles) of the
+// sixteen sums D_c = sum_{i > j} a_j(i) a_c(i): D_j is the squared norm
+// below the diagonal, and with the reflector v_j = e_j + s a_j(below j),
+// s = 1 / (x0 - alpha), every other product follows without a second pass,
+// v_j^T a_c = a_c(j) + s D_c: for c > j the update of the trailing panel
+// columns, for c < j (a_c below row c holds v_c) the product v_c^T v_j, from
+// which column j of T (H_0 ... H_{jb-1} = I - V T V^T) follows by the
+// forward recurrence T(r, j) = -tau_j sum_{r <= q < j} T(r, q) v_q^T v_j.
+// Row j of the panel (before H_j) comes from the thread that holds it.
 // Writes the reflectors below the diagonal of the panel (unit diagonal
 // implicit), R on and above it, tau, V explicit (mm x jb) and T (jb x jb).
 constexpr int PB = 256;
@@ -568,10 +572,9 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
   T += blockIdx.y * sT;
   constexpr int NB = 16, S = PBT / NB;   // S strips per column in the first reduction stage
   // block sums through LDS: every thread's partials in P (conflict-free
-  // columns), then S partial sums per column in Q, then the final sums
+  // columns), then S partial sums per column in Q, then the sums in D
   __shared__ double P[NB][PBT], Q[NB][S];
-  __shared__ double sd[NB], Ts[NB][NB];
-  __shared__ double s_x0;
+  __shared__ double D[NB], rowj[2][NB], Ts[NB][NB];
   const int tid = threadIdx.x;
   const int rc = tid / S, rj = tid % S;   // (column, strip) of the first reduction stage
   double a[RPT][NB];
@@ -584,54 +587,19 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
 #pragma clang loop unroll(full)
   for (int j = 0; j < NB; ++j) {
     if (j >= jb) continue;   // uniform; the loop is fully unrolled (constant j)
-    // norm of column j below the diagonal; x0 = A(j, j) sits in thread j
-    double part = 0.0;
+    // row j (thread j) and every thread's partials of D_c over its rows below j
+    if (tid == j)
 #pragma unroll
-    for (int k = 0; k < RPT; ++k)
-      if (tid + k * PBT > j) part += a[k][j] * a[k][j];
-    P[0][tid] = part;
-    if (tid == j) s_x0 = a[0][j];
-    __syncthreads();
-    if (tid < S) {
-      double sum = 0.0;
-#pragma unroll
-      for (int u = 0; u < PBT / S; ++u) sum += P[0][u * S + tid];
-      Q[0][tid] = sum;
-    }
-    __syncthreads();
-    double tail = 0.0;
-#pragma unroll
-    for (int q = 0; q < S; ++q) tail += Q[0][q];
-    const double x0 = s_x0;
-    double tj = 0.0, alpha = x0, scale = 0.0;
-    if (tail != 0.0) {
-      const double nrm = sqrt(x0 * x0 + tail);
-      alpha = x0 >= 0.0 ? -nrm : nrm;
-      tj = (alpha - x0) / alpha;
-      scale = 1.0 / (x0 - alpha);
-    }
-    // v_j: 1 at row j, the scaled column below it
-    double v[RPT];
-#pragma unroll
-    for (int k = 0; k < RPT; ++k) {
-      const int i = tid + k * PBT;
-      if (i > j && tj != 0.0) a[k][j] *= scale;
-      v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
-    }
-    // products with every other column: a_c for c > j, v_c for c < j
-    __syncthreads();   // every thread has read Q[0][] and s_x0
+      for (int c = 0; c < NB; ++c) rowj[j & 1][c] = a[0][c];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      double sum = 0.0;
-      if (c != j && c < jb) {
+      double part = 0.0;
+      if (c < jb) {
 #pragma unroll
-        for (int k = 0; k < RPT; ++k) {
-          const int i = tid + k * PBT;
-          const double x = (c > j) ? a[k][c] : ((i > c) ? a[k][c] : (i == c ? 1.0 : 0.0));
-          sum += v[k] * x;
-        }
+        for (int k = 0; k < RPT; ++k)
+          if (tid + k * PBT > j) part += a[k][j] * a[k][c];
       }
-      P[c][tid] = sum;
+      P[c][tid] = part;
     }
     __syncthreads();
     {
@@ -645,9 +613,28 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
       double sum = 0.0;
 #pragma unroll
       for (int q = 0; q < S; ++q) sum += Q[tid][q];
-      sd[tid] = sum;
+      D[tid] = sum;
     }
     __syncthreads();
+    const double tail = D[j], x0 = rowj[j & 1][j];
+    double tj = 0.0, alpha = x0, scale = 0.0;
+    if (tail != 0.0) {
+      const double nrm = sqrt(x0 * x0 + tail);
+      alpha = x0 >= 0.0 ? -nrm : nrm;
+      tj = (alpha - x0) / alpha;
+      scale = 1.0 / (x0 - alpha);
+    }
+    double sd[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) sd[c] = rowj[j & 1][c] + scale * D[c];
+    // v_j: 1 at row j, the scaled column below it
+    double v[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = tid + k * PBT;
+      if (i > j && tj != 0.0) a[k][j] *= scale;
+      v[k] = (i > j) ? a[k][j] : (i == j ? 1.0 : 0.0);
+    }
     // apply H_j to the later columns; column j of T from the earlier ones
 #pragma unroll
     for (int c = j + 1; c < NB; ++c) {
@@ -661,7 +648,9 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
       double t = 0.0;
       if (tid < j) {
         double acc = 0.0;
-        for (int q = tid; q < j; ++q) acc += Ts[tid][q] * sd[q];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q >= tid && q < j) acc += Ts[tid][q] * sd[q];
         t = -tj * acc;
       } else if (tid == j) {
         t = tj;
@@ -670,8 +659,11 @@ __global__ void __launch_bounds__(PBT) k_qr_panel_reg(double* A, int mm, int jb,
     }
     if (tid == j) a[0][j] = alpha;   // R's diagonal entry
     if (tid == 0) tau[j] = tj;
-    __syncthreads();   // sd and Ts column j are complete before the next column
+    // (the next column's first barrier orders Ts, D and rowj: T's column j is
+    // read only from the next column's recurrence on, after that barrier;
+    // D is rewritten only after two more; rowj alternates by parity)
   }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int i = tid + k * PBT;
