@@ -11,8 +11,9 @@
 // expand: a wave owns 64 points and keeps their rows of F as A operands in
 //   registers for the whole launch; the workgroup (4 waves, 256 points)
 //   walks the thetas in blocks of 64, each block of Z fetched into LDS by
-//   direct global->LDS loads while the previous block is multiplied.  Each
-//   K-step reads 4 B operands from LDS for 16 MFMAs.
+//   direct global->LDS loads while the previous block is multiplied, in two
+//   halves of 32 thetas (half the accumulators live: three waves per SIMD).
+//   Each K-step reads 2 B operands from LDS for 8 MFMAs.
 //   Output: register v of a lane is 4 consecutive points of one column of
 //   the column-major Y, stored as one 16-byte write.
 // reduce: a workgroup owns 128 thetas and one chunk of the points; blocks of
@@ -91,42 +92,46 @@ __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict_
     __syncthreads();                             // everyone's; and block ib - 1 is consumed
     asm volatile("" ::: "memory");               // LDS reads below see the DMA writes
     if (ib + 1 < nb) issue(b0 + EX_TB, zsm + (size_t)((ib + 1) & 1) * stage);
-    f4 acc[4][4];
+    // the block's 64 thetas in two halves of 32 (half the accumulators live)
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[s][q] = f4{0.f, 0.f, 0.f, 0.f};
-    // B[c][theta] = Z[c + (b0 + theta) r] = zs[theta r + c]
-    const float* zrow = zs + i16 * r + kq;
-#pragma unroll
-    for (int t = 0; t < KS; ++t) {
-      float bz[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) bz[q] = zrow[16 * q * r + 4 * t];
+    for (int h = 0; h < 2; ++h) {
+      f4 acc[4][2];
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[s][q] = mfma4(af[s][t], bz[q], acc[s][q]);
-    }
-    // D[4 kq + v][i16]: points p0 + 16 s + 4 kq + v, theta b0 + 16 q + i16
+        for (int q = 0; q < 2; ++q) acc[s][q] = f4{0.f, 0.f, 0.f, 0.f};
+      // B[c][theta] = Z[c + (b0 + theta) r] = zs[theta r + c]
+      const float* zrow = zs + (32 * h + i16) * r + kq;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int th = b0 + 16 * q + i16;
-      if (th >= B) continue;
-      float* ycol = Y + (int64_t)th * ldy;
+      for (int t = 0; t < KS; ++t) {
+        float bz[2];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t p = p0 + 16 * s + 4 * kq;
-        if (VEC && p + 3 < N) {
-          if (ACC) *reinterpret_cast<f4*>(ycol + p) += acc[s][q];
-          else *reinterpret_cast<f4*>(ycol + p) = acc[s][q];
-        } else {
+        for (int q = 0; q < 2; ++q) bz[q] = zrow[16 * q * r + 4 * t];
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (p + v < N) {
-              if (ACC) ycol[p + v] += acc[s][q][v];
-              else ycol[p + v] = acc[s][q][v];
-            }
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) acc[s][q] = mfma4(af[s][t], bz[q], acc[s][q]);
+      }
+      // D[4 kq + v][i16]: points p0 + 16 s + 4 kq + v, theta b0 + 32 h + 16 q + i16
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int th = b0 + 32 * h + 16 * q + i16;
+        if (th >= B) continue;
+        float* ycol = Y + (int64_t)th * ldy;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int64_t p = p0 + 16 * s + 4 * kq;
+          if (VEC && p + 3 < N) {
+            if (ACC) *reinterpret_cast<f4*>(ycol + p) += acc[s][q];
+            else *reinterpret_cast<f4*>(ycol + p) = acc[s][q];
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (p + v < N) {
+                if (ACC) ycol[p + v] += acc[s][q][v];
+                else ycol[p + v] = acc[s][q][v];
+              }
+          }
         }
       }
     }
