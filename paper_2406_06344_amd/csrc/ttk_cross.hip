@@ -329,7 +329,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 struct TTTile {
   int32_t i, start, count, pad;   // the group's index, first position in perm, points (<= 16)
 };
-constexpr int TTW = 8;   // waves per block of k_tt_core
+constexpr int TTW = 16;  // waves per block of k_tt_core (one 16-column tile each up to r = 256)
 constexpr int TTB = 8;   // MFMA steps whose B operands are loaded together
 __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, int r1, int m, const double* Vin,
                                                       int ldin, double* Vout, int ldout, const int32_t* perm,
