@@ -678,7 +678,7 @@ tt_status apply_expand(int dtype, const void* F, int ldf, int64_t N, int r, cons
     return TTK_OK;
   }
   if (B <= SB && r <= SR) {
-    if (dtype == TTK_FP32 && skinny_mfma_ok(F, ldf, r, B))
+    if (dtype == TTK_FP32 && skinny_expand_mfma_ok(F, ldf, r, B))
       return expand_skinny_mfma(static_cast<const float*>(F), ldf, N, r, static_cast<const float*>(Z), B,
                                 static_cast<float*>(Y), ldy, st);
     const unsigned g = (unsigned)((N + ST - 1) / ST);

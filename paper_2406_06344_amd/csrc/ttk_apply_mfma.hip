@@ -381,8 +381,9 @@ __global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ p
 
 // ------------------------------------------------------------------ skinny
 // Short batches (2 <= B <= 16 thetas, r <= 128) with F rows 16-byte aligned
-// (ldf % 4 == 0): one 16 x 16 theta tile, so a wave keeps every operand in
-// registers and nothing is staged in LDS.  Each lane loads 4 consecutive
+// (ldf % 4 == 0): one 16 x 16 theta tile, so a wave keeps Z or X and its
+// sums in registers (the expand stages its rows of F in LDS, the reduce
+// loads them straight into registers).  Each lane reads 4 consecutive
 // columns of a row of F (16 bytes) and the MFMA K index is permuted to
 // match: within a 16-row step of the reduce, lane group kq = l / 16 takes
 // rows 4 kq .. 4 kq + 3, the four MFMAs of the step one row each; in the
@@ -393,13 +394,14 @@ __global__ void __launch_bounds__(256) k_sum_chunks(const double* __restrict__ p
 // W (r x B) = F^T X over 256 rows per workgroup (64 per wave, in 16-row
 // steps), float32 MFMA sums over the wave's rows, the four waves' sums added
 // in float64 and written as the workgroup's partial
-// part[blockIdx.x r B + c + theta r] (k_sum_ranges / k_sum_final add them).
+// part[blockIdx.x r B + c + theta r] (k_sum_ranges, then k_sum_final or
+// k_bmatvec_lds, add them).
 // Columns: G groups of 64 read as 16-byte loads (group g, element e of lane
 // i16 is column 64 g + 4 i16 + e: four MFMA tiles per group, tile (g, e)
 // holding the columns 64 g + 4 m + e, m < 16), then TT tiles of 16 columns
 // read one float per lane (column 64 G + 16 t + i16).  VEC: X's columns are
 // 16-byte aligned, so a lane's 4 rows of one theta are one load.
-constexpr int SK_P = 256;   // rows per workgroup of the skinny reduce, points per workgroup of the expand
+constexpr int SK_P = 256;   // rows per workgroup of the skinny reduce
 
 template <int G, int TT, bool VEC>
 __global__ void __launch_bounds__(256, 2) k_reduce_skinny_mfma(const float* __restrict__ F, int ldf, int64_t N,
@@ -489,77 +491,17 @@ __global__ void __launch_bounds__(256, 2) k_reduce_skinny_mfma(const float* __re
     }
 }
 
-// Y (N x B) = F Z, 64 points per wave in four 16-point tiles.  Z (r x B,
-// leading dimension r) is held in registers: lane (i16, kq) keeps
-// Z[16 u + 4 kq + e][i16]; the lane's A operand for step (u, e) is element e
-// of its 16-byte load F[p][16 u + 4 kq ..].  U = ceil(r / 16).  VEC: Y's
-// columns are 16-byte aligned, a lane's 4 consecutive points go as one store.
-template <int U, bool VEC>
-__global__ void __launch_bounds__(256, 2) k_expand_skinny_mfma(const float* __restrict__ F, int ldf, int64_t N,
-                                                               int r, const float* __restrict__ Z, int B,
-                                                               float* __restrict__ Y, int64_t ldy) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int i16 = lane & 15, kq = lane >> 4;
-  const int64_t p0 = (int64_t)blockIdx.x * SK_P + (int64_t)w * 64;
-  if (p0 >= N) return;                           // (no barrier below)
-  f4 fv[4][U];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int64_t p = p0 + 16 * s + i16;
-    const bool pin = p < N;
-    const float* row = F + (pin ? p : 0) * (int64_t)ldf;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = 16 * u + 4 * kq;
-      f4 v = f4{0.f, 0.f, 0.f, 0.f};
-      if (pin && c < r) {
-        v = *reinterpret_cast<const f4*>(row + c);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (c + e >= r) v[e] = 0.f;
-      }
-      fv[s][u] = v;
-    }
-  }
-  float zr[U][4];
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = 16 * u + 4 * kq + e;
-      zr[u][e] = (i16 < B && c < r) ? Z[c + (int64_t)i16 * r] : 0.f;
-    }
-  f4 acc[4];
-#pragma unroll
-  for (int s = 0; s < 4; ++s) acc[s] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) acc[s] = mfma4(fv[s][u][e], zr[u][e], acc[s]);
-  if (i16 >= B) return;
-  // D[4 kq + v][i16]: point p0 + 16 s + 4 kq + v, theta i16
-  float* ycol = Y + (int64_t)i16 * ldy;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int64_t p = p0 + 16 * s + 4 * kq;
-    if (VEC && p + 3 < N) {
-      *reinterpret_cast<f4*>(ycol + p) = acc[s];
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (p + v < N) ycol[p + v] = acc[s][v];
-    }
-  }
-}
-
-// The same product with the rows of F staged in LDS first: one wave per
-// workgroup copies its 64 rows (contiguous in memory, ldf apart) by 16-byte
-// direct global->LDS loads, lane l to dword 4 l of each 1 KB piece, so every
-// quarter-wave reads 256 contiguous bytes; the A operands are then 16-byte
-// LDS reads in the layout above.  Of the last row only the first
-// ceil(r / 4) 16-byte pieces are copied.  ldf <= SK_DMA_MAXLD.
+// Y (N x B) = F Z, one wave per workgroup, 64 points in four 16-point
+// tiles.  The wave first copies its 64 rows of F (contiguous in memory, ldf
+// apart) into LDS by 16-byte direct global->LDS loads, lane l to dword 4 l
+// of each 1 KB piece, so every quarter-wave reads 256 contiguous bytes (the
+// A operands loaded straight from memory would take 16 rows per
+// quarter-wave); of the last row only the first ceil(r / 4) 16-byte pieces
+// are copied.  Z (r x B, leading dimension r) is held in registers: lane
+// (i16, kq) keeps Z[16 u + 4 kq + e][i16]; its A operand for step (u, e) is
+// element e of its 16-byte LDS read F[p][16 u + 4 kq ..].  U = ceil(r / 16).
+// VEC: Y's columns are 16-byte aligned, a lane's 4 consecutive points go as
+// one store.  ldf <= SK_DMA_MAXLD (64 rows in LDS).
 constexpr int SK_DMA_MAXLD = 160;
 template <int U, bool VEC>
 __global__ void __launch_bounds__(64) k_expand_skinny_dma(const float* __restrict__ F, int ldf, int64_t N, int r,
@@ -724,22 +666,13 @@ template <int U>
 void launch_expand_skinny(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y, int64_t ldy,
                           hipStream_t st) {
   const bool vec = (ldy % 4 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
-  if (ldf <= SK_DMA_MAXLD) {
-    const dim3 grid((unsigned)((N + 63) / 64));
-    const size_t sh = (size_t)64 * ldf * sizeof(float);
-    if (vec)
-      hipLaunchKernelGGL((k_expand_skinny_dma<U, true>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
-    else
-      hipLaunchKernelGGL((k_expand_skinny_dma<U, false>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
-    return;
-  }
-  const dim3 grid((unsigned)((N + SK_P - 1) / SK_P));
+  const dim3 grid((unsigned)((N + 63) / 64));
+  const size_t sh = (size_t)64 * ldf * sizeof(float);
   if (vec)
-    hipLaunchKernelGGL((k_expand_skinny_mfma<U, true>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
+    hipLaunchKernelGGL((k_expand_skinny_dma<U, true>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
   else
-    hipLaunchKernelGGL((k_expand_skinny_mfma<U, false>), grid, dim3(256), 0, st, F, ldf, N, r, Z, B, Y, ldy);
+    hipLaunchKernelGGL((k_expand_skinny_dma<U, false>), grid, dim3(64), sh, st, F, ldf, N, r, Z, B, Y, ldy);
 }
-
 }  // namespace
 
 bool apply_mfma_ok(int r, int B) { return r >= 1 && r <= MFMA_APPLY_MAXR && B > 16; }
@@ -800,10 +733,14 @@ tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const fl
   return TTK_OK;
 }
 
+bool skinny_expand_mfma_ok(const void* F, int ldf, int r, int B) {
+  return skinny_mfma_ok(F, ldf, r, B) && ldf <= SK_DMA_MAXLD;
+}
+
 tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
                              int64_t ldy, hipStream_t st) {
   if (N <= 0) return TTK_OK;
-  if (!skinny_mfma_ok(F, ldf, r, B))
+  if (!skinny_expand_mfma_ok(F, ldf, r, B))
     return fail(TTK_ERR_ARG, "skinny MFMA expand: unsupported shape (r %d, ldf %d, B %d)", r, ldf, B);
   switch ((r + 15) / 16) {
     case 1: launch_expand_skinny<1>(F, ldf, N, r, Z, B, Y, ldy, st); break;

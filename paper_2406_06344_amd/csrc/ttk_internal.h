@@ -308,6 +308,7 @@ tt_status apply_expand_mfma(const float* F, int ldf, int64_t N, int r, const flo
 // rows of F (ldf % 4 == 0).  The reduce writes one float64 partial of W
 // (r x B) per 256 rows, part[g r B + c + b r] for g < groups, groups >= N / 256.
 bool skinny_mfma_ok(const void* F, int ldf, int r, int B);
+bool skinny_expand_mfma_ok(const void* F, int ldf, int r, int B);   // and ldf <= 160
 tt_status reduce_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* X, int64_t ldx, int B,
                              double* part, unsigned groups, hipStream_t st);
 tt_status expand_skinny_mfma(const float* F, int ldf, int64_t N, int r, const float* Z, int B, float* Y,
