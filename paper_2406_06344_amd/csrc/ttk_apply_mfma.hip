@@ -100,17 +100,23 @@ __global__ void __launch_bounds__(256, 2) k_expand_mfma(const float* __restrict_
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[s][q] = f4{0.f, 0.f, 0.f, 0.f};
-      // B[c][theta] = Z[c + (b0 + theta) r] = zs[theta r + c]
+      // B[c][theta] = Z[c + (b0 + theta) r] = zs[theta r + c], read one
+      // K-step ahead of its MFMAs (scheduling barriers keep the reads there)
       const float* zrow = zs + (32 * h + i16) * r + kq;
+      float bz[2][2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) bz[0][q] = zrow[16 * q * r];
 #pragma unroll
       for (int t = 0; t < KS; ++t) {
-        float bz[2];
+        if (t + 1 < KS)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) bz[q] = zrow[16 * q * r + 4 * t];
+          for (int q = 0; q < 2; ++q) bz[(t + 1) & 1][q] = zrow[16 * q * r + 4 * (t + 1)];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
-          for (int q = 0; q < 2; ++q) acc[s][q] = mfma4(af[s][t], bz[q], acc[s][q]);
+          for (int q = 0; q < 2; ++q) acc[s][q] = mfma4(af[s][t], bz[t & 1][q], acc[s][q]);
+        __builtin_amdgcn_sched_barrier(0);
       }
       // D[4 kq + v][i16]: points p0 + 16 s + 4 kq + v, theta b0 + 32 h + 16 q + i16
 #pragma unroll
@@ -332,20 +338,37 @@ __global__ void __launch_bounds__(256, 2) k_reduce_mfma_dma(const float* __restr
     for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
       for (int q = 0; q < NH; ++q) acc[ct][q] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-    for (int t = 0; t < RD_P / 4; ++t) {
-      float bx[NH];
+    // the K-steps' LDS operands one step ahead of their MFMAs (two register
+    // sets), so the reads are in flight while the previous step multiplies
+    auto ldop = [&](int t, float (&a)[CT], float (&b)[NH]) {
 #pragma unroll
       for (int q = 0; q < NH; ++q) {
         const int th = 16 * NH * w + 16 * q + i16;
-        bx[q] = xs[th * RD_P + 4 * ((t - th) & 15) + kq];
+        b[q] = xs[th * RD_P + 4 * ((t - th) & 15) + kq];
       }
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        const float a = fa[4 * t * ldf + 16 * ct];
+      for (int ct = 0; ct < CT; ++ct) a[ct] = fa[4 * t * ldf + 16 * ct];
+    };
+    auto mm = [&](const float (&a)[CT], const float (&b)[NH]) {
 #pragma unroll
-        for (int q = 0; q < NH; ++q) acc[ct][q] = mfma4(a, bx[q], acc[ct][q]);
-      }
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int q = 0; q < NH; ++q) acc[ct][q] = mfma4(a[ct], b[q], acc[ct][q]);
+    };
+    // (scheduling barriers keep the compiler from sinking each read next
+    // to its MFMA, which would leave one read in flight at a time)
+    float a0[CT], b0[NH], a1[CT], b1[NH];
+    ldop(0, a0, b0);
+#pragma unroll
+    for (int t = 0; t < RD_P / 4; t += 2) {
+      ldop(t + 1, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mm(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (t + 2 < RD_P / 4) ldop(t + 2, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mm(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct)
