@@ -42,10 +42,10 @@ TRAFFIC = None
 FP32_PEAK_TFLOPS = 157.3
 # HBM bytes per launch of the projection kernel k_reduce_mfma_dma<5, 1> on
 # the 1M-point workload from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
-# separate runs): (2.000 x 8311093.1 + 1.000 x 19840.4) KiB, averaged over its
+# separate runs): (2.000 x 8426797.5 + 1.000 x 19840.8) KiB, averaged over its
 # two launches, with the scales 2.000 and 1.000 read off the same counters on
 # a plain 1 GiB copy.  None whenever the kernel has changed since.
-PROJECT_TRAFFIC = 17041435184
+PROJECT_TRAFFIC = 17278398259
 PROJECT_TRAFFIC_NOTE = ("HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (scales from a plain 1 GiB "
                         "copy), average of the two launches; algorithmic 16.72 GB (X, F, float64 chunk partials)")
 
