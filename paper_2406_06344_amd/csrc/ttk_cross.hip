@@ -641,7 +641,10 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
   extern __shared__ double sa[];   // A operands (2 x 64 x nst)
   __shared__ double red[SW][16], sn[D * MAXN], sAs[16], redm[SW], S[SPB * D];
   __shared__ int64_t offL[SPB], offR[SPB];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // (wv through readfirstlane: the tile index and the triangular step bound
+  // below are then known to be wave-uniform, so the step guards are scalar
+  // branches)
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lg = lane >> 4;
   const int i0 = blockIdx.x * SPB;
   const int nv = min(SPB, ns - i0);   // samples of this block (none past the variant's extent)
@@ -650,16 +653,21 @@ __global__ void __launch_bounds__(SW * 64) k_sample_resid(KSpec ks, const StepDe
   const double* Wt = W + FT;
   // B operands in batches of HB steps, two register sets: the next batch
   // loads while the current one multiplies; the first tile's first batch
-  // loads before the gathers
+  // loads before the gathers.  Every load reads a clamped, valid address and
+  // zeros what lies past r by a select (a guarded load compiles to a branch
+  // per load, after which the compiler waits for all loads at every MFMA).
   constexpr int HB = SB / 2;
   double bgA[HB], btA[HB], bgB[HB], btB[HB];
   auto loadb = [&](int p, int s0, double (&bg)[HB], double (&bt)[HB]) {
+    const int pc = min(p, MAXR - 1);
 #pragma unroll
     for (int u = 0; u < HB; ++u) {
       const int q = 4 * (s0 + u) + lg;
       const bool ok = p < r && q < r;
-      bg[u] = ok ? Wt[p + (int64_t)q * MAXR] : 0.0;
-      bt[u] = ok ? Li[p + (int64_t)q * MAXR] : 0.0;
+      const int64_t e = pc + (int64_t)min(q, MAXR - 1) * MAXR;
+      const double w = Wt[e], l = Li[e];
+      bg[u] = ok ? w : 0.0;
+      bt[u] = ok ? l : 0.0;
     }
   };
   loadb(wv * 16 + li, 0, bgA, btA);
