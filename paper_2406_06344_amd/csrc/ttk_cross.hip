@@ -493,8 +493,13 @@ __device__ __forceinline__ void row_dots(const double* M, const double* v, int r
 #pragma unroll
       for (int u = 0; u < RB; ++u)
         mv[u] = (q + u < q1 && tri_in(TRI, t, q + u)) ? M[t + (int64_t)(q + u) * MAXR] : 0.0;
+      if (q + RB <= q1) {   // a whole batch: no guard, so the LDS reads of v issue together
 #pragma unroll
-      for (int u = 0; u < RB; ++u) a[u & 7] += q + u < q1 ? mv[u] * v[q + u] : 0.0;
+        for (int u = 0; u < RB; ++u) a[u & 7] += mv[u] * v[q + u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < RB; ++u) a[u & 7] += q + u < q1 ? mv[u] * v[q + u] : 0.0;
+      }
     }
     acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
@@ -892,7 +897,20 @@ __global__ void __launch_bounds__(256) k_search(KSpec ks, const StepDesc* desc, 
         FRk[fibre_right_col(ib, r) + ia] = vf;
       }
     }
-    for (int q = lj; q <= r; q += 16) {
+    // the lane's terms q = lj, lj + 16, ... in order; four at a time while
+    // all four lie below r, so their loads issue together
+    int q = lj;
+    for (; q + 48 < r; q += 64) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = crow[q + 16 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc += v[u] * sx[q + 16 * u];
+        m = fmax(m, fabs(v[u]));
+      }
+    }
+    for (; q <= r; q += 16) {
       const double v = q < r ? crow[q] : vf;
       acc += v * sx[q];
       m = fmax(m, fabs(v));
