@@ -337,9 +337,26 @@ __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, i
   __shared__ double As[16][MAXR + 1];
   const TTTile t = tiles[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int e = tid; e < 16 * r0; e += TTW * 64) {
-    const int row = e / r0, kk = e - row * r0;
-    As[row][kk] = row < t.count ? Vin[(int64_t)perm[t.start + row] * ldin + kk] : 0.0;
+  {   // the 16 points' rows of V: each thread's (at most 4 at 16 waves) point
+      // indices first, then their rows, so the two rounds of loads issue together
+    constexpr int ST = TTW * 64, NU = (16 * MAXR + ST - 1) / ST;
+    int pidx[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + u * ST, row = e / r0;
+      pidx[u] = (e < 16 * r0 && row < t.count) ? perm[t.start + row] : -1;
+    }
+    double v[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + u * ST, row = e / r0, kk = e - row * r0;
+      v[u] = pidx[u] >= 0 ? Vin[(int64_t)pidx[u] * ldin + kk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int e = tid + u * ST, row = e / r0, kk = e - row * r0;
+      if (e < 16 * r0) As[row][kk] = v[u];
+    }
   }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
