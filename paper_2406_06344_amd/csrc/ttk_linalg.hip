@@ -1907,6 +1907,33 @@ __global__ void __launch_bounds__(256) k_qr_t64(const double* Vp, int ldv, size_
 // in turn, so V is read once per chunk whatever the width of C.
 constexpr int WQ = QRC;   // rows per chunk of the wide products
 
+// Vs[i][c] = vpan(Vp, ldv, r0 + i, c, mm, ob) for the chunk's WQ x OB panel,
+// 256 threads.  Every read is from a clamped, valid entry of the panel and
+// is turned into 0 or 1 arithmetically (v 0 + 1 on the diagonal, v 0 off the
+// reflectors), eight per thread at a time: written as vpan() the reads
+// compiled to one conditional load and wait per element.  (A zero of either
+// sign contributes nothing to the products that read Vs.)
+__device__ inline void stage_vpan(const double* Vp, int ldv, int r0, int mm, int ob, double (*Vs)[OB + 1], int tid) {
+  constexpr int NE = WQ * OB / 256, UB = 8;
+  static_assert(NE % UB == 0, "whole groups of UB elements per thread");
+#pragma unroll
+  for (int e0 = 0; e0 < NE; e0 += UB) {
+    double v[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + (e0 + u) * 256, i = e % WQ, c = e / WQ, gi = r0 + i;
+      v[u] = Vp[min(gi, mm - 1) + (size_t)min(c, ob - 1) * ldv];
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int e = tid + (e0 + u) * 256, i = e % WQ, c = e / WQ, gi = r0 + i;
+      const bool in = gi < mm && c < ob;
+      const double keep = (in && gi > c) ? 1.0 : 0.0, one = (in && gi == c) ? 1.0 : 0.0;
+      Vs[i][c] = v[u] * keep + one;
+    }
+  }
+}
+
 // W partials: Wp[((chunk * tiles + tile) * 4 + s) * 256 + m * 16 + n] =
 // sum over the chunk's rows of V[i, 16 s + m] C[i, 16 tile + n].
 __global__ void __launch_bounds__(256) k_qr_w64(const double* Vp, int ldv, size_t sV, int mm, int ob, const double* C,
@@ -1919,10 +1946,7 @@ __global__ void __launch_bounds__(256) k_qr_w64(const double* Vp, int ldv, size_
   const int li = lane & 15, lk = lane >> 4;
   const int ch = blockIdx.x, r0 = ch * WQ;
   const int tiles = (nc + 15) / 16, ns = (ob + 15) / 16;
-  for (int e = tid; e < WQ * OB; e += 256) {
-    const int i = e % WQ, c = e / WQ;
-    Vs[i][c] = vpan(Vp, ldv, r0 + i, c, mm, ob);
-  }
+  stage_vpan(Vp, ldv, r0, mm, ob, Vs, tid);
   __syncthreads();
   for (int t = wv; t < tiles; t += 4) {
     const int c = t * 16 + li;
@@ -1994,10 +2018,7 @@ __global__ void __launch_bounds__(256) k_qr_c64(const double* Vp, int ldv, size_
   const int li = lane & 15, lk = lane >> 4;
   const int ch = blockIdx.x, r0 = ch * WQ;
   const int tiles = (nc + 15) / 16, nst = (ob + 3) / 4;
-  for (int e = tid; e < WQ * OB; e += 256) {
-    const int i = e % WQ, c = e / WQ;
-    Vs[i][c] = vpan(Vp, ldv, r0 + i, c, mm, ob);
-  }
+  stage_vpan(Vp, ldv, r0, mm, ob, Vs, tid);
   __syncthreads();
   for (int t = wv; t < tiles; t += 4) {
     const int c = t * 16 + li;
