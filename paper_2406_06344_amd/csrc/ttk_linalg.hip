@@ -1417,10 +1417,23 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
     const int g = b * JB_W + (c & (JB_W - 1));
     return (b < nb && g < n) ? g : -1;
   };
-  for (int e = tid; e < 2 * JB_W * n; e += JB_T) {
-    const int c = e / n, i = e - c * n;
-    const int g = gcol(c);
-    sj[e] = g >= 0 ? A[i + (size_t)g * lda] : 0.0;
+  {   // the 2 JB_W columns (n <= JB_L E): every load issued before the first
+      // store, from clamped addresses with the missing entries zeroed by a
+      // select (a copy loop of runtime length waits for each load in turn)
+    constexpr int CL = 2 * JB_W * JB_L * E / JB_T;
+    const int ne = 2 * JB_W * n;
+    double v[CL];
+#pragma unroll
+    for (int u = 0; u < CL; ++u) {
+      const int e = min(tid + u * JB_T, ne - 1);
+      const int c = e / n, i = e - c * n;
+      const int g = gcol(c);
+      const double a = A[i + (size_t)max(g, 0) * lda];
+      v[u] = g >= 0 ? a : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < CL; ++u)
+      if (tid + u * JB_T < ne) sj[tid + u * JB_T] = v[u];
   }
   const double gfloor = 1e-30 * aux[0];
   __syncthreads();
