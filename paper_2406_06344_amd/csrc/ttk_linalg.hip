@@ -1402,7 +1402,8 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
   aux += blockIdx.y * sS;
   int32_t* fl = reinterpret_cast<int32_t*>(aux + 1);
   if (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;   // converged
-  extern __shared__ double sj[];   // the 2 JB_W columns, leading dimension n
+  constexpr int LDN = JB_L * E;    // LDS rows per column (n <= LDN)
+  extern __shared__ double sj[];   // the 2 JB_W columns, leading dimension LDN
   __shared__ int s_rot, s_large;
   const int tid = threadIdx.x;
   if (tid == 0) s_rot = s_large = 0;
@@ -1417,23 +1418,22 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
     const int g = b * JB_W + (c & (JB_W - 1));
     return (b < nb && g < n) ? g : -1;
   };
-  {   // the 2 JB_W columns (n <= JB_L E): every load issued before the first
-      // store, from clamped addresses with the missing entries zeroed by a
-      // select (a copy loop of runtime length waits for each load in turn)
-    constexpr int CL = 2 * JB_W * JB_L * E / JB_T;
-    const int ne = 2 * JB_W * n;
+  {   // the 2 JB_W columns, each padded with zero rows to LDN: every load
+      // issued before the first store, from clamped addresses with the
+      // missing entries zeroed by a select (a copy loop of runtime length
+      // waits for each load in turn)
+    constexpr int CL = 2 * JB_W * LDN / JB_T;
     double v[CL];
 #pragma unroll
     for (int u = 0; u < CL; ++u) {
-      const int e = min(tid + u * JB_T, ne - 1);
-      const int c = e / n, i = e - c * n;
+      const int e = tid + u * JB_T;
+      const int c = e / LDN, i = e - c * LDN;
       const int g = gcol(c);
-      const double a = A[i + (size_t)max(g, 0) * lda];
-      v[u] = g >= 0 ? a : 0.0;
+      const double a = A[min(i, n - 1) + (size_t)max(g, 0) * lda];
+      v[u] = (g >= 0 && i < n) ? a : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < CL; ++u)
-      if (tid + u * JB_T < ne) sj[tid + u * JB_T] = v[u];
+    for (int u = 0; u < CL; ++u) sj[tid + u * JB_T] = v[u];
   }
   const double gfloor = 1e-30 * aux[0];
   __syncthreads();
@@ -1450,23 +1450,20 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
     int q = 1 + (y >= NP - 1 ? y - (NP - 1) : y);
     if (p > q) { const int t = p; p = q; q = t; }
     if (gcol(p) >= 0 && gcol(q) >= 0) {
-      double* ap = sj + (size_t)p * n;
-      double* aq = sj + (size_t)q * n;
+      double* ap = sj + p * LDN + gl;
+      double* aq = sj + q * LDN + gl;
       double xv[E], yv[E];
 #pragma unroll
       for (int u = 0; u < E; ++u) {
-        const int i = min(gl + JB_L * u, n - 1);
-        xv[u] = ap[i];
-        yv[u] = aq[i];
+        xv[u] = ap[JB_L * u];
+        yv[u] = aq[JB_L * u];
       }
       double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-      for (int u = 0; u < E; ++u) {   // (rows past n enter as zeros)
-        const bool in = gl + JB_L * u < n;
-        const double x = in ? xv[u] : 0.0, y = in ? yv[u] : 0.0;
-        al = fma(x, x, al);
-        be = fma(y, y, be);
-        ga = fma(x, y, ga);
+      for (int u = 0; u < E; ++u) {   // (the padding rows are zeros and stay so)
+        al = fma(xv[u], xv[u], al);
+        be = fma(yv[u], yv[u], be);
+        ga = fma(xv[u], yv[u], ga);
       }
       al = row32_sum(al);
       be = row32_sum(be);
@@ -1476,9 +1473,8 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
         jacobi_rotation(al, be, ga, c, sn);
 #pragma unroll
         for (int u = 0; u < E; ++u) {
-          const int i = min(gl + JB_L * u, n - 1);
-          ap[i] = c * xv[u] - sn * yv[u];
-          aq[i] = sn * xv[u] + c * yv[u];
+          ap[JB_L * u] = c * xv[u] - sn * yv[u];
+          aq[JB_L * u] = sn * xv[u] + c * yv[u];
         }
         rot = 1;
         if (ga * ga > JACOBI_LAST * JACOBI_LAST * (al * be)) large = 1;
@@ -1486,10 +1482,12 @@ __global__ void __launch_bounds__(JB_T) k_jacobi_block(double* A, int n, int lda
     }
     __syncthreads();
   }
-  for (int e = tid; e < 2 * JB_W * n; e += JB_T) {
-    const int c = e / n, i = e - c * n;
+#pragma unroll
+  for (int u = 0; u < 2 * JB_W * LDN / JB_T; ++u) {
+    const int e = tid + u * JB_T;
+    const int c = e / LDN, i = e - c * LDN;
     const int g = gcol(c);
-    if (g >= 0) A[i + (size_t)g * lda] = sj[e];
+    if (g >= 0 && i < n) A[i + (size_t)g * lda] = sj[e];
   }
   if (rot) s_rot = 1;
   if (large) s_large = 1;
@@ -2391,9 +2389,10 @@ bool jacobi_lds_launch(double* A, int n, int lda, double* V, int ldv, double* si
 }
 
 template <int E>
-void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux, size_t sh, int count, size_t sA,
-                        size_t sS, hipStream_t st) {
+void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux, int count, size_t sA, size_t sS,
+                        hipStream_t st) {
   static size_t attr = 48 * 1024;   // dynamic LDS the instantiation is allowed so far
+  const size_t sh = (size_t)2 * JB_W * JB_L * E * sizeof(double);   // the columns padded to JB_L E rows
   if (sh > attr) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_jacobi_block<E>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh) != hipSuccess)
@@ -2409,8 +2408,7 @@ void jacobi_block_round(double* A, int n, int lda, int nbp, int rnd, double* aux
 // host reading the convergence flags between batches (launches queued past a
 // matrix's convergence return at once for it).
 bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, size_t sS, int count, hipStream_t st) {
-  if (n < 2 || n > JB_L * 16 || count < 1 || count > 65535) return false;   // E <= 16; 2 JB_W n doubles of LDS
-  const size_t sh = (size_t)2 * JB_W * n * sizeof(double);
+  if (n < 2 || n > JB_L * 16 || count < 1 || count > 65535) return false;   // E <= 16: 128 KB of LDS at most
   const int nb = (n + JB_W - 1) / JB_W, nbp = nb + (nb & 1);
   double* aux = sigma + (size_t)n * n + 3 * (size_t)n + 2;
   hipLaunchKernelGGL(k_jb_init, dim3(count), dim3(BS), 0, st, (const double*)A, n, lda, aux, sA, sS);
@@ -2419,12 +2417,12 @@ bool jacobi_block_left_n(double* A, int n, int lda, size_t sA, double* sigma, si
   for (int batch = 6; sweeps < 60; batch = 2) {
     for (int b = 0; b < batch && sweeps < 60; ++b, ++sweeps) {
       for (int rnd = 0; rnd < nbp - 1; ++rnd) {
-        if (E <= 2) jacobi_block_round<2>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 6) jacobi_block_round<6>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
-        else jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, sh, count, sA, sS, st);
+        if (E <= 2) jacobi_block_round<2>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
+        else if (E <= 4) jacobi_block_round<4>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
+        else if (E <= 6) jacobi_block_round<6>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
+        else if (E <= 8) jacobi_block_round<8>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
+        else if (E <= 12) jacobi_block_round<12>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
+        else jacobi_block_round<16>(A, n, lda, nbp, rnd, aux, count, sA, sS, st);
       }
       hipLaunchKernelGGL(k_jb_check, dim3(count), dim3(64), 0, st, aux, sS);
     }
