@@ -486,8 +486,10 @@ def bench_pairs(args, torch, pkg):
         p["src_off"], p["tgt_off"] = so, to
         so += p["n_src"]
         to += p["n_tgt"]
-    Xd = torch.tensor(np.vstack(xs), device="cuda")
-    Yd = torch.tensor(np.vstack(ys), device="cuda")
+    # (np.clip against the float64 box bounds returns float64: the points are
+    # handed over in the batch's float32, as its Phase 3 entry point expects)
+    Xd = torch.tensor(np.vstack(xs), dtype=torch.float32, device="cuda")
+    Yd = torch.tensor(np.vstack(ys), dtype=torch.float32, device="cuda")
     B = 256
     th = synth.thetas(base, count=B, seed=1)
     thd = torch.tensor(th, dtype=torch.float32, device="cuda")
