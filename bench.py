@@ -387,7 +387,7 @@ def bench_batched(args, torch, pkg):
         "traffic_note": PROJECT_TRAFFIC_NOTE,
     }
     # ---- the paper's Phase 4 (TT-Round through S and T, on a tall-skinny QR)
-    # on this build, after every other measurement (it replaces U, V and the
+    # on the same kernel handle, after every other measurement (it replaces U, V and the
     # parameter cores of the handle)
     print("phase 4", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -555,8 +555,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: the path shards by rows of U and V with one small all-reduce per "
-              "apply direction (see the design notes); multi-GPU runs are not part of this build.",
+        print("bench.py runs on one GPU only: the path would shard by rows of U and V, with one small "
+              "all-reduce per apply direction, but runs on more than one GPU are not supported.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -11,7 +11,7 @@ has rows (s, i_k) -> s + i_k r_{k-1} and columns (i_{k+1}, t) -> i_{k+1} + t n_{
 (little-endian, Section 2.2).  A pivot row l adds (L[k-1][l mod r_{k-1}], l div r_{k-1})
 to I^{<=k}; a pivot column c adds (c mod n_{k+1}, R[k+1][c div n_{k+1}]) to I^{>k}.
 
-Readings of the paper taken here (each written out in the design notes):
+Readings of the paper taken here:
 * Algorithm 5 residual: R = A(:, J) A(I, J)^{-1} A(I, :) - A (rows I, columns J),
   the skeleton of Appendix A; A(I,J)^{-1} applied by an LU solve.
 * Random samples: max{rows, cols} distinct linear positions lin = row*cols + col
