@@ -336,7 +336,10 @@ __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, i
                                                       const TTTile* tiles) {
   __shared__ double As[16][MAXR + 1];
   const TTTile t = tiles[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // (wv through readfirstlane: the tile loop and the step guards below are
+  // then known to be wave-uniform, scalar branches)
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nst = (r0 + 3) / 4;
   {   // the 16 points' rows of V: each thread's (at most 4 at 16 waves) point
       // indices first, then their rows, so the two rounds of loads issue together
     constexpr int ST = TTW * 64, NU = (16 * MAXR + ST - 1) / ST;
@@ -357,29 +360,32 @@ __global__ void __launch_bounds__(TTW * 64) k_tt_core(const double* C, int r0, i
       const int e = tid + u * ST, row = e / r0, kk = e - row * r0;
       if (e < 16 * r0) As[row][kk] = v[u];
     }
+    // zeros in the columns r0 .. 4 nst - 1 of the last MFMA step, so the A
+    // operand reads need no guard
+    if (tid < 64 && r0 + (tid & 3) < 4 * nst) As[tid >> 2][r0 + (tid & 3)] = 0.0;
   }
   __syncthreads();
   const int li = lane & 15, lk = lane >> 4;
-  const int nst = (r0 + 3) / 4;
   const double* Ci = C + (int64_t)t.i * r0;
   for (int ct = wv; ct < (r1 + 15) / 16; ct += TTW) {
     const int col = ct * 16 + li;
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     // batches of TTB steps; the B operands of the next batch are loaded
-    // while the current batch's products issue (two register sets)
+    // while the current batch's products issue (two register sets).  Every
+    // load reads a clamped, valid entry of the slice and nothing is masked:
+    // past r0 the A operand is zero, and columns past r1 are not stored (a
+    // guarded or selected load makes the compiler wait for every outstanding
+    // load at once, the next batch's included)
+    const int cc = min(col, r1 - 1);
     auto loadb = [&](int s0, double (&b)[TTB]) {
 #pragma unroll
-      for (int u = 0; u < TTB; ++u) {
-        const int kk = 4 * (s0 + u) + lk;
-        b[u] = (kk < r0 && col < r1) ? Ci[kk + (int64_t)col * m] : 0.0;
-      }
+      for (int u = 0; u < TTB; ++u) b[u] = Ci[min(4 * (s0 + u) + lk, r0 - 1) + (int64_t)cc * m];
     };
     auto mma = [&](int s0, const double (&b)[TTB]) {
 #pragma unroll
       for (int u = 0; u < TTB; ++u) {
         const int kk = 4 * (s0 + u) + lk;
-        if (s0 + u < nst)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(kk < r0 ? As[li][kk] : 0.0, b[u], acc, 0, 0, 0);
+        if (s0 + u < nst) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(As[li][kk], b[u], acc, 0, 0, 0);
       }
     };
     const int nbat = (nst + TTB - 1) / TTB;
