@@ -1220,18 +1220,19 @@ struct CoreEval {
 // lane order (step s, lane l at s * 64 + l), B(q, p) = Bt[p + q MAXR] for this
 // lane's column p, over the steps [sb, se) (B is zero outside them); the B
 // loads of the next SB / 2 steps are in flight while the current ones
-// multiply.
-__device__ inline dbl4 mfma_tile_lds(const double* sa, int sb, int se, const double* Bt, int p, int r, int lane) {
+// multiply.  The A rows past r must be zero in LDS and the output columns
+// past r are not stored, so the B loads read clamped entries of the r x r
+// factor unmasked (a masked load makes the compiler wait for every
+// outstanding load before each MFMA, the next batch's included).
+__device__ __attribute__((always_inline)) inline dbl4 mfma_tile_lds(const double* sa, int sb, int se, const double* Bt, int p,
+                                                                  int r, int lane) {
   constexpr int HB = SB / 2;   // steps per batch: the next batch loads while this one multiplies
   const int lk = lane >> 4;
-  const bool pok = p < r;
+  const double* Bp = Bt + min(p, r - 1);
   dbl4 acc = {0.0, 0.0, 0.0, 0.0};
   auto loadb = [&](int s0, double (&b)[HB]) {
 #pragma unroll
-    for (int u = 0; u < HB; ++u) {
-      const int q = 4 * (s0 + u) + lk;
-      b[u] = (pok && q < r) ? Bt[p + (int64_t)q * MAXR] : 0.0;
-    }
+    for (int u = 0; u < HB; ++u) b[u] = Bp[(int64_t)min(4 * (s0 + u) + lk, r - 1) * MAXR];
   };
   auto mma = [&](int s0, const double (&b)[HB]) {
 #pragma unroll
